@@ -1,0 +1,216 @@
+"""FP64 CPU oracle for the restricted-domain dual segmentation method.
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, by the smoke check and by the
+CPU-baseline leg of the benchmark, never by the product package.  It shares no
+code with the HIP path.  The arithmetic lives in ``rdseg_oracle.c`` (plain C,
+FP64, single thread); this module only marshals numpy arrays through ctypes.
+
+Parity status of each function (pins live in ``tests/test_oracle_*.py``):
+
+* ``active_set``  -- pinned (brute force on tiny grids, closed forms delta=inf / delta<=0).
+* ``grad``/``div`` -- pinned (adjointness <grad u, p> = -<u, div p>; hand-worked 2x3 case).
+* ``solve``       -- pinned (duality-gap certificate of the restricted energy, closed forms,
+  symmetries, resume, invariants, monotone dual objective, independent matrix formulation).
+* ``dual_steps``  -- pinned (monotone dual objective, fixed point of the ROF dual).
+* ``reverse``/``tangent`` -- pinned (dot-product identity, central finite differences).
+* ``fit_term``/``fit_vjp`` -- pinned (hand-worked values, finite differences).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_fp = ctypes.POINTER(ctypes.c_float)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        from . import build as _b
+        _b.build()
+    lib = ctypes.CDLL(_LIB_PATH)
+    c_int, c_double, c_size = ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+    lib.orc_active_set.argtypes = [_fp, c_int, c_int, c_double, _i32p, _u64p, _i32p,
+                                   _i32p, _i32p, _i64p]
+    lib.orc_grad.argtypes = [_dp, c_int, c_int, _dp, _dp]
+    lib.orc_grad.restype = None
+    lib.orc_div.argtypes = [_dp, _dp, c_int, c_int, _dp]
+    lib.orc_div.restype = None
+    lib.orc_solve.argtypes = [_fp, c_int, c_int, c_double, c_double, c_double, c_double,
+                              c_int, c_int, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
+    lib.orc_dual_steps.argtypes = [_fp, c_int, c_int, c_double, c_double, c_double, _dp,
+                                   c_int, _dp, _dp]
+    lib.orc_reverse.argtypes = [_fp, c_int, c_int, c_double, c_double, c_double, c_double,
+                                c_int, _dp, _dp, _dp, _dp]
+    lib.orc_tangent.argtypes = [_fp, c_int, c_int, c_double, c_double, c_double, c_double,
+                                c_int, _dp, c_double, _dp, _dp]
+    lib.orc_fit_term.argtypes = [_fp, _fp, c_size, c_double, c_double, c_double, _dp]
+    lib.orc_fit_term.restype = None
+    lib.orc_fit_vjp.argtypes = [_fp, _fp, c_size, c_double, c_double, _dp, _dp, _dp, _dp]
+    lib.orc_fit_vjp.restype = None
+    _lib = lib
+    return lib
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _ptr(a, t):
+    return None if a is None else a.ctypes.data_as(t)
+
+
+def _check(rc, name):
+    if rc != 0:
+        raise ValueError(f"oracle {name} failed with code {rc}")
+
+
+def active_set(f, delta):
+    """Restricted domain |f| < delta as 8x8 tiles and as an ascending pixel list.
+
+    Returns dict(tile_ids int32[n], masks uint64[n], slot_map int32[TH*TW],
+    pixels int32[m]).  Paper: Sec. 3 (Fg/Bg/RD thresholding of the fitting term).
+    """
+    lib = _load()
+    f = _f32(f)
+    H, W = f.shape
+    TH, TW = (H + 7) // 8, (W + 7) // 8
+    nt_cap = TH * TW
+    tile_ids = np.zeros(nt_cap, np.int32)
+    masks = np.zeros(nt_cap, np.uint64)
+    slot = np.zeros(nt_cap, np.int32)
+    pix = np.zeros(H * W, np.int32)
+    nt = ctypes.c_int32(0)
+    npx = ctypes.c_int64(0)
+    _check(lib.orc_active_set(_ptr(f, _fp), H, W, float(delta), _ptr(tile_ids, _i32p),
+                              _ptr(masks, _u64p), _ptr(slot, _i32p), ctypes.byref(nt),
+                              _ptr(pix, _i32p), ctypes.byref(npx)), "active_set")
+    return dict(tile_ids=tile_ids[:nt.value].copy(), masks=masks[:nt.value].copy(),
+                slot_map=slot, pixels=pix[:npx.value].copy())
+
+
+def grad(u):
+    """Forward-difference gradient of Chambolle (2004), zero on the last column/row."""
+    lib = _load()
+    u = _f64(u)
+    H, W = u.shape
+    gx = np.empty_like(u)
+    gy = np.empty_like(u)
+    lib.orc_grad(_ptr(u, _dp), H, W, _ptr(gx, _dp), _ptr(gy, _dp))
+    return gx, gy
+
+
+def div(px, py):
+    """Divergence with div = -grad^T (Chambolle 2004)."""
+    lib = _load()
+    px, py = _f64(px), _f64(py)
+    H, W = px.shape
+    d = np.empty_like(px)
+    lib.orc_div(_ptr(px, _dp), _ptr(py, _dp), H, W, _ptr(d, _dp))
+    return d
+
+
+def solve(f, lam, theta, tau, delta, iters, inner=1, u0=None, p0=None):
+    """Restricted alternating dual iteration (Sec. 2.1 restricted as in Sec. 3).
+
+    f: float32 [H][W] (held exactly in FP64).  u0: [H][W] or None (H(-f)).
+    p0: [2][H][W] or None (zero).  Returns (u, v, p) in FP64, p as [2][H][W].
+    """
+    lib = _load()
+    f = _f32(f)
+    H, W = f.shape
+    u = np.empty((H, W))
+    v = np.empty((H, W))
+    px = np.empty((H, W))
+    py = np.empty((H, W))
+    u0c = None if u0 is None else _f64(u0)
+    p0x = None if p0 is None else _f64(p0[0])
+    p0y = None if p0 is None else _f64(p0[1])
+    _check(lib.orc_solve(_ptr(f, _fp), H, W, float(lam), float(theta), float(tau),
+                         float(delta), int(iters), int(inner), _ptr(u0c, _dp),
+                         _ptr(p0x, _dp), _ptr(p0y, _dp), _ptr(u, _dp), _ptr(v, _dp),
+                         _ptr(px, _dp), _ptr(py, _dp)), "solve")
+    return u, v, np.stack([px, py])
+
+
+def dual_steps(f, v, theta, tau, delta, n, p0=None):
+    """`n` restricted Chambolle fixed-point steps for p with v held fixed."""
+    lib = _load()
+    f = _f32(f)
+    H, W = f.shape
+    v = _f64(v)
+    px = np.zeros((H, W)) if p0 is None else _f64(p0[0]).copy()
+    py = np.zeros((H, W)) if p0 is None else _f64(p0[1]).copy()
+    _check(lib.orc_dual_steps(_ptr(f, _fp), H, W, float(theta), float(tau), float(delta),
+                              _ptr(v, _dp), int(n), _ptr(px, _dp), _ptr(py, _dp)),
+           "dual_steps")
+    return np.stack([px, py])
+
+
+def reverse(f, lam, theta, tau, delta, iters, ubar, vbar=None):
+    """Reverse-mode derivative of the unrolled solve (default start).
+
+    Returns (fbar [H][W], lambar).  RD and u0 = H(-f) are held fixed.
+    """
+    lib = _load()
+    f = _f32(f)
+    H, W = f.shape
+    ub = _f64(ubar)
+    vb = None if vbar is None else _f64(vbar)
+    fbar = np.empty((H, W))
+    lb = ctypes.c_double(0.0)
+    _check(lib.orc_reverse(_ptr(f, _fp), H, W, float(lam), float(theta), float(tau),
+                           float(delta), int(iters), _ptr(ub, _dp), _ptr(vb, _dp),
+                           _ptr(fbar, _dp), ctypes.byref(lb)), "reverse")
+    return fbar, lb.value
+
+
+def tangent(f, lam, theta, tau, delta, iters, df, dlam):
+    """Forward-mode derivative of the final (u, v) along (df, dlam)."""
+    lib = _load()
+    f = _f32(f)
+    H, W = f.shape
+    dfc = _f64(df)
+    du = np.empty((H, W))
+    dv = np.empty((H, W))
+    _check(lib.orc_tangent(_ptr(f, _fp), H, W, float(lam), float(theta), float(tau),
+                           float(delta), int(iters), _ptr(dfc, _dp), float(dlam),
+                           _ptr(du, _dp), _ptr(dv, _dp)), "tangent")
+    return du, dv
+
+
+def fit_term(z, c1, c2, gamma=0.0, P=None):
+    """Fitting term of eq. CV (P None) or eq. DS, in FP64."""
+    lib = _load()
+    z = _f32(z)
+    Pc = None if P is None else _f32(P)
+    out = np.empty(z.shape)
+    lib.orc_fit_term(_ptr(z, _fp), _ptr(Pc, _fp), z.size, float(c1), float(c2),
+                     float(gamma), _ptr(out, _dp))
+    return out
+
+
+def fit_vjp(z, c1, c2, fbar, P=None):
+    """(c1bar, c2bar, gammabar) = fbar . d f / d(c1, c2, gamma)."""
+    lib = _load()
+    z = _f32(z)
+    Pc = None if P is None else _f32(P)
+    fb = _f64(fbar)
+    a, b, g = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    lib.orc_fit_vjp(_ptr(z, _fp), _ptr(Pc, _fp), z.size, float(c1), float(c2),
+                    _ptr(fb, _dp), ctypes.byref(a), ctypes.byref(b), ctypes.byref(g))
+    return a.value, b.value, g.value
