@@ -1,0 +1,241 @@
+/*
+ * rdseg.h -- C ABI of the MI355X (gfx950) implementation of the restricted-domain
+ * dual method for convexly relaxed two-phase segmentation
+ * (Spencer, arXiv 1807.11534).
+ *
+ * The method minimises TV(u) + lambda <f, u> over u in [0, 1] (Sec. 2, eq. CR)
+ * with the split energy of eq. DF (Sec. 2.1), alternating
+ *   - Chambolle's semi-implicit fixed-point step for the dual field p (Sec. 3),
+ *   - the u-step        u = v - theta div p               (Sec. 2.1 / Sec. 3),
+ *   - the v-step        v = min(max(u - theta lambda f, 0), 1),
+ * and runs the three steps only on the restricted domain RD = {|f| < delta}
+ * (Sec. 3, where delta is called q-hat); elsewhere u = v = H(-f), p = 0, with
+ * u0 = H(-f) (Sec. 1) and H(0) = 0.  The discrete gradient is the forward
+ * difference with a zero component on the last column / row; the divergence
+ * is its negative adjoint (Chambolle 2004, cited at the end of Sec. 2.1).
+ * Frozen neighbours enter the dual step through w = -H(-f)/theta.
+ *
+ * Conventions shared by every entry point
+ *   - Images are row-major FP32 planes [H][ld], x contiguous, ld >= W elements.
+ *     The dual field p is two planes [2][H][ld]: p (x component) then
+ *     p + H*ld (y component).
+ *   - Pointers marked "device" are HIP device pointers; "host" are host memory.
+ *   - The caller allocates and owns every buffer, including the workspace
+ *     `ws` (device) and the tape.  Nothing is allocated on the device by
+ *     rdseg_active_set, rdseg_solve, rdseg_backward or the fit-term calls;
+ *     rdseg_solve_batched allocates only inside its plan (see there).
+ *   - All work is enqueued asynchronously on `stream` (a hipStream_t; NULL =
+ *     the default stream).  Device-side counts are device scalars: synchronise
+ *     the stream before reading them.
+ *   - Every call validates its arguments on the host before enqueuing work and
+ *     returns an rdseg_status; no C++ exception crosses the ABI.  On failure
+ *     rdseg_last_error() returns a thread-local message.
+ *   - Calls that overlap on one stream are ordered; calls on different streams
+ *     that share a workspace race.
+ */
+#ifndef RDSEG_H
+#define RDSEG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RDSEG_OK = 0,
+    RDSEG_ERR_ARG = 1,        /* invalid scalar or NULL / aliased pointer */
+    RDSEG_ERR_SHAPE = 2,      /* H or W < 1, ld < W, or H*ld >= 2^31 */
+    RDSEG_ERR_WORKSPACE = 3,  /* ws NULL or ws_bytes below the required size */
+    RDSEG_ERR_HIP = 4,        /* a HIP runtime call or kernel launch failed */
+    RDSEG_ERR_TAPE = 5        /* tape missing or inconsistent with the parameters */
+} rdseg_status;
+
+typedef struct {
+    int32_t H, W;   /* grid size, >= 1 */
+    int64_t ld;     /* row pitch in elements, >= W */
+} rdseg_shape;
+
+/* Solver parameters.  lambda >= 0, theta > 0, tau > 0 finite; delta not NaN
+ * (+INFINITY = full domain, the paper's q = 1; delta <= min|f| = pure
+ * thresholding, q = 0).  iters >= 0 outer iterations, each one dual step, one
+ * u-step and one v-step.  iters_per_launch, tile_w, tile_h: the temporally
+ * blocked kernel runs iters_per_launch iterations per launch on tile_w x tile_h
+ * blocks (multiples of 8); 0 = chosen by the library (autotuned, see
+ * rdseg_autotune; choosing synchronises the stream once).  ckpt_every > 0
+ * asks rdseg_solve to write a checkpoint of (v, p) every ckpt_every
+ * iterations into `tape` for rdseg_backward. */
+typedef struct {
+    double lambda, theta, tau, delta;
+    int32_t iters;
+    int32_t iters_per_launch;
+    int32_t tile_w, tile_h;
+    int32_t ckpt_every;
+} rdseg_params;
+
+/* Fitting term of Sec. 1: f = (z - c1)^2 - (z - c2)^2 + gamma P   (eq. CV when
+ * P is NULL, eq. DS otherwise).  z, P: device planes with the solve's shape. */
+typedef struct {
+    const float* z;
+    const float* P;   /* nullable */
+    double c1, c2, gamma;
+} rdseg_fit;
+
+/* One image of a batch (all device pointers, layout as above). */
+typedef struct {
+    const float* f;
+    float* u;
+    float* v;
+    float* p;         /* [2][H][ld] */
+    rdseg_shape s;
+    double lambda, delta;
+} rdseg_image;
+
+/* ---------------------------------------------------------------------- */
+/* Sizes                                                                   */
+/* ---------------------------------------------------------------------- */
+
+/* Workspace bytes needed by rdseg_solve (prm may be NULL: the maximum over
+ * all tile configurations) and by rdseg_active_set.  0 if the shape is invalid. */
+size_t rdseg_workspace_size(const rdseg_shape* s, const rdseg_params* prm);
+
+/* Tape bytes needed by rdseg_solve / rdseg_backward for prm->iters and
+ * prm->ckpt_every: ceil(iters / ckpt_every) checkpoints of (v, px, py), each
+ * 3 * H * ld floats.  0 if ckpt_every <= 0 or the arguments are invalid. */
+size_t rdseg_tape_size(const rdseg_shape* s, const rdseg_params* prm);
+
+/* Workspace bytes needed by rdseg_backward (includes a segment tape of
+ * ckpt_every states and the adjoint state). */
+size_t rdseg_backward_workspace_size(const rdseg_shape* s, const rdseg_params* prm);
+
+/* ---------------------------------------------------------------------- */
+/* Restricted domain (Sec. 3: Fg = {f <= -delta}, Bg = {f >= delta},       */
+/* RD = the rest)                                                           */
+/* ---------------------------------------------------------------------- */
+
+/* Compacts RD = {x : |f(x)| < delta} (strict, compared in FP64; NaN is never
+ * in RD) into 8x8 tiles.  Tile t = ty * ceil(W/8) + tx; its 64-bit mask has
+ * bit (y mod 8) * 8 + (x mod 8) set for pixels of RD.
+ * Outputs (device):
+ *   tile_ids [ceil(H/8)*ceil(W/8)]  ascending ids of tiles with a non-empty mask
+ *   tile_masks [same]               their masks
+ *   slot_map [ceil(H/8)*ceil(W/8)]  position of tile t in tile_ids, or -1
+ *   n_tiles (device int32)          number of listed tiles
+ *   pixel_idx [H*W] (nullable)      ascending y*W + x of RD pixels
+ *   n_pixels (device int64, nullable with pixel_idx)
+ * Errors: RDSEG_ERR_ARG for NULL required pointers or NaN delta. */
+rdseg_status rdseg_active_set(const float* f, rdseg_shape s, double delta,
+                              int32_t* tile_ids, uint64_t* tile_masks, int32_t* slot_map,
+                              int32_t* n_tiles, int32_t* pixel_idx, int64_t* n_pixels,
+                              void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------- */
+/* Solve (Sec. 2.1 iteration restricted as in Sec. 3)                      */
+/* ---------------------------------------------------------------------- */
+
+/* Runs prm->iters iterations from u0 (nullable: H(-f)) and p0 (nullable: 0;
+ * [2][H][ld]); v0 = clamp(u0 - theta lambda f, 0, 1).  A start u0 / p0 is used
+ * on RD only, and p0's x component on the last column and y component on the
+ * last row are taken as 0.  Writes u, v, p (device, full grids; frozen pixels
+ * hold u = v = H(-f), p = 0).  u0 == u and p0 == p are allowed (warm start in
+ * place); u, v, p must not overlap f or each other.  iters == 0 returns the
+ * initial state.  tape (device, nullable) receives the checkpoints when
+ * prm->ckpt_every > 0 (size rdseg_tape_size).  Results are bitwise identical
+ * for every tile configuration and iters_per_launch, and a solve of K1
+ * iterations resumed for K2 more (u0 = u, p0 = p) equals one of K1 + K2. */
+rdseg_status rdseg_solve(const float* f, rdseg_shape s, const rdseg_params* prm,
+                         const float* u0, const float* p0,
+                         float* u, float* v, float* p, float* tape,
+                         void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------- */
+/* Batched solve                                                            */
+/* ---------------------------------------------------------------------- */
+
+/* Solves n independent images (imgs: host array; per-image lambda and delta,
+ * shared theta, tau, iters) over one global queue of (image, tile) work items,
+ * each launch covering every image.  With graph_plan non-NULL, the first call
+ * (*graph_plan == NULL) builds a plan (device descriptors, its own workspace,
+ * a captured hipGraph of the whole sequence) and stores it in *graph_plan;
+ * later calls with the same plan replay the graph (the image set, shapes,
+ * pointers and scalars must then be unchanged; only the contents of f may
+ * change).  The plan allocates its device memory once, at creation, and
+ * frees it in rdseg_plan_destroy.  With graph_plan NULL, the call runs eagerly
+ * using `ws` (size rdseg_batched_workspace_size).  tile_w / tile_h /
+ * iters_per_launch 0 = defaults.  Results are bitwise identical to rdseg_solve
+ * on each image with the same tile configuration. */
+size_t rdseg_batched_workspace_size(const rdseg_image* imgs, int32_t n, int32_t tile_w,
+                                    int32_t tile_h);
+rdseg_status rdseg_solve_batched(const rdseg_image* imgs, int32_t n, double theta, double tau,
+                                 int32_t iters, int32_t iters_per_launch, int32_t tile_w,
+                                 int32_t tile_h, void** graph_plan, void* ws, size_t ws_bytes,
+                                 void* stream);
+rdseg_status rdseg_plan_destroy(void* plan);
+
+/* ---------------------------------------------------------------------- */
+/* Adjoint of the unrolled solve                                            */
+/* ---------------------------------------------------------------------- */
+
+/* Reverse-mode derivative of the solve that wrote `tape` (same f, shape and
+ * prm, default start u0 = H(-f), p0 = 0; prm->ckpt_every > 0).  The domain RD
+ * and u0 depend on f through comparisons only and are held fixed; the clamp
+ * has derivative 1 strictly inside (0, 1); d|g|/dg = g/|g| (0 at g = 0).
+ * Inputs: grad_u (device [H][ld]) = dL/du of the final u; grad_v (nullable).
+ * Outputs: grad_f (device [H][ld], 0 off RD), grad_lambda (device double).
+ * With fit non-NULL (the f of the solve came from rdseg_fit_forward with the
+ * same fit), also grad_c1, grad_c2 and grad_gamma (device doubles) through
+ * eq. CV / eq. DS.  Scalar reductions are FP64 in a fixed order
+ * (deterministic).  RDSEG_ERR_TAPE if tape is NULL or ckpt_every <= 0. */
+rdseg_status rdseg_backward(const float* f, rdseg_shape s, const rdseg_params* prm,
+                            const float* tape, const float* grad_u, const float* grad_v,
+                            float* grad_f, double* grad_lambda, const rdseg_fit* fit,
+                            double* grad_c1, double* grad_c2, double* grad_gamma,
+                            void* ws, size_t ws_bytes, void* stream);
+
+/* Fitting term of Sec. 1 (eq. CV / eq. DS), evaluated in FP64 and rounded to
+ * FP32: f = (z - c1)^2 - (z - c2)^2 + gamma P.  f: device [H][ld]. */
+rdseg_status rdseg_fit_forward(const rdseg_fit* fit, rdseg_shape s, float* f, void* stream);
+
+/* dL/d(c1, c2, gamma) from grad_f = dL/df (device doubles out; FP64 fixed-order
+ * reductions).  ws: at least rdseg_reduce_workspace_size(s) bytes. */
+size_t rdseg_reduce_workspace_size(const rdseg_shape* s);
+rdseg_status rdseg_fit_backward(const rdseg_fit* fit, rdseg_shape s, const float* grad_f,
+                                double* grad_c1, double* grad_c2, double* grad_gamma,
+                                void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------- */
+/* Autotuning, timing, diagnostics                                          */
+/* ---------------------------------------------------------------------- */
+
+/* Times every compiled (tile_w, tile_h, iters_per_launch) configuration on
+ * this problem for `probe_iters` iterations (synchronous), stores the fastest
+ * in the process-wide cache under (shape class, active-fraction bucket), and
+ * returns it.  u, v, p, ws as for rdseg_solve (their contents are
+ * overwritten). */
+rdseg_status rdseg_autotune(const float* f, rdseg_shape s, const rdseg_params* prm,
+                            int32_t probe_iters, float* u, float* v, float* p,
+                            void* ws, size_t ws_bytes, void* stream,
+                            int32_t* tile_w, int32_t* tile_h, int32_t* iters_per_launch);
+
+/* Number of compiled configurations and their parameters (i < count). */
+int32_t rdseg_config_count(void);
+rdseg_status rdseg_config_get(int32_t i, int32_t* tile_w, int32_t* tile_h,
+                              int32_t* iters_per_launch, int32_t* threads);
+
+/* When enabled, every launch of the iteration kernel is bracketed by HIP
+ * events on its stream; rdseg_timing_read synchronises on the recorded events
+ * and returns the summed kernel milliseconds, the launch count and the summed
+ * algorithmic bytes (28 bytes per active pixel-iteration), then resets. */
+rdseg_status rdseg_timing_enable(int32_t on);
+rdseg_status rdseg_timing_read(double* kernel_ms, int64_t* launches, double* alg_bytes,
+                               int64_t* pixel_updates);
+
+const char* rdseg_status_string(rdseg_status st);
+const char* rdseg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RDSEG_H */

@@ -1,0 +1,320 @@
+// compact.hip -- stream compaction of the restricted domain RD = {|f| < delta}
+// (Sec. 3: Fg / Bg / RD thresholding of the fitting term).
+//
+// One wave64 scans an 8-row x 64-column strip: for each of the 8 rows the
+// wave's ballot of (|f| < delta) is a 64-bit row mask, and the 8 bytes of the
+// 8 ballots that fall in one 8x8 tile form that tile's 64-bit mask (bit
+// (y mod 8) * 8 + (x mod 8)).  Lists are built with a three-pass exclusive
+// scan (block sums, one-block scan of the sums, block-local scan + scatter),
+// so every list is in ascending order and identical run to run.
+#include "rdseg_internal.h"
+
+namespace rdseg {
+
+namespace {
+
+constexpr int SCAN_T = 256;
+constexpr int SCAN_I = 8;
+constexpr int SCAN_B = SCAN_T * SCAN_I;
+
+__device__ __forceinline__ int find_image(const int64_t* off, int n, int64_t g) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= g) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int wave_incl_scan(int x) {
+    int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    return x;
+}
+
+// Exclusive scan of one value per thread over a 256-thread block.
+__device__ __forceinline__ int block_excl_scan(int x, int* s_w, int& total) {
+    int incl = wave_incl_scan(x);
+    int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 63) s_w[wid] = incl;
+    __syncthreads();
+    int pre = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_T / 64; ++k) {
+        int v = s_w[k];
+        pre += (k < wid) ? v : 0;
+        tot += v;
+    }
+    total = tot;
+    __syncthreads();
+    return pre + incl - x;
+}
+
+__global__ __launch_bounds__(SCAN_T) void k_scan_partial(const int32_t* __restrict__ in,
+                                                         int64_t n, int32_t* __restrict__ part) {
+    __shared__ int s_w[SCAN_T / 64];
+    int64_t base = (int64_t)blockIdx.x * SCAN_B + (int64_t)threadIdx.x * SCAN_I;
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_I; ++k) s += (base + k < n) ? in[base + k] : 0;
+    int tot;
+    (void)block_excl_scan(s, s_w, tot);
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(SCAN_T) void k_scan_top(int32_t* __restrict__ part, int64_t nb,
+                                                     int32_t* __restrict__ total) {
+    __shared__ int s_w[SCAN_T / 64];
+    int carry = 0;
+    for (int64_t b0 = 0; b0 < nb; b0 += SCAN_T) {
+        int64_t i = b0 + threadIdx.x;
+        int x = (i < nb) ? part[i] : 0;
+        int tot;
+        int ex = block_excl_scan(x, s_w, tot);
+        if (i < nb) part[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ __launch_bounds__(SCAN_T) void k_scan_final(const int32_t* __restrict__ in, int64_t n,
+                                                       const int32_t* __restrict__ part,
+                                                       int32_t* __restrict__ out) {
+    __shared__ int s_w[SCAN_T / 64];
+    int64_t base = (int64_t)blockIdx.x * SCAN_B + (int64_t)threadIdx.x * SCAN_I;
+    int v[SCAN_I];
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_I; ++k) {
+        v[k] = (base + k < n) ? in[base + k] : 0;
+        s += v[k];
+    }
+    int tot;
+    int ex = block_excl_scan(s, s_w, tot) + part[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < SCAN_I; ++k) {
+        if (base + k < n) out[base + k] = ex;
+        ex += v[k];
+    }
+}
+
+__global__ void k_fill_i64(int64_t* p, int64_t n, int64_t v) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_i32_to_i64(const int32_t* a, int64_t* b) { *b = (int64_t)*a; }
+
+// ---------------------------------------------------------------- tile masks
+template <bool BATCHED>
+__global__ __launch_bounds__(256) void k_tile_masks(ImgDesc d0, const ImgDesc* __restrict__ descs,
+                                                    OffTables off, int n_img, int64_t n_strips,
+                                                    uint64_t* __restrict__ masks,
+                                                    int64_t* __restrict__ npix) {
+    int64_t s = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (s >= n_strips) return;   // uniform per wave
+    int lane = threadIdx.x & 63;
+    int img = BATCHED ? find_image(off.soff, n_img, s) : 0;
+    const ImgDesc& d = BATCHED ? descs[img] : d0;
+    int64_t ls = s - (BATCHED ? off.soff[img] : 0);
+    int sw = (d.tw + 7) >> 3;
+    int ty = (int)(ls / sw);
+    int sx = (int)(ls - (int64_t)ty * sw);
+    int x = sx * 64 + lane;
+    uint64_t b[8];
+    int cnt = 0;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        int y = ty * 8 + r;
+        bool a = false;
+        if (x < d.W && y < d.H) a = fabs((double)d.f[(int64_t)y * d.ld + x]) < d.delta;
+        b[r] = __ballot(a);
+        cnt += __popcll(b[r]);
+    }
+    if (lane < 8) {
+        int tx = sx * 8 + lane;
+        if (tx < d.tw) {
+            uint64_t m = 0;
+#pragma unroll
+            for (int r = 0; r < 8; ++r) m |= ((b[r] >> (8 * lane)) & 0xFFull) << (8 * r);
+            masks[d.toff + (int64_t)ty * d.tw + tx] = m;
+        }
+    }
+    if (lane == 0 && cnt) atomicAdd((unsigned long long*)&npix[img], (unsigned long long)cnt);
+}
+
+__global__ void k_mask_flags(const uint64_t* __restrict__ masks, int64_t n,
+                             int32_t* __restrict__ flags) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) flags[i] = masks[i] != 0 ? 1 : 0;
+}
+
+__global__ void k_tile_scatter(const uint64_t* __restrict__ masks, int64_t n,
+                               const int32_t* __restrict__ offs, int32_t* __restrict__ ids,
+                               uint64_t* __restrict__ mout, int32_t* __restrict__ slot) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    uint64_t m = masks[t];
+    if (m) {
+        int o = offs[t];
+        ids[o] = (int32_t)t;
+        mout[o] = m;
+        slot[t] = o;
+    } else {
+        slot[t] = -1;
+    }
+}
+
+// ---------------------------------------------------------------- pixel list
+__global__ __launch_bounds__(256) void k_pix_count(const float* __restrict__ f, int H, int W,
+                                                   int ld, double delta, int64_t n_chunks,
+                                                   int32_t* __restrict__ counts) {
+    int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (c >= n_chunks) return;
+    int lane = threadIdx.x & 63;
+    int64_t p = c * 64 + lane;
+    bool a = false;
+    if (p < (int64_t)H * W) {
+        int y = (int)(p / W), x = (int)(p - (int64_t)y * W);
+        a = fabs((double)f[(int64_t)y * ld + x]) < delta;
+    }
+    uint64_t b = __ballot(a);
+    if (lane == 0) counts[c] = __popcll(b);
+}
+
+__global__ __launch_bounds__(256) void k_pix_scatter(const float* __restrict__ f, int H, int W,
+                                                     int ld, double delta, int64_t n_chunks,
+                                                     const int32_t* __restrict__ offs,
+                                                     int32_t* __restrict__ pix) {
+    int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (c >= n_chunks) return;
+    int lane = threadIdx.x & 63;
+    int64_t p = c * 64 + lane;
+    bool a = false;
+    if (p < (int64_t)H * W) {
+        int y = (int)(p / W), x = (int)(p - (int64_t)y * W);
+        a = fabs((double)f[(int64_t)y * ld + x]) < delta;
+    }
+    uint64_t b = __ballot(a);
+    if (a) {
+        uint64_t below = (lane == 0) ? 0ull : (b & ((~0ull) >> (64 - lane)));
+        pix[offs[c] + __popcll(below)] = (int32_t)p;
+    }
+}
+
+// ---------------------------------------------------------------- macro queue
+template <bool BATCHED>
+__global__ void k_macro_flags(ImgDesc d0, const ImgDesc* __restrict__ descs, OffTables off,
+                              int n_img, int64_t n_macro, int bx8, int by8,
+                              const uint64_t* __restrict__ masks, int32_t* __restrict__ flags) {
+    int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n_macro) return;
+    int img = BATCHED ? find_image(off.moff, n_img, m) : 0;
+    const ImgDesc& d = BATCHED ? descs[img] : d0;
+    int64_t lm = m - (BATCHED ? off.moff[img] : 0);
+    int my = (int)(lm / d.mw), mx = (int)(lm - (int64_t)my * d.mw);
+    int ty1 = min(d.th, (my + 1) * by8), tx1 = min(d.tw, (mx + 1) * bx8);
+    int any = 0;
+    for (int ty = my * by8; ty < ty1; ++ty)
+        for (int tx = mx * bx8; tx < tx1; ++tx)
+            any |= masks[d.toff + (int64_t)ty * d.tw + tx] != 0 ? 1 : 0;
+    flags[m] = any;
+}
+
+template <bool BATCHED>
+__global__ void k_macro_scatter(ImgDesc d0, OffTables off, int n_img, int64_t n_macro,
+                                const int32_t* __restrict__ flags,
+                                const int32_t* __restrict__ offs, int2* __restrict__ queue) {
+    int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n_macro || !flags[m]) return;
+    int img = BATCHED ? find_image(off.moff, n_img, m) : 0;
+    int64_t lm = m - (BATCHED ? off.moff[img] : d0.moff);
+    queue[offs[m]] = make_int2(img, (int)lm);
+}
+
+inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+int64_t scan_partials(int64_t n) { return (n + SCAN_B - 1) / SCAN_B + 1; }
+
+int launch_scan_ints(const int32_t* counts, int64_t n, int32_t* out, int32_t* part,
+                     int32_t* total, hipStream_t st) {
+    int64_t nb = (n + SCAN_B - 1) / SCAN_B;
+    if (nb == 0) nb = 1;
+    hipLaunchKernelGGL(k_scan_partial, dim3((unsigned)nb), dim3(SCAN_T), 0, st, counts, n, part);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_T), 0, st, part, nb, total);
+    hipLaunchKernelGGL(k_scan_final, dim3((unsigned)nb), dim3(SCAN_T), 0, st, counts, n, part, out);
+    RDSEG_HIP_CHECK(hipGetLastError());
+    return 0;
+}
+
+int launch_tile_masks(const ImgDesc* d0, const ImgDesc* descs, OffTables off, int n_img,
+                      int64_t n_strips, uint64_t* masks, int64_t* npix, hipStream_t st) {
+    hipLaunchKernelGGL(k_fill_i64, dim3(nblk(n_img, 256)), dim3(256), 0, st, npix,
+                       (int64_t)n_img, (int64_t)0);
+    if (descs)
+        hipLaunchKernelGGL(k_tile_masks<true>, dim3(nblk(n_strips, 4)), dim3(256), 0, st, *d0,
+                           descs, off, n_img, n_strips, masks, npix);
+    else
+        hipLaunchKernelGGL(k_tile_masks<false>, dim3(nblk(n_strips, 4)), dim3(256), 0, st, *d0,
+                           descs, off, n_img, n_strips, masks, npix);
+    RDSEG_HIP_CHECK(hipGetLastError());
+    return 0;
+}
+
+int launch_tile_list(const uint64_t* masks, int64_t n_tiles, int32_t* flags, int32_t* offs,
+                     int32_t* part, int32_t* n_listed, int32_t* tile_ids, uint64_t* tile_masks,
+                     int32_t* slot_map, hipStream_t st) {
+    hipLaunchKernelGGL(k_mask_flags, dim3(nblk(n_tiles, 256)), dim3(256), 0, st, masks, n_tiles,
+                       flags);
+    int rc = launch_scan_ints(flags, n_tiles, offs, part, n_listed, st);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_tile_scatter, dim3(nblk(n_tiles, 256)), dim3(256), 0, st, masks,
+                       n_tiles, offs, tile_ids, tile_masks, slot_map);
+    RDSEG_HIP_CHECK(hipGetLastError());
+    return 0;
+}
+
+int launch_pixel_list(const float* f, int H, int W, int ld, double delta, int32_t* counts,
+                      int32_t* offs, int32_t* part, int32_t* total, int32_t* pix,
+                      int64_t* n_pix, hipStream_t st) {
+    int64_t n_chunks = ((int64_t)H * W + 63) / 64;
+    hipLaunchKernelGGL(k_pix_count, dim3(nblk(n_chunks, 4)), dim3(256), 0, st, f, H, W, ld,
+                       delta, n_chunks, counts);
+    int rc = launch_scan_ints(counts, n_chunks, offs, part, total, st);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_pix_scatter, dim3(nblk(n_chunks, 4)), dim3(256), 0, st, f, H, W, ld,
+                       delta, n_chunks, offs, pix);
+    hipLaunchKernelGGL(k_i32_to_i64, dim3(1), dim3(1), 0, st, total, n_pix);
+    RDSEG_HIP_CHECK(hipGetLastError());
+    return 0;
+}
+
+int launch_macro_queue(const ImgDesc* d0, const ImgDesc* descs, OffTables off, int n_img,
+                       int64_t n_macro, int bx, int by, const uint64_t* masks, int32_t* flags,
+                       int32_t* offs, int32_t* part, int2* queue, int32_t* n_queue,
+                       hipStream_t st) {
+    if (descs)
+        hipLaunchKernelGGL(k_macro_flags<true>, dim3(nblk(n_macro, 256)), dim3(256), 0, st, *d0,
+                           descs, off, n_img, n_macro, bx / 8, by / 8, masks, flags);
+    else
+        hipLaunchKernelGGL(k_macro_flags<false>, dim3(nblk(n_macro, 256)), dim3(256), 0, st, *d0,
+                           descs, off, n_img, n_macro, bx / 8, by / 8, masks, flags);
+    int rc = launch_scan_ints(flags, n_macro, offs, part, n_queue, st);
+    if (rc) return rc;
+    if (descs)
+        hipLaunchKernelGGL(k_macro_scatter<true>, dim3(nblk(n_macro, 256)), dim3(256), 0, st,
+                           *d0, off, n_img, n_macro, flags, offs, queue);
+    else
+        hipLaunchKernelGGL(k_macro_scatter<false>, dim3(nblk(n_macro, 256)), dim3(256), 0, st,
+                           *d0, off, n_img, n_macro, flags, offs, queue);
+    RDSEG_HIP_CHECK(hipGetLastError());
+    return 0;
+}
+
+}  // namespace rdseg

@@ -1,0 +1,324 @@
+// iterate.hip -- initial state and the temporally blocked restricted iteration.
+//
+// The iteration kernel processes one macro tile (BX x BY pixels) of the
+// compacted queue at a time.  It loads the macro tile plus a halo of IT + 1
+// pixels on the left / top and IT on the right / bottom into LDS (p) and
+// registers (v, c, flags), runs `nit` <= IT outer iterations entirely on chip,
+// and writes back the macro tile's RD pixels.  Per iteration two barriers
+// separate
+//   phase B (dual step, reads w at x, x + e_x, x + e_y; writes p), and
+//   phase A (u-step and v-step from div p at x, x - e_x, x - e_y; writes the
+//           next w),
+// so every on-chip value depends on cells at most one step away per phase.
+// After n iterations p is exact n cells inside the loaded region on every
+// side and v one more on the left / top, which is why that halo suffices;
+// garbage computed at the region's border never reaches the macro tile.
+//
+// State is double-buffered in HBM (launch reads buffer `in_buf`, writes the
+// other), so tiles never read a neighbour's halo while it is being written.
+// Pixels off RD are never read from or written to the state buffers: their
+// values (v = H(-f), p = 0) come from c = -/+inf.
+#include "rdseg_internal.h"
+
+namespace rdseg {
+
+namespace {
+
+__device__ __forceinline__ int find_image(const int64_t* off, int n, int64_t g) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= g) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <bool BATCHED>
+__global__ __launch_bounds__(256) void k_init(ImgDesc d0, const ImgDesc* __restrict__ descs,
+                                              OffTables off, int n_img, int64_t n_rows) {
+    for (int64_t R = blockIdx.x; R < n_rows; R += gridDim.x) {
+        int img = BATCHED ? find_image(off.roff, n_img, R) : 0;
+        const ImgDesc& d = BATCHED ? descs[img] : d0;
+        int y = (int)(R - (BATCHED ? off.roff[img] : 0));
+        for (int x = threadIdx.x; x < d.W; x += blockDim.x) {
+            int g = y * d.ld + x;
+            float fv = d.f[g];
+            float c = c_of(fv, d.delta, d.tl);
+            bool act = c_active(c);
+            float h = (fv < 0.0f) ? 1.0f : 0.0f;
+            float u0 = act ? (d.u0 ? d.u0[g] : h) : h;
+            float v0 = v_step(u0, c);
+            float px = (act && x < d.W - 1 && d.p0x) ? d.p0x[g] : 0.0f;
+            float py = (act && y < d.H - 1 && d.p0y) ? d.p0y[g] : 0.0f;
+            d.c[g] = c;
+            d.u[g] = u0;
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                d.st[b][0][g] = v0;
+                d.st[b][1][g] = px;
+                d.st[b][2][g] = py;
+            }
+        }
+    }
+}
+
+template <int BX, int BY, int IT, int NT, bool BATCHED>
+__global__ __launch_bounds__(NT) void k_iterate(ImgDesc d0, const ImgDesc* __restrict__ descs,
+                                                const int2* __restrict__ queue,
+                                                const int32_t* __restrict__ n_queue, int in_buf,
+                                                int nit, int write_u, float theta,
+                                                float inv_theta, float tau) {
+    constexpr int RX = BX + 2 * IT + 1;
+    constexpr int RY = BY + 2 * IT + 1;
+    constexpr int RC = RX * RY;
+    constexpr int CPT = (RC + NT - 1) / NT;
+    constexpr int PAD = RX + 1;
+    constexpr int LS = RC + 2 * PAD;
+    constexpr int H0 = IT + 1;   // left / top halo
+    __shared__ float sPX[LS];
+    __shared__ float sPY[LS];
+    __shared__ float sW[LS];
+
+    const int t = threadIdx.x;
+    for (int k = t; k < PAD; k += NT) {
+        sPX[k] = 0.0f; sPY[k] = 0.0f; sW[k] = 0.0f;
+        sPX[PAD + RC + k] = 0.0f; sPY[PAD + RC + k] = 0.0f; sW[PAD + RC + k] = 0.0f;
+    }
+
+    // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
+    // contiguous run of the ascending queue so that neighbouring macro tiles
+    // (which re-read each other's halos) share that XCD's L2.
+    const int nq = *n_queue;
+    const int per = gridDim.x >> 3;
+    const int xcd = blockIdx.x & 7;
+    const int rank = blockIdx.x >> 3;
+    const int chunk = (nq + 7) >> 3;
+    const int q0 = xcd * chunk;
+    const int q1 = min(nq, q0 + chunk);
+    const int out_buf = 1 - in_buf;
+
+    for (int item = q0 + rank; item < q1; item += per) {
+        const int2 q = queue[item];
+        const ImgDesc& d = BATCHED ? descs[q.x] : d0;
+        const int my = q.y / d.mw;
+        const int mx = q.y - my * d.mw;
+        const int ox = mx * BX - H0;
+        const int oy = my * BY - H0;
+        const int W = d.W, H = d.H, ld = d.ld;
+        const float* __restrict__ C = d.c;
+        const float* __restrict__ Vi = d.st[in_buf][0];
+        const float* __restrict__ PXi = d.st[in_buf][1];
+        const float* __restrict__ PYi = d.st[in_buf][2];
+
+        float rv[CPT], rpx[CPT], rpy[CPT], rc[CPT];
+        uint32_t fl[CPT];
+        int gi[CPT];
+
+        __syncthreads();   // LDS of the previous item fully consumed
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) {
+            const int i = t + j * NT;
+            rv[j] = 0.0f; rpx[j] = 0.0f; rpy[j] = 0.0f; rc[j] = __builtin_inff();
+            fl[j] = 0u; gi[j] = 0;
+            if (i < RC) {
+                const int ry = i / RX;
+                const int rx = i - ry * RX;
+                const int gx = ox + rx, gy = oy + ry;
+                const bool inb = (unsigned)gx < (unsigned)W && (unsigned)gy < (unsigned)H;
+                const int g = gy * ld + gx;
+                gi[j] = g;
+                float c = inb ? C[g] : __builtin_inff();
+                const bool act = c_active(c);
+                rc[j] = c;
+                if (act) {
+                    rv[j] = Vi[g];
+                    rpx[j] = PXi[g];
+                    rpy[j] = PYi[g];
+                } else {
+                    rv[j] = heav_from_c(c);
+                }
+                uint32_t f = act ? CF_ACT : 0u;
+                if (gx == W - 1) f |= CF_LASTC;
+                if (gy == H - 1) f |= CF_LASTR;
+                const bool interior = rx >= H0 && rx < H0 + BX && ry >= H0 && ry < H0 + BY;
+                if (interior && act) f |= CF_OUT;
+                fl[j] = f;
+                sPX[PAD + i] = rpx[j];
+                sPY[PAD + i] = rpy[j];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) {
+            const int i = t + j * NT;
+            if (i < RC) {
+                float dd = div_p(rpx[j], sPX[PAD + i - 1], rpy[j], sPY[PAD + i - RX]);
+                sW[PAD + i] = w_of(dd, rv[j], inv_theta, (fl[j] & CF_ACT) != 0);
+            }
+        }
+        __syncthreads();
+        for (int it = 0; it < nit; ++it) {
+            // phase B: dual step
+#pragma unroll
+            for (int j = 0; j < CPT; ++j) {
+                const int i = t + j * NT;
+                if (i < RC) {
+                    DualOut o = dual_update(rpx[j], rpy[j], sW[PAD + i], sW[PAD + i + 1],
+                                            sW[PAD + i + RX], fl[j], tau);
+                    rpx[j] = o.px;
+                    rpy[j] = o.py;
+                    sPX[PAD + i] = o.px;
+                    sPY[PAD + i] = o.py;
+                }
+            }
+            __syncthreads();
+            // phase A: u-step, v-step, next w
+            const bool last = (it == nit - 1);
+#pragma unroll
+            for (int j = 0; j < CPT; ++j) {
+                const int i = t + j * NT;
+                if (i < RC) {
+                    float dd = div_p(rpx[j], sPX[PAD + i - 1], rpy[j], sPY[PAD + i - RX]);
+                    float u = u_step(rv[j], dd, theta);
+                    rv[j] = v_step(u, rc[j]);
+                    if (last) {
+                        if (write_u && (fl[j] & CF_OUT)) d.u[gi[j]] = u;
+                    } else {
+                        sW[PAD + i] = w_of(dd, rv[j], inv_theta, (fl[j] & CF_ACT) != 0);
+                    }
+                }
+            }
+            if (!last) __syncthreads();
+        }
+        float* __restrict__ Vo = d.st[out_buf][0];
+        float* __restrict__ PXo = d.st[out_buf][1];
+        float* __restrict__ PYo = d.st[out_buf][2];
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) {
+            if (fl[j] & CF_OUT) {
+                Vo[gi[j]] = rv[j];
+                PXo[gi[j]] = rpx[j];
+                PYo[gi[j]] = rpy[j];
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_state_copy(ImgDesc d, int buf, float* __restrict__ slot,
+                                                    int to_slot) {
+    const int64_t plane = (int64_t)d.H * d.ld;
+    for (int y = blockIdx.x; y < d.H; y += gridDim.x) {
+        for (int x = threadIdx.x; x < d.W; x += blockDim.x) {
+            int g = y * d.ld + x;
+            if (!c_active(d.c[g])) continue;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                if (to_slot) slot[k * plane + g] = d.st[buf][k][g];
+                else d.st[buf][k][g] = slot[k * plane + g];
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- config table
+using IterFn = void (*)(ImgDesc, const ImgDesc*, const int2*, const int32_t*, int, int, int,
+                        float, float, float);
+
+struct CfgEntry {
+    TileCfg cfg;
+    IterFn single;
+    IterFn batched;
+};
+
+#define RDSEG_CFG(bx, by, it, nt)                                     \
+    CfgEntry{TileCfg{bx, by, it, nt}, k_iterate<bx, by, it, nt, false>, \
+             k_iterate<bx, by, it, nt, true>}
+
+const CfgEntry kCfgs[] = {
+    RDSEG_CFG(8, 8, 1, 64),
+    RDSEG_CFG(16, 16, 1, 128),
+    RDSEG_CFG(16, 16, 2, 128),
+    RDSEG_CFG(32, 16, 2, 256),
+    RDSEG_CFG(32, 32, 2, 256),
+    RDSEG_CFG(32, 32, 4, 256),
+    RDSEG_CFG(64, 32, 2, 256),
+    RDSEG_CFG(64, 32, 4, 512),
+    RDSEG_CFG(64, 64, 2, 512),
+    RDSEG_CFG(64, 64, 4, 512),
+    RDSEG_CFG(64, 64, 8, 1024),
+};
+constexpr int kNumCfgs = sizeof(kCfgs) / sizeof(kCfgs[0]);
+
+int g_grid_cache[kNumCfgs][2];
+
+}  // namespace
+
+int config_count() { return kNumCfgs; }
+
+TileCfg config_at(int i) { return kCfgs[i].cfg; }
+
+int config_index(int bx, int by, int it) {
+    for (int i = 0; i < kNumCfgs; ++i)
+        if (kCfgs[i].cfg.bx == bx && kCfgs[i].cfg.by == by && kCfgs[i].cfg.it == it) return i;
+    return -1;
+}
+
+int persistent_blocks(const void* kernel, int threads, size_t dyn_lds) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    int per = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, dyn_lds) != hipSuccess)
+        return 0;
+    if (per < 1) per = 1;
+    return per * ncu;
+}
+
+int launch_init(const ImgDesc* d0, const ImgDesc* descs, OffTables off, int n_img,
+                int64_t n_rows, hipStream_t st) {
+    unsigned grid = (unsigned)(n_rows < 65536 ? n_rows : 65536);
+    if (descs)
+        hipLaunchKernelGGL(k_init<true>, dim3(grid), dim3(256), 0, st, *d0, descs, off, n_img,
+                           n_rows);
+    else
+        hipLaunchKernelGGL(k_init<false>, dim3(grid), dim3(256), 0, st, *d0, descs, off, n_img,
+                           n_rows);
+    RDSEG_HIP_CHECK(hipGetLastError());
+    return 0;
+}
+
+int launch_iterate(int ci, const ImgDesc* d0, const ImgDesc* descs, bool batched,
+                   const int2* queue, const int32_t* n_queue, int64_t max_items, int in_buf,
+                   int nit, bool write_u, float theta, float inv_theta, float tau,
+                   hipStream_t st) {
+    const CfgEntry& e = kCfgs[ci];
+    IterFn fn = batched ? e.batched : e.single;
+    int& cached = g_grid_cache[ci][batched ? 1 : 0];
+    if (cached == 0) {
+        cached = persistent_blocks(reinterpret_cast<const void*>(fn), e.cfg.nt, 0);
+        if (cached <= 0) {
+            set_error("occupancy query failed for the iteration kernel");
+            return 4;
+        }
+    }
+    int64_t g = cached;
+    if (max_items < g) g = max_items;
+    g = ((g + 7) / 8) * 8;
+    if (g < 8) g = 8;
+    hipLaunchKernelGGL(fn, dim3((unsigned)g), dim3(e.cfg.nt), 0, st, *d0, descs, queue, n_queue,
+                       in_buf, nit, write_u ? 1 : 0, theta, inv_theta, tau);
+    RDSEG_HIP_CHECK(hipGetLastError());
+    return 0;
+}
+
+int launch_state_copy(const ImgDesc& d, int buf, float* slot, bool to_slot, hipStream_t st) {
+    unsigned grid = (unsigned)(d.H < 65536 ? d.H : 65536);
+    hipLaunchKernelGGL(k_state_copy, dim3(grid), dim3(256), 0, st, d, buf, slot,
+                       to_slot ? 1 : 0);
+    RDSEG_HIP_CHECK(hipGetLastError());
+    return 0;
+}
+
+}  // namespace rdseg

@@ -1,0 +1,113 @@
+// rdseg_internal.h -- host-side declarations shared by the library's
+// translation units (kernel launchers, error helpers, configuration table).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "rdseg_device.h"
+
+namespace rdseg {
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string& msg);
+const char* get_error();
+
+#define RDSEG_HIP_CHECK(expr)                                                        \
+    do {                                                                             \
+        hipError_t e_ = (expr);                                                      \
+        if (e_ != hipSuccess) {                                                      \
+            ::rdseg::set_error(std::string(#expr) + ": " + hipGetErrorString(e_));  \
+            return 4; /* RDSEG_ERR_HIP */                                            \
+        }                                                                            \
+    } while (0)
+
+// Offset tables of a batch (device arrays of n + 1 entries each).
+struct OffTables {
+    const int64_t* soff;   // 8x64 strips
+    const int64_t* toff;   // 8x8 tiles
+    const int64_t* moff;   // macro tiles
+    const int64_t* roff;   // rows
+};
+
+// ---------------------------------------------------------------- compaction
+// Exclusive prefix scan of int32 counts (n elements) into out, total into
+// *total.  part: scratch of scan_partials(n) int32.  Launch order is fixed,
+// so results are deterministic.
+int64_t scan_partials(int64_t n);
+int launch_scan_ints(const int32_t* counts, int64_t n, int32_t* out, int32_t* part,
+                     int32_t* total, hipStream_t st);
+
+// Dense 8x8 tile masks of every image (masks[toff[i] + ty * tw + tx]) and the
+// number of RD pixels per image (npix[i], zeroed by this launcher).
+int launch_tile_masks(const ImgDesc* d0, const ImgDesc* descs, OffTables off, int n_img,
+                      int64_t n_strips, uint64_t* masks, int64_t* npix, hipStream_t st);
+
+// Single-image active-set outputs from dense masks.
+int launch_tile_list(const uint64_t* masks, int64_t n_tiles, int32_t* flags_scratch,
+                     int32_t* offs, int32_t* part, int32_t* n_listed, int32_t* tile_ids,
+                     uint64_t* tile_masks, int32_t* slot_map, hipStream_t st);
+int launch_pixel_list(const float* f, int H, int W, int ld, double delta, int32_t* counts,
+                      int32_t* offs, int32_t* part, int32_t* total, int32_t* pix,
+                      int64_t* n_pix, hipStream_t st);
+
+// Macro-tile queue (bx x by pixels, multiples of 8) from dense tile masks:
+// queue[k] = (image, local macro id) for every macro tile holding an RD pixel,
+// in ascending global order; *n_queue = count.
+int launch_macro_queue(const ImgDesc* d0, const ImgDesc* descs, OffTables off, int n_img,
+                       int64_t n_macro, int bx, int by, const uint64_t* masks, int32_t* flags,
+                       int32_t* offs, int32_t* part, int2* queue, int32_t* n_queue,
+                       hipStream_t st);
+
+// ---------------------------------------------------------------- iteration
+int launch_init(const ImgDesc* d0, const ImgDesc* descs, OffTables off, int n_img,
+                int64_t n_rows, hipStream_t st);
+
+struct TileCfg {
+    int bx, by, it, nt;
+};
+int config_count();
+TileCfg config_at(int i);
+int config_index(int bx, int by, int it);   // -1 if not compiled
+
+// One launch of the temporally blocked iteration kernel: `nit` (<= cfg.it)
+// iterations over the queued macro tiles, reading state buffer `in_buf` and
+// writing 1 - in_buf; writes u on RD when write_u.  grid = persistent size.
+int launch_iterate(int cfg_index, const ImgDesc* d0, const ImgDesc* descs, bool batched,
+                   const int2* queue, const int32_t* n_queue, int64_t max_items, int in_buf,
+                   int nit, bool write_u, float theta, float inv_theta, float tau,
+                   hipStream_t st);
+
+// Copy (v, px, py) of RD pixels between a state buffer and a full-grid slot
+// [3][H][ld] (to_slot: buffer -> slot, else slot -> buffer).
+int launch_state_copy(const ImgDesc& d, int buf, float* slot, bool to_slot, hipStream_t st);
+
+// ---------------------------------------------------------------- adjoint
+struct AdjBufs {
+    float* pbx[2];
+    float* pby[2];
+    float* vb[2];
+    float* sacc;          // sum over steps of the clamp adjoint
+};
+int adj_config_count();
+int launch_adj_step(const ImgDesc& d, const float* fx, const float* fy, const float* fv,
+                    const AdjBufs& ab, int in_buf, bool first, const float* grad_v,
+                    const float* grad_u, const int2* queue, const int32_t* n_queue,
+                    int64_t max_items, int bx, int by, float theta, float tau, hipStream_t st);
+int launch_adj_final(const ImgDesc& d, const float* sacc, const float* vb0, float* grad_f,
+                     double lambda, double theta, const float* z, const float* P, double c1,
+                     double c2, double* partials, int64_t n_part, double* out4,
+                     hipStream_t st);
+int launch_fit_forward(const float* z, const float* P, double c1, double c2, double gamma,
+                       int H, int W, int ld, float* f, hipStream_t st);
+int launch_fit_backward(const float* z, const float* P, const float* grad_f, double c1,
+                        double c2, int H, int W, int ld, double* partials, int64_t n_part,
+                        double* out3, hipStream_t st);
+int64_t reduce_partials(int H);
+
+int persistent_blocks(const void* kernel, int threads, size_t dyn_lds);
+
+}  // namespace rdseg

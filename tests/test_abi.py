@@ -1,0 +1,95 @@
+"""C-ABI checks that need no GPU: the library loads, exports every declared
+symbol, and host-side validation rejects bad arguments before any launch."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rdseg.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rdseg_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1807_11534_amd import _lib
+    return _lib.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert len(names) >= 15
+    missing = [n for n in names if getattr(lib, n, None) is None]
+    assert not missing, missing
+
+
+def test_binding_covers_header():
+    from paper_1807_11534_amd import _lib
+    assert set(declared_functions()) == set(_lib.SIGNATURES)
+
+
+def test_status_strings(lib):
+    for st in range(6):
+        assert lib.rdseg_status_string(st)
+
+
+def _solve(lib, shape, prm, f=1, u=2, v=3, p=4, ws=8, ws_bytes=1 << 40, tape=None):
+    from paper_1807_11534_amd._lib import Shape
+    return lib.rdseg_solve(ctypes.c_void_p(f) if f else None, Shape(*shape), ctypes.byref(prm),
+                           None, None, ctypes.c_void_p(u << 32) if u else None,
+                           ctypes.c_void_p(v << 32) if v else None,
+                           ctypes.c_void_p(p << 32) if p else None, tape,
+                           ctypes.c_void_p(ws) if ws else None, ws_bytes, None)
+
+
+def _prm(**kw):
+    from paper_1807_11534_amd._lib import Params
+    d = dict(lambda_=1.0, theta=0.1, tau=0.125, delta=math.inf, iters=10, iters_per_launch=0,
+             tile_w=0, tile_h=0, ckpt_every=0)
+    d.update(kw)
+    return Params(**d)
+
+
+@pytest.mark.parametrize("shape,code", [((0, 5, 5), 2), ((5, 0, 5), 2), ((5, 5, 4), 2),
+                                        ((1 << 16, 1 << 15, 1 << 15), 2)])
+def test_bad_shapes(lib, shape, code):
+    assert _solve(lib, shape, _prm()) == code
+
+
+@pytest.mark.parametrize("kw", [dict(theta=0.0), dict(theta=-1.0), dict(tau=0.0),
+                                dict(tau=math.nan), dict(lambda_=-1.0), dict(lambda_=math.inf),
+                                dict(delta=math.nan), dict(iters=-1), dict(ckpt_every=-2),
+                                dict(tile_w=64, tile_h=0, iters_per_launch=0),
+                                dict(tile_w=24, tile_h=24, iters_per_launch=3)])
+def test_bad_scalars(lib, kw):
+    assert _solve(lib, (16, 16, 16), _prm(**kw)) == 1
+
+
+def test_null_pointers_and_workspace(lib):
+    assert _solve(lib, (16, 16, 16), _prm(), f=0) == 1
+    assert _solve(lib, (16, 16, 16), _prm(), u=0) == 1
+    assert _solve(lib, (16, 16, 16), _prm(), ws=0) == 3
+    assert _solve(lib, (16, 16, 16), _prm(), ws_bytes=16) == 3
+    assert _solve(lib, (16, 16, 16), _prm(ckpt_every=5)) == 5
+
+
+def test_aliasing_rejected(lib):
+    # v overlapping u
+    assert _solve(lib, (16, 16, 16), _prm(), u=3, v=3) == 1
+
+
+def test_workspace_sizes(lib):
+    from paper_1807_11534_amd._lib import Shape
+    s = Shape(100, 100, 128)
+    n = lib.rdseg_workspace_size(ctypes.byref(s), None)
+    assert n >= 4 * 4 * 100 * 128
+    assert lib.rdseg_workspace_size(ctypes.byref(Shape(0, 1, 1)), None) == 0
+    prm = _prm(iters=95, ckpt_every=30)
+    assert lib.rdseg_tape_size(ctypes.byref(s), ctypes.byref(prm)) == 4 * 3 * 100 * 128 * 4

@@ -1,0 +1,208 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Bars: active-set lists bit-exact; FP32 u within 1e-4 max-abs of the FP64
+oracle at equal iteration count; thresholded labels (u > 0.5) differing on at
+most 0.01 % of pixels; invariants; bitwise determinism across runs, across all
+compiled tile configurations and across a resumed solve.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+U_TOL = 1e-4
+LABEL_FRAC = 1e-4
+
+
+def p_norm_tol(iters):
+    """|p| <= 1 holds exactly in real arithmetic ((|p| + tau n) / (1 + tau n) <= 1).
+    One FP32 step rounds the numerator (0.5 ulp), uses the hardware reciprocal
+    and square root (<= 1 ulp each) and rounds the product (0.5 ulp): an excess
+    of at most ~2 ulp of 2^-23 per step.  The next step divides the excess by
+    1 + tau |g|, which is ~1 where |g| ~ 0, so over K steps the excess performs a
+    random walk of K signed roundings: the bar is 8 + 4 sqrt(K) ulp."""
+    return 1 + (8 + 4 * np.sqrt(iters)) * 2.0 ** -23
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def rd(gpu):
+    from paper_1807_11534_amd import rdseg
+    return rdseg
+
+
+def compare(u, v, p, uo, vo, po, f, delta, tag="", iters=500):
+    u, v, p = host(u).astype(np.float64), host(v).astype(np.float64), host(p).astype(np.float64)
+    err_u = np.abs(u - uo).max()
+    err_v = np.abs(v - vo).max()
+    lab = ((u > 0.5) != (uo > 0.5)).sum()
+    assert err_u <= U_TOL, (tag, "u", err_u)
+    assert err_v <= U_TOL, (tag, "v", err_v)
+    assert lab <= LABEL_FRAC * u.size, (tag, "labels", lab)
+    # invariants of the FP32 state
+    A = np.abs(f.astype(np.float64)) < delta
+    h = (f < 0).astype(np.float64)
+    assert np.sqrt(p[0] ** 2 + p[1] ** 2).max() <= p_norm_tol(iters)
+    assert v.min() >= 0 and v.max() <= 1
+    np.testing.assert_array_equal(u[~A], h[~A])
+    np.testing.assert_array_equal(v[~A], h[~A])
+    assert (p[:, ~A] == 0).all()
+    assert (p[0][:, -1] == 0).all() and (p[1][-1, :] == 0).all()
+    return err_u, lab
+
+
+# ------------------------------------------------------------ active set
+@pytest.mark.parametrize("shape", [(1, 1), (8, 8), (37, 45), (64, 200), (129, 77)])
+@pytest.mark.parametrize("frac", [-1.0, 0.0, 0.05, 0.3, math.inf])
+def test_active_set_bit_exact(rd, shape, frac):
+    H, W = shape
+    f = synth.smooth_field(H, W, 21, noise=0.2)
+    if H * W > 4:
+        f[H // 2, W // 2] = np.nan
+    delta = frac * float(np.nanmax(np.abs(f))) if math.isfinite(frac) else math.inf
+    say(f"active_set {shape} delta={delta}")
+    o = oracle.active_set(f, delta)
+    g = rd.active_set(dev(f), delta)
+    np.testing.assert_array_equal(host(g["tile_ids"]), o["tile_ids"])
+    np.testing.assert_array_equal(host(g["masks"]).view(np.uint64), o["masks"])
+    np.testing.assert_array_equal(host(g["slot_map"]), o["slot_map"])
+    np.testing.assert_array_equal(host(g["pixels"]), o["pixels"])
+
+
+def test_active_set_pitched(rd):
+    """Row pitch ld > W: the same lists as the packed field."""
+    f = synth.smooth_field(50, 70, 22, noise=0.2)
+    big = np.zeros((50, 96), np.float32)
+    big[:, :70] = f
+    t = dev(big)[:, :70]
+    delta = 0.25
+    o = oracle.active_set(f, delta)
+    g = rd.active_set(t, delta)
+    np.testing.assert_array_equal(host(g["tile_ids"]), o["tile_ids"])
+    np.testing.assert_array_equal(host(g["pixels"]), o["pixels"])
+
+
+# ------------------------------------------------------------ solve parity
+def test_plain_disc_rect_128(rd):
+    """Plain method, 128x128 disc + rectangle, lambda 5, full domain, 200 iterations."""
+    prob = synth.config1(seed=0)
+    say("plain 128x128 K=200")
+    u, v, p = rd.solve(dev(prob.f), prob.lam, prob.theta, prob.tau, math.inf, prob.iters)
+    uo, vo, po = oracle.solve(prob.f, prob.lam, prob.theta, prob.tau, math.inf, prob.iters)
+    compare(u, v, p, uo, vo, po, prob.f, math.inf, "c1", prob.iters)
+
+
+@pytest.mark.parametrize("lam_index", [0, 1, 2])
+@pytest.mark.parametrize("frac", [math.inf, 0.5, 0.2, 0.05])
+def test_restricted_sweep_256(rd, lam_index, frac):
+    """The restricted-domain sweep at 256^2 (lambda 1/5/20, delta fractions of max|f|)."""
+    prob = synth.config2(lam_index, size=256, iters=150)
+    delta = synth.band_delta(prob.f, frac)
+    say(f"sweep256 lam={prob.lam} frac={frac}")
+    u, v, p = rd.solve(dev(prob.f), prob.lam, prob.theta, prob.tau, delta, prob.iters)
+    uo, vo, po = oracle.solve(prob.f, prob.lam, prob.theta, prob.tau, delta, prob.iters)
+    compare(u, v, p, uo, vo, po, prob.f, delta, f"sweep lam={prob.lam} frac={frac}", prob.iters)
+
+
+@pytest.mark.parametrize("shape", [(37, 45), (150, 203), (8, 300), (301, 9)])
+def test_ragged_shapes(rd, shape):
+    H, W = shape
+    f = synth.smooth_field(H, W, 23, noise=0.2)
+    delta = 0.4
+    say(f"ragged {shape}")
+    u, v, p = rd.solve(dev(f), 3.0, 0.1, 0.125, delta, 61)
+    uo, vo, po = oracle.solve(f, 3.0, 0.1, 0.125, delta, 61)
+    compare(u, v, p, uo, vo, po, f, delta, f"ragged {shape}", 61)
+
+
+def test_all_configs_bitwise_identical(rd):
+    """Every compiled (tile, iterations-per-launch) gives the same FP32 bits."""
+    f = synth.smooth_field(150, 203, 24, noise=0.2)
+    ft = dev(f)
+    ref = None
+    for (tw, th, it, nt) in rd.configs():
+        say(f"config {tw}x{th} it={it} threads={nt}")
+        out = [host(x) for x in rd.solve(ft, 2.0, 0.1, 0.125, 0.35, 37, tile=(tw, th),
+                                         iters_per_launch=it)]
+        if ref is None:
+            ref = out
+            uo, vo, po = oracle.solve(f, 2.0, 0.1, 0.125, 0.35, 37)
+            assert np.abs(out[0] - uo).max() <= U_TOL
+        else:
+            for a, b in zip(out, ref):
+                np.testing.assert_array_equal(a, b)
+
+
+def test_determinism_and_resume(rd):
+    f = synth.smooth_field(96, 130, 25, noise=0.2)
+    ft = dev(f)
+    say("determinism / resume")
+    a = [host(x) for x in rd.solve(ft, 2.0, 0.1, 0.125, 0.4, 40, tile=(32, 32), iters_per_launch=4)]
+    b = [host(x) for x in rd.solve(ft, 2.0, 0.1, 0.125, 0.4, 40, tile=(32, 32), iters_per_launch=4)]
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x, y)
+    u1, v1, p1 = rd.solve(ft, 2.0, 0.1, 0.125, 0.4, 23, tile=(32, 32), iters_per_launch=4)
+    # resume in place: u0 is u, p0 is p
+    u2, v2, p2 = rd.solve(ft, 2.0, 0.1, 0.125, 0.4, 17, u0=u1, p0=p1, tile=(16, 16),
+                          iters_per_launch=2, out=(u1, v1, p1))
+    for x, y in zip([host(u2), host(v2), host(p2)], a):
+        np.testing.assert_array_equal(x, y)
+
+
+def test_zero_iterations_is_initial_state(rd):
+    f = synth.smooth_field(40, 50, 26, noise=0.2)
+    u, v, p = rd.solve(dev(f), 2.0, 0.1, 0.125, 0.3, 0)
+    uo, vo, po = oracle.solve(f, 2.0, 0.1, 0.125, 0.3, 0)
+    np.testing.assert_array_equal(host(u), uo.astype(np.float32))
+    np.testing.assert_allclose(host(v), vo, atol=1e-6)
+    assert (host(p) == 0).all()
+
+
+def test_closed_forms_gpu(rd):
+    """Constant f, large lambda (v = H(-f) exactly), empty domain (thresholding)."""
+    f = np.full((33, 41), 0.3, np.float32)
+    u, v, p = rd.solve(dev(f), 2.0, 0.1, 0.125, math.inf, 30)
+    assert (host(u) == 0).all() and (host(v) == 0).all() and (host(p) == 0).all()
+    g = synth.smooth_field(64, 64, 27, noise=0.2)
+    g[np.abs(g) < 0.05] = 0.05
+    lam = 4.0 / float(np.abs(g).min()) + 1.0
+    u, v, p = rd.solve(dev(g), lam, 0.1, 0.125, math.inf, 40)
+    h = (g < 0).astype(np.float32)
+    np.testing.assert_array_equal(host(v), h)
+    np.testing.assert_array_equal(host(u) > 0.5, h > 0.5)
+    u, v, p = rd.solve(dev(g), 3.0, 0.1, 0.125, 0.0, 25)
+    np.testing.assert_array_equal(host(u), h)
+    np.testing.assert_array_equal(host(v), h)
+    assert (host(p) == 0).all()
+
+
+def test_full_size_sweep_point_1024(rd):
+    """1024^2, 500 iterations, lambda 5, delta 0.5 max|f|, in the benchmark's
+    launch configuration, against the full oracle."""
+    prob = synth.config2(1)
+    delta = synth.band_delta(prob.f, 0.5)
+    say("full 1024^2 K=500 frac=0.5")
+    u, v, p = rd.solve(dev(prob.f), prob.lam, prob.theta, prob.tau, delta, prob.iters,
+                       tile=(64, 64), iters_per_launch=4)
+    uo, vo, po = oracle.solve(prob.f, prob.lam, prob.theta, prob.tau, delta, prob.iters)
+    compare(u, v, p, uo, vo, po, prob.f, delta, "full1024", prob.iters)
