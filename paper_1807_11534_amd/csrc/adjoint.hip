@@ -1,0 +1,454 @@
+// adjoint.hip -- reverse mode of the unrolled restricted iteration, the fitting
+// terms of Sec. 1 (eq. CV / eq. DS) and fixed-order FP64 reductions.
+//
+// One launch reverses one outer iteration k on the queued macro tiles.  From
+// the stored state (p^{k-1}, v^{k-1}) it recomputes w, g = grad w, m =
+// 1/(1 + tau|g|), p^k and the clamp argument s = u^k - theta lambda f, then
+// applies, on RD only (RD and u0 = H(-f) are held fixed):
+//   sbar  = vbar^k [0 < s < 1]                  (clamp)
+//   ubar  = sbar (+ dL/du at the last iteration)
+//   pbt   = pbar^k + theta grad(ubar)           (u = v - theta div p, div = -grad^T)
+//   gbar  = tau m pbt - tau m (p^k . pbt) g/|g| (normalised dual update)
+//   wbar  = -div gbar                           (g = grad w)
+//   vbar^{k-1} = ubar - wbar / theta,  pbar^{k-1} = m pbt - grad(wbar)
+// The x component on the last column and the y component on the last row are
+// constants (zero) and get no adjoint.  The sum of sbar over iterations is
+// accumulated per pixel; dL/df = -theta lambda * that sum and dL/dlambda =
+// -theta sum f * that sum.  Six LDS phases separated by barriers; the halo is 3
+// pixels on every side (each phase reaches one cell further).
+#include "rdseg_internal.h"
+
+namespace rdseg {
+
+namespace {
+
+constexpr int RED_T = 256;
+
+template <int BX, int BY, int NT>
+__global__ __launch_bounds__(NT) void k_adj_step(
+    ImgDesc d, const float* __restrict__ fx, const float* __restrict__ fy,
+    const float* __restrict__ fv, const float* __restrict__ pbx_in,
+    const float* __restrict__ pby_in, const float* __restrict__ vb_in,
+    float* __restrict__ pbx_out, float* __restrict__ pby_out, float* __restrict__ vb_out,
+    float* __restrict__ sacc, int first, const float* __restrict__ grad_v,
+    const float* __restrict__ grad_u, const int2* __restrict__ queue,
+    const int32_t* __restrict__ n_queue, float theta, float inv_theta, float tau) {
+    constexpr int HL = 3;
+    constexpr int RX = BX + 2 * HL;
+    constexpr int RY = BY + 2 * HL;
+    constexpr int RC = RX * RY;
+    constexpr int CPT = (RC + NT - 1) / NT;
+    constexpr int PAD = RX + 1;
+    constexpr int LS = RC + 2 * PAD;
+    __shared__ float sA[LS];
+    __shared__ float sB[LS];
+    __shared__ float sC[LS];
+
+    const int t = threadIdx.x;
+    for (int k = t; k < PAD; k += NT) {
+        sA[k] = 0.0f; sB[k] = 0.0f; sC[k] = 0.0f;
+        sA[PAD + RC + k] = 0.0f; sB[PAD + RC + k] = 0.0f; sC[PAD + RC + k] = 0.0f;
+    }
+    const int nq = *n_queue;
+    const int W = d.W, H = d.H, ld = d.ld;
+    for (int item = blockIdx.x; item < nq; item += gridDim.x) {
+        const int2 q = queue[item];
+        const int my = q.y / d.mw;
+        const int mx = q.y - my * d.mw;
+        const int ox = mx * BX - HL;
+        const int oy = my * BY - HL;
+
+        float rv[CPT], rc[CPT], rpbx[CPT], rpby[CPT], rvb[CPT];
+        float rnx[CPT], rny[CPT], rgx[CPT], rgy[CPT], rm[CPT], rsb[CPT], rub[CPT];
+        uint32_t fl[CPT];
+        int gi[CPT];
+
+        __syncthreads();
+        // P0: load
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) {
+            const int i = t + j * NT;
+            rv[j] = 0.0f; rc[j] = __builtin_inff(); rpbx[j] = 0.0f; rpby[j] = 0.0f;
+            rvb[j] = 0.0f; fl[j] = 0u; gi[j] = 0;
+            if (i < RC) {
+                const int ry = i / RX;
+                const int rx = i - ry * RX;
+                const int gx = ox + rx, gy = oy + ry;
+                const bool inb = (unsigned)gx < (unsigned)W && (unsigned)gy < (unsigned)H;
+                const int g = gy * ld + gx;
+                gi[j] = g;
+                const float c = inb ? d.c[g] : __builtin_inff();
+                const bool act = c_active(c);
+                rc[j] = c;
+                float px0 = 0.0f, py0 = 0.0f;
+                if (act) {
+                    rv[j] = fv[g];
+                    px0 = fx[g];
+                    py0 = fy[g];
+                    if (first) {
+                        rvb[j] = grad_v ? grad_v[g] : 0.0f;
+                    } else {
+                        rpbx[j] = pbx_in[g];
+                        rpby[j] = pby_in[g];
+                        rvb[j] = vb_in[g];
+                    }
+                } else {
+                    rv[j] = heav_from_c(c);
+                }
+                uint32_t f = act ? CF_ACT : 0u;
+                if (gx == W - 1) f |= CF_LASTC;
+                if (gy == H - 1) f |= CF_LASTR;
+                const bool interior = rx >= HL && rx < HL + BX && ry >= HL && ry < HL + BY;
+                if (interior && act) f |= CF_OUT;
+                fl[j] = f;
+                sA[PAD + i] = px0;
+                sB[PAD + i] = py0;
+            }
+        }
+        __syncthreads();
+        // P1: w from p^{k-1}, v^{k-1}
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) {
+            const int i = t + j * NT;
+            if (i < RC) {
+                float dd = div_p(sA[PAD + i], sA[PAD + i - 1], sB[PAD + i], sB[PAD + i - RX]);
+                sC[PAD + i] = w_of(dd, rv[j], inv_theta, (fl[j] & CF_ACT) != 0);
+            }
+        }
+        __syncthreads();
+        // P2: dual update -> p^k, keep g and m
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) {
+            const int i = t + j * NT;
+            if (i < RC) {
+                DualOut o = dual_update(sA[PAD + i], sB[PAD + i], sC[PAD + i], sC[PAD + i + 1],
+                                        sC[PAD + i + RX], fl[j], tau);
+                rnx[j] = o.px;
+                rny[j] = o.py;
+                rgx[j] = o.gx;
+                rgy[j] = o.gy;
+                rm[j] = o.m;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) {
+            const int i = t + j * NT;
+            if (i < RC) {
+                sA[PAD + i] = rnx[j];
+                sB[PAD + i] = rny[j];
+            }
+        }
+        __syncthreads();
+        // P3: u^k, s, clamp adjoint, ubar
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) {
+            const int i = t + j * NT;
+            if (i < RC) {
+                float d1 = div_p(rnx[j], sA[PAD + i - 1], rny[j], sB[PAD + i - RX]);
+                float u = u_step(rv[j], d1, theta);
+                float s = u - rc[j];
+                const bool act = (fl[j] & CF_ACT) != 0;
+                float sb = (act && s > 0.0f && s < 1.0f) ? rvb[j] : 0.0f;
+                float ub = sb;
+                if (grad_u && act) ub += grad_u[gi[j]];
+                ub = act ? ub : 0.0f;
+                rsb[j] = sb;
+                rub[j] = ub;
+                sC[PAD + i] = ub;
+            }
+        }
+        __syncthreads();
+        // P4: pbt = pbar^k + theta grad(ubar); gbar
+        float rptx[CPT], rpty[CPT];
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) {
+            const int i = t + j * NT;
+            rptx[j] = 0.0f; rpty[j] = 0.0f;
+            if (i < RC) {
+                const uint32_t f = fl[j];
+                const bool act = (f & CF_ACT) != 0;
+                float uc = sC[PAD + i];
+                float gux = (f & CF_LASTC) ? 0.0f : (sC[PAD + i + 1] - uc);
+                float guy = (f & CF_LASTR) ? 0.0f : (sC[PAD + i + RX] - uc);
+                float ptx = act ? fmaf(theta, gux, rpbx[j]) : 0.0f;
+                float pty = act ? fmaf(theta, guy, rpby[j]) : 0.0f;
+                rptx[j] = ptx;
+                rpty[j] = pty;
+                float nn = __builtin_amdgcn_sqrtf(fmaf(rgx[j], rgx[j], rgy[j] * rgy[j]));
+                float inv_n = nn > 0.0f ? __builtin_amdgcn_rcpf(nn) : 0.0f;
+                float tm = tau * rm[j];
+                float dot = fmaf(rnx[j], ptx, rny[j] * pty);
+                float k2 = tm * dot * inv_n;
+                float gbx = fmaf(tm, ptx, -k2 * rgx[j]);
+                float gby = fmaf(tm, pty, -k2 * rgy[j]);
+                gbx = (act && !(f & CF_LASTC)) ? gbx : 0.0f;
+                gby = (act && !(f & CF_LASTR)) ? gby : 0.0f;
+                sA[PAD + i] = gbx;
+                sB[PAD + i] = gby;
+            }
+        }
+        __syncthreads();
+        // P5: wbar = -div gbar; vbar^{k-1}
+        float rwb[CPT];
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) {
+            const int i = t + j * NT;
+            rwb[j] = 0.0f;
+            if (i < RC) {
+                const bool act = (fl[j] & CF_ACT) != 0;
+                float dg = div_p(sA[PAD + i], sA[PAD + i - 1], sB[PAD + i], sB[PAD + i - RX]);
+                float wb = act ? -dg : 0.0f;
+                rwb[j] = wb;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) {
+            const int i = t + j * NT;
+            if (i < RC) sC[PAD + i] = rwb[j];
+        }
+        __syncthreads();
+        // P6: pbar^{k-1}; outputs
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) {
+            const int i = t + j * NT;
+            const uint32_t f = fl[j];
+            if (i < RC && (f & CF_OUT)) {
+                float wc = rwb[j];
+                float gwx = (f & CF_LASTC) ? 0.0f : (sC[PAD + i + 1] - wc);
+                float gwy = (f & CF_LASTR) ? 0.0f : (sC[PAD + i + RX] - wc);
+                float pbx = (f & CF_LASTC) ? 0.0f : fmaf(rm[j], rptx[j], -gwx);
+                float pby = (f & CF_LASTR) ? 0.0f : fmaf(rm[j], rpty[j], -gwy);
+                float vb = fmaf(-wc, inv_theta, rub[j]);
+                const int g = gi[j];
+                pbx_out[g] = pbx;
+                pby_out[g] = pby;
+                vb_out[g] = vb;
+                sacc[g] += rsb[j];
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_fill_f32(float* __restrict__ p, int H, int W, int ld,
+                                                  float v) {
+    for (int y = blockIdx.x; y < H; y += gridDim.x)
+        for (int x = threadIdx.x; x < W; x += blockDim.x) p[y * ld + x] = v;
+}
+
+// Per-block FP64 partial sums over rows assigned in a fixed pattern; the
+// block tree is fixed too, so the result does not depend on timing.
+template <int NV>
+__device__ __forceinline__ void block_reduce_store(double (&acc)[NV], double* __restrict__ out) {
+    __shared__ double s[NV][RED_T];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) s[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int o = RED_T / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+#pragma unroll
+            for (int k = 0; k < NV; ++k) s[k][threadIdx.x] += s[k][threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) out[k] = s[k][0];
+    }
+}
+
+// grad_f, and per-block partials of (lambda, c1, c2, gamma) adjoints.
+__global__ __launch_bounds__(RED_T) void k_adj_final(
+    ImgDesc d, const float* __restrict__ sacc, const float* __restrict__ vb0,
+    float* __restrict__ grad_f, double lambda, double theta, const float* __restrict__ z,
+    const float* __restrict__ P, double c1, double c2, double* __restrict__ partials) {
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    const double tl = theta * lambda;
+    for (int y = blockIdx.x; y < d.H; y += gridDim.x) {
+        for (int x = threadIdx.x; x < d.W; x += RED_T) {
+            const int g = y * d.ld + x;
+            const float c = d.c[g];
+            double gf = 0.0;
+            if (c_active(c)) {
+                const float h = d.f[g] < 0.0f ? 1.0f : 0.0f;
+                const float s0 = h - c;   // clamp argument of v0 with u0 = H(-f)
+                double S = (double)sacc[g];
+                if (s0 > 0.0f && s0 < 1.0f) S += (double)vb0[g];
+                gf = -tl * S;
+                acc[0] += -theta * (double)d.f[g] * S;
+                if (z) {
+                    const double zz = (double)z[g];
+                    acc[1] += gf * (-2.0 * (zz - c1));
+                    acc[2] += gf * (2.0 * (zz - c2));
+                    if (P) acc[3] += gf * (double)P[g];
+                }
+            }
+            grad_f[g] = (float)gf;
+        }
+    }
+    block_reduce_store<4>(acc, partials + 4 * (int64_t)blockIdx.x);
+}
+
+__global__ __launch_bounds__(RED_T) void k_reduce_partials(const double* __restrict__ part,
+                                                           int nblk, int nv,
+                                                           double* __restrict__ out) {
+    // one thread per value, fixed sequential order over blocks
+    int k = threadIdx.x;
+    if (k < nv) {
+        double s = 0.0;
+        for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * 4 + k];
+        out[k] = s;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_fit_fwd(const float* __restrict__ z,
+                                                 const float* __restrict__ P, double c1,
+                                                 double c2, double gamma, int H, int W, int ld,
+                                                 float* __restrict__ f) {
+    for (int y = blockIdx.x; y < H; y += gridDim.x)
+        for (int x = threadIdx.x; x < W; x += blockDim.x) {
+            const int g = y * ld + x;
+            const double zz = (double)z[g];
+            const double a = zz - c1, b = zz - c2;
+            double v = a * a - b * b;
+            if (P) v += gamma * (double)P[g];
+            f[g] = (float)v;
+        }
+}
+
+__global__ __launch_bounds__(RED_T) void k_fit_bwd(const float* __restrict__ z,
+                                                   const float* __restrict__ P,
+                                                   const float* __restrict__ gf, double c1,
+                                                   double c2, int H, int W, int ld,
+                                                   double* __restrict__ partials) {
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int y = blockIdx.x; y < H; y += gridDim.x)
+        for (int x = threadIdx.x; x < W; x += RED_T) {
+            const int g = y * ld + x;
+            const double zz = (double)z[g];
+            const double b = (double)gf[g];
+            acc[0] += b * (-2.0 * (zz - c1));
+            acc[1] += b * (2.0 * (zz - c2));
+            if (P) acc[2] += b * (double)P[g];
+        }
+    block_reduce_store<4>(acc, partials + 4 * (int64_t)blockIdx.x);
+}
+
+__global__ void k_scatter_scalars(const double* __restrict__ src, double* a, double* b,
+                                  double* c, double* d) {
+    if (threadIdx.x == 0) {
+        if (a) *a = src[0];
+        if (b) *b = src[1];
+        if (c) *c = src[2];
+        if (d) *d = src[3];
+    }
+}
+
+using AdjFn = void (*)(ImgDesc, const float*, const float*, const float*, const float*,
+                       const float*, const float*, float*, float*, float*, float*, int,
+                       const float*, const float*, const int2*, const int32_t*, float, float,
+                       float);
+
+struct AdjEntry {
+    int bx, by, nt;
+    AdjFn fn;
+};
+
+const AdjEntry kAdj[] = {
+    {32, 32, 256, k_adj_step<32, 32, 256>},
+};
+int g_adj_grid[sizeof(kAdj) / sizeof(kAdj[0])];
+
+inline unsigned red_blocks(int H) { return (unsigned)(H < 1024 ? H : 1024); }
+
+}  // namespace
+
+int adj_config_count() { return (int)(sizeof(kAdj) / sizeof(kAdj[0])); }
+
+int64_t reduce_partials(int H) { return (int64_t)red_blocks(H) * 4; }
+
+int launch_adj_step(const ImgDesc& d, const float* fx, const float* fy, const float* fv,
+                    const AdjBufs& ab, int in_buf, bool first, const float* grad_v,
+                    const float* grad_u, const int2* queue, const int32_t* n_queue,
+                    int64_t max_items, int bx, int by, float theta, float tau, hipStream_t st) {
+    int ai = -1;
+    for (int i = 0; i < adj_config_count(); ++i)
+        if (kAdj[i].bx == bx && kAdj[i].by == by) ai = i;
+    if (ai < 0) {
+        set_error("no adjoint kernel for this tile size");
+        return 1;
+    }
+    if (g_adj_grid[ai] == 0) {
+        g_adj_grid[ai] = persistent_blocks(reinterpret_cast<const void*>(kAdj[ai].fn), kAdj[ai].nt, 0);
+        if (g_adj_grid[ai] <= 0) {
+            g_adj_grid[ai] = 0;
+            set_error("occupancy query failed for the adjoint kernel");
+            return 4;
+        }
+    }
+    int64_t g = g_adj_grid[ai];
+    if (max_items < g) g = max_items;
+    if (g < 1) g = 1;
+    const int out = 1 - in_buf;
+    hipLaunchKernelGGL(kAdj[ai].fn, dim3((unsigned)g), dim3(kAdj[ai].nt), 0, st, d, fx, fy, fv,
+                       ab.pbx[in_buf], ab.pby[in_buf], ab.vb[in_buf], ab.pbx[out], ab.pby[out],
+                       ab.vb[out], ab.sacc, first ? 1 : 0, grad_v, grad_u, queue, n_queue, theta,
+                       1.0f / theta, tau);
+    RDSEG_HIP_CHECK(hipGetLastError());
+    return 0;
+}
+
+int launch_fill(float* p, int H, int W, int ld, float v, hipStream_t st) {
+    hipLaunchKernelGGL(k_fill_f32, dim3(red_blocks(H)), dim3(256), 0, st, p, H, W, ld, v);
+    RDSEG_HIP_CHECK(hipGetLastError());
+    return 0;
+}
+
+int launch_adj_final(const ImgDesc& d, const float* sacc, const float* vb0, float* grad_f,
+                     double lambda, double theta, const float* z, const float* P, double c1,
+                     double c2, double* partials, int64_t n_part, double* out4,
+                     hipStream_t st) {
+    unsigned nb = red_blocks(d.H);
+    if ((int64_t)nb * 4 > n_part) {
+        set_error("reduction scratch too small");
+        return 3;
+    }
+    hipLaunchKernelGGL(k_adj_final, dim3(nb), dim3(RED_T), 0, st, d, sacc, vb0, grad_f, lambda,
+                       theta, z, P, c1, c2, partials);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(RED_T), 0, st, partials, (int)nb, 4, out4);
+    RDSEG_HIP_CHECK(hipGetLastError());
+    return 0;
+}
+
+int launch_scatter_scalars(const double* src, double* a, double* b, double* c, double* d,
+                           hipStream_t st) {
+    hipLaunchKernelGGL(k_scatter_scalars, dim3(1), dim3(64), 0, st, src, a, b, c, d);
+    RDSEG_HIP_CHECK(hipGetLastError());
+    return 0;
+}
+
+int launch_fit_forward(const float* z, const float* P, double c1, double c2, double gamma,
+                       int H, int W, int ld, float* f, hipStream_t st) {
+    hipLaunchKernelGGL(k_fit_fwd, dim3(red_blocks(H)), dim3(256), 0, st, z, P, c1, c2, gamma, H,
+                       W, ld, f);
+    RDSEG_HIP_CHECK(hipGetLastError());
+    return 0;
+}
+
+int launch_fit_backward(const float* z, const float* P, const float* grad_f, double c1,
+                        double c2, int H, int W, int ld, double* partials, int64_t n_part,
+                        double* out3, hipStream_t st) {
+    unsigned nb = red_blocks(H);
+    if ((int64_t)nb * 4 > n_part) {
+        set_error("reduction scratch too small");
+        return 3;
+    }
+    hipLaunchKernelGGL(k_fit_bwd, dim3(nb), dim3(RED_T), 0, st, z, P, grad_f, c1, c2, H, W, ld,
+                       partials);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(RED_T), 0, st, partials, (int)nb, 3, out3);
+    RDSEG_HIP_CHECK(hipGetLastError());
+    return 0;
+}
+
+}  // namespace rdseg

@@ -390,6 +390,218 @@ rdseg_status solve_impl(const float* f, rdseg_shape s, const rdseg_params* prm, 
     return enqueue_iterations(a);
 }
 
+// ------------------------------------------------------------------ batched
+struct BatchLayout {
+    std::vector<ImgDesc> descs;
+    std::vector<int64_t> tabs;   // soff | toff | moff | roff, each n + 1
+    int64_t strips = 0, tiles = 0, macros = 0, rows = 0;
+    size_t bytes = 0;
+    // device pointers (after carving)
+    ImgDesc* d_descs = nullptr;
+    int64_t* d_tabs = nullptr;
+    uint64_t* masks = nullptr;
+    int64_t* npix = nullptr;
+    int64_t* npix_total = nullptr;
+    int32_t* flags = nullptr;
+    int32_t* offs = nullptr;
+    int32_t* part = nullptr;
+    int2* queue = nullptr;
+    int32_t* totals = nullptr;
+};
+
+rdseg_status validate_batch(const rdseg_image* imgs, int32_t n, double theta, double tau,
+                            int32_t iters) {
+    if (!imgs || n < 1) return fail(RDSEG_ERR_ARG, "imgs must hold n >= 1 images");
+    if (iters < 0) return fail(RDSEG_ERR_ARG, "iters must be >= 0");
+    for (int i = 0; i < n; ++i) {
+        const rdseg_image& im = imgs[i];
+        rdseg_status r = check_shape(im.s);
+        if (r) return fail(r, "image " + std::to_string(i) + ": " + get_error());
+        r = check_scalars(im.lambda, theta, tau, im.delta);
+        if (r) return fail(r, "image " + std::to_string(i) + ": " + get_error());
+        if (!im.f || !im.u || !im.v || !im.p)
+            return fail(RDSEG_ERR_ARG, "image " + std::to_string(i) + ": f, u, v, p must be non-NULL");
+        const size_t pb = (size_t)im.s.H * im.s.ld * sizeof(float);
+        if (ranges_overlap(im.u, pb, im.f, pb) || ranges_overlap(im.v, pb, im.f, pb) ||
+            ranges_overlap(im.p, 2 * pb, im.f, pb) || ranges_overlap(im.u, pb, im.v, pb) ||
+            ranges_overlap(im.u, pb, im.p, 2 * pb) || ranges_overlap(im.v, pb, im.p, 2 * pb))
+            return fail(RDSEG_ERR_ARG, "image " + std::to_string(i) + ": u, v, p must not overlap f or each other");
+    }
+    return RDSEG_OK;
+}
+
+int resolve_batch_cfg(int32_t tile_w, int32_t tile_h, int32_t ipl) {
+    if (tile_w == 0 && tile_h == 0 && ipl == 0) return config_index(32, 32, 4);
+    return config_index(tile_w, tile_h, ipl);
+}
+
+// Host-side layout of a batch; with base != NULL also fills device pointers.
+BatchLayout layout_batch(const rdseg_image* imgs, int32_t n, int bx, int by, double theta,
+                         void* base) {
+    BatchLayout L;
+    L.descs.resize(n);
+    L.tabs.assign(4 * (size_t)(n + 1), 0);
+    int64_t* soff = L.tabs.data();
+    int64_t* toff = soff + (n + 1);
+    int64_t* moff = toff + (n + 1);
+    int64_t* roff = moff + (n + 1);
+    Carver cv(base);
+    L.d_descs = cv.take<ImgDesc>(n);
+    L.d_tabs = cv.take<int64_t>(4 * (size_t)(n + 1));
+    for (int i = 0; i < n; ++i) {
+        const rdseg_image& im = imgs[i];
+        Geo g = geo_of(im.s);
+        soff[i + 1] = soff[i] + g.strips;
+        toff[i + 1] = toff[i] + g.nt;
+        moff[i + 1] = moff[i] + macro_count(im.s, bx, by);
+        roff[i + 1] = roff[i] + im.s.H;
+        float* c = cv.take<float>(g.plane);
+        float* st1[3];
+        for (int k = 0; k < 3; ++k) st1[k] = cv.take<float>(g.plane);
+        ImgDesc d = make_desc(im.f, im.s, im.lambda, theta, im.delta, im.u, im.v, im.p, c, st1,
+                              nullptr, nullptr, bx, by);
+        d.toff = toff[i];
+        d.soff = soff[i];
+        d.moff = moff[i];
+        d.roff = roff[i];
+        L.descs[i] = d;
+    }
+    L.strips = soff[n];
+    L.tiles = toff[n];
+    L.macros = moff[n];
+    L.rows = roff[n];
+    L.masks = cv.take<uint64_t>(L.tiles);
+    L.npix = cv.take<int64_t>(n);
+    L.npix_total = cv.take<int64_t>(1);
+    L.flags = cv.take<int32_t>(L.macros);
+    L.offs = cv.take<int32_t>(L.macros);
+    L.part = cv.take<int32_t>(scan_partials(L.macros));
+    L.queue = cv.take<int2>(L.macros);
+    L.totals = cv.take<int32_t>(4);
+    L.bytes = cv.off;
+    return L;
+}
+
+OffTables tables_of(const BatchLayout& L, int n) {
+    OffTables t;
+    t.soff = L.d_tabs;
+    t.toff = L.d_tabs + (n + 1);
+    t.moff = L.d_tabs + 2 * (n + 1);
+    t.roff = L.d_tabs + 3 * (n + 1);
+    return t;
+}
+
+// Enqueue the whole batched solve (descriptors already resident).
+rdseg_status enqueue_batch(const BatchLayout& L, int n, int ci, int iters, double theta,
+                           double tau, hipStream_t st) {
+    TileCfg cfg = config_at(ci);
+    OffTables off = tables_of(L, n);
+    const ImgDesc* d0 = &L.descs[0];   // unused by the batched kernels
+    if (launch_init(d0, L.d_descs, off, n, L.rows, st)) return RDSEG_ERR_HIP;
+    if (launch_tile_masks(d0, L.d_descs, off, n, L.strips, L.masks, L.npix, st)) return RDSEG_ERR_HIP;
+    if (launch_sum_i64(L.npix, n, L.npix_total, st)) return RDSEG_ERR_HIP;
+    if (launch_macro_queue(d0, L.d_descs, off, n, L.macros, cfg.bx, cfg.by, L.masks, L.flags,
+                           L.offs, L.part, L.queue, L.totals, st))
+        return RDSEG_ERR_HIP;
+    SolvePlanArgs a;
+    a.d0 = d0;
+    a.descs = L.d_descs;
+    a.queue = L.queue;
+    a.n_queue = L.totals;
+    a.max_items = L.macros;
+    a.ci = ci;
+    a.iters = iters;
+    a.theta = (float)theta;
+    a.inv_theta = (float)(1.0 / theta);
+    a.tau = (float)tau;
+    a.ckpt_every = 0;
+    a.tape = nullptr;
+    a.npix = L.npix_total;
+    a.st = st;
+    return enqueue_iterations(a);
+}
+
+// ------------------------------------------------------------------ backward
+constexpr int kAdjTile = 32;   // macro tile of the reverse sweep and its recompute
+
+struct BackWs {
+    float* c;
+    float* seg;        // (ce - 1) slots of [3][H][ld]
+    float* ab[6];      // pbx0, pby0, vb0, pbx1, pby1, vb1
+    float* sacc;
+    uint64_t* masks;
+    int64_t* npix;
+    int32_t* flags;
+    int32_t* offs;
+    int32_t* part;
+    int2* queue;
+    int32_t* totals;
+    double* red;       // reduction partials
+    double* out4;
+    size_t bytes;
+};
+
+BackWs carve_back(void* base, const rdseg_shape& s, int ce) {
+    Geo g = geo_of(s);
+    Carver cv(base);
+    BackWs w;
+    w.c = cv.take<float>(g.plane);
+    w.seg = cv.take<float>((size_t)std::max(ce - 1, 0) * 3 * g.plane);
+    for (int k = 0; k < 6; ++k) w.ab[k] = cv.take<float>(g.plane);
+    w.sacc = cv.take<float>(g.plane);
+    w.masks = cv.take<uint64_t>(g.nt);
+    w.npix = cv.take<int64_t>(1);
+    w.flags = cv.take<int32_t>(g.nt);
+    w.offs = cv.take<int32_t>(g.nt);
+    w.part = cv.take<int32_t>(scan_partials(g.nt));
+    w.queue = cv.take<int2>(g.nt);
+    w.totals = cv.take<int32_t>(4);
+    w.red = cv.take<double>(reduce_partials(s.H));
+    w.out4 = cv.take<double>(4);
+    w.bytes = cv.off;
+    return w;
+}
+
+size_t reduce_ws_bytes(const rdseg_shape& s) {
+    Carver cv(nullptr);
+    cv.take<double>(reduce_partials(s.H));
+    cv.take<double>(4);
+    return cv.off;
+}
+
+struct BatchPlan {
+    std::vector<rdseg_image> imgs;
+    double theta, tau;
+    int32_t iters, ci;
+    void* mem = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+bool same_batch(const BatchPlan& P, const rdseg_image* imgs, int32_t n, double theta, double tau,
+                int32_t iters, int ci) {
+    if ((int32_t)P.imgs.size() != n || P.theta != theta || P.tau != tau || P.iters != iters ||
+        P.ci != ci)
+        return false;
+    for (int i = 0; i < n; ++i) {
+        const rdseg_image& a = P.imgs[i];
+        const rdseg_image& b = imgs[i];
+        if (a.f != b.f || a.u != b.u || a.v != b.v || a.p != b.p || a.s.H != b.s.H ||
+            a.s.W != b.s.W || a.s.ld != b.s.ld || a.lambda != b.lambda ||
+            memcmp(&a.delta, &b.delta, sizeof(double)) != 0)
+            return false;
+    }
+    return true;
+}
+
+void plan_free(BatchPlan* P) {
+    if (!P) return;
+    if (P->exec) (void)hipGraphExecDestroy(P->exec);
+    if (P->graph) (void)hipGraphDestroy(P->graph);
+    if (P->mem) (void)hipFree(P->mem);
+    delete P;
+}
+
 }  // namespace
 
 // ====================================================================== C ABI
@@ -459,6 +671,248 @@ rdseg_status rdseg_solve(const float* f, rdseg_shape s, const rdseg_params* prm,
                          size_t ws_bytes, void* stream) {
     return solve_impl(f, s, prm, u0, p0, u, v, p, tape, ws, ws_bytes,
                       static_cast<hipStream_t>(stream), -1);
+}
+
+size_t rdseg_batched_workspace_size(const rdseg_image* imgs, int32_t n, int32_t tile_w,
+                                    int32_t tile_h) {
+    if (!imgs || n < 1) return 0;
+    for (int i = 0; i < n; ++i)
+        if (!shape_ok(imgs[i].s)) return 0;
+    int bx = tile_w > 0 ? tile_w : 32, by = tile_h > 0 ? tile_h : 32;
+    if (bx % 8 || by % 8) return 0;
+    return layout_batch(imgs, n, bx, by, 1.0, nullptr).bytes;
+}
+
+rdseg_status rdseg_solve_batched(const rdseg_image* imgs, int32_t n, double theta, double tau,
+                                 int32_t iters, int32_t iters_per_launch, int32_t tile_w,
+                                 int32_t tile_h, void** graph_plan, void* ws, size_t ws_bytes,
+                                 void* stream) {
+    rdseg_status r = validate_batch(imgs, n, theta, tau, iters);
+    if (r) return r;
+    int ci = resolve_batch_cfg(tile_w, tile_h, iters_per_launch);
+    if (ci < 0) return fail(RDSEG_ERR_ARG, "tile_w / tile_h / iters_per_launch is not a compiled configuration");
+    TileCfg cfg = config_at(ci);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+
+    if (!graph_plan) {
+        // eager: caller workspace, descriptors uploaded synchronously
+        BatchLayout need = layout_batch(imgs, n, cfg.bx, cfg.by, theta, nullptr);
+        if (!ws || ws_bytes < need.bytes)
+            return fail(RDSEG_ERR_WORKSPACE, "workspace too small: need " + std::to_string(need.bytes) + " bytes");
+        BatchLayout L = layout_batch(imgs, n, cfg.bx, cfg.by, theta, ws);
+        if (hipMemcpyAsync(L.d_descs, L.descs.data(), n * sizeof(ImgDesc), hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(L.d_tabs, L.tabs.data(), L.tabs.size() * sizeof(int64_t), hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return fail(RDSEG_ERR_HIP, "uploading batch descriptors failed");
+        return enqueue_batch(L, n, ci, iters, theta, tau, st);
+    }
+
+    BatchPlan* P = static_cast<BatchPlan*>(*graph_plan);
+    if (P) {
+        if (!same_batch(*P, imgs, n, theta, tau, iters, ci))
+            return fail(RDSEG_ERR_ARG, "plan was built for a different batch");
+        if (hipGraphLaunch(P->exec, st) != hipSuccess) return fail(RDSEG_ERR_HIP, "hipGraphLaunch failed");
+        return RDSEG_OK;
+    }
+    // build a plan: own workspace, resident descriptors, captured graph
+    P = new BatchPlan();
+    P->imgs.assign(imgs, imgs + n);
+    P->theta = theta;
+    P->tau = tau;
+    P->iters = iters;
+    P->ci = ci;
+    BatchLayout need = layout_batch(imgs, n, cfg.bx, cfg.by, theta, nullptr);
+    if (hipMalloc(&P->mem, need.bytes) != hipSuccess) {
+        plan_free(P);
+        return fail(RDSEG_ERR_HIP, "hipMalloc of the plan workspace failed");
+    }
+    BatchLayout L = layout_batch(imgs, n, cfg.bx, cfg.by, theta, P->mem);
+    if (hipMemcpy(L.d_descs, L.descs.data(), n * sizeof(ImgDesc), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(L.d_tabs, L.tabs.data(), L.tabs.size() * sizeof(int64_t), hipMemcpyHostToDevice) != hipSuccess) {
+        plan_free(P);
+        return fail(RDSEG_ERR_HIP, "uploading batch descriptors failed");
+    }
+    // occupancy query outside the capture
+    if (prepare_iterate(ci, true)) {
+        plan_free(P);
+        return RDSEG_ERR_HIP;
+    }
+    hipStream_t cap = nullptr;
+    if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) {
+        plan_free(P);
+        return fail(RDSEG_ERR_HIP, "hipStreamCreate failed");
+    }
+    bool timing_was = g_timing.on;
+    g_timing.on = false;   // no events inside the captured graph
+    r = RDSEG_OK;
+    if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        r = fail(RDSEG_ERR_HIP, "hipStreamBeginCapture failed");
+    } else {
+        r = enqueue_batch(L, n, ci, iters, theta, tau, cap);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(cap, &g);
+        if (r == RDSEG_OK && e != hipSuccess) r = fail(RDSEG_ERR_HIP, "hipStreamEndCapture failed");
+        P->graph = g;
+        if (r == RDSEG_OK && hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0) != hipSuccess)
+            r = fail(RDSEG_ERR_HIP, "hipGraphInstantiate failed");
+    }
+    g_timing.on = timing_was;
+    (void)hipStreamDestroy(cap);
+    if (r) {
+        plan_free(P);
+        return r;
+    }
+    *graph_plan = P;
+    if (hipGraphLaunch(P->exec, st) != hipSuccess) return fail(RDSEG_ERR_HIP, "hipGraphLaunch failed");
+    return RDSEG_OK;
+}
+
+rdseg_status rdseg_plan_destroy(void* plan) {
+    plan_free(static_cast<BatchPlan*>(plan));
+    return RDSEG_OK;
+}
+
+size_t rdseg_backward_workspace_size(const rdseg_shape* s, const rdseg_params* prm) {
+    if (!s || !prm || !shape_ok(*s) || prm->ckpt_every <= 0) return 0;
+    return carve_back(nullptr, *s, prm->ckpt_every).bytes;
+}
+
+rdseg_status rdseg_backward(const float* f, rdseg_shape s, const rdseg_params* prm,
+                            const float* tape, const float* grad_u, const float* grad_v,
+                            float* grad_f, double* grad_lambda, const rdseg_fit* fit,
+                            double* grad_c1, double* grad_c2, double* grad_gamma, void* ws,
+                            size_t ws_bytes, void* stream) {
+    if (!prm) return fail(RDSEG_ERR_ARG, "prm is NULL");
+    rdseg_status r = check_shape(s);
+    if (r) return r;
+    r = check_scalars(prm->lambda, prm->theta, prm->tau, prm->delta);
+    if (r) return r;
+    if (prm->iters < 0) return fail(RDSEG_ERR_ARG, "iters must be >= 0");
+    if (!f || !grad_u || !grad_f || !grad_lambda)
+        return fail(RDSEG_ERR_ARG, "f, grad_u, grad_f and grad_lambda must be non-NULL");
+    if (!tape || prm->ckpt_every <= 0)
+        return fail(RDSEG_ERR_TAPE, "backward needs the tape of a solve with ckpt_every > 0");
+    if (fit && !fit->z) return fail(RDSEG_ERR_ARG, "fit->z must be non-NULL");
+    const size_t pb = (size_t)s.H * s.ld * sizeof(float);
+    if (ranges_overlap(grad_f, pb, f, pb) || ranges_overlap(grad_f, pb, grad_u, pb) ||
+        (grad_v && ranges_overlap(grad_f, pb, grad_v, pb)))
+        return fail(RDSEG_ERR_ARG, "grad_f must not overlap f, grad_u or grad_v");
+    const int ce = prm->ckpt_every;
+    BackWs need = carve_back(nullptr, s, ce);
+    if (!ws || ws_bytes < need.bytes)
+        return fail(RDSEG_ERR_WORKSPACE, "workspace too small: need " + std::to_string(need.bytes) + " bytes");
+    BackWs w = carve_back(ws, s, ce);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Geo g = geo_of(s);
+    const int fci = config_index(kAdjTile, kAdjTile, 2);
+    if (fci < 0) return fail(RDSEG_ERR_ARG, "recompute configuration missing");
+    float* nost[3] = {nullptr, nullptr, nullptr};
+    ImgDesc d = make_desc(f, s, prm->lambda, prm->theta, prm->delta, nullptr, nullptr, nullptr,
+                          w.c, nost, nullptr, nullptr, kAdjTile, kAdjTile);
+    OffTables off{nullptr, nullptr, nullptr, nullptr};
+    if (launch_init(&d, nullptr, off, 1, s.H, st)) return RDSEG_ERR_HIP;   // c only
+    if (launch_tile_masks(&d, nullptr, off, 1, g.strips, w.masks, w.npix, st)) return RDSEG_ERR_HIP;
+    const int64_t nm = macro_count(s, kAdjTile, kAdjTile);
+    if (launch_macro_queue(&d, nullptr, off, 1, nm, kAdjTile, kAdjTile, w.masks, w.flags, w.offs,
+                           w.part, w.queue, w.totals, st))
+        return RDSEG_ERR_HIP;
+    if (launch_fill(w.sacc, s.H, s.W, (int)s.ld, 0.0f, st)) return RDSEG_ERR_HIP;
+    const float theta = (float)prm->theta, inv_theta = (float)(1.0 / prm->theta);
+    const float tau = (float)prm->tau;
+    AdjBufs ab;
+    ab.pbx[0] = w.ab[0]; ab.pby[0] = w.ab[1]; ab.vb[0] = w.ab[2];
+    ab.pbx[1] = w.ab[3]; ab.pby[1] = w.ab[4]; ab.vb[1] = w.ab[5];
+    ab.sacc = w.sacc;
+    const int K = prm->iters;
+    const int nseg = (K + ce - 1) / ce;
+    const int64_t plane = g.plane;
+    int in_buf = 0;
+    for (int sg = nseg - 1; sg >= 0; --sg) {
+        const int k0 = sg * ce;
+        const int len = std::min(ce, K - k0);
+        auto slot = [&](int j) -> float* {
+            return j == 0 ? const_cast<float*>(tape) + (int64_t)sg * 3 * plane
+                          : w.seg + (int64_t)(j - 1) * 3 * plane;
+        };
+        // recompute the forward states k0+1 .. k0+len-1 of this segment
+        for (int j = 0; j + 1 < len; ++j) {
+            ImgDesc dr = d;
+            dr.st[1][0] = slot(j); dr.st[1][1] = slot(j) + plane; dr.st[1][2] = slot(j) + 2 * plane;
+            dr.st[0][0] = slot(j + 1); dr.st[0][1] = slot(j + 1) + plane; dr.st[0][2] = slot(j + 1) + 2 * plane;
+            if (launch_iterate(fci, &dr, nullptr, false, w.queue, w.totals, nm, 1, 1, false, theta,
+                               inv_theta, tau, st))
+                return RDSEG_ERR_HIP;
+        }
+        // reverse sweep
+        for (int k = k0 + len; k >= k0 + 1; --k) {
+            float* sl = slot(k - 1 - k0);
+            const bool first = (k == K);
+            if (launch_adj_step(d, sl + plane, sl + 2 * plane, sl, ab, in_buf, first, grad_v,
+                                first ? grad_u : nullptr, w.queue, w.totals, nm, kAdjTile,
+                                kAdjTile, theta, tau, st))
+                return RDSEG_ERR_HIP;
+            in_buf = 1 - in_buf;
+        }
+    }
+    const float* vb0 = ab.vb[in_buf];
+    if (K == 0) {
+        if (grad_v) {
+            vb0 = grad_v;
+        } else {
+            if (launch_fill(ab.vb[0], s.H, s.W, (int)s.ld, 0.0f, st)) return RDSEG_ERR_HIP;
+            vb0 = ab.vb[0];
+        }
+    }
+    if (launch_adj_final(d, w.sacc, vb0, grad_f, prm->lambda, prm->theta, fit ? fit->z : nullptr,
+                         fit ? fit->P : nullptr, fit ? fit->c1 : 0.0, fit ? fit->c2 : 0.0, w.red,
+                         reduce_partials(s.H), w.out4, st))
+        return RDSEG_ERR_HIP;
+    if (launch_scatter_scalars(w.out4, grad_lambda, fit ? grad_c1 : nullptr, fit ? grad_c2 : nullptr,
+                               fit ? grad_gamma : nullptr, st))
+        return RDSEG_ERR_HIP;
+    return RDSEG_OK;
+}
+
+rdseg_status rdseg_fit_forward(const rdseg_fit* fit, rdseg_shape s, float* f, void* stream) {
+    rdseg_status r = check_shape(s);
+    if (r) return r;
+    if (!fit || !fit->z || !f) return fail(RDSEG_ERR_ARG, "fit, fit->z and f must be non-NULL");
+    if (!(isfinite(fit->c1) && isfinite(fit->c2) && isfinite(fit->gamma)))
+        return fail(RDSEG_ERR_ARG, "c1, c2, gamma must be finite");
+    const size_t pb = (size_t)s.H * s.ld * sizeof(float);
+    if (ranges_overlap(f, pb, fit->z, pb) || (fit->P && ranges_overlap(f, pb, fit->P, pb)))
+        return fail(RDSEG_ERR_ARG, "f must not overlap z or P");
+    if (launch_fit_forward(fit->z, fit->P, fit->c1, fit->c2, fit->gamma, s.H, s.W, (int)s.ld, f,
+                           static_cast<hipStream_t>(stream)))
+        return RDSEG_ERR_HIP;
+    return RDSEG_OK;
+}
+
+size_t rdseg_reduce_workspace_size(const rdseg_shape* s) {
+    if (!s || !shape_ok(*s)) return 0;
+    return reduce_ws_bytes(*s);
+}
+
+rdseg_status rdseg_fit_backward(const rdseg_fit* fit, rdseg_shape s, const float* grad_f,
+                                double* grad_c1, double* grad_c2, double* grad_gamma, void* ws,
+                                size_t ws_bytes, void* stream) {
+    rdseg_status r = check_shape(s);
+    if (r) return r;
+    if (!fit || !fit->z || !grad_f) return fail(RDSEG_ERR_ARG, "fit, fit->z and grad_f must be non-NULL");
+    if (!(isfinite(fit->c1) && isfinite(fit->c2)))
+        return fail(RDSEG_ERR_ARG, "c1, c2 must be finite");
+    size_t need = reduce_ws_bytes(s);
+    if (!ws || ws_bytes < need)
+        return fail(RDSEG_ERR_WORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
+    Carver cv(ws);
+    double* red = cv.take<double>(reduce_partials(s.H));
+    double* out = cv.take<double>(4);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (launch_fit_backward(fit->z, fit->P, grad_f, fit->c1, fit->c2, s.H, s.W, (int)s.ld, red,
+                            reduce_partials(s.H), out, st))
+        return RDSEG_ERR_HIP;
+    if (launch_scatter_scalars(out, grad_c1, grad_c2, grad_gamma, nullptr, st)) return RDSEG_ERR_HIP;
+    return RDSEG_OK;
 }
 
 int32_t rdseg_config_count(void) { return config_count(); }

@@ -109,6 +109,21 @@ __global__ void k_fill_i64(int64_t* p, int64_t n, int64_t v) {
 
 __global__ void k_i32_to_i64(const int32_t* a, int64_t* b) { *b = (int64_t)*a; }
 
+// Fixed-order sum of n int64 values (one block).
+__global__ __launch_bounds__(256) void k_sum_i64(const int64_t* __restrict__ a, int n,
+                                                 int64_t* __restrict__ out) {
+    __shared__ int64_t s[256];
+    int64_t acc = 0;
+    for (int i = threadIdx.x; i < n; i += 256) acc += a[i];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = s[0];
+}
+
 // ---------------------------------------------------------------- tile masks
 template <bool BATCHED>
 __global__ __launch_bounds__(256) void k_tile_masks(ImgDesc d0, const ImgDesc* __restrict__ descs,
@@ -263,6 +278,12 @@ int launch_tile_masks(const ImgDesc* d0, const ImgDesc* descs, OffTables off, in
     else
         hipLaunchKernelGGL(k_tile_masks<false>, dim3(nblk(n_strips, 4)), dim3(256), 0, st, *d0,
                            descs, off, n_img, n_strips, masks, npix);
+    RDSEG_HIP_CHECK(hipGetLastError());
+    return 0;
+}
+
+int launch_sum_i64(const int64_t* a, int n, int64_t* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_sum_i64, dim3(1), dim3(256), 0, st, a, n, out);
     RDSEG_HIP_CHECK(hipGetLastError());
     return 0;
 }

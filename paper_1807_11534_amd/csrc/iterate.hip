@@ -51,6 +51,7 @@ __global__ __launch_bounds__(256) void k_init(ImgDesc d0, const ImgDesc* __restr
             float px = (act && x < d.W - 1 && d.p0x) ? d.p0x[g] : 0.0f;
             float py = (act && y < d.H - 1 && d.p0y) ? d.p0y[g] : 0.0f;
             d.c[g] = c;
+            if (!d.u) continue;   // c-only mode (used by the adjoint)
             d.u[g] = u0;
 #pragma unroll
             for (int b = 0; b < 2; ++b) {
@@ -236,8 +237,13 @@ struct CfgEntry {
 
 const CfgEntry kCfgs[] = {
     RDSEG_CFG(8, 8, 1, 64),
+    RDSEG_CFG(8, 8, 4, 128),
+    RDSEG_CFG(8, 8, 8, 256),
+    RDSEG_CFG(8, 8, 16, 512),
     RDSEG_CFG(16, 16, 1, 128),
     RDSEG_CFG(16, 16, 2, 128),
+    RDSEG_CFG(16, 16, 4, 256),
+    RDSEG_CFG(16, 16, 8, 512),
     RDSEG_CFG(32, 16, 2, 256),
     RDSEG_CFG(32, 32, 2, 256),
     RDSEG_CFG(32, 32, 4, 256),
@@ -289,21 +295,29 @@ int launch_init(const ImgDesc* d0, const ImgDesc* descs, OffTables off, int n_im
     return 0;
 }
 
-int launch_iterate(int ci, const ImgDesc* d0, const ImgDesc* descs, bool batched,
-                   const int2* queue, const int32_t* n_queue, int64_t max_items, int in_buf,
-                   int nit, bool write_u, float theta, float inv_theta, float tau,
-                   hipStream_t st) {
+int prepare_iterate(int ci, bool batched) {
     const CfgEntry& e = kCfgs[ci];
     IterFn fn = batched ? e.batched : e.single;
     int& cached = g_grid_cache[ci][batched ? 1 : 0];
     if (cached == 0) {
         cached = persistent_blocks(reinterpret_cast<const void*>(fn), e.cfg.nt, 0);
         if (cached <= 0) {
+            cached = 0;
             set_error("occupancy query failed for the iteration kernel");
             return 4;
         }
     }
-    int64_t g = cached;
+    return 0;
+}
+
+int launch_iterate(int ci, const ImgDesc* d0, const ImgDesc* descs, bool batched,
+                   const int2* queue, const int32_t* n_queue, int64_t max_items, int in_buf,
+                   int nit, bool write_u, float theta, float inv_theta, float tau,
+                   hipStream_t st) {
+    const CfgEntry& e = kCfgs[ci];
+    IterFn fn = batched ? e.batched : e.single;
+    if (prepare_iterate(ci, batched)) return 4;
+    int64_t g = g_grid_cache[ci][batched ? 1 : 0];
     if (max_items < g) g = max_items;
     g = ((g + 7) / 8) * 8;
     if (g < 8) g = 8;

@@ -46,6 +46,9 @@ int launch_scan_ints(const int32_t* counts, int64_t n, int32_t* out, int32_t* pa
 int launch_tile_masks(const ImgDesc* d0, const ImgDesc* descs, OffTables off, int n_img,
                       int64_t n_strips, uint64_t* masks, int64_t* npix, hipStream_t st);
 
+// Fixed-order sum of n int64 device values into *out.
+int launch_sum_i64(const int64_t* a, int n, int64_t* out, hipStream_t st);
+
 // Single-image active-set outputs from dense masks.
 int launch_tile_list(const uint64_t* masks, int64_t n_tiles, int32_t* flags_scratch,
                      int32_t* offs, int32_t* part, int32_t* n_listed, int32_t* tile_ids,
@@ -72,6 +75,9 @@ struct TileCfg {
 int config_count();
 TileCfg config_at(int i);
 int config_index(int bx, int by, int it);   // -1 if not compiled
+
+// Occupancy query for the persistent grid of configuration ci (cached).
+int prepare_iterate(int ci, bool batched);
 
 // One launch of the temporally blocked iteration kernel: `nit` (<= cfg.it)
 // iterations over the queued macro tiles, reading state buffer `in_buf` and
@@ -107,6 +113,9 @@ int launch_fit_backward(const float* z, const float* P, const float* grad_f, dou
                         double c2, int H, int W, int ld, double* partials, int64_t n_part,
                         double* out3, hipStream_t st);
 int64_t reduce_partials(int H);
+int launch_fill(float* p, int H, int W, int ld, float v, hipStream_t st);
+int launch_scatter_scalars(const double* src, double* a, double* b, double* c, double* d,
+                           hipStream_t st);
 
 int persistent_blocks(const void* kernel, int threads, size_t dyn_lds);
 

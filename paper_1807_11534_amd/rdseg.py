@@ -113,6 +113,120 @@ def solve(f, lam, theta=THETA, tau=TAU, delta=math.inf, iters=100, u0=None, p0=N
     return u, v, p
 
 
+class BatchedSolver:
+    """Many independent images solved over one global tile queue.
+
+    graph=True captures the whole sequence (init, compaction, every iteration
+    launch) into a hipGraph on the first run and replays it afterwards; only
+    the contents of the f tensors may change between runs."""
+
+    def __init__(self, fs, lams, deltas, theta=THETA, tau=TAU, iters=100, tile=(32, 32),
+                 iters_per_launch=4, graph=True):
+        self.lib = _lib.load()
+        n = len(fs)
+        if not (len(lams) == len(deltas) == n and n > 0):
+            raise ValueError("fs, lams and deltas must have the same non-zero length")
+        self.fs = list(fs)
+        self.out = []
+        arr = (Image * n)()
+        for i, f in enumerate(self.fs):
+            s = shape_of(f)
+            u, v, p = _empty_like_grid(f), _empty_like_grid(f), _empty_like_grid(f, 2)
+            self.out.append((u, v, p))
+            arr[i] = Image(f.data_ptr(), u.data_ptr(), v.data_ptr(), p.data_ptr(), s,
+                           float(lams[i]), float(deltas[i]))
+        self.imgs = arr
+        self.n = n
+        self.theta, self.tau, self.iters = float(theta), float(tau), int(iters)
+        self.tile, self.ipl = tile, int(iters_per_launch)
+        self.graph = graph
+        self.plan = ctypes.c_void_p(None)
+        self.ws = None
+        if not graph:
+            nbytes = self.lib.rdseg_batched_workspace_size(arr, n, tile[0], tile[1])
+            if nbytes == 0:
+                raise ValueError("invalid batch")
+            self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.fs[0].device)
+
+    def run(self):
+        plan = ctypes.byref(self.plan) if self.graph else None
+        ws = self.ws
+        check(self.lib.rdseg_solve_batched(self.imgs, self.n, self.theta, self.tau, self.iters,
+                                           self.ipl, self.tile[0], self.tile[1], plan, _vp(ws),
+                                           0 if ws is None else ws.numel(), _stream()))
+        return self.out
+
+    def close(self):
+        if self.plan.value:
+            check(self.lib.rdseg_plan_destroy(self.plan))
+            self.plan = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def backward(f, lam, theta, tau, delta, iters, ckpt_every, tape, grad_u, grad_v=None,
+             fit=None):
+    """Reverse mode of the solve that wrote `tape` (default start).
+
+    fit: None or (z, P or None, c1, c2, gamma) -- the f of the solve came from
+    fit_forward with these values.  Returns (grad_f, grad_lambda) and, with fit,
+    (grad_c1, grad_c2, grad_gamma) as float64 device scalars."""
+    lib = _lib.load()
+    s = shape_of(f)
+    prm = params(lam, theta, tau, delta, iters, 0, 0, 0, ckpt_every)
+    nbytes = lib.rdseg_backward_workspace_size(ctypes.byref(s), ctypes.byref(prm))
+    if nbytes == 0:
+        raise ValueError("invalid shape or ckpt_every")
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=f.device)
+    gf = _empty_like_grid(f)
+    scal = torch.zeros(4, dtype=torch.float64, device=f.device)
+    fitp = None
+    if fit is not None:
+        z, P, c1, c2, gamma = fit
+        fitp = ctypes.byref(Fit(z.data_ptr(), None if P is None else P.data_ptr(), float(c1),
+                                float(c2), float(gamma)))
+    check(lib.rdseg_backward(_vp(f), s, ctypes.byref(prm), _vp(tape), _vp(grad_u), _vp(grad_v),
+                             _vp(gf), ctypes.c_void_p(scal.data_ptr()), fitp,
+                             ctypes.c_void_p(scal.data_ptr() + 8),
+                             ctypes.c_void_p(scal.data_ptr() + 16),
+                             ctypes.c_void_p(scal.data_ptr() + 24), _vp(ws), ws.numel(),
+                             _stream()))
+    if fit is None:
+        return gf, scal[0]
+    return gf, scal[0], scal[1], scal[2], scal[3]
+
+
+def fit_forward(z, c1, c2, gamma=0.0, P=None):
+    """Fitting term of eq. CV (P None) or eq. DS, evaluated on the GPU."""
+    lib = _lib.load()
+    s = shape_of(z)
+    f = _empty_like_grid(z)
+    fit = Fit(z.data_ptr(), None if P is None else P.data_ptr(), float(c1), float(c2),
+              float(gamma))
+    check(lib.rdseg_fit_forward(ctypes.byref(fit), s, _vp(f), _stream()))
+    return f
+
+
+def fit_backward(z, c1, c2, grad_f, P=None):
+    """(dL/dc1, dL/dc2, dL/dgamma) from dL/df, as float64 device scalars."""
+    lib = _lib.load()
+    s = shape_of(z)
+    nbytes = lib.rdseg_reduce_workspace_size(ctypes.byref(s))
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=z.device)
+    out = torch.zeros(3, dtype=torch.float64, device=z.device)
+    fit = Fit(z.data_ptr(), None if P is None else P.data_ptr(), float(c1), float(c2), 0.0)
+    check(lib.rdseg_fit_backward(ctypes.byref(fit), s, _vp(grad_f),
+                                 ctypes.c_void_p(out.data_ptr()),
+                                 ctypes.c_void_p(out.data_ptr() + 8),
+                                 ctypes.c_void_p(out.data_ptr() + 16), _vp(ws), ws.numel(),
+                                 _stream()))
+    return out[0], out[1], out[2]
+
+
 def configs():
     """Compiled (tile_w, tile_h, iters_per_launch, threads) configurations."""
     lib = _lib.load()

@@ -110,3 +110,74 @@ def rof_dual_objective(f, theta, delta, v, p):
     G = grad_matrix(*f.shape)
     d = (-G.T @ np.concatenate([p[0].ravel(), p[1].ravel()])).reshape(f.shape)
     return ((theta * d - v) ** 2)[A].sum() - 2 * theta * (h * d)[~A].sum()
+
+
+def _shift(a, dy, dx):
+    """b[y, x] = a[y + dy, x + dx], zero outside the grid."""
+    H, W = a.shape
+    out = np.zeros_like(a)
+    ys_dst = slice(max(0, -dy), H - max(0, dy))
+    xs_dst = slice(max(0, -dx), W - max(0, dx))
+    ys_src = slice(max(0, dy), H - max(0, -dy))
+    xs_src = slice(max(0, dx), W - max(0, -dx))
+    out[ys_dst, xs_dst] = a[ys_src, xs_src]
+    return out
+
+
+def reverse_with_w_noise(f, lam, theta, tau, delta, iters, ubar, rng=None, amp=0.0):
+    """FP64 reverse mode of the restricted iteration (default start) in which the
+    forward dual argument w is perturbed by amp * (|div p| + |v/theta|) * N(0,1)
+    at every step -- a model of rounding w in a lower precision.  With amp = 0
+    it is a second, array-level formulation of the oracle's reverse sweep.
+    Returns (fbar, lambar)."""
+    f64 = np.asarray(f, np.float32).astype(np.float64)
+    H, W = f64.shape
+    A = np.abs(f64) < delta
+    h = (f64 < 0).astype(np.float64)
+    c = np.where(A, theta * lam * f64, 0.0)
+    lastc = np.zeros((H, W), bool)
+    lastc[:, -1] = True
+    lastr = np.zeros((H, W), bool)
+    lastr[-1, :] = True
+
+    def div(px, py):
+        return (px - _shift(px, 0, -1)) + (py - _shift(py, -1, 0))
+
+    def fwd(px, py, v, nz):
+        d = div(px, py)
+        w = np.where(A, d, 0.0) - v / theta + nz * (np.abs(d) + np.abs(v / theta))
+        gx = np.where(lastc, 0.0, _shift(w, 0, 1) - w)
+        gy = np.where(lastr, 0.0, _shift(w, 1, 0) - w)
+        m = 1.0 / (1.0 + tau * np.sqrt(gx ** 2 + gy ** 2))
+        nx = np.where(A, (px + tau * gx) * m, 0.0)
+        ny = np.where(A, (py + tau * gy) * m, 0.0)
+        s = v - theta * div(nx, ny) - c
+        return nx, ny, np.where(A, np.clip(s, 0.0, 1.0), h), gx, gy, m, s
+
+    v = np.where(A, np.clip(h - c, 0.0, 1.0), h)
+    states = [(np.zeros((H, W)), np.zeros((H, W)), v)]
+    noises = []
+    for _ in range(iters):
+        nz = amp * rng.normal(size=(H, W)) if amp > 0 else 0.0
+        noises.append(nz)
+        nx, ny, vn, _, _, _, _ = fwd(*states[-1], nz)
+        states.append((nx, ny, vn))
+    pbx, pby, vb = np.zeros((H, W)), np.zeros((H, W)), np.zeros((H, W))
+    S = np.zeros((H, W))
+    for k in range(iters, 0, -1):
+        nx, ny, _, gx, gy, m, s = fwd(*states[k - 1], noises[k - 1])
+        sb = np.where(A & (s > 0) & (s < 1), vb, 0.0)
+        ub = np.where(A, sb + (ubar if k == iters else 0.0), 0.0)
+        S += sb
+        ptx = np.where(A, pbx + theta * np.where(lastc, 0.0, _shift(ub, 0, 1) - ub), 0.0)
+        pty = np.where(A, pby + theta * np.where(lastr, 0.0, _shift(ub, 1, 0) - ub), 0.0)
+        n = np.sqrt(gx ** 2 + gy ** 2)
+        inv_n = np.where(n > 0, 1.0 / np.where(n > 0, n, 1.0), 0.0)
+        k2 = tau * m * (nx * ptx + ny * pty) * inv_n
+        gbx = np.where(A & ~lastc, tau * m * ptx - k2 * gx, 0.0)
+        gby = np.where(A & ~lastr, tau * m * pty - k2 * gy, 0.0)
+        wb = np.where(A, -div(gbx, gby), 0.0)
+        pbx = np.where(A & ~lastc, m * ptx - np.where(lastc, 0.0, _shift(wb, 0, 1) - wb), 0.0)
+        pby = np.where(A & ~lastr, m * pty - np.where(lastr, 0.0, _shift(wb, 1, 0) - wb), 0.0)
+        vb = np.where(A, ub - wb / theta, 0.0)
+    return np.where(A, -theta * lam * S, 0.0), float((-theta * f64 * S)[A].sum())
