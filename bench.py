@@ -8,17 +8,21 @@ pixel-updates per second over the whole step (sum over solves of |RD| times
 iterations, divided by the step time).
 
 Also reported on the same line:
-  roofline      achieved algorithmic HBM bytes per second of the iteration
-                kernel (28 bytes per active pixel-iteration), measured with HIP
-                events around every launch of that kernel in a separate pass
-                over the same step, against the 8 TB/s HBM peak;
+  roofline      the dominant iteration-kernel instantiation (most kernel time in
+                the step): algorithmic bytes (28 per active pixel-iteration)
+                per launch over its average launch duration, from HIP events
+                around every launch on its stream, in a separate pass over the
+                same step; peak = 8 TB/s HBM;
   cpu_baseline  the FP64 oracle (single thread) on a bounded sample of the same
                 sweep (every case, fewer iterations), in the same unit;
   sweep         per case: active fraction, GPU time, label mismatch against
-                the delta = inf solve at the same lambda, speed-up over it.
+                the delta = inf solve at the same lambda, speed-up over it;
+  extras        the batched workload (512 images, sides 64..1024, 300
+                iterations, one hipGraph) against 512 sequential solves, also
+                at delta = inf; forward + adjoint ms of the 2048^2
+                differentiation workload; the 4096^2 distance-selective solve.
 
-`python bench.py --gpus N --steps K --warmup W`; only N = 1 is supported (the
-build runs on one GPU).
+`python bench.py --gpus N --steps K --warmup W`; only N = 1 is supported.
 """
 import argparse
 import json
@@ -44,12 +48,133 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--size", type=int, default=1024)
     ap.add_argument("--iters", type=int, default=500)
-    ap.add_argument("--cpu-iters", type=int, default=30,
+    ap.add_argument("--cpu-iters", type=int, default=100,
                     help="iterations per case for the oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--tune", default="auto", choices=["auto", "fixed"],
                     help="auto: autotune each case; fixed: 64x64 tiles, 4 iterations/launch")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first copy a MIB-sized buffer with torch (counter calibration)")
     return ap.parse_args()
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def timed(torch, fn, reps=1):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / reps
+
+
+def sweep_cases(torch, rdseg, synth, args, dev):
+    probs = [synth.config2(i, size=args.size, iters=args.iters) for i in range(len(synth.C2_LAMBDAS))]
+    cases = []
+    for li, prob in enumerate(probs):
+        f_dev = torch.from_numpy(prob.f).to(dev)
+        for fr in synth.C2_FRACS:
+            delta = synth.band_delta(prob.f, fr)
+            q = float((np.abs(prob.f.astype(np.float64)) < delta).mean())
+            cases.append(dict(li=li, lam=prob.lam, frac=fr, delta=delta, q=q, f=f_dev,
+                              f_host=prob.f))
+    for c in cases:
+        f = c["f"]
+        H, W = f.shape
+        c["out"] = (torch.empty((H, W), device=dev), torch.empty((H, W), device=dev),
+                    torch.empty((2, H, W), device=dev))
+        c["ws"] = rdseg.workspace(rdseg.shape_of(f))
+        if args.tune == "auto":
+            tile, ipl = rdseg.autotune(f, c["lam"], synth.THETA, synth.TAU, c["delta"], 16)
+        else:
+            tile, ipl = (64, 64), 4
+        c["tile"], c["ipl"] = tile, ipl
+    return probs, cases
+
+
+def extras(torch, rdseg, synth, dev):
+    out = {}
+    # ---- batched workload: 512 images, sides 64..1024, 300 iterations
+    log("extras: generating the batched workload")
+    probs = synth.config4(512, frac=0.1)
+    for frac, name in [(0.1, "batched_512"), (math.inf, "batched_512_delta_inf")]:
+        log(f"extras: {name}")
+        fs = [torch.from_numpy(p.f).to(dev) for p in probs]
+        lams = [p.lam for p in probs]
+        deltas = [p.delta if math.isfinite(frac) else math.inf for p in probs]
+        n_px = sum(p.f.size for p in probs)
+        q = sum(float((np.abs(p.f.astype(np.float64)) < d).sum())
+                for p, d in zip(probs, deltas)) / n_px
+        tile, ipl = ((64, 64), 8) if not math.isfinite(frac) else ((16, 16), 8)
+        bs = rdseg.BatchedSolver(fs, lams, deltas, synth.THETA, synth.TAU, 300, tile=tile,
+                                 iters_per_launch=ipl, graph=True)
+        bs.run()
+        t_graph = timed(torch, bs.run, 2)
+        outs = [tuple(t.clone() for t in o) for o in bs.out]
+        seq_out = [tuple(torch.empty_like(t) for t in o) for o in bs.out]
+        wss = [rdseg.workspace(rdseg.shape_of(f)) for f in fs]
+
+        def sequential():
+            for i, f in enumerate(fs):
+                rdseg.solve(f, lams[i], synth.THETA, synth.TAU, deltas[i], 300, tile=tile,
+                            iters_per_launch=ipl, out=seq_out[i], ws=wss[i])
+
+        sequential()
+        t_seq = timed(torch, sequential, 1)
+        same = all(torch.equal(a[0], b[0]) for a, b in zip(outs, seq_out))
+        upd = q * n_px * 300
+        out[name] = dict(images=512, pixels=n_px, active_fraction=q, iters=300,
+                         tile=list(tile), iters_per_launch=ipl,
+                         graph_ms=t_graph, sequential_ms=t_seq, speedup=t_seq / t_graph,
+                         updates_per_s=upd / (t_graph * 1e-3),
+                         bitwise_equal_to_sequential=bool(same))
+        bs.close()
+        del fs, outs, seq_out, wss, bs
+        torch.cuda.empty_cache()
+    # ---- differentiation workload: 2048^2, 300 iterations, checkpoints every 30
+    prob = synth.config5()
+    f = torch.from_numpy(prob.f).to(dev)
+    tgt = torch.from_numpy(prob.mask.astype(np.float32)).to(dev)
+    for frac, name in [(0.1, "fwd_adjoint_2048"), (0.5, "fwd_adjoint_2048_delta_0.5")]:
+        log(f"extras: {name}")
+        delta = synth.band_delta(prob.f, frac)
+        q = float((np.abs(prob.f.astype(np.float64)) < delta).mean())
+
+        def fwd_bwd():
+            u, v, p, tape = rdseg.solve(f, prob.lam, synth.THETA, synth.TAU, delta, 300,
+                                        tile=(32, 32), iters_per_launch=2, ckpt_every=30)
+            rdseg.backward(f, prob.lam, synth.THETA, synth.TAU, delta, 300, 30, tape,
+                           2 * (u - tgt))
+
+        def fwd_only():
+            rdseg.solve(f, prob.lam, synth.THETA, synth.TAU, delta, 300, tile=(32, 32),
+                        iters_per_launch=2)
+
+        fwd_bwd()
+        t_fb = timed(torch, fwd_bwd, 3)
+        fwd_only()
+        t_f = timed(torch, fwd_only, 3)
+        out[name] = dict(size=2048, iters=300, ckpt_every=30, active_fraction=q,
+                         fwd_adjoint_ms=t_fb, forward_ms=t_f)
+    del f, tgt
+    # ---- 4096^2 distance-selective solve, delta 0.1 max|f|, 1000 iterations
+    log("extras: ds_4096")
+    prob = synth.config3()
+    f = torch.from_numpy(prob.f).to(dev)
+    q = float((np.abs(prob.f.astype(np.float64)) < prob.delta).mean())
+    tile, ipl = rdseg.autotune(f, prob.lam, synth.THETA, synth.TAU, prob.delta, 16)
+    run = lambda: rdseg.solve(f, prob.lam, synth.THETA, synth.TAU, prob.delta, 1000, tile=tile,
+                              iters_per_launch=ipl)
+    run()
+    t = timed(torch, run, 2)
+    out["ds_4096"] = dict(size=4096, iters=1000, active_fraction=q, ms=t, tile=list(tile),
+                          iters_per_launch=ipl,
+                          updates_per_s=q * prob.f.size * 1000 / (t * 1e-3))
+    return out
 
 
 def main():
@@ -64,29 +189,16 @@ def main():
     from paper_1807_11534_amd import rdseg
 
     dev = torch.device("cuda:0")
-    lams = synth.C2_LAMBDAS
-    fracs = synth.C2_FRACS
-    probs = [synth.config2(i, size=args.size, iters=args.iters) for i in range(len(lams))]
-    cases = []
-    for li, prob in enumerate(probs):
-        f_dev = torch.from_numpy(prob.f).to(dev)
-        for fr in fracs:
-            delta = synth.band_delta(prob.f, fr)
-            q = float((np.abs(prob.f.astype(np.float64)) < delta).mean())
-            cases.append(dict(li=li, lam=prob.lam, frac=fr, delta=delta, q=q, f=f_dev,
-                              f_host=prob.f))
-    # preallocate outputs and workspaces (inputs and state resident in HBM)
-    for c in cases:
-        f = c["f"]
-        H, W = f.shape
-        c["out"] = (torch.empty((H, W), device=dev), torch.empty((H, W), device=dev),
-                    torch.empty((2, H, W), device=dev))
-        c["ws"] = rdseg.workspace(rdseg.shape_of(f))
-        if args.tune == "auto":
-            tile, ipl = rdseg.autotune(f, c["lam"], synth.THETA, synth.TAU, c["delta"], 16)
-        else:
-            tile, ipl = (64, 64), 4
-        c["tile"], c["ipl"] = tile, ipl
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        a = torch.ones(n, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    log("sweep: generating and tuning")
+    probs, cases = sweep_cases(torch, rdseg, synth, args, dev)
 
     def step():
         for c in cases:
@@ -107,12 +219,24 @@ def main():
     value = updates_per_step / (ms_per_step * 1e-3)
 
     # roofline pass: HIP events around every iteration-kernel launch
+    rdseg.timing_reset()
     rdseg.timing_enable(True)
     step()
     torch.cuda.synchronize()
-    k_ms, k_launch, k_bytes, k_upd = rdseg.timing_read()
     rdseg.timing_enable(False)
-    achieved = k_bytes / (k_ms * 1e-3) / 1e9 if k_ms > 0 else 0.0
+    cfgs = rdseg.configs()
+    per_cfg = []
+    for ci, (tw, th, it, nt) in enumerate(cfgs):
+        ms, nl, by, upd = rdseg.timing_read(ci)
+        if nl:
+            per_cfg.append(dict(config=ci, kernel=f"k_iterate<{tw},{th},{it},{nt}>", ms=ms,
+                                launches=nl, alg_bytes=by, updates=upd))
+    dom = max(per_cfg, key=lambda r: r["ms"])
+    avg_ms = dom["ms"] / dom["launches"]
+    bytes_per_launch = dom["alg_bytes"] / dom["launches"]
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    all_ms, all_n, all_b, _ = rdseg.timing_read(-1)
+    rdseg.timing_reset()
 
     # per-case detail (one more timed pass, per solve)
     detail = []
@@ -137,9 +261,14 @@ def main():
                            speedup_vs_inf=round(ref_ms / ms, 3),
                            tile=list(c["tile"]), iters_per_launch=c["ipl"]))
 
+    ext = None
+    if not args.no_extras:
+        ext = extras(torch, rdseg, synth, dev)
+
     cpu = None
     if not args.no_cpu:
         import oracle
+        log("cpu baseline: oracle sample")
         t0 = time.perf_counter()
         upd = 0.0
         for c in cases:
@@ -168,10 +297,15 @@ def main():
                     pixel_updates_per_step=updates_per_step),
         roofline=dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
                       frac=achieved / HBM_PEAK_GBS, traffic=None,
-                      kernel="k_iterate", launches=k_launch, kernel_ms=k_ms,
-                      alg_bytes_per_update=BYTES_PER_UPDATE),
+                      kernel=dom["kernel"], launches=dom["launches"], avg_launch_ms=avg_ms,
+                      alg_bytes_per_launch=bytes_per_launch,
+                      alg_bytes_per_update=BYTES_PER_UPDATE,
+                      all_iterate_launches=dict(launches=all_n, ms=all_ms,
+                                                gbs=all_b / (all_ms * 1e-3) / 1e9 if all_ms else 0.0),
+                      per_config=per_cfg),
         cpu_baseline=cpu,
         sweep=detail,
+        extras=ext,
     )
     print(json.dumps(line), flush=True)
 

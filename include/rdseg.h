@@ -223,13 +223,18 @@ int32_t rdseg_config_count(void);
 rdseg_status rdseg_config_get(int32_t i, int32_t* tile_w, int32_t* tile_h,
                               int32_t* iters_per_launch, int32_t* threads);
 
-/* When enabled, every launch of the iteration kernel is bracketed by HIP
- * events on its stream; rdseg_timing_read synchronises on the recorded events
- * and returns the summed kernel milliseconds, the launch count and the summed
- * algorithmic bytes (28 bytes per active pixel-iteration), then resets. */
+/* When enabled, every run of back-to-back launches of the iteration kernel
+ * (a whole solve, or one checkpoint segment) is bracketed by a pair of HIP
+ * events on its stream.  rdseg_timing_read synchronises on the recorded events
+ * of configuration `config` (an index of rdseg_config_get; -1 = all) and
+ * returns their summed kernel milliseconds, the launch count, the summed
+ * algorithmic bytes (28 bytes per active pixel-iteration: read f, v, p_x, p_y,
+ * write v, p_x, p_y) and pixel-updates.  Records accumulate until
+ * rdseg_timing_reset.  Not recorded inside batched graph plans. */
 rdseg_status rdseg_timing_enable(int32_t on);
-rdseg_status rdseg_timing_read(double* kernel_ms, int64_t* launches, double* alg_bytes,
-                               int64_t* pixel_updates);
+rdseg_status rdseg_timing_read(int32_t config, double* kernel_ms, int64_t* launches,
+                               double* alg_bytes, int64_t* pixel_updates);
+rdseg_status rdseg_timing_reset(void);
 
 const char* rdseg_status_string(rdseg_status st);
 const char* rdseg_last_error(void);

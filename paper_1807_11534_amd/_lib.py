@@ -74,8 +74,9 @@ SIGNATURES = {
     "rdseg_config_get": (ctypes.c_int, [_i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
                                         ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "rdseg_timing_enable": (ctypes.c_int, [_i32]),
-    "rdseg_timing_read": (ctypes.c_int, [ctypes.POINTER(_d), ctypes.POINTER(ctypes.c_int64),
+    "rdseg_timing_read": (ctypes.c_int, [_i32, ctypes.POINTER(_d), ctypes.POINTER(ctypes.c_int64),
                                          ctypes.POINTER(_d), ctypes.POINTER(ctypes.c_int64)]),
+    "rdseg_timing_reset": (ctypes.c_int, []),
     "rdseg_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "rdseg_last_error": (ctypes.c_char_p, []),
 }

@@ -162,13 +162,17 @@ bool ranges_overlap(const void* a, size_t na, const void* b, size_t nb) {
 // ------------------------------------------------------------------ timing
 struct TimingRec {
     hipEvent_t e0, e1;
-    int nit;
+    int nit;              // iterations covered by the bracketed launches
+    int launches;         // launches bracketed
+    int ci;
     int64_t* npix_host;   // pinned slot filled by an async copy
 };
 
 struct Timing {
     std::mutex mu;
     bool on = false;
+    TimingRec open{};
+    bool has_open = false;
     std::vector<TimingRec> recs;
     std::vector<hipEvent_t> pool;
     int64_t* pinned = nullptr;
@@ -270,28 +274,46 @@ rdseg_status enqueue_iterations(const SolvePlanArgs& a) {
             if (rc) return RDSEG_ERR_HIP;
             ++seg;
         }
-        TimingRec rec{};
-        bool timed = false;
-        if (g_timing.on) {
+        // Timing brackets each run of back-to-back iteration launches (the whole
+        // solve, or one checkpoint segment) with one event pair.
+        const bool run_start = (j == 0) || (a.tape && seg_start.size() > seg - 1 && seg >= 1 &&
+                                            seg_start[seg - 1] == j);
+        const bool run_end = (j == L - 1) || (a.tape && seg < seg_start.size() && seg_start[seg] == j + 1);
+        if (g_timing.on && run_start) {
             std::lock_guard<std::mutex> lk(g_timing.mu);
+            TimingRec rec{};
             rec.e0 = timing_event();
             rec.e1 = timing_event();
-            rec.nit = nits[j];
+            rec.nit = 0;
+            rec.launches = 0;
+            rec.ci = a.ci;
             rec.npix_host = nullptr;
-            timed = rec.e0 && rec.e1;
-            if (timed) (void)hipEventRecord(rec.e0, a.st);
+            if (rec.e0 && rec.e1) {
+                (void)hipEventRecord(rec.e0, a.st);
+                g_timing.open = rec;
+                g_timing.has_open = true;
+            }
         }
         int rc = launch_iterate(a.ci, a.d0, a.descs, a.descs != nullptr, a.queue, a.n_queue,
                                 a.max_items, in_buf, nits[j], j == L - 1, a.theta, a.inv_theta,
                                 a.tau, a.st);
         if (rc) return RDSEG_ERR_HIP;
-        if (timed) {
+        if (g_timing.on) {
             std::lock_guard<std::mutex> lk(g_timing.mu);
-            (void)hipEventRecord(rec.e1, a.st);
-            rec.npix_host = timing_slot();
-            if (rec.npix_host && a.npix)
-                (void)hipMemcpyAsync(rec.npix_host, a.npix, sizeof(int64_t), hipMemcpyDeviceToHost, a.st);
-            g_timing.recs.push_back(rec);
+            if (g_timing.has_open) {
+                g_timing.open.nit += nits[j];
+                g_timing.open.launches += 1;
+                if (run_end) {
+                    TimingRec rec = g_timing.open;
+                    g_timing.has_open = false;
+                    (void)hipEventRecord(rec.e1, a.st);
+                    rec.npix_host = timing_slot();
+                    if (rec.npix_host && a.npix)
+                        (void)hipMemcpyAsync(rec.npix_host, a.npix, sizeof(int64_t),
+                                             hipMemcpyDeviceToHost, a.st);
+                    g_timing.recs.push_back(rec);
+                }
+            }
         }
     }
     return RDSEG_OK;
@@ -986,12 +1008,13 @@ rdseg_status rdseg_timing_enable(int32_t on) {
     return RDSEG_OK;
 }
 
-rdseg_status rdseg_timing_read(double* kernel_ms, int64_t* launches, double* alg_bytes,
-                               int64_t* pixel_updates) {
+rdseg_status rdseg_timing_read(int32_t config, double* kernel_ms, int64_t* launches,
+                               double* alg_bytes, int64_t* pixel_updates) {
     std::lock_guard<std::mutex> lk(g_timing.mu);
     double ms = 0.0, bytes = 0.0;
-    int64_t upd = 0;
+    int64_t upd = 0, n = 0;
     for (auto& r : g_timing.recs) {
+        if (config >= 0 && r.ci != config) continue;
         if (hipEventSynchronize(r.e1) != hipSuccess) return fail(RDSEG_ERR_HIP, "event sync failed");
         float t = 0.0f;
         (void)hipEventElapsedTime(&t, r.e0, r.e1);
@@ -999,13 +1022,22 @@ rdseg_status rdseg_timing_read(double* kernel_ms, int64_t* launches, double* alg
         int64_t np = r.npix_host ? *r.npix_host : 0;
         upd += np * r.nit;
         bytes += 28.0 * (double)np * r.nit;
+        n += r.launches;
+    }
+    if (kernel_ms) *kernel_ms = ms;
+    if (launches) *launches = n;
+    if (alg_bytes) *alg_bytes = bytes;
+    if (pixel_updates) *pixel_updates = upd;
+    return RDSEG_OK;
+}
+
+rdseg_status rdseg_timing_reset(void) {
+    std::lock_guard<std::mutex> lk(g_timing.mu);
+    for (auto& r : g_timing.recs) {
+        if (hipEventSynchronize(r.e1) != hipSuccess) return fail(RDSEG_ERR_HIP, "event sync failed");
         g_timing.pool.push_back(r.e0);
         g_timing.pool.push_back(r.e1);
     }
-    if (kernel_ms) *kernel_ms = ms;
-    if (launches) *launches = (int64_t)g_timing.recs.size();
-    if (alg_bytes) *alg_bytes = bytes;
-    if (pixel_updates) *pixel_updates = upd;
     g_timing.recs.clear();
     g_timing.pinned_used = 0;
     return RDSEG_OK;

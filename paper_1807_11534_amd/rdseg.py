@@ -257,9 +257,21 @@ def timing_enable(on=True):
     check(_lib.load().rdseg_timing_enable(1 if on else 0))
 
 
-def timing_read():
-    """(kernel_ms, launches, algorithmic_bytes, pixel_updates) since the last read."""
+def timing_read(config=-1):
+    """(kernel_ms, launches, algorithmic_bytes, pixel_updates) of the recorded
+    iteration-kernel launches of one configuration index (-1 = all)."""
     ms, n, b, upd = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double(), ctypes.c_int64()
-    check(_lib.load().rdseg_timing_read(ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b),
-                                        ctypes.byref(upd)))
+    check(_lib.load().rdseg_timing_read(int(config), ctypes.byref(ms), ctypes.byref(n),
+                                        ctypes.byref(b), ctypes.byref(upd)))
     return ms.value, n.value, b.value, upd.value
+
+
+def timing_reset():
+    check(_lib.load().rdseg_timing_reset())
+
+
+def config_index(tile, iters_per_launch):
+    for i, (tw, th, it, _) in enumerate(configs()):
+        if (tw, th) == tuple(tile) and it == iters_per_launch:
+            return i
+    raise ValueError("configuration not compiled")
