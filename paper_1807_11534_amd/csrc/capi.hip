@@ -100,7 +100,10 @@ struct SolveWs {
     int32_t* offs;
     int32_t* part;
     int2* queue;
-    int32_t* totals;   // [0] n_queue, [1] scratch total
+    int32_t* tstate;
+    int32_t* cflags;
+    int2* cqueue;
+    int32_t* totals;   // [0] n_queue, [1] scratch total, [2] n_closed
     size_t bytes;
 };
 
@@ -117,6 +120,9 @@ SolveWs carve_solve(void* base, const rdseg_shape& s) {
     w.offs = cv.take<int32_t>(nflag);
     w.part = cv.take<int32_t>(scan_partials(nflag));
     w.queue = cv.take<int2>(g.nt);
+    w.tstate = cv.take<int32_t>(g.nt);
+    w.cflags = cv.take<int32_t>(g.nt);
+    w.cqueue = cv.take<int2>(g.nt);
     w.totals = cv.take<int32_t>(4);
     w.bytes = cv.off;
     return w;
@@ -391,8 +397,16 @@ rdseg_status solve_impl(const float* f, rdseg_shape s, const rdseg_params* prm, 
     d = make_desc(f, s, prm->lambda, prm->theta, prm->delta, u, v, p, w.c, w.st, u0, p0, cfg.bx, cfg.by);
     if (launch_init(&d, nullptr, off, 1, s.H, st)) return RDSEG_ERR_HIP;
     int64_t nm = macro_count(s, cfg.bx, cfg.by);
-    if (launch_macro_queue(&d, nullptr, off, 1, nm, cfg.bx, cfg.by, w.masks, w.flags, w.offs,
-                           w.part, w.queue, w.totals, st))
+    // Closed tiles run every iteration in one launch; a solve that writes a
+    // checkpoint tape sends every tile through the blocked kernel instead.
+    const bool use_closed = !(prm->ckpt_every > 0 && tape) && prm->iters > 0;
+    QueueScratch qs{w.tstate, w.cflags, w.flags, w.offs, w.part};
+    if (launch_macro_queue(&d, nullptr, off, 1, nm, cfg.bx, cfg.by, w.masks, qs, w.queue, w.totals,
+                           g.nt, use_closed ? w.cqueue : nullptr, w.totals + 2, st))
+        return RDSEG_ERR_HIP;
+    if (use_closed &&
+        launch_closed(&d, nullptr, false, w.cqueue, w.totals + 2, g.nt, prm->iters,
+                      (float)prm->theta, (float)(1.0 / prm->theta), (float)prm->tau, st))
         return RDSEG_ERR_HIP;
     SolvePlanArgs a;
     a.d0 = &d;
@@ -428,6 +442,9 @@ struct BatchLayout {
     int32_t* offs = nullptr;
     int32_t* part = nullptr;
     int2* queue = nullptr;
+    int32_t* tstate = nullptr;
+    int32_t* cflags = nullptr;
+    int2* cqueue = nullptr;
     int32_t* totals = nullptr;
 };
 
@@ -495,9 +512,13 @@ BatchLayout layout_batch(const rdseg_image* imgs, int32_t n, int bx, int by, dou
     L.masks = cv.take<uint64_t>(L.tiles);
     L.npix = cv.take<int64_t>(n);
     L.npix_total = cv.take<int64_t>(1);
+    const int64_t nmax = std::max(L.macros, L.tiles);
     L.flags = cv.take<int32_t>(L.macros);
-    L.offs = cv.take<int32_t>(L.macros);
-    L.part = cv.take<int32_t>(scan_partials(L.macros));
+    L.offs = cv.take<int32_t>(nmax);
+    L.part = cv.take<int32_t>(scan_partials(nmax));
+    L.tstate = cv.take<int32_t>(L.tiles);
+    L.cflags = cv.take<int32_t>(L.tiles);
+    L.cqueue = cv.take<int2>(L.tiles);
     L.queue = cv.take<int2>(L.macros);
     L.totals = cv.take<int32_t>(4);
     L.bytes = cv.off;
@@ -522,8 +543,14 @@ rdseg_status enqueue_batch(const BatchLayout& L, int n, int ci, int iters, doubl
     if (launch_init(d0, L.d_descs, off, n, L.rows, st)) return RDSEG_ERR_HIP;
     if (launch_tile_masks(d0, L.d_descs, off, n, L.strips, L.masks, L.npix, st)) return RDSEG_ERR_HIP;
     if (launch_sum_i64(L.npix, n, L.npix_total, st)) return RDSEG_ERR_HIP;
-    if (launch_macro_queue(d0, L.d_descs, off, n, L.macros, cfg.bx, cfg.by, L.masks, L.flags,
-                           L.offs, L.part, L.queue, L.totals, st))
+    QueueScratch qs{L.tstate, L.cflags, L.flags, L.offs, L.part};
+    const bool use_closed = iters > 0;
+    if (launch_macro_queue(d0, L.d_descs, off, n, L.macros, cfg.bx, cfg.by, L.masks, qs, L.queue,
+                           L.totals, L.tiles, use_closed ? L.cqueue : nullptr, L.totals + 2, st))
+        return RDSEG_ERR_HIP;
+    if (use_closed &&
+        launch_closed(d0, L.d_descs, true, L.cqueue, L.totals + 2, L.tiles, iters, (float)theta,
+                      (float)(1.0 / theta), (float)tau, st))
         return RDSEG_ERR_HIP;
     SolvePlanArgs a;
     a.d0 = d0;
@@ -557,6 +584,7 @@ struct BackWs {
     int32_t* offs;
     int32_t* part;
     int2* queue;
+    int32_t* tstate;
     int32_t* totals;
     double* red;       // reduction partials
     double* out4;
@@ -577,6 +605,7 @@ BackWs carve_back(void* base, const rdseg_shape& s, int ce) {
     w.offs = cv.take<int32_t>(g.nt);
     w.part = cv.take<int32_t>(scan_partials(g.nt));
     w.queue = cv.take<int2>(g.nt);
+    w.tstate = cv.take<int32_t>(g.nt);
     w.totals = cv.take<int32_t>(4);
     w.red = cv.take<double>(reduce_partials(s.H));
     w.out4 = cv.take<double>(4);
@@ -755,7 +784,7 @@ rdseg_status rdseg_solve_batched(const rdseg_image* imgs, int32_t n, double thet
         return fail(RDSEG_ERR_HIP, "uploading batch descriptors failed");
     }
     // occupancy query outside the capture
-    if (prepare_iterate(ci, true)) {
+    if (prepare_iterate(ci, true) || prepare_closed(true)) {
         plan_free(P);
         return RDSEG_ERR_HIP;
     }
@@ -835,8 +864,9 @@ rdseg_status rdseg_backward(const float* f, rdseg_shape s, const rdseg_params* p
     if (launch_init(&d, nullptr, off, 1, s.H, st)) return RDSEG_ERR_HIP;   // c only
     if (launch_tile_masks(&d, nullptr, off, 1, g.strips, w.masks, w.npix, st)) return RDSEG_ERR_HIP;
     const int64_t nm = macro_count(s, kAdjTile, kAdjTile);
-    if (launch_macro_queue(&d, nullptr, off, 1, nm, kAdjTile, kAdjTile, w.masks, w.flags, w.offs,
-                           w.part, w.queue, w.totals, st))
+    QueueScratch qs{w.tstate, nullptr, w.flags, w.offs, w.part};
+    if (launch_macro_queue(&d, nullptr, off, 1, nm, kAdjTile, kAdjTile, w.masks, qs, w.queue,
+                           w.totals, g.nt, nullptr, nullptr, st))
         return RDSEG_ERR_HIP;
     if (launch_fill(w.sacc, s.H, s.W, (int)s.ld, 0.0f, st)) return RDSEG_ERR_HIP;
     const float theta = (float)prm->theta, inv_theta = (float)(1.0 / prm->theta);

@@ -221,11 +221,52 @@ __global__ __launch_bounds__(256) void k_pix_scatter(const float* __restrict__ f
     }
 }
 
+// ---------------------------------------------------------------- tile states
+// The iteration couples two RD pixels only through 4-neighbour chains of RD
+// pixels (off RD, p = 0 and w = -H(-f)/theta are constants).  An 8x8 tile whose
+// RD pixels have no RD 4-neighbour in another tile therefore evolves on its
+// own: it is "closed" and can run every iteration on chip.  tstate: 0 = no RD
+// pixel, 1 = closed, 2 = open (or any non-empty tile when closed tiles are
+// not used).
+constexpr uint64_t kCol0 = 0x0101010101010101ull;
+
+template <bool BATCHED>
+__global__ void k_tile_state(ImgDesc d0, const ImgDesc* __restrict__ descs, OffTables off,
+                             int n_img, int64_t n_tiles, const uint64_t* __restrict__ masks,
+                             int use_closed, int32_t* __restrict__ tstate) {
+    int64_t T = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (T >= n_tiles) return;
+    const uint64_t m = masks[T];
+    if (!m) {
+        tstate[T] = 0;
+        return;
+    }
+    if (!use_closed) {
+        tstate[T] = 2;
+        return;
+    }
+    int img = BATCHED ? find_image(off.toff, n_img, T) : 0;
+    const ImgDesc& d = BATCHED ? descs[img] : d0;
+    const int64_t lt = T - (BATCHED ? off.toff[img] : 0);
+    const int ty = (int)(lt / d.tw), tx = (int)(lt - (int64_t)ty * d.tw);
+    const uint64_t mL = tx > 0 ? masks[T - 1] : 0ull;
+    const uint64_t mR = tx < d.tw - 1 ? masks[T + 1] : 0ull;
+    const uint64_t mU = ty > 0 ? masks[T - d.tw] : 0ull;
+    const uint64_t mD = ty < d.th - 1 ? masks[T + d.tw] : 0ull;
+    uint64_t touch = (m & kCol0) & ((mL >> 7) & kCol0);          // left column vs left tile
+    touch |= ((m >> 7) & kCol0) & (mR & kCol0);                   // right column vs right tile
+    touch |= (m & 0xFFull) & (mU >> 56);                          // top row vs upper tile
+    touch |= (m >> 56) & (mD & 0xFFull);                          // bottom row vs lower tile
+    tstate[T] = touch ? 2 : 1;
+}
+
 // ---------------------------------------------------------------- macro queue
+// A macro tile is queued for the temporally blocked kernel iff it holds an open
+// 8x8 tile; closed tiles inside such a macro tile are computed there too.
 template <bool BATCHED>
 __global__ void k_macro_flags(ImgDesc d0, const ImgDesc* __restrict__ descs, OffTables off,
                               int n_img, int64_t n_macro, int bx8, int by8,
-                              const uint64_t* __restrict__ masks, int32_t* __restrict__ flags) {
+                              const int32_t* __restrict__ tstate, int32_t* __restrict__ flags) {
     int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= n_macro) return;
     int img = BATCHED ? find_image(off.moff, n_img, m) : 0;
@@ -236,8 +277,39 @@ __global__ void k_macro_flags(ImgDesc d0, const ImgDesc* __restrict__ descs, Off
     int any = 0;
     for (int ty = my * by8; ty < ty1; ++ty)
         for (int tx = mx * bx8; tx < tx1; ++tx)
-            any |= masks[d.toff + (int64_t)ty * d.tw + tx] != 0 ? 1 : 0;
+            any |= tstate[d.toff + (int64_t)ty * d.tw + tx] == 2 ? 1 : 0;
     flags[m] = any;
+}
+
+// Closed tiles that are not inside a queued macro tile.
+template <bool BATCHED>
+__global__ void k_closed_flags(ImgDesc d0, const ImgDesc* __restrict__ descs, OffTables off,
+                               int n_img, int64_t n_tiles, int bx8, int by8,
+                               const int32_t* __restrict__ tstate,
+                               const int32_t* __restrict__ mflags, int32_t* __restrict__ cflags) {
+    int64_t T = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (T >= n_tiles) return;
+    if (tstate[T] != 1) {
+        cflags[T] = 0;
+        return;
+    }
+    int img = BATCHED ? find_image(off.toff, n_img, T) : 0;
+    const ImgDesc& d = BATCHED ? descs[img] : d0;
+    const int64_t lt = T - (BATCHED ? off.toff[img] : 0);
+    const int ty = (int)(lt / d.tw), tx = (int)(lt - (int64_t)ty * d.tw);
+    const int64_t M = (BATCHED ? d.moff : 0) + (int64_t)(ty / by8) * d.mw + tx / bx8;
+    cflags[T] = mflags[M] ? 0 : 1;
+}
+
+template <bool BATCHED>
+__global__ void k_closed_scatter(OffTables off, int n_img, int64_t n_tiles,
+                                 const int32_t* __restrict__ cflags,
+                                 const int32_t* __restrict__ offs, int2* __restrict__ cqueue) {
+    int64_t T = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (T >= n_tiles || !cflags[T]) return;
+    int img = BATCHED ? find_image(off.toff, n_img, T) : 0;
+    int64_t lt = T - (BATCHED ? off.toff[img] : 0);
+    cqueue[offs[T]] = make_int2(img, (int)lt);
 }
 
 template <bool BATCHED>
@@ -317,23 +389,48 @@ int launch_pixel_list(const float* f, int H, int W, int ld, double delta, int32_
 }
 
 int launch_macro_queue(const ImgDesc* d0, const ImgDesc* descs, OffTables off, int n_img,
-                       int64_t n_macro, int bx, int by, const uint64_t* masks, int32_t* flags,
-                       int32_t* offs, int32_t* part, int2* queue, int32_t* n_queue,
-                       hipStream_t st) {
+                       int64_t n_macro, int bx, int by, const uint64_t* masks,
+                       const QueueScratch& q, int2* queue, int32_t* n_queue, int64_t n_tiles,
+                       int2* cqueue, int32_t* n_closed, hipStream_t st) {
+    const bool use_closed = cqueue != nullptr;
+    if (descs)
+        hipLaunchKernelGGL(k_tile_state<true>, dim3(nblk(n_tiles, 256)), dim3(256), 0, st, *d0,
+                           descs, off, n_img, n_tiles, masks, use_closed ? 1 : 0, q.tstate);
+    else
+        hipLaunchKernelGGL(k_tile_state<false>, dim3(nblk(n_tiles, 256)), dim3(256), 0, st, *d0,
+                           descs, off, n_img, n_tiles, masks, use_closed ? 1 : 0, q.tstate);
     if (descs)
         hipLaunchKernelGGL(k_macro_flags<true>, dim3(nblk(n_macro, 256)), dim3(256), 0, st, *d0,
-                           descs, off, n_img, n_macro, bx / 8, by / 8, masks, flags);
+                           descs, off, n_img, n_macro, bx / 8, by / 8, q.tstate, q.mflags);
     else
         hipLaunchKernelGGL(k_macro_flags<false>, dim3(nblk(n_macro, 256)), dim3(256), 0, st, *d0,
-                           descs, off, n_img, n_macro, bx / 8, by / 8, masks, flags);
-    int rc = launch_scan_ints(flags, n_macro, offs, part, n_queue, st);
+                           descs, off, n_img, n_macro, bx / 8, by / 8, q.tstate, q.mflags);
+    int rc = launch_scan_ints(q.mflags, n_macro, q.offs, q.part, n_queue, st);
     if (rc) return rc;
     if (descs)
         hipLaunchKernelGGL(k_macro_scatter<true>, dim3(nblk(n_macro, 256)), dim3(256), 0, st,
-                           *d0, off, n_img, n_macro, flags, offs, queue);
+                           *d0, off, n_img, n_macro, q.mflags, q.offs, queue);
     else
         hipLaunchKernelGGL(k_macro_scatter<false>, dim3(nblk(n_macro, 256)), dim3(256), 0, st,
-                           *d0, off, n_img, n_macro, flags, offs, queue);
+                           *d0, off, n_img, n_macro, q.mflags, q.offs, queue);
+    if (use_closed) {
+        if (descs)
+            hipLaunchKernelGGL(k_closed_flags<true>, dim3(nblk(n_tiles, 256)), dim3(256), 0, st,
+                               *d0, descs, off, n_img, n_tiles, bx / 8, by / 8, q.tstate, q.mflags,
+                               q.cflags);
+        else
+            hipLaunchKernelGGL(k_closed_flags<false>, dim3(nblk(n_tiles, 256)), dim3(256), 0, st,
+                               *d0, descs, off, n_img, n_tiles, bx / 8, by / 8, q.tstate, q.mflags,
+                               q.cflags);
+        rc = launch_scan_ints(q.cflags, n_tiles, q.offs, q.part, n_closed, st);
+        if (rc) return rc;
+        if (descs)
+            hipLaunchKernelGGL(k_closed_scatter<true>, dim3(nblk(n_tiles, 256)), dim3(256), 0, st,
+                               off, n_img, n_tiles, q.cflags, q.offs, cqueue);
+        else
+            hipLaunchKernelGGL(k_closed_scatter<false>, dim3(nblk(n_tiles, 256)), dim3(256), 0,
+                               st, off, n_img, n_tiles, q.cflags, q.offs, cqueue);
+    }
     RDSEG_HIP_CHECK(hipGetLastError());
     return 0;
 }

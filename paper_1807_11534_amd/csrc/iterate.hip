@@ -63,7 +63,92 @@ __global__ __launch_bounds__(256) void k_init(ImgDesc d0, const ImgDesc* __restr
     }
 }
 
-template <int BX, int BY, int IT, int NT, bool BATCHED>
+// The on-chip iterations.  FAST: every region cell is inside the grid, in RD
+// and away from the last column / row, so no per-cell selects are needed.
+template <int BX, int BY, int IT, int NT, bool FAST>
+__device__ __forceinline__ void run_iterations(float* __restrict__ sPX, float* __restrict__ sPY,
+                                               float* __restrict__ sW, float* rv, float* rpx,
+                                               float* rpy, const float* rc, const uint32_t* fl,
+                                               const int* gi, float* __restrict__ U, int nit,
+                                               int write_u, float theta, float inv_theta,
+                                               float tau) {
+    constexpr int RX = BX + 2 * IT + 1;
+    constexpr int RY = BY + 2 * IT + 1;
+    constexpr int RC = RX * RY;
+    constexpr int CPT = (RC + NT - 1) / NT;
+    constexpr int PAD = RX + 1;
+    constexpr int H0 = IT + 1;
+    const int t = threadIdx.x;
+    // prologue: w from the loaded state
+    {
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) {
+            const int i = t + j * NT;
+            if (i < RC) {
+                float dd = div_p(rpx[j], sPX[PAD + i - 1], rpy[j], sPY[PAD + i - RX]);
+                sW[PAD + i] = FAST ? fmaf(-rv[j], inv_theta, dd)
+                                   : w_of(dd, rv[j], inv_theta, (fl[j] & CF_ACT) != 0);
+            }
+        }
+    }
+    __syncthreads();
+    for (int it = 0; it < nit; ++it) {
+        // phase B: dual step
+        {
+#pragma unroll
+            for (int j = 0; j < CPT; ++j) {
+                const int i = t + j * NT;
+                    if (i < RC) {
+                    const float wc = sW[PAD + i];
+                    float npx, npy;
+                    if (FAST) {
+                        const float gx = sW[PAD + i + 1] - wc;
+                        const float gy = sW[PAD + i + RX] - wc;
+                        const float nn = __builtin_amdgcn_sqrtf(fmaf(gx, gx, gy * gy));
+                        const float m = __builtin_amdgcn_rcpf(fmaf(tau, nn, 1.0f));
+                        npx = fmaf(tau, gx, rpx[j]) * m;
+                        npy = fmaf(tau, gy, rpy[j]) * m;
+                    } else {
+                        DualOut o = dual_update(rpx[j], rpy[j], wc, sW[PAD + i + 1],
+                                                sW[PAD + i + RX], fl[j], tau);
+                        npx = o.px;
+                        npy = o.py;
+                    }
+                    rpx[j] = npx;
+                    rpy[j] = npy;
+                    sPX[PAD + i] = npx;
+                    sPY[PAD + i] = npy;
+                }
+            }
+        }
+        __syncthreads();
+        // phase A: u-step, v-step, next w
+        const bool last = (it == nit - 1);
+        {
+#pragma unroll
+            for (int j = 0; j < CPT; ++j) {
+                const int i = t + j * NT;
+                    if (i < RC) {
+                    float dd = div_p(rpx[j], sPX[PAD + i - 1], rpy[j], sPY[PAD + i - RX]);
+                    float u = u_step(rv[j], dd, theta);
+                    rv[j] = v_step(u, rc[j]);
+                    if (last) {
+                        if (write_u && (fl[j] & CF_OUT)) U[gi[j]] = u;
+                    } else {
+                        sW[PAD + i] = FAST ? fmaf(-rv[j], inv_theta, dd)
+                                           : w_of(dd, rv[j], inv_theta, (fl[j] & CF_ACT) != 0);
+                    }
+                }
+            }
+        }
+        if (!last) __syncthreads();
+    }
+}
+
+// FAST_OK: whether this instantiation carries the select-free variant for
+// tiles that lie inside the grid and inside RD (worth it for large tiles, where
+// such tiles dominate; small sparse-band tiles rarely qualify).
+template <int BX, int BY, int IT, int NT, bool BATCHED, bool FAST_OK = (BX >= 64)>
 __global__ __launch_bounds__(NT) void k_iterate(ImgDesc d0, const ImgDesc* __restrict__ descs,
                                                 const int2* __restrict__ queue,
                                                 const int32_t* __restrict__ n_queue, int in_buf,
@@ -116,6 +201,7 @@ __global__ __launch_bounds__(NT) void k_iterate(ImgDesc d0, const ImgDesc* __res
         int gi[CPT];
 
         __syncthreads();   // LDS of the previous item fully consumed
+        int plain = 1;     // every cell inside the grid, in RD, off the last column / row
 #pragma unroll
         for (int j = 0; j < CPT; ++j) {
             const int i = t + j * NT;
@@ -144,6 +230,97 @@ __global__ __launch_bounds__(NT) void k_iterate(ImgDesc d0, const ImgDesc* __res
                 const bool interior = rx >= H0 && rx < H0 + BX && ry >= H0 && ry < H0 + BY;
                 if (interior && act) f |= CF_OUT;
                 fl[j] = f;
+                plain &= (act && !(f & (CF_LASTC | CF_LASTR))) ? 1 : 0;
+                sPX[PAD + i] = rpx[j];
+                sPY[PAD + i] = rpy[j];
+            }
+        }
+        bool fast = false;
+        if (FAST_OK) fast = __syncthreads_and(plain) != 0;
+        else __syncthreads();
+        if (fast)
+            run_iterations<BX, BY, IT, NT, true>(sPX, sPY, sW, rv, rpx, rpy, rc, fl, gi, d.u, nit,
+                                                 write_u, theta, inv_theta, tau);
+        else
+            run_iterations<BX, BY, IT, NT, false>(sPX, sPY, sW, rv, rpx, rpy, rc, fl, gi, d.u, nit,
+                                                  write_u, theta, inv_theta, tau);
+        float* __restrict__ Vo = d.st[out_buf][0];
+        float* __restrict__ PXo = d.st[out_buf][1];
+        float* __restrict__ PYo = d.st[out_buf][2];
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) {
+            if (fl[j] & CF_OUT) {
+                Vo[gi[j]] = rv[j];
+                PXo[gi[j]] = rpx[j];
+                PYo[gi[j]] = rpy[j];
+            }
+        }
+    }
+}
+
+// Every iteration of one closed 8x8 tile per 64-thread workgroup.  A closed
+// tile's RD pixels have no RD 4-neighbour outside the tile, so the only values
+// they read from outside are the constants of frozen neighbours (p = 0,
+// w = -H(-f)/theta): the region is the tile plus a one-pixel ring, and the ring
+// never changes.  (An RD pixel of the ring belongs to another component and
+// is never read by this tile's RD pixels; it is held as a frozen cell.)  The
+// per-pixel arithmetic is that of k_iterate, so results are bitwise equal.
+template <bool BATCHED>
+__global__ __launch_bounds__(64) void k_closed(ImgDesc d0, const ImgDesc* __restrict__ descs,
+                                               const int2* __restrict__ cqueue,
+                                               const int32_t* __restrict__ n_closed, int iters,
+                                               float theta, float inv_theta, float tau) {
+    constexpr int RX = 10;
+    constexpr int RC = RX * RX;
+    constexpr int CPT = 2;
+    constexpr int PAD = RX + 1;
+    constexpr int LS = RC + 2 * PAD;
+    __shared__ float sPX[LS];
+    __shared__ float sPY[LS];
+    __shared__ float sW[LS];
+    const int t = threadIdx.x;
+    for (int k = t; k < PAD; k += 64) {
+        sPX[k] = 0.0f; sPY[k] = 0.0f; sW[k] = 0.0f;
+        sPX[PAD + RC + k] = 0.0f; sPY[PAD + RC + k] = 0.0f; sW[PAD + RC + k] = 0.0f;
+    }
+    const int n = *n_closed;
+    for (int item = blockIdx.x; item < n; item += gridDim.x) {
+        const int2 q = cqueue[item];
+        const ImgDesc& d = BATCHED ? descs[q.x] : d0;
+        const int ty = q.y / d.tw;
+        const int tx = q.y - ty * d.tw;
+        const int ox = tx * 8 - 1, oy = ty * 8 - 1;
+        float rv[CPT], rpx[CPT], rpy[CPT], rc[CPT];
+        uint32_t fl[CPT];
+        int gi[CPT];
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) {
+            const int i = t + j * 64;
+            rv[j] = 0.0f; rpx[j] = 0.0f; rpy[j] = 0.0f; rc[j] = __builtin_inff();
+            fl[j] = 0u; gi[j] = 0;
+            if (i < RC) {
+                const int ry = i / RX, rx = i - ry * RX;
+                const int gx = ox + rx, gy = oy + ry;
+                const bool inb = (unsigned)gx < (unsigned)d.W && (unsigned)gy < (unsigned)d.H;
+                const bool ring = rx == 0 || rx == RX - 1 || ry == 0 || ry == RX - 1;
+                const int g = gy * d.ld + gx;
+                gi[j] = g;
+                float c = inb ? d.c[g] : __builtin_inff();
+                if (ring && c_active(c)) c = __builtin_inff();   // held as a frozen cell
+                const bool act = c_active(c);
+                rc[j] = c;
+                if (act) {
+                    rv[j] = d.st[0][0][g];
+                    rpx[j] = d.st[0][1][g];
+                    rpy[j] = d.st[0][2][g];
+                } else {
+                    rv[j] = heav_from_c(c);
+                }
+                uint32_t f = act ? (CF_ACT | CF_OUT) : 0u;
+                if (gx == d.W - 1) f |= CF_LASTC;
+                if (gy == d.H - 1) f |= CF_LASTR;
+                fl[j] = f;
                 sPX[PAD + i] = rpx[j];
                 sPY[PAD + i] = rpy[j];
             }
@@ -151,18 +328,17 @@ __global__ __launch_bounds__(NT) void k_iterate(ImgDesc d0, const ImgDesc* __res
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < CPT; ++j) {
-            const int i = t + j * NT;
+            const int i = t + j * 64;
             if (i < RC) {
                 float dd = div_p(rpx[j], sPX[PAD + i - 1], rpy[j], sPY[PAD + i - RX]);
                 sW[PAD + i] = w_of(dd, rv[j], inv_theta, (fl[j] & CF_ACT) != 0);
             }
         }
         __syncthreads();
-        for (int it = 0; it < nit; ++it) {
-            // phase B: dual step
+        for (int it = 0; it < iters; ++it) {
 #pragma unroll
             for (int j = 0; j < CPT; ++j) {
-                const int i = t + j * NT;
+                const int i = t + j * 64;
                 if (i < RC) {
                     DualOut o = dual_update(rpx[j], rpy[j], sW[PAD + i], sW[PAD + i + 1],
                                             sW[PAD + i + RX], fl[j], tau);
@@ -173,33 +349,29 @@ __global__ __launch_bounds__(NT) void k_iterate(ImgDesc d0, const ImgDesc* __res
                 }
             }
             __syncthreads();
-            // phase A: u-step, v-step, next w
-            const bool last = (it == nit - 1);
+            const bool last = (it == iters - 1);
 #pragma unroll
             for (int j = 0; j < CPT; ++j) {
-                const int i = t + j * NT;
+                const int i = t + j * 64;
                 if (i < RC) {
                     float dd = div_p(rpx[j], sPX[PAD + i - 1], rpy[j], sPY[PAD + i - RX]);
                     float u = u_step(rv[j], dd, theta);
                     rv[j] = v_step(u, rc[j]);
                     if (last) {
-                        if (write_u && (fl[j] & CF_OUT)) d.u[gi[j]] = u;
+                        if (fl[j] & CF_OUT) d.u[gi[j]] = u;
                     } else {
                         sW[PAD + i] = w_of(dd, rv[j], inv_theta, (fl[j] & CF_ACT) != 0);
                     }
                 }
             }
-            if (!last) __syncthreads();
+            __syncthreads();
         }
-        float* __restrict__ Vo = d.st[out_buf][0];
-        float* __restrict__ PXo = d.st[out_buf][1];
-        float* __restrict__ PYo = d.st[out_buf][2];
 #pragma unroll
         for (int j = 0; j < CPT; ++j) {
             if (fl[j] & CF_OUT) {
-                Vo[gi[j]] = rv[j];
-                PXo[gi[j]] = rpx[j];
-                PYo[gi[j]] = rpy[j];
+                d.st[0][0][gi[j]] = rv[j];
+                d.st[0][1][gi[j]] = rpx[j];
+                d.st[0][2][gi[j]] = rpy[j];
             }
         }
     }
@@ -323,6 +495,40 @@ int launch_iterate(int ci, const ImgDesc* d0, const ImgDesc* descs, bool batched
     if (g < 8) g = 8;
     hipLaunchKernelGGL(fn, dim3((unsigned)g), dim3(e.cfg.nt), 0, st, *d0, descs, queue, n_queue,
                        in_buf, nit, write_u ? 1 : 0, theta, inv_theta, tau);
+    RDSEG_HIP_CHECK(hipGetLastError());
+    return 0;
+}
+
+int g_closed_grid[2] = {0, 0};
+
+int prepare_closed(bool batched) {
+    const void* fn = batched ? reinterpret_cast<const void*>(k_closed<true>)
+                             : reinterpret_cast<const void*>(k_closed<false>);
+    int& cached = g_closed_grid[batched ? 1 : 0];
+    if (cached == 0) {
+        cached = persistent_blocks(fn, 64, 0);
+        if (cached <= 0) {
+            cached = 0;
+            set_error("occupancy query failed for the closed-tile kernel");
+            return 4;
+        }
+    }
+    return 0;
+}
+
+int launch_closed(const ImgDesc* d0, const ImgDesc* descs, bool batched, const int2* cqueue,
+                  const int32_t* n_closed, int64_t max_items, int iters, float theta,
+                  float inv_theta, float tau, hipStream_t st) {
+    if (prepare_closed(batched)) return 4;
+    int64_t g = g_closed_grid[batched ? 1 : 0];
+    if (max_items < g) g = max_items;
+    if (g < 1) g = 1;
+    if (batched)
+        hipLaunchKernelGGL(k_closed<true>, dim3((unsigned)g), dim3(64), 0, st, *d0, descs, cqueue,
+                           n_closed, iters, theta, inv_theta, tau);
+    else
+        hipLaunchKernelGGL(k_closed<false>, dim3((unsigned)g), dim3(64), 0, st, *d0, descs, cqueue,
+                           n_closed, iters, theta, inv_theta, tau);
     RDSEG_HIP_CHECK(hipGetLastError());
     return 0;
 }

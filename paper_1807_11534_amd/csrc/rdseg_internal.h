@@ -57,13 +57,33 @@ int launch_pixel_list(const float* f, int H, int W, int ld, double delta, int32_
                       int32_t* offs, int32_t* part, int32_t* total, int32_t* pix,
                       int64_t* n_pix, hipStream_t st);
 
-// Macro-tile queue (bx x by pixels, multiples of 8) from dense tile masks:
-// queue[k] = (image, local macro id) for every macro tile holding an RD pixel,
-// in ascending global order; *n_queue = count.
+// Scratch of the queue builder: tstate [n_tiles], cflags [n_tiles],
+// mflags [n_macro], offs [max(n_tiles, n_macro)], part [scan_partials of that].
+struct QueueScratch {
+    int32_t* tstate;
+    int32_t* cflags;
+    int32_t* mflags;
+    int32_t* offs;
+    int32_t* part;
+};
+
+// Work lists from dense tile masks.  Macro-tile queue (bx x by pixels,
+// multiples of 8): queue[k] = (image, local macro id) for every macro tile
+// holding an open 8x8 tile, ascending; *n_queue = count.  With cqueue non-NULL,
+// also the closed 8x8 tiles outside queued macro tiles (cqueue[k] = (image,
+// local tile id), *n_closed = count); with cqueue NULL every non-empty tile
+// counts as open.
 int launch_macro_queue(const ImgDesc* d0, const ImgDesc* descs, OffTables off, int n_img,
-                       int64_t n_macro, int bx, int by, const uint64_t* masks, int32_t* flags,
-                       int32_t* offs, int32_t* part, int2* queue, int32_t* n_queue,
-                       hipStream_t st);
+                       int64_t n_macro, int bx, int by, const uint64_t* masks,
+                       const QueueScratch& q, int2* queue, int32_t* n_queue, int64_t n_tiles,
+                       int2* cqueue, int32_t* n_closed, hipStream_t st);
+
+// All iterations of the closed 8x8 tiles in one launch (one wave per tile):
+// reads the initial state from buffer 0 and writes the final (v, p) there and u.
+int prepare_closed(bool batched);
+int launch_closed(const ImgDesc* d0, const ImgDesc* descs, bool batched, const int2* cqueue,
+                  const int32_t* n_closed, int64_t max_items, int iters, float theta,
+                  float inv_theta, float tau, hipStream_t st);
 
 // ---------------------------------------------------------------- iteration
 int launch_init(const ImgDesc* d0, const ImgDesc* descs, OffTables off, int n_img,

@@ -206,3 +206,24 @@ def test_full_size_sweep_point_1024(rd):
                        tile=(64, 64), iters_per_launch=4)
     uo, vo, po = oracle.solve(prob.f, prob.lam, prob.theta, prob.tau, delta, prob.iters)
     compare(u, v, p, uo, vo, po, prob.f, delta, "full1024", prob.iters)
+
+
+@pytest.mark.parametrize("frac", [0.02, 0.2, 0.5])
+def test_closed_tiles_match_blocked_path(rd, frac):
+    """Sparse bands: tiles whose RD pixels have no RD 4-neighbour outside them
+    run every iteration in one launch.  A solve that writes a checkpoint tape
+    routes every tile through the temporally blocked kernel instead; the two
+    must agree bitwise, and with the oracle."""
+    prob = synth.config2(1, size=256, iters=120)
+    delta = synth.band_delta(prob.f, frac)
+    ft = dev(prob.f)
+    say(f"closed tiles frac={frac}")
+    for tile, ipl in [((16, 16), 8), ((64, 64), 4)]:
+        a = [host(x) for x in rd.solve(ft, prob.lam, 0.1, 0.125, delta, 120, tile=tile,
+                                       iters_per_launch=ipl)]
+        b = [host(x) for x in rd.solve(ft, prob.lam, 0.1, 0.125, delta, 120, tile=tile,
+                                       iters_per_launch=ipl, ckpt_every=120)[:3]]
+        for x, y in zip(a, b):
+            np.testing.assert_array_equal(x, y)
+    uo, vo, po = oracle.solve(prob.f, prob.lam, 0.1, 0.125, delta, 120)
+    compare(dev(a[0]), dev(a[1]), dev(a[2]), uo, vo, po, prob.f, delta, "closed", 120)
