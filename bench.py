@@ -89,7 +89,8 @@ def sweep_cases(torch, rdseg, synth, args, dev):
                     torch.empty((2, H, W), device=dev))
         c["ws"] = rdseg.workspace(rdseg.shape_of(f))
         if args.tune == "auto":
-            tile, ipl = rdseg.autotune(f, c["lam"], synth.THETA, synth.TAU, c["delta"], 16)
+            tile, ipl = rdseg.autotune(f, c["lam"], synth.THETA, synth.TAU, c["delta"],
+                                       args.iters)
         else:
             tile, ipl = (64, 64), 4
         c["tile"], c["ipl"] = tile, ipl
@@ -166,7 +167,7 @@ def extras(torch, rdseg, synth, dev):
     prob = synth.config3()
     f = torch.from_numpy(prob.f).to(dev)
     q = float((np.abs(prob.f.astype(np.float64)) < prob.delta).mean())
-    tile, ipl = rdseg.autotune(f, prob.lam, synth.THETA, synth.TAU, prob.delta, 16)
+    tile, ipl = rdseg.autotune(f, prob.lam, synth.THETA, synth.TAU, prob.delta, 200)
     run = lambda: rdseg.solve(f, prob.lam, synth.THETA, synth.TAU, prob.delta, 1000, tile=tile,
                               iters_per_launch=ipl)
     run()

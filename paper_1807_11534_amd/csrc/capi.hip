@@ -400,7 +400,7 @@ rdseg_status solve_impl(const float* f, rdseg_shape s, const rdseg_params* prm, 
     // Closed tiles run every iteration in one launch; a solve that writes a
     // checkpoint tape sends every tile through the blocked kernel instead.
     const bool use_closed = !(prm->ckpt_every > 0 && tape) && prm->iters > 0;
-    QueueScratch qs{w.tstate, w.cflags, w.flags, w.offs, w.part};
+    QueueScratch qs{w.cflags, w.tstate, w.flags, w.offs, w.part};
     if (launch_macro_queue(&d, nullptr, off, 1, nm, cfg.bx, cfg.by, w.masks, qs, w.queue, w.totals,
                            g.nt, use_closed ? w.cqueue : nullptr, w.totals + 2, st))
         return RDSEG_ERR_HIP;
@@ -543,7 +543,7 @@ rdseg_status enqueue_batch(const BatchLayout& L, int n, int ci, int iters, doubl
     if (launch_init(d0, L.d_descs, off, n, L.rows, st)) return RDSEG_ERR_HIP;
     if (launch_tile_masks(d0, L.d_descs, off, n, L.strips, L.masks, L.npix, st)) return RDSEG_ERR_HIP;
     if (launch_sum_i64(L.npix, n, L.npix_total, st)) return RDSEG_ERR_HIP;
-    QueueScratch qs{L.tstate, L.cflags, L.flags, L.offs, L.part};
+    QueueScratch qs{L.cflags, L.tstate, L.flags, L.offs, L.part};
     const bool use_closed = iters > 0;
     if (launch_macro_queue(d0, L.d_descs, off, n, L.macros, cfg.bx, cfg.by, L.masks, qs, L.queue,
                            L.totals, L.tiles, use_closed ? L.cqueue : nullptr, L.totals + 2, st))
@@ -864,7 +864,7 @@ rdseg_status rdseg_backward(const float* f, rdseg_shape s, const rdseg_params* p
     if (launch_init(&d, nullptr, off, 1, s.H, st)) return RDSEG_ERR_HIP;   // c only
     if (launch_tile_masks(&d, nullptr, off, 1, g.strips, w.masks, w.npix, st)) return RDSEG_ERR_HIP;
     const int64_t nm = macro_count(s, kAdjTile, kAdjTile);
-    QueueScratch qs{w.tstate, nullptr, w.flags, w.offs, w.part};
+    QueueScratch qs{nullptr, nullptr, w.flags, w.offs, w.part};
     if (launch_macro_queue(&d, nullptr, off, 1, nm, kAdjTile, kAdjTile, w.masks, qs, w.queue,
                            w.totals, g.nt, nullptr, nullptr, st))
         return RDSEG_ERR_HIP;

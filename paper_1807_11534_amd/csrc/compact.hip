@@ -7,6 +7,8 @@
 // (y mod 8) * 8 + (x mod 8)).  Lists are built with a three-pass exclusive
 // scan (block sums, one-block scan of the sums, block-local scan + scatter),
 // so every list is in ascending order and identical run to run.
+#include <algorithm>
+
 #include "rdseg_internal.h"
 
 namespace rdseg {
@@ -221,106 +223,125 @@ __global__ __launch_bounds__(256) void k_pix_scatter(const float* __restrict__ f
     }
 }
 
-// ---------------------------------------------------------------- tile states
+// ---------------------------------------------------------------- work lists
 // The iteration couples two RD pixels only through 4-neighbour chains of RD
 // pixels (off RD, p = 0 and w = -H(-f)/theta are constants).  An 8x8 tile whose
 // RD pixels have no RD 4-neighbour in another tile therefore evolves on its
-// own: it is "closed" and can run every iteration on chip.  tstate: 0 = no RD
-// pixel, 1 = closed, 2 = open (or any non-empty tile when closed tiles are
-// not used).
+// own: it is "closed" and can run every iteration on chip.  A macro tile is
+// queued for the temporally blocked kernel iff it holds an open 8x8 tile
+// (closed tiles inside it are computed there too); the closed tiles of the
+// other macro tiles go to the closed-tile list.  One thread per macro tile.
 constexpr uint64_t kCol0 = 0x0101010101010101ull;
 
-template <bool BATCHED>
-__global__ void k_tile_state(ImgDesc d0, const ImgDesc* __restrict__ descs, OffTables off,
-                             int n_img, int64_t n_tiles, const uint64_t* __restrict__ masks,
-                             int use_closed, int32_t* __restrict__ tstate) {
-    int64_t T = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (T >= n_tiles) return;
-    const uint64_t m = masks[T];
-    if (!m) {
-        tstate[T] = 0;
-        return;
-    }
-    if (!use_closed) {
-        tstate[T] = 2;
-        return;
-    }
-    int img = BATCHED ? find_image(off.toff, n_img, T) : 0;
-    const ImgDesc& d = BATCHED ? descs[img] : d0;
-    const int64_t lt = T - (BATCHED ? off.toff[img] : 0);
-    const int ty = (int)(lt / d.tw), tx = (int)(lt - (int64_t)ty * d.tw);
+__device__ __forceinline__ bool tile_touches_neighbour(const uint64_t* __restrict__ masks,
+                                                       int64_t T, int tx, int ty, int tw, int th,
+                                                       uint64_t m) {
     const uint64_t mL = tx > 0 ? masks[T - 1] : 0ull;
-    const uint64_t mR = tx < d.tw - 1 ? masks[T + 1] : 0ull;
-    const uint64_t mU = ty > 0 ? masks[T - d.tw] : 0ull;
-    const uint64_t mD = ty < d.th - 1 ? masks[T + d.tw] : 0ull;
-    uint64_t touch = (m & kCol0) & ((mL >> 7) & kCol0);          // left column vs left tile
-    touch |= ((m >> 7) & kCol0) & (mR & kCol0);                   // right column vs right tile
-    touch |= (m & 0xFFull) & (mU >> 56);                          // top row vs upper tile
-    touch |= (m >> 56) & (mD & 0xFFull);                          // bottom row vs lower tile
-    tstate[T] = touch ? 2 : 1;
+    const uint64_t mR = tx < tw - 1 ? masks[T + 1] : 0ull;
+    const uint64_t mU = ty > 0 ? masks[T - tw] : 0ull;
+    const uint64_t mD = ty < th - 1 ? masks[T + tw] : 0ull;
+    uint64_t touch = (m & kCol0) & ((mL >> 7) & kCol0);   // left column vs left tile
+    touch |= ((m >> 7) & kCol0) & (mR & kCol0);            // right column vs right tile
+    touch |= (m & 0xFFull) & (mU >> 56);                   // top row vs upper tile
+    touch |= (m >> 56) & (mD & 0xFFull);                   // bottom row vs lower tile
+    return touch != 0;
 }
 
-// ---------------------------------------------------------------- macro queue
-// A macro tile is queued for the temporally blocked kernel iff it holds an open
-// 8x8 tile; closed tiles inside such a macro tile are computed there too.
 template <bool BATCHED>
-__global__ void k_macro_flags(ImgDesc d0, const ImgDesc* __restrict__ descs, OffTables off,
-                              int n_img, int64_t n_macro, int bx8, int by8,
-                              const int32_t* __restrict__ tstate, int32_t* __restrict__ flags) {
+__global__ void k_lists(ImgDesc d0, const ImgDesc* __restrict__ descs, OffTables off, int n_img,
+                        int64_t n_macro, int bx8, int by8, const uint64_t* __restrict__ masks,
+                        int use_closed, int32_t* __restrict__ mflags,
+                        int32_t* __restrict__ cflags) {
     int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= n_macro) return;
     int img = BATCHED ? find_image(off.moff, n_img, m) : 0;
     const ImgDesc& d = BATCHED ? descs[img] : d0;
     int64_t lm = m - (BATCHED ? off.moff[img] : 0);
     int my = (int)(lm / d.mw), mx = (int)(lm - (int64_t)my * d.mw);
-    int ty1 = min(d.th, (my + 1) * by8), tx1 = min(d.tw, (mx + 1) * bx8);
-    int any = 0;
-    for (int ty = my * by8; ty < ty1; ++ty)
-        for (int tx = mx * bx8; tx < tx1; ++tx)
-            any |= tstate[d.toff + (int64_t)ty * d.tw + tx] == 2 ? 1 : 0;
-    flags[m] = any;
+    int ty0 = my * by8, tx0 = mx * bx8;
+    int ty1 = min(d.th, ty0 + by8), tx1 = min(d.tw, tx0 + bx8);
+    int any_open = 0;
+    uint64_t closed_bits = 0;   // at most 8 x 8 tiles per macro tile
+    int k = 0;
+    for (int ty = ty0; ty < ty1; ++ty)
+        for (int tx = tx0; tx < tx1; ++tx, ++k) {
+            const int64_t T = d.toff + (int64_t)ty * d.tw + tx;
+            const uint64_t mk = masks[T];
+            if (!mk) continue;
+            if (!use_closed || tile_touches_neighbour(masks, T, tx, ty, d.tw, d.th, mk))
+                any_open = 1;
+            else
+                closed_bits |= 1ull << k;
+        }
+    mflags[m] = any_open;
+    if (!use_closed) return;
+    k = 0;
+    for (int ty = ty0; ty < ty1; ++ty)
+        for (int tx = tx0; tx < tx1; ++tx, ++k)
+            cflags[d.toff + (int64_t)ty * d.tw + tx] =
+                (!any_open && ((closed_bits >> k) & 1ull)) ? 1 : 0;
 }
 
-// Closed tiles that are not inside a queued macro tile.
-template <bool BATCHED>
-__global__ void k_closed_flags(ImgDesc d0, const ImgDesc* __restrict__ descs, OffTables off,
-                               int n_img, int64_t n_tiles, int bx8, int by8,
-                               const int32_t* __restrict__ tstate,
-                               const int32_t* __restrict__ mflags, int32_t* __restrict__ cflags) {
-    int64_t T = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (T >= n_tiles) return;
-    if (tstate[T] != 1) {
-        cflags[T] = 0;
-        return;
+// Exclusive scans of up to two int32 arrays of at most SMALL_N elements, one
+// 1024-thread block per array.
+constexpr int SMALL_T = 1024;
+constexpr int SMALL_I = 64;
+constexpr int64_t SMALL_N = (int64_t)SMALL_T * SMALL_I;
+
+__global__ __launch_bounds__(SMALL_T) void k_scan_small2(const int32_t* __restrict__ a, int64_t na,
+                                                         int32_t* __restrict__ oa,
+                                                         int32_t* __restrict__ ta,
+                                                         const int32_t* __restrict__ b, int64_t nb,
+                                                         int32_t* __restrict__ ob,
+                                                         int32_t* __restrict__ tb) {
+    __shared__ int s_w[SMALL_T / 64];
+    const int32_t* in = blockIdx.x == 0 ? a : b;
+    const int64_t n = blockIdx.x == 0 ? na : nb;
+    int32_t* out = blockIdx.x == 0 ? oa : ob;
+    int32_t* tot_out = blockIdx.x == 0 ? ta : tb;
+    if (!in) return;   // uniform per block
+    const int64_t base = (int64_t)threadIdx.x * SMALL_I;
+    int s = 0;
+    for (int k = 0; k < SMALL_I; ++k) s += (base + k < n) ? in[base + k] : 0;
+    int incl = wave_incl_scan(s);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 63) s_w[wid] = incl;
+    __syncthreads();
+    int pre = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < SMALL_T / 64; ++k) {
+        const int v = s_w[k];
+        pre += (k < wid) ? v : 0;
+        tot += v;
     }
-    int img = BATCHED ? find_image(off.toff, n_img, T) : 0;
-    const ImgDesc& d = BATCHED ? descs[img] : d0;
-    const int64_t lt = T - (BATCHED ? off.toff[img] : 0);
-    const int ty = (int)(lt / d.tw), tx = (int)(lt - (int64_t)ty * d.tw);
-    const int64_t M = (BATCHED ? d.moff : 0) + (int64_t)(ty / by8) * d.mw + tx / bx8;
-    cflags[T] = mflags[M] ? 0 : 1;
+    int ex = pre + incl - s;
+    for (int k = 0; k < SMALL_I; ++k) {
+        if (base + k < n) {
+            const int v = in[base + k];
+            out[base + k] = ex;
+            ex += v;
+        }
+    }
+    if (threadIdx.x == 0) *tot_out = tot;
 }
 
 template <bool BATCHED>
-__global__ void k_closed_scatter(OffTables off, int n_img, int64_t n_tiles,
-                                 const int32_t* __restrict__ cflags,
-                                 const int32_t* __restrict__ offs, int2* __restrict__ cqueue) {
-    int64_t T = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (T >= n_tiles || !cflags[T]) return;
-    int img = BATCHED ? find_image(off.toff, n_img, T) : 0;
-    int64_t lt = T - (BATCHED ? off.toff[img] : 0);
-    cqueue[offs[T]] = make_int2(img, (int)lt);
-}
-
-template <bool BATCHED>
-__global__ void k_macro_scatter(ImgDesc d0, OffTables off, int n_img, int64_t n_macro,
-                                const int32_t* __restrict__ flags,
-                                const int32_t* __restrict__ offs, int2* __restrict__ queue) {
-    int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= n_macro || !flags[m]) return;
-    int img = BATCHED ? find_image(off.moff, n_img, m) : 0;
-    int64_t lm = m - (BATCHED ? off.moff[img] : d0.moff);
-    queue[offs[m]] = make_int2(img, (int)lm);
+__global__ void k_scatter_lists(OffTables off, int n_img, int64_t n_macro, int64_t n_tiles,
+                                const int32_t* __restrict__ mflags,
+                                const int32_t* __restrict__ moffs, int2* __restrict__ queue,
+                                const int32_t* __restrict__ cflags,
+                                const int32_t* __restrict__ coffs, int2* __restrict__ cqueue) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n_macro && mflags[i]) {
+        const int img = BATCHED ? find_image(off.moff, n_img, i) : 0;
+        const int64_t lm = i - (BATCHED ? off.moff[img] : 0);
+        queue[moffs[i]] = make_int2(img, (int)lm);
+    }
+    if (cqueue && i < n_tiles && cflags[i]) {
+        const int img = BATCHED ? find_image(off.toff, n_img, i) : 0;
+        const int64_t lt = i - (BATCHED ? off.toff[img] : 0);
+        cqueue[coffs[i]] = make_int2(img, (int)lt);
+    }
 }
 
 inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
@@ -394,43 +415,34 @@ int launch_macro_queue(const ImgDesc* d0, const ImgDesc* descs, OffTables off, i
                        int2* cqueue, int32_t* n_closed, hipStream_t st) {
     const bool use_closed = cqueue != nullptr;
     if (descs)
-        hipLaunchKernelGGL(k_tile_state<true>, dim3(nblk(n_tiles, 256)), dim3(256), 0, st, *d0,
-                           descs, off, n_img, n_tiles, masks, use_closed ? 1 : 0, q.tstate);
+        hipLaunchKernelGGL(k_lists<true>, dim3(nblk(n_macro, 64)), dim3(64), 0, st, *d0, descs,
+                           off, n_img, n_macro, bx / 8, by / 8, masks, use_closed ? 1 : 0,
+                           q.mflags, q.cflags);
     else
-        hipLaunchKernelGGL(k_tile_state<false>, dim3(nblk(n_tiles, 256)), dim3(256), 0, st, *d0,
-                           descs, off, n_img, n_tiles, masks, use_closed ? 1 : 0, q.tstate);
-    if (descs)
-        hipLaunchKernelGGL(k_macro_flags<true>, dim3(nblk(n_macro, 256)), dim3(256), 0, st, *d0,
-                           descs, off, n_img, n_macro, bx / 8, by / 8, q.tstate, q.mflags);
-    else
-        hipLaunchKernelGGL(k_macro_flags<false>, dim3(nblk(n_macro, 256)), dim3(256), 0, st, *d0,
-                           descs, off, n_img, n_macro, bx / 8, by / 8, q.tstate, q.mflags);
-    int rc = launch_scan_ints(q.mflags, n_macro, q.offs, q.part, n_queue, st);
-    if (rc) return rc;
-    if (descs)
-        hipLaunchKernelGGL(k_macro_scatter<true>, dim3(nblk(n_macro, 256)), dim3(256), 0, st,
-                           *d0, off, n_img, n_macro, q.mflags, q.offs, queue);
-    else
-        hipLaunchKernelGGL(k_macro_scatter<false>, dim3(nblk(n_macro, 256)), dim3(256), 0, st,
-                           *d0, off, n_img, n_macro, q.mflags, q.offs, queue);
-    if (use_closed) {
-        if (descs)
-            hipLaunchKernelGGL(k_closed_flags<true>, dim3(nblk(n_tiles, 256)), dim3(256), 0, st,
-                               *d0, descs, off, n_img, n_tiles, bx / 8, by / 8, q.tstate, q.mflags,
-                               q.cflags);
-        else
-            hipLaunchKernelGGL(k_closed_flags<false>, dim3(nblk(n_tiles, 256)), dim3(256), 0, st,
-                               *d0, descs, off, n_img, n_tiles, bx / 8, by / 8, q.tstate, q.mflags,
-                               q.cflags);
-        rc = launch_scan_ints(q.cflags, n_tiles, q.offs, q.part, n_closed, st);
+        hipLaunchKernelGGL(k_lists<false>, dim3(nblk(n_macro, 64)), dim3(64), 0, st, *d0, descs,
+                           off, n_img, n_macro, bx / 8, by / 8, masks, use_closed ? 1 : 0,
+                           q.mflags, q.cflags);
+    if (n_macro <= SMALL_N && (!use_closed || n_tiles <= SMALL_N)) {
+        hipLaunchKernelGGL(k_scan_small2, dim3(use_closed ? 2 : 1), dim3(SMALL_T), 0, st,
+                           q.mflags, n_macro, q.offs, n_queue,
+                           use_closed ? q.cflags : nullptr, n_tiles, q.coffs, n_closed);
+    } else {
+        int rc = launch_scan_ints(q.mflags, n_macro, q.offs, q.part, n_queue, st);
         if (rc) return rc;
-        if (descs)
-            hipLaunchKernelGGL(k_closed_scatter<true>, dim3(nblk(n_tiles, 256)), dim3(256), 0, st,
-                               off, n_img, n_tiles, q.cflags, q.offs, cqueue);
-        else
-            hipLaunchKernelGGL(k_closed_scatter<false>, dim3(nblk(n_tiles, 256)), dim3(256), 0,
-                               st, off, n_img, n_tiles, q.cflags, q.offs, cqueue);
+        if (use_closed) {
+            rc = launch_scan_ints(q.cflags, n_tiles, q.coffs, q.part, n_closed, st);
+            if (rc) return rc;
+        }
     }
+    const int64_t n_all = use_closed ? std::max(n_macro, n_tiles) : n_macro;
+    if (descs)
+        hipLaunchKernelGGL(k_scatter_lists<true>, dim3(nblk(n_all, 256)), dim3(256), 0, st, off,
+                           n_img, n_macro, n_tiles, q.mflags, q.offs, queue, q.cflags, q.coffs,
+                           use_closed ? cqueue : nullptr);
+    else
+        hipLaunchKernelGGL(k_scatter_lists<false>, dim3(nblk(n_all, 256)), dim3(256), 0, st, off,
+                           n_img, n_macro, n_tiles, q.mflags, q.offs, queue, q.cflags, q.coffs,
+                           use_closed ? cqueue : nullptr);
     RDSEG_HIP_CHECK(hipGetLastError());
     return 0;
 }

@@ -77,7 +77,6 @@ __device__ __forceinline__ void run_iterations(float* __restrict__ sPX, float* _
     constexpr int RC = RX * RY;
     constexpr int CPT = (RC + NT - 1) / NT;
     constexpr int PAD = RX + 1;
-    constexpr int H0 = IT + 1;
     const int t = threadIdx.x;
     // prologue: w from the loaded state
     {

@@ -57,11 +57,11 @@ int launch_pixel_list(const float* f, int H, int W, int ld, double delta, int32_
                       int32_t* offs, int32_t* part, int32_t* total, int32_t* pix,
                       int64_t* n_pix, hipStream_t st);
 
-// Scratch of the queue builder: tstate [n_tiles], cflags [n_tiles],
-// mflags [n_macro], offs [max(n_tiles, n_macro)], part [scan_partials of that].
+// Scratch of the queue builder: mflags, offs [n_macro]; cflags, coffs
+// [n_tiles]; part [scan_partials(max(n_tiles, n_macro))].
 struct QueueScratch {
-    int32_t* tstate;
     int32_t* cflags;
+    int32_t* coffs;
     int32_t* mflags;
     int32_t* offs;
     int32_t* part;
