@@ -219,26 +219,6 @@ def main():
     updates_per_step = sum(c["q"] * n_px * args.iters for c in cases)
     value = updates_per_step / (ms_per_step * 1e-3)
 
-    # roofline pass: HIP events around every iteration-kernel launch
-    rdseg.timing_reset()
-    rdseg.timing_enable(True)
-    step()
-    torch.cuda.synchronize()
-    rdseg.timing_enable(False)
-    cfgs = rdseg.configs()
-    per_cfg = []
-    for ci, (tw, th, it, nt) in enumerate(cfgs):
-        ms, nl, by, upd = rdseg.timing_read(ci)
-        if nl:
-            per_cfg.append(dict(config=ci, kernel=f"k_iterate<{tw},{th},{it},{nt}>", ms=ms,
-                                launches=nl, alg_bytes=by, updates=upd))
-    dom = max(per_cfg, key=lambda r: r["ms"])
-    avg_ms = dom["ms"] / dom["launches"]
-    bytes_per_launch = dom["alg_bytes"] / dom["launches"]
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    all_ms, all_n, all_b, _ = rdseg.timing_read(-1)
-    rdseg.timing_reset()
-
     # per-case detail (one more timed pass, per solve)
     detail = []
     ref_labels = {}
@@ -262,6 +242,28 @@ def main():
                            speedup_vs_inf=round(ref_ms / ms, 3),
                            tile=list(c["tile"]), iters_per_launch=c["ipl"]))
 
+    # roofline pass: HIP events around every iteration-kernel launch; the last
+    # GPU work before the extras, so that its launches are the last dispatches of
+    # their kernels in a profiler trace of a run without extras
+    rdseg.timing_reset()
+    rdseg.timing_enable(True)
+    step()
+    torch.cuda.synchronize()
+    rdseg.timing_enable(False)
+    cfgs = rdseg.configs()
+    per_cfg = []
+    for ci, (tw, th, it, nt) in enumerate(cfgs):
+        ms, nl, by, upd = rdseg.timing_read(ci)
+        if nl:
+            per_cfg.append(dict(config=ci, kernel=f"k_iterate<{tw},{th},{it},{nt}>", ms=ms,
+                                launches=nl, alg_bytes=by, updates=upd))
+    dom = max(per_cfg, key=lambda r: r["ms"])
+    avg_ms = dom["ms"] / dom["launches"]
+    bytes_per_launch = dom["alg_bytes"] / dom["launches"]
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    all_ms, all_n, all_b, _ = rdseg.timing_read(-1)
+    rdseg.timing_reset()
+
     ext = None
     if not args.no_extras:
         ext = extras(torch, rdseg, synth, dev)
@@ -280,6 +282,14 @@ def main():
                    sample=f"all 12 sweep cases at {args.size}^2, {args.cpu_iters} iterations each "
                           f"(FP64, single thread), {dt:.1f} s")
 
+    # HBM bytes per launch of the dominant kernel from the counter passes
+    # (FETCH_SIZE + WRITE_SIZE, copy-calibrated) recorded under profiles/,
+    # only when they were taken from the current kernel sources
+    from paper_1807_11534_amd.profiling import recorded_traffic
+    rec = recorded_traffic(dom["kernel"], os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                                       "profiles"))
+    traffic = rec[0] if rec else None
+
     line = dict(
         metric="active pixel-updates/s (restricted-domain sweep)",
         value=value,
@@ -297,7 +307,8 @@ def main():
                     images=len(probs), solves_per_step=len(cases),
                     pixel_updates_per_step=updates_per_step),
         roofline=dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
-                      frac=achieved / HBM_PEAK_GBS, traffic=None,
+                      frac=achieved / HBM_PEAK_GBS, traffic=traffic,
+                      traffic_source=rec[1] if rec else None,
                       kernel=dom["kernel"], launches=dom["launches"], avg_launch_ms=avg_ms,
                       alg_bytes_per_launch=bytes_per_launch,
                       alg_bytes_per_update=BYTES_PER_UPDATE,

@@ -1,7 +1,8 @@
 """Summaries of rocprofv3 result databases (rocpd SQLite) for the profiles/ notes.
 
     python -m paper_1807_11534_amd.profiling --trace T.db [--fetch F.db --write W.db]
-        [--kernel SUBSTRING] [--copy-mib N] [--bench-json B.json]
+        [--kernel SUBSTRING] [--copy-mib N] [--bench-json B.json] [--traced-json T.out]
+        [--fetch-json F.out] [--write-json W.out]
 
 --trace    database of `rocprofv3 --kernel-trace --stats`
 --fetch    database of `rocprofv3 --pmc FETCH_SIZE`   (KiB per dispatch)
@@ -9,13 +10,49 @@
 --copy-mib size of the plain buffer copy run first in the counter passes; the
            ratio (copy bytes) / (counter bytes of that copy) calibrates both
            counters.
+--traced-json output of the benchmark run under the trace: its roofline pass is
+           the last GPU work of the run, so the last `launches` dispatches of
+           the kernel are the launches its HIP events timed
+--fetch-json, --write-json  the same for the two counter runs (their roofline
+           pass gives the dispatches averaged)
 Prints a short markdown report: per-kernel duration table, and for the kernel
 matching --kernel its average duration, calibrated HBM bytes per launch and,
 with --bench-json, the benchmark's live figures beside them.
 """
 import argparse
+import glob
+import hashlib
 import json
+import os
+import re
 import sqlite3
+
+_CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+# sources that define the iteration kernels: a change to either voids a
+# recorded traffic figure
+KERNEL_SOURCES = ("iterate.hip", "rdseg_device.h")
+
+
+def kernel_source_digest():
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(_CSRC, name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(kernel, profiles_dir):
+    """HBM bytes per launch of `kernel` recorded in a summary under
+    profiles_dir, or None when none was taken from the current kernel sources."""
+    want = kernel_source_digest()
+    for path in sorted(glob.glob(os.path.join(profiles_dir, "*.md"))):
+        text = open(path).read()
+        k = re.search(r"^traffic_kernel: (.+)$", text, re.M)
+        b = re.search(r"^traffic_bytes_per_launch: ([0-9.eE+]+)$", text, re.M)
+        d = re.search(r"^traffic_source_digest: ([0-9a-f]+)$", text, re.M)
+        if k and b and d and k.group(1).strip() == kernel and d.group(1) == want:
+            return float(b.group(1)), os.path.basename(path)
+    return None
 
 
 def kernel_stats(db):
@@ -27,12 +64,56 @@ def kernel_stats(db):
     return rows
 
 
+def _dispatch_source(con):
+    """(relation, name column, start column, end column) of the per-dispatch
+    kernel records in a rocpd database."""
+    rels = [r[0] for r in con.execute(
+        "select name from sqlite_master where type in ('view', 'table')").fetchall()]
+    order = sorted(rels, key=lambda r: (r != "kernels", "kernel" not in r.lower(), r))
+    for rel in order:
+        cols = [c[1] for c in con.execute(f"pragma table_info('{rel}')").fetchall()]
+        start = next((c for c in ("start", "start_ns", "begin") if c in cols), None)
+        end = next((c for c in ("end", "end_ns", "stop") if c in cols), None)
+        name = next((c for c in ("name", "kernel_name") if c in cols), None)
+        if start and end and name and "kernel" in rel.lower():
+            return rel, name, start, end
+    raise RuntimeError("no per-dispatch kernel relation among " + ", ".join(rels))
+
+
+def last_dispatches(db, substring, n):
+    """Durations (us) of the last n dispatches, by start time, of the kernel
+    whose name contains substring, and the total number of its dispatches."""
+    con = sqlite3.connect(db)
+    rel, name, start, end = _dispatch_source(con)
+    rows = con.execute(f'select "{start}", "{end}" from "{rel}" where "{name}" like ? '
+                       f'order by "{start}"', ("%" + substring + "%",)).fetchall()
+    con.close()
+    return [(e - b) * 1e-3 for b, e in rows[-n:]], len(rows)
+
+
 def counter_by_kernel(db, counter):
     con = sqlite3.connect(db)
     rows = con.execute("select kernel_name, count(*), avg(value), sum(value) from counters_collection "
                        "where counter_name = ? group by kernel_name", (counter,)).fetchall()
     con.close()
     return {r[0]: dict(dispatches=r[1], avg_kib=r[2], sum_kib=r[3]) for r in rows}
+
+
+def last_counter_values(db, counter, substring, n):
+    """Counter values (KiB) of the last n dispatches of the kernel whose name
+    contains substring, in dispatch order, or None when the table has no
+    ordering column."""
+    con = sqlite3.connect(db)
+    cols = [c[1] for c in con.execute("pragma table_info('counters_collection')").fetchall()]
+    key = next((c for c in ("dispatch_id", "start", "correlation_id", "id") if c in cols), None)
+    if key is None:
+        con.close()
+        return None
+    rows = con.execute(f'select value from counters_collection where counter_name = ? and '
+                       f'kernel_name like ? order by "{key}"',
+                       (counter, "%" + substring + "%")).fetchall()
+    con.close()
+    return [r[0] for r in rows[-n:]]
 
 
 def copy_reading(db, counter):
@@ -54,12 +135,22 @@ def main():
     ap.add_argument("--trace", required=True)
     ap.add_argument("--fetch")
     ap.add_argument("--write")
-    ap.add_argument("--kernel", default="k_iterate<64, 64, 8, 1024")
+    ap.add_argument("--kernel", help="substring of the kernel name (default: the "
+                    "benchmark's dominant kernel)")
     ap.add_argument("--copy-mib", type=float, default=0.0)
     ap.add_argument("--bench-json")
+    ap.add_argument("--traced-json", help="benchmark output of the traced run itself")
+    ap.add_argument("--fetch-json", help="benchmark output of the FETCH_SIZE run")
+    ap.add_argument("--write-json", help="benchmark output of the WRITE_SIZE run")
     ap.add_argument("--top", type=int, default=12)
     a = ap.parse_args()
 
+    if not a.kernel:
+        src = a.traced_json or a.bench_json
+        if not src:
+            ap.error("--kernel or a benchmark output is needed")
+        lines = [l for l in open(src).read().splitlines() if l.strip().startswith("{")]
+        a.kernel = json.loads(lines[-1])["roofline"]["kernel"].replace(",", ", ").rstrip(">")
     rows = kernel_stats(a.trace)
     print("| kernel | calls | total us | avg us | % |")
     print("|---|---:|---:|---:|---:|")
@@ -70,17 +161,32 @@ def main():
         print(f"\nno kernel matches {a.kernel!r}")
         return
     name, calls, tot, avg, pct = sel[0]
-    print(f"\nselected kernel `{short(name)}`: {calls} dispatches, average {avg:.3f} us")
+    print(f"\nselected kernel `{short(name)}`: {calls} dispatches in the trace (tuning probes "
+          f"included), average {avg:.3f} us")
+
+    def bench_line(path):
+        lines = [l for l in open(path).read().splitlines() if l.strip().startswith("{")]
+        return json.loads(lines[-1])
+
     bench = None
+    if a.traced_json:
+        r = bench_line(a.traced_json)["roofline"]
+        durs, total = last_dispatches(a.trace, a.kernel, r["launches"])
+        mean = sum(durs) / len(durs)
+        print(f"\nthe benchmark's roofline pass = the last {len(durs)} of {total} dispatches: "
+              f"rocprof average {mean:.3f} us; the same run's HIP-event average "
+              f"{r['avg_launch_ms'] * 1e3:.3f} us (ratio {r['avg_launch_ms'] * 1e3 / mean:.4f})")
+        print(f"algorithmic bytes per launch {r['alg_bytes_per_launch']:.4g} -> "
+              f"{r['alg_bytes_per_launch'] / (mean * 1e-6) / 1e9:.1f} GB/s at the rocprof average")
     if a.bench_json:
-        lines = [l for l in open(a.bench_json).read().splitlines() if l.strip().startswith("{")]
-        bench = json.loads(lines[-1])
+        bench = bench_line(a.bench_json)
         r = bench["roofline"]
-        print(f"benchmark (HIP events): average {r['avg_launch_ms'] * 1e3:.3f} us over "
+        print(f"unprofiled benchmark (HIP events): average {r['avg_launch_ms'] * 1e3:.3f} us over "
               f"{r['launches']} launches, algorithmic bytes per launch {r['alg_bytes_per_launch']:.4g}, "
-              f"achieved {r['achieved']:.1f} GB/s")
-        print(f"algorithmic GB/s at the rocprof average: "
-              f"{r['alg_bytes_per_launch'] / (avg * 1e-6) / 1e9:.1f}")
+              f"achieved {r['achieved']:.1f} GB/s ({r['frac']:.3f} of peak)")
+    total = 0.0
+    n_counters = 0
+    runs = {"fetch": a.fetch_json, "write": a.write_json}
     for label, db, counter in [("fetch", a.fetch, "FETCH_SIZE"), ("write", a.write, "WRITE_SIZE")]:
         if not db:
             continue
@@ -93,6 +199,26 @@ def main():
             v = k[0]
             print(f"{counter} of the selected kernel: {v['dispatches']} dispatches, average "
                   f"{v['avg_kib']:.1f} KiB raw, {v['avg_kib'] * factor * 1024 / 1e6:.3f} MB calibrated per dispatch")
+            kib = v["avg_kib"]
+            n_last = 0
+            if runs[label]:
+                r = bench_line(runs[label])["roofline"]
+                n_last = r["launches"] if r["kernel"].replace(",", ", ").rstrip(">") == a.kernel else 0
+            if n_last:
+                vals = last_counter_values(db, counter, a.kernel, n_last)
+                if vals:
+                    kib = sum(vals) / len(vals)
+                    print(f"{counter} over the roofline pass (last {len(vals)} dispatches): "
+                          f"average {kib:.1f} KiB raw, {kib * factor * 1024 / 1e6:.3f} MB calibrated")
+            total += kib * factor * 1024
+            n_counters += 1
+    if n_counters == 2:
+        print("\nmachine-readable record (read by bench.py for roofline.traffic):\n")
+        print("```")
+        print(f"traffic_kernel: {bench['roofline']['kernel'] if bench else short(name)}")
+        print(f"traffic_bytes_per_launch: {total:.0f}")
+        print(f"traffic_source_digest: {kernel_source_digest()}")
+        print("```")
 
 
 if __name__ == "__main__":
