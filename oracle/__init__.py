@@ -14,6 +14,12 @@ Parity status of each function (pins live in ``tests/test_oracle_*.py``):
 * ``dual_steps``  -- pinned (monotone dual objective, fixed point of the ROF dual).
 * ``reverse``/``tangent`` -- pinned (dot-product identity, central finite differences).
 * ``fit_term``/``fit_vjp`` -- pinned (hand-worked values, finite differences).
+* ``count_needed`` -- pinned (exact rational ceiling via ``fractions``).
+* ``band_threshold`` -- pinned (brute force over every candidate threshold on tiny
+  inputs; exact fraction and minimality on larger ones; q = 0 / 1, ties, NaN, inf).
+* ``solve_until`` -- pinned (diffs re-measured from two fixed-count solves; stop
+  index; tolerance 0 / inf; empty domain stops at the first check).
+* ``metrics``     -- pinned (hand-worked 2x3 case, identity, disjoint labels, symmetry).
 """
 import ctypes
 import os
@@ -58,6 +64,14 @@ def _load():
     lib.orc_fit_term.restype = None
     lib.orc_fit_vjp.argtypes = [_fp, _fp, c_size, c_double, c_double, _dp, _dp, _dp, _dp]
     lib.orc_fit_vjp.restype = None
+    lib.orc_count_needed.argtypes = [c_double, ctypes.c_int64]
+    lib.orc_count_needed.restype = ctypes.c_int64
+    lib.orc_band_threshold.argtypes = [_fp, c_int, c_int, c_double, _dp]
+    lib.orc_solve_until.argtypes = [_fp, c_int, c_int, c_double, c_double, c_double, c_double,
+                                    c_int, c_double, c_int, _dp, _dp, _dp, _dp, _dp, _dp, _dp,
+                                    ctypes.POINTER(c_int), _dp]
+    lib.orc_metrics.argtypes = [_dp, _dp, c_size, c_double, _i64p, _i64p, _dp]
+    lib.orc_metrics.restype = None
     _lib = lib
     return lib
 
@@ -214,3 +228,57 @@ def fit_vjp(z, c1, c2, fbar, P=None):
     lib.orc_fit_vjp(_ptr(z, _fp), _ptr(Pc, _fp), z.size, float(c1), float(c2),
                     _ptr(fb, _dp), ctypes.byref(a), ctypes.byref(b), ctypes.byref(g))
     return a.value, b.value, g.value
+
+
+def count_needed(q, n):
+    """ceil(q n), exact: the number of RD nodes a fraction q of n asks for."""
+    return int(_load().orc_count_needed(float(q), int(n)))
+
+
+def band_threshold(f, q):
+    """q-hat (Sec. 3): the smallest double with #{|f| < q-hat} >= q N."""
+    lib = _load()
+    f = _f32(f)
+    H, W = f.shape
+    out = ctypes.c_double()
+    _check(lib.orc_band_threshold(_ptr(f, _fp), H, W, float(q), ctypes.byref(out)),
+           "band_threshold")
+    return out.value
+
+
+def solve_until(f, lam, theta, tau, delta, max_iters, tol, check_every=1, u0=None, p0=None):
+    """Solve with the stopping rule of Sec. 4 evaluated every `check_every`
+    iterations.  Returns (u, v, p, iterations run, measured values), p as
+    [2][H][W]."""
+    lib = _load()
+    f = _f32(f)
+    H, W = f.shape
+    u = np.empty((H, W))
+    v = np.empty((H, W))
+    px = np.empty((H, W))
+    py = np.empty((H, W))
+    u0c = None if u0 is None else _f64(u0)
+    p0x = None if p0 is None else _f64(p0[0])
+    p0y = None if p0 is None else _f64(p0[1])
+    diffs = np.full(max(1, max_iters // check_every), np.nan)
+    done = ctypes.c_int()
+    _check(lib.orc_solve_until(_ptr(f, _fp), H, W, float(lam), float(theta), float(tau),
+                               float(delta), int(max_iters), float(tol), int(check_every),
+                               _ptr(u0c, _dp), _ptr(p0x, _dp), _ptr(p0y, _dp),
+                               _ptr(u, _dp), _ptr(v, _dp), _ptr(px, _dp), _ptr(py, _dp),
+                               ctypes.byref(done), _ptr(diffs, _dp)), "solve_until")
+    n_checks = done.value // check_every
+    return u, v, np.stack([px, py]), done.value, diffs[:n_checks]
+
+
+def metrics(u, u_gt, eps=0.5):
+    """Sec. 4 measures: (E1, E2, N(GT and Omega), N(GT or Omega))."""
+    lib = _load()
+    a = _f64(u)
+    b = _f64(u_gt)
+    assert a.shape == b.shape
+    ni, nu, e2 = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_double()
+    lib.orc_metrics(_ptr(a, _dp), _ptr(b, _dp), a.size, float(eps), ctypes.byref(ni),
+                    ctypes.byref(nu), ctypes.byref(e2))
+    e1 = 1.0 if nu.value == 0 else ni.value / nu.value
+    return e1, e2.value, ni.value, nu.value

@@ -548,3 +548,132 @@ void orc_fit_vjp(const float* z, const float* P, size_t n, double c1, double c2,
     *c2bar = s2;
     *gbar = s3;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Band threshold from a target fraction [Sec. 3: q-hat starts at 0 and is   */
+/* raised until the fraction of nodes in RD = {|f| < q-hat} reaches q].      */
+/* Reading: q-hat is the smallest double with #{|f| < q-hat} >= q N, N = all */
+/* nodes.  With a_k the k-th smallest |f| and k = ceil(q N) (exact), that is */
+/* 0 for k = 0 and the next double above a_k otherwise.  NaN and infinite    */
+/* |f| never enter RD; when fewer than k values are finite no q-hat reaches  */
+/* q and the result is +inf (RD = every finite node).                        */
+/* ------------------------------------------------------------------------ */
+
+/* ceil(q * n) in exact integer arithmetic: q = M 2^E with M a 53-bit integer. */
+int64_t orc_count_needed(double q, int64_t n)
+{
+    if (!(q > 0.0) || n <= 0) return 0;
+    if (q >= 1.0) return n;
+    int e;
+    double m = frexp(q, &e);                  /* q = m 2^e, 0.5 <= m < 1 */
+    uint64_t M = (uint64_t)ldexp(m, 53);      /* exact: q = M 2^(e - 53) */
+    int s = 53 - e;                           /* q n = M n / 2^s, s >= 53 */
+    unsigned __int128 prod = (unsigned __int128)M * (unsigned __int128)(uint64_t)n;
+    if (s >= 127) return prod > 0 ? 1 : 0;    /* 0 < q n < 1 */
+    unsigned __int128 one = 1;
+    unsigned __int128 k = (prod + ((one << s) - 1)) >> s;
+    return (int64_t)k;
+}
+
+static int cmp_double(const void* a, const void* b)
+{
+    double x = *(const double*)a, y = *(const double*)b;
+    return (x > y) - (x < y);
+}
+
+int orc_band_threshold(const float* f, int H, int W, double q, double* qhat)
+{
+    if (!f || !qhat || H < 1 || W < 1 || isnan(q) || q < 0.0 || q > 1.0) return ORC_ERR_ARG;
+    size_t N = (size_t)H * W;
+    int64_t k = orc_count_needed(q, (int64_t)N);
+    if (k == 0) { *qhat = 0.0; return ORC_OK; }
+    double* a = (double*)malloc(N * sizeof(double));
+    if (!a) return ORC_ERR_MEM;
+    size_t nf = 0;
+    for (size_t i = 0; i < N; ++i) {
+        double v = fabs((double)f[i]);
+        if (isfinite(v)) a[nf++] = v;
+    }
+    if ((size_t)k > nf) {
+        *qhat = INFINITY;
+    } else {
+        qsort(a, nf, sizeof(double), cmp_double);
+        *qhat = nextafter(a[k - 1], INFINITY);
+    }
+    free(a);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Convergence-driven solve [Sec. 4: iterate until the larger of the norms   */
+/* of u^l - u^(l-1) and v^l - v^(l-1) is at most a tolerance].               */
+/* Readings: the norm is the maximum norm over all nodes (frozen nodes never */
+/* change); the criterion is evaluated at every iteration l that is a        */
+/* multiple of check_every; the solve stops at the first such l that meets   */
+/* it, or after max_iters.  diffs (nullable) receives the measured value at  */
+/* each evaluated l, in order; *iters_done the number of iterations run.     */
+/* ------------------------------------------------------------------------ */
+int orc_solve_until(const float* f, int H, int W, double lambda, double theta, double tau,
+                    double delta, int max_iters, double tol, int check_every,
+                    const double* u0, const double* p0x, const double* p0y,
+                    double* u, double* v, double* px, double* py,
+                    int* iters_done, double* diffs)
+{
+    if (!f || !u || !v || !px || !py || !iters_done || H < 1 || W < 1 || max_iters < 0 ||
+        check_every < 1 || !(theta > 0) || !(tau > 0) || !(lambda >= 0) || isnan(delta) ||
+        isnan(tol))
+        return ORC_ERR_ARG;
+    orc_ctx c;
+    if (ctx_init(&c, f, H, W, delta)) return ORC_ERR_MEM;
+    size_t N = c.N;
+    double* uprev = (double*)malloc(N * sizeof(double));
+    double* vprev = (double*)malloc(N * sizeof(double));
+    if (!uprev || !vprev) { free(uprev); free(vprev); ctx_free(&c); return ORC_ERR_MEM; }
+    init_state(&c, lambda, theta, u0, p0x, p0y, u, v, px, py);
+    int done = 0, n_checks = 0;
+    for (int l = 1; l <= max_iters; ++l) {
+        memcpy(uprev, u, N * sizeof(double));
+        memcpy(vprev, v, N * sizeof(double));
+        dual_step(&c, theta, tau, v, px, py);
+        uv_step(&c, lambda, theta, px, py, u, v);
+        done = l;
+        if (l % check_every == 0) {
+            double d = 0.0;
+            for (size_t i = 0; i < N; ++i) {
+                double du = fabs(u[i] - uprev[i]), dv = fabs(v[i] - vprev[i]);
+                if (du > d) d = du;
+                if (dv > d) d = dv;
+            }
+            if (diffs) diffs[n_checks] = d;
+            ++n_checks;
+            if (d <= tol) break;
+        }
+    }
+    *iters_done = done;
+    free(uprev); free(vprev);
+    ctx_free(&c);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Evaluation measures [Sec. 4]: thresholded labels GT = (u_gt > eps) and    */
+/* Omega = (u > eps); E1 = N(GT and Omega) / N(GT or Omega) (Tanimoto), E2 = */
+/* the integral of (u - u_gt)^2, here a plain sum over nodes (unit cell).    */
+/* Returns the two counts and E2; E1 with an empty union is taken as 1.      */
+/* ------------------------------------------------------------------------ */
+void orc_metrics(const double* u, const double* ugt, size_t n, double eps,
+                 int64_t* n_inter, int64_t* n_union, double* e2)
+{
+    int64_t a = 0, b = 0;
+    double s = 0.0;
+    for (size_t i = 0; i < n; ++i) {
+        int g = ugt[i] > eps, o = u[i] > eps;
+        a += (g && o);
+        b += (g || o);
+        double d = u[i] - ugt[i];
+        s += d * d;
+    }
+    *n_inter = a;
+    *n_union = b;
+    *e2 = s;
+}
