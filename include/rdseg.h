@@ -130,6 +130,22 @@ rdseg_status rdseg_active_set(const float* f, rdseg_shape s, double delta,
                               int32_t* n_tiles, int32_t* pixel_idx, int64_t* n_pixels,
                               void* ws, size_t ws_bytes, void* stream);
 
+/* Band threshold from a target fraction (Sec. 3: q-hat starts at 0 and grows
+ * until the share of nodes in RD = {|f| < q-hat} reaches q).  Writes to
+ * *delta_out (device double) the smallest double q-hat with
+ * #{x : |f(x)| < q-hat} >= ceil(q * H * W), the ceiling taken exactly:
+ * 0 for q = 0, otherwise the double just above the ceil(q H W)-th smallest |f|,
+ * or +INFINITY when that value is +inf or NaN (fewer finite |f| than needed;
+ * RD is then every finite node).  Ties can make the share exceed q.  The result
+ * passed as prm->delta (or rdseg_image.delta) gives the restricted domain of
+ * fraction q; it is exact (integer counting on the bit patterns of |f|), so it
+ * equals a sort-based reference bit for bit.
+ * q in [0, 1]; ws (device) of at least rdseg_band_workspace_size() bytes.
+ * Errors: RDSEG_ERR_ARG for NULL f / delta_out or q outside [0, 1] or NaN. */
+size_t rdseg_band_workspace_size(void);
+rdseg_status rdseg_band_threshold(const float* f, rdseg_shape s, double q, double* delta_out,
+                                  void* ws, size_t ws_bytes, void* stream);
+
 /* ---------------------------------------------------------------------- */
 /* Solve (Sec. 2.1 iteration restricted as in Sec. 3)                      */
 /* ---------------------------------------------------------------------- */

@@ -55,6 +55,8 @@ SIGNATURES = {
     "rdseg_tape_size": (_sz, [ctypes.POINTER(Shape), ctypes.POINTER(Params)]),
     "rdseg_backward_workspace_size": (_sz, [ctypes.POINTER(Shape), ctypes.POINTER(Params)]),
     "rdseg_active_set": (ctypes.c_int, [_vp, Shape, _d, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "rdseg_band_workspace_size": (_sz, []),
+    "rdseg_band_threshold": (ctypes.c_int, [_vp, Shape, _d, _vp, _vp, _sz, _vp]),
     "rdseg_solve": (ctypes.c_int, [_vp, Shape, ctypes.POINTER(Params), _vp, _vp, _vp, _vp, _vp,
                                    _vp, _vp, _sz, _vp]),
     "rdseg_batched_workspace_size": (_sz, [ctypes.POINTER(Image), _i32, _i32, _i32]),

@@ -71,6 +71,21 @@ rdseg_status check_scalars(double lambda, double theta, double tau, double delta
     return RDSEG_OK;
 }
 
+// ceil(q n) without rounding error: with p = q n rounded and e = fma(q, n, -p)
+// its exact residual (q n = p + e), the ceiling moves past p only when p is
+// an integer and e > 0; a non-integer p lies within half an ulp of q n, never
+// across an integer.
+int64_t needed_count(double q, int64_t n) {
+    if (!(q > 0.0) || n <= 0) return 0;
+    if (q >= 1.0) return n;
+    const double dn = (double)n;
+    const double p = q * dn;
+    const double e = fma(q, dn, -p);
+    double c = ceil(p);
+    if (c == p && e > 0.0) c += 1.0;
+    return (int64_t)c;
+}
+
 struct Geo {
     int64_t plane, tw, th, nt, strips, chunks;
 };
@@ -715,6 +730,30 @@ rdseg_status rdseg_active_set(const float* f, rdseg_shape s, double delta, int32
             return RDSEG_ERR_HIP;
     }
     return RDSEG_OK;
+}
+
+size_t rdseg_band_workspace_size(void) {
+    Carver c(nullptr);
+    c.take<uint32_t>(kBandHistBins);
+    c.take<BandState>(1);
+    return c.off;
+}
+
+rdseg_status rdseg_band_threshold(const float* f, rdseg_shape s, double q, double* delta_out,
+                                  void* ws, size_t ws_bytes, void* stream) {
+    rdseg_status r = check_shape(s);
+    if (r) return r;
+    if (!f || !delta_out) return fail(RDSEG_ERR_ARG, "f and delta_out must be non-NULL");
+    if (!(q >= 0.0 && q <= 1.0)) return fail(RDSEG_ERR_ARG, "q must lie in [0, 1]");
+    const size_t need = rdseg_band_workspace_size();
+    if (!ws || ws_bytes < need)
+        return fail(RDSEG_ERR_WORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
+    Carver c(ws);
+    uint32_t* hist = c.take<uint32_t>(kBandHistBins);
+    BandState* state = c.take<BandState>(1);
+    const int64_t k = needed_count(q, (int64_t)s.H * s.W);
+    return hip_status(launch_band_threshold(f, s.H, s.W, (int)s.ld, k, hist, state, delta_out,
+                                            static_cast<hipStream_t>(stream)));
 }
 
 rdseg_status rdseg_solve(const float* f, rdseg_shape s, const rdseg_params* prm, const float* u0,

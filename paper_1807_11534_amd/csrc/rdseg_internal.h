@@ -85,6 +85,21 @@ int launch_closed(const ImgDesc* d0, const ImgDesc* descs, bool batched, const i
                   const int32_t* n_closed, int64_t max_items, int iters, float theta,
                   float inv_theta, float tau, hipStream_t st);
 
+// ---------------------------------------------------------------- band threshold
+// Radix-select state: digits of the k-th smallest |f| chosen so far and the
+// rank still to find among keys that share them.
+struct BandState {
+    uint32_t prefix;
+    uint32_t pad;
+    int64_t rank;
+};
+constexpr int kBandHistBins = 2048;
+// q-hat for k = ceil(q N) into *out (device double): 0 for k = 0, else the
+// double just above the k-th smallest |f| (+inf if that is not finite).
+// hist: kBandHistBins uint32 of scratch.
+int launch_band_threshold(const float* f, int H, int W, int ld, int64_t k, uint32_t* hist,
+                          BandState* state, double* out, hipStream_t st);
+
 // ---------------------------------------------------------------- iteration
 int launch_init(const ImgDesc* d0, const ImgDesc* descs, OffTables off, int n_img,
                 int64_t n_rows, hipStream_t st);

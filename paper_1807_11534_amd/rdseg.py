@@ -84,6 +84,25 @@ def active_set(f, delta, pixels=True):
     return out
 
 
+def band_threshold(f, q, out=None, ws=None):
+    """q-hat of Sec. 3 for a target fraction q of nodes in the restricted
+    domain, as a device float64 scalar tensor (no synchronisation)."""
+    lib = _lib.load()
+    s = shape_of(f)
+    if out is None:
+        out = torch.empty((), dtype=torch.float64, device=f.device)
+    if ws is None:
+        ws = torch.empty(lib.rdseg_band_workspace_size(), dtype=torch.uint8, device=f.device)
+    check(lib.rdseg_band_threshold(_vp(f), s, float(q), _vp(out), _vp(ws), ws.numel(),
+                                   _stream()))
+    return out
+
+
+def delta_for_fraction(f, q):
+    """q-hat as a Python float (synchronises once)."""
+    return float(band_threshold(f, q).item())
+
+
 def solve(f, lam, theta=THETA, tau=TAU, delta=math.inf, iters=100, u0=None, p0=None,
           tile=None, iters_per_launch=0, ckpt_every=0, out=None, ws=None):
     """Restricted-domain dual iteration (Sec. 2.1 restricted as in Sec. 3).

@@ -93,3 +93,18 @@ def test_workspace_sizes(lib):
     assert lib.rdseg_workspace_size(ctypes.byref(Shape(0, 1, 1)), None) == 0
     prm = _prm(iters=95, ckpt_every=30)
     assert lib.rdseg_tape_size(ctypes.byref(s), ctypes.byref(prm)) == 4 * 3 * 100 * 128 * 4
+
+
+def test_band_threshold_validation(lib):
+    from paper_1807_11534_amd._lib import Shape
+    n = lib.rdseg_band_workspace_size()
+    assert 8192 <= n <= 16384
+    fp, out, ws = ctypes.c_void_p(1 << 32), ctypes.c_void_p(2 << 32), ctypes.c_void_p(3 << 32)
+    sh = Shape(16, 16, 16)
+    for q in (-0.1, 1.0000001, math.nan, math.inf):
+        assert lib.rdseg_band_threshold(fp, sh, q, out, ws, n, None) == 1
+    assert lib.rdseg_band_threshold(None, sh, 0.5, out, ws, n, None) == 1
+    assert lib.rdseg_band_threshold(fp, sh, 0.5, None, ws, n, None) == 1
+    assert lib.rdseg_band_threshold(fp, sh, 0.5, out, None, n, None) == 3
+    assert lib.rdseg_band_threshold(fp, sh, 0.5, out, ws, n - 1, None) == 3
+    assert lib.rdseg_band_threshold(fp, Shape(16, 16, 8), 0.5, out, ws, n, None) == 2
