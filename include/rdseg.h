@@ -165,6 +165,49 @@ rdseg_status rdseg_solve(const float* f, rdseg_shape s, const rdseg_params* prm,
                          float* u, float* v, float* p, float* tape,
                          void* ws, size_t ws_bytes, void* stream);
 
+/* Convergence-driven solve with the stopping rule of Sec. 4: stop at the
+ * first iteration l, among the multiples of check_every, where
+ *     max( max|u^l - u^(l-1)|, max|v^l - v^(l-1)| ) <= tol
+ * (the maximum norm over all nodes; frozen nodes never change), or after
+ * prm->iters iterations.  Same arguments and outputs as rdseg_solve (no tape:
+ * prm->ckpt_every must be 0), plus
+ *   tol          stopping tolerance (the paper's delta: 1e-2 for its results,
+ *                1e-10 for its ground truth); < 0 never stops; not NaN;
+ *   check_every  >= 1 spacing of the checks;
+ *   iters_done   (device int32) iterations run, a multiple of check_every
+ *                unless the solve ran to prm->iters;
+ *   diffs        (device float[prm->iters / check_every], may be NULL only
+ *                when that count is 0) the measured change at each check, in
+ *                order; entries after the stopping check stay 0.
+ * u, v, p hold iterate iters_done, bitwise equal to rdseg_solve with
+ * prm->iters = iters_done (the change is measured in FP32).  The decision is
+ * taken on the device: launches after the stopping check return at once, so
+ * the call never synchronises.  Tile configuration as in rdseg_solve. */
+rdseg_status rdseg_solve_until(const float* f, rdseg_shape s, const rdseg_params* prm,
+                               double tol, int32_t check_every,
+                               const float* u0, const float* p0,
+                               float* u, float* v, float* p,
+                               int32_t* iters_done, float* diffs,
+                               void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------- */
+/* Evaluation measures (Sec. 4)                                             */
+/* ---------------------------------------------------------------------- */
+
+/* Measures of a result u against a reference u_ref (both device planes of
+ * shape s): with the thresholded labels Omega = {u > eps} and
+ * GT = {u_ref > eps} (values compared in FP64; the paper uses eps = 0.5),
+ * writes to out (device double[3]) the node counts N(GT and Omega) and
+ * N(GT or Omega) and E2 = sum over nodes of (u - u_ref)^2 (a unit cell per
+ * node).  E1 = out[0] / out[1] (taken as 1 when both label sets are empty).
+ * Counts are exact; E2 is an FP64 sum in a fixed order (the same bits on every
+ * call with the same shape).  ws (device) of at least
+ * rdseg_metrics_workspace_size() bytes.
+ * Errors: RDSEG_ERR_ARG for NULL pointers or NaN eps. */
+size_t rdseg_metrics_workspace_size(void);
+rdseg_status rdseg_metrics(const float* u, const float* u_ref, rdseg_shape s, double eps,
+                           double* out, void* ws, size_t ws_bytes, void* stream);
+
 /* ---------------------------------------------------------------------- */
 /* Batched solve                                                            */
 /* ---------------------------------------------------------------------- */

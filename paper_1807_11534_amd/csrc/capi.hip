@@ -269,23 +269,45 @@ struct SolvePlanArgs {
     float* tape;            // single image only
     const int64_t* npix;    // for timing
     hipStream_t st;
+    const struct StopSpec* stop = nullptr;   // convergence-driven solve (single image)
+    int launches = 0;                        // out: number of launches enqueued
+    int launches_per_check = 0;              // out (with stop)
+};
+
+// Stopping rule of a convergence-driven solve: change slots (one uint32
+// float pattern per check, zeroed first), tolerance, check spacing.
+struct StopSpec {
+    double tol;
+    int check_every;
+    uint32_t* slots;
+    int n_checks;
+    int32_t* iters_done;
 };
 
 // Enqueue the launches of `iters` iterations; the final state lands in
 // buffer 0 (the caller's v, p) and u is written by the last launch.
-rdseg_status enqueue_iterations(const SolvePlanArgs& a) {
+rdseg_status enqueue_iterations(SolvePlanArgs& a) {
     if (a.iters <= 0) return RDSEG_OK;
     const int IT = config_at(a.ci).it;
-    const int ce = (a.tape && a.ckpt_every > 0) ? a.ckpt_every : a.iters;
-    // launch schedule: segments of ce iterations, each split into <= IT chunks
+    const bool stop = a.stop != nullptr;
+    const int ce = stop ? a.stop->check_every
+                        : ((a.tape && a.ckpt_every > 0) ? a.ckpt_every : a.iters);
+    // launch schedule: segments of ce iterations (checkpoint spacing, or the
+    // spacing of the stopping rule's checks), each split into <= IT chunks
     std::vector<int> nits;
     std::vector<int> seg_start;   // launch index that starts each segment
+    std::vector<int> seg_of;      // segment of each launch
     for (int k0 = 0; k0 < a.iters; k0 += ce) {
         int len = std::min(ce, a.iters - k0);
         seg_start.push_back((int)nits.size());
-        for (int j = 0; j < len; j += IT) nits.push_back(std::min(IT, len - j));
+        for (int j = 0; j < len; j += IT) {
+            nits.push_back(std::min(IT, len - j));
+            seg_of.push_back((int)seg_start.size() - 1);
+        }
     }
     const int L = (int)nits.size();
+    a.launches = L;
+    a.launches_per_check = (ce + IT - 1) / IT;
     size_t seg = 0;
     const int64_t plane = (int64_t)a.d0->H * a.d0->ld;
     for (int j = 0; j < L; ++j) {
@@ -315,9 +337,17 @@ rdseg_status enqueue_iterations(const SolvePlanArgs& a) {
                 g_timing.has_open = true;
             }
         }
+        StopLaunch sl{};
+        if (stop) {
+            const int sg = seg_of[j];
+            const bool seg_end = (j == L - 1) || seg_of[j + 1] != sg;
+            sl.skip_slot = sg > 0 ? a.stop->slots + (sg - 1) : nullptr;
+            sl.diff_slot = (seg_end && sg < a.stop->n_checks) ? a.stop->slots + sg : nullptr;
+            sl.tol = a.stop->tol;
+        }
         int rc = launch_iterate(a.ci, a.d0, a.descs, a.descs != nullptr, a.queue, a.n_queue,
-                                a.max_items, in_buf, nits[j], j == L - 1, a.theta, a.inv_theta,
-                                a.tau, a.st);
+                                a.max_items, in_buf, nits[j], stop || j == L - 1, a.theta,
+                                a.inv_theta, a.tau, a.st, stop ? &sl : nullptr);
         if (rc) return RDSEG_ERR_HIP;
         if (g_timing.on) {
             std::lock_guard<std::mutex> lk(g_timing.mu);
@@ -370,7 +400,8 @@ rdseg_status choose_cfg(const rdseg_params& prm, const rdseg_shape& s, const int
 
 rdseg_status solve_impl(const float* f, rdseg_shape s, const rdseg_params* prm, const float* u0,
                         const float* p0, float* u, float* v, float* p, float* tape, void* ws,
-                        size_t ws_bytes, hipStream_t st, int forced_ci) {
+                        size_t ws_bytes, hipStream_t st, int forced_ci,
+                        const StopSpec* stop = nullptr) {
     if (!prm) return fail(RDSEG_ERR_ARG, "prm is NULL");
     rdseg_status r = check_shape(s);
     if (r) return r;
@@ -414,7 +445,13 @@ rdseg_status solve_impl(const float* f, rdseg_shape s, const rdseg_params* prm, 
     int64_t nm = macro_count(s, cfg.bx, cfg.by);
     // Closed tiles run every iteration in one launch; a solve that writes a
     // checkpoint tape sends every tile through the blocked kernel instead.
-    const bool use_closed = !(prm->ckpt_every > 0 && tape) && prm->iters > 0;
+    // The stopping rule needs every RD pixel's change at each check, so it
+    // also keeps closed tiles in the blocked kernel.
+    const bool use_closed = !(prm->ckpt_every > 0 && tape) && prm->iters > 0 && !stop;
+    if (stop && stop->n_checks > 0 &&
+        launch_fill(reinterpret_cast<float*>(stop->slots), 1, stop->n_checks, stop->n_checks,
+                    0.0f, st))
+        return RDSEG_ERR_HIP;
     QueueScratch qs{w.cflags, w.tstate, w.flags, w.offs, w.part};
     if (launch_macro_queue(&d, nullptr, off, 1, nm, cfg.bx, cfg.by, w.masks, qs, w.queue, w.totals,
                            g.nt, use_closed ? w.cqueue : nullptr, w.totals + 2, st))
@@ -438,7 +475,12 @@ rdseg_status solve_impl(const float* f, rdseg_shape s, const rdseg_params* prm, 
     a.tape = prm->ckpt_every > 0 ? tape : nullptr;
     a.npix = w.npix;
     a.st = st;
-    return enqueue_iterations(a);
+    a.stop = stop;
+    r = enqueue_iterations(a);
+    if (r || !stop) return r;
+    return hip_status(launch_stop_finalize(d, stop->slots, stop->n_checks, stop->tol,
+                                           stop->check_every, a.launches_per_check, a.launches,
+                                           prm->iters, stop->iters_done, st));
 }
 
 // ------------------------------------------------------------------ batched
@@ -761,6 +803,39 @@ rdseg_status rdseg_solve(const float* f, rdseg_shape s, const rdseg_params* prm,
                          size_t ws_bytes, void* stream) {
     return solve_impl(f, s, prm, u0, p0, u, v, p, tape, ws, ws_bytes,
                       static_cast<hipStream_t>(stream), -1);
+}
+
+rdseg_status rdseg_solve_until(const float* f, rdseg_shape s, const rdseg_params* prm,
+                               double tol, int32_t check_every, const float* u0, const float* p0,
+                               float* u, float* v, float* p, int32_t* iters_done, float* diffs,
+                               void* ws, size_t ws_bytes, void* stream) {
+    if (!prm) return fail(RDSEG_ERR_ARG, "prm is NULL");
+    if (isnan(tol)) return fail(RDSEG_ERR_ARG, "tol must not be NaN");
+    if (check_every < 1) return fail(RDSEG_ERR_ARG, "check_every must be >= 1");
+    if (prm->ckpt_every != 0)
+        return fail(RDSEG_ERR_ARG, "a convergence-driven solve writes no checkpoints (ckpt_every must be 0)");
+    if (!iters_done) return fail(RDSEG_ERR_ARG, "iters_done must be non-NULL");
+    const int n_checks = prm->iters > 0 ? prm->iters / check_every : 0;
+    if (n_checks > 0 && !diffs)
+        return fail(RDSEG_ERR_ARG, "diffs must hold iters / check_every floats");
+    StopSpec sp{tol, check_every, reinterpret_cast<uint32_t*>(diffs), n_checks, iters_done};
+    return solve_impl(f, s, prm, u0, p0, u, v, p, nullptr, ws, ws_bytes,
+                      static_cast<hipStream_t>(stream), -1, &sp);
+}
+
+size_t rdseg_metrics_workspace_size(void) { return align_up(metrics_partials_bytes()); }
+
+rdseg_status rdseg_metrics(const float* u, const float* u_ref, rdseg_shape s, double eps,
+                           double* out, void* ws, size_t ws_bytes, void* stream) {
+    rdseg_status r = check_shape(s);
+    if (r) return r;
+    if (!u || !u_ref || !out) return fail(RDSEG_ERR_ARG, "u, u_ref and out must be non-NULL");
+    if (isnan(eps)) return fail(RDSEG_ERR_ARG, "eps must not be NaN");
+    const size_t need = rdseg_metrics_workspace_size();
+    if (!ws || ws_bytes < need)
+        return fail(RDSEG_ERR_WORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
+    return hip_status(launch_metrics(u, u_ref, s.H, s.W, (int)s.ld, eps, static_cast<double*>(ws),
+                                     out, static_cast<hipStream_t>(stream)));
 }
 
 size_t rdseg_batched_workspace_size(const rdseg_image* imgs, int32_t n, int32_t tile_w,

@@ -65,13 +65,17 @@ __global__ __launch_bounds__(256) void k_init(ImgDesc d0, const ImgDesc* __restr
 
 // The on-chip iterations.  FAST: every region cell is inside the grid, in RD
 // and away from the last column / row, so no per-cell selects are needed.
-template <int BX, int BY, int IT, int NT, bool FAST>
+// STOP: ru holds u of the previous iteration on CF_OUT cells; with `check`,
+// the last iteration folds max(|u - u_prev|, |v - v_prev|) of those cells into
+// dmax (bit patterns of non-negative floats order like their values).
+template <int BX, int BY, int IT, int NT, bool FAST, bool STOP>
 __device__ __forceinline__ void run_iterations(float* __restrict__ sPX, float* __restrict__ sPY,
                                                float* __restrict__ sW, float* rv, float* rpx,
                                                float* rpy, const float* rc, const uint32_t* fl,
                                                const int* gi, float* __restrict__ U, int nit,
                                                int write_u, float theta, float inv_theta,
-                                               float tau) {
+                                               float tau, float* ru, bool check,
+                                               uint32_t& dmax) {
     constexpr int RX = BX + 2 * IT + 1;
     constexpr int RY = BY + 2 * IT + 1;
     constexpr int RC = RX * RY;
@@ -130,7 +134,16 @@ __device__ __forceinline__ void run_iterations(float* __restrict__ sPX, float* _
                     if (i < RC) {
                     float dd = div_p(rpx[j], sPX[PAD + i - 1], rpy[j], sPY[PAD + i - RX]);
                     float u = u_step(rv[j], dd, theta);
-                    rv[j] = v_step(u, rc[j]);
+                    const float vn = v_step(u, rc[j]);
+                    if (STOP) {
+                        if (last && check && (fl[j] & CF_OUT)) {
+                            const uint32_t a = __float_as_uint(fabsf(u - ru[j]));
+                            const uint32_t b = __float_as_uint(fabsf(vn - rv[j]));
+                            dmax = max(dmax, max(a, b));
+                        }
+                        ru[j] = u;
+                    }
+                    rv[j] = vn;
                     if (last) {
                         if (write_u && (fl[j] & CF_OUT)) U[gi[j]] = u;
                     } else {
@@ -147,12 +160,22 @@ __device__ __forceinline__ void run_iterations(float* __restrict__ sPX, float* _
 // FAST_OK: whether this instantiation carries the select-free variant for
 // tiles that lie inside the grid and inside RD (worth it for large tiles, where
 // such tiles dominate; small sparse-band tiles rarely qualify).
-template <int BX, int BY, int IT, int NT, bool BATCHED, bool FAST_OK = (BX >= 64)>
+//
+// STOP (single image, convergence-driven solve): a launch whose skip_slot
+// already holds a change <= tol does nothing (the solve has converged at an
+// earlier check; slots of checks that never ran stay 0); otherwise u of the
+// previous iteration is loaded with the state, and with diff_slot non-NULL the
+// last iteration's max(|u - u_prev|, |v - v_prev|) over RD is reduced into
+// *diff_slot (one atomicMax per wave).
+template <int BX, int BY, int IT, int NT, bool BATCHED, bool STOP, bool FAST_OK = (BX >= 64)>
 __global__ __launch_bounds__(NT) void k_iterate(ImgDesc d0, const ImgDesc* __restrict__ descs,
                                                 const int2* __restrict__ queue,
                                                 const int32_t* __restrict__ n_queue, int in_buf,
                                                 int nit, int write_u, float theta,
-                                                float inv_theta, float tau) {
+                                                float inv_theta, float tau,
+                                                const uint32_t* __restrict__ skip_slot,
+                                                uint32_t* __restrict__ diff_slot, double tol) {
+    if (STOP && skip_slot && (double)__uint_as_float(*skip_slot) <= tol) return;
     constexpr int RX = BX + 2 * IT + 1;
     constexpr int RY = BY + 2 * IT + 1;
     constexpr int RC = RX * RY;
@@ -181,6 +204,8 @@ __global__ __launch_bounds__(NT) void k_iterate(ImgDesc d0, const ImgDesc* __res
     const int q0 = xcd * chunk;
     const int q1 = min(nq, q0 + chunk);
     const int out_buf = 1 - in_buf;
+    const bool check = STOP && diff_slot != nullptr;
+    uint32_t dmax = 0u;
 
     for (int item = q0 + rank; item < q1; item += per) {
         const int2 q = queue[item];
@@ -196,6 +221,7 @@ __global__ __launch_bounds__(NT) void k_iterate(ImgDesc d0, const ImgDesc* __res
         const float* __restrict__ PYi = d.st[in_buf][2];
 
         float rv[CPT], rpx[CPT], rpy[CPT], rc[CPT];
+        float ru[STOP ? CPT : 1];
         uint32_t fl[CPT];
         int gi[CPT];
 
@@ -229,6 +255,7 @@ __global__ __launch_bounds__(NT) void k_iterate(ImgDesc d0, const ImgDesc* __res
                 const bool interior = rx >= H0 && rx < H0 + BX && ry >= H0 && ry < H0 + BY;
                 if (interior && act) f |= CF_OUT;
                 fl[j] = f;
+                if (STOP) ru[j] = (f & CF_OUT) ? d.u[g] : 0.0f;
                 plain &= (act && !(f & (CF_LASTC | CF_LASTR))) ? 1 : 0;
                 sPX[PAD + i] = rpx[j];
                 sPY[PAD + i] = rpy[j];
@@ -238,11 +265,13 @@ __global__ __launch_bounds__(NT) void k_iterate(ImgDesc d0, const ImgDesc* __res
         if (FAST_OK) fast = __syncthreads_and(plain) != 0;
         else __syncthreads();
         if (fast)
-            run_iterations<BX, BY, IT, NT, true>(sPX, sPY, sW, rv, rpx, rpy, rc, fl, gi, d.u, nit,
-                                                 write_u, theta, inv_theta, tau);
+            run_iterations<BX, BY, IT, NT, true, STOP>(sPX, sPY, sW, rv, rpx, rpy, rc, fl, gi, d.u,
+                                                       nit, write_u, theta, inv_theta, tau, ru,
+                                                       check, dmax);
         else
-            run_iterations<BX, BY, IT, NT, false>(sPX, sPY, sW, rv, rpx, rpy, rc, fl, gi, d.u, nit,
-                                                  write_u, theta, inv_theta, tau);
+            run_iterations<BX, BY, IT, NT, false, STOP>(sPX, sPY, sW, rv, rpx, rpy, rc, fl, gi,
+                                                        d.u, nit, write_u, theta, inv_theta, tau,
+                                                        ru, check, dmax);
         float* __restrict__ Vo = d.st[out_buf][0];
         float* __restrict__ PXo = d.st[out_buf][1];
         float* __restrict__ PYo = d.st[out_buf][2];
@@ -254,6 +283,10 @@ __global__ __launch_bounds__(NT) void k_iterate(ImgDesc d0, const ImgDesc* __res
                 PYo[gi[j]] = rpy[j];
             }
         }
+    }
+    if (check) {
+        for (int o = 32; o > 0; o >>= 1) dmax = max(dmax, (uint32_t)__shfl_xor((int)dmax, o));
+        if ((threadIdx.x & 63) == 0 && dmax) atomicMax(diff_slot, dmax);
     }
 }
 
@@ -394,17 +427,17 @@ __global__ __launch_bounds__(256) void k_state_copy(ImgDesc d, int buf, float* _
 
 // ---------------------------------------------------------------- config table
 using IterFn = void (*)(ImgDesc, const ImgDesc*, const int2*, const int32_t*, int, int, int,
-                        float, float, float);
+                        float, float, float, const uint32_t*, uint32_t*, double);
 
 struct CfgEntry {
     TileCfg cfg;
-    IterFn single;
-    IterFn batched;
+    IterFn fn[3];   // single image, batched, single image with the stopping rule
 };
 
-#define RDSEG_CFG(bx, by, it, nt)                                     \
-    CfgEntry{TileCfg{bx, by, it, nt}, k_iterate<bx, by, it, nt, false>, \
-             k_iterate<bx, by, it, nt, true>}
+#define RDSEG_CFG(bx, by, it, nt)                                                         \
+    CfgEntry{TileCfg{bx, by, it, nt},                                                     \
+             {k_iterate<bx, by, it, nt, false, false>, k_iterate<bx, by, it, nt, true, false>, \
+              k_iterate<bx, by, it, nt, false, true>}}
 
 const CfgEntry kCfgs[] = {
     RDSEG_CFG(8, 8, 1, 64),
@@ -426,7 +459,7 @@ const CfgEntry kCfgs[] = {
 };
 constexpr int kNumCfgs = sizeof(kCfgs) / sizeof(kCfgs[0]);
 
-int g_grid_cache[kNumCfgs][2];
+int g_grid_cache[kNumCfgs][3];
 
 }  // namespace
 
@@ -466,10 +499,11 @@ int launch_init(const ImgDesc* d0, const ImgDesc* descs, OffTables off, int n_im
     return 0;
 }
 
-int prepare_iterate(int ci, bool batched) {
+int prepare_iterate(int ci, bool batched, bool stop) {
     const CfgEntry& e = kCfgs[ci];
-    IterFn fn = batched ? e.batched : e.single;
-    int& cached = g_grid_cache[ci][batched ? 1 : 0];
+    const int kind = stop ? 2 : (batched ? 1 : 0);
+    IterFn fn = e.fn[kind];
+    int& cached = g_grid_cache[ci][kind];
     if (cached == 0) {
         cached = persistent_blocks(reinterpret_cast<const void*>(fn), e.cfg.nt, 0);
         if (cached <= 0) {
@@ -484,16 +518,79 @@ int prepare_iterate(int ci, bool batched) {
 int launch_iterate(int ci, const ImgDesc* d0, const ImgDesc* descs, bool batched,
                    const int2* queue, const int32_t* n_queue, int64_t max_items, int in_buf,
                    int nit, bool write_u, float theta, float inv_theta, float tau,
-                   hipStream_t st) {
+                   hipStream_t st, const StopLaunch* stop) {
     const CfgEntry& e = kCfgs[ci];
-    IterFn fn = batched ? e.batched : e.single;
-    if (prepare_iterate(ci, batched)) return 4;
-    int64_t g = g_grid_cache[ci][batched ? 1 : 0];
+    if (stop && batched) {
+        set_error("the stopping rule is available for single-image solves only");
+        return 1;
+    }
+    const int kind = stop ? 2 : (batched ? 1 : 0);
+    IterFn fn = e.fn[kind];
+    if (prepare_iterate(ci, batched, stop != nullptr)) return 4;
+    int64_t g = g_grid_cache[ci][kind];
     if (max_items < g) g = max_items;
     g = ((g + 7) / 8) * 8;
     if (g < 8) g = 8;
     hipLaunchKernelGGL(fn, dim3((unsigned)g), dim3(e.cfg.nt), 0, st, *d0, descs, queue, n_queue,
-                       in_buf, nit, write_u ? 1 : 0, theta, inv_theta, tau);
+                       in_buf, nit, write_u ? 1 : 0, theta, inv_theta, tau,
+                       stop ? stop->skip_slot : nullptr, stop ? stop->diff_slot : nullptr,
+                       stop ? stop->tol : 0.0);
+    RDSEG_HIP_CHECK(hipGetLastError());
+    return 0;
+}
+
+namespace {
+
+__global__ __launch_bounds__(256) void k_stop_decide(const uint32_t* __restrict__ slots,
+                                                     int n_checks, double tol, int check_every,
+                                                     int iters, int32_t* __restrict__ iters_done) {
+    __shared__ int smin[256];
+    const int t = threadIdx.x;
+    int best = n_checks;
+    for (int c = t; c < n_checks; c += 256) {
+        if ((double)__uint_as_float(slots[c]) <= tol) {
+            best = c;   // ascending per thread: the first hit is its minimum
+            break;
+        }
+    }
+    smin[t] = best;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (t < o) smin[t] = min(smin[t], smin[t + o]);
+        __syncthreads();
+    }
+    if (t == 0) *iters_done = smin[0] < n_checks ? (smin[0] + 1) * check_every : iters;
+}
+
+__global__ __launch_bounds__(256) void k_stop_copy(ImgDesc d, const int32_t* __restrict__ iters_done,
+                                                   int check_every, int launches_per_check,
+                                                   int n_launches, int iters) {
+    const int done = *iters_done;
+    if (done >= iters) return;   // ran to the end: the last launch wrote buffer 0
+    const int c = done / check_every - 1;
+    const int j = (c + 1) * launches_per_check - 1;
+    if (1 - (n_launches - j) % 2 == 0) return;
+    for (int y = blockIdx.x; y < d.H; y += gridDim.x) {
+        for (int x = threadIdx.x; x < d.W; x += blockDim.x) {
+            const int g = y * d.ld + x;
+            if (!c_active(d.c[g])) continue;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) d.st[0][k][g] = d.st[1][k][g];
+        }
+    }
+}
+
+}  // namespace
+
+int launch_stop_finalize(const ImgDesc& d, const uint32_t* slots, int n_checks, double tol,
+                         int check_every, int launches_per_check, int n_launches, int iters,
+                         int32_t* iters_done, hipStream_t st) {
+    hipLaunchKernelGGL(k_stop_decide, dim3(1), dim3(256), 0, st, slots, n_checks, tol,
+                       check_every, iters, iters_done);
+    RDSEG_HIP_CHECK(hipGetLastError());
+    const unsigned grid = (unsigned)(d.H < 4096 ? d.H : 4096);
+    hipLaunchKernelGGL(k_stop_copy, dim3(grid), dim3(256), 0, st, d, (const int32_t*)iters_done,
+                       check_every, launches_per_check, n_launches, iters);
     RDSEG_HIP_CHECK(hipGetLastError());
     return 0;
 }

@@ -100,6 +100,14 @@ constexpr int kBandHistBins = 2048;
 int launch_band_threshold(const float* f, int H, int W, int ld, int64_t k, uint32_t* hist,
                           BandState* state, double* out, hipStream_t st);
 
+// ---------------------------------------------------------------- measures
+// Sec. 4 measures of u against u_ref: out[0] = #(both labels), out[1] =
+// #(either label), out[2] = sum (u - u_ref)^2; partials of
+// metrics_partials_bytes() bytes.
+size_t metrics_partials_bytes();
+int launch_metrics(const float* u, const float* g, int H, int W, int ld, double eps,
+                   double* partials, double* out, hipStream_t st);
+
 // ---------------------------------------------------------------- iteration
 int launch_init(const ImgDesc* d0, const ImgDesc* descs, OffTables off, int n_img,
                 int64_t n_rows, hipStream_t st);
@@ -112,7 +120,16 @@ TileCfg config_at(int i);
 int config_index(int bx, int by, int it);   // -1 if not compiled
 
 // Occupancy query for the persistent grid of configuration ci (cached).
-int prepare_iterate(int ci, bool batched);
+int prepare_iterate(int ci, bool batched, bool stop = false);
+
+// Per-launch arguments of the convergence-driven solve: skip the launch when
+// *skip_slot <= tol (skip_slot nullable); reduce the last iteration's change
+// into *diff_slot (nullable: this launch does not end at a check).
+struct StopLaunch {
+    const uint32_t* skip_slot;
+    uint32_t* diff_slot;
+    double tol;
+};
 
 // One launch of the temporally blocked iteration kernel: `nit` (<= cfg.it)
 // iterations over the queued macro tiles, reading state buffer `in_buf` and
@@ -120,7 +137,16 @@ int prepare_iterate(int ci, bool batched);
 int launch_iterate(int cfg_index, const ImgDesc* d0, const ImgDesc* descs, bool batched,
                    const int2* queue, const int32_t* n_queue, int64_t max_items, int in_buf,
                    int nit, bool write_u, float theta, float inv_theta, float tau,
-                   hipStream_t st);
+                   hipStream_t st, const StopLaunch* stop = nullptr);
+
+// After a convergence-driven solve: *iters_done = (c + 1) * check_every for
+// the first check c with slots[c] <= tol (else iters), then the state of
+// that check is moved into buffer 0 when it lies in buffer 1.  The check c
+// ended launch (c + 1) * launches_per_check - 1 of n_launches, which wrote
+// buffer 1 - (n_launches - j) % 2.
+int launch_stop_finalize(const ImgDesc& d, const uint32_t* slots, int n_checks, double tol,
+                         int check_every, int launches_per_check, int n_launches, int iters,
+                         int32_t* iters_done, hipStream_t st);
 
 // Copy (v, px, py) of RD pixels between a state buffer and a full-grid slot
 // [3][H][ld] (to_slot: buffer -> slot, else slot -> buffer).

@@ -132,6 +132,57 @@ def solve(f, lam, theta=THETA, tau=TAU, delta=math.inf, iters=100, u0=None, p0=N
     return u, v, p
 
 
+def solve_until(f, lam, theta=THETA, tau=TAU, delta=math.inf, max_iters=1000, tol=1e-2,
+                check_every=1, u0=None, p0=None, tile=None, iters_per_launch=0, out=None,
+                ws=None):
+    """Solve with the stopping rule of Sec. 4 (maximum-norm change of u and v
+    at most tol, checked every `check_every` iterations, decided on the device).
+
+    Returns (u, v, p, iters_done, diffs): iters_done a device int32 scalar,
+    diffs the device float32 changes at each check (zeros after the stop)."""
+    lib = _lib.load()
+    s = shape_of(f)
+    tw, th = (0, 0) if tile is None else tile
+    prm = params(lam, theta, tau, delta, max_iters, iters_per_launch, tw, th, 0)
+    if out is None:
+        u, v, p = _empty_like_grid(f), _empty_like_grid(f), _empty_like_grid(f, 2)
+    else:
+        u, v, p = out
+    if p.stride(0) != s.H * s.ld or p.stride(1) != s.ld:
+        raise ValueError("p must be [2][H][ld] with the pitch of f")
+    n_checks = max_iters // check_every if max_iters > 0 and check_every > 0 else 0
+    diffs = torch.zeros(max(n_checks, 1), dtype=torch.float32, device=f.device)
+    done = torch.zeros((), dtype=torch.int32, device=f.device)
+    if ws is None:
+        ws = workspace(s, prm)
+    check(lib.rdseg_solve_until(_vp(f), s, ctypes.byref(prm), float(tol), int(check_every),
+                                _vp(u0), _vp(p0), _vp(u), _vp(v), _vp(p), _vp(done), _vp(diffs),
+                                _vp(ws), ws.numel(), _stream()))
+    return u, v, p, done, diffs[:n_checks]
+
+
+def metrics(u, u_ref, eps=0.5, out=None, ws=None):
+    """Sec. 4 measures on the device: tensor [N(GT and Omega), N(GT or Omega),
+    E2] (float64, no synchronisation); E1 = out[0] / out[1]."""
+    lib = _lib.load()
+    s = shape_of(u)
+    if shape_of(u_ref).H != s.H or shape_of(u_ref).W != s.W or u_ref.stride(0) != s.ld:
+        raise ValueError("u_ref must have the shape and pitch of u")
+    if out is None:
+        out = torch.empty(3, dtype=torch.float64, device=u.device)
+    if ws is None:
+        ws = torch.empty(lib.rdseg_metrics_workspace_size(), dtype=torch.uint8, device=u.device)
+    check(lib.rdseg_metrics(_vp(u), _vp(u_ref), s, float(eps), _vp(out), _vp(ws), ws.numel(),
+                            _stream()))
+    return out
+
+
+def e1_e2(u, u_ref, eps=0.5):
+    """(E1, E2) of Sec. 4 as Python floats (synchronises)."""
+    a, b, e2 = metrics(u, u_ref, eps).tolist()
+    return (1.0 if b == 0 else a / b), e2
+
+
 class BatchedSolver:
     """Many independent images solved over one global tile queue.
 

@@ -108,3 +108,35 @@ def test_band_threshold_validation(lib):
     assert lib.rdseg_band_threshold(fp, sh, 0.5, out, None, n, None) == 3
     assert lib.rdseg_band_threshold(fp, sh, 0.5, out, ws, n - 1, None) == 3
     assert lib.rdseg_band_threshold(fp, Shape(16, 16, 8), 0.5, out, ws, n, None) == 2
+
+
+def test_solve_until_validation(lib):
+    from paper_1807_11534_amd._lib import Shape
+    sh = Shape(16, 16, 16)
+    P = lambda a: ctypes.c_void_p(a << 32)
+
+    def call(prm, tol=1e-2, ce=1, done=P(9), diffs=P(10)):
+        return lib.rdseg_solve_until(P(1), sh, ctypes.byref(prm), tol, ce, None, None, P(2), P(3),
+                                     P(4), done, diffs, P(8), 1 << 40, None)
+    assert call(_prm(), tol=math.nan) == 1
+    assert call(_prm(), ce=0) == 1
+    assert call(_prm(ckpt_every=5)) == 1
+    assert call(_prm(), done=None) == 1
+    assert call(_prm(iters=10), ce=3, diffs=None) == 1
+    assert call(_prm(theta=0.0)) == 1
+    assert lib.rdseg_solve_until(P(1), sh, None, 1e-2, 1, None, None, P(2), P(3), P(4), P(9),
+                                 P(10), P(8), 1 << 40, None) == 1
+
+
+def test_metrics_validation(lib):
+    from paper_1807_11534_amd._lib import Shape
+    n = lib.rdseg_metrics_workspace_size()
+    assert n >= 1024 * 3 * 8
+    P = lambda a: ctypes.c_void_p(a << 32)
+    sh = Shape(16, 16, 16)
+    assert lib.rdseg_metrics(None, P(2), sh, 0.5, P(3), P(4), n, None) == 1
+    assert lib.rdseg_metrics(P(1), None, sh, 0.5, P(3), P(4), n, None) == 1
+    assert lib.rdseg_metrics(P(1), P(2), sh, 0.5, None, P(4), n, None) == 1
+    assert lib.rdseg_metrics(P(1), P(2), sh, math.nan, P(3), P(4), n, None) == 1
+    assert lib.rdseg_metrics(P(1), P(2), sh, 0.5, P(3), P(4), n - 1, None) == 3
+    assert lib.rdseg_metrics(P(1), P(2), Shape(0, 16, 16), 0.5, P(3), P(4), n, None) == 2
