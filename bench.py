@@ -97,6 +97,48 @@ def sweep_cases(torch, rdseg, synth, args, dev):
     return probs, cases
 
 
+def protocol(torch, rdseg, synth, dev):
+    """The evaluation protocol of Sec. 4 on synthetic stand-ins of the paper's
+    three 128^2 examples (two eq. CV terms, one eq. DS term): ground truth from
+    the unrestricted solve stopped at a change of 1e-10 (or 20000 iterations),
+    then for q = 0, 0.1, ..., 1 the restricted solve with q-hat from q, stopped
+    at 1e-2 (checked every iteration); E1, E2 against the ground truth,
+    iterations and wall time (q-hat selection included)."""
+    cases = [("disc_rect_cv", synth.config1()),
+             ("ellipses_cv", synth.config2(1, 128, 500)),
+             ("blobs_ds", synth.config3(size=128))]
+    out = {}
+    for name, pr in cases:
+        log(f"extras: protocol {name}")
+        f = torch.from_numpy(pr.f).to(dev)
+        ws = rdseg.workspace(rdseg.shape_of(f))
+        ugt, _, _, done_gt, d_gt = rdseg.solve_until(f, pr.lam, synth.THETA, synth.TAU, math.inf,
+                                                     20000, 1e-10, 1, tile=(16, 16),
+                                                     iters_per_launch=1, ws=ws)
+        ugt = ugt.clone()
+        n_gt = int(done_gt.item())
+        rows = []
+        for q in [round(0.1 * k, 1) for k in range(11)]:
+            def run():
+                delta = rdseg.band_threshold(f, q)
+                dq = float(delta.item())
+                return dq, rdseg.solve_until(f, pr.lam, synth.THETA, synth.TAU, dq, 20000, 1e-2,
+                                             1, tile=(16, 16), iters_per_launch=1, ws=ws)
+            run()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            dq, (u, v, p, done, _) = run()
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3
+            e1, e2 = rdseg.e1_e2(u, ugt)
+            rows.append(dict(q=q, qhat=dq, iters=int(done.item()), ms=round(ms, 3),
+                             E1=round(e1, 5), E2=float(f"{e2:.4g}")))
+        out[name] = dict(size=list(pr.f.shape), lam=pr.lam, gt_iters=n_gt,
+                         gt_last_change=float(d_gt[n_gt - 1].item()) if n_gt else None,
+                         rows=rows)
+    return out
+
+
 def extras(torch, rdseg, synth, dev):
     out = {}
     # ---- batched workload: 512 images, sides 64..1024, 300 iterations
@@ -162,6 +204,7 @@ def extras(torch, rdseg, synth, dev):
         out[name] = dict(size=2048, iters=300, ckpt_every=30, active_fraction=q,
                          fwd_adjoint_ms=t_fb, forward_ms=t_f)
     del f, tgt
+    out["paper_protocol_128"] = protocol(torch, rdseg, synth, dev)
     # ---- 4096^2 distance-selective solve, delta 0.1 max|f|, 1000 iterations
     log("extras: ds_4096")
     prob = synth.config3()

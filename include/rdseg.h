@@ -174,6 +174,14 @@ rdseg_status rdseg_solve(const float* f, rdseg_shape s, const rdseg_params* prm,
  *   tol          stopping tolerance (the paper's delta: 1e-2 for its results,
  *                1e-10 for its ground truth); < 0 never stops; not NaN;
  *   check_every  >= 1 spacing of the checks;
+ *   poll         0: every launch up to prm->iters is enqueued and the call
+ *                never synchronises; launches after the stopping check exit
+ *                at once (each still costs a launch).  1: the checks are read
+ *                back to the host in chunks of doubling length (2, 4, ...,
+ *                1024 checks), the next chunk running while the host looks at
+ *                the last one, and enqueuing ends one chunk after the stop; the
+ *                call waits for the checks it read and uses a small pinned host
+ *                buffer that the library allocates once;
  *   iters_done   (device int32) iterations run, a multiple of check_every
  *                unless the solve ran to prm->iters;
  *   diffs        (device float[prm->iters / check_every], may be NULL only
@@ -182,9 +190,10 @@ rdseg_status rdseg_solve(const float* f, rdseg_shape s, const rdseg_params* prm,
  * u, v, p hold iterate iters_done, bitwise equal to rdseg_solve with
  * prm->iters = iters_done (the change is measured in FP32).  The decision is
  * taken on the device: launches after the stopping check return at once, so
- * the call never synchronises.  Tile configuration as in rdseg_solve. */
+ * with poll = 0 the call never synchronises.  Tile configuration as in
+ * rdseg_solve. */
 rdseg_status rdseg_solve_until(const float* f, rdseg_shape s, const rdseg_params* prm,
-                               double tol, int32_t check_every,
+                               double tol, int32_t check_every, int32_t poll,
                                const float* u0, const float* p0,
                                float* u, float* v, float* p,
                                int32_t* iters_done, float* diffs,

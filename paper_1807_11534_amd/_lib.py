@@ -62,7 +62,8 @@ SIGNATURES = {
     "rdseg_metrics_workspace_size": (_sz, []),
     "rdseg_metrics": (ctypes.c_int, [_vp, _vp, Shape, _d, _vp, _vp, _sz, _vp]),
     "rdseg_solve_until": (ctypes.c_int, [_vp, Shape, ctypes.POINTER(Params), _d, ctypes.c_int32,
-                                         _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+                                         ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                         _sz, _vp]),
     "rdseg_batched_workspace_size": (_sz, [ctypes.POINTER(Image), _i32, _i32, _i32]),
     "rdseg_solve_batched": (ctypes.c_int, [ctypes.POINTER(Image), _i32, _d, _d, _i32, _i32, _i32,
                                            _i32, ctypes.POINTER(_vp), _vp, _sz, _vp]),

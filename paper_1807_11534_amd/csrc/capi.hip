@@ -282,6 +282,66 @@ struct StopSpec {
     uint32_t* slots;
     int n_checks;
     int32_t* iters_done;
+    bool poll;   // read the changes back chunk by chunk and stop enqueuing
+};
+
+// Host side of a polled convergence-driven solve: checks are read back in
+// chunks of doubling length through a small pinned ring (two chunks in
+// flight); the chunk after the current one is enqueued before the current
+// one is waited for, so the device stays busy while the host decides.
+constexpr int kPollMax = 1024;
+std::mutex g_poll_mu;
+float* g_poll_host = nullptr;   // 2 * kPollMax floats, pinned, kept for the process
+
+struct Poller {
+    const StopSpec& sp;
+    hipStream_t st;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    int c0[2] = {0, 0}, n[2] = {0, 0};
+    bool busy[2] = {false, false};
+    int k = 0;               // chunks issued
+    int chunk_start = 0;     // first check of the open chunk
+    int chunk_len = 2;
+    bool stopped = false;
+    bool ok = true;
+
+    Poller(const StopSpec& s, hipStream_t stream) : sp(s), st(stream) {
+        for (int r = 0; r < 2; ++r)
+            if (hipEventCreateWithFlags(&ev[r], hipEventDisableTiming) != hipSuccess) ok = false;
+    }
+    ~Poller() {
+        for (int r = 0; r < 2; ++r) {
+            if (busy[r]) (void)hipEventSynchronize(ev[r]);
+            if (ev[r]) (void)hipEventDestroy(ev[r]);
+        }
+    }
+    int chunk_end() const { return std::min(chunk_start + chunk_len, sp.n_checks) - 1; }
+    // wait for ring slot r and look for a change <= tol among its checks
+    void settle(int r) {
+        if (!busy[r]) return;
+        if (hipEventSynchronize(ev[r]) != hipSuccess) ok = false;
+        busy[r] = false;
+        const float* h = g_poll_host + r * kPollMax;
+        for (int i = 0; i < n[r]; ++i)
+            if ((double)h[i] <= sp.tol) stopped = true;
+    }
+    // called after the launch that ends check c has been enqueued
+    void after_check(int c) {
+        if (c != chunk_end()) return;
+        const int r = k & 1;
+        settle(r);   // chunk k - 2, normally settled already
+        c0[r] = chunk_start;
+        n[r] = c - chunk_start + 1;
+        if (hipMemcpyAsync(g_poll_host + r * kPollMax, sp.slots + c0[r], n[r] * sizeof(float),
+                           hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipEventRecord(ev[r], st) != hipSuccess)
+            ok = false;
+        busy[r] = true;
+        ++k;
+        chunk_start = c + 1;
+        chunk_len = std::min(chunk_len * 2, kPollMax);
+        settle(r ^ 1);   // the previous chunk, while this one runs
+    }
 };
 
 // Enqueue the launches of `iters` iterations; the final state lands in
@@ -310,6 +370,26 @@ rdseg_status enqueue_iterations(SolvePlanArgs& a) {
     a.launches_per_check = (ce + IT - 1) / IT;
     size_t seg = 0;
     const int64_t plane = (int64_t)a.d0->H * a.d0->ld;
+    std::unique_lock<std::mutex> poll_lock;
+    Poller* poller = nullptr;
+    if (stop && a.stop->poll && a.stop->n_checks > 0) {
+        poll_lock = std::unique_lock<std::mutex>(g_poll_mu);
+        if (!g_poll_host &&
+            hipHostMalloc(reinterpret_cast<void**>(&g_poll_host), 2 * kPollMax * sizeof(float), 0) !=
+                hipSuccess) {
+            g_poll_host = nullptr;
+            return fail(RDSEG_ERR_HIP, "pinned host buffer for polling could not be allocated");
+        }
+        poller = new Poller(*a.stop, a.st);
+        if (!poller->ok) {
+            delete poller;
+            return fail(RDSEG_ERR_HIP, "event creation for polling failed");
+        }
+    }
+    struct PollGuard {
+        Poller*& p;
+        ~PollGuard() { delete p; }
+    } poll_guard{poller};
     for (int j = 0; j < L; ++j) {
         int in_buf = (L - j) % 2;
         if (a.tape && seg < seg_start.size() && seg_start[seg] == j) {
@@ -349,12 +429,18 @@ rdseg_status enqueue_iterations(SolvePlanArgs& a) {
                                 a.max_items, in_buf, nits[j], stop || j == L - 1, a.theta,
                                 a.inv_theta, a.tau, a.st, stop ? &sl : nullptr);
         if (rc) return RDSEG_ERR_HIP;
+        bool stop_now = false;
+        if (poller && sl.diff_slot) {
+            poller->after_check(seg_of[j]);
+            if (!poller->ok) return fail(RDSEG_ERR_HIP, "reading back the changes failed");
+            stop_now = poller->stopped;
+        }
         if (g_timing.on) {
             std::lock_guard<std::mutex> lk(g_timing.mu);
             if (g_timing.has_open) {
                 g_timing.open.nit += nits[j];
                 g_timing.open.launches += 1;
-                if (run_end) {
+                if (run_end || stop_now) {
                     TimingRec rec = g_timing.open;
                     g_timing.has_open = false;
                     (void)hipEventRecord(rec.e1, a.st);
@@ -366,6 +452,7 @@ rdseg_status enqueue_iterations(SolvePlanArgs& a) {
                 }
             }
         }
+        if (stop_now) break;   // later launches would only skip; finalize reads the slots
     }
     return RDSEG_OK;
 }
@@ -806,7 +893,8 @@ rdseg_status rdseg_solve(const float* f, rdseg_shape s, const rdseg_params* prm,
 }
 
 rdseg_status rdseg_solve_until(const float* f, rdseg_shape s, const rdseg_params* prm,
-                               double tol, int32_t check_every, const float* u0, const float* p0,
+                               double tol, int32_t check_every, int32_t poll, const float* u0,
+                               const float* p0,
                                float* u, float* v, float* p, int32_t* iters_done, float* diffs,
                                void* ws, size_t ws_bytes, void* stream) {
     if (!prm) return fail(RDSEG_ERR_ARG, "prm is NULL");
@@ -818,7 +906,8 @@ rdseg_status rdseg_solve_until(const float* f, rdseg_shape s, const rdseg_params
     const int n_checks = prm->iters > 0 ? prm->iters / check_every : 0;
     if (n_checks > 0 && !diffs)
         return fail(RDSEG_ERR_ARG, "diffs must hold iters / check_every floats");
-    StopSpec sp{tol, check_every, reinterpret_cast<uint32_t*>(diffs), n_checks, iters_done};
+    StopSpec sp{tol, check_every, reinterpret_cast<uint32_t*>(diffs), n_checks, iters_done,
+                poll != 0};
     return solve_impl(f, s, prm, u0, p0, u, v, p, nullptr, ws, ws_bytes,
                       static_cast<hipStream_t>(stream), -1, &sp);
 }

@@ -134,9 +134,11 @@ def solve(f, lam, theta=THETA, tau=TAU, delta=math.inf, iters=100, u0=None, p0=N
 
 def solve_until(f, lam, theta=THETA, tau=TAU, delta=math.inf, max_iters=1000, tol=1e-2,
                 check_every=1, u0=None, p0=None, tile=None, iters_per_launch=0, out=None,
-                ws=None):
+                ws=None, poll=True):
     """Solve with the stopping rule of Sec. 4 (maximum-norm change of u and v
     at most tol, checked every `check_every` iterations, decided on the device).
+    poll: read the checks back in growing chunks and stop enqueuing soon after
+    the stop (synchronises); False enqueues all max_iters iterations.
 
     Returns (u, v, p, iters_done, diffs): iters_done a device int32 scalar,
     diffs the device float32 changes at each check (zeros after the stop)."""
@@ -156,7 +158,7 @@ def solve_until(f, lam, theta=THETA, tau=TAU, delta=math.inf, max_iters=1000, to
     if ws is None:
         ws = workspace(s, prm)
     check(lib.rdseg_solve_until(_vp(f), s, ctypes.byref(prm), float(tol), int(check_every),
-                                _vp(u0), _vp(p0), _vp(u), _vp(v), _vp(p), _vp(done), _vp(diffs),
+                                1 if poll else 0, _vp(u0), _vp(p0), _vp(u), _vp(v), _vp(p), _vp(done), _vp(diffs),
                                 _vp(ws), ws.numel(), _stream()))
     return u, v, p, done, diffs[:n_checks]
 

@@ -116,15 +116,15 @@ def test_solve_until_validation(lib):
     P = lambda a: ctypes.c_void_p(a << 32)
 
     def call(prm, tol=1e-2, ce=1, done=P(9), diffs=P(10)):
-        return lib.rdseg_solve_until(P(1), sh, ctypes.byref(prm), tol, ce, None, None, P(2), P(3),
-                                     P(4), done, diffs, P(8), 1 << 40, None)
+        return lib.rdseg_solve_until(P(1), sh, ctypes.byref(prm), tol, ce, 0, None, None, P(2),
+                                     P(3), P(4), done, diffs, P(8), 1 << 40, None)
     assert call(_prm(), tol=math.nan) == 1
     assert call(_prm(), ce=0) == 1
     assert call(_prm(ckpt_every=5)) == 1
     assert call(_prm(), done=None) == 1
     assert call(_prm(iters=10), ce=3, diffs=None) == 1
     assert call(_prm(theta=0.0)) == 1
-    assert lib.rdseg_solve_until(P(1), sh, None, 1e-2, 1, None, None, P(2), P(3), P(4), P(9),
+    assert lib.rdseg_solve_until(P(1), sh, None, 1e-2, 1, 0, None, None, P(2), P(3), P(4), P(9),
                                  P(10), P(8), 1 << 40, None) == 1
 
 

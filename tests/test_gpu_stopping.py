@@ -22,7 +22,7 @@ U_TOL = 1e-4            # FP32 iterate vs FP64 oracle at equal iteration count
 DIFF_TOL = 2 * U_TOL    # a change is the difference of two such iterates
 
 
-def until(f_np, lam, delta, max_iters, tol, ce, tile=(16, 16), ipl=4, pitch=None):
+def until(f_np, lam, delta, max_iters, tol, ce, tile=(16, 16), ipl=4, pitch=None, poll=True):
     import torch
 
     from paper_1807_11534_amd import rdseg
@@ -34,7 +34,7 @@ def until(f_np, lam, delta, max_iters, tol, ce, tile=(16, 16), ipl=4, pitch=None
         big[:, :W] = torch.from_numpy(f_np).cuda()
         f = big[:, :W]
     u, v, p, done, diffs = rdseg.solve_until(f, lam, TH, TAU, delta, max_iters, tol, ce,
-                                             tile=tile, iters_per_launch=ipl)
+                                             tile=tile, iters_per_launch=ipl, poll=poll)
     return (u.cpu().numpy(), v.cpu().numpy(), p.cpu().numpy(), int(done.item()),
             diffs.cpu().numpy())
 
@@ -86,6 +86,25 @@ def test_stop_equals_fixed_solve_and_oracle(gpu, kind, ce):
         assert abs(d_o[c] - tol) <= DIFF_TOL, (done, done_or)
     ur, vr, _ = oracle.solve(f, lam, TH, TAU, delta, done)
     assert np.abs(u - ur).max() < U_TOL
+
+
+@pytest.mark.parametrize("ce", [1, 3])
+def test_poll_and_device_only_agree(gpu, ce):
+    """Host polling (chunks of 2, 4, 8, ... checks) and the device-only
+    schedule give the same stop and the same bits, for stops at the first
+    check, inside and at the end of the first chunks, late, and never."""
+    f, lam, delta = problem("c1_band")
+    K = 600
+    _, _, _, _, d_all = until(f, lam, delta, K, -1.0, ce, poll=False)
+    picks = [math.inf, float(d_all[1]), float(d_all[2]), float(d_all[5]), float(d_all[6]),
+             float(np.sort(d_all)[len(d_all) // 3]), float(d_all.min()), -1.0]
+    for tol in picks:
+        a = until(f, lam, delta, K, tol, ce, poll=True)
+        b = until(f, lam, delta, K, tol, ce, poll=False)
+        assert a[3] == b[3], tol
+        for x, y in zip(a[:3], b[:3]):
+            np.testing.assert_array_equal(x, y)
+        np.testing.assert_array_equal(a[4], b[4])
 
 
 def test_stop_is_configuration_invariant(gpu):
