@@ -63,19 +63,26 @@ __global__ __launch_bounds__(256) void k_init(ImgDesc d0, const ImgDesc* __restr
     }
 }
 
-// The on-chip iterations.  FAST: every region cell is inside the grid, in RD
-// and away from the last column / row, so no per-cell selects are needed.
+// The on-chip iterations.  Slot j of a thread is region cell t + j * NT in
+// MODE_DENSE (every region cell, with per-cell selects for cells off RD and on
+// the last column / row) and MODE_FAST (every region cell is inside the grid,
+// in RD and away from the last column / row: no selects), and the j-th entry
+// of the block's ascending list of RD cells in MODE_COMPACT (idx[j] < 0: empty
+// slot); there cells off RD are never visited: their p = 0 and
+// w = -H(-f)/theta were stored in LDS when the region was loaded.
 // STOP: ru holds u of the previous iteration on CF_OUT cells; with `check`,
 // the last iteration folds max(|u - u_prev|, |v - v_prev|) of those cells into
 // dmax (bit patterns of non-negative floats order like their values).
-template <int BX, int BY, int IT, int NT, bool FAST, bool STOP>
+enum { MODE_DENSE = 0, MODE_FAST = 1, MODE_COMPACT = 2 };
+
+template <int BX, int BY, int IT, int NT, int MODE, bool STOP>
 __device__ __forceinline__ void run_iterations(float* __restrict__ sPX, float* __restrict__ sPY,
-                                               float* __restrict__ sW, float* rv, float* rpx,
-                                               float* rpy, const float* rc, const uint32_t* fl,
-                                               const int* gi, float* __restrict__ U, int nit,
-                                               int write_u, float theta, float inv_theta,
-                                               float tau, float* ru, bool check,
-                                               uint32_t& dmax) {
+                                               float* __restrict__ sW, const int* idx, float* rv,
+                                               float* rpx, float* rpy, const float* rc,
+                                               const uint32_t* fl, const int* gi,
+                                               float* __restrict__ U, int nit, int write_u,
+                                               float theta, float inv_theta, float tau, float* ru,
+                                               bool check, uint32_t& dmax) {
     constexpr int RX = BX + 2 * IT + 1;
     constexpr int RY = BY + 2 * IT + 1;
     constexpr int RC = RX * RY;
@@ -86,11 +93,11 @@ __device__ __forceinline__ void run_iterations(float* __restrict__ sPX, float* _
     {
 #pragma unroll
         for (int j = 0; j < CPT; ++j) {
-            const int i = t + j * NT;
-            if (i < RC) {
+            const int i = MODE == MODE_COMPACT ? idx[j] : t + j * NT;
+            if (MODE == MODE_COMPACT ? (i >= 0) : (i < RC)) {
                 float dd = div_p(rpx[j], sPX[PAD + i - 1], rpy[j], sPY[PAD + i - RX]);
-                sW[PAD + i] = FAST ? fmaf(-rv[j], inv_theta, dd)
-                                   : w_of(dd, rv[j], inv_theta, (fl[j] & CF_ACT) != 0);
+                sW[PAD + i] = w_of(dd, rv[j], inv_theta,
+                                   MODE == MODE_DENSE ? (fl[j] & CF_ACT) != 0 : true);
             }
         }
     }
@@ -100,11 +107,11 @@ __device__ __forceinline__ void run_iterations(float* __restrict__ sPX, float* _
         {
 #pragma unroll
             for (int j = 0; j < CPT; ++j) {
-                const int i = t + j * NT;
-                    if (i < RC) {
+                const int i = MODE == MODE_COMPACT ? idx[j] : t + j * NT;
+                if (MODE == MODE_COMPACT ? (i >= 0) : (i < RC)) {
                     const float wc = sW[PAD + i];
                     float npx, npy;
-                    if (FAST) {
+                    if (MODE == MODE_FAST) {
                         const float gx = sW[PAD + i + 1] - wc;
                         const float gy = sW[PAD + i + RX] - wc;
                         const float nn = __builtin_amdgcn_sqrtf(fmaf(gx, gx, gy * gy));
@@ -130,8 +137,8 @@ __device__ __forceinline__ void run_iterations(float* __restrict__ sPX, float* _
         {
 #pragma unroll
             for (int j = 0; j < CPT; ++j) {
-                const int i = t + j * NT;
-                    if (i < RC) {
+                const int i = MODE == MODE_COMPACT ? idx[j] : t + j * NT;
+                if (MODE == MODE_COMPACT ? (i >= 0) : (i < RC)) {
                     float dd = div_p(rpx[j], sPX[PAD + i - 1], rpy[j], sPY[PAD + i - RX]);
                     float u = u_step(rv[j], dd, theta);
                     const float vn = v_step(u, rc[j]);
@@ -147,8 +154,8 @@ __device__ __forceinline__ void run_iterations(float* __restrict__ sPX, float* _
                     if (last) {
                         if (write_u && (fl[j] & CF_OUT)) U[gi[j]] = u;
                     } else {
-                        sW[PAD + i] = FAST ? fmaf(-rv[j], inv_theta, dd)
-                                           : w_of(dd, rv[j], inv_theta, (fl[j] & CF_ACT) != 0);
+                        sW[PAD + i] = w_of(dd, rv[j], inv_theta,
+                                           MODE == MODE_DENSE ? (fl[j] & CF_ACT) != 0 : true);
                     }
                 }
             }
@@ -157,9 +164,32 @@ __device__ __forceinline__ void run_iterations(float* __restrict__ sPX, float* _
     }
 }
 
+// Per-cell flags of region cell (rx, ry) at grid position (gx, gy).
+template <int BX, int BY, int IT>
+__device__ __forceinline__ uint32_t cell_flags(bool act, int rx, int ry, int gx, int gy, int W,
+                                               int H) {
+    constexpr int H0 = IT + 1;
+    uint32_t f = act ? CF_ACT : 0u;
+    if (gx == W - 1) f |= CF_LASTC;
+    if (gy == H - 1) f |= CF_LASTR;
+    const bool interior = rx >= H0 && rx < H0 + BX && ry >= H0 && ry < H0 + BY;
+    if (interior && act) f |= CF_OUT;
+    return f;
+}
+
 // FAST_OK: whether this instantiation carries the select-free variant for
 // tiles that lie inside the grid and inside RD (worth it for large tiles, where
-// such tiles dominate; small sparse-band tiles rarely qualify).
+// such tiles dominate).  COMPACT_OK (the smaller tiles, chosen for sparse
+// bands): a tile whose region is less than 40 % RD runs on its compacted RD
+// cells (the 64-wide tiles serve dense images and skip this machinery, which
+// costs them a few per cent of LDS traffic and barriers): wave ballots of
+// the RD flags, a scan of the per-wave counts and a scatter give the ascending
+// list of RD cells, and the threads take the listed cells in order, so the
+// work per iteration follows the number of RD cells.  Listed cells are
+// gathered from LDS (scattered addresses, bank conflicts), which costs about
+// 2.4x a dense cell, so denser tiles run every region cell with selects.  The
+// arithmetic per cell is the same in every variant, so the results do not
+// depend on which one ran.
 //
 // STOP (single image, convergence-driven solve): a launch whose skip_slot
 // already holds a change <= tol does nothing (the solve has converged at an
@@ -167,7 +197,8 @@ __device__ __forceinline__ void run_iterations(float* __restrict__ sPX, float* _
 // previous iteration is loaded with the state, and with diff_slot non-NULL the
 // last iteration's max(|u - u_prev|, |v - v_prev|) over RD is reduced into
 // *diff_slot (one atomicMax per wave).
-template <int BX, int BY, int IT, int NT, bool BATCHED, bool STOP, bool FAST_OK = (BX >= 64)>
+template <int BX, int BY, int IT, int NT, bool BATCHED, bool STOP, bool FAST_OK = (BX >= 64),
+          bool COMPACT_OK = (BX < 64)>
 __global__ __launch_bounds__(NT) void k_iterate(ImgDesc d0, const ImgDesc* __restrict__ descs,
                                                 const int2* __restrict__ queue,
                                                 const int32_t* __restrict__ n_queue, int in_buf,
@@ -183,11 +214,20 @@ __global__ __launch_bounds__(NT) void k_iterate(ImgDesc d0, const ImgDesc* __res
     constexpr int PAD = RX + 1;
     constexpr int LS = RC + 2 * PAD;
     constexpr int H0 = IT + 1;   // left / top halo
+    constexpr int NW = NT / 64;  // waves per workgroup
+    constexpr int NCNT = CPT * NW;
+    static_assert(NT % 64 == 0 && NCNT <= 128, "the count scan covers at most 128 entries");
+    static_assert(RC < 32768, "region index must fit the 16-bit cell list");
     __shared__ float sPX[LS];
     __shared__ float sPY[LS];
     __shared__ float sW[LS];
+    __shared__ float sC[COMPACT_OK ? RC : 1];
+    __shared__ uint16_t sList[COMPACT_OK ? RC : 1];
+    __shared__ int sCnt[COMPACT_OK ? NCNT + 1 : 1];
 
     const int t = threadIdx.x;
+    const int lane = t & 63;
+    const int wv = t >> 6;
     for (int k = t; k < PAD; k += NT) {
         sPX[k] = 0.0f; sPY[k] = 0.0f; sW[k] = 0.0f;
         sPX[PAD + RC + k] = 0.0f; sPY[PAD + RC + k] = 0.0f; sW[PAD + RC + k] = 0.0f;
@@ -224,6 +264,8 @@ __global__ __launch_bounds__(NT) void k_iterate(ImgDesc d0, const ImgDesc* __res
         float ru[STOP ? CPT : 1];
         uint32_t fl[CPT];
         int gi[CPT];
+        int idx[CPT];
+        uint64_t amask[CPT];
 
         __syncthreads();   // LDS of the previous item fully consumed
         int plain = 1;     // every cell inside the grid, in RD, off the last column / row
@@ -232,6 +274,7 @@ __global__ __launch_bounds__(NT) void k_iterate(ImgDesc d0, const ImgDesc* __res
             const int i = t + j * NT;
             rv[j] = 0.0f; rpx[j] = 0.0f; rpy[j] = 0.0f; rc[j] = __builtin_inff();
             fl[j] = 0u; gi[j] = 0;
+            bool act = false;
             if (i < RC) {
                 const int ry = i / RX;
                 const int rx = i - ry * RX;
@@ -239,8 +282,8 @@ __global__ __launch_bounds__(NT) void k_iterate(ImgDesc d0, const ImgDesc* __res
                 const bool inb = (unsigned)gx < (unsigned)W && (unsigned)gy < (unsigned)H;
                 const int g = gy * ld + gx;
                 gi[j] = g;
-                float c = inb ? C[g] : __builtin_inff();
-                const bool act = c_active(c);
+                const float c = inb ? C[g] : __builtin_inff();
+                act = c_active(c);
                 rc[j] = c;
                 if (act) {
                     rv[j] = Vi[g];
@@ -249,29 +292,98 @@ __global__ __launch_bounds__(NT) void k_iterate(ImgDesc d0, const ImgDesc* __res
                 } else {
                     rv[j] = heav_from_c(c);
                 }
-                uint32_t f = act ? CF_ACT : 0u;
-                if (gx == W - 1) f |= CF_LASTC;
-                if (gy == H - 1) f |= CF_LASTR;
-                const bool interior = rx >= H0 && rx < H0 + BX && ry >= H0 && ry < H0 + BY;
-                if (interior && act) f |= CF_OUT;
+                const uint32_t f = cell_flags<BX, BY, IT>(act, rx, ry, gx, gy, W, H);
                 fl[j] = f;
                 if (STOP) ru[j] = (f & CF_OUT) ? d.u[g] : 0.0f;
                 plain &= (act && !(f & (CF_LASTC | CF_LASTR))) ? 1 : 0;
                 sPX[PAD + i] = rpx[j];
                 sPY[PAD + i] = rpy[j];
+                if (COMPACT_OK) {
+                    // RD cells park v here until the prologue writes their w;
+                    // other cells hold their constant w = -H(-f)/theta
+                    sW[PAD + i] = act ? rv[j] : w_of(0.0f, rv[j], inv_theta, false);
+                    sC[i] = c;
+                }
             }
+            if (COMPACT_OK) amask[j] = __ballot(act);
         }
         bool fast = false;
         if (FAST_OK) fast = __syncthreads_and(plain) != 0;
         else __syncthreads();
-        if (fast)
-            run_iterations<BX, BY, IT, NT, true, STOP>(sPX, sPY, sW, rv, rpx, rpy, rc, fl, gi, d.u,
-                                                       nit, write_u, theta, inv_theta, tau, ru,
-                                                       check, dmax);
-        else
-            run_iterations<BX, BY, IT, NT, false, STOP>(sPX, sPY, sW, rv, rpx, rpy, rc, fl, gi,
-                                                        d.u, nit, write_u, theta, inv_theta, tau,
-                                                        ru, check, dmax);
+        if (fast) {
+            run_iterations<BX, BY, IT, NT, MODE_FAST, STOP>(sPX, sPY, sW, idx, rv, rpx, rpy, rc,
+                                                            fl, gi, d.u, nit, write_u, theta,
+                                                            inv_theta, tau, ru, check, dmax);
+        } else if (!COMPACT_OK) {
+            run_iterations<BX, BY, IT, NT, MODE_DENSE, STOP>(sPX, sPY, sW, idx, rv, rpx, rpy, rc,
+                                                             fl, gi, d.u, nit, write_u, theta,
+                                                             inv_theta, tau, ru, check, dmax);
+        } else {
+            // count the RD cells of the region (ascending list offsets)
+            if (lane == 0) {
+#pragma unroll
+                for (int j = 0; j < CPT; ++j) sCnt[j * NW + wv] = __popcll(amask[j]);
+            }
+            __syncthreads();
+            if (wv == 0) {   // exclusive scan of the NCNT counts, two per lane
+                const int e0 = 2 * lane < NCNT ? sCnt[2 * lane] : 0;
+                const int e1 = 2 * lane + 1 < NCNT ? sCnt[2 * lane + 1] : 0;
+                const int s = e0 + e1;
+                int incl = s;
+                for (int o = 1; o < 64; o <<= 1) {
+                    const int y = __shfl_up(incl, o);
+                    if (lane >= o) incl += y;
+                }
+                const int excl = incl - s;
+                if (2 * lane < NCNT) sCnt[2 * lane] = excl;
+                if (2 * lane + 1 < NCNT) sCnt[2 * lane + 1] = excl + e0;
+                if (lane == 63) sCnt[NCNT] = incl;
+            }
+            __syncthreads();
+            const int n_act = sCnt[NCNT];
+            if (5 * n_act >= 2 * RC) {   // dense enough: every region cell
+                run_iterations<BX, BY, IT, NT, MODE_DENSE, STOP>(sPX, sPY, sW, idx, rv, rpx, rpy,
+                                                                 rc, fl, gi, d.u, nit, write_u,
+                                                                 theta, inv_theta, tau, ru,
+                                                                 check, dmax);
+            } else {
+                const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+                for (int j = 0; j < CPT; ++j) {
+                    if ((amask[j] >> lane) & 1ull)
+                        sList[sCnt[j * NW + wv] + __popcll(amask[j] & below)] =
+                            (uint16_t)(t + j * NT);
+                }
+                __syncthreads();
+#pragma unroll
+                for (int j = 0; j < CPT; ++j) {
+                    const int k = t + j * NT;
+                    idx[j] = -1;
+                    fl[j] = 0u;
+                    if (k < n_act) {
+                        const int i = sList[k];
+                        const int ry = i / RX;
+                        const int rx = i - ry * RX;
+                        const int gx = ox + rx, gy = oy + ry;
+                        const int g = gy * ld + gx;
+                        idx[j] = i;
+                        gi[j] = g;
+                        rv[j] = sW[PAD + i];
+                        rpx[j] = sPX[PAD + i];
+                        rpy[j] = sPY[PAD + i];
+                        rc[j] = sC[i];
+                        const uint32_t f = cell_flags<BX, BY, IT>(true, rx, ry, gx, gy, W, H);
+                        fl[j] = f;
+                        if (STOP) ru[j] = (f & CF_OUT) ? d.u[g] : 0.0f;
+                    }
+                }
+                __syncthreads();   // parked v read before the prologue overwrites it
+                run_iterations<BX, BY, IT, NT, MODE_COMPACT, STOP>(sPX, sPY, sW, idx, rv, rpx, rpy,
+                                                                   rc, fl, gi, d.u, nit, write_u,
+                                                                   theta, inv_theta, tau, ru,
+                                                                   check, dmax);
+            }
+        }
         float* __restrict__ Vo = d.st[out_buf][0];
         float* __restrict__ PXo = d.st[out_buf][1];
         float* __restrict__ PYo = d.st[out_buf][2];
