@@ -282,19 +282,24 @@ __global__ __launch_bounds__(NT) void k_iterate(ImgDesc d0, const ImgDesc* __res
                 const bool inb = (unsigned)gx < (unsigned)W && (unsigned)gy < (unsigned)H;
                 const int g = gy * ld + gx;
                 gi[j] = g;
-                const float c = inb ? C[g] : __builtin_inff();
+                // all loads of the cell are issued together (one memory round
+                // trip); state read off RD is discarded by the selects below
+                float c = __builtin_inff(), v = 0.0f, px = 0.0f, py = 0.0f, uo = 0.0f;
+                if (inb) {
+                    c = C[g];
+                    v = Vi[g];
+                    px = PXi[g];
+                    py = PYi[g];
+                    if (STOP) uo = d.u[g];
+                }
                 act = c_active(c);
                 rc[j] = c;
-                if (act) {
-                    rv[j] = Vi[g];
-                    rpx[j] = PXi[g];
-                    rpy[j] = PYi[g];
-                } else {
-                    rv[j] = heav_from_c(c);
-                }
+                rv[j] = act ? v : heav_from_c(c);
+                rpx[j] = act ? px : 0.0f;
+                rpy[j] = act ? py : 0.0f;
                 const uint32_t f = cell_flags<BX, BY, IT>(act, rx, ry, gx, gy, W, H);
                 fl[j] = f;
-                if (STOP) ru[j] = (f & CF_OUT) ? d.u[g] : 0.0f;
+                if (STOP) ru[j] = (f & CF_OUT) ? uo : 0.0f;
                 plain &= (act && !(f & (CF_LASTC | CF_LASTR))) ? 1 : 0;
                 sPX[PAD + i] = rpx[j];
                 sPY[PAD + i] = rpy[j];
