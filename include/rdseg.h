@@ -59,19 +59,24 @@ typedef struct {
 
 /* Solver parameters.  lambda >= 0, theta > 0, tau > 0 finite; delta not NaN
  * (+INFINITY = full domain, the paper's q = 1; delta <= min|f| = pure
- * thresholding, q = 0).  iters >= 0 outer iterations, each one dual step, one
- * u-step and one v-step.  iters_per_launch, tile_w, tile_h: the temporally
- * blocked kernel runs iters_per_launch iterations per launch on tile_w x tile_h
- * blocks (multiples of 8); 0 = chosen by the library (autotuned, see
- * rdseg_autotune; choosing synchronises the stream once).  ckpt_every > 0
- * asks rdseg_solve to write a checkpoint of (v, p) every ckpt_every
- * iterations into `tape` for rdseg_backward. */
+ * thresholding, q = 0).  iters >= 0 outer iterations, each `inner` dual steps
+ * (Chambolle's fixed point for p with v held, Sec. 3), one u-step and one
+ * v-step; inner = 0 or 1 means one dual step, at most 16 (between the dual
+ * steps of one outer iteration w = div p - v/theta is refreshed with the same
+ * v).  iters_per_launch, tile_w, tile_h: the temporally blocked kernel runs
+ * iters_per_launch dual steps per launch (its halo depth, so
+ * iters_per_launch / inner outer iterations; it must be >= inner) on
+ * tile_w x tile_h blocks (multiples of 8); 0 = chosen by the library
+ * (autotuned, see rdseg_autotune; choosing synchronises the stream once).
+ * ckpt_every > 0 asks rdseg_solve to write a checkpoint of (v, p) every
+ * ckpt_every iterations into `tape` for rdseg_backward (inner = 1 only). */
 typedef struct {
     double lambda, theta, tau, delta;
     int32_t iters;
     int32_t iters_per_launch;
     int32_t tile_w, tile_h;
     int32_t ckpt_every;
+    int32_t inner;
 } rdseg_params;
 
 /* Fitting term of Sec. 1: f = (z - c1)^2 - (z - c2)^2 + gamma P   (eq. CV when

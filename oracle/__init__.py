@@ -69,7 +69,7 @@ def _load():
     lib.orc_band_threshold.argtypes = [_fp, c_int, c_int, c_double, _dp]
     lib.orc_solve_until.argtypes = [_fp, c_int, c_int, c_double, c_double, c_double, c_double,
                                     c_int, c_double, c_int, _dp, _dp, _dp, _dp, _dp, _dp, _dp,
-                                    ctypes.POINTER(c_int), _dp]
+                                    ctypes.POINTER(c_int), _dp, c_int]
     lib.orc_metrics.argtypes = [_dp, _dp, c_size, c_double, _i64p, _i64p, _dp]
     lib.orc_metrics.restype = None
     _lib = lib
@@ -246,7 +246,8 @@ def band_threshold(f, q):
     return out.value
 
 
-def solve_until(f, lam, theta, tau, delta, max_iters, tol, check_every=1, u0=None, p0=None):
+def solve_until(f, lam, theta, tau, delta, max_iters, tol, check_every=1, u0=None, p0=None,
+                inner=1):
     """Solve with the stopping rule of Sec. 4 evaluated every `check_every`
     iterations.  Returns (u, v, p, iterations run, measured values), p as
     [2][H][W]."""
@@ -266,7 +267,7 @@ def solve_until(f, lam, theta, tau, delta, max_iters, tol, check_every=1, u0=Non
                                float(delta), int(max_iters), float(tol), int(check_every),
                                _ptr(u0c, _dp), _ptr(p0x, _dp), _ptr(p0y, _dp),
                                _ptr(u, _dp), _ptr(v, _dp), _ptr(px, _dp), _ptr(py, _dp),
-                               ctypes.byref(done), _ptr(diffs, _dp)), "solve_until")
+                               ctypes.byref(done), _ptr(diffs, _dp), int(inner)), "solve_until")
     n_checks = done.value // check_every
     return u, v, np.stack([px, py]), done.value, diffs[:n_checks]
 

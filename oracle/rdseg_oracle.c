@@ -612,16 +612,17 @@ int orc_band_threshold(const float* f, int H, int W, double q, double* qhat)
 /* multiple of check_every; the solve stops at the first such l that meets   */
 /* it, or after max_iters.  diffs (nullable) receives the measured value at  */
 /* each evaluated l, in order; *iters_done the number of iterations run.     */
+/* Each iteration takes `inner` dual steps, as in orc_solve.                 */
 /* ------------------------------------------------------------------------ */
 int orc_solve_until(const float* f, int H, int W, double lambda, double theta, double tau,
                     double delta, int max_iters, double tol, int check_every,
                     const double* u0, const double* p0x, const double* p0y,
                     double* u, double* v, double* px, double* py,
-                    int* iters_done, double* diffs)
+                    int* iters_done, double* diffs, int inner)
 {
     if (!f || !u || !v || !px || !py || !iters_done || H < 1 || W < 1 || max_iters < 0 ||
-        check_every < 1 || !(theta > 0) || !(tau > 0) || !(lambda >= 0) || isnan(delta) ||
-        isnan(tol))
+        check_every < 1 || inner < 1 || !(theta > 0) || !(tau > 0) || !(lambda >= 0) ||
+        isnan(delta) || isnan(tol))
         return ORC_ERR_ARG;
     orc_ctx c;
     if (ctx_init(&c, f, H, W, delta)) return ORC_ERR_MEM;
@@ -634,7 +635,7 @@ int orc_solve_until(const float* f, int H, int W, double lambda, double theta, d
     for (int l = 1; l <= max_iters; ++l) {
         memcpy(uprev, u, N * sizeof(double));
         memcpy(vprev, v, N * sizeof(double));
-        dual_step(&c, theta, tau, v, px, py);
+        for (int j = 0; j < inner; ++j) dual_step(&c, theta, tau, v, px, py);
         uv_step(&c, lambda, theta, px, py, u, v);
         done = l;
         if (l % check_every == 0) {

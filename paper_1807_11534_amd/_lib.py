@@ -30,7 +30,7 @@ class Params(ctypes.Structure):
                 ("tau", ctypes.c_double), ("delta", ctypes.c_double),
                 ("iters", ctypes.c_int32), ("iters_per_launch", ctypes.c_int32),
                 ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
-                ("ckpt_every", ctypes.c_int32)]
+                ("ckpt_every", ctypes.c_int32), ("inner", ctypes.c_int32)]
 
 
 class Fit(ctypes.Structure):

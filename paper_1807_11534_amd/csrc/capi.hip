@@ -269,6 +269,7 @@ struct SolvePlanArgs {
     float* tape;            // single image only
     const int64_t* npix;    // for timing
     hipStream_t st;
+    int inner = 1;                           // dual steps per outer iteration
     const struct StopSpec* stop = nullptr;   // convergence-driven solve (single image)
     int launches = 0;                        // out: number of launches enqueued
     int launches_per_check = 0;              // out (with stop)
@@ -348,7 +349,7 @@ struct Poller {
 // buffer 0 (the caller's v, p) and u is written by the last launch.
 rdseg_status enqueue_iterations(SolvePlanArgs& a) {
     if (a.iters <= 0) return RDSEG_OK;
-    const int IT = config_at(a.ci).it;
+    const int IT = std::max(1, config_at(a.ci).it / a.inner);   // outer iterations per launch
     const bool stop = a.stop != nullptr;
     const int ce = stop ? a.stop->check_every
                         : ((a.tape && a.ckpt_every > 0) ? a.ckpt_every : a.iters);
@@ -427,7 +428,7 @@ rdseg_status enqueue_iterations(SolvePlanArgs& a) {
         }
         int rc = launch_iterate(a.ci, a.d0, a.descs, a.descs != nullptr, a.queue, a.n_queue,
                                 a.max_items, in_buf, nits[j], stop || j == L - 1, a.theta,
-                                a.inv_theta, a.tau, a.st, stop ? &sl : nullptr);
+                                a.inv_theta, a.tau, a.st, stop ? &sl : nullptr, a.inner);
         if (rc) return RDSEG_ERR_HIP;
         bool stop_now = false;
         if (poller && sl.diff_slot) {
@@ -455,6 +456,26 @@ rdseg_status enqueue_iterations(SolvePlanArgs& a) {
         if (stop_now) break;   // later launches would only skip; finalize reads the slots
     }
     return RDSEG_OK;
+}
+
+constexpr int kMaxInner = 16;   // deepest compiled halo
+
+// The configuration with the tile of `ci` (or the nearest larger one) whose
+// halo holds at least `inner` dual steps.
+int deeper_cfg(int ci, int inner) {
+    const TileCfg c = config_at(ci);
+    int best = -1;
+    for (int k = 0; k < config_count(); ++k) {
+        const TileCfg e = config_at(k);
+        if (e.it < inner) continue;
+        const bool same = e.bx == c.bx && e.by == c.by;
+        if (best < 0) { best = k; continue; }
+        const TileCfg b = config_at(best);
+        const bool best_same = b.bx == c.bx && b.by == c.by;
+        if (same && !best_same) best = k;
+        else if (same == best_same && e.it < b.it) best = k;
+    }
+    return best;
 }
 
 // Choose the tile configuration for a single-image solve.
@@ -498,6 +519,11 @@ rdseg_status solve_impl(const float* f, rdseg_shape s, const rdseg_params* prm, 
     if (prm->iters < 0) return fail(RDSEG_ERR_ARG, "iters must be >= 0");
     if (prm->ckpt_every < 0) return fail(RDSEG_ERR_ARG, "ckpt_every must be >= 0");
     if (prm->ckpt_every > 0 && !tape) return fail(RDSEG_ERR_TAPE, "ckpt_every > 0 needs a tape");
+    if (prm->inner < 0 || prm->inner > kMaxInner)
+        return fail(RDSEG_ERR_ARG, "inner must lie in [0, 16]");
+    const int inner = prm->inner > 1 ? prm->inner : 1;
+    if (inner > 1 && prm->ckpt_every > 0)
+        return fail(RDSEG_ERR_ARG, "checkpoints (for the adjoint) need inner = 1");
     const size_t plane_b = (size_t)s.H * s.ld * sizeof(float);
     if (ranges_overlap(u, plane_b, f, plane_b) || ranges_overlap(v, plane_b, f, plane_b) ||
         ranges_overlap(p, 2 * plane_b, f, plane_b) || ranges_overlap(u, plane_b, v, plane_b) ||
@@ -515,6 +541,8 @@ rdseg_status solve_impl(const float* f, rdseg_shape s, const rdseg_params* prm, 
         r = choose_cfg(*prm, s, nullptr, st, &ci);   // validates before any launch
         if (r) return r;
     }
+    if (ci >= 0 && config_at(ci).it < inner)
+        return fail(RDSEG_ERR_ARG, "iters_per_launch (dual steps per launch) must be >= inner");
     SolveWs w = carve_solve(ws, s);
     Geo g = geo_of(s);
 
@@ -525,6 +553,7 @@ rdseg_status solve_impl(const float* f, rdseg_shape s, const rdseg_params* prm, 
     if (ci < 0) {
         r = choose_cfg(*prm, s, w.npix, st, &ci);
         if (r) return r;
+        if (config_at(ci).it < inner) ci = deeper_cfg(ci, inner);
     }
     TileCfg cfg = config_at(ci);
     d = make_desc(f, s, prm->lambda, prm->theta, prm->delta, u, v, p, w.c, w.st, u0, p0, cfg.bx, cfg.by);
@@ -545,7 +574,7 @@ rdseg_status solve_impl(const float* f, rdseg_shape s, const rdseg_params* prm, 
         return RDSEG_ERR_HIP;
     if (use_closed &&
         launch_closed(&d, nullptr, false, w.cqueue, w.totals + 2, g.nt, prm->iters,
-                      (float)prm->theta, (float)(1.0 / prm->theta), (float)prm->tau, st))
+                      (float)prm->theta, (float)(1.0 / prm->theta), (float)prm->tau, st, inner))
         return RDSEG_ERR_HIP;
     SolvePlanArgs a;
     a.d0 = &d;
@@ -563,6 +592,7 @@ rdseg_status solve_impl(const float* f, rdseg_shape s, const rdseg_params* prm, 
     a.npix = w.npix;
     a.st = st;
     a.stop = stop;
+    a.inner = inner;
     r = enqueue_iterations(a);
     if (r || !stop) return r;
     return hip_status(launch_stop_finalize(d, stop->slots, stop->n_checks, stop->tol,
@@ -1046,6 +1076,7 @@ rdseg_status rdseg_backward(const float* f, rdseg_shape s, const rdseg_params* p
         return fail(RDSEG_ERR_ARG, "f, grad_u, grad_f and grad_lambda must be non-NULL");
     if (!tape || prm->ckpt_every <= 0)
         return fail(RDSEG_ERR_TAPE, "backward needs the tape of a solve with ckpt_every > 0");
+    if (prm->inner > 1) return fail(RDSEG_ERR_ARG, "the adjoint is available for inner = 1 only");
     if (fit && !fit->z) return fail(RDSEG_ERR_ARG, "fit->z must be non-NULL");
     const size_t pb = (size_t)s.H * s.ld * sizeof(float);
     if (ranges_overlap(grad_f, pb, f, pb) || ranges_overlap(grad_f, pb, grad_u, pb) ||
@@ -1198,7 +1229,9 @@ rdseg_status rdseg_autotune(const float* f, rdseg_shape s, const rdseg_params* p
         return fail(RDSEG_ERR_HIP, "hipEventCreate failed");
     int best = -1;
     float best_ms = 0.0f;
+    const int inner = prm->inner > 1 ? prm->inner : 1;
     for (int ci = 0; ci < config_count(); ++ci) {
+        if (config_at(ci).it < inner) continue;
         // warm-up, then timed
         rdseg_status r = solve_impl(f, s, &q, nullptr, nullptr, u, v, p, nullptr, ws, ws_bytes, st, ci);
         if (r) { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); return r; }

@@ -82,7 +82,7 @@ __device__ __forceinline__ void run_iterations(float* __restrict__ sPX, float* _
                                                const uint32_t* fl, const int* gi,
                                                float* __restrict__ U, int nit, int write_u,
                                                float theta, float inv_theta, float tau, float* ru,
-                                               bool check, uint32_t& dmax) {
+                                               bool check, uint32_t& dmax, int inner) {
     constexpr int RX = BX + 2 * IT + 1;
     constexpr int RY = BY + 2 * IT + 1;
     constexpr int RC = RX * RY;
@@ -102,7 +102,11 @@ __device__ __forceinline__ void run_iterations(float* __restrict__ sPX, float* _
         }
     }
     __syncthreads();
-    for (int it = 0; it < nit; ++it) {
+    // nit outer iterations of `inner` dual steps each; between the dual steps
+    // of one outer iteration phase A only refreshes w = div p - v/theta
+    const int steps = nit * inner;
+    int left = inner;   // dual steps left in the current outer iteration
+    for (int it = 0; it < steps; ++it) {
         // phase B: dual step
         {
 #pragma unroll
@@ -132,9 +136,20 @@ __device__ __forceinline__ void run_iterations(float* __restrict__ sPX, float* _
             }
         }
         __syncthreads();
-        // phase A: u-step, v-step, next w
-        const bool last = (it == nit - 1);
-        {
+        // phase A: u-step, v-step, next w (w alone inside an outer iteration)
+        const bool last = (it == steps - 1);
+        if (--left > 0) {
+#pragma unroll
+            for (int j = 0; j < CPT; ++j) {
+                const int i = MODE == MODE_COMPACT ? idx[j] : t + j * NT;
+                if (MODE == MODE_COMPACT ? (i >= 0) : (i < RC)) {
+                    float dd = div_p(rpx[j], sPX[PAD + i - 1], rpy[j], sPY[PAD + i - RX]);
+                    sW[PAD + i] = w_of(dd, rv[j], inv_theta,
+                                       MODE == MODE_DENSE ? (fl[j] & CF_ACT) != 0 : true);
+                }
+            }
+        } else {
+            left = inner;
 #pragma unroll
             for (int j = 0; j < CPT; ++j) {
                 const int i = MODE == MODE_COMPACT ? idx[j] : t + j * NT;
@@ -205,7 +220,8 @@ __global__ __launch_bounds__(NT) void k_iterate(ImgDesc d0, const ImgDesc* __res
                                                 int nit, int write_u, float theta,
                                                 float inv_theta, float tau,
                                                 const uint32_t* __restrict__ skip_slot,
-                                                uint32_t* __restrict__ diff_slot, double tol) {
+                                                uint32_t* __restrict__ diff_slot, double tol,
+                                                int inner) {
     if (STOP && skip_slot && (double)__uint_as_float(*skip_slot) <= tol) return;
     constexpr int RX = BX + 2 * IT + 1;
     constexpr int RY = BY + 2 * IT + 1;
@@ -318,11 +334,11 @@ __global__ __launch_bounds__(NT) void k_iterate(ImgDesc d0, const ImgDesc* __res
         if (fast) {
             run_iterations<BX, BY, IT, NT, MODE_FAST, STOP>(sPX, sPY, sW, idx, rv, rpx, rpy, rc,
                                                             fl, gi, d.u, nit, write_u, theta,
-                                                            inv_theta, tau, ru, check, dmax);
+                                                            inv_theta, tau, ru, check, dmax, inner);
         } else if (!COMPACT_OK) {
             run_iterations<BX, BY, IT, NT, MODE_DENSE, STOP>(sPX, sPY, sW, idx, rv, rpx, rpy, rc,
                                                              fl, gi, d.u, nit, write_u, theta,
-                                                             inv_theta, tau, ru, check, dmax);
+                                                             inv_theta, tau, ru, check, dmax, inner);
         } else {
             // count the RD cells of the region (ascending list offsets)
             if (lane == 0) {
@@ -350,7 +366,7 @@ __global__ __launch_bounds__(NT) void k_iterate(ImgDesc d0, const ImgDesc* __res
                 run_iterations<BX, BY, IT, NT, MODE_DENSE, STOP>(sPX, sPY, sW, idx, rv, rpx, rpy,
                                                                  rc, fl, gi, d.u, nit, write_u,
                                                                  theta, inv_theta, tau, ru,
-                                                                 check, dmax);
+                                                                 check, dmax, inner);
             } else {
                 const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
@@ -386,7 +402,7 @@ __global__ __launch_bounds__(NT) void k_iterate(ImgDesc d0, const ImgDesc* __res
                 run_iterations<BX, BY, IT, NT, MODE_COMPACT, STOP>(sPX, sPY, sW, idx, rv, rpx, rpy,
                                                                    rc, fl, gi, d.u, nit, write_u,
                                                                    theta, inv_theta, tau, ru,
-                                                                   check, dmax);
+                                                                   check, dmax, inner);
             }
         }
         float* __restrict__ Vo = d.st[out_buf][0];
@@ -418,7 +434,8 @@ template <bool BATCHED>
 __global__ __launch_bounds__(64) void k_closed(ImgDesc d0, const ImgDesc* __restrict__ descs,
                                                const int2* __restrict__ cqueue,
                                                const int32_t* __restrict__ n_closed, int iters,
-                                               float theta, float inv_theta, float tau) {
+                                               int inner, float theta, float inv_theta,
+                                               float tau) {
     constexpr int RX = 10;
     constexpr int RC = RX * RX;
     constexpr int CPT = 2;
@@ -484,7 +501,9 @@ __global__ __launch_bounds__(64) void k_closed(ImgDesc d0, const ImgDesc* __rest
             }
         }
         __syncthreads();
-        for (int it = 0; it < iters; ++it) {
+        const int steps = iters * inner;
+        int left = inner;   // dual steps left in the current outer iteration
+        for (int it = 0; it < steps; ++it) {
 #pragma unroll
             for (int j = 0; j < CPT; ++j) {
                 const int i = t + j * 64;
@@ -498,19 +517,23 @@ __global__ __launch_bounds__(64) void k_closed(ImgDesc d0, const ImgDesc* __rest
                 }
             }
             __syncthreads();
-            const bool last = (it == iters - 1);
+            const bool last = (it == steps - 1);
+            const bool outer_end = --left == 0;
+            if (outer_end) left = inner;
 #pragma unroll
             for (int j = 0; j < CPT; ++j) {
                 const int i = t + j * 64;
                 if (i < RC) {
                     float dd = div_p(rpx[j], sPX[PAD + i - 1], rpy[j], sPY[PAD + i - RX]);
-                    float u = u_step(rv[j], dd, theta);
-                    rv[j] = v_step(u, rc[j]);
-                    if (last) {
-                        if (fl[j] & CF_OUT) d.u[gi[j]] = u;
-                    } else {
-                        sW[PAD + i] = w_of(dd, rv[j], inv_theta, (fl[j] & CF_ACT) != 0);
+                    if (outer_end) {
+                        float u = u_step(rv[j], dd, theta);
+                        rv[j] = v_step(u, rc[j]);
+                        if (last) {
+                            if (fl[j] & CF_OUT) d.u[gi[j]] = u;
+                            continue;
+                        }
                     }
+                    sW[PAD + i] = w_of(dd, rv[j], inv_theta, (fl[j] & CF_ACT) != 0);
                 }
             }
             __syncthreads();
@@ -544,7 +567,7 @@ __global__ __launch_bounds__(256) void k_state_copy(ImgDesc d, int buf, float* _
 
 // ---------------------------------------------------------------- config table
 using IterFn = void (*)(ImgDesc, const ImgDesc*, const int2*, const int32_t*, int, int, int,
-                        float, float, float, const uint32_t*, uint32_t*, double);
+                        float, float, float, const uint32_t*, uint32_t*, double, int);
 
 struct CfgEntry {
     TileCfg cfg;
@@ -635,7 +658,7 @@ int prepare_iterate(int ci, bool batched, bool stop) {
 int launch_iterate(int ci, const ImgDesc* d0, const ImgDesc* descs, bool batched,
                    const int2* queue, const int32_t* n_queue, int64_t max_items, int in_buf,
                    int nit, bool write_u, float theta, float inv_theta, float tau,
-                   hipStream_t st, const StopLaunch* stop) {
+                   hipStream_t st, const StopLaunch* stop, int inner) {
     const CfgEntry& e = kCfgs[ci];
     if (stop && batched) {
         set_error("the stopping rule is available for single-image solves only");
@@ -651,7 +674,7 @@ int launch_iterate(int ci, const ImgDesc* d0, const ImgDesc* descs, bool batched
     hipLaunchKernelGGL(fn, dim3((unsigned)g), dim3(e.cfg.nt), 0, st, *d0, descs, queue, n_queue,
                        in_buf, nit, write_u ? 1 : 0, theta, inv_theta, tau,
                        stop ? stop->skip_slot : nullptr, stop ? stop->diff_slot : nullptr,
-                       stop ? stop->tol : 0.0);
+                       stop ? stop->tol : 0.0, inner);
     RDSEG_HIP_CHECK(hipGetLastError());
     return 0;
 }
@@ -731,17 +754,17 @@ int prepare_closed(bool batched) {
 
 int launch_closed(const ImgDesc* d0, const ImgDesc* descs, bool batched, const int2* cqueue,
                   const int32_t* n_closed, int64_t max_items, int iters, float theta,
-                  float inv_theta, float tau, hipStream_t st) {
+                  float inv_theta, float tau, hipStream_t st, int inner) {
     if (prepare_closed(batched)) return 4;
     int64_t g = g_closed_grid[batched ? 1 : 0];
     if (max_items < g) g = max_items;
     if (g < 1) g = 1;
     if (batched)
         hipLaunchKernelGGL(k_closed<true>, dim3((unsigned)g), dim3(64), 0, st, *d0, descs, cqueue,
-                           n_closed, iters, theta, inv_theta, tau);
+                           n_closed, iters, inner, theta, inv_theta, tau);
     else
         hipLaunchKernelGGL(k_closed<false>, dim3((unsigned)g), dim3(64), 0, st, *d0, descs, cqueue,
-                           n_closed, iters, theta, inv_theta, tau);
+                           n_closed, iters, inner, theta, inv_theta, tau);
     RDSEG_HIP_CHECK(hipGetLastError());
     return 0;
 }

@@ -83,7 +83,7 @@ int launch_macro_queue(const ImgDesc* d0, const ImgDesc* descs, OffTables off, i
 int prepare_closed(bool batched);
 int launch_closed(const ImgDesc* d0, const ImgDesc* descs, bool batched, const int2* cqueue,
                   const int32_t* n_closed, int64_t max_items, int iters, float theta,
-                  float inv_theta, float tau, hipStream_t st);
+                  float inv_theta, float tau, hipStream_t st, int inner = 1);
 
 // ---------------------------------------------------------------- band threshold
 // Radix-select state: digits of the k-th smallest |f| chosen so far and the
@@ -131,13 +131,14 @@ struct StopLaunch {
     double tol;
 };
 
-// One launch of the temporally blocked iteration kernel: `nit` (<= cfg.it)
-// iterations over the queued macro tiles, reading state buffer `in_buf` and
+// One launch of the temporally blocked iteration kernel: `nit` outer
+// iterations of `inner` dual steps each (nit * inner <= cfg.it, the halo
+// depth) over the queued macro tiles, reading state buffer `in_buf` and
 // writing 1 - in_buf; writes u on RD when write_u.  grid = persistent size.
 int launch_iterate(int cfg_index, const ImgDesc* d0, const ImgDesc* descs, bool batched,
                    const int2* queue, const int32_t* n_queue, int64_t max_items, int in_buf,
                    int nit, bool write_u, float theta, float inv_theta, float tau,
-                   hipStream_t st, const StopLaunch* stop = nullptr);
+                   hipStream_t st, const StopLaunch* stop = nullptr, int inner = 1);
 
 // After a convergence-driven solve: *iters_done = (c + 1) * check_every for
 // the first check c with slots[c] <= tol (else iters), then the state of

@@ -40,9 +40,9 @@ def shape_of(f):
 
 
 def params(lam, theta=THETA, tau=TAU, delta=math.inf, iters=0, iters_per_launch=0, tile_w=0,
-           tile_h=0, ckpt_every=0):
+           tile_h=0, ckpt_every=0, inner=1):
     return Params(float(lam), float(theta), float(tau), float(delta), int(iters),
-                  int(iters_per_launch), int(tile_w), int(tile_h), int(ckpt_every))
+                  int(iters_per_launch), int(tile_w), int(tile_h), int(ckpt_every), int(inner))
 
 
 def workspace(s, prm=None):
@@ -104,15 +104,16 @@ def delta_for_fraction(f, q):
 
 
 def solve(f, lam, theta=THETA, tau=TAU, delta=math.inf, iters=100, u0=None, p0=None,
-          tile=None, iters_per_launch=0, ckpt_every=0, out=None, ws=None):
+          tile=None, iters_per_launch=0, ckpt_every=0, out=None, ws=None, inner=1):
     """Restricted-domain dual iteration (Sec. 2.1 restricted as in Sec. 3).
 
-    tile: (tile_w, tile_h) or None (autotuned).  Returns (u, v, p) with p of
-    shape [2][H][W]; with ckpt_every > 0 returns (u, v, p, tape)."""
+    tile: (tile_w, tile_h) or None (autotuned); inner: dual steps per outer
+    iteration.  Returns (u, v, p) with p of shape [2][H][W]; with
+    ckpt_every > 0 returns (u, v, p, tape)."""
     lib = _lib.load()
     s = shape_of(f)
     tw, th = (0, 0) if tile is None else tile
-    prm = params(lam, theta, tau, delta, iters, iters_per_launch, tw, th, ckpt_every)
+    prm = params(lam, theta, tau, delta, iters, iters_per_launch, tw, th, ckpt_every, inner)
     if out is None:
         u, v, p = _empty_like_grid(f), _empty_like_grid(f), _empty_like_grid(f, 2)
     else:
@@ -134,7 +135,7 @@ def solve(f, lam, theta=THETA, tau=TAU, delta=math.inf, iters=100, u0=None, p0=N
 
 def solve_until(f, lam, theta=THETA, tau=TAU, delta=math.inf, max_iters=1000, tol=1e-2,
                 check_every=1, u0=None, p0=None, tile=None, iters_per_launch=0, out=None,
-                ws=None, poll=True):
+                ws=None, poll=True, inner=1):
     """Solve with the stopping rule of Sec. 4 (maximum-norm change of u and v
     at most tol, checked every `check_every` iterations, decided on the device).
     poll: read the checks back in growing chunks and stop enqueuing soon after
@@ -145,7 +146,7 @@ def solve_until(f, lam, theta=THETA, tau=TAU, delta=math.inf, max_iters=1000, to
     lib = _lib.load()
     s = shape_of(f)
     tw, th = (0, 0) if tile is None else tile
-    prm = params(lam, theta, tau, delta, max_iters, iters_per_launch, tw, th, 0)
+    prm = params(lam, theta, tau, delta, max_iters, iters_per_launch, tw, th, 0, inner)
     if out is None:
         u, v, p = _empty_like_grid(f), _empty_like_grid(f), _empty_like_grid(f, 2)
     else:

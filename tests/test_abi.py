@@ -140,3 +140,12 @@ def test_metrics_validation(lib):
     assert lib.rdseg_metrics(P(1), P(2), sh, math.nan, P(3), P(4), n, None) == 1
     assert lib.rdseg_metrics(P(1), P(2), sh, 0.5, P(3), P(4), n - 1, None) == 3
     assert lib.rdseg_metrics(P(1), P(2), Shape(0, 16, 16), 0.5, P(3), P(4), n, None) == 2
+
+
+def test_inner_steps_validation(lib):
+    assert _solve(lib, (16, 16, 16), _prm(inner=-1)) == 1
+    assert _solve(lib, (16, 16, 16), _prm(inner=17)) == 1
+    tape = ctypes.c_void_p(7 << 32)
+    assert _solve(lib, (16, 16, 16), _prm(inner=2, ckpt_every=5), tape=tape) == 1
+    # an explicit configuration whose halo holds fewer dual steps than inner
+    assert _solve(lib, (16, 16, 16), _prm(inner=4, tile_w=16, tile_h=16, iters_per_launch=2)) == 1

@@ -184,3 +184,18 @@ def test_metrics_properties():
     ones, zeros = np.ones((4, 4)), np.zeros((4, 4))
     assert oracle.metrics(ones, zeros)[:2] == (0.0, 16.0)
     assert oracle.metrics(zeros, zeros)[0] == 1.0        # empty union read as agreement
+
+
+def test_stopping_rule_with_inner_steps():
+    """With several dual steps per iteration the stopped state is the
+    fixed-count solve of the same inner count."""
+    f, lam, delta = stop_problem()
+    _, _, _, _, d = oracle.solve_until(f, lam, TH, TAU, delta, 40, -1.0, 4, inner=3)
+    tol = float(np.median(d))
+    u, v, p, done, _ = oracle.solve_until(f, lam, TH, TAU, delta, 40, tol, 4, inner=3)
+    ur, vr, pr = oracle.solve(f, lam, TH, TAU, delta, done, inner=3)
+    np.testing.assert_array_equal(u, ur)
+    np.testing.assert_array_equal(p, pr)
+    u1, v1, _ = oracle.solve(f, lam, TH, TAU, delta, done - 1, inner=3)
+    j = done // 4 - 1
+    assert d[j] == max(np.abs(ur - u1).max(), np.abs(vr - v1).max())
