@@ -20,6 +20,9 @@ Parity status of each function (pins live in ``tests/test_oracle_*.py``):
 * ``solve_until`` -- pinned (diffs re-measured from two fixed-count solves; stop
   index; tolerance 0 / inf; empty domain stops at the first check).
 * ``metrics``     -- pinned (hand-worked 2x3 case, identity, disjoint labels, symmetry).
+* ``grad3``/``div3`` -- pinned (adjointness, hand-worked 2x2x2 case).
+* ``solve3``      -- pinned (a volume of identical slices equals the pinned 2-D solve on
+  each slice bit for bit; axis permutations; D = 1).
 """
 import ctypes
 import os
@@ -72,6 +75,12 @@ def _load():
                                     ctypes.POINTER(c_int), _dp, c_int]
     lib.orc_metrics.argtypes = [_dp, _dp, c_size, c_double, _i64p, _i64p, _dp]
     lib.orc_metrics.restype = None
+    lib.orc_grad3.argtypes = [_dp, c_int, c_int, c_int, _dp, _dp, _dp]
+    lib.orc_grad3.restype = None
+    lib.orc_div3.argtypes = [_dp, _dp, _dp, c_int, c_int, c_int, _dp]
+    lib.orc_div3.restype = None
+    lib.orc_solve3.argtypes = [_fp, c_int, c_int, c_int, c_double, c_double, c_double, c_double,
+                               c_int, c_int, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
     _lib = lib
     return lib
 
@@ -283,3 +292,41 @@ def metrics(u, u_gt, eps=0.5):
                     ctypes.byref(nu), ctypes.byref(e2))
     e1 = 1.0 if nu.value == 0 else ni.value / nu.value
     return e1, e2.value, ni.value, nu.value
+
+
+def grad3(u):
+    """Forward-difference gradient of a volume [D][H][W]."""
+    lib = _load()
+    u = _f64(u)
+    D, H, W = u.shape
+    g = [np.empty_like(u) for _ in range(3)]
+    lib.orc_grad3(_ptr(u, _dp), D, H, W, *[_ptr(a, _dp) for a in g])
+    return tuple(g)
+
+
+def div3(px, py, pz):
+    """Divergence of a volume field, div = -grad^T."""
+    lib = _load()
+    px, py, pz = _f64(px), _f64(py), _f64(pz)
+    D, H, W = px.shape
+    d = np.empty_like(px)
+    lib.orc_div3(_ptr(px, _dp), _ptr(py, _dp), _ptr(pz, _dp), D, H, W, _ptr(d, _dp))
+    return d
+
+
+def solve3(f, lam, theta, tau, delta, iters, inner=1, u0=None, p0=None):
+    """Restricted iteration on a volume f [D][H][W]; returns (u, v, p) with p
+    as [3][D][H][W]."""
+    lib = _load()
+    f = _f32(f)
+    D, H, W = f.shape
+    u, v = np.empty((D, H, W)), np.empty((D, H, W))
+    p = np.empty((3, D, H, W))
+    u0c = None if u0 is None else _f64(u0)
+    p0c = None if p0 is None else [_f64(a) for a in p0]
+    _check(lib.orc_solve3(_ptr(f, _fp), D, H, W, float(lam), float(theta), float(tau),
+                          float(delta), int(iters), int(inner), _ptr(u0c, _dp),
+                          *(([None] * 3) if p0c is None else [_ptr(a, _dp) for a in p0c]),
+                          _ptr(u, _dp), _ptr(v, _dp), _ptr(p[0], _dp), _ptr(p[1], _dp),
+                          _ptr(p[2], _dp)), "solve3")
+    return u, v, p

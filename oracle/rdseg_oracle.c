@@ -678,3 +678,106 @@ void orc_metrics(const double* u, const double* ugt, size_t n, double eps,
     *n_union = b;
     *e2 = s;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Volumes (the conclusion, Sec. 5, names 3-D problems as an extension of    */
+/* interest; the method carries over with a third axis).  Layout             */
+/* [D][H][W], index (z*H + y)*W + x.  Gradient: forward differences along    */
+/* x, y and z with a zero component on the last plane of each axis;          */
+/* divergence: its negative adjoint.  The restricted iteration is the one of */
+/* orc_solve with the 3-vector p and |g| the Euclidean norm of the 3-vector. */
+/* ------------------------------------------------------------------------ */
+void orc_grad3(const double* u, int D, int H, int W, double* gx, double* gy, double* gz)
+{
+    for (int z = 0; z < D; ++z)
+        for (int y = 0; y < H; ++y)
+            for (int x = 0; x < W; ++x) {
+                size_t i = ((size_t)z * H + y) * W + x;
+                gx[i] = x < W - 1 ? u[i + 1] - u[i] : 0.0;
+                gy[i] = y < H - 1 ? u[i + W] - u[i] : 0.0;
+                gz[i] = z < D - 1 ? u[i + (size_t)H * W] - u[i] : 0.0;
+            }
+}
+
+void orc_div3(const double* px, const double* py, const double* pz, int D, int H, int W,
+              double* d)
+{
+    size_t S = (size_t)H * W;
+    for (int z = 0; z < D; ++z)
+        for (int y = 0; y < H; ++y)
+            for (int x = 0; x < W; ++x) {
+                size_t i = ((size_t)z * H + y) * W + x;
+                double a = (x < W - 1 ? px[i] : 0.0) - (x > 0 ? px[i - 1] : 0.0);
+                double b = (y < H - 1 ? py[i] : 0.0) - (y > 0 ? py[i - W] : 0.0);
+                double c = (z < D - 1 ? pz[i] : 0.0) - (z > 0 ? pz[i - S] : 0.0);
+                d[i] = a + b + c;
+            }
+}
+
+/* Restricted solve on a volume: init as orc_solve (u0 = H(-f) or the        */
+/* caller's, v0 = clamp(u0 - theta lambda f), p0 = 0 or the caller's with the */
+/* last-plane components zero), then iters x (inner dual steps, u-step,      */
+/* v-step) on RD = {|f| < delta}; frozen voxels hold u = v = H(-f), p = 0.    */
+int orc_solve3(const float* f, int D, int H, int W, double lambda, double theta, double tau,
+               double delta, int iters, int inner, const double* u0, const double* p0x,
+               const double* p0y, const double* p0z, double* u, double* v, double* px,
+               double* py, double* pz)
+{
+    if (!f || !u || !v || !px || !py || !pz || D < 1 || H < 1 || W < 1 || iters < 0 ||
+        inner < 1 || !(theta > 0) || !(tau > 0) || !(lambda >= 0) || isnan(delta))
+        return ORC_ERR_ARG;
+    size_t N = (size_t)D * H * W;
+    unsigned char* A = (unsigned char*)malloc(N);
+    double* h = (double*)malloc(N * sizeof(double));
+    double* d = (double*)malloc(N * sizeof(double));
+    double* w = (double*)malloc(N * sizeof(double));
+    double* gx = (double*)malloc(N * sizeof(double));
+    double* gy = (double*)malloc(N * sizeof(double));
+    double* gz = (double*)malloc(N * sizeof(double));
+    if (!A || !h || !d || !w || !gx || !gy || !gz) {
+        free(A); free(h); free(d); free(w); free(gx); free(gy); free(gz);
+        return ORC_ERR_MEM;
+    }
+    for (size_t i = 0; i < N; ++i) {
+        A[i] = (unsigned char)in_rd(f[i], delta);
+        h[i] = heav_neg(f[i]);
+    }
+    for (int z = 0; z < D; ++z)
+        for (int y = 0; y < H; ++y)
+            for (int x = 0; x < W; ++x) {
+                size_t i = ((size_t)z * H + y) * W + x;
+                if (A[i]) {
+                    u[i] = u0 ? u0[i] : h[i];
+                    v[i] = clamp01(u[i] - theta * lambda * (double)f[i]);
+                    px[i] = (p0x && x < W - 1) ? p0x[i] : 0.0;
+                    py[i] = (p0y && y < H - 1) ? p0y[i] : 0.0;
+                    pz[i] = (p0z && z < D - 1) ? p0z[i] : 0.0;
+                } else {
+                    u[i] = v[i] = h[i];
+                    px[i] = py[i] = pz[i] = 0.0;
+                }
+            }
+    for (int k = 0; k < iters; ++k) {
+        for (int j = 0; j < inner; ++j) {
+            /* dual step with v held: w = div p - v/theta on RD, -h/theta off RD */
+            orc_div3(px, py, pz, D, H, W, d);
+            for (size_t i = 0; i < N; ++i) w[i] = A[i] ? d[i] - v[i] / theta : -h[i] / theta;
+            orc_grad3(w, D, H, W, gx, gy, gz);
+            for (size_t i = 0; i < N; ++i) {
+                if (!A[i]) continue;
+                double n = sqrt(gx[i] * gx[i] + gy[i] * gy[i] + gz[i] * gz[i]);
+                px[i] = (px[i] + tau * gx[i]) / (1.0 + tau * n);
+                py[i] = (py[i] + tau * gy[i]) / (1.0 + tau * n);
+                pz[i] = (pz[i] + tau * gz[i]) / (1.0 + tau * n);
+            }
+        }
+        /* u-step, then v-step, on RD */
+        orc_div3(px, py, pz, D, H, W, d);
+        for (size_t i = 0; i < N; ++i)
+            if (A[i]) u[i] = v[i] - theta * d[i];
+        for (size_t i = 0; i < N; ++i)
+            if (A[i]) v[i] = clamp01(u[i] - theta * lambda * (double)f[i]);
+    }
+    free(A); free(h); free(d); free(w); free(gx); free(gy); free(gz);
+    return ORC_OK;
+}
