@@ -205,6 +205,34 @@ rdseg_status rdseg_solve_until(const float* f, rdseg_shape s, const rdseg_params
                                void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------- */
+/* Volumes (Sec. 5 names 3-D problems as the extension of interest)        */
+/* ---------------------------------------------------------------------- */
+
+/* A volume [D][H][W]: voxel (z, y, x) at z * lds + y * ld + x (elements);
+ * ld >= W, lds >= H * ld, D * lds < 2^31. */
+typedef struct {
+    int32_t D, H, W;
+    int64_t ld, lds;
+} rdseg_shape3;
+
+/* Workspace bytes for rdseg_solve3d (0 if the shape is invalid). */
+size_t rdseg_workspace_size3(const rdseg_shape3* s);
+
+/* The restricted iteration of rdseg_solve on a volume: forward-difference
+ * gradient along x, y and z (zero component on the last plane of each axis),
+ * divergence its negative adjoint, p a 3-vector with |g| its Euclidean norm;
+ * RD = {|f| < delta}, frozen voxels u = v = H(-f), p = 0.  prm as for
+ * rdseg_solve except that tile_w, tile_h, iters_per_launch and ckpt_every must
+ * be 0 (one dual step per launch on 32 x 8 x 8 blocks; no tape).  Note that
+ * Chambolle's step bound is tau <= 1/12 in three dimensions.
+ * u0 (nullable), u, v: [D][lds] planes; p0 (nullable), p: [3][D][lds] (x, y, z
+ * components).  u, v, p must not overlap f or each other.  A volume of
+ * identical slices returns, slice by slice, the bits of rdseg_solve. */
+rdseg_status rdseg_solve3d(const float* f, rdseg_shape3 s, const rdseg_params* prm,
+                           const float* u0, const float* p0, float* u, float* v, float* p,
+                           void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------- */
 /* Evaluation measures (Sec. 4)                                             */
 /* ---------------------------------------------------------------------- */
 

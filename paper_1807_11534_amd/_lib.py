@@ -33,6 +33,11 @@ class Params(ctypes.Structure):
                 ("ckpt_every", ctypes.c_int32), ("inner", ctypes.c_int32)]
 
 
+class Shape3(ctypes.Structure):
+    _fields_ = [("D", ctypes.c_int32), ("H", ctypes.c_int32), ("W", ctypes.c_int32),
+                ("ld", ctypes.c_int64), ("lds", ctypes.c_int64)]
+
+
 class Fit(ctypes.Structure):
     _fields_ = [("z", ctypes.c_void_p), ("P", ctypes.c_void_p), ("c1", ctypes.c_double),
                 ("c2", ctypes.c_double), ("gamma", ctypes.c_double)]
@@ -59,6 +64,9 @@ SIGNATURES = {
     "rdseg_band_threshold": (ctypes.c_int, [_vp, Shape, _d, _vp, _vp, _sz, _vp]),
     "rdseg_solve": (ctypes.c_int, [_vp, Shape, ctypes.POINTER(Params), _vp, _vp, _vp, _vp, _vp,
                                    _vp, _vp, _sz, _vp]),
+    "rdseg_workspace_size3": (_sz, [ctypes.POINTER(Shape3)]),
+    "rdseg_solve3d": (ctypes.c_int, [_vp, Shape3, ctypes.POINTER(Params), _vp, _vp, _vp, _vp, _vp,
+                                     _vp, _sz, _vp]),
     "rdseg_metrics_workspace_size": (_sz, []),
     "rdseg_metrics": (ctypes.c_int, [_vp, _vp, Shape, _d, _vp, _vp, _sz, _vp]),
     "rdseg_solve_until": (ctypes.c_int, [_vp, Shape, ctypes.POINTER(Params), _d, ctypes.c_int32,

@@ -827,6 +827,35 @@ void plan_free(BatchPlan* P) {
     delete P;
 }
 
+// ------------------------------------------------------------------ volumes
+bool shape3_ok(const rdseg_shape3& s) {
+    if (s.D < 1 || s.H < 1 || s.W < 1 || s.ld < s.W || s.lds < (int64_t)s.H * s.ld) return false;
+    if ((int64_t)s.D * s.lds >= (int64_t)1 << 31) return false;
+    return true;
+}
+
+struct VolWs {
+    float* c;
+    float* st[4];
+    int32_t* flags;
+    int64_t n_tiles;
+    size_t bytes;
+};
+
+VolWs carve_vol(void* base, const rdseg_shape3& s) {
+    int bx, by, bz;
+    volume_tile(&bx, &by, &bz);
+    const int64_t vol = (int64_t)s.D * s.lds;
+    Carver cv(base);
+    VolWs w;
+    w.c = cv.take<float>(vol);
+    for (int k = 0; k < 4; ++k) w.st[k] = cv.take<float>(vol);
+    w.n_tiles = (int64_t)((s.W + bx - 1) / bx) * ((s.H + by - 1) / by) * ((s.D + bz - 1) / bz);
+    w.flags = cv.take<int32_t>(w.n_tiles);
+    w.bytes = cv.off;
+    return w;
+}
+
 }  // namespace
 
 // ====================================================================== C ABI
@@ -940,6 +969,69 @@ rdseg_status rdseg_solve_until(const float* f, rdseg_shape s, const rdseg_params
                 poll != 0};
     return solve_impl(f, s, prm, u0, p0, u, v, p, nullptr, ws, ws_bytes,
                       static_cast<hipStream_t>(stream), -1, &sp);
+}
+
+size_t rdseg_workspace_size3(const rdseg_shape3* s) {
+    if (!s || !shape3_ok(*s)) return 0;
+    return carve_vol(nullptr, *s).bytes;
+}
+
+rdseg_status rdseg_solve3d(const float* f, rdseg_shape3 s, const rdseg_params* prm,
+                           const float* u0, const float* p0, float* u, float* v, float* p,
+                           void* ws, size_t ws_bytes, void* stream) {
+    if (!prm) return fail(RDSEG_ERR_ARG, "prm is NULL");
+    if (!shape3_ok(s))
+        return fail(RDSEG_ERR_SHAPE, "invalid volume shape: need D, H, W >= 1, ld >= W, lds >= H*ld and D*lds < 2^31");
+    rdseg_status r = check_scalars(prm->lambda, prm->theta, prm->tau, prm->delta);
+    if (r) return r;
+    if (prm->iters < 0) return fail(RDSEG_ERR_ARG, "iters must be >= 0");
+    if (prm->inner < 0 || prm->inner > kMaxInner) return fail(RDSEG_ERR_ARG, "inner must lie in [0, 16]");
+    if (prm->tile_w || prm->tile_h || prm->iters_per_launch || prm->ckpt_every)
+        return fail(RDSEG_ERR_ARG, "tile_w, tile_h, iters_per_launch and ckpt_every must be 0 for volumes");
+    if (!f || !u || !v || !p) return fail(RDSEG_ERR_ARG, "f, u, v and p must be non-NULL");
+    const int64_t vol = (int64_t)s.D * s.lds;
+    const size_t vb = (size_t)vol * sizeof(float);
+    if (ranges_overlap(u, vb, f, vb) || ranges_overlap(v, vb, f, vb) ||
+        ranges_overlap(p, 3 * vb, f, vb) || ranges_overlap(u, vb, v, vb) ||
+        ranges_overlap(u, vb, p, 3 * vb) || ranges_overlap(v, vb, p, 3 * vb))
+        return fail(RDSEG_ERR_ARG, "u, v, p must not overlap f or each other");
+    if ((u0 && u0 != u && ranges_overlap(u0, vb, u, vb)) ||
+        (p0 && p0 != p && ranges_overlap(p0, 3 * vb, p, 3 * vb)))
+        return fail(RDSEG_ERR_ARG, "u0 / p0 may equal u / p but must not partially overlap them");
+    const VolWs need = carve_vol(nullptr, s);
+    if (!ws || ws_bytes < need.bytes)
+        return fail(RDSEG_ERR_WORKSPACE, "workspace too small: need " + std::to_string(need.bytes) + " bytes");
+    const VolWs w = carve_vol(ws, s);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    VolDesc d{};
+    d.f = f;
+    d.u = u;
+    d.c = w.c;
+    d.st[0][0] = v;
+    for (int k = 0; k < 3; ++k) d.st[0][1 + k] = p + k * vol;
+    for (int k = 0; k < 4; ++k) d.st[1][k] = w.st[k];
+    d.u0 = u0;
+    for (int k = 0; k < 3; ++k) d.p0[k] = p0 ? p0 + k * vol : nullptr;
+    d.D = s.D;
+    d.H = s.H;
+    d.W = s.W;
+    d.ld = (int32_t)s.ld;
+    d.lds = (int32_t)s.lds;
+    d.tl = (float)(prm->theta * prm->lambda);
+    d.delta = prm->delta;
+    if (launch_init3(d, st) || launch_tile_flags3(d, w.n_tiles, w.flags, st)) return RDSEG_ERR_HIP;
+    const int inner = prm->inner > 1 ? prm->inner : 1;
+    const int64_t L = (int64_t)prm->iters * inner;
+    const float theta = (float)prm->theta, inv_theta = (float)(1.0 / prm->theta);
+    const float tau = (float)prm->tau;
+    for (int64_t j = 0; j < L; ++j) {
+        const int in_buf = (int)((L - j) % 2);   // the last launch writes buffer 0
+        const bool uv = (j + 1) % inner == 0;
+        if (launch_iterate3(d, w.flags, w.n_tiles, in_buf, uv, j == L - 1, theta, inv_theta,
+                            tau, st))
+            return RDSEG_ERR_HIP;
+    }
+    return RDSEG_OK;
 }
 
 size_t rdseg_metrics_workspace_size(void) { return align_up(metrics_partials_bytes()); }

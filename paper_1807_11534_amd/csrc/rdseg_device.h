@@ -46,6 +46,20 @@ struct ImgDesc {
     double delta;
 };
 
+// A volume [D][H][W]: voxel (z, y, x) at z * lds + y * ld + x.  The two state
+// buffers are st[0] = the caller's (v, p_x, p_y, p_z), st[1] = the workspace's.
+struct VolDesc {
+    const float* f;
+    float* u;
+    float* c;
+    float* st[2][4];
+    const float* u0;
+    const float* p0[3];
+    int32_t D, H, W, ld, lds;
+    float tl;             // (float)(theta * lambda)
+    double delta;
+};
+
 // Cell flags kept in a register per LDS cell.
 enum : uint32_t { CF_ACT = 1u, CF_LASTC = 2u, CF_LASTR = 4u, CF_OUT = 8u };
 

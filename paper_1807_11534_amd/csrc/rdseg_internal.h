@@ -108,6 +108,15 @@ size_t metrics_partials_bytes();
 int launch_metrics(const float* u, const float* g, int H, int W, int ld, double eps,
                    double* partials, double* out, hipStream_t st);
 
+// ---------------------------------------------------------------- volumes
+void volume_tile(int* bx, int* by, int* bz);   // the volume kernel's tile
+int launch_init3(const VolDesc& d, hipStream_t st);
+int launch_tile_flags3(const VolDesc& d, int64_t n_tiles, int32_t* flags, hipStream_t st);
+// One dual step on the flagged tiles, reading state buffer in_buf and writing
+// 1 - in_buf; with uv also the u-step and v-step (u written when write_u).
+int launch_iterate3(const VolDesc& d, const int32_t* flags, int64_t n_tiles, int in_buf, bool uv,
+                    bool write_u, float theta, float inv_theta, float tau, hipStream_t st);
+
 // ---------------------------------------------------------------- iteration
 int launch_init(const ImgDesc* d0, const ImgDesc* descs, OffTables off, int n_img,
                 int64_t n_rows, hipStream_t st);

@@ -10,7 +10,7 @@ import math
 import torch
 
 from . import _lib
-from ._lib import Fit, Image, Params, Shape, check
+from ._lib import Fit, Image, Params, Shape, Shape3, check
 
 THETA = 0.1
 TAU = 0.125
@@ -184,6 +184,46 @@ def e1_e2(u, u_ref, eps=0.5):
     """(E1, E2) of Sec. 4 as Python floats (synchronises)."""
     a, b, e2 = metrics(u, u_ref, eps).tolist()
     return (1.0 if b == 0 else a / b), e2
+
+
+def shape3_of(f):
+    if not isinstance(f, torch.Tensor) or not f.is_cuda or f.dtype != torch.float32:
+        raise TypeError("f must be a float32 tensor on the GPU")
+    if f.dim() != 3 or f.stride(2) != 1:
+        raise ValueError("a volume must be 3-D [D][H][W] with unit stride along x")
+    D, H, W = f.shape
+    return Shape3(D, H, W, f.stride(1), f.stride(0))
+
+
+def _empty_like_volume(f, planes=None):
+    D, H, W = f.shape
+    ld, lds = f.stride(1), f.stride(0)
+    n = D * lds if planes is None else planes * D * lds
+    buf = torch.empty(n, dtype=torch.float32, device=f.device)
+    if planes is None:
+        return buf.as_strided((D, H, W), (lds, ld, 1))
+    return buf.as_strided((planes, D, H, W), (D * lds, lds, ld, 1))
+
+
+def solve3d(f, lam, theta=THETA, tau=1.0 / 12.0, delta=math.inf, iters=100, inner=1, u0=None,
+            p0=None, out=None, ws=None):
+    """The restricted iteration on a volume f [D][H][W] (7-point stencil).
+    Returns (u, v, p) with p of shape [3][D][H][W] (x, y, z components)."""
+    lib = _lib.load()
+    s = shape3_of(f)
+    prm = params(lam, theta, tau, delta, iters, 0, 0, 0, 0, inner)
+    if out is None:
+        u, v, p = _empty_like_volume(f), _empty_like_volume(f), _empty_like_volume(f, 3)
+    else:
+        u, v, p = out
+    if ws is None:
+        n = lib.rdseg_workspace_size3(ctypes.byref(s))
+        if n == 0:
+            raise ValueError("invalid volume shape")
+        ws = torch.empty(n, dtype=torch.uint8, device=f.device)
+    check(lib.rdseg_solve3d(_vp(f), s, ctypes.byref(prm), _vp(u0), _vp(p0), _vp(u), _vp(v),
+                            _vp(p), _vp(ws), ws.numel(), _stream()))
+    return u, v, p
 
 
 class BatchedSolver:

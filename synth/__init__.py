@@ -184,6 +184,38 @@ def config5(size=2048, frac=0.1, iters=300, seed=11):
     return prob
 
 
+TAU3 = 1.0 / 12.0   # Chambolle's step bound with three gradient components
+
+
+def ellipsoids_volume(D, H, W, n, seed, sigma=0.05):
+    """n random ellipsoids (intensity U[0.6, 0.9]) on a U[0.1, 0.3] background,
+    Gaussian noise sigma; returns (z, mask) in FP64."""
+    rng = np.random.default_rng(seed)
+    z = np.full((D, H, W), rng.uniform(0.1, 0.3))
+    mask = np.zeros((D, H, W), bool)
+    zz, yy, xx = np.mgrid[0:D, 0:H, 0:W].astype(np.float64)
+    for _ in range(n):
+        c = rng.uniform(0.2, 0.8, 3) * np.array([D, H, W])
+        a = rng.uniform(0.08, 0.2, 3) * np.array([D, H, W])
+        inside = (((zz - c[0]) / a[0]) ** 2 + ((yy - c[1]) / a[1]) ** 2 +
+                  ((xx - c[2]) / a[2]) ** 2) <= 1.0
+        z[inside] = rng.uniform(0.6, 0.9)
+        mask |= inside
+    z = z + rng.normal(0.0, sigma, (D, H, W))
+    return z, mask
+
+
+def config_volume(size=256, n=8, lam=5.0, frac=float("inf"), iters=100, seed=21):
+    """Volume workload: ellipsoids in a size^3 volume with the eq. CV term
+    (c1, c2 the region means)."""
+    z, mask = ellipsoids_volume(size, size, size, n, seed)
+    c1, c2 = _region_means(z, mask)
+    prob = _finish(z, mask, c1, c2, lam=lam, iters=iters, tau=TAU3,
+                   meta=dict(name="ellipsoids", seed=seed, size=size))
+    prob.delta = band_delta(prob.f, frac)
+    return prob
+
+
 def smooth_field(H, W, seed, scale=1.0, noise=0.1, modes=4):
     """Random smooth field plus noise: f with bands of small |f| along curves.
 

@@ -14,7 +14,7 @@ HEADER = os.path.join(ROOT, "include", "rdseg.h")
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(rdseg_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(rdseg_[a-z0-9_]+)\s*\(", text)))
 
 
 @pytest.fixture(scope="module")
@@ -149,3 +149,25 @@ def test_inner_steps_validation(lib):
     assert _solve(lib, (16, 16, 16), _prm(inner=2, ckpt_every=5), tape=tape) == 1
     # an explicit configuration whose halo holds fewer dual steps than inner
     assert _solve(lib, (16, 16, 16), _prm(inner=4, tile_w=16, tile_h=16, iters_per_launch=2)) == 1
+
+
+def test_volume_validation(lib):
+    from paper_1807_11534_amd._lib import Shape3
+    P = lambda a: ctypes.c_void_p(a << 32)
+    assert lib.rdseg_workspace_size3(ctypes.byref(Shape3(4, 5, 6, 6, 30))) > 0
+    assert lib.rdseg_workspace_size3(ctypes.byref(Shape3(4, 5, 6, 6, 29))) == 0
+
+    def call(sh, prm, f=P(1)):
+        return lib.rdseg_solve3d(f, sh, ctypes.byref(prm), None, None, P(2), P(3), P(4), P(8),
+                                 1 << 40, None)
+    ok = Shape3(4, 5, 6, 6, 30)
+    assert call(Shape3(0, 5, 6, 6, 30), _prm()) == 2
+    assert call(Shape3(4, 5, 6, 5, 30), _prm()) == 2
+    assert call(Shape3(1 << 12, 1 << 10, 1 << 10, 1 << 10, 1 << 20), _prm()) == 2
+    assert call(ok, _prm(theta=0.0)) == 1
+    assert call(ok, _prm(tile_w=8, tile_h=8, iters_per_launch=1)) == 1
+    assert call(ok, _prm(ckpt_every=4)) == 1
+    assert call(ok, _prm(inner=17)) == 1
+    assert call(ok, _prm(), f=None) == 1
+    assert lib.rdseg_solve3d(P(1), ok, ctypes.byref(_prm()), None, None, P(2), P(3), P(4), P(8),
+                             16, None) == 3
