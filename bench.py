@@ -205,6 +205,28 @@ def extras(torch, rdseg, synth, dev):
                          fwd_adjoint_ms=t_fb, forward_ms=t_f)
     del f, tgt
     out["paper_protocol_128"] = protocol(torch, rdseg, synth, dev)
+    # ---- 256^3 volume (7-point stencil), 100 iterations
+    prob = synth.config_volume(256)
+    f = torch.from_numpy(prob.f).to(dev)
+    for frac, name in [(math.inf, "volume_256_delta_inf"), (0.2, "volume_256_delta_0.2")]:
+        log(f"extras: {name}")
+        delta = synth.band_delta(prob.f, frac)
+        q = float((np.abs(prob.f.astype(np.float64)) < delta).mean())
+        out3 = (torch.empty_like(f), torch.empty_like(f),
+                torch.empty((3,) + tuple(f.shape), dtype=torch.float32, device=dev))
+        ws = torch.empty(rdseg._lib.load().rdseg_workspace_size3(
+            rdseg.ctypes.byref(rdseg.shape3_of(f))), dtype=torch.uint8, device=dev)
+        run = lambda: rdseg.solve3d(f, prob.lam, synth.THETA, synth.TAU3, delta, 100, out=out3,
+                                    ws=ws)
+        run()
+        t = timed(torch, run, 3)
+        upd = q * prob.f.size * 100
+        out[name] = dict(size=[256, 256, 256], iters=100, active_fraction=q, ms=t,
+                         updates_per_s=upd / (t * 1e-3),
+                         alg_gbs=36.0 * upd / (t * 1e-3) / 1e9)
+        del ws, out3
+    del f
+    torch.cuda.empty_cache()
     # ---- 4096^2 distance-selective solve, delta 0.1 max|f|, 1000 iterations
     log("extras: ds_4096")
     prob = synth.config3()
