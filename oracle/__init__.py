@@ -20,6 +20,8 @@ Parity status of each function (pins live in ``tests/test_oracle_*.py``):
 * ``solve_until`` -- pinned (diffs re-measured from two fixed-count solves; stop
   index; tolerance 0 / inf; empty domain stops at the first check).
 * ``metrics``     -- pinned (hand-worked 2x3 case, identity, disjoint labels, symmetry).
+* ``solve_pd``    -- pinned (duality gap of the restricted eq. CR problem closes; weak
+  duality at every iterate; hand-derived two-pixel minimisers).
 * ``grad3``/``div3`` -- pinned (adjointness, hand-worked 2x2x2 case).
 * ``solve3``      -- pinned (a volume of identical slices equals the pinned 2-D solve on
   each slice bit for bit; axis permutations; D = 1).
@@ -75,6 +77,8 @@ def _load():
                                     ctypes.POINTER(c_int), _dp, c_int]
     lib.orc_metrics.argtypes = [_dp, _dp, c_size, c_double, _i64p, _i64p, _dp]
     lib.orc_metrics.restype = None
+    lib.orc_solve_pd.argtypes = [_fp, c_int, c_int, c_double, c_double, c_double, c_double,
+                                 c_int, _dp, _dp, _dp, _dp, _dp, _dp]
     lib.orc_grad3.argtypes = [_dp, c_int, c_int, c_int, _dp, _dp, _dp]
     lib.orc_grad3.restype = None
     lib.orc_div3.argtypes = [_dp, _dp, _dp, c_int, c_int, c_int, _dp]
@@ -330,3 +334,21 @@ def solve3(f, lam, theta, tau, delta, iters, inner=1, u0=None, p0=None):
                           _ptr(u, _dp), _ptr(v, _dp), _ptr(p[0], _dp), _ptr(p[1], _dp),
                           _ptr(p[2], _dp)), "solve3")
     return u, v, p
+
+
+def solve_pd(f, lam, tau, sigma, delta, iters, u0=None, p0=None):
+    """Restricted primal-dual (Chambolle-Pock) iteration for eq. CR; returns
+    (u, p) with p as [2][H][W]."""
+    lib = _load()
+    f = _f32(f)
+    H, W = f.shape
+    u = np.empty((H, W))
+    px, py = np.empty((H, W)), np.empty((H, W))
+    u0c = None if u0 is None else _f64(u0)
+    p0x = None if p0 is None else _f64(p0[0])
+    p0y = None if p0 is None else _f64(p0[1])
+    _check(lib.orc_solve_pd(_ptr(f, _fp), H, W, float(lam), float(tau), float(sigma),
+                            float(delta), int(iters), _ptr(u0c, _dp), _ptr(p0x, _dp),
+                            _ptr(p0y, _dp), _ptr(u, _dp), _ptr(px, _dp), _ptr(py, _dp)),
+           "solve_pd")
+    return u, np.stack([px, py])

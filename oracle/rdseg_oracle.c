@@ -781,3 +781,64 @@ int orc_solve3(const float* f, int D, int H, int W, double lambda, double theta,
     free(A); free(h); free(d); free(w); free(gx); free(gy); free(gz);
     return ORC_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* The restriction applied to another solver (Sec. 5 proposes carrying the   */
+/* restricted domain over to other methods): the first-order primal-dual     */
+/* iteration of Chambolle and Pock for eq. CR itself,                        */
+/*     min over u in [0,1] of  TV(u) + lambda <f, u>,                         */
+/* restricted as in Sec. 3: u = H(-f) on Fg and Bg, p = 0 there, the TV terms */
+/* of the pixels of RD.  Per iteration, on RD:                               */
+/*     p <- (p + sigma grad ubar) / max(1, |p + sigma grad ubar|)             */
+/*     u_new = clamp(u + tau div p - tau lambda f, 0, 1)                      */
+/*     ubar  = 2 u_new - u                                                   */
+/* with ubar = u = H(-f) off RD; sigma tau <= 1/8 for convergence.           */
+/* Start: u0 (or H(-f)), ubar0 = u0, p0 (or 0).  Outputs u, p.               */
+/* ------------------------------------------------------------------------ */
+int orc_solve_pd(const float* f, int H, int W, double lambda, double tau, double sigma,
+                 double delta, int iters, const double* u0, const double* p0x,
+                 const double* p0y, double* u, double* px, double* py)
+{
+    if (!f || !u || !px || !py || H < 1 || W < 1 || iters < 0 || !(tau > 0) || !(sigma > 0) ||
+        !(lambda >= 0) || isnan(delta))
+        return ORC_ERR_ARG;
+    orc_ctx c;
+    if (ctx_init(&c, f, H, W, delta)) return ORC_ERR_MEM;
+    size_t N = c.N;
+    double* ub = (double*)malloc(N * sizeof(double));
+    if (!ub) { ctx_free(&c); return ORC_ERR_MEM; }
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+            size_t i = (size_t)y * W + x;
+            if (c.A[i]) {
+                u[i] = u0 ? u0[i] : c.h[i];
+                px[i] = (p0x && x < W - 1) ? p0x[i] : 0.0;
+                py[i] = (p0y && y < H - 1) ? p0y[i] : 0.0;
+            } else {
+                u[i] = c.h[i];
+                px[i] = py[i] = 0.0;
+            }
+            ub[i] = u[i];
+        }
+    for (int k = 0; k < iters; ++k) {
+        orc_grad(ub, H, W, c.gx, c.gy);
+        for (size_t i = 0; i < N; ++i) {
+            if (!c.A[i]) continue;
+            double ax = px[i] + sigma * c.gx[i], ay = py[i] + sigma * c.gy[i];
+            double n = sqrt(ax * ax + ay * ay);
+            double s = n > 1.0 ? n : 1.0;
+            px[i] = ax / s;
+            py[i] = ay / s;
+        }
+        orc_div(px, py, H, W, c.d);
+        for (size_t i = 0; i < N; ++i) {
+            if (!c.A[i]) continue;
+            double un = clamp01(u[i] + tau * c.d[i] - tau * lambda * c.fd[i]);
+            ub[i] = 2.0 * un - u[i];
+            u[i] = un;
+        }
+    }
+    free(ub);
+    ctx_free(&c);
+    return ORC_OK;
+}
