@@ -205,6 +205,36 @@ rdseg_status rdseg_solve_until(const float* f, rdseg_shape s, const rdseg_params
                                void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------- */
+/* The restriction on another solver (Sec. 5): primal-dual for eq. CR      */
+/* ---------------------------------------------------------------------- */
+
+/* Parameters of the primal-dual (Chambolle-Pock) iteration: lambda >= 0,
+ * tau > 0, sigma > 0 finite (convergence needs tau * sigma <= 1/8), delta not
+ * NaN as for rdseg_params; iters >= 0; tile_w, tile_h, iters_per_launch all 0
+ * (chosen by the library) or a compiled configuration (8x8/16, 16x16/8,
+ * 32x32/4, 64x64/8). */
+typedef struct {
+    double lambda, tau, sigma, delta;
+    int32_t iters;
+    int32_t iters_per_launch;
+    int32_t tile_w, tile_h;
+} rdseg_pd_params;
+
+/* Workspace bytes for rdseg_solve_pd (0 if the shape is invalid). */
+size_t rdseg_pd_workspace_size(const rdseg_shape* s);
+
+/* Solves eq. CR itself, min over u in [0,1] of TV(u) + lambda <f, u>, with the
+ * restriction of Sec. 3 carried over as Sec. 5 proposes: on RD = {|f| < delta}
+ *     p    <- (p + sigma grad ubar) / max(1, |p + sigma grad ubar|)
+ *     u'   =  clamp(u + tau div p - tau lambda f, 0, 1),  ubar = 2 u' - u
+ * and u = ubar = H(-f), p = 0 elsewhere; start u0 (nullable: H(-f)),
+ * ubar0 = u0, p0 (nullable: 0; [2][H][ld]).  Same operators, layout and
+ * ownership as rdseg_solve; writes u and p (full grids). */
+rdseg_status rdseg_solve_pd(const float* f, rdseg_shape s, const rdseg_pd_params* prm,
+                            const float* u0, const float* p0, float* u, float* p,
+                            void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------- */
 /* Volumes (Sec. 5 names 3-D problems as the extension of interest)        */
 /* ---------------------------------------------------------------------- */
 

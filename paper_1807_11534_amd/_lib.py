@@ -38,6 +38,13 @@ class Shape3(ctypes.Structure):
                 ("ld", ctypes.c_int64), ("lds", ctypes.c_int64)]
 
 
+class PdParams(ctypes.Structure):
+    _fields_ = [("lambda_", ctypes.c_double), ("tau", ctypes.c_double),
+                ("sigma", ctypes.c_double), ("delta", ctypes.c_double),
+                ("iters", ctypes.c_int32), ("iters_per_launch", ctypes.c_int32),
+                ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32)]
+
+
 class Fit(ctypes.Structure):
     _fields_ = [("z", ctypes.c_void_p), ("P", ctypes.c_void_p), ("c1", ctypes.c_double),
                 ("c2", ctypes.c_double), ("gamma", ctypes.c_double)]
@@ -64,6 +71,9 @@ SIGNATURES = {
     "rdseg_band_threshold": (ctypes.c_int, [_vp, Shape, _d, _vp, _vp, _sz, _vp]),
     "rdseg_solve": (ctypes.c_int, [_vp, Shape, ctypes.POINTER(Params), _vp, _vp, _vp, _vp, _vp,
                                    _vp, _vp, _sz, _vp]),
+    "rdseg_pd_workspace_size": (_sz, [ctypes.POINTER(Shape)]),
+    "rdseg_solve_pd": (ctypes.c_int, [_vp, Shape, ctypes.POINTER(PdParams), _vp, _vp, _vp, _vp,
+                                      _vp, _sz, _vp]),
     "rdseg_workspace_size3": (_sz, [ctypes.POINTER(Shape3)]),
     "rdseg_solve3d": (ctypes.c_int, [_vp, Shape3, ctypes.POINTER(Params), _vp, _vp, _vp, _vp, _vp,
                                      _vp, _sz, _vp]),

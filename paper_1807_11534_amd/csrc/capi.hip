@@ -827,6 +827,29 @@ void plan_free(BatchPlan* P) {
     delete P;
 }
 
+// ------------------------------------------------------------------ primal-dual
+struct PdWs {
+    SolveWs base;      // c, masks, scan scratch, queue (its state planes unused)
+    float* ubar0;      // ubar of buffer 0 (the caller has no plane for it)
+    float* st1[4];     // buffer 1: u, ubar, p_x, p_y
+    size_t bytes;
+};
+
+PdWs carve_pd(void* base, const rdseg_shape& s) {
+    PdWs w;
+    w.base = carve_solve(base, s);
+    Carver cv(base);
+    cv.off = w.base.bytes;
+    const int64_t plane = (int64_t)s.H * s.ld;
+    w.ubar0 = cv.take<float>(plane);
+    w.st1[0] = w.base.st[0];
+    w.st1[1] = cv.take<float>(plane);
+    w.st1[2] = w.base.st[1];
+    w.st1[3] = w.base.st[2];
+    w.bytes = cv.off;
+    return w;
+}
+
 // ------------------------------------------------------------------ volumes
 bool shape3_ok(const rdseg_shape3& s) {
     if (s.D < 1 || s.H < 1 || s.W < 1 || s.ld < s.W || s.lds < (int64_t)s.H * s.ld) return false;
@@ -969,6 +992,93 @@ rdseg_status rdseg_solve_until(const float* f, rdseg_shape s, const rdseg_params
                 poll != 0};
     return solve_impl(f, s, prm, u0, p0, u, v, p, nullptr, ws, ws_bytes,
                       static_cast<hipStream_t>(stream), -1, &sp);
+}
+
+size_t rdseg_pd_workspace_size(const rdseg_shape* s) {
+    if (!s || !shape_ok(*s)) return 0;
+    return carve_pd(nullptr, *s).bytes;
+}
+
+rdseg_status rdseg_solve_pd(const float* f, rdseg_shape s, const rdseg_pd_params* prm,
+                            const float* u0, const float* p0, float* u, float* p, void* ws,
+                            size_t ws_bytes, void* stream) {
+    if (!prm) return fail(RDSEG_ERR_ARG, "prm is NULL");
+    rdseg_status r = check_shape(s);
+    if (r) return r;
+    if (!(isfinite(prm->lambda) && prm->lambda >= 0)) return fail(RDSEG_ERR_ARG, "lambda must be finite and >= 0");
+    if (!(isfinite(prm->tau) && prm->tau > 0)) return fail(RDSEG_ERR_ARG, "tau must be finite and > 0");
+    if (!(isfinite(prm->sigma) && prm->sigma > 0)) return fail(RDSEG_ERR_ARG, "sigma must be finite and > 0");
+    if (isnan(prm->delta)) return fail(RDSEG_ERR_ARG, "delta must not be NaN");
+    if (prm->iters < 0) return fail(RDSEG_ERR_ARG, "iters must be >= 0");
+    if (!f || !u || !p) return fail(RDSEG_ERR_ARG, "f, u and p must be non-NULL");
+    const size_t pb = (size_t)s.H * s.ld * sizeof(float);
+    if (ranges_overlap(u, pb, f, pb) || ranges_overlap(p, 2 * pb, f, pb) ||
+        ranges_overlap(u, pb, p, 2 * pb))
+        return fail(RDSEG_ERR_ARG, "u and p must not overlap f or each other");
+    if ((u0 && u0 != u && ranges_overlap(u0, pb, u, pb)) ||
+        (p0 && p0 != p && ranges_overlap(p0, 2 * pb, p, 2 * pb)))
+        return fail(RDSEG_ERR_ARG, "u0 / p0 may equal u / p but must not partially overlap them");
+    int ci = -1;
+    if (prm->tile_w || prm->tile_h || prm->iters_per_launch) {
+        ci = pd_config_index(prm->tile_w, prm->tile_h, prm->iters_per_launch);
+        if (ci < 0) return fail(RDSEG_ERR_ARG, "tile_w / tile_h / iters_per_launch is not a compiled primal-dual configuration");
+    }
+    const PdWs need = carve_pd(nullptr, s);
+    if (!ws || ws_bytes < need.bytes)
+        return fail(RDSEG_ERR_WORKSPACE, "workspace too small: need " + std::to_string(need.bytes) + " bytes");
+    const PdWs w = carve_pd(ws, s);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Geo g = geo_of(s);
+    // tile masks and the macro queue come from the same compaction as rdseg_solve
+    ImgDesc d = make_desc(f, s, prm->lambda, prm->tau, prm->delta, nullptr, nullptr, nullptr,
+                          w.base.c, w.base.st, nullptr, nullptr, 8, 8);
+    OffTables off{nullptr, nullptr, nullptr, nullptr};
+    if (launch_tile_masks(&d, nullptr, off, 1, g.strips, w.base.masks, w.base.npix, st))
+        return RDSEG_ERR_HIP;
+    if (ci < 0) {
+        // dense problems take the large tiles, sparse bands the small ones
+        int64_t np = 0;
+        if (hipMemcpyAsync(&np, w.base.npix, sizeof(np), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return fail(RDSEG_ERR_HIP, "reading the active-pixel count failed");
+        const double q = (double)np / ((double)s.H * s.W);
+        ci = q > 0.3 ? pd_config_index(64, 64, 8) : pd_config_index(16, 16, 8);
+    }
+    const TileCfg cfg = pd_config_at(ci);
+    d = make_desc(f, s, prm->lambda, prm->tau, prm->delta, nullptr, nullptr, nullptr, w.base.c,
+                  w.base.st, nullptr, nullptr, cfg.bx, cfg.by);
+    PdDesc pd{};
+    pd.f = f;
+    pd.c = w.base.c;
+    const int64_t plane = (int64_t)s.H * s.ld;
+    pd.st[0][0] = u;
+    pd.st[0][1] = w.ubar0;
+    pd.st[0][2] = p;
+    pd.st[0][3] = p + plane;
+    for (int k = 0; k < 4; ++k) pd.st[1][k] = w.st1[k];
+    pd.u0 = u0;
+    pd.p0x = p0;
+    pd.p0y = p0 ? p0 + plane : nullptr;
+    pd.H = s.H;
+    pd.W = s.W;
+    pd.ld = (int32_t)s.ld;
+    pd.mw = d.mw;
+    pd.tl = (float)(prm->tau * prm->lambda);
+    pd.delta = prm->delta;
+    if (launch_pd_init(pd, st)) return RDSEG_ERR_HIP;
+    const int64_t nm = macro_count(s, cfg.bx, cfg.by);
+    QueueScratch qs{nullptr, nullptr, w.base.flags, w.base.offs, w.base.part};
+    if (launch_macro_queue(&d, nullptr, off, 1, nm, cfg.bx, cfg.by, w.base.masks, qs,
+                           w.base.queue, w.base.totals, g.nt, nullptr, w.base.totals + 2, st))
+        return RDSEG_ERR_HIP;
+    const int L = (prm->iters + cfg.it - 1) / cfg.it;
+    for (int j = 0; j < L; ++j) {
+        const int nit = std::min(cfg.it, prm->iters - j * cfg.it);
+        if (launch_pd_iterate(ci, pd, w.base.queue, w.base.totals, nm, (L - j) % 2, nit,
+                              (float)prm->tau, (float)prm->sigma, st))
+            return RDSEG_ERR_HIP;
+    }
+    return RDSEG_OK;
 }
 
 size_t rdseg_workspace_size3(const rdseg_shape3* s) {

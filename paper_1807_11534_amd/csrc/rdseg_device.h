@@ -60,6 +60,20 @@ struct VolDesc {
     double delta;
 };
 
+// An image solved with the primal-dual iteration: state buffers st[b] =
+// (u, ubar, p_x, p_y); c = tau*lambda*f on RD, -/+inf on Fg / Bg.
+struct PdDesc {
+    const float* f;
+    float* c;
+    float* st[2][4];
+    const float* u0;
+    const float* p0x;
+    const float* p0y;
+    int32_t H, W, ld, mw;
+    float tl;             // (float)(tau * lambda)
+    double delta;
+};
+
 // Cell flags kept in a register per LDS cell.
 enum : uint32_t { CF_ACT = 1u, CF_LASTC = 2u, CF_LASTR = 4u, CF_OUT = 8u };
 

@@ -108,6 +108,23 @@ size_t metrics_partials_bytes();
 int launch_metrics(const float* u, const float* g, int H, int W, int ld, double eps,
                    double* partials, double* out, hipStream_t st);
 
+// Tile configuration of a temporally blocked kernel: bx x by macro tiles,
+// `it` steps per launch (the halo depth), nt threads per workgroup.
+struct TileCfg {
+    int bx, by, it, nt;
+};
+
+// ---------------------------------------------------------------- primal-dual
+int pd_config_count();
+TileCfg pd_config_at(int i);
+int pd_config_index(int bx, int by, int it);   // -1 if not compiled
+int launch_pd_init(const PdDesc& d, hipStream_t st);
+// nit (<= cfg.it) primal-dual iterations over the queued macro tiles, reading
+// state buffer in_buf and writing 1 - in_buf.
+int launch_pd_iterate(int ci, const PdDesc& d, const int2* queue, const int32_t* n_queue,
+                      int64_t max_items, int in_buf, int nit, float tau, float sigma,
+                      hipStream_t st);
+
 // ---------------------------------------------------------------- volumes
 void volume_tile(int* bx, int* by, int* bz);   // the volume kernel's tile
 int launch_init3(const VolDesc& d, hipStream_t st);
@@ -121,9 +138,6 @@ int launch_iterate3(const VolDesc& d, const int32_t* flags, int64_t n_tiles, int
 int launch_init(const ImgDesc* d0, const ImgDesc* descs, OffTables off, int n_img,
                 int64_t n_rows, hipStream_t st);
 
-struct TileCfg {
-    int bx, by, it, nt;
-};
 int config_count();
 TileCfg config_at(int i);
 int config_index(int bx, int by, int it);   // -1 if not compiled

@@ -10,7 +10,7 @@ import math
 import torch
 
 from . import _lib
-from ._lib import Fit, Image, Params, Shape, Shape3, check
+from ._lib import Fit, Image, Params, PdParams, Shape, Shape3, check
 
 THETA = 0.1
 TAU = 0.125
@@ -184,6 +184,34 @@ def e1_e2(u, u_ref, eps=0.5):
     """(E1, E2) of Sec. 4 as Python floats (synchronises)."""
     a, b, e2 = metrics(u, u_ref, eps).tolist()
     return (1.0 if b == 0 else a / b), e2
+
+
+PD_STEP = 1.0 / math.sqrt(8.0)   # tau = sigma with tau * sigma * |grad|^2 <= 1
+
+
+def solve_pd(f, lam, delta=math.inf, iters=500, tau=PD_STEP, sigma=PD_STEP, u0=None, p0=None,
+             tile=None, iters_per_launch=0, out=None, ws=None):
+    """The restricted primal-dual (Chambolle-Pock) iteration for eq. CR.
+    Returns (u, p) with p of shape [2][H][W]."""
+    lib = _lib.load()
+    s = shape_of(f)
+    tw, th = (0, 0) if tile is None else tile
+    prm = PdParams(float(lam), float(tau), float(sigma), float(delta), int(iters),
+                   int(iters_per_launch), int(tw), int(th))
+    if out is None:
+        u, p = _empty_like_grid(f), _empty_like_grid(f, 2)
+    else:
+        u, p = out
+    if p.stride(0) != s.H * s.ld or p.stride(1) != s.ld:
+        raise ValueError("p must be [2][H][ld] with the pitch of f")
+    if ws is None:
+        n = lib.rdseg_pd_workspace_size(ctypes.byref(s))
+        if n == 0:
+            raise ValueError("invalid shape")
+        ws = torch.empty(n, dtype=torch.uint8, device=f.device)
+    check(lib.rdseg_solve_pd(_vp(f), s, ctypes.byref(prm), _vp(u0), _vp(p0), _vp(u), _vp(p),
+                             _vp(ws), ws.numel(), _stream()))
+    return u, p
 
 
 def shape3_of(f):

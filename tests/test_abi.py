@@ -171,3 +171,27 @@ def test_volume_validation(lib):
     assert call(ok, _prm(), f=None) == 1
     assert lib.rdseg_solve3d(P(1), ok, ctypes.byref(_prm()), None, None, P(2), P(3), P(4), P(8),
                              16, None) == 3
+
+
+def test_primal_dual_validation(lib):
+    from paper_1807_11534_amd._lib import PdParams, Shape
+    P = lambda a: ctypes.c_void_p(a << 32)
+    sh = Shape(16, 16, 16)
+    n = lib.rdseg_pd_workspace_size(ctypes.byref(sh))
+    assert n > lib.rdseg_workspace_size(ctypes.byref(sh), None)
+
+    def call(**kw):
+        d = dict(lambda_=1.0, tau=0.35, sigma=0.35, delta=math.inf, iters=10, iters_per_launch=0,
+                 tile_w=0, tile_h=0)
+        d.update(kw)
+        prm = PdParams(**d)
+        return lib.rdseg_solve_pd(P(1), sh, ctypes.byref(prm), None, None, P(2), P(3), P(8), n,
+                                  None)
+    for kw in (dict(tau=0.0), dict(sigma=-1.0), dict(lambda_=math.nan), dict(delta=math.nan),
+               dict(iters=-1), dict(tile_w=24, tile_h=24, iters_per_launch=3)):
+        assert call(**kw) == 1, kw
+    prm = PdParams(1.0, 0.35, 0.35, math.inf, 10, 0, 0, 0)
+    assert lib.rdseg_solve_pd(P(1), sh, ctypes.byref(prm), None, None, P(2), P(3), P(8), 16,
+                              None) == 3
+    assert lib.rdseg_solve_pd(P(1), sh, ctypes.byref(prm), None, None, P(1), P(3), P(8), n,
+                              None) == 1   # u aliases f
