@@ -205,6 +205,27 @@ def extras(torch, rdseg, synth, dev):
                          fwd_adjoint_ms=t_fb, forward_ms=t_f)
     del f, tgt
     out["paper_protocol_128"] = protocol(torch, rdseg, synth, dev)
+    # ---- restricted primal-dual solve of eq. CR on the 1024^2 sweep image
+    prob = synth.config2(1, 1024, 500)
+    f = torch.from_numpy(prob.f).to(dev)
+    for frac, name in [(math.inf, "primal_dual_1024_delta_inf"),
+                       (0.5, "primal_dual_1024_delta_0.5")]:
+        log(f"extras: {name}")
+        delta = synth.band_delta(prob.f, frac)
+        q = float((np.abs(prob.f.astype(np.float64)) < delta).mean())
+        outp = (torch.empty_like(f), torch.empty((2,) + tuple(f.shape), dtype=torch.float32,
+                                                 device=dev))
+        wsp = torch.empty(rdseg._lib.load().rdseg_pd_workspace_size(
+            rdseg.ctypes.byref(rdseg.shape_of(f))), dtype=torch.uint8, device=dev)
+        run = lambda: rdseg.solve_pd(f, prob.lam, delta, 500, out=outp, ws=wsp)
+        run()
+        t = timed(torch, run, 3)
+        upd = q * prob.f.size * 500
+        out[name] = dict(size=1024, iters=500, active_fraction=q, ms=t,
+                         updates_per_s=upd / (t * 1e-3),
+                         alg_gbs=36.0 * upd / (t * 1e-3) / 1e9)
+        del outp, wsp
+    del f
     # ---- 256^3 volume (7-point stencil), 100 iterations
     prob = synth.config_volume(256)
     f = torch.from_numpy(prob.f).to(dev)
