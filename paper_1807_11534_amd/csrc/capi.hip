@@ -255,7 +255,76 @@ int heuristic_cfg(const rdseg_shape& s, double q) {
     return config_index(16, 16, 1);
 }
 
-// ------------------------------------------------------------------ solve core
+// ------------------------------------------------------------------ side stream
+// Closed tiles are independent of every other RD pixel (no RD 4-neighbour
+// outside the tile) and their pixels lie outside the queued macro tiles, so
+// their all-iteration kernel can run beside the blocked launches: it is
+// latency bound (one wave runs every iteration of its tile), the blocked
+// launches are many short kernels, and the two write disjoint pixels.  The
+// blocked kernel may read a closed tile's pixels as halo while they are being
+// written, but those cells feed no RD pixel outside the tile (no RD
+// 4-neighbour there; frozen cells contribute constants), so its results do
+// not depend on what it reads.  One non-blocking stream per device, default
+// priority, created on first use and kept for the process.
+std::mutex g_side_mu;
+std::map<int, hipStream_t> g_side;
+
+hipStream_t side_stream() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> lk(g_side_mu);
+    auto it = g_side.find(dev);
+    if (it != g_side.end()) return it->second;
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return nullptr;
+    g_side[dev] = s;
+    return s;
+}
+
+// Enqueue the closed-tile kernel after the work already on `st`, on the side
+// stream when there is one (*join then receives the event that `st` must wait
+// for before the solve's results are complete), else, and while `st` is being
+// captured into a graph, on `st` itself.
+template <class Launch>
+rdseg_status closed_beside(hipStream_t st, hipEvent_t* join, Launch launch) {
+    *join = nullptr;
+    // under graph capture (batched plans) the kernel stays on the captured stream
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone)
+        return launch(st) ? RDSEG_ERR_HIP : RDSEG_OK;
+    hipStream_t side = side_stream();
+    hipEvent_t fork = nullptr;
+    if (!side || hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess)
+        return launch(st) ? RDSEG_ERR_HIP : RDSEG_OK;
+    if (hipEventCreateWithFlags(join, hipEventDisableTiming) != hipSuccess) {
+        (void)hipEventDestroy(fork);
+        *join = nullptr;
+        return launch(st) ? RDSEG_ERR_HIP : RDSEG_OK;
+    }
+    rdseg_status r = RDSEG_OK;
+    if (hipEventRecord(fork, st) != hipSuccess || hipStreamWaitEvent(side, fork, 0) != hipSuccess)
+        r = fail(RDSEG_ERR_HIP, "forking the closed-tile stream failed");
+    else if (launch(side))
+        r = RDSEG_ERR_HIP;
+    else if (hipEventRecord(*join, side) != hipSuccess)
+        r = fail(RDSEG_ERR_HIP, "recording the closed-tile join failed");
+    (void)hipEventDestroy(fork);
+    if (r) {
+        (void)hipEventDestroy(*join);
+        *join = nullptr;
+    }
+    return r;
+}
+
+// Make `st` wait for the closed-tile kernel (no-op without a join event).
+rdseg_status join_closed(hipStream_t st, hipEvent_t join) {
+    if (!join) return RDSEG_OK;
+    const hipError_t e = hipStreamWaitEvent(st, join, 0);
+    (void)hipEventDestroy(join);
+    return e == hipSuccess ? RDSEG_OK : fail(RDSEG_ERR_HIP, "joining the closed-tile stream failed");
+}
+
+// ------------------------------------------------------------------ solve core// ------------------------------------------------------------------ solve core
 struct SolvePlanArgs {
     const ImgDesc* d0;
     const ImgDesc* descs;   // batched when non-NULL
@@ -572,10 +641,15 @@ rdseg_status solve_impl(const float* f, rdseg_shape s, const rdseg_params* prm, 
     if (launch_macro_queue(&d, nullptr, off, 1, nm, cfg.bx, cfg.by, w.masks, qs, w.queue, w.totals,
                            g.nt, use_closed ? w.cqueue : nullptr, w.totals + 2, st))
         return RDSEG_ERR_HIP;
-    if (use_closed &&
-        launch_closed(&d, nullptr, false, w.cqueue, w.totals + 2, g.nt, prm->iters,
-                      (float)prm->theta, (float)(1.0 / prm->theta), (float)prm->tau, st, inner))
-        return RDSEG_ERR_HIP;
+    hipEvent_t join = nullptr;
+    if (use_closed) {
+        r = closed_beside(st, &join, [&](hipStream_t cs) {
+            return launch_closed(&d, nullptr, false, w.cqueue, w.totals + 2, g.nt, prm->iters,
+                                 (float)prm->theta, (float)(1.0 / prm->theta), (float)prm->tau,
+                                 cs, inner);
+        });
+        if (r) return r;
+    }
     SolvePlanArgs a;
     a.d0 = &d;
     a.descs = nullptr;
@@ -594,7 +668,10 @@ rdseg_status solve_impl(const float* f, rdseg_shape s, const rdseg_params* prm, 
     a.stop = stop;
     a.inner = inner;
     r = enqueue_iterations(a);
-    if (r || !stop) return r;
+    const rdseg_status rj = join_closed(st, join);
+    if (r) return r;
+    if (rj) return rj;
+    if (!stop) return RDSEG_OK;
     return hip_status(launch_stop_finalize(d, stop->slots, stop->n_checks, stop->tol,
                                            stop->check_every, a.launches_per_check, a.launches,
                                            prm->iters, stop->iters_done, st));
@@ -722,10 +799,14 @@ rdseg_status enqueue_batch(const BatchLayout& L, int n, int ci, int iters, doubl
     if (launch_macro_queue(d0, L.d_descs, off, n, L.macros, cfg.bx, cfg.by, L.masks, qs, L.queue,
                            L.totals, L.tiles, use_closed ? L.cqueue : nullptr, L.totals + 2, st))
         return RDSEG_ERR_HIP;
-    if (use_closed &&
-        launch_closed(d0, L.d_descs, true, L.cqueue, L.totals + 2, L.tiles, iters, (float)theta,
-                      (float)(1.0 / theta), (float)tau, st))
-        return RDSEG_ERR_HIP;
+    hipEvent_t join = nullptr;
+    if (use_closed) {
+        rdseg_status r = closed_beside(st, &join, [&](hipStream_t cs) {
+            return launch_closed(d0, L.d_descs, true, L.cqueue, L.totals + 2, L.tiles, iters,
+                                 (float)theta, (float)(1.0 / theta), (float)tau, cs);
+        });
+        if (r) return r;
+    }
     SolvePlanArgs a;
     a.d0 = d0;
     a.descs = L.d_descs;
@@ -741,7 +822,9 @@ rdseg_status enqueue_batch(const BatchLayout& L, int n, int ci, int iters, doubl
     a.tape = nullptr;
     a.npix = L.npix_total;
     a.st = st;
-    return enqueue_iterations(a);
+    const rdseg_status r = enqueue_iterations(a);
+    const rdseg_status rj = join_closed(st, join);
+    return r ? r : rj;
 }
 
 // ------------------------------------------------------------------ backward

@@ -283,7 +283,7 @@ __global__ void k_lists(ImgDesc d0, const ImgDesc* __restrict__ descs, OffTables
 }
 
 // Exclusive scans of up to two int32 arrays of at most SMALL_N elements, one
-// 1024-thread block per array.
+// 1024-thread block per array (the arrays are 16-byte aligned workspace).
 constexpr int SMALL_T = 1024;
 constexpr int SMALL_I = 64;
 constexpr int64_t SMALL_N = (int64_t)SMALL_T * SMALL_I;
@@ -294,35 +294,53 @@ __global__ __launch_bounds__(SMALL_T) void k_scan_small2(const int32_t* __restri
                                                          const int32_t* __restrict__ b, int64_t nb,
                                                          int32_t* __restrict__ ob,
                                                          int32_t* __restrict__ tb) {
+    // Chunks of 4 * SMALL_T values: one aligned int4 per thread (coalesced),
+    // a wave scan, a scan of the wave totals, and a running carry.
     __shared__ int s_w[SMALL_T / 64];
     const int32_t* in = blockIdx.x == 0 ? a : b;
     const int64_t n = blockIdx.x == 0 ? na : nb;
     int32_t* out = blockIdx.x == 0 ? oa : ob;
     int32_t* tot_out = blockIdx.x == 0 ? ta : tb;
     if (!in) return;   // uniform per block
-    const int64_t base = (int64_t)threadIdx.x * SMALL_I;
-    int s = 0;
-    for (int k = 0; k < SMALL_I; ++k) s += (base + k < n) ? in[base + k] : 0;
-    int incl = wave_incl_scan(s);
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (lane == 63) s_w[wid] = incl;
-    __syncthreads();
-    int pre = 0, tot = 0;
-#pragma unroll
-    for (int k = 0; k < SMALL_T / 64; ++k) {
-        const int v = s_w[k];
-        pre += (k < wid) ? v : 0;
-        tot += v;
-    }
-    int ex = pre + incl - s;
-    for (int k = 0; k < SMALL_I; ++k) {
-        if (base + k < n) {
-            const int v = in[base + k];
-            out[base + k] = ex;
-            ex += v;
+    const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+    int carry = 0;
+    for (int64_t base = 0; base < n; base += 4 * SMALL_T) {
+        const int64_t i0 = base + 4 * t;
+        int4 v = make_int4(0, 0, 0, 0);
+        if (i0 + 3 < n) {
+            v = *reinterpret_cast<const int4*>(in + i0);
+        } else if (i0 < n) {
+            v.x = in[i0];
+            if (i0 + 1 < n) v.y = in[i0 + 1];
+            if (i0 + 2 < n) v.z = in[i0 + 2];
         }
+        const int s = v.x + v.y + v.z + v.w;
+        const int incl = wave_incl_scan(s);
+        if (lane == 63) s_w[wid] = incl;
+        __syncthreads();
+        int pre = 0, tot = 0;
+#pragma unroll
+        for (int k = 0; k < SMALL_T / 64; ++k) {
+            const int w = s_w[k];
+            pre += (k < wid) ? w : 0;
+            tot += w;
+        }
+        int4 o;
+        o.x = carry + pre + incl - s;
+        o.y = o.x + v.x;
+        o.z = o.y + v.y;
+        o.w = o.z + v.z;
+        if (i0 + 3 < n) {
+            *reinterpret_cast<int4*>(out + i0) = o;
+        } else if (i0 < n) {
+            out[i0] = o.x;
+            if (i0 + 1 < n) out[i0 + 1] = o.y;
+            if (i0 + 2 < n) out[i0 + 2] = o.z;
+        }
+        carry += tot;
+        __syncthreads();   // s_w is rewritten by the next chunk
     }
-    if (threadIdx.x == 0) *tot_out = tot;
+    if (t == 0) *tot_out = carry;
 }
 
 template <bool BATCHED>
