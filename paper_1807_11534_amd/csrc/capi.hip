@@ -1515,25 +1515,31 @@ rdseg_status rdseg_autotune(const float* f, rdseg_shape s, const rdseg_params* p
     int best = -1;
     float best_ms = 0.0f;
     const int inner = prm->inner > 1 ? prm->inner : 1;
-    for (int ci = 0; ci < config_count(); ++ci) {
-        if (config_at(ci).it < inner) continue;
-        // warm-up, then timed
-        rdseg_status r = solve_impl(f, s, &q, nullptr, nullptr, u, v, p, nullptr, ws, ws_bytes, st, ci);
-        if (r) { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); return r; }
-        (void)hipEventRecord(e0, st);
-        for (int rep = 0; rep < 3; ++rep) {
-            r = solve_impl(f, s, &q, nullptr, nullptr, u, v, p, nullptr, ws, ws_bytes, st, ci);
+    // two rounds over all configurations, each timed over three solves after a
+    // warm-up; the minimum per configuration damps clock and cache noise
+    std::vector<float> ms_min(config_count(), -1.0f);
+    for (int round = 0; round < 2; ++round) {
+        for (int ci = 0; ci < config_count(); ++ci) {
+            if (config_at(ci).it < inner) continue;
+            rdseg_status r = solve_impl(f, s, &q, nullptr, nullptr, u, v, p, nullptr, ws, ws_bytes, st, ci);
             if (r) { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); return r; }
+            (void)hipEventRecord(e0, st);
+            for (int rep = 0; rep < 3; ++rep) {
+                r = solve_impl(f, s, &q, nullptr, nullptr, u, v, p, nullptr, ws, ws_bytes, st, ci);
+                if (r) { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); return r; }
+            }
+            (void)hipEventRecord(e1, st);
+            if (hipEventSynchronize(e1) != hipSuccess) {
+                (void)hipEventDestroy(e0); (void)hipEventDestroy(e1);
+                return fail(RDSEG_ERR_HIP, "autotune timing failed");
+            }
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (ms_min[ci] < 0.0f || ms < ms_min[ci]) ms_min[ci] = ms;
         }
-        (void)hipEventRecord(e1, st);
-        if (hipEventSynchronize(e1) != hipSuccess) {
-            (void)hipEventDestroy(e0); (void)hipEventDestroy(e1);
-            return fail(RDSEG_ERR_HIP, "autotune timing failed");
-        }
-        float ms = 0.0f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        if (best < 0 || ms < best_ms) { best = ci; best_ms = ms; }
     }
+    for (int ci = 0; ci < config_count(); ++ci)
+        if (ms_min[ci] >= 0.0f && (best < 0 || ms_min[ci] < best_ms)) { best = ci; best_ms = ms_min[ci]; }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     // record under the problem's class and active-fraction bucket

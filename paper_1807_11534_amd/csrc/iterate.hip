@@ -65,15 +65,18 @@ __global__ __launch_bounds__(256) void k_init(ImgDesc d0, const ImgDesc* __restr
 
 // The on-chip iterations.  Slot j of a thread is region cell t + j * NT in
 // MODE_DENSE (every region cell, with per-cell selects for cells off RD and on
-// the last column / row) and MODE_FAST (every region cell is inside the grid,
-// in RD and away from the last column / row: no selects), and the j-th entry
+// the last column / row), MODE_DENSE_IN (the same for a region that holds no
+// cell of the last column / row: the dual step runs select-free with a step of
+// 0 on cells off RD, which leaves their p = 0 exactly) and MODE_FAST (every
+// region cell is inside the grid, in RD and away from the last column / row:
+// no selects), and the j-th entry
 // of the block's ascending list of RD cells in MODE_COMPACT (idx[j] < 0: empty
 // slot); there cells off RD are never visited: their p = 0 and
 // w = -H(-f)/theta were stored in LDS when the region was loaded.
 // STOP: ru holds u of the previous iteration on CF_OUT cells; with `check`,
 // the last iteration folds max(|u - u_prev|, |v - v_prev|) of those cells into
 // dmax (bit patterns of non-negative floats order like their values).
-enum { MODE_DENSE = 0, MODE_FAST = 1, MODE_COMPACT = 2 };
+enum { MODE_DENSE = 0, MODE_FAST = 1, MODE_COMPACT = 2, MODE_DENSE_IN = 3 };
 
 template <int BX, int BY, int IT, int NT, int MODE, bool STOP>
 __device__ __forceinline__ void run_iterations(float* __restrict__ sPX, float* __restrict__ sPY,
@@ -97,7 +100,7 @@ __device__ __forceinline__ void run_iterations(float* __restrict__ sPX, float* _
             if (MODE == MODE_COMPACT ? (i >= 0) : (i < RC)) {
                 float dd = div_p(rpx[j], sPX[PAD + i - 1], rpy[j], sPY[PAD + i - RX]);
                 sW[PAD + i] = w_of(dd, rv[j], inv_theta,
-                                   MODE == MODE_DENSE ? (fl[j] & CF_ACT) != 0 : true);
+                                   (MODE == MODE_DENSE || MODE == MODE_DENSE_IN) ? (fl[j] & CF_ACT) != 0 : true);
             }
         }
     }
@@ -115,13 +118,14 @@ __device__ __forceinline__ void run_iterations(float* __restrict__ sPX, float* _
                 if (MODE == MODE_COMPACT ? (i >= 0) : (i < RC)) {
                     const float wc = sW[PAD + i];
                     float npx, npy;
-                    if (MODE == MODE_FAST) {
+                    if (MODE == MODE_FAST || MODE == MODE_DENSE_IN) {
+                        const float tc = (MODE == MODE_FAST || (fl[j] & CF_ACT)) ? tau : 0.0f;
                         const float gx = sW[PAD + i + 1] - wc;
                         const float gy = sW[PAD + i + RX] - wc;
                         const float nn = __builtin_amdgcn_sqrtf(fmaf(gx, gx, gy * gy));
-                        const float m = __builtin_amdgcn_rcpf(fmaf(tau, nn, 1.0f));
-                        npx = fmaf(tau, gx, rpx[j]) * m;
-                        npy = fmaf(tau, gy, rpy[j]) * m;
+                        const float m = __builtin_amdgcn_rcpf(fmaf(tc, nn, 1.0f));
+                        npx = fmaf(tc, gx, rpx[j]) * m;
+                        npy = fmaf(tc, gy, rpy[j]) * m;
                     } else {
                         DualOut o = dual_update(rpx[j], rpy[j], wc, sW[PAD + i + 1],
                                                 sW[PAD + i + RX], fl[j], tau);
@@ -145,7 +149,7 @@ __device__ __forceinline__ void run_iterations(float* __restrict__ sPX, float* _
                 if (MODE == MODE_COMPACT ? (i >= 0) : (i < RC)) {
                     float dd = div_p(rpx[j], sPX[PAD + i - 1], rpy[j], sPY[PAD + i - RX]);
                     sW[PAD + i] = w_of(dd, rv[j], inv_theta,
-                                       MODE == MODE_DENSE ? (fl[j] & CF_ACT) != 0 : true);
+                                       (MODE == MODE_DENSE || MODE == MODE_DENSE_IN) ? (fl[j] & CF_ACT) != 0 : true);
                 }
             }
         } else {
@@ -170,7 +174,7 @@ __device__ __forceinline__ void run_iterations(float* __restrict__ sPX, float* _
                         if (write_u && (fl[j] & CF_OUT)) U[gi[j]] = u;
                     } else {
                         sW[PAD + i] = w_of(dd, rv[j], inv_theta,
-                                           MODE == MODE_DENSE ? (fl[j] & CF_ACT) != 0 : true);
+                                           (MODE == MODE_DENSE || MODE == MODE_DENSE_IN) ? (fl[j] & CF_ACT) != 0 : true);
                     }
                 }
             }
@@ -331,14 +335,23 @@ __global__ __launch_bounds__(NT) void k_iterate(ImgDesc d0, const ImgDesc* __res
         bool fast = false;
         if (FAST_OK) fast = __syncthreads_and(plain) != 0;
         else __syncthreads();
+        // does the region reach the grid's last column or row?
+        const bool edge = ox + RX >= W || oy + RY >= H;
         if (fast) {
             run_iterations<BX, BY, IT, NT, MODE_FAST, STOP>(sPX, sPY, sW, idx, rv, rpx, rpy, rc,
                                                             fl, gi, d.u, nit, write_u, theta,
                                                             inv_theta, tau, ru, check, dmax, inner);
         } else if (!COMPACT_OK) {
-            run_iterations<BX, BY, IT, NT, MODE_DENSE, STOP>(sPX, sPY, sW, idx, rv, rpx, rpy, rc,
-                                                             fl, gi, d.u, nit, write_u, theta,
-                                                             inv_theta, tau, ru, check, dmax, inner);
+            if (edge)
+                run_iterations<BX, BY, IT, NT, MODE_DENSE, STOP>(sPX, sPY, sW, idx, rv, rpx, rpy,
+                                                                 rc, fl, gi, d.u, nit, write_u,
+                                                                 theta, inv_theta, tau, ru,
+                                                                 check, dmax, inner);
+            else
+                run_iterations<BX, BY, IT, NT, MODE_DENSE_IN, STOP>(sPX, sPY, sW, idx, rv, rpx,
+                                                                    rpy, rc, fl, gi, d.u, nit,
+                                                                    write_u, theta, inv_theta,
+                                                                    tau, ru, check, dmax, inner);
         } else {
             // count the RD cells of the region (ascending list offsets)
             if (lane == 0) {
@@ -363,10 +376,15 @@ __global__ __launch_bounds__(NT) void k_iterate(ImgDesc d0, const ImgDesc* __res
             __syncthreads();
             const int n_act = sCnt[NCNT];
             if (5 * n_act >= 2 * RC) {   // dense enough: every region cell
-                run_iterations<BX, BY, IT, NT, MODE_DENSE, STOP>(sPX, sPY, sW, idx, rv, rpx, rpy,
-                                                                 rc, fl, gi, d.u, nit, write_u,
-                                                                 theta, inv_theta, tau, ru,
-                                                                 check, dmax, inner);
+                if (edge)
+                    run_iterations<BX, BY, IT, NT, MODE_DENSE, STOP>(sPX, sPY, sW, idx, rv, rpx,
+                                                                     rpy, rc, fl, gi, d.u, nit,
+                                                                     write_u, theta, inv_theta,
+                                                                     tau, ru, check, dmax, inner);
+                else
+                    run_iterations<BX, BY, IT, NT, MODE_DENSE_IN, STOP>(
+                        sPX, sPY, sW, idx, rv, rpx, rpy, rc, fl, gi, d.u, nit, write_u, theta,
+                        inv_theta, tau, ru, check, dmax, inner);
             } else {
                 const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
