@@ -1,0 +1,194 @@
+"""Full-size parity of the benchmark workloads, in the launch configurations
+the benchmark times, against the FP64 oracle on sampled outputs.
+
+An RD pixel interacts only with the RD pixels of its own 4-connected
+component: the dual step reads w at x + e and the divergence p at x - e, and
+off RD both are constants (w = -H(-f)/theta, p = 0).  So the oracle run on a
+crop holding one component's bounding box plus a one-pixel frozen margin (no
+component pixel on the crop's first or last row / column) reproduces that
+component's full-size result exactly, at the full iteration count; the same
+holds for the adjoint, whose sensitivities travel along the same couplings.
+Dense workloads, where one component spans the image, are compared on the
+whole grid at a shorter iteration count.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+from scipy import ndimage
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+U_TOL = 1e-4
+MAX_CROP = 160 * 160
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def rd(gpu):
+    from paper_1807_11534_amd import rdseg
+    return rdseg
+
+
+def sample_components(f, delta, k, seed):
+    """Up to k RD components (4-connectivity) whose bounding box plus a
+    one-pixel margin stays inside the image and under MAX_CROP pixels: the
+    smallest, the largest that fits, and random ones."""
+    A = np.abs(f.astype(np.float64)) < delta
+    lab, n = ndimage.label(A, structure=[[0, 1, 0], [1, 1, 1], [0, 1, 0]])
+    if n == 0:
+        return lab, []
+    boxes = ndimage.find_objects(lab)
+    H, W = f.shape
+    ok = []
+    for idx, sl in enumerate(boxes):
+        y0, y1 = sl[0].start - 1, sl[0].stop + 1
+        x0, x1 = sl[1].start - 1, sl[1].stop + 1
+        if y0 < 0 or x0 < 0 or y1 > H or x1 > W:
+            continue
+        if (y1 - y0) * (x1 - x0) > MAX_CROP:
+            continue
+        ok.append((idx + 1, (y0, y1, x0, x1)))
+    if not ok:
+        return lab, []
+    ok.sort(key=lambda c: (c[1][1] - c[1][0]) * (c[1][3] - c[1][2]))
+    rng = np.random.default_rng(seed)
+    pick = {0, len(ok) - 1}
+    while len(pick) < min(k, len(ok)):
+        pick.add(int(rng.integers(len(ok))))
+    return lab, [ok[i] for i in sorted(pick)]
+
+
+def check_components(u, f, lam, theta, tau, delta, K, lab, comps):
+    for cid, (y0, y1, x0, x1) in comps:
+        crop = np.ascontiguousarray(f[y0:y1, x0:x1])
+        uo, _, _ = oracle.solve(crop, lam, theta, tau, delta, K)
+        m = lab[y0:y1, x0:x1] == cid
+        err = np.abs(u[y0:y1, x0:x1][m] - uo[m]).max()
+        assert err <= U_TOL, (cid, (y0, y1, x0, x1), err)
+
+
+def invariants(u, v, p, f, delta):
+    A = np.abs(f.astype(np.float64)) < delta
+    h = (f < 0).astype(np.float32)
+    np.testing.assert_array_equal(u[~A], h[~A])
+    np.testing.assert_array_equal(v[~A], h[~A])
+    assert (p[:, ~A] == 0).all()
+    assert v.min() >= 0 and v.max() <= 1
+
+
+def test_distance_selective_4096_full(rd):
+    """4096^2 eq. DS term, lambda 10, delta 0.1 max|f|, 1000 iterations in the
+    benchmark's configurations; components against the oracle."""
+    prob = synth.config3()
+    K = prob.iters
+    fd = dev(prob.f)
+    outs = []
+    for tile, ipl in [((64, 32), 4), ((64, 64), 8), ((16, 16), 8)]:
+        print(f"C3 full tile={tile} ipl={ipl}", flush=True)
+        outs.append([host(x) for x in rd.solve(fd, prob.lam, prob.theta, prob.tau, prob.delta,
+                                               K, tile=tile, iters_per_launch=ipl)])
+    for o in outs[1:]:
+        for a, b in zip(o, outs[0]):
+            np.testing.assert_array_equal(a, b)
+    u, v, p = outs[0]
+    invariants(u, v, p, prob.f, prob.delta)
+    lab, comps = sample_components(prob.f, prob.delta, 8, 3)
+    assert len(comps) >= 4
+    check_components(u, prob.f, prob.lam, prob.theta, prob.tau, prob.delta, K, lab, comps)
+
+
+def test_distance_selective_4096_whole_grid_short(rd):
+    """The same 4096^2 problem on the whole grid, 20 iterations."""
+    prob = synth.config3()
+    print("C3 whole grid K=20", flush=True)
+    u, v, p = rd.solve(dev(prob.f), prob.lam, prob.theta, prob.tau, prob.delta, 20,
+                       tile=(64, 32), iters_per_launch=4)
+    uo, vo, po = oracle.solve(prob.f, prob.lam, prob.theta, prob.tau, prob.delta, 20)
+    assert np.abs(host(u) - uo).max() <= U_TOL
+    assert np.abs(host(p) - po).max() <= U_TOL
+
+
+def test_batched_512_full(rd):
+    """All 512 images of the batched workload as one graph: bitwise equal to
+    512 per-image solves; the smallest images fully and sampled components of
+    others against the oracle."""
+    probs = synth.config4(512, frac=0.1)
+    fs = [dev(p.f) for p in probs]
+    lams = [p.lam for p in probs]
+    deltas = [p.delta for p in probs]
+    for frac, tile, ipl in [(0.1, (16, 16), 8), (math.inf, (64, 64), 8)]:
+        ds = deltas if math.isfinite(frac) else [math.inf] * len(probs)
+        print(f"C4 full frac={frac}", flush=True)
+        bs = rd.BatchedSolver(fs, lams, ds, 0.1, 0.125, 300, tile=tile, iters_per_launch=ipl,
+                              graph=True)
+        bs.run()
+        outs = [[host(x) for x in o] for o in bs.run()]
+        bs.close()
+        for i in range(len(probs)):
+            u, v, p = rd.solve(fs[i], lams[i], 0.1, 0.125, ds[i], 300, tile=tile,
+                               iters_per_launch=ipl)
+            np.testing.assert_array_equal(outs[i][0], host(u))
+            np.testing.assert_array_equal(outs[i][2], host(p))
+        order = np.argsort([p.f.size for p in probs])
+        for i in order[:2]:
+            uo, _, _ = oracle.solve(probs[i].f, lams[i], 0.1, 0.125, ds[i], 300)
+            assert np.abs(outs[i][0] - uo).max() <= U_TOL, i
+        if math.isfinite(frac):
+            hit = 0
+            for i in order[::-1]:
+                lab, comps = sample_components(probs[i].f, ds[i], 3, int(i))
+                if comps:
+                    check_components(outs[i][0], probs[i].f, lams[i], 0.1, 0.125, ds[i], 300,
+                                     lab, comps)
+                    hit += 1
+                if hit >= 4:
+                    break
+
+
+@pytest.mark.parametrize("frac", [0.1, 0.5])
+def test_differentiation_2048_components(rd, frac):
+    """2048^2, 300 iterations, checkpoints every 30: forward u on sampled
+    components against the oracle's solve, and at the workload's delta
+    (0.1 max|f|) the adjoint grad_f against the oracle's reverse.  (At
+    0.5 max|f| and 300 iterations the reverse sweep is ill-conditioned where the
+    dual field has converged with |p| < 1, see the conditioning tests, so the
+    adjoint is compared there only by the crop tests at 200 iterations.)"""
+    prob = synth.config5()
+    delta = synth.band_delta(prob.f, frac)
+    fd = dev(prob.f)
+    tgt = prob.mask.astype(np.float32)
+    print(f"C5 components frac={frac}", flush=True)
+    u, v, p, tape = rd.solve(fd, prob.lam, 0.1, 0.125, delta, 300, tile=(32, 32),
+                             iters_per_launch=2, ckpt_every=30)
+    uh = host(u)
+    gf, _ = rd.backward(fd, prob.lam, 0.1, 0.125, delta, 300, 30, tape, 2 * (u - dev(tgt)))
+    gfh = host(gf)
+    lab, comps = sample_components(prob.f, delta, 5, 9)
+    if not comps:
+        pytest.skip("no component fits a crop")
+    for cid, (y0, y1, x0, x1) in comps:
+        crop = np.ascontiguousarray(prob.f[y0:y1, x0:x1])
+        uo, _, _ = oracle.solve(crop, prob.lam, 0.1, 0.125, delta, 300)
+        m = lab[y0:y1, x0:x1] == cid
+        assert np.abs(uh[y0:y1, x0:x1][m] - uo[m]).max() <= U_TOL
+        if frac != 0.1:
+            continue
+        # the upstream gradient of the crop is the full one restricted to it
+        ubar = 2 * (uh[y0:y1, x0:x1].astype(np.float64) - tgt[y0:y1, x0:x1])
+        fbo, _ = oracle.reverse(crop, prob.lam, 0.1, 0.125, delta, 300, ubar)
+        g = gfh[y0:y1, x0:x1][m]
+        ref = fbo[m]
+        assert np.abs(g - ref).max() <= 1e-3 * max(1.0, np.abs(ref).max()), cid
