@@ -4,15 +4,14 @@
 // gradient / divergence component, in the same operation order, so a volume of
 // identical slices reproduces the image solve bit for bit.
 //
-// One launch runs one dual step on 32 x 8 x 8 blocks (plus, at the end of an
-// outer iteration, the u-step and v-step).  The block loads its tile with a
-// halo of two voxels on the low side and one on the high side of every axis
-// into LDS (p) and registers (v, c, flags): the prologue's w is exact one voxel
-// inside the region, the dual step's p on the tile plus one low layer, which
-// the u-step's backward differences need.  Deeper temporal blocking would
-// multiply the halo volume, so the kernel streams its 36 bytes per voxel
-// (read c, v, p: 20; write v, p: 16) from HBM.  Tiles without a voxel of RD
-// return at once (flags computed once per solve).
+// One launch runs one dual step (plus, at the end of an outer iteration, the
+// u-step and v-step) with one workgroup per 32 x 16 column tile and chunk of 32
+// planes, streamed along z (see k_stream3): the x-y halo is two voxels on the
+// low side and one on the high side, the z neighbours pass from one plane to
+// the next in registers.  Deeper temporal blocking would multiply the halo
+// volume, so the kernel streams its 36 bytes per voxel (read c, v, p: 20;
+// write v, p: 16) from HBM.  Tiles without a voxel of RD return at once (flags
+// computed once per solve).
 #include <algorithm>
 
 #include "rdseg_internal.h"
@@ -20,8 +19,6 @@
 namespace rdseg {
 
 namespace {
-
-constexpr uint32_t CF_LASTZ = 16u;
 
 __device__ __forceinline__ float div_p3(float pxc, float pxl, float pyc, float pyu, float pzc,
                                         float pzd) {
@@ -74,138 +71,185 @@ __global__ __launch_bounds__(256) void k_tile_flags3(VolDesc d, int bx, int by, 
     if (threadIdx.x == 0) flags[t] = any;
 }
 
-template <int BX, int BY, int BZ, int NT>
-__global__ __launch_bounds__(NT) void k_iterate3(VolDesc d, const int32_t* __restrict__ flags,
-                                                 int in_buf, int uv, int write_u, float theta,
-                                                 float inv_theta, float tau) {
-    constexpr int H0 = 2;   // low-side halo; high side 1
-    constexpr int RX = BX + 3, RY = BY + 3, RZ = BZ + 3;
-    constexpr int RS = RX * RY;             // region slice
-    constexpr int RC = RS * RZ;
-    constexpr int CPT = (RC + NT - 1) / NT;
-    constexpr int PAD = RS + RX + 1;        // largest neighbour offset, both ends
-    constexpr int LS = RC + 2 * PAD;
-    __shared__ float sPX[LS], sPY[LS], sPZ[LS], sW[LS];
+// One dual step (and, at the end of an outer iteration, the u/v step) on a
+// BX x BY column tile over ZC planes, streamed plane by plane.  Step s loads
+// plane s, forms w(s), then finishes plane s - 1: its dual step (w of planes
+// s - 1 and s), then its u/v step (the new p of planes s - 1 and s - 2).  The
+// z neighbours travel in registers from one step to the next; only the x-y
+// neighbours go through LDS, so the halo is x-y only (2 low, 1 high) and the
+// z halo is the two planes below the chunk and one above.
+template <int BX, int BY, int ZC, int NT>
+__global__ __launch_bounds__(NT) void k_stream3(VolDesc d, const int32_t* __restrict__ flags,
+                                                int in_buf, int uv, int write_u, float theta,
+                                                float inv_theta, float tau) {
+    constexpr int RX = BX + 3, RY = BY + 3, RS = RX * RY;   // plane region
+    constexpr int CPT = (RS + NT - 1) / NT;
+    constexpr int PAD = RX + 1;
+    constexpr int LS = RS + 2 * PAD;
+    constexpr uint32_t XY_IN = 32u, XY_OUT = 64u;   // in the grid / in the tile
+    __shared__ float sPX[LS], sPY[LS];    // old p of plane s (x-y divergence of w(s))
+    __shared__ float sW[2][LS];           // w of planes s - 1 and s
+    __shared__ float sNX[LS], sNY[LS];    // new p of plane s - 1
 
-    const int t = blockIdx.x;
-    if (!flags[t]) return;
+    // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
+    // contiguous run of tiles so that x and y neighbours, which fetch each
+    // other's halo lines, share that XCD's L2.
     const int ntx = (d.W + BX - 1) / BX, nty = (d.H + BY - 1) / BY;
-    const int tz = t / (ntx * nty), rt = t - tz * ntx * nty;
+    const int ntz = (d.D + ZC - 1) / ZC;
+    const int n_tiles = ntx * nty * ntz;
+    const int per_xcd = (n_tiles + 7) >> 3;
+    const int tb = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+    if (tb >= n_tiles || !flags[tb]) return;
+    const int tz = tb / (ntx * nty), rt = tb - tz * ntx * nty;
     const int ty = rt / ntx, tx = rt - ty * ntx;
-    const int ox = tx * BX - H0, oy = ty * BY - H0, oz = tz * BZ - H0;
-    const int th = threadIdx.x;
-    for (int k = th; k < PAD; k += NT) {
-        sPX[k] = 0.0f; sPY[k] = 0.0f; sPZ[k] = 0.0f; sW[k] = 0.0f;
-        sPX[PAD + RC + k] = 0.0f; sPY[PAD + RC + k] = 0.0f;
-        sPZ[PAD + RC + k] = 0.0f; sW[PAD + RC + k] = 0.0f;
+    const int ox = tx * BX - 2, oy = ty * BY - 2;
+    const int z0 = tz * ZC, z1 = min(z0 + ZC, d.D);
+    const int t = threadIdx.x;
+    for (int k = t; k < PAD; k += NT) {
+        sPX[k] = 0.0f; sPY[k] = 0.0f; sW[0][k] = 0.0f; sW[1][k] = 0.0f;
+        sNX[k] = 0.0f; sNY[k] = 0.0f;
+        sPX[PAD + RS + k] = 0.0f; sPY[PAD + RS + k] = 0.0f; sW[0][PAD + RS + k] = 0.0f;
+        sW[1][PAD + RS + k] = 0.0f; sNX[PAD + RS + k] = 0.0f; sNY[PAD + RS + k] = 0.0f;
     }
     const float* __restrict__ Vi = d.st[in_buf][0];
     const float* __restrict__ PXi = d.st[in_buf][1];
     const float* __restrict__ PYi = d.st[in_buf][2];
     const float* __restrict__ PZi = d.st[in_buf][3];
-
-    float rv[CPT], rpx[CPT], rpy[CPT], rpz[CPT], rc[CPT];
-    uint32_t fl[CPT];
-    int gi[CPT];
-#pragma unroll
-    for (int j = 0; j < CPT; ++j) {
-        const int i = th + j * NT;
-        rv[j] = 0.0f; rpx[j] = 0.0f; rpy[j] = 0.0f; rpz[j] = 0.0f; rc[j] = __builtin_inff();
-        fl[j] = 0u; gi[j] = 0;
-        if (i < RC) {
-            const int rz = i / RS, rr = i - rz * RS;
-            const int ry = rr / RX, rx = rr - ry * RX;
-            const int gx = ox + rx, gy = oy + ry, gz = oz + rz;
-            const bool inb = (unsigned)gx < (unsigned)d.W && (unsigned)gy < (unsigned)d.H &&
-                             (unsigned)gz < (unsigned)d.D;
-            const int g = gz * d.lds + gy * d.ld + gx;
-            gi[j] = g;
-            float c = __builtin_inff(), v = 0.0f, px = 0.0f, py = 0.0f, pz = 0.0f;
-            if (inb) {   // issued together; state off RD is discarded below
-                c = d.c[g];
-                v = Vi[g];
-                px = PXi[g];
-                py = PYi[g];
-                pz = PZi[g];
-            }
-            const bool act = c_active(c);
-            rc[j] = c;
-            rv[j] = act ? v : heav_from_c(c);
-            rpx[j] = act ? px : 0.0f;
-            rpy[j] = act ? py : 0.0f;
-            rpz[j] = act ? pz : 0.0f;
-            uint32_t f = act ? CF_ACT : 0u;
-            if (gx == d.W - 1) f |= CF_LASTC;
-            if (gy == d.H - 1) f |= CF_LASTR;
-            if (gz == d.D - 1) f |= CF_LASTZ;
-            const bool interior = rx >= H0 && rx < H0 + BX && ry >= H0 && ry < H0 + BY &&
-                                  rz >= H0 && rz < H0 + BZ;
-            if (interior && act) f |= CF_OUT;
-            fl[j] = f;
-            sPX[PAD + i] = rpx[j];
-            sPY[PAD + i] = rpy[j];
-            sPZ[PAD + i] = rpz[j];
-        }
-    }
-    __syncthreads();
-    // w = div p - v/theta on RD, -H(-f)/theta off RD
-#pragma unroll
-    for (int j = 0; j < CPT; ++j) {
-        const int i = th + j * NT;
-        if (i < RC) {
-            const float dd = div_p3(rpx[j], sPX[PAD + i - 1], rpy[j], sPY[PAD + i - RX], rpz[j],
-                                    sPZ[PAD + i - RS]);
-            sW[PAD + i] = w_of(dd, rv[j], inv_theta, (fl[j] & CF_ACT) != 0);
-        }
-    }
-    __syncthreads();
-    // dual step
-#pragma unroll
-    for (int j = 0; j < CPT; ++j) {
-        const int i = th + j * NT;
-        if (i < RC) {
-            const float wc = sW[PAD + i];
-            const float gx = (fl[j] & CF_LASTC) ? 0.0f : (sW[PAD + i + 1] - wc);
-            const float gy = (fl[j] & CF_LASTR) ? 0.0f : (sW[PAD + i + RX] - wc);
-            const float gz = (fl[j] & CF_LASTZ) ? 0.0f : (sW[PAD + i + RS] - wc);
-            const float nn = __builtin_amdgcn_sqrtf(fmaf(gx, gx, fmaf(gy, gy, gz * gz)));
-            const float m = __builtin_amdgcn_rcpf(fmaf(tau, nn, 1.0f));
-            const bool act = (fl[j] & CF_ACT) != 0;
-            rpx[j] = act ? fmaf(tau, gx, rpx[j]) * m : 0.0f;
-            rpy[j] = act ? fmaf(tau, gy, rpy[j]) * m : 0.0f;
-            rpz[j] = act ? fmaf(tau, gz, rpz[j]) * m : 0.0f;
-            sPX[PAD + i] = rpx[j];
-            sPY[PAD + i] = rpy[j];
-            sPZ[PAD + i] = rpz[j];
-        }
-    }
-    __syncthreads();
-    // u-step and v-step at the end of an outer iteration; write the tile
     float* __restrict__ Vo = d.st[1 - in_buf][0];
     float* __restrict__ PXo = d.st[1 - in_buf][1];
     float* __restrict__ PYo = d.st[1 - in_buf][2];
     float* __restrict__ PZo = d.st[1 - in_buf][3];
+
+    int gxy[CPT];
+    uint32_t fxy[CPT];
+    // plane s - 1: old state, its w, and the new p_z of plane s - 2
+    float c1[CPT], v1[CPT], px1[CPT], py1[CPT], pz1[CPT], w1[CPT], pzn2[CPT];
 #pragma unroll
     for (int j = 0; j < CPT; ++j) {
-        const int i = th + j * NT;
-        if (i < RC && (fl[j] & CF_OUT)) {
-            float vn = rv[j];
-            if (uv) {
-                const float dd = div_p3(rpx[j], sPX[PAD + i - 1], rpy[j], sPY[PAD + i - RX],
-                                        rpz[j], sPZ[PAD + i - RS]);
-                const float u = u_step(rv[j], dd, theta);
-                vn = v_step(u, rc[j]);
-                if (write_u) d.u[gi[j]] = u;
-            }
-            Vo[gi[j]] = vn;
-            PXo[gi[j]] = rpx[j];
-            PYo[gi[j]] = rpy[j];
-            PZo[gi[j]] = rpz[j];
+        const int i = t + j * NT;
+        const int ry = i / RX, rx = i - ry * RX;
+        const int gx = ox + rx, gy = oy + ry;
+        uint32_t f = 0u;
+        if (i < RS && (unsigned)gx < (unsigned)d.W && (unsigned)gy < (unsigned)d.H) {
+            f |= XY_IN;
+            if (gx == d.W - 1) f |= CF_LASTC;
+            if (gy == d.H - 1) f |= CF_LASTR;
+            if (rx >= 2 && rx < 2 + BX && ry >= 2 && ry < 2 + BY) f |= XY_OUT;
         }
+        fxy[j] = f;
+        gxy[j] = gy * d.ld + gx;
+        c1[j] = __builtin_inff(); v1[j] = 0.0f; px1[j] = 0.0f; py1[j] = 0.0f; pz1[j] = 0.0f;
+        w1[j] = 0.0f; pzn2[j] = 0.0f;
+    }
+    // raw loads of the next plane, issued one step ahead so that their
+    // latency overlaps the three phases of the current plane
+    float lc[CPT], lv[CPT], lpx[CPT], lpy[CPT], lpz[CPT];
+    auto fetch = [&](int z) {
+        const bool zin = z >= 0 && z < d.D;
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) {
+            lc[j] = __builtin_inff(); lv[j] = 0.0f; lpx[j] = 0.0f; lpy[j] = 0.0f; lpz[j] = 0.0f;
+            if (zin && (fxy[j] & XY_IN)) {   // state off RD is discarded after use
+                const int g = z * d.lds + gxy[j];
+                lc[j] = d.c[g];
+                lv[j] = Vi[g];
+                lpx[j] = PXi[g];
+                lpy[j] = PYi[g];
+                lpz[j] = PZi[g];
+            }
+        }
+    };
+    fetch(z0 - 2);
+    int cur = 0;
+    for (int s = z0 - 2; s <= z1; ++s) {
+        float c0[CPT], v0[CPT], px0[CPT], py0[CPT], pz0[CPT], w0[CPT];
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) {
+            const float c = lc[j];
+            const bool act = c_active(c);
+            c0[j] = c;
+            v0[j] = act ? lv[j] : heav_from_c(c);
+            px0[j] = act ? lpx[j] : 0.0f;
+            py0[j] = act ? lpy[j] : 0.0f;
+            pz0[j] = act ? lpz[j] : 0.0f;
+        }
+        if (s < z1) fetch(s + 1);
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) {
+            const int i = t + j * NT;
+            if (i < RS) {
+                sPX[PAD + i] = px0[j];
+                sPY[PAD + i] = py0[j];
+            }
+        }
+        __syncthreads();
+        // w(s) = div p - v/theta on RD, -H(-f)/theta off RD
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) {
+            const int i = t + j * NT;
+            if (i < RS) {
+                const float dd = div_p3(px0[j], sPX[PAD + i - 1], py0[j], sPY[PAD + i - RX],
+                                        pz0[j], pz1[j]);
+                w0[j] = w_of(dd, v0[j], inv_theta, c_active(c0[j]));
+                sW[cur][PAD + i] = w0[j];
+            }
+        }
+        __syncthreads();
+        // dual step of plane s - 1 (from w of planes s - 1 and s)
+        float pxn[CPT], pyn[CPT], pzn[CPT];
+        const bool lastz = s - 1 == d.D - 1;
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) {
+            const int i = t + j * NT;
+            pxn[j] = 0.0f; pyn[j] = 0.0f; pzn[j] = 0.0f;
+            if (i < RS && s - 1 >= z0 - 1) {
+                const float wc = w1[j];
+                const float gx = (fxy[j] & CF_LASTC) ? 0.0f : (sW[cur ^ 1][PAD + i + 1] - wc);
+                const float gy = (fxy[j] & CF_LASTR) ? 0.0f : (sW[cur ^ 1][PAD + i + RX] - wc);
+                const float gz = lastz ? 0.0f : (w0[j] - wc);
+                const float nn = __builtin_amdgcn_sqrtf(fmaf(gx, gx, fmaf(gy, gy, gz * gz)));
+                const float m = __builtin_amdgcn_rcpf(fmaf(tau, nn, 1.0f));
+                const bool act = c_active(c1[j]);
+                pxn[j] = act ? fmaf(tau, gx, px1[j]) * m : 0.0f;
+                pyn[j] = act ? fmaf(tau, gy, py1[j]) * m : 0.0f;
+                pzn[j] = act ? fmaf(tau, gz, pz1[j]) * m : 0.0f;
+                sNX[PAD + i] = pxn[j];
+                sNY[PAD + i] = pyn[j];
+            }
+        }
+        __syncthreads();
+        // u-step and v-step of plane s - 1, then its tile voxels are written
+        if (s - 1 >= z0) {
+#pragma unroll
+            for (int j = 0; j < CPT; ++j) {
+                const int i = t + j * NT;
+                if (i < RS && (fxy[j] & XY_OUT) && c_active(c1[j])) {
+                    float vn = v1[j];
+                    const int g = (s - 1) * d.lds + gxy[j];
+                    if (uv) {
+                        const float dd = div_p3(pxn[j], sNX[PAD + i - 1], pyn[j],
+                                                sNY[PAD + i - RX], pzn[j], pzn2[j]);
+                        const float u = u_step(v1[j], dd, theta);
+                        vn = v_step(u, c1[j]);
+                        if (write_u) d.u[g] = u;
+                    }
+                    Vo[g] = vn;
+                    PXo[g] = pxn[j];
+                    PYo[g] = pyn[j];
+                    PZo[g] = pzn[j];
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) {
+            c1[j] = c0[j]; v1[j] = v0[j]; px1[j] = px0[j]; py1[j] = py0[j]; pz1[j] = pz0[j];
+            w1[j] = w0[j]; pzn2[j] = pzn[j];
+        }
+        cur ^= 1;
     }
 }
 
-constexpr int kVBX = 32, kVBY = 8, kVBZ = 8, kVNT = 512;
+constexpr int kVBX = 32, kVBY = 16, kVBZ = 32, kVNT = 256;
 
 }  // namespace
 
@@ -232,7 +276,8 @@ int launch_tile_flags3(const VolDesc& d, int64_t n_tiles, int32_t* flags, hipStr
 
 int launch_iterate3(const VolDesc& d, const int32_t* flags, int64_t n_tiles, int in_buf, bool uv,
                     bool write_u, float theta, float inv_theta, float tau, hipStream_t st) {
-    hipLaunchKernelGGL((k_iterate3<kVBX, kVBY, kVBZ, kVNT>), dim3((unsigned)n_tiles), dim3(kVNT),
+    hipLaunchKernelGGL((k_stream3<kVBX, kVBY, kVBZ, kVNT>), dim3((unsigned)((n_tiles + 7) / 8 * 8)),
+                       dim3(kVNT),
                        0, st, d, flags, in_buf, uv ? 1 : 0, write_u ? 1 : 0, theta, inv_theta,
                        tau);
     RDSEG_HIP_CHECK(hipGetLastError());
