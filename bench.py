@@ -54,6 +54,10 @@ def parse():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--tune", default="auto", choices=["auto", "fixed"],
                     help="auto: autotune each case; fixed: 64x64 tiles, 4 iterations/launch")
+    ap.add_argument("--extras", default="all",
+                    help="comma-separated subset of the extra workloads: " + ", ".join(EXTRAS))
+    ap.add_argument("--extras-only", action="store_true",
+                    help="run only the selected extra workloads and print their JSON")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy a MIB-sized buffer with torch (counter calibration)")
     return ap.parse_args()
@@ -139,128 +143,137 @@ def protocol(torch, rdseg, synth, dev):
     return out
 
 
-def extras(torch, rdseg, synth, dev):
+EXTRAS = ("batched", "adjoint", "protocol", "primal_dual", "volume", "ds_4096")
+
+
+def extras(torch, rdseg, synth, dev, which=EXTRAS):
     out = {}
-    # ---- batched workload: 512 images, sides 64..1024, 300 iterations
-    log("extras: generating the batched workload")
-    probs = synth.config4(512, frac=0.1)
-    for frac, name in [(0.1, "batched_512"), (math.inf, "batched_512_delta_inf")]:
-        log(f"extras: {name}")
-        fs = [torch.from_numpy(p.f).to(dev) for p in probs]
-        lams = [p.lam for p in probs]
-        deltas = [p.delta if math.isfinite(frac) else math.inf for p in probs]
-        n_px = sum(p.f.size for p in probs)
-        q = sum(float((np.abs(p.f.astype(np.float64)) < d).sum())
-                for p, d in zip(probs, deltas)) / n_px
-        tile, ipl = ((64, 64), 8) if not math.isfinite(frac) else ((16, 16), 8)
-        bs = rdseg.BatchedSolver(fs, lams, deltas, synth.THETA, synth.TAU, 300, tile=tile,
-                                 iters_per_launch=ipl, graph=True)
-        bs.run()
-        t_graph = timed(torch, bs.run, 2)
-        outs = [tuple(t.clone() for t in o) for o in bs.out]
-        seq_out = [tuple(torch.empty_like(t) for t in o) for o in bs.out]
-        wss = [rdseg.workspace(rdseg.shape_of(f)) for f in fs]
+    if "batched" in which:
+        # ---- batched workload: 512 images, sides 64..1024, 300 iterations
+        log("extras: generating the batched workload")
+        probs = synth.config4(512, frac=0.1)
+        for frac, name in [(0.1, "batched_512"), (math.inf, "batched_512_delta_inf")]:
+            log(f"extras: {name}")
+            fs = [torch.from_numpy(p.f).to(dev) for p in probs]
+            lams = [p.lam for p in probs]
+            deltas = [p.delta if math.isfinite(frac) else math.inf for p in probs]
+            n_px = sum(p.f.size for p in probs)
+            q = sum(float((np.abs(p.f.astype(np.float64)) < d).sum())
+                    for p, d in zip(probs, deltas)) / n_px
+            tile, ipl = ((64, 64), 8) if not math.isfinite(frac) else ((16, 16), 8)
+            bs = rdseg.BatchedSolver(fs, lams, deltas, synth.THETA, synth.TAU, 300, tile=tile,
+                                     iters_per_launch=ipl, graph=True)
+            bs.run()
+            t_graph = timed(torch, bs.run, 2)
+            outs = [tuple(t.clone() for t in o) for o in bs.out]
+            seq_out = [tuple(torch.empty_like(t) for t in o) for o in bs.out]
+            wss = [rdseg.workspace(rdseg.shape_of(f)) for f in fs]
 
-        def sequential():
-            for i, f in enumerate(fs):
-                rdseg.solve(f, lams[i], synth.THETA, synth.TAU, deltas[i], 300, tile=tile,
-                            iters_per_launch=ipl, out=seq_out[i], ws=wss[i])
+            def sequential():
+                for i, f in enumerate(fs):
+                    rdseg.solve(f, lams[i], synth.THETA, synth.TAU, deltas[i], 300, tile=tile,
+                                iters_per_launch=ipl, out=seq_out[i], ws=wss[i])
 
-        sequential()
-        t_seq = timed(torch, sequential, 1)
-        same = all(torch.equal(a[0], b[0]) for a, b in zip(outs, seq_out))
-        upd = q * n_px * 300
-        out[name] = dict(images=512, pixels=n_px, active_fraction=q, iters=300,
-                         tile=list(tile), iters_per_launch=ipl,
-                         graph_ms=t_graph, sequential_ms=t_seq, speedup=t_seq / t_graph,
-                         updates_per_s=upd / (t_graph * 1e-3),
-                         bitwise_equal_to_sequential=bool(same))
-        bs.close()
-        del fs, outs, seq_out, wss, bs
+            sequential()
+            t_seq = timed(torch, sequential, 1)
+            same = all(torch.equal(a[0], b[0]) for a, b in zip(outs, seq_out))
+            upd = q * n_px * 300
+            out[name] = dict(images=512, pixels=n_px, active_fraction=q, iters=300,
+                             tile=list(tile), iters_per_launch=ipl,
+                             graph_ms=t_graph, sequential_ms=t_seq, speedup=t_seq / t_graph,
+                             updates_per_s=upd / (t_graph * 1e-3),
+                             bitwise_equal_to_sequential=bool(same))
+            bs.close()
+            del fs, outs, seq_out, wss, bs
+            torch.cuda.empty_cache()
+    if "adjoint" in which:
+        # ---- differentiation workload: 2048^2, 300 iterations, checkpoints every 30
+        prob = synth.config5()
+        f = torch.from_numpy(prob.f).to(dev)
+        tgt = torch.from_numpy(prob.mask.astype(np.float32)).to(dev)
+        for frac, name in [(0.1, "fwd_adjoint_2048"), (0.5, "fwd_adjoint_2048_delta_0.5")]:
+            log(f"extras: {name}")
+            delta = synth.band_delta(prob.f, frac)
+            q = float((np.abs(prob.f.astype(np.float64)) < delta).mean())
+
+            def fwd_bwd():
+                u, v, p, tape = rdseg.solve(f, prob.lam, synth.THETA, synth.TAU, delta, 300,
+                                            tile=(32, 32), iters_per_launch=2, ckpt_every=30)
+                rdseg.backward(f, prob.lam, synth.THETA, synth.TAU, delta, 300, 30, tape,
+                               2 * (u - tgt))
+
+            def fwd_only():
+                rdseg.solve(f, prob.lam, synth.THETA, synth.TAU, delta, 300, tile=(32, 32),
+                            iters_per_launch=2)
+
+            fwd_bwd()
+            t_fb = timed(torch, fwd_bwd, 3)
+            fwd_only()
+            t_f = timed(torch, fwd_only, 3)
+            out[name] = dict(size=2048, iters=300, ckpt_every=30, active_fraction=q,
+                             fwd_adjoint_ms=t_fb, forward_ms=t_f)
+        del f, tgt
+    if "protocol" in which:
+        out["paper_protocol_128"] = protocol(torch, rdseg, synth, dev)
+    if "primal_dual" in which:
+        # ---- restricted primal-dual solve of eq. CR on the 1024^2 sweep image
+        prob = synth.config2(1, 1024, 500)
+        f = torch.from_numpy(prob.f).to(dev)
+        for frac, name in [(math.inf, "primal_dual_1024_delta_inf"),
+                           (0.5, "primal_dual_1024_delta_0.5")]:
+            log(f"extras: {name}")
+            delta = synth.band_delta(prob.f, frac)
+            q = float((np.abs(prob.f.astype(np.float64)) < delta).mean())
+            outp = (torch.empty_like(f), torch.empty((2,) + tuple(f.shape), dtype=torch.float32,
+                                                     device=dev))
+            wsp = torch.empty(rdseg._lib.load().rdseg_pd_workspace_size(
+                rdseg.ctypes.byref(rdseg.shape_of(f))), dtype=torch.uint8, device=dev)
+            run = lambda: rdseg.solve_pd(f, prob.lam, delta, 500, out=outp, ws=wsp)
+            run()
+            t = timed(torch, run, 3)
+            upd = q * prob.f.size * 500
+            out[name] = dict(size=1024, iters=500, active_fraction=q, ms=t,
+                             updates_per_s=upd / (t * 1e-3),
+                             alg_gbs=36.0 * upd / (t * 1e-3) / 1e9)
+            del outp, wsp
+        del f
+    if "volume" in which:
+        # ---- 256^3 volume (7-point stencil), 100 iterations
+        prob = synth.config_volume(256)
+        f = torch.from_numpy(prob.f).to(dev)
+        for frac, name in [(math.inf, "volume_256_delta_inf"), (0.2, "volume_256_delta_0.2")]:
+            log(f"extras: {name}")
+            delta = synth.band_delta(prob.f, frac)
+            q = float((np.abs(prob.f.astype(np.float64)) < delta).mean())
+            out3 = (torch.empty_like(f), torch.empty_like(f),
+                    torch.empty((3,) + tuple(f.shape), dtype=torch.float32, device=dev))
+            ws = torch.empty(rdseg._lib.load().rdseg_workspace_size3(
+                rdseg.ctypes.byref(rdseg.shape3_of(f))), dtype=torch.uint8, device=dev)
+            run = lambda: rdseg.solve3d(f, prob.lam, synth.THETA, synth.TAU3, delta, 100, out=out3,
+                                        ws=ws)
+            run()
+            t = timed(torch, run, 3)
+            upd = q * prob.f.size * 100
+            out[name] = dict(size=[256, 256, 256], iters=100, active_fraction=q, ms=t,
+                             updates_per_s=upd / (t * 1e-3),
+                             alg_gbs=36.0 * upd / (t * 1e-3) / 1e9)
+            del ws, out3
+        del f
         torch.cuda.empty_cache()
-    # ---- differentiation workload: 2048^2, 300 iterations, checkpoints every 30
-    prob = synth.config5()
-    f = torch.from_numpy(prob.f).to(dev)
-    tgt = torch.from_numpy(prob.mask.astype(np.float32)).to(dev)
-    for frac, name in [(0.1, "fwd_adjoint_2048"), (0.5, "fwd_adjoint_2048_delta_0.5")]:
-        log(f"extras: {name}")
-        delta = synth.band_delta(prob.f, frac)
-        q = float((np.abs(prob.f.astype(np.float64)) < delta).mean())
-
-        def fwd_bwd():
-            u, v, p, tape = rdseg.solve(f, prob.lam, synth.THETA, synth.TAU, delta, 300,
-                                        tile=(32, 32), iters_per_launch=2, ckpt_every=30)
-            rdseg.backward(f, prob.lam, synth.THETA, synth.TAU, delta, 300, 30, tape,
-                           2 * (u - tgt))
-
-        def fwd_only():
-            rdseg.solve(f, prob.lam, synth.THETA, synth.TAU, delta, 300, tile=(32, 32),
-                        iters_per_launch=2)
-
-        fwd_bwd()
-        t_fb = timed(torch, fwd_bwd, 3)
-        fwd_only()
-        t_f = timed(torch, fwd_only, 3)
-        out[name] = dict(size=2048, iters=300, ckpt_every=30, active_fraction=q,
-                         fwd_adjoint_ms=t_fb, forward_ms=t_f)
-    del f, tgt
-    out["paper_protocol_128"] = protocol(torch, rdseg, synth, dev)
-    # ---- restricted primal-dual solve of eq. CR on the 1024^2 sweep image
-    prob = synth.config2(1, 1024, 500)
-    f = torch.from_numpy(prob.f).to(dev)
-    for frac, name in [(math.inf, "primal_dual_1024_delta_inf"),
-                       (0.5, "primal_dual_1024_delta_0.5")]:
-        log(f"extras: {name}")
-        delta = synth.band_delta(prob.f, frac)
-        q = float((np.abs(prob.f.astype(np.float64)) < delta).mean())
-        outp = (torch.empty_like(f), torch.empty((2,) + tuple(f.shape), dtype=torch.float32,
-                                                 device=dev))
-        wsp = torch.empty(rdseg._lib.load().rdseg_pd_workspace_size(
-            rdseg.ctypes.byref(rdseg.shape_of(f))), dtype=torch.uint8, device=dev)
-        run = lambda: rdseg.solve_pd(f, prob.lam, delta, 500, out=outp, ws=wsp)
+    if "ds_4096" in which:
+        # ---- 4096^2 distance-selective solve, delta 0.1 max|f|, 1000 iterations
+        log("extras: ds_4096")
+        prob = synth.config3()
+        f = torch.from_numpy(prob.f).to(dev)
+        q = float((np.abs(prob.f.astype(np.float64)) < prob.delta).mean())
+        tile, ipl = rdseg.autotune(f, prob.lam, synth.THETA, synth.TAU, prob.delta, 200)
+        run = lambda: rdseg.solve(f, prob.lam, synth.THETA, synth.TAU, prob.delta, 1000, tile=tile,
+                                  iters_per_launch=ipl)
         run()
-        t = timed(torch, run, 3)
-        upd = q * prob.f.size * 500
-        out[name] = dict(size=1024, iters=500, active_fraction=q, ms=t,
-                         updates_per_s=upd / (t * 1e-3),
-                         alg_gbs=36.0 * upd / (t * 1e-3) / 1e9)
-        del outp, wsp
-    del f
-    # ---- 256^3 volume (7-point stencil), 100 iterations
-    prob = synth.config_volume(256)
-    f = torch.from_numpy(prob.f).to(dev)
-    for frac, name in [(math.inf, "volume_256_delta_inf"), (0.2, "volume_256_delta_0.2")]:
-        log(f"extras: {name}")
-        delta = synth.band_delta(prob.f, frac)
-        q = float((np.abs(prob.f.astype(np.float64)) < delta).mean())
-        out3 = (torch.empty_like(f), torch.empty_like(f),
-                torch.empty((3,) + tuple(f.shape), dtype=torch.float32, device=dev))
-        ws = torch.empty(rdseg._lib.load().rdseg_workspace_size3(
-            rdseg.ctypes.byref(rdseg.shape3_of(f))), dtype=torch.uint8, device=dev)
-        run = lambda: rdseg.solve3d(f, prob.lam, synth.THETA, synth.TAU3, delta, 100, out=out3,
-                                    ws=ws)
-        run()
-        t = timed(torch, run, 3)
-        upd = q * prob.f.size * 100
-        out[name] = dict(size=[256, 256, 256], iters=100, active_fraction=q, ms=t,
-                         updates_per_s=upd / (t * 1e-3),
-                         alg_gbs=36.0 * upd / (t * 1e-3) / 1e9)
-        del ws, out3
-    del f
-    torch.cuda.empty_cache()
-    # ---- 4096^2 distance-selective solve, delta 0.1 max|f|, 1000 iterations
-    log("extras: ds_4096")
-    prob = synth.config3()
-    f = torch.from_numpy(prob.f).to(dev)
-    q = float((np.abs(prob.f.astype(np.float64)) < prob.delta).mean())
-    tile, ipl = rdseg.autotune(f, prob.lam, synth.THETA, synth.TAU, prob.delta, 200)
-    run = lambda: rdseg.solve(f, prob.lam, synth.THETA, synth.TAU, prob.delta, 1000, tile=tile,
-                              iters_per_launch=ipl)
-    run()
-    t = timed(torch, run, 2)
-    out["ds_4096"] = dict(size=4096, iters=1000, active_fraction=q, ms=t, tile=list(tile),
-                          iters_per_launch=ipl,
-                          updates_per_s=q * prob.f.size * 1000 / (t * 1e-3))
+        t = timed(torch, run, 2)
+        out["ds_4096"] = dict(size=4096, iters=1000, active_fraction=q, ms=t, tile=list(tile),
+                              iters_per_launch=ipl,
+                              updates_per_s=q * prob.f.size * 1000 / (t * 1e-3))
     return out
 
 
@@ -284,6 +297,14 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+    which = EXTRAS if args.extras == "all" else tuple(x.strip() for x in args.extras.split(","))
+    unknown = [x for x in which if x not in EXTRAS]
+    if unknown:
+        print(f"unknown extra workloads: {unknown}; choose from {EXTRAS}", file=sys.stderr)
+        sys.exit(2)
+    if args.extras_only:
+        print(json.dumps(dict(extras=extras(torch, rdseg, synth, dev, which))), flush=True)
+        return
     log("sweep: generating and tuning")
     probs, cases = sweep_cases(torch, rdseg, synth, args, dev)
 
@@ -352,7 +373,7 @@ def main():
 
     ext = None
     if not args.no_extras:
-        ext = extras(torch, rdseg, synth, dev)
+        ext = extras(torch, rdseg, synth, dev, which)
 
     cpu = None
     if not args.no_cpu:
