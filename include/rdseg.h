@@ -340,10 +340,13 @@ rdseg_status rdseg_fit_backward(const rdseg_fit* fit, rdseg_shape s, const float
 /* ---------------------------------------------------------------------- */
 
 /* Times every compiled (tile_w, tile_h, iters_per_launch) configuration on
- * this problem for `probe_iters` iterations (synchronous), stores the fastest
- * in the process-wide cache under (shape class, active-fraction bucket), and
- * returns it.  u, v, p, ws as for rdseg_solve (their contents are
- * overwritten). */
+ * this problem for `probe_iters` iterations (synchronous) and returns the
+ * fastest.  A nonzero prm->tile_w, tile_h or iters_per_launch fixes that
+ * parameter (only matching configurations are timed; RDSEG_ERR_ARG if none is
+ * compiled); with all three zero the result is also stored in the
+ * process-wide cache under (shape class, active-fraction bucket) that solves
+ * with tile_w = tile_h = iters_per_launch = 0 read.  u, v, p, ws as for
+ * rdseg_solve (their contents are overwritten). */
 rdseg_status rdseg_autotune(const float* f, rdseg_shape s, const rdseg_params* prm,
                             int32_t probe_iters, float* u, float* v, float* p,
                             void* ws, size_t ws_bytes, void* stream,

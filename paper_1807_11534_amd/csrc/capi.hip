@@ -1510,17 +1510,33 @@ rdseg_status rdseg_autotune(const float* f, rdseg_shape s, const rdseg_params* p
     q.iters = probe_iters;
     q.ckpt_every = 0;
     hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
-        return fail(RDSEG_ERR_HIP, "hipEventCreate failed");
     int best = -1;
     float best_ms = 0.0f;
     const int inner = prm->inner > 1 ? prm->inner : 1;
+    // a nonzero tile_w / tile_h / iters_per_launch in prm fixes that parameter:
+    // only configurations that match it take part
+    auto candidate = [&](int ci) {
+        const TileCfg c = config_at(ci);
+        return c.it >= inner && (prm->tile_w <= 0 || c.bx == prm->tile_w) &&
+               (prm->tile_h <= 0 || c.by == prm->tile_h) &&
+               (prm->iters_per_launch <= 0 || c.it == prm->iters_per_launch);
+    };
+    const bool restricted = prm->tile_w > 0 || prm->tile_h > 0 || prm->iters_per_launch > 0;
+    {
+        bool any = false;
+        for (int ci = 0; ci < config_count(); ++ci) any = any || candidate(ci);
+        if (!any)
+            return fail(RDSEG_ERR_ARG, "no compiled configuration matches the fixed tile_w / tile_h / iters_per_launch");
+    }
+    q.tile_w = q.tile_h = q.iters_per_launch = 0;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(RDSEG_ERR_HIP, "hipEventCreate failed");
     // two rounds over all configurations, each timed over three solves after a
     // warm-up; the minimum per configuration damps clock and cache noise
     std::vector<float> ms_min(config_count(), -1.0f);
     for (int round = 0; round < 2; ++round) {
         for (int ci = 0; ci < config_count(); ++ci) {
-            if (config_at(ci).it < inner) continue;
+            if (!candidate(ci)) continue;
             rdseg_status r = solve_impl(f, s, &q, nullptr, nullptr, u, v, p, nullptr, ws, ws_bytes, st, ci);
             if (r) { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); return r; }
             (void)hipEventRecord(e0, st);
@@ -1542,13 +1558,14 @@ rdseg_status rdseg_autotune(const float* f, rdseg_shape s, const rdseg_params* p
         if (ms_min[ci] >= 0.0f && (best < 0 || ms_min[ci] < best_ms)) { best = ci; best_ms = ms_min[ci]; }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    // record under the problem's class and active-fraction bucket
-    SolveWs w = carve_solve(ws, s);
-    int64_t np = 0;
-    if (hipMemcpy(&np, w.npix, sizeof(np), hipMemcpyDeviceToHost) != hipSuccess)
-        return fail(RDSEG_ERR_HIP, "reading the active-pixel count failed");
-    double qf = (double)np / ((double)s.H * s.W);
-    {
+    // record under the problem's class and active-fraction bucket (a search
+    // over a restricted set does not speak for the class)
+    if (!restricted) {
+        SolveWs w = carve_solve(ws, s);
+        int64_t np = 0;
+        if (hipMemcpy(&np, w.npix, sizeof(np), hipMemcpyDeviceToHost) != hipSuccess)
+            return fail(RDSEG_ERR_HIP, "reading the active-pixel count failed");
+        double qf = (double)np / ((double)s.H * s.W);
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tune[TuneKey{size_class(s), q_bucket(qf)}] = best;
     }

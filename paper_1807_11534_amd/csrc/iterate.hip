@@ -609,6 +609,7 @@ const CfgEntry kCfgs[] = {
     RDSEG_CFG(32, 16, 2, 256),
     RDSEG_CFG(32, 32, 2, 256),
     RDSEG_CFG(32, 32, 4, 256),
+    RDSEG_CFG(32, 32, 8, 512),
     RDSEG_CFG(64, 32, 2, 256),
     RDSEG_CFG(64, 32, 4, 512),
     RDSEG_CFG(64, 64, 2, 512),

@@ -380,11 +380,18 @@ def configs():
     return out
 
 
-def autotune(f, lam, theta=THETA, tau=TAU, delta=math.inf, probe_iters=16):
-    """Time every compiled configuration on this problem; cache and return the best."""
+def autotune(f, lam, theta=THETA, tau=TAU, delta=math.inf, probe_iters=16, iters_per_launch=0,
+             tile=None):
+    """Time every compiled configuration on this problem and return the best
+    ((tile_w, tile_h), iters_per_launch).  A nonzero iters_per_launch or a
+    tile fixes that parameter and only the matching configurations are timed;
+    an unrestricted search is also cached for solves that leave the choice to
+    the library."""
     lib = _lib.load()
     s = shape_of(f)
-    prm = params(lam, theta, tau, delta, probe_iters)
+    tw, th = (0, 0) if tile is None else tile
+    prm = params(lam, theta, tau, delta, probe_iters, iters_per_launch=iters_per_launch, tile_w=tw,
+                 tile_h=th)
     u, v, p = _empty_like_grid(f), _empty_like_grid(f), _empty_like_grid(f, 2)
     ws = workspace(s, prm)
     a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()

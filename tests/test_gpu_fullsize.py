@@ -90,13 +90,19 @@ def invariants(u, v, p, f, delta):
 
 
 def test_distance_selective_4096_full(rd):
-    """4096^2 eq. DS term, lambda 10, delta 0.1 max|f|, 1000 iterations in the
-    benchmark's configurations; components against the oracle."""
+    """4096^2 eq. DS term, lambda 10, delta 0.1 max|f|, 1000 iterations with the
+    persistent kernel at 8 iterations per launch (the autotuned tile and every
+    other compiled tile) and one shallower launch depth, all bitwise equal;
+    components against the oracle."""
     prob = synth.config3()
     K = prob.iters
     fd = dev(prob.f)
     outs = []
-    for tile, ipl in [((64, 32), 4), ((64, 64), 8), ((16, 16), 8)]:
+    tuned, tipl = rd.autotune(fd, prob.lam, prob.theta, prob.tau, prob.delta, 200,
+                              iters_per_launch=8)
+    assert tipl == 8
+    for tile, ipl in [(tuned, 8), ((64, 64), 8), ((32, 32), 8), ((16, 16), 8), ((8, 8), 8),
+                      ((64, 32), 4)]:
         print(f"C3 full tile={tile} ipl={ipl}", flush=True)
         outs.append([host(x) for x in rd.solve(fd, prob.lam, prob.theta, prob.tau, prob.delta,
                                                K, tile=tile, iters_per_launch=ipl)])

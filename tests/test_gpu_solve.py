@@ -153,6 +153,33 @@ def test_all_configs_bitwise_identical(rd):
                 np.testing.assert_array_equal(a, b)
 
 
+
+def test_autotune_restrictions(rd):
+    """The autotuner returns a compiled configuration; a fixed launch depth or
+    tile restricts the search to matching configurations, and a combination
+    that is not compiled is an argument error.  The chosen configuration
+    solves to the same bits as any other."""
+    from paper_1807_11534_amd._lib import RdsegError
+    f = synth.smooth_field(300, 257, 27, noise=0.2)
+    ft = dev(f)
+    cfgs = {(tw, th, it) for (tw, th, it, _) in rd.configs()}
+    say("autotune free")
+    tile, ipl = rd.autotune(ft, 2.0, 0.1, 0.125, 0.35, 8)
+    assert (tile[0], tile[1], ipl) in cfgs
+    say("autotune iters_per_launch=8")
+    tile8, ipl8 = rd.autotune(ft, 2.0, 0.1, 0.125, 0.35, 8, iters_per_launch=8)
+    assert ipl8 == 8 and (tile8[0], tile8[1], 8) in cfgs
+    say("autotune tile 16x16")
+    t16, i16 = rd.autotune(ft, 2.0, 0.1, 0.125, 0.35, 8, tile=(16, 16))
+    assert t16 == (16, 16) and (16, 16, i16) in cfgs
+    with pytest.raises(RdsegError):
+        rd.autotune(ft, 2.0, 0.1, 0.125, 0.35, 8, tile=(8, 8), iters_per_launch=2)
+    a = [host(x) for x in rd.solve(ft, 2.0, 0.1, 0.125, 0.35, 24, tile=tile8, iters_per_launch=8)]
+    b = [host(x) for x in rd.solve(ft, 2.0, 0.1, 0.125, 0.35, 24, tile=(64, 32),
+                                   iters_per_launch=4)]
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x, y)
+
 def test_determinism_and_resume(rd):
     f = synth.smooth_field(96, 130, 25, noise=0.2)
     ft = dev(f)

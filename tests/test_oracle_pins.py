@@ -12,7 +12,8 @@ import pytest
 
 import oracle
 import synth
-from tests.twin import Twin, dual_value, restricted_energy, rof_dual_objective
+from tests.twin import (Twin, dense_primal_dual_split, dual_value, restricted_energy,
+                        rof_dual_objective)
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 TH, TAU = 0.1, 0.125
@@ -122,6 +123,21 @@ def test_duality_gap_certificate(delta, lam):
     assert P - D <= 1e-12 * max(1.0, abs(P))
     assert np.sqrt(p[0] ** 2 + p[1] ** 2).max() <= 1.0 + 1e-12
 
+
+
+@pytest.mark.parametrize("delta", [np.inf, 0.8, 0.35, 0.1])
+@pytest.mark.parametrize("lam", [0.7, 2.5])
+def test_dense_projected_solve_8x8(delta, lam):
+    """The limit of the iteration is the minimiser of the restricted split
+    energy (Sec. 2.1 eq. DF with the restricted systems of Sec. 3): a
+    brute-force dense projected primal-dual solve of that energy, to 1e-12,
+    lands on the oracle's converged u and v.  The dense solve shares neither
+    the algorithm nor the operators with the oracle."""
+    f = rand_f(8, 8, 5, scale=0.8)
+    ud, vd, _ = dense_primal_dual_split(f, lam, TH, delta)
+    u, v, _ = oracle.solve(f, lam, TH, TAU, delta, 300000)
+    assert np.abs(u - ud).max() <= 1e-12
+    assert np.abs(v - vd).max() <= 1e-12
 
 # ---------------------------------------------------------------- closed forms
 def test_constant_f():

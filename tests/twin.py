@@ -181,3 +181,53 @@ def reverse_with_w_noise(f, lam, theta, tau, delta, iters, ubar, rng=None, amp=0
         pby = np.where(A & ~lastr, m * pty - np.where(lastr, 0.0, _shift(wb, 1, 0) - wb), 0.0)
         vb = np.where(A, ub - wb / theta, 0.0)
     return np.where(A, -theta * lam * S, 0.0), float((-theta * f64 * S)[A].sum())
+
+
+
+def dense_primal_dual_split(f, lam, theta, delta, t=0.025, tol=1e-15, max_iters=400000):
+    """Brute-force dense solve of the restricted split energy (Sec. 2.1 eq. DF,
+    restricted as in Sec. 3) by projected primal-dual gradient steps on its
+    saddle form
+        min over (u, v), 0 <= v <= 1 on RD,  max over |p(x)| <= 1 on RD, of
+        <G u~, p> + |u - v|^2_RD / (2 theta) + lam <f, v>_RD,
+    u~ = u on RD and H(-f) elsewhere, p = 0 off RD.  This is the first-order
+    primal-dual method of Chambolle and Pock (steps t, s with t s |G|^2 < 1,
+    |G|^2 <= 8) with the exact per-pixel proximal map of the (u, v) part: a
+    different algorithm from the alternation that the paper iterates, with its
+    own dense operator.  It runs until no coordinate moves by more than tol in
+    one step, then as many steps again (the tail is linear, so the second half
+    takes the error to rounding level).  Returns (u, v, steps)."""
+    f = np.asarray(f, np.float32).astype(np.float64)
+    H, W = f.shape
+    N = f.size
+    fv = f.ravel()
+    A = np.abs(fv) < delta
+    h = (fv < 0).astype(np.float64)
+    G = grad_matrix(H, W)
+    AA = np.concatenate([A, A])
+    s = 0.999 / (8.0 * t)
+    u, v = h.copy(), h.copy()
+    ub = u.copy()
+    p = np.zeros(2 * N)
+    stop = max_iters
+    k = 0
+    while k < stop:
+        q = p + s * (G @ ub)
+        n = np.sqrt(q[:N] ** 2 + q[N:] ** 2)
+        q = q / np.maximum(1.0, np.concatenate([n, n]))
+        p = np.where(AA, q, 0.0)
+        a = u - t * (G.T @ p)
+        # argmin over v in [0,1], u of (|u-a|^2 + |v-v_k|^2)/(2t) + (u-v)^2/(2 theta) + lam f v:
+        # u = (theta a + t v) / (theta + t) for each v, leaving a 1-D quadratic in v
+        vn = (a / (theta + t) + v / t - lam * fv) / (1.0 / (theta + t) + 1.0 / t)
+        vn = np.where(A, np.clip(vn, 0.0, 1.0), h)
+        un = np.where(A, (theta * a + t * vn) / (theta + t), h)
+        r = max(np.abs(un - u).max(), np.abs(vn - v).max())
+        ub = 2.0 * un - u
+        u, v = un, vn
+        k += 1
+        if stop == max_iters and k > 10 and r < tol:
+            stop = min(max_iters, 2 * k)
+    if stop == max_iters:
+        raise RuntimeError("dense primal-dual solve did not reach its tolerance")
+    return u.reshape(H, W), v.reshape(H, W), k
