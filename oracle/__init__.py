@@ -9,8 +9,13 @@ Parity status of each function (pins live in ``tests/test_oracle_*.py``):
 
 * ``active_set``  -- pinned (brute force on tiny grids, closed forms delta=inf / delta<=0).
 * ``grad``/``div`` -- pinned (adjointness <grad u, p> = -<u, div p>; hand-worked 2x3 case).
-* ``solve``       -- pinned (duality-gap certificate of the restricted energy, closed forms,
-  symmetries, resume, invariants, monotone dual objective, independent matrix formulation).
+* ``solve``       -- pinned (duality-gap certificate of the restricted energy, a brute-force
+  dense projected primal-dual solve of that energy on 8x8 inputs, closed forms, symmetries,
+  resume, invariants, monotone dual objective, independent matrix formulation).
+
+``tests/test_oracle_mutants.py`` plants plausible mistakes (signs, indices, boundaries,
+dropped terms, transposed operands, order) into copies of the C source and checks that
+the pins above catch every one.
 * ``dual_steps``  -- pinned (monotone dual objective, fixed point of the ROF dual).
 * ``reverse``/``tangent`` -- pinned (dot-product identity, central finite differences).
 * ``fit_term``/``fit_vjp`` -- pinned (hand-worked values, finite differences).
@@ -21,7 +26,8 @@ Parity status of each function (pins live in ``tests/test_oracle_*.py``):
   index; tolerance 0 / inf; empty domain stops at the first check).
 * ``metrics``     -- pinned (hand-worked 2x3 case, identity, disjoint labels, symmetry).
 * ``solve_pd``    -- pinned (duality gap of the restricted eq. CR problem closes; weak
-  duality at every iterate; hand-derived two-pixel minimisers).
+  duality at every iterate; hand-derived two-pixel minimisers; mid-trajectory iterates
+  of a dense-matrix formulation of the published algorithm).
 * ``grad3``/``div3`` -- pinned (adjointness, hand-worked 2x2x2 case).
 * ``solve3``      -- pinned (a volume of identical slices equals the pinned 2-D solve on
   each slice bit for bit; axis permutations; D = 1).
@@ -49,7 +55,14 @@ def _load():
     if not os.path.exists(_LIB_PATH):
         from . import build as _b
         _b.build()
-    lib = ctypes.CDLL(_LIB_PATH)
+    _lib = _bind(_LIB_PATH)
+    return _lib
+
+
+def _bind(path):
+    """Load a build of rdseg_oracle.c and declare its signatures (the tests
+    also bind deliberately broken builds to check that the pins catch them)."""
+    lib = ctypes.CDLL(path)
     c_int, c_double, c_size = ctypes.c_int, ctypes.c_double, ctypes.c_size_t
     lib.orc_active_set.argtypes = [_fp, c_int, c_int, c_double, _i32p, _u64p, _i32p,
                                    _i32p, _i32p, _i64p]
@@ -85,7 +98,6 @@ def _load():
     lib.orc_div3.restype = None
     lib.orc_solve3.argtypes = [_fp, c_int, c_int, c_int, c_double, c_double, c_double, c_double,
                                c_int, c_int, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
-    _lib = lib
     return lib
 
 

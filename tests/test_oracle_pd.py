@@ -4,7 +4,10 @@ the restriction of Sec. 3 carried over to another solver as Sec. 5 proposes.
 The energy and its dual are written here independently of the oracle (sparse
 matrix gradient, NumPy): weak duality must hold at every iterate, the gap must
 close at convergence (an optimality certificate), and hand-derived two-pixel
-minimisers (tests/golden/two_pixel_cr_minimisers.txt) must be reached.
+minimisers (tests/golden/two_pixel_cr_minimisers.txt) must be reached.  The
+trajectory itself (the extrapolation step that makes the method Chambolle and
+Pock's and not a plain alternation) is pinned by a dense-matrix formulation of
+the published algorithm at a finite iteration count.
 """
 import math
 import os
@@ -14,7 +17,7 @@ import pytest
 
 import oracle
 import synth
-from tests.twin import grad_matrix
+from tests.twin import grad_matrix, pd_twin
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden", "two_pixel_cr_minimisers.txt")
 STEP = 1.0 / math.sqrt(8.0)   # tau = sigma, tau sigma |grad|^2 <= 1
@@ -100,3 +103,16 @@ def test_pd_frozen_and_bounds():
     assert (p[0][:, -1] == 0).all() and (p[1][-1, :] == 0).all()
     u0, _ = oracle.solve_pd(f, 3.0, STEP, STEP, 0.0, 50)   # q = 0: thresholding
     np.testing.assert_array_equal(u0, h)
+
+
+@pytest.mark.parametrize("shape", [(8, 8), (7, 13)])
+@pytest.mark.parametrize("frac", [math.inf, 0.5])
+def test_pd_matches_matrix_twin(shape, frac):
+    """Mid-trajectory iterates (37 steps, far from convergence) of the oracle
+    equal those of the dense-matrix formulation to rounding."""
+    f = synth.smooth_field(*shape, seed=17, scale=0.3, noise=0.3)
+    delta = frac * float(np.abs(f).max()) if math.isfinite(frac) else math.inf
+    u, p = oracle.solve_pd(f, 3.0, STEP, 0.9 * STEP, delta, 37)
+    ut, pt = pd_twin(f, 3.0, STEP, 0.9 * STEP, delta, 37)
+    assert np.abs(u - ut).max() <= 1e-12
+    assert np.abs(p - pt).max() <= 1e-12

@@ -158,6 +158,18 @@ def test_constant_f():
     np.testing.assert_array_equal(v, vk)
 
 
+def test_heaviside_at_zero_reading():
+    """The reading H(0) = 0 (the paper leaves the Heaviside function's value at
+    0 open): with an empty domain u = H(-f) is 0 where f = 0, and a pixel with
+    f = 0 inside RD starts from u = H(-0) = 0 and, having no data term and no
+    neighbours, stays there."""
+    f = np.array([[0.0, -0.5, 0.5], [-0.0, 0.0, -1.0]], np.float32)
+    u, v, p = oracle.solve(f, 2.0, TH, TAU, 0.0, 10)
+    np.testing.assert_array_equal(u, [[0, 1, 0], [0, 0, 1]])
+    np.testing.assert_array_equal(v, u)
+    u1, v1, _ = oracle.solve(np.zeros((1, 1), np.float32), 2.0, TH, TAU, 1.0, 50)
+    assert u1[0, 0] == 0.0 and v1[0, 0] == 0.0
+
 def test_large_lambda_gives_heaviside():
     """Large lambda (Sec. 1): with |div p| <= 2 + sqrt 2 and lambda*min|f| >= 4,
     v = H(-f) exactly at every iterate and the labels u > 1/2 equal H(-f)."""

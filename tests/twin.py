@@ -231,3 +231,33 @@ def dense_primal_dual_split(f, lam, theta, delta, t=0.025, tol=1e-15, max_iters=
     if stop == max_iters:
         raise RuntimeError("dense primal-dual solve did not reach its tolerance")
     return u.reshape(H, W), v.reshape(H, W), k
+
+
+def pd_twin(f, lam, tau, sigma, delta, iters):
+    """Restricted first-order primal-dual iteration for eq. CR (Sec. 5 carries
+    the restriction of Sec. 3 over to other solvers), written from Chambolle
+    and Pock's algorithm with extrapolation parameter 1 and dense operators:
+        p    <- projection onto |p(x)| <= 1 of p + sigma G ubar   (RD rows)
+        u'   <- clamp(u - tau (G^T p + lam f), 0, 1)              (RD)
+        ubar <- 2 u' - u
+    with u = ubar = H(-f) and p = 0 off RD.  Returns (u, p) after `iters`."""
+    f = np.asarray(f, np.float32).astype(np.float64)
+    H, W = f.shape
+    N = f.size
+    fv = f.ravel()
+    A = np.abs(fv) < delta
+    h = (fv < 0).astype(np.float64)
+    G = grad_matrix(H, W)
+    AA = np.concatenate([A, A])
+    u = h.copy()
+    ub = u.copy()
+    p = np.zeros(2 * N)
+    for _ in range(iters):
+        q = p + sigma * (G @ ub)
+        n = np.sqrt(q[:N] ** 2 + q[N:] ** 2)
+        q = q / np.maximum(1.0, np.concatenate([n, n]))
+        p = np.where(AA, q, 0.0)
+        un = np.where(A, np.clip(u - tau * (G.T @ p + lam * fv), 0.0, 1.0), h)
+        ub = 2.0 * un - u
+        u = un
+    return u.reshape(H, W), p.reshape(2, H, W)
