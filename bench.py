@@ -9,7 +9,8 @@ iterations, divided by the step time).
 
 Also reported on the same line:
   roofline      the dominant iteration-kernel instantiation (most kernel time in
-                the step): algorithmic bytes (28 per active pixel-iteration)
+                the step; a resident solve counts as one launch of its own
+                kernel): algorithmic bytes (28 per active pixel-iteration)
                 per launch over its average launch duration, from HIP events
                 around every launch on its stream, in a separate pass over the
                 same step; peak = 8 TB/s HBM;
@@ -366,10 +367,12 @@ def main():
     cfgs = rdseg.configs()
     per_cfg = []
     for ci, (tw, th, it, nt) in enumerate(cfgs):
-        ms, nl, by, upd = rdseg.timing_read(ci)
-        if nl:
-            per_cfg.append(dict(config=ci, kernel=f"k_iterate<{tw},{th},{it},{nt}>", ms=ms,
-                                launches=nl, alg_bytes=by, updates=upd))
+        # form 0: separate launches of the blocked kernel; 1: resident launches
+        for form, name in ((0, "k_iterate"), (1, "k_resident")):
+            ms, nl, by, upd = rdseg.timing_read_form(ci, form)
+            if nl:
+                per_cfg.append(dict(config=ci, kernel=f"{name}<{tw},{th},{it},{nt}>", ms=ms,
+                                    launches=nl, alg_bytes=by, updates=upd))
     dom = max(per_cfg, key=lambda r: r["ms"])
     avg_ms = dom["ms"] / dom["launches"]
     bytes_per_launch = dom["alg_bytes"] / dom["launches"]

@@ -352,6 +352,15 @@ rdseg_status rdseg_autotune(const float* f, rdseg_shape s, const rdseg_params* p
                             void* ws, size_t ws_bytes, void* stream,
                             int32_t* tile_w, int32_t* tile_h, int32_t* iters_per_launch);
 
+/* Single-image solves without checkpoints or stopping rule whose queued
+ * macro tiles all fit on the chip at once (one workgroup each; e.g. a 1024^2
+ * image in 64x64 tiles) run as one cooperative launch in which every tile
+ * stays on chip and exchanges only its halo frame with its neighbours after
+ * each block of iterations (results bitwise equal to separate launches).
+ * on = 0 forces separate launches, on != 0 (the default) allows the resident
+ * form.  Process-wide. */
+rdseg_status rdseg_set_resident(int32_t on);
+
 /* Number of compiled configurations and their parameters (i < count). */
 int32_t rdseg_config_count(void);
 rdseg_status rdseg_config_get(int32_t i, int32_t* tile_w, int32_t* tile_h,
@@ -368,6 +377,12 @@ rdseg_status rdseg_config_get(int32_t i, int32_t* tile_w, int32_t* tile_h,
 rdseg_status rdseg_timing_enable(int32_t on);
 rdseg_status rdseg_timing_read(int32_t config, double* kernel_ms, int64_t* launches,
                                double* alg_bytes, int64_t* pixel_updates);
+/* As rdseg_timing_read, restricted to one form of launch: form 0 = separate
+ * launches of the blocked kernel, 1 = resident launches (one per solve), -1 =
+ * both.  RDSEG_ERR_ARG for any other form. */
+rdseg_status rdseg_timing_read_form(int32_t config, int32_t form, double* kernel_ms,
+                                    int64_t* launches, double* alg_bytes,
+                                    int64_t* pixel_updates);
 rdseg_status rdseg_timing_reset(void);
 
 const char* rdseg_status_string(rdseg_status st);

@@ -101,7 +101,11 @@ SIGNATURES = {
     "rdseg_timing_enable": (ctypes.c_int, [_i32]),
     "rdseg_timing_read": (ctypes.c_int, [_i32, ctypes.POINTER(_d), ctypes.POINTER(ctypes.c_int64),
                                          ctypes.POINTER(_d), ctypes.POINTER(ctypes.c_int64)]),
+    "rdseg_timing_read_form": (ctypes.c_int, [_i32, _i32, ctypes.POINTER(_d),
+                                              ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(_d),
+                                              ctypes.POINTER(ctypes.c_int64)]),
     "rdseg_timing_reset": (ctypes.c_int, []),
+    "rdseg_set_resident": (ctypes.c_int, [_i32]),
     "rdseg_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "rdseg_last_error": (ctypes.c_char_p, []),
 }

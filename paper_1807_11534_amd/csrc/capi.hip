@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <map>
+#include <atomic>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -119,6 +120,7 @@ struct SolveWs {
     int32_t* cflags;
     int2* cqueue;
     int32_t* totals;   // [0] n_queue, [1] scratch total, [2] n_closed
+    int32_t* epoch;    // resident solve: per macro tile block counts, then a status word
     size_t bytes;
 };
 
@@ -139,6 +141,7 @@ SolveWs carve_solve(void* base, const rdseg_shape& s) {
     w.cflags = cv.take<int32_t>(g.nt);
     w.cqueue = cv.take<int2>(g.nt);
     w.totals = cv.take<int32_t>(4);
+    w.epoch = cv.take<int32_t>(g.nt + 1);
     w.bytes = cv.off;
     return w;
 }
@@ -187,7 +190,10 @@ struct TimingRec {
     int launches;         // launches bracketed
     int ci;
     int64_t* npix_host;   // pinned slot filled by an async copy
+    bool resident;        // one launch of the resident kernel
 };
+
+std::atomic<bool> g_resident_on{true};
 
 struct Timing {
     std::mutex mu;
@@ -342,6 +348,9 @@ struct SolvePlanArgs {
     const struct StopSpec* stop = nullptr;   // convergence-driven solve (single image)
     int launches = 0;                        // out: number of launches enqueued
     int launches_per_check = 0;              // out (with stop)
+    bool resident = false;                   // try the resident form first (single image)
+    const int32_t* mflags = nullptr;         // resident: queued flag per macro tile
+    int32_t* epoch = nullptr;                // resident: max_items + 1 int32 of workspace
 };
 
 // Stopping rule of a convergence-driven solve: change slots (one uint32
@@ -438,6 +447,37 @@ rdseg_status enqueue_iterations(SolvePlanArgs& a) {
     const int L = (int)nits.size();
     a.launches = L;
     a.launches_per_check = (ce + IT - 1) / IT;
+    if (a.resident && !a.descs && !a.tape && !stop) {
+        TimingRec rec{};
+        const bool timed = g_timing.on;
+        if (timed) {
+            rec.e0 = timing_event();
+            rec.e1 = timing_event();
+            if (rec.e0) (void)hipEventRecord(rec.e0, a.st);
+        }
+        const int rc = launch_resident(a.ci, *a.d0, a.queue, a.n_queue, a.mflags, a.epoch,
+                                       a.epoch + a.max_items, a.max_items, L % 2, a.iters, IT,
+                                       a.inner, a.theta, a.inv_theta, a.tau, a.st);
+        if (rc > 0) return RDSEG_ERR_HIP;
+        if (rc == 0) {
+            a.launches = 1;
+            if (timed && rec.e0 && rec.e1) {
+                std::lock_guard<std::mutex> lk(g_timing.mu);
+                (void)hipEventRecord(rec.e1, a.st);
+                rec.nit = a.iters;
+                rec.launches = 1;
+                rec.ci = a.ci;
+                rec.resident = true;
+                rec.npix_host = timing_slot();
+                if (rec.npix_host && a.npix)
+                    (void)hipMemcpyAsync(rec.npix_host, a.npix, sizeof(int64_t),
+                                         hipMemcpyDeviceToHost, a.st);
+                g_timing.recs.push_back(rec);
+            }
+            return RDSEG_OK;
+        }
+        // rc < 0: not applicable, fall through to separate launches
+    }
     size_t seg = 0;
     const int64_t plane = (int64_t)a.d0->H * a.d0->ld;
     std::unique_lock<std::mutex> poll_lock;
@@ -641,14 +681,28 @@ rdseg_status solve_impl(const float* f, rdseg_shape s, const rdseg_params* prm, 
     if (launch_macro_queue(&d, nullptr, off, 1, nm, cfg.bx, cfg.by, w.masks, qs, w.queue, w.totals,
                            g.nt, use_closed ? w.cqueue : nullptr, w.totals + 2, st))
         return RDSEG_ERR_HIP;
+    // The resident form keeps every queued macro tile on chip for the whole
+    // solve; it needs all of them resident at once, so closed tiles then run
+    // before it on the same stream instead of beside it.
+    bool resident = false;
+    if (g_resident_on.load() && !stop && !(prm->ckpt_every > 0 && tape) && prm->iters > 0 &&
+        resident_fits(ci, nm)) {
+        hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+        resident = hipStreamIsCapturing(st, &cap) == hipSuccess && cap == hipStreamCaptureStatusNone;
+    }
     hipEvent_t join = nullptr;
     if (use_closed) {
-        r = closed_beside(st, &join, [&](hipStream_t cs) {
+        auto closed = [&](hipStream_t cs) {
             return launch_closed(&d, nullptr, false, w.cqueue, w.totals + 2, g.nt, prm->iters,
                                  (float)prm->theta, (float)(1.0 / prm->theta), (float)prm->tau,
                                  cs, inner);
-        });
-        if (r) return r;
+        };
+        if (resident) {
+            if (closed(st)) return RDSEG_ERR_HIP;
+        } else {
+            r = closed_beside(st, &join, closed);
+            if (r) return r;
+        }
     }
     SolvePlanArgs a;
     a.d0 = &d;
@@ -667,6 +721,9 @@ rdseg_status solve_impl(const float* f, rdseg_shape s, const rdseg_params* prm, 
     a.st = st;
     a.stop = stop;
     a.inner = inner;
+    a.resident = resident;
+    a.mflags = w.flags;
+    a.epoch = w.epoch;
     r = enqueue_iterations(a);
     const rdseg_status rj = join_closed(st, join);
     if (r) return r;
@@ -1576,6 +1633,11 @@ rdseg_status rdseg_autotune(const float* f, rdseg_shape s, const rdseg_params* p
     return RDSEG_OK;
 }
 
+rdseg_status rdseg_set_resident(int32_t on) {
+    g_resident_on.store(on != 0);
+    return RDSEG_OK;
+}
+
 rdseg_status rdseg_timing_enable(int32_t on) {
     std::lock_guard<std::mutex> lk(g_timing.mu);
     g_timing.on = on != 0;
@@ -1584,11 +1646,19 @@ rdseg_status rdseg_timing_enable(int32_t on) {
 
 rdseg_status rdseg_timing_read(int32_t config, double* kernel_ms, int64_t* launches,
                                double* alg_bytes, int64_t* pixel_updates) {
+    return rdseg_timing_read_form(config, -1, kernel_ms, launches, alg_bytes, pixel_updates);
+}
+
+rdseg_status rdseg_timing_read_form(int32_t config, int32_t form, double* kernel_ms,
+                                    int64_t* launches, double* alg_bytes,
+                                    int64_t* pixel_updates) {
+    if (form < -1 || form > 1) return fail(RDSEG_ERR_ARG, "form must be -1, 0 or 1");
     std::lock_guard<std::mutex> lk(g_timing.mu);
     double ms = 0.0, bytes = 0.0;
     int64_t upd = 0, n = 0;
     for (auto& r : g_timing.recs) {
         if (config >= 0 && r.ci != config) continue;
+        if (form >= 0 && (int)r.resident != form) continue;
         if (hipEventSynchronize(r.e1) != hipSuccess) return fail(RDSEG_ERR_HIP, "event sync failed");
         float t = 0.0f;
         (void)hipEventElapsedTime(&t, r.e0, r.e1);

@@ -567,6 +567,219 @@ __global__ __launch_bounds__(64) void k_closed(ImgDesc d0, const ImgDesc* __rest
     }
 }
 
+// Resident variant of the blocked iteration (single image, no checkpoint
+// tape, no stopping rule), for images whose queued macro tiles fit on the
+// chip at once (a cooperative launch guarantees that every workgroup is
+// resident).  Each workgroup loads its macro tile's region once and keeps it
+// in registers and LDS for the whole solve: after every block of `per` outer
+// iterations it writes the frame of its macro tile that the neighbours' halos
+// cover (the IT + 1 outermost rows and columns; everything at the last block)
+// to the state buffer the equivalent separate launch would write, publishes
+// the block count in epoch[m], waits until each of its up to 8 queued
+// neighbours has published the same count, and reloads only its halo ring
+// from that buffer.  Values and buffer parities are those of the separate
+// launches, so the results are bitwise equal.  A neighbour that is not queued
+// holds no open RD tile; its pixels belong to other components than this
+// tile's RD pixels, so they are not waited for.
+//
+// Ordering without cache-wide fences: frame values are written and the ring
+// is read with device-scope atomic stores and loads, which the hardware keeps
+// coherent across the XCDs' L2 caches (they do not stay in, or hit stale
+// lines of, one XCD's L2).  Each thread waits for its frame stores to complete
+// (s_waitcnt 0) before the barrier after which thread 0 stores the count, and
+// the ring loads are issued only after the waiting lanes have read the
+// neighbours' counts and the workgroup has passed a barrier.  (Release and
+// acquire fences at device scope would write back and invalidate the whole
+// L2 of the XCD at every block, which costs more than a separate launch.)
+// Every wait is bounded in time: on expiry the workgroup records the failure
+// in *status, stops waiting and writes NaN for u, so a solve can never hang.
+constexpr uint64_t kResidentWaitTicks = 100000000ull;   // 1 s of the 100 MHz clock
+
+template <int BX, int BY, int IT, int NT>
+__global__ __launch_bounds__(NT) void k_resident(ImgDesc d, const int2* __restrict__ queue,
+                                                 const int32_t* __restrict__ n_queue,
+                                                 const int32_t* __restrict__ mflags,
+                                                 int32_t* __restrict__ epoch,
+                                                 int32_t* __restrict__ status, int in_buf,
+                                                 int iters, int per, int inner, float theta,
+                                                 float inv_theta, float tau) {
+    constexpr int RX = BX + 2 * IT + 1;
+    constexpr int RY = BY + 2 * IT + 1;
+    constexpr int RC = RX * RY;
+    constexpr int CPT = (RC + NT - 1) / NT;
+    constexpr int PAD = RX + 1;
+    constexpr int LS = RC + 2 * PAD;
+    constexpr int H0 = IT + 1;
+    __shared__ float sPX[LS];
+    __shared__ float sPY[LS];
+    __shared__ float sW[LS];
+    __shared__ int sFail;
+
+    const int t = threadIdx.x;
+    // the same XCD-contiguous assignment of queue items as the launched kernel
+    const int nq = *n_queue;
+    const int xcd = blockIdx.x & 7;
+    const int rank = blockIdx.x >> 3;
+    const int chunk = (nq + 7) >> 3;
+    const int item = xcd * chunk + rank;
+    if (rank >= chunk || item >= nq) return;   // the whole workgroup leaves together
+
+    for (int k = t; k < PAD; k += NT) {
+        sPX[k] = 0.0f; sPY[k] = 0.0f; sW[k] = 0.0f;
+        sPX[PAD + RC + k] = 0.0f; sPY[PAD + RC + k] = 0.0f; sW[PAD + RC + k] = 0.0f;
+    }
+    if (t == 0) sFail = 0;
+    const int2 q = queue[item];
+    const int m = q.y;
+    const int my = m / d.mw;
+    const int mx = m - my * d.mw;
+    const int ox = mx * BX - H0;
+    const int oy = my * BY - H0;
+    const int W = d.W, H = d.H, ld = d.ld;
+
+    float rv[CPT], rpx[CPT], rpy[CPT], rc[CPT];
+    float ru[1];
+    uint32_t fl[CPT];
+    int gi[CPT];
+    int idx[CPT];
+    uint32_t ring = 0u;   // bit j: slot j is a halo cell inside the grid
+    uint32_t frame = 0u;  // bit j: slot j is an RD cell of the macro tile a neighbour reads
+    int plain = 1;
+    {
+        const float* __restrict__ Vi = d.st[in_buf][0];
+        const float* __restrict__ PXi = d.st[in_buf][1];
+        const float* __restrict__ PYi = d.st[in_buf][2];
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) {
+            const int i = t + j * NT;
+            rv[j] = 0.0f; rpx[j] = 0.0f; rpy[j] = 0.0f; rc[j] = __builtin_inff();
+            fl[j] = 0u; gi[j] = 0; idx[j] = i;
+            if (i < RC) {
+                const int ry = i / RX;
+                const int rx = i - ry * RX;
+                const int gx = ox + rx, gy = oy + ry;
+                const bool inb = (unsigned)gx < (unsigned)W && (unsigned)gy < (unsigned)H;
+                const int g = gy * ld + gx;
+                gi[j] = g;
+                float c = __builtin_inff(), v = 0.0f, px = 0.0f, py = 0.0f;
+                if (inb) {
+                    c = d.c[g];
+                    v = Vi[g];
+                    px = PXi[g];
+                    py = PYi[g];
+                }
+                const bool act = c_active(c);
+                rc[j] = c;
+                rv[j] = act ? v : heav_from_c(c);
+                rpx[j] = act ? px : 0.0f;
+                rpy[j] = act ? py : 0.0f;
+                const uint32_t f = cell_flags<BX, BY, IT>(act, rx, ry, gx, gy, W, H);
+                fl[j] = f;
+                plain &= (act && !(f & (CF_LASTC | CF_LASTR))) ? 1 : 0;
+                const int xi = rx - H0, yi = ry - H0;
+                const bool interior = xi >= 0 && xi < BX && yi >= 0 && yi < BY;
+                if (!interior && inb) ring |= 1u << j;
+                if ((f & CF_OUT) && (xi <= IT || xi >= BX - IT - 1 || yi <= IT || yi >= BY - IT - 1))
+                    frame |= 1u << j;
+                sPX[PAD + i] = rpx[j];
+                sPY[PAD + i] = rpy[j];
+            }
+        }
+    }
+    const bool fast = __syncthreads_and(plain) != 0;
+    const bool edge = ox + RX >= W || oy + RY >= H;
+    uint32_t dmax = 0u;
+    const int nb = (iters + per - 1) / per;
+    for (int b = 0; b < nb; ++b) {
+        const int nit = min(per, iters - b * per);
+        const bool lastb = b == nb - 1;
+        const int wu = lastb ? 1 : 0;
+        if (fast)
+            run_iterations<BX, BY, IT, NT, MODE_FAST, false>(sPX, sPY, sW, idx, rv, rpx, rpy, rc,
+                                                             fl, gi, d.u, nit, wu, theta,
+                                                             inv_theta, tau, ru, false, dmax,
+                                                             inner);
+        else if (edge)
+            run_iterations<BX, BY, IT, NT, MODE_DENSE, false>(sPX, sPY, sW, idx, rv, rpx, rpy,
+                                                              rc, fl, gi, d.u, nit, wu, theta,
+                                                              inv_theta, tau, ru, false, dmax,
+                                                              inner);
+        else
+            run_iterations<BX, BY, IT, NT, MODE_DENSE_IN, false>(sPX, sPY, sW, idx, rv, rpx,
+                                                                 rpy, rc, fl, gi, d.u, nit, wu,
+                                                                 theta, inv_theta, tau, ru,
+                                                                 false, dmax, inner);
+        const int xb = (in_buf + b + 1) & 1;   // the buffer launch b would write
+        float* __restrict__ Vo = d.st[xb][0];
+        float* __restrict__ PXo = d.st[xb][1];
+        float* __restrict__ PYo = d.st[xb][2];
+        if (lastb) {
+#pragma unroll
+            for (int j = 0; j < CPT; ++j) {
+                if (fl[j] & CF_OUT) {
+                    Vo[gi[j]] = rv[j];
+                    PXo[gi[j]] = rpx[j];
+                    PYo[gi[j]] = rpy[j];
+                }
+            }
+            break;
+        }
+        // The frame goes out as device-coherent stores (they do not stay in
+        // this XCD's L2); once every thread has seen its stores complete, the
+        // barrier lets thread 0 publish the block count.
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) {
+            if ((frame >> j) & 1u) {
+                __hip_atomic_store(Vo + gi[j], rv[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(PXo + gi[j], rpx[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(PYo + gi[j], rpy[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (t == 0) __hip_atomic_store(epoch + m, b + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (t < 9 && t != 4 && !sFail) {
+            const int nx = mx + (t % 3) - 1, ny = my + (t / 3) - 1;
+            if (nx >= 0 && nx < d.mw && ny >= 0 && ny < d.mh && mflags[ny * d.mw + nx]) {
+                const int32_t* e = epoch + ny * d.mw + nx;
+                const uint64_t t0 = wall_clock64();
+                while (__hip_atomic_load(e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < b + 1) {
+                    if (wall_clock64() - t0 > kResidentWaitTicks) {
+                        sFail = 1;
+                        __hip_atomic_store(status, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+            }
+        }
+        __syncthreads();
+        // the halo ring from the neighbours' frames, as device-coherent loads
+        // issued after the counts were seen
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) {
+            if ((ring >> j) & 1u) {
+                const int i = t + j * NT;
+                const bool act = (fl[j] & CF_ACT) != 0;
+                const float v = __hip_atomic_load(Vo + gi[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const float px = __hip_atomic_load(PXo + gi[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const float py = __hip_atomic_load(PYo + gi[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                rv[j] = act ? v : heav_from_c(rc[j]);
+                rpx[j] = act ? px : 0.0f;
+                rpy[j] = act ? py : 0.0f;
+                sPX[PAD + i] = rpx[j];
+                sPY[PAD + i] = rpy[j];
+            }
+        }
+        __syncthreads();
+    }
+    if (sFail) {
+#pragma unroll
+        for (int j = 0; j < CPT; ++j)
+            if (fl[j] & CF_OUT) d.u[gi[j]] = __builtin_nanf("");
+    }
+}
+
 __global__ __launch_bounds__(256) void k_state_copy(ImgDesc d, int buf, float* __restrict__ slot,
                                                     int to_slot) {
     const int64_t plane = (int64_t)d.H * d.ld;
@@ -620,6 +833,31 @@ constexpr int kNumCfgs = sizeof(kCfgs) / sizeof(kCfgs[0]);
 
 int g_grid_cache[kNumCfgs][3];
 
+using ResFn = void (*)(ImgDesc, const int2*, const int32_t*, const int32_t*, int32_t*, int32_t*,
+                       int, int, int, int, float, float, float);
+
+struct ResEntry {
+    int bx, by, it, nt;
+    ResFn fn;
+};
+
+#define RDSEG_RES(bx, by, it, nt) ResEntry{bx, by, it, nt, k_resident<bx, by, it, nt>}
+
+const ResEntry kRes[] = {
+    RDSEG_RES(64, 32, 4, 512),
+    RDSEG_RES(64, 64, 8, 1024),
+};
+constexpr int kNumRes = sizeof(kRes) / sizeof(kRes[0]);
+int g_res_cap[kNumRes];
+
+int resident_entry(int ci) {
+    const TileCfg c = kCfgs[ci].cfg;
+    for (int r = 0; r < kNumRes; ++r)
+        if (kRes[r].bx == c.bx && kRes[r].by == c.by && kRes[r].it == c.it && kRes[r].nt == c.nt)
+            return r;
+    return -1;
+}
+
 }  // namespace
 
 int config_count() { return kNumCfgs; }
@@ -643,6 +881,40 @@ int persistent_blocks(const void* kernel, int threads, size_t dyn_lds) {
         return 0;
     if (per < 1) per = 1;
     return per * ncu;
+}
+
+bool resident_fits(int ci, int64_t max_items) {
+    const int r = resident_entry(ci);
+    if (r < 0 || max_items < 1) return false;
+    int& cap = g_res_cap[r];
+    if (cap == 0) {
+        cap = persistent_blocks(reinterpret_cast<const void*>(kRes[r].fn), kRes[r].nt, 0);
+        if (cap <= 0) cap = -1;
+    }
+    return cap > 0 && ((max_items + 7) / 8) * 8 <= cap;
+}
+
+int launch_resident(int ci, const ImgDesc& d, const int2* queue, const int32_t* n_queue,
+                    const int32_t* mflags, int32_t* epoch, int32_t* status, int64_t max_items,
+                    int in_buf, int iters, int per, int inner, float theta, float inv_theta,
+                    float tau, hipStream_t st) {
+    const int r = resident_entry(ci);
+    if (r < 0 || !resident_fits(ci, max_items)) return -1;
+    // epoch[0 .. max_items) and *status start at 0
+    if (launch_fill(reinterpret_cast<float*>(epoch), 1, (int)max_items, (int)max_items, 0.0f, st) ||
+        launch_fill(reinterpret_cast<float*>(status), 1, 1, 1, 0.0f, st))
+        return 1;
+    const unsigned grid = (unsigned)(((max_items + 7) / 8) * 8);
+    ImgDesc dd = d;
+    void* args[] = {&dd,     &queue, &n_queue, &mflags, &epoch,     &status, &in_buf,
+                    &iters,  &per,   &inner,   &theta,  &inv_theta, &tau};
+    const hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kRes[r].fn),
+                                                    dim3(grid), dim3(kRes[r].nt), args, 0, st);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return -1;   // not launched: the caller falls back to separate launches
+    }
+    return 0;
 }
 
 int launch_init(const ImgDesc* d0, const ImgDesc* descs, OffTables off, int n_img,

@@ -145,6 +145,20 @@ int config_index(int bx, int by, int it);   // -1 if not compiled
 // Occupancy query for the persistent grid of configuration ci (cached).
 int prepare_iterate(int ci, bool batched, bool stop = false);
 
+// Resident form of a whole single-image solve: whether configuration ci has a
+// resident kernel whose workgroups, one per queued macro tile (at most
+// max_items), all fit on the chip at once; and the launch, which runs `iters`
+// outer iterations in blocks of `per` (per * inner <= cfg.it), reading buffer
+// in_buf and leaving the final state where the equivalent separate launches
+// would.  epoch: max_items int32 of workspace, status: one int32 (set to 1 if a
+// bounded wait expired, in which case u holds NaN).  Returns 0 when launched,
+// -1 when the resident form does not apply (nothing was enqueued), > 0 on error.
+bool resident_fits(int ci, int64_t max_items);
+int launch_resident(int ci, const ImgDesc& d, const int2* queue, const int32_t* n_queue,
+                    const int32_t* mflags, int32_t* epoch, int32_t* status, int64_t max_items,
+                    int in_buf, int iters, int per, int inner, float theta, float inv_theta,
+                    float tau, hipStream_t st);
+
 // Per-launch arguments of the convergence-driven solve: skip the launch when
 // *skip_slot <= tol (skip_slot nullable); reduce the last iteration's change
 // into *diff_slot (nullable: this launch does not end at a check).

@@ -414,6 +414,20 @@ def timing_read(config=-1):
     return ms.value, n.value, b.value, upd.value
 
 
+def timing_read_form(config=-1, form=-1):
+    """As timing_read, for one form of launch: 0 = separate launches of the
+    blocked kernel, 1 = resident launches (one per solve), -1 = both."""
+    ms, n, b, upd = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double(), ctypes.c_int64()
+    check(_lib.load().rdseg_timing_read_form(int(config), int(form), ctypes.byref(ms),
+                                             ctypes.byref(n), ctypes.byref(b), ctypes.byref(upd)))
+    return ms.value, n.value, b.value, upd.value
+
+
+def set_resident(on=True):
+    """Allow (default) or forbid the resident form of single-image solves."""
+    check(_lib.load().rdseg_set_resident(1 if on else 0))
+
+
 def timing_reset():
     check(_lib.load().rdseg_timing_reset())
 

@@ -180,6 +180,44 @@ def test_autotune_restrictions(rd):
     for x, y in zip(a, b):
         np.testing.assert_array_equal(x, y)
 
+
+@pytest.mark.parametrize("shape,tile,ipl,frac,iters", [
+    ((1024, 1024), (64, 64), 8, math.inf, 61),
+    ((1024, 1024), (64, 64), 8, 0.5, 40),
+    ((700, 515), (64, 64), 8, 0.3, 33),
+    ((300, 257), (64, 32), 4, 0.5, 29),
+    ((64, 64), (64, 64), 8, math.inf, 5),
+])
+def test_resident_matches_separate_launches(rd, shape, tile, ipl, frac, iters):
+    """Single-image solves whose tiles fit on the chip run as one resident
+    launch; the results equal those of separate launches bit for bit, and the
+    resident form is the one that ran (timing records of form 1)."""
+    H, W = shape
+    f = synth.smooth_field(H, W, 31, noise=0.2)
+    delta = synth.band_delta(f, frac) if math.isfinite(frac) else math.inf
+    ft = dev(f)
+    say(f"resident {shape} tile={tile} ipl={ipl} frac={frac} iters={iters}")
+    try:
+        rd.set_resident(False)
+        sep = [host(x) for x in rd.solve(ft, 3.0, 0.1, 0.125, delta, iters, tile=tile,
+                                         iters_per_launch=ipl)]
+        rd.set_resident(True)
+        rd.timing_reset()
+        rd.timing_enable(True)
+        res = [host(x) for x in rd.solve(ft, 3.0, 0.1, 0.125, delta, iters, tile=tile,
+                                         iters_per_launch=ipl)]
+        ms, n, _, _ = rd.timing_read_form(-1, 1)
+    finally:
+        rd.timing_enable(False)
+        rd.timing_reset()
+        rd.set_resident(True)
+    assert n == 1, "the resident form did not run"
+    for a, b in zip(res, sep):
+        np.testing.assert_array_equal(a, b)
+    if H * W <= 300 * 257:
+        uo, vo, po = oracle.solve(f, 3.0, 0.1, 0.125, delta, iters)
+        assert np.abs(res[0] - uo).max() <= U_TOL
+
 def test_determinism_and_resume(rd):
     f = synth.smooth_field(96, 130, 25, noise=0.2)
     ft = dev(f)
