@@ -1,8 +1,9 @@
 """Summaries of rocprofv3 result databases (rocpd SQLite) for the profiles/ notes.
 
-    python -m paper_1807_11534_amd.profiling --trace T.db [--fetch F.db --write W.db]
+    python -m paper_1807_11534_amd.profiling [--trace T.db] [--fetch F.db] [--write W.db]
         [--kernel SUBSTRING] [--copy-mib N] [--bench-json B.json] [--traced-json T.out]
         [--fetch-json F.out] [--write-json W.out]
+    python -m paper_1807_11534_amd.profiling --combine PART.md [PART.md ...]
 
 --trace    database of `rocprofv3 --kernel-trace --stats`
 --fetch    database of `rocprofv3 --pmc FETCH_SIZE`   (KiB per dispatch)
@@ -17,7 +18,10 @@
            pass gives the dispatches averaged)
 Prints a short markdown report: per-kernel duration table, and for the kernel
 matching --kernel its average duration, calibrated HBM bytes per launch and,
-with --bench-json, the benchmark's live figures beside them.
+with --bench-json, the benchmark's live figures beside them.  Each counter
+run also prints a `counter_bytes_per_launch:` line; --combine reads such
+partial reports (from separate profiler runs) and prints the traffic record
+(FETCH_SIZE + WRITE_SIZE bytes per launch of one kernel).
 """
 import argparse
 import glob
@@ -132,7 +136,8 @@ def short(name):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--trace", required=True)
+    ap.add_argument("--combine", nargs="+", metavar="PART.md")
+    ap.add_argument("--trace")
     ap.add_argument("--fetch")
     ap.add_argument("--write")
     ap.add_argument("--kernel", help="substring of the kernel name (default: the "
@@ -145,31 +150,36 @@ def main():
     ap.add_argument("--top", type=int, default=12)
     a = ap.parse_args()
 
+    if a.combine:
+        combine(a.combine)
+        return
     if not a.kernel:
-        src = a.traced_json or a.bench_json
+        src = a.traced_json or a.bench_json or a.fetch_json or a.write_json
         if not src:
             ap.error("--kernel or a benchmark output is needed")
         lines = [l for l in open(src).read().splitlines() if l.strip().startswith("{")]
         a.kernel = json.loads(lines[-1])["roofline"]["kernel"].replace(",", ", ").rstrip(">")
-    rows = kernel_stats(a.trace)
-    print("| kernel | calls | total us | avg us | % |")
-    print("|---|---:|---:|---:|---:|")
-    for name, calls, tot, avg, pct in rows[: a.top]:
-        print(f"| `{short(name)}` | {calls} | {tot:.1f} | {avg:.3f} | {pct:.1f} |")
-    sel = [r for r in rows if a.kernel in r[0]]
-    if not sel:
-        print(f"\nno kernel matches {a.kernel!r}")
-        return
-    name, calls, tot, avg, pct = sel[0]
-    print(f"\nselected kernel `{short(name)}`: {calls} dispatches in the trace (tuning probes "
-          f"included), average {avg:.3f} us")
+    name = a.kernel
+    if a.trace:
+        rows = kernel_stats(a.trace)
+        print("| kernel | calls | total us | avg us | % |")
+        print("|---|---:|---:|---:|---:|")
+        for name, calls, tot, avg, pct in rows[: a.top]:
+            print(f"| `{short(name)}` | {calls} | {tot:.1f} | {avg:.3f} | {pct:.1f} |")
+        sel = [r for r in rows if a.kernel in r[0]]
+        if not sel:
+            print(f"\nno kernel matches {a.kernel!r}")
+            return
+        name, calls, tot, avg, pct = sel[0]
+        print(f"\nselected kernel `{short(name)}`: {calls} dispatches in the trace (tuning probes "
+              f"included), average {avg:.3f} us")
 
     def bench_line(path):
         lines = [l for l in open(path).read().splitlines() if l.strip().startswith("{")]
         return json.loads(lines[-1])
 
     bench = None
-    if a.traced_json:
+    if a.traced_json and a.trace:
         r = bench_line(a.traced_json)["roofline"]
         durs, total = last_dispatches(a.trace, a.kernel, r["launches"])
         mean = sum(durs) / len(durs)
@@ -186,6 +196,10 @@ def main():
               f"achieved {r['achieved']:.1f} GB/s ({r['frac']:.3f} of peak)")
     total = 0.0
     n_counters = 0
+    if a.fetch or a.write:
+        src = a.fetch_json or a.write_json or a.bench_json
+        kname = bench_line(src)["roofline"]["kernel"] if src else record_name(None, name)
+        print(f"\ncombine_kernel: {kname}")
     runs = {"fetch": a.fetch_json, "write": a.write_json}
     for label, db, counter in [("fetch", a.fetch, "FETCH_SIZE"), ("write", a.write, "WRITE_SIZE")]:
         if not db:
@@ -212,13 +226,41 @@ def main():
                           f"average {kib:.1f} KiB raw, {kib * factor * 1024 / 1e6:.3f} MB calibrated")
             total += kib * factor * 1024
             n_counters += 1
+            print(f"counter_bytes_per_launch: {counter} {kib * factor * 1024:.0f}")
     if n_counters == 2:
         print("\nmachine-readable record (read by bench.py for roofline.traffic):\n")
         print("```")
-        print(f"traffic_kernel: {bench['roofline']['kernel'] if bench else short(name)}")
+        print(f"traffic_kernel: {record_name(bench, name)}")
         print(f"traffic_bytes_per_launch: {total:.0f}")
         print(f"traffic_source_digest: {kernel_source_digest()}")
         print("```")
+
+
+def record_name(bench, name):
+    """Kernel name as the benchmark's roofline reports it (no spaces)."""
+    if bench:
+        return bench["roofline"]["kernel"]
+    return short(name).replace(" ", "").split(",false")[0].split(",true")[0].rstrip(">") + ">"
+
+
+def combine(parts):
+    """Traffic record from partial reports of separate counter runs of one
+    kernel (each holding `counter_bytes_per_launch:` lines and a
+    `combine_kernel:` line)."""
+    got, kernels = {}, set()
+    for path in parts:
+        text = open(path).read()
+        for c, v in re.findall(r"^counter_bytes_per_launch: (\S+) ([0-9.eE+]+)$", text, re.M):
+            got[c] = float(v)
+        kernels.update(k.strip() for k in re.findall(r"^combine_kernel: (.+)$", text, re.M))
+    if set(got) != {"FETCH_SIZE", "WRITE_SIZE"} or len(kernels) != 1:
+        raise SystemExit("need one FETCH_SIZE and one WRITE_SIZE report of the same kernel")
+    print("machine-readable record (read by bench.py for roofline.traffic):\n")
+    print("```")
+    print(f"traffic_kernel: {kernels.pop()}")
+    print(f"traffic_bytes_per_launch: {got['FETCH_SIZE'] + got['WRITE_SIZE']:.0f}")
+    print(f"traffic_source_digest: {kernel_source_digest()}")
+    print("```")
 
 
 if __name__ == "__main__":
