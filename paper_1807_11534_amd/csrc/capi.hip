@@ -453,11 +453,11 @@ rdseg_status enqueue_iterations(SolvePlanArgs& a) {
         if (timed) {
             rec.e0 = timing_event();
             rec.e1 = timing_event();
-            if (rec.e0) (void)hipEventRecord(rec.e0, a.st);
         }
         const int rc = launch_resident(a.ci, *a.d0, a.queue, a.n_queue, a.mflags, a.epoch,
                                        a.epoch + a.max_items, a.max_items, L % 2, a.iters, IT,
-                                       a.inner, a.theta, a.inv_theta, a.tau, a.st);
+                                       a.inner, a.theta, a.inv_theta, a.tau, a.st,
+                                       timed ? rec.e0 : nullptr);
         if (rc > 0) return RDSEG_ERR_HIP;
         if (rc == 0) {
             a.launches = 1;
@@ -477,6 +477,11 @@ rdseg_status enqueue_iterations(SolvePlanArgs& a) {
             return RDSEG_OK;
         }
         // rc < 0: not applicable, fall through to separate launches
+        if (timed) {
+            std::lock_guard<std::mutex> lk(g_timing.mu);
+            if (rec.e0) g_timing.pool.push_back(rec.e0);
+            if (rec.e1) g_timing.pool.push_back(rec.e1);
+        }
     }
     size_t seg = 0;
     const int64_t plane = (int64_t)a.d0->H * a.d0->ld;

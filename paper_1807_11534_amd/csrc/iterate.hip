@@ -897,13 +897,14 @@ bool resident_fits(int ci, int64_t max_items) {
 int launch_resident(int ci, const ImgDesc& d, const int2* queue, const int32_t* n_queue,
                     const int32_t* mflags, int32_t* epoch, int32_t* status, int64_t max_items,
                     int in_buf, int iters, int per, int inner, float theta, float inv_theta,
-                    float tau, hipStream_t st) {
+                    float tau, hipStream_t st, hipEvent_t before) {
     const int r = resident_entry(ci);
     if (r < 0 || !resident_fits(ci, max_items)) return -1;
     // epoch[0 .. max_items) and *status start at 0
     if (launch_fill(reinterpret_cast<float*>(epoch), 1, (int)max_items, (int)max_items, 0.0f, st) ||
         launch_fill(reinterpret_cast<float*>(status), 1, 1, 1, 0.0f, st))
         return 1;
+    if (before) (void)hipEventRecord(before, st);
     const unsigned grid = (unsigned)(((max_items + 7) / 8) * 8);
     ImgDesc dd = d;
     void* args[] = {&dd,     &queue, &n_queue, &mflags, &epoch,     &status, &in_buf,

@@ -153,11 +153,12 @@ int prepare_iterate(int ci, bool batched, bool stop = false);
 // would.  epoch: max_items int32 of workspace, status: one int32 (set to 1 if a
 // bounded wait expired, in which case u holds NaN).  Returns 0 when launched,
 // -1 when the resident form does not apply (nothing was enqueued), > 0 on error.
+// `before` (nullable) is recorded on st right before the resident kernel.
 bool resident_fits(int ci, int64_t max_items);
 int launch_resident(int ci, const ImgDesc& d, const int2* queue, const int32_t* n_queue,
                     const int32_t* mflags, int32_t* epoch, int32_t* status, int64_t max_items,
                     int in_buf, int iters, int per, int inner, float theta, float inv_theta,
-                    float tau, hipStream_t st);
+                    float tau, hipStream_t st, hipEvent_t before);
 
 // Per-launch arguments of the convergence-driven solve: skip the launch when
 // *skip_slot <= tol (skip_slot nullable); reduce the last iteration's change
