@@ -127,41 +127,61 @@ __global__ __launch_bounds__(256) void k_sum_i64(const int64_t* __restrict__ a, 
 }
 
 // ---------------------------------------------------------------- tile masks
+// One wave per 8-row x 64-column strip (grid-stride): 8 ballots give the 8
+// tile masks.  The RD pixel count of a single image is summed per workgroup
+// and added with one atomic per workgroup (thousands of waves adding to one
+// counter serialise at the memory-side atomic unit); batched images keep one
+// atomic per strip, on their own counters.
 template <bool BATCHED>
 __global__ __launch_bounds__(256) void k_tile_masks(ImgDesc d0, const ImgDesc* __restrict__ descs,
                                                     OffTables off, int n_img, int64_t n_strips,
                                                     uint64_t* __restrict__ masks,
                                                     int64_t* __restrict__ npix) {
-    int64_t s = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (s >= n_strips) return;   // uniform per wave
-    int lane = threadIdx.x & 63;
-    int img = BATCHED ? find_image(off.soff, n_img, s) : 0;
-    const ImgDesc& d = BATCHED ? descs[img] : d0;
-    int64_t ls = s - (BATCHED ? off.soff[img] : 0);
-    int sw = (d.tw + 7) >> 3;
-    int ty = (int)(ls / sw);
-    int sx = (int)(ls - (int64_t)ty * sw);
-    int x = sx * 64 + lane;
-    uint64_t b[8];
-    int cnt = 0;
+    __shared__ unsigned long long sCnt[4];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    unsigned long long mine = 0;
+    for (int64_t s = (int64_t)blockIdx.x * 4 + wv; s < n_strips; s += (int64_t)gridDim.x * 4) {
+        int img = BATCHED ? find_image(off.soff, n_img, s) : 0;
+        const ImgDesc& d = BATCHED ? descs[img] : d0;
+        int64_t ls = s - (BATCHED ? off.soff[img] : 0);
+        int sw = (d.tw + 7) >> 3;
+        int ty = (int)(ls / sw);
+        int sx = (int)(ls - (int64_t)ty * sw);
+        int x = sx * 64 + lane;
+        uint64_t b[8];
+        int cnt = 0;
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
-        int y = ty * 8 + r;
-        bool a = false;
-        if (x < d.W && y < d.H) a = fabs((double)d.f[(int64_t)y * d.ld + x]) < d.delta;
-        b[r] = __ballot(a);
-        cnt += __popcll(b[r]);
-    }
-    if (lane < 8) {
-        int tx = sx * 8 + lane;
-        if (tx < d.tw) {
-            uint64_t m = 0;
+        for (int r = 0; r < 8; ++r) {
+            int y = ty * 8 + r;
+            bool a = false;
+            if (x < d.W && y < d.H) a = fabs((double)d.f[(int64_t)y * d.ld + x]) < d.delta;
+            b[r] = __ballot(a);
+            cnt += __popcll(b[r]);
+        }
+        if (lane < 8) {
+            int tx = sx * 8 + lane;
+            if (tx < d.tw) {
+                uint64_t m = 0;
 #pragma unroll
-            for (int r = 0; r < 8; ++r) m |= ((b[r] >> (8 * lane)) & 0xFFull) << (8 * r);
-            masks[d.toff + (int64_t)ty * d.tw + tx] = m;
+                for (int r = 0; r < 8; ++r) m |= ((b[r] >> (8 * lane)) & 0xFFull) << (8 * r);
+                masks[d.toff + (int64_t)ty * d.tw + tx] = m;
+            }
+        }
+        if (BATCHED) {
+            if (lane == 0 && cnt) atomicAdd((unsigned long long*)&npix[img], (unsigned long long)cnt);
+        } else {
+            mine += (unsigned long long)cnt;
         }
     }
-    if (lane == 0 && cnt) atomicAdd((unsigned long long*)&npix[img], (unsigned long long)cnt);
+    if (!BATCHED) {
+        if (lane == 0) sCnt[wv] = mine;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const unsigned long long tot = sCnt[0] + sCnt[1] + sCnt[2] + sCnt[3];
+            if (tot) atomicAdd((unsigned long long*)npix, tot);
+        }
+    }
 }
 
 __global__ void k_mask_flags(const uint64_t* __restrict__ masks, int64_t n,
@@ -247,39 +267,36 @@ __device__ __forceinline__ bool tile_touches_neighbour(const uint64_t* __restric
     return touch != 0;
 }
 
+// One wave per macro tile, one lane per 8x8 tile of it (a macro tile holds at
+// most 8 x 8 of them): a tile is open when one of its RD pixels has an RD
+// 4-neighbour in another tile; the macro tile is queued when it holds an open
+// tile, and each closed tile of an unqueued macro tile is flagged for the
+// closed-tile kernel.
 template <bool BATCHED>
-__global__ void k_lists(ImgDesc d0, const ImgDesc* __restrict__ descs, OffTables off, int n_img,
-                        int64_t n_macro, int bx8, int by8, const uint64_t* __restrict__ masks,
-                        int use_closed, int32_t* __restrict__ mflags,
-                        int32_t* __restrict__ cflags) {
-    int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= n_macro) return;
-    int img = BATCHED ? find_image(off.moff, n_img, m) : 0;
+__global__ __launch_bounds__(256) void k_lists(ImgDesc d0, const ImgDesc* __restrict__ descs,
+                                               OffTables off, int n_img, int64_t n_macro, int bx8,
+                                               int by8, const uint64_t* __restrict__ masks,
+                                               int use_closed, int32_t* __restrict__ mflags,
+                                               int32_t* __restrict__ cflags) {
+    const int64_t m = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (m >= n_macro) return;   // uniform per wave
+    const int lane = threadIdx.x & 63;
+    const int img = BATCHED ? find_image(off.moff, n_img, m) : 0;
     const ImgDesc& d = BATCHED ? descs[img] : d0;
-    int64_t lm = m - (BATCHED ? off.moff[img] : 0);
-    int my = (int)(lm / d.mw), mx = (int)(lm - (int64_t)my * d.mw);
-    int ty0 = my * by8, tx0 = mx * bx8;
-    int ty1 = min(d.th, ty0 + by8), tx1 = min(d.tw, tx0 + bx8);
-    int any_open = 0;
-    uint64_t closed_bits = 0;   // at most 8 x 8 tiles per macro tile
-    int k = 0;
-    for (int ty = ty0; ty < ty1; ++ty)
-        for (int tx = tx0; tx < tx1; ++tx, ++k) {
-            const int64_t T = d.toff + (int64_t)ty * d.tw + tx;
-            const uint64_t mk = masks[T];
-            if (!mk) continue;
-            if (!use_closed || tile_touches_neighbour(masks, T, tx, ty, d.tw, d.th, mk))
-                any_open = 1;
-            else
-                closed_bits |= 1ull << k;
-        }
-    mflags[m] = any_open;
-    if (!use_closed) return;
-    k = 0;
-    for (int ty = ty0; ty < ty1; ++ty)
-        for (int tx = tx0; tx < tx1; ++tx, ++k)
-            cflags[d.toff + (int64_t)ty * d.tw + tx] =
-                (!any_open && ((closed_bits >> k) & 1ull)) ? 1 : 0;
+    const int64_t lm = m - (BATCHED ? off.moff[img] : 0);
+    const int my = (int)(lm / d.mw), mx = (int)(lm - (int64_t)my * d.mw);
+    const int tx = mx * bx8 + lane % bx8, ty = my * by8 + lane / bx8;
+    const bool mine = lane < bx8 * by8 && tx < d.tw && ty < d.th;
+    const int64_t T = d.toff + (int64_t)ty * d.tw + tx;
+    uint64_t mk = 0;
+    bool open = false;
+    if (mine) {
+        mk = masks[T];
+        if (mk) open = !use_closed || tile_touches_neighbour(masks, T, tx, ty, d.tw, d.th, mk);
+    }
+    const bool any_open = __ballot(open) != 0ull;
+    if (lane == 0) mflags[m] = any_open ? 1 : 0;
+    if (use_closed && mine) cflags[T] = (!any_open && mk && !open) ? 1 : 0;
 }
 
 // Exclusive scans of up to two int32 arrays of at most SMALL_N elements, one
@@ -387,8 +404,8 @@ int launch_tile_masks(const ImgDesc* d0, const ImgDesc* descs, OffTables off, in
         hipLaunchKernelGGL(k_tile_masks<true>, dim3(nblk(n_strips, 4)), dim3(256), 0, st, *d0,
                            descs, off, n_img, n_strips, masks, npix);
     else
-        hipLaunchKernelGGL(k_tile_masks<false>, dim3(nblk(n_strips, 4)), dim3(256), 0, st, *d0,
-                           descs, off, n_img, n_strips, masks, npix);
+        hipLaunchKernelGGL(k_tile_masks<false>, dim3(std::min<int64_t>(nblk(n_strips, 4), 512)),
+                           dim3(256), 0, st, *d0, descs, off, n_img, n_strips, masks, npix);
     RDSEG_HIP_CHECK(hipGetLastError());
     return 0;
 }
@@ -433,11 +450,11 @@ int launch_macro_queue(const ImgDesc* d0, const ImgDesc* descs, OffTables off, i
                        int2* cqueue, int32_t* n_closed, hipStream_t st) {
     const bool use_closed = cqueue != nullptr;
     if (descs)
-        hipLaunchKernelGGL(k_lists<true>, dim3(nblk(n_macro, 64)), dim3(64), 0, st, *d0, descs,
+        hipLaunchKernelGGL(k_lists<true>, dim3(nblk(n_macro, 4)), dim3(256), 0, st, *d0, descs,
                            off, n_img, n_macro, bx / 8, by / 8, masks, use_closed ? 1 : 0,
                            q.mflags, q.cflags);
     else
-        hipLaunchKernelGGL(k_lists<false>, dim3(nblk(n_macro, 64)), dim3(64), 0, st, *d0, descs,
+        hipLaunchKernelGGL(k_lists<false>, dim3(nblk(n_macro, 4)), dim3(256), 0, st, *d0, descs,
                            off, n_img, n_macro, bx / 8, by / 8, masks, use_closed ? 1 : 0,
                            q.mflags, q.cflags);
     if (n_macro <= SMALL_N && (!use_closed || n_tiles <= SMALL_N)) {

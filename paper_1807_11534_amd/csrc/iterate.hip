@@ -815,10 +815,12 @@ const CfgEntry kCfgs[] = {
     RDSEG_CFG(8, 8, 4, 128),
     RDSEG_CFG(8, 8, 8, 256),
     RDSEG_CFG(8, 8, 16, 512),
+    RDSEG_CFG(8, 8, 32, 512),
     RDSEG_CFG(16, 16, 1, 128),
     RDSEG_CFG(16, 16, 2, 128),
     RDSEG_CFG(16, 16, 4, 256),
     RDSEG_CFG(16, 16, 8, 512),
+    RDSEG_CFG(16, 16, 16, 512),
     RDSEG_CFG(32, 16, 2, 256),
     RDSEG_CFG(32, 32, 2, 256),
     RDSEG_CFG(32, 32, 4, 256),
