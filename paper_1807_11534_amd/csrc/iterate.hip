@@ -441,132 +441,6 @@ __global__ __launch_bounds__(NT) void k_iterate(ImgDesc d0, const ImgDesc* __res
     }
 }
 
-// Every iteration of one closed 8x8 tile per 64-thread workgroup.  A closed
-// tile's RD pixels have no RD 4-neighbour outside the tile, so the only values
-// they read from outside are the constants of frozen neighbours (p = 0,
-// w = -H(-f)/theta): the region is the tile plus a one-pixel ring, and the ring
-// never changes.  (An RD pixel of the ring belongs to another component and
-// is never read by this tile's RD pixels; it is held as a frozen cell.)  The
-// per-pixel arithmetic is that of k_iterate, so results are bitwise equal.
-template <bool BATCHED>
-__global__ __launch_bounds__(64) void k_closed(ImgDesc d0, const ImgDesc* __restrict__ descs,
-                                               const int2* __restrict__ cqueue,
-                                               const int32_t* __restrict__ n_closed, int iters,
-                                               int inner, float theta, float inv_theta,
-                                               float tau) {
-    constexpr int RX = 10;
-    constexpr int RC = RX * RX;
-    constexpr int CPT = 2;
-    constexpr int PAD = RX + 1;
-    constexpr int LS = RC + 2 * PAD;
-    __shared__ float sPX[LS];
-    __shared__ float sPY[LS];
-    __shared__ float sW[LS];
-    const int t = threadIdx.x;
-    for (int k = t; k < PAD; k += 64) {
-        sPX[k] = 0.0f; sPY[k] = 0.0f; sW[k] = 0.0f;
-        sPX[PAD + RC + k] = 0.0f; sPY[PAD + RC + k] = 0.0f; sW[PAD + RC + k] = 0.0f;
-    }
-    const int n = *n_closed;
-    for (int item = blockIdx.x; item < n; item += gridDim.x) {
-        const int2 q = cqueue[item];
-        const ImgDesc& d = BATCHED ? descs[q.x] : d0;
-        const int ty = q.y / d.tw;
-        const int tx = q.y - ty * d.tw;
-        const int ox = tx * 8 - 1, oy = ty * 8 - 1;
-        float rv[CPT], rpx[CPT], rpy[CPT], rc[CPT];
-        uint32_t fl[CPT];
-        int gi[CPT];
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < CPT; ++j) {
-            const int i = t + j * 64;
-            rv[j] = 0.0f; rpx[j] = 0.0f; rpy[j] = 0.0f; rc[j] = __builtin_inff();
-            fl[j] = 0u; gi[j] = 0;
-            if (i < RC) {
-                const int ry = i / RX, rx = i - ry * RX;
-                const int gx = ox + rx, gy = oy + ry;
-                const bool inb = (unsigned)gx < (unsigned)d.W && (unsigned)gy < (unsigned)d.H;
-                const bool ring = rx == 0 || rx == RX - 1 || ry == 0 || ry == RX - 1;
-                const int g = gy * d.ld + gx;
-                gi[j] = g;
-                float c = inb ? d.c[g] : __builtin_inff();
-                if (ring && c_active(c)) c = __builtin_inff();   // held as a frozen cell
-                const bool act = c_active(c);
-                rc[j] = c;
-                if (act) {
-                    rv[j] = d.st[0][0][g];
-                    rpx[j] = d.st[0][1][g];
-                    rpy[j] = d.st[0][2][g];
-                } else {
-                    rv[j] = heav_from_c(c);
-                }
-                uint32_t f = act ? (CF_ACT | CF_OUT) : 0u;
-                if (gx == d.W - 1) f |= CF_LASTC;
-                if (gy == d.H - 1) f |= CF_LASTR;
-                fl[j] = f;
-                sPX[PAD + i] = rpx[j];
-                sPY[PAD + i] = rpy[j];
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < CPT; ++j) {
-            const int i = t + j * 64;
-            if (i < RC) {
-                float dd = div_p(rpx[j], sPX[PAD + i - 1], rpy[j], sPY[PAD + i - RX]);
-                sW[PAD + i] = w_of(dd, rv[j], inv_theta, (fl[j] & CF_ACT) != 0);
-            }
-        }
-        __syncthreads();
-        const int steps = iters * inner;
-        int left = inner;   // dual steps left in the current outer iteration
-        for (int it = 0; it < steps; ++it) {
-#pragma unroll
-            for (int j = 0; j < CPT; ++j) {
-                const int i = t + j * 64;
-                if (i < RC) {
-                    DualOut o = dual_update(rpx[j], rpy[j], sW[PAD + i], sW[PAD + i + 1],
-                                            sW[PAD + i + RX], fl[j], tau);
-                    rpx[j] = o.px;
-                    rpy[j] = o.py;
-                    sPX[PAD + i] = o.px;
-                    sPY[PAD + i] = o.py;
-                }
-            }
-            __syncthreads();
-            const bool last = (it == steps - 1);
-            const bool outer_end = --left == 0;
-            if (outer_end) left = inner;
-#pragma unroll
-            for (int j = 0; j < CPT; ++j) {
-                const int i = t + j * 64;
-                if (i < RC) {
-                    float dd = div_p(rpx[j], sPX[PAD + i - 1], rpy[j], sPY[PAD + i - RX]);
-                    if (outer_end) {
-                        float u = u_step(rv[j], dd, theta);
-                        rv[j] = v_step(u, rc[j]);
-                        if (last) {
-                            if (fl[j] & CF_OUT) d.u[gi[j]] = u;
-                            continue;
-                        }
-                    }
-                    sW[PAD + i] = w_of(dd, rv[j], inv_theta, (fl[j] & CF_ACT) != 0);
-                }
-            }
-            __syncthreads();
-        }
-#pragma unroll
-        for (int j = 0; j < CPT; ++j) {
-            if (fl[j] & CF_OUT) {
-                d.st[0][0][gi[j]] = rv[j];
-                d.st[0][1][gi[j]] = rpx[j];
-                d.st[0][2][gi[j]] = rpy[j];
-            }
-        }
-    }
-}
-
 // Resident variant of the blocked iteration (single image, no checkpoint
 // tape, no stopping rule), for images whose queued macro tiles fit on the
 // chip at once (a cooperative launch guarantees that every workgroup is
@@ -1025,40 +899,6 @@ int launch_stop_finalize(const ImgDesc& d, const uint32_t* slots, int n_checks, 
     const unsigned grid = (unsigned)(d.H < 4096 ? d.H : 4096);
     hipLaunchKernelGGL(k_stop_copy, dim3(grid), dim3(256), 0, st, d, (const int32_t*)iters_done,
                        check_every, launches_per_check, n_launches, iters);
-    RDSEG_HIP_CHECK(hipGetLastError());
-    return 0;
-}
-
-int g_closed_grid[2] = {0, 0};
-
-int prepare_closed(bool batched) {
-    const void* fn = batched ? reinterpret_cast<const void*>(k_closed<true>)
-                             : reinterpret_cast<const void*>(k_closed<false>);
-    int& cached = g_closed_grid[batched ? 1 : 0];
-    if (cached == 0) {
-        cached = persistent_blocks(fn, 64, 0);
-        if (cached <= 0) {
-            cached = 0;
-            set_error("occupancy query failed for the closed-tile kernel");
-            return 4;
-        }
-    }
-    return 0;
-}
-
-int launch_closed(const ImgDesc* d0, const ImgDesc* descs, bool batched, const int2* cqueue,
-                  const int32_t* n_closed, int64_t max_items, int iters, float theta,
-                  float inv_theta, float tau, hipStream_t st, int inner) {
-    if (prepare_closed(batched)) return 4;
-    int64_t g = g_closed_grid[batched ? 1 : 0];
-    if (max_items < g) g = max_items;
-    if (g < 1) g = 1;
-    if (batched)
-        hipLaunchKernelGGL(k_closed<true>, dim3((unsigned)g), dim3(64), 0, st, *d0, descs, cqueue,
-                           n_closed, iters, inner, theta, inv_theta, tau);
-    else
-        hipLaunchKernelGGL(k_closed<false>, dim3((unsigned)g), dim3(64), 0, st, *d0, descs, cqueue,
-                           n_closed, iters, inner, theta, inv_theta, tau);
     RDSEG_HIP_CHECK(hipGetLastError());
     return 0;
 }
