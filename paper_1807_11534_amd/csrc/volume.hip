@@ -9,9 +9,9 @@
 // planes, streamed along z (see k_stream3): the x-y halo is two voxels on the
 // low side and one on the high side, the z neighbours pass from one plane to
 // the next in registers.  Deeper temporal blocking would multiply the halo
-// volume, so the kernel streams its 36 bytes per voxel (read c, v, p: 20;
-// write v, p: 16) from HBM.  Tiles without a voxel of RD return at once (flags
-// computed once per solve).
+// volume, so the kernel streams its 36 bytes per voxel of RD (read c, v, p:
+// 20; write v, p: 16) from HBM; frozen voxels cost their 4-byte c alone.
+// Tiles without a voxel of RD return at once (flags computed once per solve).
 #include <algorithm>
 
 #include "rdseg_internal.h"
@@ -141,17 +141,27 @@ __global__ __launch_bounds__(NT) void k_stream3(VolDesc d, const int32_t* __rest
         c1[j] = __builtin_inff(); v1[j] = 0.0f; px1[j] = 0.0f; py1[j] = 0.0f; pz1[j] = 0.0f;
         w1[j] = 0.0f; pzn2[j] = 0.0f;
     }
-    // raw loads of the next plane, issued one step ahead so that their
-    // latency overlaps the three phases of the current plane
-    float lc[CPT], lv[CPT], lpx[CPT], lpy[CPT], lpz[CPT];
-    auto fetch = [&](int z) {
+    // Raw loads run ahead of the planes they feed: c two planes ahead, the
+    // state (v, p) of the next plane one plane ahead and only for its RD
+    // voxels (the state of a frozen voxel is not used, so lines holding only
+    // frozen voxels are never fetched), so that their latency overlaps the
+    // three phases of the current plane.
+    float lc[CPT], nc[CPT], lv[CPT], lpx[CPT], lpy[CPT], lpz[CPT];
+    auto fetch_c = [&](int z, float* dst) {
         const bool zin = z >= 0 && z < d.D;
 #pragma unroll
         for (int j = 0; j < CPT; ++j) {
-            lc[j] = __builtin_inff(); lv[j] = 0.0f; lpx[j] = 0.0f; lpy[j] = 0.0f; lpz[j] = 0.0f;
-            if (zin && (fxy[j] & XY_IN)) {   // state off RD is discarded after use
+            dst[j] = __builtin_inff();
+            if (zin && (fxy[j] & XY_IN)) dst[j] = d.c[z * d.lds + gxy[j]];
+        }
+    };
+    auto fetch_state = [&](int z) {   // plane z, whose c is in lc
+        const bool zin = z >= 0 && z < d.D;
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) {
+            lv[j] = 0.0f; lpx[j] = 0.0f; lpy[j] = 0.0f; lpz[j] = 0.0f;
+            if (zin && (fxy[j] & XY_IN) && c_active(lc[j])) {
                 const int g = z * d.lds + gxy[j];
-                lc[j] = d.c[g];
                 lv[j] = Vi[g];
                 lpx[j] = PXi[g];
                 lpy[j] = PYi[g];
@@ -159,7 +169,9 @@ __global__ __launch_bounds__(NT) void k_stream3(VolDesc d, const int32_t* __rest
             }
         }
     };
-    fetch(z0 - 2);
+    fetch_c(z0 - 2, lc);
+    fetch_state(z0 - 2);
+    fetch_c(z0 - 1, nc);
     int cur = 0;
     for (int s = z0 - 2; s <= z1; ++s) {
         float c0[CPT], v0[CPT], px0[CPT], py0[CPT], pz0[CPT], w0[CPT];
@@ -173,7 +185,12 @@ __global__ __launch_bounds__(NT) void k_stream3(VolDesc d, const int32_t* __rest
             py0[j] = act ? lpy[j] : 0.0f;
             pz0[j] = act ? lpz[j] : 0.0f;
         }
-        if (s < z1) fetch(s + 1);
+        if (s < z1) {
+#pragma unroll
+            for (int j = 0; j < CPT; ++j) lc[j] = nc[j];
+            fetch_state(s + 1);
+            if (s + 2 <= z1) fetch_c(s + 2, nc);
+        }
 #pragma unroll
         for (int j = 0; j < CPT; ++j) {
             const int i = t + j * NT;
