@@ -94,11 +94,11 @@ def sweep_cases(torch, rdseg, synth, args, dev):
                     torch.empty((2, H, W), device=dev))
         c["ws"] = rdseg.workspace(rdseg.shape_of(f))
         if args.tune == "auto":
-            tile, ipl = rdseg.autotune(f, c["lam"], synth.THETA, synth.TAU, c["delta"],
-                                       args.iters)
+            tuned = rdseg.autotune(f, c["lam"], synth.THETA, synth.TAU, c["delta"], args.iters)
+            (tile, ipl), comps = tuned, tuned.components
         else:
-            tile, ipl = (64, 64), 4
-        c["tile"], c["ipl"] = tile, ipl
+            tile, ipl, comps = (64, 64), 4, 0
+        c["tile"], c["ipl"], c["comps"] = tile, ipl, comps
     return probs, cases
 
 
@@ -271,13 +271,15 @@ def extras(torch, rdseg, synth, dev, which=EXTRAS):
         # the unrestricted autotuner's pick is timed beside it
         res = {}
         for key, fixed in (("ipl8", 8), ("free", 0)):
-            tile, ipl = rdseg.autotune(f, prob.lam, synth.THETA, synth.TAU, prob.delta, 200,
-                                       iters_per_launch=fixed)
+            tuned = rdseg.autotune(f, prob.lam, synth.THETA, synth.TAU, prob.delta, 200,
+                                   iters_per_launch=fixed)
+            (tile, ipl), comps = tuned, tuned.components
             run = lambda: rdseg.solve(f, prob.lam, synth.THETA, synth.TAU, prob.delta, 1000,
-                                      tile=tile, iters_per_launch=ipl)
+                                      tile=tile, iters_per_launch=ipl, components=comps)
             run()
             t = timed(torch, run, 2)
             res[key] = dict(ms=t, tile=list(tile), iters_per_launch=ipl,
+                            small_components={1: "on", 2: "off"}[comps],
                             updates_per_s=q * prob.f.size * 1000 / (t * 1e-3))
         out["ds_4096"] = dict(size=4096, iters=1000, active_fraction=q, **res["ipl8"],
                               autotuned_free=res["free"])
@@ -318,7 +320,8 @@ def main():
     def step():
         for c in cases:
             rdseg.solve(c["f"], c["lam"], synth.THETA, synth.TAU, c["delta"], args.iters,
-                        tile=c["tile"], iters_per_launch=c["ipl"], out=c["out"], ws=c["ws"])
+                        tile=c["tile"], iters_per_launch=c["ipl"], out=c["out"], ws=c["ws"],
+                        components=c["comps"])
 
     for _ in range(args.warmup):
         step()
@@ -341,7 +344,8 @@ def main():
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         u, v, p = rdseg.solve(c["f"], c["lam"], synth.THETA, synth.TAU, c["delta"], args.iters,
-                              tile=c["tile"], iters_per_launch=c["ipl"], out=c["out"], ws=c["ws"])
+                              tile=c["tile"], iters_per_launch=c["ipl"], out=c["out"], ws=c["ws"],
+                              components=c["comps"])
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
@@ -354,7 +358,8 @@ def main():
                            updates_per_s=c["q"] * n_px * args.iters / (ms * 1e-3),
                            label_mismatch_vs_inf=float((lab != ref_lab).mean()),
                            speedup_vs_inf=round(ref_ms / ms, 3),
-                           tile=list(c["tile"]), iters_per_launch=c["ipl"]))
+                           tile=list(c["tile"]), iters_per_launch=c["ipl"],
+                           small_components={1: "on", 2: "off"}.get(c["comps"], "default")))
 
     # roofline pass: HIP events around every iteration-kernel launch; the last
     # GPU work before the extras, so that its launches are the last dispatches of

@@ -69,7 +69,11 @@ typedef struct {
  * tile_w x tile_h blocks (multiples of 8); 0 = chosen by the library
  * (autotuned, see rdseg_autotune; choosing synchronises the stream once).
  * ckpt_every > 0 asks rdseg_solve to write a checkpoint of (v, p) every
- * ckpt_every iterations into `tape` for rdseg_backward (inner = 1 only). */
+ * ckpt_every iterations into `tape` for rdseg_backward (inner = 1 only).
+ * components: whether a plain single-image solve runs the RD components of at
+ * most 64 pixels whole in the component kernel (see rdseg_set_components):
+ * 1 = on, 2 = off, 0 = the autotuner's choice for this problem class when the
+ * library chooses the tiles, else on.  Results are bitwise equal either way. */
 typedef struct {
     double lambda, theta, tau, delta;
     int32_t iters;
@@ -77,6 +81,7 @@ typedef struct {
     int32_t tile_w, tile_h;
     int32_t ckpt_every;
     int32_t inner;
+    int32_t components;
 } rdseg_params;
 
 /* Fitting term of Sec. 1: f = (z - c1)^2 - (z - c2)^2 + gamma P   (eq. CV when
@@ -339,18 +344,21 @@ rdseg_status rdseg_fit_backward(const rdseg_fit* fit, rdseg_shape s, const float
 /* Autotuning, timing, diagnostics                                          */
 /* ---------------------------------------------------------------------- */
 
-/* Times every compiled (tile_w, tile_h, iters_per_launch) configuration on
- * this problem for `probe_iters` iterations (synchronous) and returns the
- * fastest.  A nonzero prm->tile_w, tile_h or iters_per_launch fixes that
- * parameter (only matching configurations are timed; RDSEG_ERR_ARG if none is
- * compiled); with all three zero the result is also stored in the
- * process-wide cache under (shape class, active-fraction bucket) that solves
- * with tile_w = tile_h = iters_per_launch = 0 read.  u, v, p, ws as for
- * rdseg_solve (their contents are overwritten). */
+/* Times every compiled (tile_w, tile_h, iters_per_launch) configuration, with
+ * the small-component path on and off, on this problem for `probe_iters`
+ * iterations (synchronous) and returns the fastest (components: 1 on, 2 off).
+ * A nonzero prm->tile_w, tile_h, iters_per_launch or components fixes that
+ * parameter (only matching candidates are timed; RDSEG_ERR_ARG if no
+ * configuration is compiled); with all four zero the result is also stored in
+ * the process-wide cache under (shape class, active-fraction bucket) that
+ * solves with tile_w = tile_h = iters_per_launch = components = 0 read.  u,
+ * v, p, ws as for rdseg_solve (their contents are overwritten); any output
+ * pointer may be NULL. */
 rdseg_status rdseg_autotune(const float* f, rdseg_shape s, const rdseg_params* prm,
                             int32_t probe_iters, float* u, float* v, float* p,
                             void* ws, size_t ws_bytes, void* stream,
-                            int32_t* tile_w, int32_t* tile_h, int32_t* iters_per_launch);
+                            int32_t* tile_w, int32_t* tile_h, int32_t* iters_per_launch,
+                            int32_t* components);
 
 /* Single-image solves without checkpoints or stopping rule whose queued
  * macro tiles all fit on the chip at once (one workgroup each; e.g. a 1024^2
@@ -360,6 +368,15 @@ rdseg_status rdseg_autotune(const float* f, rdseg_shape s, const rdseg_params* p
  * on = 0 forces separate launches, on != 0 (the default) allows the resident
  * form.  Process-wide. */
 rdseg_status rdseg_set_resident(int32_t on);
+
+/* In single-image solves without checkpoints or stopping rule, the RD pixels
+ * whose 4-connected RD component has at most 64 pixels run every iteration in
+ * one launch, one pixel per lane (an RD pixel interacts only with its own
+ * component, Sec. 3); the tile path covers the larger components.  Skipped on
+ * the device when more than 55 % of the pixels are RD.  Results are bitwise
+ * equal either way.  on = 0 forces the tile path for every pixel, on != 0 (the
+ * default) allows the component path.  Process-wide. */
+rdseg_status rdseg_set_components(int32_t on);
 
 /* Number of compiled configurations and their parameters (i < count). */
 int32_t rdseg_config_count(void);

@@ -30,7 +30,8 @@ class Params(ctypes.Structure):
                 ("tau", ctypes.c_double), ("delta", ctypes.c_double),
                 ("iters", ctypes.c_int32), ("iters_per_launch", ctypes.c_int32),
                 ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
-                ("ckpt_every", ctypes.c_int32), ("inner", ctypes.c_int32)]
+                ("ckpt_every", ctypes.c_int32), ("inner", ctypes.c_int32),
+                ("components", ctypes.c_int32)]
 
 
 class Shape3(ctypes.Structure):
@@ -94,7 +95,7 @@ SIGNATURES = {
                                           _vp]),
     "rdseg_autotune": (ctypes.c_int, [_vp, Shape, ctypes.POINTER(Params), _i32, _vp, _vp, _vp, _vp,
                                       _sz, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
-                                      ctypes.POINTER(_i32)]),
+                                      ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "rdseg_config_count": (_i32, []),
     "rdseg_config_get": (ctypes.c_int, [_i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
                                         ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
@@ -106,6 +107,7 @@ SIGNATURES = {
                                               ctypes.POINTER(ctypes.c_int64)]),
     "rdseg_timing_reset": (ctypes.c_int, []),
     "rdseg_set_resident": (ctypes.c_int, [_i32]),
+    "rdseg_set_components": (ctypes.c_int, [_i32]),
     "rdseg_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "rdseg_last_error": (ctypes.c_char_p, []),
 }

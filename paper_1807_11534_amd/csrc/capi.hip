@@ -121,6 +121,7 @@ struct SolveWs {
     int2* cqueue;
     int32_t* totals;   // [0] n_queue, [1] scratch total, [2] n_closed
     int32_t* epoch;    // resident solve: per macro tile block counts, then a status word
+    CompWs comp;       // small-component path
     size_t bytes;
 };
 
@@ -142,6 +143,14 @@ SolveWs carve_solve(void* base, const rdseg_shape& s) {
     w.cqueue = cv.take<int2>(g.nt);
     w.totals = cv.take<int32_t>(4);
     w.epoch = cv.take<int32_t>(g.nt + 1);
+    w.comp.lab = cv.take<int32_t>(g.plane);
+    w.comp.csize = cv.take<int32_t>(g.plane);
+    w.comp.crank = cv.take<int32_t>(g.plane);
+    w.comp.cslot = cv.take<int32_t>(g.plane);
+    w.comp.lane_of = cv.take<int32_t>(g.plane);
+    w.comp.wl_pix = cv.take<int32_t>(2 * g.plane + 7 * 64);
+    w.comp.ccount = cv.take<int32_t>(8);
+    w.comp.npix_tile = cv.take<int64_t>(1);
     w.bytes = cv.off;
     return w;
 }
@@ -194,6 +203,7 @@ struct TimingRec {
 };
 
 std::atomic<bool> g_resident_on{true};
+std::atomic<bool> g_components_on{true};
 
 struct Timing {
     std::mutex mu;
@@ -235,8 +245,12 @@ struct TuneKey {
     int cls, qb;
     bool operator<(const TuneKey& o) const { return cls != o.cls ? cls < o.cls : qb < o.qb; }
 };
+// configuration index and small-component choice (1 on, 2 off)
+struct TuneVal {
+    int ci, comps;
+};
 std::mutex g_tune_mu;
-std::map<TuneKey, int> g_tune;
+std::map<TuneKey, TuneVal> g_tune;
 
 int size_class(const rdseg_shape& s) {
     int64_t n = (int64_t)s.H * s.W;
@@ -594,7 +608,7 @@ int deeper_cfg(int ci, int inner) {
 
 // Choose the tile configuration for a single-image solve.
 rdseg_status choose_cfg(const rdseg_params& prm, const rdseg_shape& s, const int64_t* npix_dev,
-                        hipStream_t st, int* ci) {
+                        hipStream_t st, int* ci, int* comps = nullptr) {
     if (prm.tile_w > 0 && prm.tile_h > 0 && prm.iters_per_launch > 0) {
         *ci = config_index(prm.tile_w, prm.tile_h, prm.iters_per_launch);
         if (*ci < 0) return fail(RDSEG_ERR_ARG, "tile_w / tile_h / iters_per_launch is not a compiled configuration");
@@ -612,7 +626,8 @@ rdseg_status choose_cfg(const rdseg_params& prm, const rdseg_shape& s, const int
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune.find(k);
         if (it != g_tune.end()) {
-            *ci = it->second;
+            *ci = it->second.ci;
+            if (comps) *comps = it->second.comps;
             return RDSEG_OK;
         }
     }
@@ -635,6 +650,8 @@ rdseg_status solve_impl(const float* f, rdseg_shape s, const rdseg_params* prm, 
     if (prm->ckpt_every > 0 && !tape) return fail(RDSEG_ERR_TAPE, "ckpt_every > 0 needs a tape");
     if (prm->inner < 0 || prm->inner > kMaxInner)
         return fail(RDSEG_ERR_ARG, "inner must lie in [0, 16]");
+    if (prm->components < 0 || prm->components > 2)
+        return fail(RDSEG_ERR_ARG, "components must be 0 (library's choice), 1 (on) or 2 (off)");
     const int inner = prm->inner > 1 ? prm->inner : 1;
     if (inner > 1 && prm->ckpt_every > 0)
         return fail(RDSEG_ERR_ARG, "checkpoints (for the adjoint) need inner = 1");
@@ -664,8 +681,9 @@ rdseg_status solve_impl(const float* f, rdseg_shape s, const rdseg_params* prm, 
     ImgDesc d = make_desc(f, s, prm->lambda, prm->theta, prm->delta, u, v, p, w.c, w.st, u0, p0, 8, 8);
     OffTables off{nullptr, nullptr, nullptr, nullptr};
     if (launch_tile_masks(&d, nullptr, off, 1, g.strips, w.masks, w.npix, st)) return RDSEG_ERR_HIP;
+    int tuned_comps = 0;
     if (ci < 0) {
-        r = choose_cfg(*prm, s, w.npix, st, &ci);
+        r = choose_cfg(*prm, s, w.npix, st, &ci, &tuned_comps);
         if (r) return r;
         if (config_at(ci).it < inner) ci = deeper_cfg(ci, inner);
     }
@@ -677,11 +695,19 @@ rdseg_status solve_impl(const float* f, rdseg_shape s, const rdseg_params* prm, 
     // checkpoint tape sends every tile through the blocked kernel instead.
     // The stopping rule needs every RD pixel's change at each check, so it
     // also keeps closed tiles in the blocked kernel.
-    const bool use_closed = !(prm->ckpt_every > 0 && tape) && prm->iters > 0 && !stop;
+    // Small RD components (<= 64 pixels) run whole in the component kernel
+    // (which covers every closed tile as well: a closed tile's components are
+    // inside it); plain solves only, and index arithmetic in int32.
+    const int want_comps = prm->components ? prm->components : (tuned_comps ? tuned_comps : 1);
+    const bool comps = want_comps == 1 && g_components_on.load() &&
+                       !(prm->ckpt_every > 0 && tape) && prm->iters > 0 && !stop &&
+                       g.plane <= ((int64_t)1 << 29);
+    const bool use_closed = !(prm->ckpt_every > 0 && tape) && prm->iters > 0 && !stop && !comps;
     if (stop && stop->n_checks > 0 &&
         launch_fill(reinterpret_cast<float*>(stop->slots), 1, stop->n_checks, stop->n_checks,
                     0.0f, st))
         return RDSEG_ERR_HIP;
+    if (comps && launch_components_prepare(d, w.comp, w.masks, w.npix, st)) return RDSEG_ERR_HIP;
     QueueScratch qs{w.cflags, w.tstate, w.flags, w.offs, w.part};
     if (launch_macro_queue(&d, nullptr, off, 1, nm, cfg.bx, cfg.by, w.masks, qs, w.queue, w.totals,
                            g.nt, use_closed ? w.cqueue : nullptr, w.totals + 2, st))
@@ -696,7 +722,18 @@ rdseg_status solve_impl(const float* f, rdseg_shape s, const rdseg_params* prm, 
         resident = hipStreamIsCapturing(st, &cap) == hipSuccess && cap == hipStreamCaptureStatusNone;
     }
     hipEvent_t join = nullptr;
-    if (use_closed) {
+    if (comps) {
+        auto small = [&](hipStream_t cs) {
+            return launch_components(d, w.comp, w.npix, prm->iters, inner, (float)prm->theta,
+                                     (float)(1.0 / prm->theta), (float)prm->tau, cs);
+        };
+        if (resident) {
+            if (small(st)) return RDSEG_ERR_HIP;
+        } else {
+            r = closed_beside(st, &join, small);
+            if (r) return r;
+        }
+    } else if (use_closed) {
         auto closed = [&](hipStream_t cs) {
             return launch_closed(&d, nullptr, false, w.cqueue, w.totals + 2, g.nt, prm->iters,
                                  (float)prm->theta, (float)(1.0 / prm->theta), (float)prm->tau,
@@ -729,6 +766,7 @@ rdseg_status solve_impl(const float* f, rdseg_shape s, const rdseg_params* prm, 
     a.resident = resident;
     a.mflags = w.flags;
     a.epoch = w.epoch;
+    if (comps) a.npix = w.comp.npix_tile;   // timing counts the tile path's pixels
     r = enqueue_iterations(a);
     const rdseg_status rj = join_closed(st, join);
     if (r) return r;
@@ -1564,62 +1602,73 @@ rdseg_status rdseg_config_get(int32_t i, int32_t* tile_w, int32_t* tile_h,
 rdseg_status rdseg_autotune(const float* f, rdseg_shape s, const rdseg_params* prm,
                             int32_t probe_iters, float* u, float* v, float* p, void* ws,
                             size_t ws_bytes, void* stream, int32_t* tile_w, int32_t* tile_h,
-                            int32_t* iters_per_launch) {
+                            int32_t* iters_per_launch, int32_t* components) {
     if (!prm) return fail(RDSEG_ERR_ARG, "prm is NULL");
     if (probe_iters < 1) return fail(RDSEG_ERR_ARG, "probe_iters must be >= 1");
+    if (prm->components < 0 || prm->components > 2)
+        return fail(RDSEG_ERR_ARG, "components must be 0 (library's choice), 1 (on) or 2 (off)");
     hipStream_t st = static_cast<hipStream_t>(stream);
     rdseg_params q = *prm;
     q.iters = probe_iters;
     q.ckpt_every = 0;
     hipEvent_t e0, e1;
-    int best = -1;
-    float best_ms = 0.0f;
     const int inner = prm->inner > 1 ? prm->inner : 1;
-    // a nonzero tile_w / tile_h / iters_per_launch in prm fixes that parameter:
-    // only configurations that match it take part
+    // a nonzero tile_w / tile_h / iters_per_launch / components in prm fixes
+    // that parameter: only candidates that match it take part
     auto candidate = [&](int ci) {
         const TileCfg c = config_at(ci);
         return c.it >= inner && (prm->tile_w <= 0 || c.bx == prm->tile_w) &&
                (prm->tile_h <= 0 || c.by == prm->tile_h) &&
                (prm->iters_per_launch <= 0 || c.it == prm->iters_per_launch);
     };
-    const bool restricted = prm->tile_w > 0 || prm->tile_h > 0 || prm->iters_per_launch > 0;
+    const bool restricted = prm->tile_w > 0 || prm->tile_h > 0 || prm->iters_per_launch > 0 ||
+                            prm->components != 0;
     {
         bool any = false;
         for (int ci = 0; ci < config_count(); ++ci) any = any || candidate(ci);
         if (!any)
             return fail(RDSEG_ERR_ARG, "no compiled configuration matches the fixed tile_w / tile_h / iters_per_launch");
     }
+    const int comp_lo = prm->components ? prm->components : 1;
+    const int comp_hi = prm->components ? prm->components : 2;
     q.tile_w = q.tile_h = q.iters_per_launch = 0;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return fail(RDSEG_ERR_HIP, "hipEventCreate failed");
-    // two rounds over all configurations, each timed over three solves after a
-    // warm-up; the minimum per configuration damps clock and cache noise
-    std::vector<float> ms_min(config_count(), -1.0f);
+    // two rounds over all candidates, each timed over three solves after a
+    // warm-up; the minimum per candidate damps clock and cache noise
+    const int n = config_count();
+    std::vector<float> ms_min(2 * n, -1.0f);
     for (int round = 0; round < 2; ++round) {
-        for (int ci = 0; ci < config_count(); ++ci) {
+        for (int ci = 0; ci < n; ++ci) {
             if (!candidate(ci)) continue;
-            rdseg_status r = solve_impl(f, s, &q, nullptr, nullptr, u, v, p, nullptr, ws, ws_bytes, st, ci);
-            if (r) { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); return r; }
-            (void)hipEventRecord(e0, st);
-            for (int rep = 0; rep < 3; ++rep) {
-                r = solve_impl(f, s, &q, nullptr, nullptr, u, v, p, nullptr, ws, ws_bytes, st, ci);
+            for (int cm = comp_lo; cm <= comp_hi; ++cm) {
+                q.components = cm;
+                rdseg_status r = solve_impl(f, s, &q, nullptr, nullptr, u, v, p, nullptr, ws, ws_bytes, st, ci);
                 if (r) { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); return r; }
+                (void)hipEventRecord(e0, st);
+                for (int rep = 0; rep < 3; ++rep) {
+                    r = solve_impl(f, s, &q, nullptr, nullptr, u, v, p, nullptr, ws, ws_bytes, st, ci);
+                    if (r) { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); return r; }
+                }
+                (void)hipEventRecord(e1, st);
+                if (hipEventSynchronize(e1) != hipSuccess) {
+                    (void)hipEventDestroy(e0); (void)hipEventDestroy(e1);
+                    return fail(RDSEG_ERR_HIP, "autotune timing failed");
+                }
+                float ms = 0.0f;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                float& m = ms_min[2 * ci + (cm - 1)];
+                if (m < 0.0f || ms < m) m = ms;
             }
-            (void)hipEventRecord(e1, st);
-            if (hipEventSynchronize(e1) != hipSuccess) {
-                (void)hipEventDestroy(e0); (void)hipEventDestroy(e1);
-                return fail(RDSEG_ERR_HIP, "autotune timing failed");
-            }
-            float ms = 0.0f;
-            (void)hipEventElapsedTime(&ms, e0, e1);
-            if (ms_min[ci] < 0.0f || ms < ms_min[ci]) ms_min[ci] = ms;
         }
     }
-    for (int ci = 0; ci < config_count(); ++ci)
-        if (ms_min[ci] >= 0.0f && (best < 0 || ms_min[ci] < best_ms)) { best = ci; best_ms = ms_min[ci]; }
+    int best = -1;
+    float best_ms = 0.0f;
+    for (int k = 0; k < 2 * n; ++k)
+        if (ms_min[k] >= 0.0f && (best < 0 || ms_min[k] < best_ms)) { best = k; best_ms = ms_min[k]; }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    const int best_ci = best / 2, best_comps = best % 2 + 1;
     // record under the problem's class and active-fraction bucket (a search
     // over a restricted set does not speak for the class)
     if (!restricted) {
@@ -1629,17 +1678,23 @@ rdseg_status rdseg_autotune(const float* f, rdseg_shape s, const rdseg_params* p
             return fail(RDSEG_ERR_HIP, "reading the active-pixel count failed");
         double qf = (double)np / ((double)s.H * s.W);
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tune[TuneKey{size_class(s), q_bucket(qf)}] = best;
+        g_tune[TuneKey{size_class(s), q_bucket(qf)}] = TuneVal{best_ci, best_comps};
     }
-    TileCfg c = config_at(best);
+    TileCfg c = config_at(best_ci);
     if (tile_w) *tile_w = c.bx;
     if (tile_h) *tile_h = c.by;
     if (iters_per_launch) *iters_per_launch = c.it;
+    if (components) *components = best_comps;
     return RDSEG_OK;
 }
 
 rdseg_status rdseg_set_resident(int32_t on) {
     g_resident_on.store(on != 0);
+    return RDSEG_OK;
+}
+
+rdseg_status rdseg_set_components(int32_t on) {
+    g_components_on.store(on != 0);
     return RDSEG_OK;
 }
 

@@ -1,0 +1,354 @@
+// components.hip -- small RD components solved whole, one lane per pixel.
+//
+// An RD pixel interacts only with the RD pixels of its own 4-connected
+// component: the dual step reads w at x + e and the divergence p at x - e,
+// and at frozen neighbours both are constants (w = -H(-f)/theta, p = 0).  A
+// component of at most 64 pixels can therefore run every iteration inside one
+// wave, one pixel per lane, its neighbours' values fetched from other lanes
+// (ds_bpermute) and its frozen neighbours entering as constants.  Below the
+// percolation threshold of the band most RD pixels sit in such components;
+// the tile path then only has to cover the large ones.
+//
+// Steps (single image; skipped on the device when more than 55 % of the
+// pixels are RD, where one component spans the image):
+//   k_cc_init      labels: own index on RD, -1 elsewhere; counters cleared
+//   k_cc_union     lock-free union of right / down RD neighbours (the larger
+//                  root is linked below the smaller one with atomicMin)
+//   k_cc_flatten   every RD pixel points at its root; component sizes
+//   k_cc_class     each small component (<= 64 pixels) takes a slot in the
+//                  class of its size rounded up to a power of two
+//   k_cc_assign    each of its pixels takes a lane: waves of one class hold
+//                  64 / 2^k components of 2^k lanes; the pixel is then frozen
+//                  for the tile path (c = +inf, its tile-mask bit cleared; the
+//                  tile path's RD count is the full count less these pixels)
+//   k_components   every iteration of the packed waves
+// Lane order within a component depends on atomics, but no result does: each
+// pixel's arithmetic reads exact neighbour values, with the per-pixel
+// functions of the other kernels, so results are bitwise equal to theirs.
+#include <algorithm>
+
+#include "rdseg_internal.h"
+
+namespace rdseg {
+
+namespace {
+
+constexpr int kSmallMax = 64;
+constexpr int kClasses = 7;   // padded sizes 1, 2, 4, ..., 64
+// Lanes used: a component of class k >= 1 has more than 2^(k-1) pixels and
+// takes 2^k lanes, so all classes together take fewer than twice the pixels
+// plus a partly filled last wave per class: wl_pix holds 2 * plane + kWlExtra.
+constexpr int kWlExtra = kClasses * 64;
+
+__device__ __forceinline__ bool cc_skip(const int64_t* npix, const ImgDesc& d) {
+    return 100 * npix[0] > 55 * (int64_t)d.H * d.W;
+}
+
+__device__ __forceinline__ int size_class(int s) {   // ceil(log2(s)), s in [1, 64]
+    return s <= 1 ? 0 : 32 - __clz(s - 1);
+}
+
+__device__ __forceinline__ int cc_find(int32_t* lab, int x) {
+    while (true) {
+        const int p = __hip_atomic_load(lab + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (p == x) return x;
+        const int gp = __hip_atomic_load(lab + p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (gp != p)   // path halving: gp is an ancestor of x as well
+            __hip_atomic_store(lab + x, gp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        x = gp;
+    }
+}
+
+// Root of x without writing (for the flattening pass, whose only stores must
+// be roots: a path-halving store there could overwrite a finished root with
+// an intermediate ancestor).
+__device__ __forceinline__ int cc_root(const int32_t* lab, int x) {
+    while (true) {
+        const int p = __hip_atomic_load(lab + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (p == x) return x;
+        x = p;
+    }
+}
+
+__device__ __forceinline__ void cc_unite(int32_t* lab, int a, int b) {
+    while (true) {
+        a = cc_find(lab, a);
+        b = cc_find(lab, b);
+        if (a == b) return;
+        if (a < b) {
+            const int t = a;
+            a = b;
+            b = t;
+        }
+        const int old = atomicMin(lab + a, b);   // a was a root: link it below b
+        if (old == a) return;
+        a = old;   // a was linked meanwhile: continue from its new parent
+    }
+}
+
+__global__ __launch_bounds__(256) void k_cc_init(ImgDesc d, CompWs w, const int64_t* npix) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) w.npix_tile[0] = npix[0];
+    if (cc_skip(npix, d)) return;
+    const int64_t plane = (int64_t)d.H * d.ld;
+    for (int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x; g < plane;
+         g += (int64_t)gridDim.x * 256) {
+        const int y = (int)(g / d.ld), x = (int)(g - (int64_t)y * d.ld);
+        const bool act = x < d.W && c_active(d.c[g]);
+        w.lab[g] = act ? (int32_t)g : -1;
+        w.csize[g] = 0;
+        w.crank[g] = 0;
+        w.cslot[g] = 0;
+        w.lane_of[g] = -1;
+        w.wl_pix[2 * g] = -1;
+        w.wl_pix[2 * g + 1] = -1;
+        if (g < kWlExtra) w.wl_pix[2 * plane + g] = -1;
+        if (g < 8) w.ccount[g] = 0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_cc_union(ImgDesc d, CompWs w, const int64_t* npix) {
+    if (cc_skip(npix, d)) return;
+    const int64_t plane = (int64_t)d.H * d.ld;
+    for (int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x; g < plane;
+         g += (int64_t)gridDim.x * 256) {
+        const int y = (int)(g / d.ld), x = (int)(g - (int64_t)y * d.ld);
+        if (x >= d.W || !c_active(d.c[g])) continue;
+        if (x + 1 < d.W && c_active(d.c[g + 1])) cc_unite(w.lab, (int)g, (int)g + 1);
+        if (y + 1 < d.H && c_active(d.c[g + d.ld])) cc_unite(w.lab, (int)g, (int)g + d.ld);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_cc_flatten(ImgDesc d, CompWs w, const int64_t* npix) {
+    if (cc_skip(npix, d)) return;
+    const int64_t plane = (int64_t)d.H * d.ld;
+    for (int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x; g < plane;
+         g += (int64_t)gridDim.x * 256) {
+        if (w.lab[g] < 0) continue;
+        const int r = cc_root(w.lab, (int)g);
+        __hip_atomic_store(w.lab + g, r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // Sizes are exact up to kSmallMax + 1; beyond that only "large"
+        // matters.  cslot[r] (cleared by the init pass, written for small
+        // roots only by the class pass) flags a root that has passed
+        // kSmallMax, so the pixels of large components stop adding to one
+        // contended counter.  A stale read only costs an extra add.
+        if (w.cslot[r]) continue;
+        if (atomicAdd(w.csize + r, 1) >= kSmallMax) w.cslot[r] = 1;
+    }
+}
+
+// Slots within the size classes: each workgroup counts its small roots per
+// class in LDS, takes one block of slots per class with a single global
+// atomic, and hands them out in the order of its local counting.
+__global__ __launch_bounds__(256) void k_cc_class(ImgDesc d, CompWs w, const int64_t* npix) {
+    __shared__ int sCount[kClasses], sBase[kClasses];
+    if (cc_skip(npix, d)) return;   // uniform: npix is not changed by this pass
+    const int t = threadIdx.x;
+    if (t < kClasses) sCount[t] = 0;
+    __syncthreads();
+    const int64_t plane = (int64_t)d.H * d.ld;
+    const int64_t per_wg = (plane + gridDim.x - 1) / gridDim.x;
+    const int64_t g0 = (int64_t)blockIdx.x * per_wg;
+    const int64_t g1 = min(plane, g0 + per_wg);
+    for (int64_t g = g0 + t; g < g1; g += 256) {
+        if (w.lab[g] != (int32_t)g) continue;   // roots only
+        const int s = w.csize[g];
+        if (s < 1 || s > kSmallMax) continue;
+        w.cslot[g] = atomicAdd(&sCount[size_class(s)], 1);   // local slot
+    }
+    __syncthreads();
+    if (t < kClasses) sBase[t] = sCount[t] ? atomicAdd(w.ccount + t, sCount[t]) : 0;
+    __syncthreads();
+    for (int64_t g = g0 + t; g < g1; g += 256) {
+        if (w.lab[g] != (int32_t)g) continue;
+        const int s = w.csize[g];
+        if (s < 1 || s > kSmallMax) continue;
+        w.cslot[g] += sBase[size_class(s)];
+    }
+}
+
+// waves taken by the classes below k
+__device__ __forceinline__ int class_base(const int32_t* ccount, int k) {
+    int b = 0;
+    for (int j = 0; j < k; ++j) {
+        const int per = kSmallMax >> j;
+        b += (ccount[j] + per - 1) / per;
+    }
+    return b;
+}
+
+__global__ __launch_bounds__(256) void k_cc_assign(ImgDesc d, CompWs w, uint64_t* masks,
+                                                   const int64_t* npix) {
+    __shared__ int sFrozen;
+    if (cc_skip(npix, d)) return;   // uniform: npix is not changed by this pass
+    if (threadIdx.x == 0) sFrozen = 0;
+    __syncthreads();
+    const int64_t plane = (int64_t)d.H * d.ld;
+    int frozen = 0;
+    for (int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x; g < plane;
+         g += (int64_t)gridDim.x * 256) {
+        const int r = w.lab[g];
+        if (r < 0 || r >= plane) continue;
+        const int s = w.csize[r];
+        if (s < 1 || s > kSmallMax) continue;
+        const int k = size_class(s);
+        const int per = kSmallMax >> k;
+        const int slot = w.cslot[r];
+        const int rank = atomicAdd(w.crank + r, 1);
+        const int wave = class_base(w.ccount, k) + slot / per;
+        const int lane = (slot % per) * (1 << k) + rank;
+        const int L = wave * 64 + lane;
+        // never true for a well-formed labelling (see kWlExtra); a guard
+        // against writing outside the lane table
+        if (slot < 0 || rank >= s || L < 0 || L >= 2 * plane + kWlExtra) continue;
+        w.lane_of[g] = L;
+        w.wl_pix[L] = (int32_t)g;
+        // frozen for the tile path from here on
+        const int y = (int)(g / d.ld), x = (int)(g - (int64_t)y * d.ld);
+        d.c[g] = __builtin_inff();
+        const int64_t T = (int64_t)(y >> 3) * d.tw + (x >> 3);
+        atomicAnd((unsigned long long*)(masks + T), ~(1ull << (8 * (y & 7) + (x & 7))));
+        ++frozen;
+    }
+    if (frozen) atomicAdd(&sFrozen, frozen);
+    __syncthreads();
+    if (threadIdx.x == 0 && sFrozen)
+        atomicAdd((unsigned long long*)w.npix_tile, (unsigned long long)(-(long long)sFrozen));
+}
+
+// Every iteration of the packed small components: wave = packed group, lane
+// = one pixel (or empty).  The u-step / v-step / dual step are those of
+// k_iterate; x +/- 1 and y +/- 1 neighbours come from their lanes, frozen
+// neighbours as constants (w right and below, p = 0 left and above).
+__global__ __launch_bounds__(256) void k_components(ImgDesc d, CompWs w, const int64_t* npix,
+                                                    int iters, int inner, float theta,
+                                                    float inv_theta, float tau) {
+    if (cc_skip(npix, d)) return;
+    const int64_t plane = (int64_t)d.H * d.ld;
+    const int nwaves = (int)min((int64_t)class_base(w.ccount, kClasses),
+                                (2 * plane + kWlExtra) / 64);
+    const int lane = threadIdx.x & 63;
+    for (int wave = blockIdx.x * 4 + (threadIdx.x >> 6); wave < nwaves;
+         wave += gridDim.x * 4) {   // uniform per wave
+        const int g = w.wl_pix[wave * 64 + lane];
+        const bool mine = g >= 0 && g < plane;
+        const int gg = mine ? g : 0;
+        const int y = gg / d.ld, x = gg - y * d.ld;
+        // this pixel: RD by construction; its state from buffer 0
+        const float fv = mine ? d.f[gg] : 0.0f;
+        const float c = mine ? c_of(fv, d.delta, d.tl) : __builtin_inff();
+        float v = 0.0f, px = 0.0f, py = 0.0f;
+        if (mine) {
+            v = d.st[0][0][gg];
+            px = d.st[0][1][gg];
+            py = d.st[0][2][gg];
+        }
+        uint32_t fl = mine ? (CF_ACT | CF_OUT) : 0u;
+        if (mine && x == d.W - 1) fl |= CF_LASTC;
+        if (mine && y == d.H - 1) fl |= CF_LASTR;
+        // neighbour lanes (same component), or -1 with a frozen constant
+        int nR = -1, nD = -1, nL = -1, nU = -1;
+        float wR = 0.0f, wD = 0.0f;
+        if (mine) {
+            if (x + 1 < d.W) {
+                const int L = w.lane_of[gg + 1];
+                if (L >= 0) nR = L & 63;
+                else wR = w_of(0.0f, heav_from_c(c_of(d.f[gg + 1], d.delta, d.tl)), inv_theta, false);
+            } else {
+                wR = w_of(0.0f, 0.0f, inv_theta, false);
+            }
+            if (y + 1 < d.H) {
+                const int L = w.lane_of[gg + d.ld];
+                if (L >= 0) nD = L & 63;
+                else wD = w_of(0.0f, heav_from_c(c_of(d.f[gg + d.ld], d.delta, d.tl)), inv_theta, false);
+            } else {
+                wD = w_of(0.0f, 0.0f, inv_theta, false);
+            }
+            if (x > 0) {
+                const int L = w.lane_of[gg - 1];
+                if (L >= 0) nL = L & 63;
+            }
+            if (y > 0) {
+                const int L = w.lane_of[gg - d.ld];
+                if (L >= 0) nU = L & 63;
+            }
+        }
+        // bpermute addresses (a lane reads itself when the neighbour is frozen)
+        const int aR = 4 * (nR >= 0 ? nR : lane), aD = 4 * (nD >= 0 ? nD : lane);
+        const int aL = 4 * (nL >= 0 ? nL : lane), aU = 4 * (nU >= 0 ? nU : lane);
+        auto from = [](int addr, float a) {
+            return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(a)));
+        };
+        float pxl = from(aL, px), pyu = from(aU, py);
+        float dd = div_p(px, nL >= 0 ? pxl : 0.0f, py, nU >= 0 ? pyu : 0.0f);
+        float wv = w_of(dd, v, inv_theta, mine);
+        const int steps = iters * inner;
+        int left = inner;
+        for (int it = 0; it < steps; ++it) {
+            const float wr = from(aR, wv), wd = from(aD, wv);
+            const DualOut o = dual_update(px, py, wv, nR >= 0 ? wr : wR, nD >= 0 ? wd : wD, fl, tau);
+            px = o.px;
+            py = o.py;
+            pxl = from(aL, px);
+            pyu = from(aU, py);
+            dd = div_p(px, nL >= 0 ? pxl : 0.0f, py, nU >= 0 ? pyu : 0.0f);
+            const bool last = (it == steps - 1);
+            const bool outer_end = --left == 0;
+            if (outer_end) {
+                left = inner;
+                const float u = u_step(v, dd, theta);
+                v = v_step(u, c);
+                if (last) {
+                    if (mine) d.u[gg] = u;
+                    break;
+                }
+            }
+            wv = w_of(dd, v, inv_theta, mine);
+        }
+        if (mine) {
+            d.st[0][0][gg] = v;
+            d.st[0][1][gg] = px;
+            d.st[0][2][gg] = py;
+        }
+    }
+}
+
+unsigned grid_for(int64_t n) {
+    const int64_t b = (n + 255) / 256;
+    return (unsigned)(b < 4096 ? (b < 1 ? 1 : b) : 4096);
+}
+
+int g_comp_grid = 0;
+
+}  // namespace
+
+int launch_components_prepare(const ImgDesc& d, const CompWs& w, uint64_t* masks,
+                              const int64_t* npix, hipStream_t st) {
+    const unsigned grid = grid_for((int64_t)d.H * d.ld);
+    hipLaunchKernelGGL(k_cc_init, dim3(grid), dim3(256), 0, st, d, w, (const int64_t*)npix);
+    hipLaunchKernelGGL(k_cc_union, dim3(grid), dim3(256), 0, st, d, w, (const int64_t*)npix);
+    hipLaunchKernelGGL(k_cc_flatten, dim3(grid), dim3(256), 0, st, d, w, (const int64_t*)npix);
+    hipLaunchKernelGGL(k_cc_class, dim3(std::min(grid, 1024u)), dim3(256), 0, st, d, w,
+                       (const int64_t*)npix);
+    hipLaunchKernelGGL(k_cc_assign, dim3(grid), dim3(256), 0, st, d, w, masks,
+                       (const int64_t*)npix);
+    RDSEG_HIP_CHECK(hipGetLastError());
+    return 0;
+}
+
+int launch_components(const ImgDesc& d, const CompWs& w, const int64_t* npix, int iters,
+                      int inner, float theta, float inv_theta, float tau, hipStream_t st) {
+    if (g_comp_grid == 0) {
+        g_comp_grid = persistent_blocks(reinterpret_cast<const void*>(k_components), 256, 0);
+        if (g_comp_grid <= 0) {
+            g_comp_grid = 0;
+            set_error("occupancy query failed for the component kernel");
+            return 4;
+        }
+    }
+    hipLaunchKernelGGL(k_components, dim3((unsigned)g_comp_grid), dim3(256), 0, st, d, w, npix,
+                       iters, inner, theta, inv_theta, tau);
+    RDSEG_HIP_CHECK(hipGetLastError());
+    return 0;
+}
+
+}  // namespace rdseg

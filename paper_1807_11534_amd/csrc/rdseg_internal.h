@@ -145,6 +145,17 @@ int config_index(int bx, int by, int it);   // -1 if not compiled
 // Occupancy query for the persistent grid of configuration ci (cached).
 int prepare_iterate(int ci, bool batched, bool stop = false);
 
+// Small-component path of a single-image solve (components.hip): label the
+// RD components of d (c already written), pack those of at most 64 pixels
+// into waves and freeze their pixels for the tile path (c = +inf, tile-mask
+// bits cleared, w.npix_tile = the RD pixels left to it); then run every
+// iteration of them.  Both do nothing on the device when more than 55 % of
+// the pixels are RD (npix_tile is still written).
+int launch_components_prepare(const ImgDesc& d, const CompWs& w, uint64_t* masks,
+                              const int64_t* npix, hipStream_t st);
+int launch_components(const ImgDesc& d, const CompWs& w, const int64_t* npix, int iters,
+                      int inner, float theta, float inv_theta, float tau, hipStream_t st);
+
 // Resident form of a whole single-image solve: whether configuration ci has a
 // resident kernel whose workgroups, one per queued macro tile (at most
 // max_items), all fit on the chip at once; and the launch, which runs `iters`

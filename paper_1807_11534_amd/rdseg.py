@@ -40,9 +40,10 @@ def shape_of(f):
 
 
 def params(lam, theta=THETA, tau=TAU, delta=math.inf, iters=0, iters_per_launch=0, tile_w=0,
-           tile_h=0, ckpt_every=0, inner=1):
+           tile_h=0, ckpt_every=0, inner=1, components=0):
     return Params(float(lam), float(theta), float(tau), float(delta), int(iters),
-                  int(iters_per_launch), int(tile_w), int(tile_h), int(ckpt_every), int(inner))
+                  int(iters_per_launch), int(tile_w), int(tile_h), int(ckpt_every), int(inner),
+                  int(components))
 
 
 def workspace(s, prm=None):
@@ -104,16 +105,19 @@ def delta_for_fraction(f, q):
 
 
 def solve(f, lam, theta=THETA, tau=TAU, delta=math.inf, iters=100, u0=None, p0=None,
-          tile=None, iters_per_launch=0, ckpt_every=0, out=None, ws=None, inner=1):
+          tile=None, iters_per_launch=0, ckpt_every=0, out=None, ws=None, inner=1,
+          components=0):
     """Restricted-domain dual iteration (Sec. 2.1 restricted as in Sec. 3).
 
     tile: (tile_w, tile_h) or None (autotuned); inner: dual steps per outer
-    iteration.  Returns (u, v, p) with p of shape [2][H][W]; with
+    iteration; components: small-component path, 1 on, 2 off, 0 the library's
+    choice (see autotune).  Returns (u, v, p) with p of shape [2][H][W]; with
     ckpt_every > 0 returns (u, v, p, tape)."""
     lib = _lib.load()
     s = shape_of(f)
     tw, th = (0, 0) if tile is None else tile
-    prm = params(lam, theta, tau, delta, iters, iters_per_launch, tw, th, ckpt_every, inner)
+    prm = params(lam, theta, tau, delta, iters, iters_per_launch, tw, th, ckpt_every, inner,
+                 components)
     if out is None:
         u, v, p = _empty_like_grid(f), _empty_like_grid(f), _empty_like_grid(f, 2)
     else:
@@ -380,25 +384,36 @@ def configs():
     return out
 
 
+class Tuned(tuple):
+    """((tile_w, tile_h), iters_per_launch) of an autotuned configuration; the
+    small-component choice (1 on, 2 off) rides along as `.components`."""
+
+    def __new__(cls, tile, ipl, components):
+        t = super().__new__(cls, (tile, ipl))
+        t.components = components
+        return t
+
+
 def autotune(f, lam, theta=THETA, tau=TAU, delta=math.inf, probe_iters=16, iters_per_launch=0,
-             tile=None):
-    """Time every compiled configuration on this problem and return the best
-    ((tile_w, tile_h), iters_per_launch).  A nonzero iters_per_launch or a
-    tile fixes that parameter and only the matching configurations are timed;
-    an unrestricted search is also cached for solves that leave the choice to
-    the library."""
+             tile=None, components=0):
+    """Time every compiled configuration, with the small-component path on and
+    off, on this problem and return the best as Tuned ((tile_w, tile_h),
+    iters_per_launch) with `.components`.  A nonzero iters_per_launch, tile
+    or components fixes that parameter and only matching candidates are
+    timed; an unrestricted search is also cached for solves that leave the
+    choice to the library."""
     lib = _lib.load()
     s = shape_of(f)
     tw, th = (0, 0) if tile is None else tile
     prm = params(lam, theta, tau, delta, probe_iters, iters_per_launch=iters_per_launch, tile_w=tw,
-                 tile_h=th)
+                 tile_h=th, components=components)
     u, v, p = _empty_like_grid(f), _empty_like_grid(f), _empty_like_grid(f, 2)
     ws = workspace(s, prm)
-    a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    a, b, c, k = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
     check(lib.rdseg_autotune(_vp(f), s, ctypes.byref(prm), int(probe_iters), _vp(u), _vp(v),
                              _vp(p), _vp(ws), ws.numel(), _stream(), ctypes.byref(a),
-                             ctypes.byref(b), ctypes.byref(c)))
-    return (a.value, b.value), c.value
+                             ctypes.byref(b), ctypes.byref(c), ctypes.byref(k)))
+    return Tuned((a.value, b.value), c.value, k.value)
 
 
 def timing_enable(on=True):
@@ -426,6 +441,11 @@ def timing_read_form(config=-1, form=-1):
 def set_resident(on=True):
     """Allow (default) or forbid the resident form of single-image solves."""
     check(_lib.load().rdseg_set_resident(1 if on else 0))
+
+
+def set_components(on=True):
+    """Allow (default) or forbid the small-component path of single-image solves."""
+    check(_lib.load().rdseg_set_components(1 if on else 0))
 
 
 def timing_reset():

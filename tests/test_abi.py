@@ -142,6 +142,11 @@ def test_metrics_validation(lib):
     assert lib.rdseg_metrics(P(1), P(2), Shape(0, 16, 16), 0.5, P(3), P(4), n, None) == 2
 
 
+def test_components_choice_validation(lib):
+    assert _solve(lib, (16, 16, 16), _prm(components=-1)) == 1
+    assert _solve(lib, (16, 16, 16), _prm(components=3)) == 1
+
+
 def test_inner_steps_validation(lib):
     assert _solve(lib, (16, 16, 16), _prm(inner=-1)) == 1
     assert _solve(lib, (16, 16, 16), _prm(inner=17)) == 1

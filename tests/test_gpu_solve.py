@@ -218,6 +218,41 @@ def test_resident_matches_separate_launches(rd, shape, tile, ipl, frac, iters):
         uo, vo, po = oracle.solve(f, 3.0, 0.1, 0.125, delta, iters)
         assert np.abs(res[0] - uo).max() <= U_TOL
 
+
+@pytest.mark.parametrize("case", [
+    dict(shape=(1024, 1024), lam=5.0, frac=0.5, iters=40, tile=(64, 64), ipl=8, inner=1),
+    dict(shape=(1024, 1024), lam=1.0, frac=0.2, iters=37, tile=(16, 16), ipl=16, inner=1),
+    dict(shape=(300, 257), lam=3.0, frac=0.4, iters=29, tile=(16, 16), ipl=8, inner=1),
+    dict(shape=(300, 257), lam=3.0, frac=0.4, iters=21, tile=(32, 32), ipl=4, inner=2),
+    dict(shape=(97, 131), lam=2.0, frac=0.3, iters=50, tile=(8, 8), ipl=8, inner=1),
+])
+def test_small_components_match_tile_path(rd, case):
+    """Pixels of RD components of at most 64 pixels run whole in the component
+    kernel; the results equal those of the tile path for every pixel bit for
+    bit, and match the oracle on the smaller grids."""
+    H, W = case["shape"]
+    if H == 1024:
+        f = synth.config2(1 if case["lam"] == 5.0 else 0, size=1024, iters=500).f
+    else:
+        f = synth.smooth_field(H, W, 41, noise=0.3)
+    delta = synth.band_delta(f, case["frac"])
+    ft = dev(f)
+    say(f"components {case}")
+    kw = dict(tile=case["tile"], iters_per_launch=case["ipl"], inner=case["inner"])
+    try:
+        rd.set_components(False)
+        ref = [host(x) for x in rd.solve(ft, case["lam"], 0.1, 0.125, delta, case["iters"], **kw)]
+        rd.set_components(True)
+        got = [host(x) for x in rd.solve(ft, case["lam"], 0.1, 0.125, delta, case["iters"], **kw)]
+    finally:
+        rd.set_components(True)
+    for a, b in zip(got, ref):
+        np.testing.assert_array_equal(a, b)
+    if H * W <= 300 * 257:
+        uo, vo, po = oracle.solve(f, case["lam"], 0.1, 0.125, delta, case["iters"],
+                                  inner=case["inner"])
+        assert np.abs(got[0] - uo).max() <= U_TOL
+
 def test_determinism_and_resume(rd):
     f = synth.smooth_field(96, 130, 25, noise=0.2)
     ft = dev(f)
