@@ -46,24 +46,6 @@ struct ImgDesc {
     double delta;
 };
 
-// Work arrays of the small-component path (single image, indices g = y * ld
-// + x of the image's [H][ld] plane): lab (union-find parent, then root; -1
-// off RD), csize (pixels per root), crank (pixels placed so far per root),
-// cslot (slot of a root in its size class), lane_of (packed lane of a
-// small-component pixel, -1 otherwise), wl_pix (pixel of each packed lane, -1
-// for empty lanes; 2 * plane + 448 entries), ccount (components per class, 8),
-// npix_tile (RD pixels left to the tile path).
-struct CompWs {
-    int32_t* lab;
-    int32_t* csize;
-    int32_t* crank;
-    int32_t* cslot;
-    int32_t* lane_of;
-    int32_t* wl_pix;
-    int32_t* ccount;
-    int64_t* npix_tile;
-};
-
 // A volume [D][H][W]: voxel (z, y, x) at z * lds + y * ld + x.  The two state
 // buffers are st[0] = the caller's (v, p_x, p_y, p_z), st[1] = the workspace's.
 struct VolDesc {

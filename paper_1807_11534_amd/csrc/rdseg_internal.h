@@ -145,6 +145,24 @@ int config_index(int bx, int by, int it);   // -1 if not compiled
 // Occupancy query for the persistent grid of configuration ci (cached).
 int prepare_iterate(int ci, bool batched, bool stop = false);
 
+// Work arrays of the small-component path (single image, indices g = y * ld
+// + x of the image's [H][ld] plane): lab (union-find parent, then root; -1
+// off RD), csize (pixels per root), crank (pixels placed so far per root),
+// cslot (slot of a root in its size class), lane_of (packed lane of a
+// small-component pixel, -1 otherwise), wl_pix (pixel of each packed lane, -1
+// for empty lanes; 2 * plane + 448 entries), ccount (components per class, 8),
+// npix_tile (RD pixels left to the tile path).
+struct CompWs {
+    int32_t* lab;
+    int32_t* csize;
+    int32_t* crank;
+    int32_t* cslot;
+    int32_t* lane_of;
+    int32_t* wl_pix;
+    int32_t* ccount;
+    int64_t* npix_tile;
+};
+
 // Small-component path of a single-image solve (components.hip): label the
 // RD components of d (c already written), pack those of at most 64 pixels
 // into waves and freeze their pixels for the tile path (c = +inf, tile-mask
