@@ -1317,12 +1317,25 @@ rdseg_status rdseg_solve3d(const float* f, rdseg_shape3 s, const rdseg_params* p
     const int64_t L = (int64_t)prm->iters * inner;
     const float theta = (float)prm->theta, inv_theta = (float)(1.0 / prm->theta);
     const float tau = (float)prm->tau;
-    for (int64_t j = 0; j < L; ++j) {
-        const int in_buf = (int)((L - j) % 2);   // the last launch writes buffer 0
-        const bool uv = (j + 1) % inner == 0;
-        if (launch_iterate3(d, w.flags, w.n_tiles, in_buf, uv, j == L - 1, theta, inv_theta,
-                            tau, st))
-            return RDSEG_ERR_HIP;
+    // dual steps in pairs (one pass each), an odd last one alone; the last
+    // launch writes buffer 0
+    const int64_t n_launch = L / 2 + L % 2;
+    for (int64_t j = 0, step = 0; j < n_launch; ++j) {
+        const int in_buf = (int)((n_launch - j) % 2);
+        const bool last = j == n_launch - 1;
+        if (L - step >= 2) {
+            const bool uv1 = (step + 1) % inner == 0, uv2 = (step + 2) % inner == 0;
+            if (launch_iterate3x2(d, w.flags, w.n_tiles, in_buf, uv1, uv2, last, theta,
+                                  inv_theta, tau, st))
+                return RDSEG_ERR_HIP;
+            step += 2;
+        } else {
+            const bool uv = (step + 1) % inner == 0;
+            if (launch_iterate3(d, w.flags, w.n_tiles, in_buf, uv, last, theta, inv_theta, tau,
+                                st))
+                return RDSEG_ERR_HIP;
+            step += 1;
+        }
     }
     return RDSEG_OK;
 }

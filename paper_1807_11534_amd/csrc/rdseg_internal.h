@@ -133,6 +133,11 @@ int launch_tile_flags3(const VolDesc& d, int64_t n_tiles, int32_t* flags, hipStr
 // 1 - in_buf; with uv also the u-step and v-step (u written when write_u).
 int launch_iterate3(const VolDesc& d, const int32_t* flags, int64_t n_tiles, int in_buf, bool uv,
                     bool write_u, float theta, float inv_theta, float tau, hipStream_t st);
+// Two consecutive dual steps in one pass (the u/v step after the first when
+// uv1, after the second when uv2); reads buffer in_buf, writes 1 - in_buf.
+int launch_iterate3x2(const VolDesc& d, const int32_t* flags, int64_t n_tiles, int in_buf,
+                      bool uv1, bool uv2, bool write_u, float theta, float inv_theta, float tau,
+                      hipStream_t st);
 
 // ---------------------------------------------------------------- iteration
 int launch_init(const ImgDesc* d0, const ImgDesc* descs, OffTables off, int n_img,
