@@ -167,7 +167,10 @@ rdseg_status rdseg_band_threshold(const float* f, rdseg_shape s, double q, doubl
  * hold u = v = H(-f), p = 0).  u0 == u and p0 == p are allowed (warm start in
  * place); u, v, p must not overlap f or each other.  iters == 0 returns the
  * initial state.  tape (device, nullable) receives the checkpoints when
- * prm->ckpt_every > 0 (size rdseg_tape_size).  Results are bitwise identical
+ * prm->ckpt_every > 0 (size rdseg_tape_size; defined on RD pixels only); such
+ * a solve with the component path on reads the tile-queue length once
+ * (synchronises the stream, except under graph capture) to skip the tile path
+ * when the components hold every RD pixel.  Results are bitwise identical
  * for every tile configuration and iters_per_launch, and a solve of K1
  * iterations resumed for K2 more (u0 = u, p0 = p) equals one of K1 + K2. */
 rdseg_status rdseg_solve(const float* f, rdseg_shape s, const rdseg_params* prm,
@@ -322,7 +325,12 @@ rdseg_status rdseg_plan_destroy(void* plan);
  * With fit non-NULL (the f of the solve came from rdseg_fit_forward with the
  * same fit), also grad_c1, grad_c2 and grad_gamma (device doubles) through
  * eq. CV / eq. DS.  Scalar reductions are FP64 in a fixed order
- * (deterministic).  RDSEG_ERR_TAPE if tape is NULL or ckpt_every <= 0. */
+ * (deterministic).  With the component path on (prm->components != 2 and
+ * rdseg_set_components), the RD components of at most 64 pixels run their
+ * whole reverse sweep in one launch and the call synchronises the stream once
+ * (to learn whether any tile is left to the per-step path); the results are
+ * bitwise those of the per-step path.  RDSEG_ERR_TAPE if tape is NULL or
+ * ckpt_every <= 0. */
 rdseg_status rdseg_backward(const float* f, rdseg_shape s, const rdseg_params* prm,
                             const float* tape, const float* grad_u, const float* grad_v,
                             float* grad_f, double* grad_lambda, const rdseg_fit* fit,

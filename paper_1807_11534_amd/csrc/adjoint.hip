@@ -293,13 +293,15 @@ __global__ __launch_bounds__(RED_T) void k_adj_final(
 __global__ __launch_bounds__(RED_T) void k_reduce_partials(const double* __restrict__ part,
                                                            int nblk, int nv,
                                                            double* __restrict__ out) {
-    // one thread per value, fixed sequential order over blocks
-    int k = threadIdx.x;
-    if (k < nv) {
-        double s = 0.0;
-        for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * 4 + k];
-        out[k] = s;
-    }
+    // one wave per value: lane l sums blocks l, l + 64, ... in order (their
+    // loads independent of each other), then a fixed xor tree over the lanes;
+    // the order is the same on every call
+    const int k = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (k >= nv) return;   // uniform per wave
+    double s = 0.0;
+    for (int b = lane; b < nblk; b += 64) s += part[(int64_t)b * 4 + k];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (lane == 0) out[k] = s;
 }
 
 __global__ __launch_bounds__(256) void k_fit_fwd(const float* __restrict__ z,

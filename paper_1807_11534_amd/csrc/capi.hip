@@ -697,12 +697,14 @@ rdseg_status solve_impl(const float* f, rdseg_shape s, const rdseg_params* prm, 
     // also keeps closed tiles in the blocked kernel.
     // Small RD components (<= 64 pixels) run whole in the component kernel
     // (which covers every closed tile as well: a closed tile's components are
-    // inside it); plain solves only, and index arithmetic in int32.
+    // inside it); not under the stopping rule, and index arithmetic in int32.
+    // With a tape the component kernel writes its pixels' checkpoints (the
+    // tile path's checkpoint copies take only the RD pixels left to it).
+    const bool taped = prm->ckpt_every > 0 && tape;
     const int want_comps = prm->components ? prm->components : (tuned_comps ? tuned_comps : 1);
-    const bool comps = want_comps == 1 && g_components_on.load() &&
-                       !(prm->ckpt_every > 0 && tape) && prm->iters > 0 && !stop &&
+    const bool comps = want_comps == 1 && g_components_on.load() && prm->iters > 0 && !stop &&
                        g.plane <= ((int64_t)1 << 29);
-    const bool use_closed = !(prm->ckpt_every > 0 && tape) && prm->iters > 0 && !stop && !comps;
+    const bool use_closed = !taped && prm->iters > 0 && !stop && !comps;
     if (stop && stop->n_checks > 0 &&
         launch_fill(reinterpret_cast<float*>(stop->slots), 1, stop->n_checks, stop->n_checks,
                     0.0f, st))
@@ -716,17 +718,17 @@ rdseg_status solve_impl(const float* f, rdseg_shape s, const rdseg_params* prm, 
     // solve; it needs all of them resident at once, so closed tiles then run
     // before it on the same stream instead of beside it.
     bool resident = false;
-    if (g_resident_on.load() && !stop && !(prm->ckpt_every > 0 && tape) && prm->iters > 0 &&
-        resident_fits(ci, nm)) {
+    if (g_resident_on.load() && !stop && !taped && prm->iters > 0 && resident_fits(ci, nm)) {
         hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
         resident = hipStreamIsCapturing(st, &cap) == hipSuccess && cap == hipStreamCaptureStatusNone;
     }
     hipEvent_t join = nullptr;
+    auto small = [&](hipStream_t cs) {
+        return launch_components(d, w.comp, w.npix, prm->iters, inner, (float)prm->theta,
+                                 (float)(1.0 / prm->theta), (float)prm->tau,
+                                 taped ? tape : nullptr, taped ? prm->ckpt_every : 0, cs);
+    };
     if (comps) {
-        auto small = [&](hipStream_t cs) {
-            return launch_components(d, w.comp, w.npix, prm->iters, inner, (float)prm->theta,
-                                     (float)(1.0 / prm->theta), (float)prm->tau, cs);
-        };
         if (resident) {
             if (small(st)) return RDSEG_ERR_HIP;
         } else {
@@ -767,7 +769,23 @@ rdseg_status solve_impl(const float* f, rdseg_shape s, const rdseg_params* prm, 
     a.mflags = w.flags;
     a.epoch = w.epoch;
     if (comps) a.npix = w.comp.npix_tile;   // timing counts the tile path's pixels
-    r = enqueue_iterations(a);
+    // A taped solve whose RD pixels all went to the component path leaves the
+    // tile path nothing but launches on an empty queue and checkpoint copies
+    // of no pixel: read the queue length once (synchronises; not under graph
+    // capture) and skip them.
+    bool tiles_left = true;
+    if (comps && taped) {
+        hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(st, &cap) == hipSuccess && cap == hipStreamCaptureStatusNone) {
+            int32_t nq = 1;
+            if (hipMemcpyAsync(&nq, w.totals, sizeof(int32_t), hipMemcpyDeviceToHost, st) !=
+                    hipSuccess ||
+                hipStreamSynchronize(st) != hipSuccess)
+                r = fail(RDSEG_ERR_HIP, "reading the tile queue length failed");
+            tiles_left = nq > 0;
+        }
+    }
+    if (!r && tiles_left) r = enqueue_iterations(a);
     const rdseg_status rj = join_closed(st, join);
     if (r) return r;
     if (rj) return rj;
@@ -945,6 +963,7 @@ struct BackWs {
     int32_t* totals;
     double* red;       // reduction partials
     double* out4;
+    CompWs comp;       // small-component path
     size_t bytes;
 };
 
@@ -966,6 +985,14 @@ BackWs carve_back(void* base, const rdseg_shape& s, int ce) {
     w.totals = cv.take<int32_t>(4);
     w.red = cv.take<double>(reduce_partials(s.H));
     w.out4 = cv.take<double>(4);
+    w.comp.lab = cv.take<int32_t>(g.plane);
+    w.comp.csize = cv.take<int32_t>(g.plane);
+    w.comp.crank = cv.take<int32_t>(g.plane);
+    w.comp.cslot = cv.take<int32_t>(g.plane);
+    w.comp.lane_of = cv.take<int32_t>(g.plane);
+    w.comp.wl_pix = cv.take<int32_t>(2 * g.plane + 7 * 64);
+    w.comp.ccount = cv.take<int32_t>(8);
+    w.comp.npix_tile = cv.take<int64_t>(1);
     w.bytes = cv.off;
     return w;
 }
@@ -1495,6 +1522,12 @@ rdseg_status rdseg_backward(const float* f, rdseg_shape s, const rdseg_params* p
     OffTables off{nullptr, nullptr, nullptr, nullptr};
     if (launch_init(&d, nullptr, off, 1, s.H, st)) return RDSEG_ERR_HIP;   // c only
     if (launch_tile_masks(&d, nullptr, off, 1, g.strips, w.masks, w.npix, st)) return RDSEG_ERR_HIP;
+    const int K = prm->iters;
+    // RD components of at most 64 pixels take the component reverse sweep
+    // (every step in one launch); the tile path below covers the rest
+    const bool comps = g_components_on.load() && prm->components != 2 && K > 0 &&
+                       g.plane <= ((int64_t)1 << 29);
+    if (comps && launch_components_prepare(d, w.comp, w.masks, w.npix, st)) return RDSEG_ERR_HIP;
     const int64_t nm = macro_count(s, kAdjTile, kAdjTile);
     QueueScratch qs{nullptr, nullptr, w.flags, w.offs, w.part};
     if (launch_macro_queue(&d, nullptr, off, 1, nm, kAdjTile, kAdjTile, w.masks, qs, w.queue,
@@ -1503,15 +1536,31 @@ rdseg_status rdseg_backward(const float* f, rdseg_shape s, const rdseg_params* p
     if (launch_fill(w.sacc, s.H, s.W, (int)s.ld, 0.0f, st)) return RDSEG_ERR_HIP;
     const float theta = (float)prm->theta, inv_theta = (float)(1.0 / prm->theta);
     const float tau = (float)prm->tau;
+    // with the component path on, skip the tile path when no macro tile is
+    // left to it (one read of the queue length, which synchronises)
+    int32_t n_tiles_left = 1;
+    if (comps) {
+        if (hipMemcpyAsync(&n_tiles_left, w.totals, sizeof(int32_t), hipMemcpyDeviceToHost, st) !=
+                hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return fail(RDSEG_ERR_HIP, "reading the tile queue length failed");
+    }
     AdjBufs ab;
     ab.pbx[0] = w.ab[0]; ab.pby[0] = w.ab[1]; ab.vb[0] = w.ab[2];
     ab.pbx[1] = w.ab[3]; ab.pby[1] = w.ab[4]; ab.vb[1] = w.ab[5];
     ab.sacc = w.sacc;
-    const int K = prm->iters;
     const int nseg = (K + ce - 1) / ce;
     const int64_t plane = g.plane;
+    hipEvent_t join = nullptr;
+    if (comps) {
+        rdseg_status rc = closed_beside(st, &join, [&](hipStream_t cs) {
+            return launch_adj_components(d, w.comp, w.npix, tape, w.seg, K, ce, grad_u, grad_v,
+                                         ab.vb[K % 2], w.sacc, theta, inv_theta, tau, cs);
+        });
+        if (rc) return rc;
+    }
     int in_buf = 0;
-    for (int sg = nseg - 1; sg >= 0; --sg) {
+    for (int sg = n_tiles_left > 0 ? nseg - 1 : -1; sg >= 0; --sg) {
         const int k0 = sg * ce;
         const int len = std::min(ce, K - k0);
         auto slot = [&](int j) -> float* {
@@ -1538,6 +1587,12 @@ rdseg_status rdseg_backward(const float* f, rdseg_shape s, const rdseg_params* p
             in_buf = 1 - in_buf;
         }
     }
+    if (n_tiles_left == 0) in_buf = K % 2;   // where the skipped steps would have left vbar
+    {
+        const rdseg_status rj = join_closed(st, join);
+        if (rj) return rj;
+    }
+    if (comps && launch_components_restore(d, w.comp, w.npix, st)) return RDSEG_ERR_HIP;
     const float* vb0 = ab.vb[in_buf];
     if (K == 0) {
         if (grad_v) {

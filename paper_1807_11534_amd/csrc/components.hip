@@ -221,7 +221,8 @@ __global__ __launch_bounds__(256) void k_cc_assign(ImgDesc d, CompWs w, uint64_t
 // neighbours as constants (w right and below, p = 0 left and above).
 __global__ __launch_bounds__(256) void k_components(ImgDesc d, CompWs w, const int64_t* npix,
                                                     int iters, int inner, float theta,
-                                                    float inv_theta, float tau) {
+                                                    float inv_theta, float tau,
+                                                    float* __restrict__ tape, int ce) {
     if (cc_skip(npix, d)) return;
     const int64_t plane = (int64_t)d.H * d.ld;
     const int nwaves = (int)min((int64_t)class_base(w.ccount, kClasses),
@@ -283,7 +284,20 @@ __global__ __launch_bounds__(256) void k_components(ImgDesc d, CompWs w, const i
         float wv = w_of(dd, v, inv_theta, mine);
         const int steps = iters * inner;
         int left = inner;
+        // checkpoints (inner = 1): the state before iteration k goes to tape
+        // slot k / ce whenever ce divides k
+        int to_ckpt = 0, slot = 0;
         for (int it = 0; it < steps; ++it) {
+            if (tape && to_ckpt-- == 0) {
+                to_ckpt = ce - 1;
+                if (mine) {
+                    float* __restrict__ t = tape + (int64_t)slot * 3 * plane;
+                    t[gg] = v;
+                    t[plane + gg] = px;
+                    t[2 * plane + gg] = py;
+                }
+                ++slot;
+            }
             const float wr = from(aR, wv), wd = from(aD, wv);
             const DualOut o = dual_update(px, py, wv, nR >= 0 ? wr : wR, nD >= 0 ? wd : wD, fl, tau);
             px = o.px;
@@ -312,12 +326,208 @@ __global__ __launch_bounds__(256) void k_components(ImgDesc d, CompWs w, const i
     }
 }
 
+// Reverse sweep of the small components, every segment in one launch: per
+// segment (last first) each lane loads its pixel's checkpoint from the tape,
+// recomputes the segment's forward states (the arithmetic of one k_iterate
+// iteration) and then runs the segment's reverse steps with the arithmetic of
+// k_adj_step, neighbour values from other lanes and frozen neighbours as
+// constants (w right / below; p, ubar, gbar and wbar are 0 there).  The
+// recomputed states go to LDS when the segment fits (lds_slots = ce - 1 > 0:
+// one wave per workgroup, lane-major slots [ce - 1][3][64]), else to the
+// per-pixel slots of seg that the tile path uses.  The adjoint state (pbar,
+// vbar) and the clamp-adjoint sum stay in registers; the sum goes to sacc and
+// vbar^0 to vb_out at the end.  Results are bitwise those of the tile path.
+__global__ __launch_bounds__(256) void k_adj_components(
+    ImgDesc d, CompWs w, const int64_t* npix, const float* __restrict__ tape,
+    float* __restrict__ seg, int K, int ce, const float* __restrict__ grad_u,
+    const float* __restrict__ grad_v, float* __restrict__ vb_out, float* __restrict__ sacc,
+    float theta, float inv_theta, float tau, int lds_slots) {
+    extern __shared__ float s_states[];
+    if (cc_skip(npix, d)) return;
+    const int64_t plane = (int64_t)d.H * d.ld;
+    const int nwaves = (int)min((int64_t)class_base(w.ccount, kClasses),
+                                (2 * plane + kWlExtra) / 64);
+    const int lane = threadIdx.x & 63;
+    const int wpb = (int)(blockDim.x >> 6);
+    float* __restrict__ my_states = s_states + (threadIdx.x >> 6) * lds_slots * 192 + lane;
+    for (int wave = blockIdx.x * wpb + (threadIdx.x >> 6); wave < nwaves;
+         wave += gridDim.x * wpb) {   // uniform per wave
+        const int g = w.wl_pix[wave * 64 + lane];
+        const bool mine = g >= 0 && g < plane;
+        const int gg = mine ? g : 0;
+        const int y = gg / d.ld, x = gg - y * d.ld;
+        const float c = mine ? c_of(d.f[gg], d.delta, d.tl) : __builtin_inff();
+        uint32_t fl = mine ? (CF_ACT | CF_OUT) : 0u;
+        if (mine && x == d.W - 1) fl |= CF_LASTC;
+        if (mine && y == d.H - 1) fl |= CF_LASTR;
+        const bool lastc = (fl & CF_LASTC) != 0, lastr = (fl & CF_LASTR) != 0;
+        int nR = -1, nD = -1, nL = -1, nU = -1;
+        float wR = 0.0f, wD = 0.0f;
+        if (mine) {
+            if (x + 1 < d.W) {
+                const int L = w.lane_of[gg + 1];
+                if (L >= 0) nR = L & 63;
+                else wR = w_of(0.0f, heav_from_c(c_of(d.f[gg + 1], d.delta, d.tl)), inv_theta, false);
+            } else {
+                wR = w_of(0.0f, 0.0f, inv_theta, false);
+            }
+            if (y + 1 < d.H) {
+                const int L = w.lane_of[gg + d.ld];
+                if (L >= 0) nD = L & 63;
+                else wD = w_of(0.0f, heav_from_c(c_of(d.f[gg + d.ld], d.delta, d.tl)), inv_theta, false);
+            } else {
+                wD = w_of(0.0f, 0.0f, inv_theta, false);
+            }
+            if (x > 0) {
+                const int L = w.lane_of[gg - 1];
+                if (L >= 0) nL = L & 63;
+            }
+            if (y > 0) {
+                const int L = w.lane_of[gg - d.ld];
+                if (L >= 0) nU = L & 63;
+            }
+        }
+        const int aR = 4 * (nR >= 0 ? nR : lane), aD = 4 * (nD >= 0 ? nD : lane);
+        const int aL = 4 * (nL >= 0 ? nL : lane), aU = 4 * (nU >= 0 ? nU : lane);
+        auto from = [](int addr, float a) {
+            return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(a)));
+        };
+        // x - 1 / y - 1 neighbours of a quantity that is 0 at frozen cells
+        auto left = [&](float a) { const float t = from(aL, a); return nL >= 0 ? t : 0.0f; };
+        auto up = [&](float a) { const float t = from(aU, a); return nU >= 0 ? t : 0.0f; };
+        auto right0 = [&](float a) { const float t = from(aR, a); return nR >= 0 ? t : 0.0f; };
+        auto down0 = [&](float a) { const float t = from(aD, a); return nD >= 0 ? t : 0.0f; };
+
+        float pbx = 0.0f, pby = 0.0f;
+        float vb = (mine && grad_v) ? grad_v[gg] : 0.0f;
+        float S = 0.0f;
+        const int nseg = (K + ce - 1) / ce;
+        for (int sg = nseg - 1; sg >= 0; --sg) {
+            const int k0 = sg * ce;
+            const int len = min(ce, K - k0);
+            const float* __restrict__ s0 = tape + (int64_t)sg * 3 * plane;
+            float cv = 0.0f, cpx = 0.0f, cpy = 0.0f;   // the checkpoint, state k0
+            if (mine) {
+                cv = s0[gg];
+                cpx = s0[plane + gg];
+                cpy = s0[2 * plane + gg];
+            }
+            // forward: the states k0 + 1 .. k0 + len - 1 of this segment
+            {
+                float v = cv, px = cpx, py = cpy;
+                for (int j = 1; j < len; ++j) {
+                    float dd = div_p(px, left(px), py, up(py));
+                    const float wv = w_of(dd, v, inv_theta, mine);
+                    const float wr = from(aR, wv), wd = from(aD, wv);
+                    const DualOut o = dual_update(px, py, wv, nR >= 0 ? wr : wR,
+                                                  nD >= 0 ? wd : wD, fl, tau);
+                    px = o.px;
+                    py = o.py;
+                    dd = div_p(px, left(px), py, up(py));
+                    v = v_step(u_step(v, dd, theta), c);
+                    if (lds_slots) {
+                        float* __restrict__ sj = my_states + (j - 1) * 192;
+                        sj[0] = v;
+                        sj[64] = px;
+                        sj[128] = py;
+                    } else if (mine) {
+                        float* __restrict__ sj = seg + (int64_t)(j - 1) * 3 * plane;
+                        sj[gg] = v;
+                        sj[plane + gg] = px;
+                        sj[2 * plane + gg] = py;
+                    }
+                }
+            }
+            // reverse: steps k0 + len .. k0 + 1 from the states k - 1
+            for (int k = k0 + len; k >= k0 + 1; --k) {
+                const int j = k - 1 - k0;
+                float sv = 0.0f, spx = 0.0f, spy = 0.0f;
+                if (j == 0) {
+                    sv = cv;
+                    spx = cpx;
+                    spy = cpy;
+                } else if (lds_slots) {
+                    const float* __restrict__ sj = my_states + (j - 1) * 192;
+                    sv = mine ? sj[0] : 0.0f;
+                    spx = mine ? sj[64] : 0.0f;
+                    spy = mine ? sj[128] : 0.0f;
+                } else if (mine) {
+                    const float* __restrict__ sj = seg + (int64_t)(j - 1) * 3 * plane;
+                    sv = sj[gg];
+                    spx = sj[plane + gg];
+                    spy = sj[2 * plane + gg];
+                }
+                // w from p^(k-1), v^(k-1); the dual update gives p^k, g and m
+                const float dd = div_p(spx, left(spx), spy, up(spy));
+                const float wv = w_of(dd, sv, inv_theta, mine);
+                const float wr = from(aR, wv), wd = from(aD, wv);
+                const DualOut o = dual_update(spx, spy, wv, nR >= 0 ? wr : wR, nD >= 0 ? wd : wD,
+                                              fl, tau);
+                // u^k, clamp argument, clamp adjoint, ubar
+                const float d1 = div_p(o.px, left(o.px), o.py, up(o.py));
+                const float u = u_step(sv, d1, theta);
+                const float sarg = u - c;
+                const float sb = (mine && sarg > 0.0f && sarg < 1.0f) ? vb : 0.0f;
+                float ub = sb;
+                if (k == K && grad_u && mine) ub += grad_u[gg];
+                ub = mine ? ub : 0.0f;
+                // pbt = pbar^k + theta grad(ubar); gbar
+                const float gux = lastc ? 0.0f : (right0(ub) - ub);
+                const float guy = lastr ? 0.0f : (down0(ub) - ub);
+                const float ptx = mine ? fmaf(theta, gux, pbx) : 0.0f;
+                const float pty = mine ? fmaf(theta, guy, pby) : 0.0f;
+                const float nn = __builtin_amdgcn_sqrtf(fmaf(o.gx, o.gx, o.gy * o.gy));
+                const float inv_n = nn > 0.0f ? __builtin_amdgcn_rcpf(nn) : 0.0f;
+                const float tm = tau * o.m;
+                const float dot = fmaf(o.px, ptx, o.py * pty);
+                const float k2 = tm * dot * inv_n;
+                float gbx = fmaf(tm, ptx, -k2 * o.gx);
+                float gby = fmaf(tm, pty, -k2 * o.gy);
+                gbx = (mine && !lastc) ? gbx : 0.0f;
+                gby = (mine && !lastr) ? gby : 0.0f;
+                // wbar = -div gbar; pbar^(k-1), vbar^(k-1)
+                const float dg = div_p(gbx, left(gbx), gby, up(gby));
+                const float wb = mine ? -dg : 0.0f;
+                const float gwx = lastc ? 0.0f : (right0(wb) - wb);
+                const float gwy = lastr ? 0.0f : (down0(wb) - wb);
+                pbx = lastc ? 0.0f : fmaf(o.m, ptx, -gwx);
+                pby = lastr ? 0.0f : fmaf(o.m, pty, -gwy);
+                vb = fmaf(-wb, inv_theta, ub);
+                S += sb;
+            }
+        }
+        if (mine) {
+            sacc[gg] = S;
+            vb_out[gg] = vb;
+        }
+    }
+}
+
+// c of the small-component pixels back to theta lambda f (after the solve's
+// tile path, for passes that test RD through c).
+__global__ __launch_bounds__(256) void k_cc_restore(ImgDesc d, CompWs w, const int64_t* npix) {
+    if (cc_skip(npix, d)) return;
+    const int64_t plane = (int64_t)d.H * d.ld;
+    const int64_t lanes = min((int64_t)class_base(w.ccount, kClasses) * 64, 2 * plane + kWlExtra);
+    for (int64_t L = (int64_t)blockIdx.x * 256 + threadIdx.x; L < lanes;
+         L += (int64_t)gridDim.x * 256) {
+        const int g = w.wl_pix[L];
+        if (g >= 0 && g < plane) d.c[g] = c_of(d.f[g], d.delta, d.tl);
+    }
+}
+
 unsigned grid_for(int64_t n) {
     const int64_t b = (n + 255) / 256;
     return (unsigned)(b < 4096 ? (b < 1 ? 1 : b) : 4096);
 }
 
 int g_comp_grid = 0;
+int g_adj_comp_grid = 0;
+// LDS form of the component reverse sweep: (ce - 1) x 768 bytes per wave, at
+// most the default 64 KiB of a workgroup; the grid for the last size used
+constexpr int kAdjLdsMax = 65536;
+size_t g_adj_lds_bytes = 0;
+int g_adj_lds_grid = 0;
 
 }  // namespace
 
@@ -336,7 +546,12 @@ int launch_components_prepare(const ImgDesc& d, const CompWs& w, uint64_t* masks
 }
 
 int launch_components(const ImgDesc& d, const CompWs& w, const int64_t* npix, int iters,
-                      int inner, float theta, float inv_theta, float tau, hipStream_t st) {
+                      int inner, float theta, float inv_theta, float tau, float* tape, int ce,
+                      hipStream_t st) {
+    if (tape && (ce <= 0 || inner != 1)) {
+        set_error("component checkpoints need ckpt_every > 0 and inner = 1");
+        return 3;
+    }
     if (g_comp_grid == 0) {
         g_comp_grid = persistent_blocks(reinterpret_cast<const void*>(k_components), 256, 0);
         if (g_comp_grid <= 0) {
@@ -346,7 +561,51 @@ int launch_components(const ImgDesc& d, const CompWs& w, const int64_t* npix, in
         }
     }
     hipLaunchKernelGGL(k_components, dim3((unsigned)g_comp_grid), dim3(256), 0, st, d, w, npix,
-                       iters, inner, theta, inv_theta, tau);
+                       iters, inner, theta, inv_theta, tau, tape, ce);
+    RDSEG_HIP_CHECK(hipGetLastError());
+    return 0;
+}
+
+int launch_adj_components(const ImgDesc& d, const CompWs& w, const int64_t* npix,
+                          const float* tape, float* seg, int K, int ce, const float* grad_u,
+                          const float* grad_v, float* vb_out, float* sacc, float theta,
+                          float inv_theta, float tau, hipStream_t st) {
+    const size_t lds = (size_t)(ce - 1) * 192 * sizeof(float);
+    if (ce > 1 && lds <= (size_t)kAdjLdsMax) {
+        if (g_adj_lds_bytes != lds || g_adj_lds_grid <= 0) {
+            g_adj_lds_grid = persistent_blocks(reinterpret_cast<const void*>(k_adj_components), 64, lds);
+            g_adj_lds_bytes = lds;
+            if (g_adj_lds_grid <= 0) {
+                g_adj_lds_grid = 0;
+                set_error("occupancy query failed for the component adjoint kernel");
+                return 4;
+            }
+        }
+        hipLaunchKernelGGL(k_adj_components, dim3((unsigned)g_adj_lds_grid), dim3(64), lds, st, d,
+                           w, npix, tape, seg, K, ce, grad_u, grad_v, vb_out, sacc, theta,
+                           inv_theta, tau, ce - 1);
+        RDSEG_HIP_CHECK(hipGetLastError());
+        return 0;
+    }
+    if (g_adj_comp_grid == 0) {
+        g_adj_comp_grid = persistent_blocks(reinterpret_cast<const void*>(k_adj_components), 256, 0);
+        if (g_adj_comp_grid <= 0) {
+            g_adj_comp_grid = 0;
+            set_error("occupancy query failed for the component adjoint kernel");
+            return 4;
+        }
+    }
+    hipLaunchKernelGGL(k_adj_components, dim3((unsigned)g_adj_comp_grid), dim3(256), 0, st, d, w,
+                       npix, tape, seg, K, ce, grad_u, grad_v, vb_out, sacc, theta, inv_theta,
+                       tau, 0);
+    RDSEG_HIP_CHECK(hipGetLastError());
+    return 0;
+}
+
+int launch_components_restore(const ImgDesc& d, const CompWs& w, const int64_t* npix,
+                              hipStream_t st) {
+    hipLaunchKernelGGL(k_cc_restore, dim3(grid_for(2 * (int64_t)d.H * d.ld)), dim3(256), 0, st, d,
+                       w, npix);
     RDSEG_HIP_CHECK(hipGetLastError());
     return 0;
 }

@@ -173,11 +173,26 @@ struct CompWs {
 // into waves and freeze their pixels for the tile path (c = +inf, tile-mask
 // bits cleared, w.npix_tile = the RD pixels left to it); then run every
 // iteration of them.  Both do nothing on the device when more than 55 % of
-// the pixels are RD (npix_tile is still written).
+// the pixels are RD (npix_tile is still written).  With a tape (inner = 1,
+// ce > 0) the component kernel also writes its pixels' checkpoints (the state
+// before iteration k into slot k / ce, [3][H][ld] per slot); the tile path's
+// copies write only the RD pixels left to it, so the two may run side by side.
 int launch_components_prepare(const ImgDesc& d, const CompWs& w, uint64_t* masks,
                               const int64_t* npix, hipStream_t st);
 int launch_components(const ImgDesc& d, const CompWs& w, const int64_t* npix, int iters,
-                      int inner, float theta, float inv_theta, float tau, hipStream_t st);
+                      int inner, float theta, float inv_theta, float tau, float* tape, int ce,
+                      hipStream_t st);
+// The reverse sweep of the small components (all K steps of the adjoint,
+// segments of ce steps recomputed from the tape checkpoints into LDS when
+// (ce - 1) x 768 bytes fit a workgroup, else into seg, the (ce - 1) x
+// [3][H][ld] slots of the backward): writes sacc and vbar^0 (vb_out) of their
+// pixels.  Then c of those pixels back to theta lambda f.
+int launch_adj_components(const ImgDesc& d, const CompWs& w, const int64_t* npix,
+                          const float* tape, float* seg, int K, int ce, const float* grad_u,
+                          const float* grad_v, float* vb_out, float* sacc, float theta,
+                          float inv_theta, float tau, hipStream_t st);
+int launch_components_restore(const ImgDesc& d, const CompWs& w, const int64_t* npix,
+                              hipStream_t st);
 
 // Resident form of a whole single-image solve: whether configuration ci has a
 // resident kernel whose workgroups, one per queued macro tile (at most

@@ -229,3 +229,45 @@ def test_backward_full_size_differentiation_workload(rd):
         A = np.abs(prob.f.astype(np.float64)) < delta
         assert (res[0][0][~A] == 0).all()
         assert np.isfinite(res[0][0]).all() and math.isfinite(res[0][1])
+
+
+@pytest.mark.parametrize("case", [("config5_512", 0.1, 300, 30), ("config5_512", 0.5, 120, 30),
+                                  ("ragged", 0.4, 90, 30), ("ragged", 0.4, 90, 7),
+                                  ("config5_512", 0.5, 120, 100)])
+def test_component_reverse_matches_tile_path(rd, case):
+    """RD components of at most 64 pixels in both directions: the component
+    forward writes the same checkpoints (on RD, where the tape is defined) and
+    the same u, v, p as the tile path, and their reverse sweep (all steps in
+    one launch; states in LDS for ckpt_every <= 86, else in the per-pixel
+    segment slots) gives the same bits as the tile path's per-step launches,
+    with a fitting-term gradient and both adjoint inputs."""
+    name, frac, K, ce = case
+    if name == "ragged":
+        f = synth.smooth_field(173, 211, 45, noise=0.35)
+        z = synth.smooth_field(173, 211, 46, noise=0.1)
+        target = (f < 0).astype(np.float32)
+    else:
+        prob = synth.config5(size=512)
+        f, z, target = prob.f, prob.z, prob.mask.astype(np.float32)
+    delta = synth.band_delta(f, frac)
+    A = np.abs(f.astype(np.float64)) < delta
+    fd = dev(f)
+    print(f"component forward / reverse {case}", flush=True)
+    out = {}
+    try:
+        for on in (False, True):
+            rd.set_components(on)
+            u, v, p, tape = rd.solve(fd, 4.0, 0.1, 0.125, delta, K, tile=(32, 32),
+                                     iters_per_launch=2, ckpt_every=ce)
+            gu = 2 * (u - dev(target))
+            gv = 0.5 * (v - dev(target))
+            fit = (dev(z), None, 0.8, 0.2, 0.0)
+            H, W = f.shape
+            slots = host(tape).reshape(-1, 3, H, W)[:, :, A]
+            out[on] = [host(u), host(v), host(p), slots] + [
+                host(x) for x in rd.backward(fd, 4.0, 0.1, 0.125, delta, K, ce, tape, gu, gv,
+                                             fit=fit)]
+    finally:
+        rd.set_components(True)
+    for a, b in zip(out[True], out[False]):
+        np.testing.assert_array_equal(a, b)
