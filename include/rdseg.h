@@ -386,6 +386,27 @@ rdseg_status rdseg_set_resident(int32_t on);
  * default) allows the component path.  Process-wide. */
 rdseg_status rdseg_set_components(int32_t on);
 
+/* The autotuner's cache (the choices of rdseg_autotune, keyed by size class
+ * and active-fraction bucket, read by solves that let the library choose) as
+ * JSON text, so that a tuning run can be kept and reloaded in a later process:
+ *   {"version": 1, "entries": [{"size_class": c, "q_bucket": b, "tile_w": w,
+ *    "tile_h": h, "iters_per_launch": i, "components": m}, ...]}
+ * size_class c: the number of times H * W can be divided by 4 while it stays
+ * above 4096 (at most 12); q_bucket b: 0 for an active fraction q < 0.01,
+ * 1 for q < 0.05, 2 for q < 0.2, 3 for q < 0.5, 4 above; components m: 1 on,
+ * 2 off.  Host memory only; no GPU call.
+ * rdseg_tune_cache_export writes the text and its NUL into buf (host, cap
+ * bytes; buf may be NULL when cap is 0) and the bytes needed, NUL included,
+ * into *len; RDSEG_ERR_ARG (buf untouched) if cap is smaller than that.
+ * rdseg_tune_cache_import merges the entries of such a text (host,
+ * NUL-terminated) into the cache, replacing entries with the same key; a text
+ * that does not parse, a key out of range or a configuration that is not
+ * compiled is RDSEG_ERR_ARG and nothing is merged.
+ * rdseg_tune_cache_clear empties the cache. */
+rdseg_status rdseg_tune_cache_export(char* buf, size_t cap, size_t* len);
+rdseg_status rdseg_tune_cache_import(const char* json);
+rdseg_status rdseg_tune_cache_clear(void);
+
 /* Number of compiled configurations and their parameters (i < count). */
 int32_t rdseg_config_count(void);
 rdseg_status rdseg_config_get(int32_t i, int32_t* tile_w, int32_t* tile_h,

@@ -108,6 +108,10 @@ SIGNATURES = {
     "rdseg_timing_reset": (ctypes.c_int, []),
     "rdseg_set_resident": (ctypes.c_int, [_i32]),
     "rdseg_set_components": (ctypes.c_int, [_i32]),
+    "rdseg_tune_cache_export": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_size_t,
+                                               ctypes.POINTER(ctypes.c_size_t)]),
+    "rdseg_tune_cache_import": (ctypes.c_int, [ctypes.c_char_p]),
+    "rdseg_tune_cache_clear": (ctypes.c_int, []),
     "rdseg_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "rdseg_last_error": (ctypes.c_char_p, []),
 }

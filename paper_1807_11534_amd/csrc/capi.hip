@@ -1091,6 +1091,115 @@ VolWs carve_vol(void* base, const rdseg_shape3& s) {
 
 }  // namespace
 
+// ------------------------------------------------------------------ tuning cache as text
+namespace {
+
+// Parser of the cache text: {"version": 1, "entries": [{"key": int, ...}, ...]}
+// (whitespace anywhere between tokens; keys in any order; no other values).
+struct CacheParser {
+    const char* p;
+    void ws() {
+        while (*p == ' ' || *p == '\t' || *p == '\n' || *p == '\r') ++p;
+    }
+    bool lit(char c) {
+        ws();
+        if (*p != c) return false;
+        ++p;
+        return true;
+    }
+    bool str(std::string& out) {
+        ws();
+        if (*p != '"') return false;
+        ++p;
+        out.clear();
+        while (*p && *p != '"') {
+            if (*p == '\\' || out.size() > 32) return false;
+            out += *p++;
+        }
+        if (*p != '"') return false;
+        ++p;
+        return true;
+    }
+    bool integer(long& v) {
+        ws();
+        const char* q = p;
+        if (*q == '-') ++q;
+        if (*q < '0' || *q > '9') return false;
+        char* end = nullptr;
+        v = strtol(p, &end, 10);
+        if (end == p || end - p > 10) return false;
+        p = end;
+        return true;
+    }
+};
+
+bool parse_cache_text(const char* text, std::vector<std::pair<TuneKey, TuneVal>>& out,
+                      std::string& why) {
+    CacheParser ps{text};
+    std::string key;
+    long version = -1;
+    bool have_entries = false;
+    if (!ps.lit('{')) { why = "expected '{'"; return false; }
+    if (ps.lit('}')) { why = "no \"entries\""; return false; }
+    do {
+        if (!ps.str(key) || !ps.lit(':')) { why = "expected a quoted key and ':'"; return false; }
+        if (key == "version") {
+            if (!ps.integer(version) || version != 1) { why = "version must be 1"; return false; }
+        } else if (key == "entries") {
+            have_entries = true;
+            if (!ps.lit('[')) { why = "entries must be a list"; return false; }
+            if (ps.lit(']')) continue;
+            do {
+                if (!ps.lit('{')) { why = "an entry must be an object"; return false; }
+                const char* names[6] = {"size_class", "q_bucket", "tile_w", "tile_h",
+                                        "iters_per_launch", "components"};
+                long val[6];
+                bool seen[6] = {false, false, false, false, false, false};
+                do {
+                    long x = 0;
+                    if (!ps.str(key) || !ps.lit(':') || !ps.integer(x)) {
+                        why = "an entry holds \"key\": integer pairs only";
+                        return false;
+                    }
+                    int k = -1;
+                    for (int j = 0; j < 6; ++j)
+                        if (key == names[j]) k = j;
+                    if (k < 0 || seen[k]) { why = "unknown or repeated key \"" + key + "\""; return false; }
+                    seen[k] = true;
+                    val[k] = x;
+                } while (ps.lit(','));
+                if (!ps.lit('}')) { why = "expected '}' after an entry"; return false; }
+                for (int j = 0; j < 6; ++j)
+                    if (!seen[j]) { why = std::string("entry without \"") + names[j] + "\""; return false; }
+                if (val[0] < 0 || val[0] > 12 || val[1] < 0 || val[1] > 4) {
+                    why = "size_class must lie in [0, 12] and q_bucket in [0, 4]";
+                    return false;
+                }
+                if (val[5] != 1 && val[5] != 2) { why = "components must be 1 or 2"; return false; }
+                if (val[2] < 1 || val[2] > 4096 || val[3] < 1 || val[3] > 4096 || val[4] < 1 ||
+                    val[4] > 4096) {
+                    why = "tile_w, tile_h and iters_per_launch out of range";
+                    return false;
+                }
+                const int ci = config_index((int)val[2], (int)val[3], (int)val[4]);
+                if (ci < 0) { why = "an entry names a configuration that is not compiled"; return false; }
+                out.push_back({TuneKey{(int)val[0], (int)val[1]}, TuneVal{ci, (int)val[5]}});
+            } while (ps.lit(','));
+            if (!ps.lit(']')) { why = "expected ']' after the entries"; return false; }
+        } else {
+            why = "unknown key \"" + key + "\"";
+            return false;
+        }
+    } while (ps.lit(','));
+    if (!ps.lit('}')) { why = "expected '}'"; return false; }
+    ps.ws();
+    if (*ps.p) { why = "text after the closing '}'"; return false; }
+    if (version != 1 || !have_entries) { why = "needs \"version\": 1 and \"entries\""; return false; }
+    return true;
+}
+
+}  // namespace
+
 // ====================================================================== C ABI
 extern "C" {
 
@@ -1753,6 +1862,48 @@ rdseg_status rdseg_autotune(const float* f, rdseg_shape s, const rdseg_params* p
     if (tile_h) *tile_h = c.by;
     if (iters_per_launch) *iters_per_launch = c.it;
     if (components) *components = best_comps;
+    return RDSEG_OK;
+}
+
+rdseg_status rdseg_tune_cache_export(char* buf, size_t cap, size_t* len) {
+    if (!len) return fail(RDSEG_ERR_ARG, "len is NULL");
+    std::string t = "{\"version\": 1, \"entries\": [";
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        bool first = true;
+        for (const auto& kv : g_tune) {
+            const TileCfg c = config_at(kv.second.ci);
+            char e[256];
+            snprintf(e, sizeof(e),
+                     "%s\n  {\"size_class\": %d, \"q_bucket\": %d, \"tile_w\": %d, \"tile_h\": %d, "
+                     "\"iters_per_launch\": %d, \"components\": %d}",
+                     first ? "" : ",", kv.first.cls, kv.first.qb, c.bx, c.by, c.it,
+                     kv.second.comps);
+            t += e;
+            first = false;
+        }
+    }
+    t += "]}\n";
+    *len = t.size() + 1;
+    if (cap < t.size() + 1 || !buf)
+        return fail(RDSEG_ERR_ARG, "buffer too small: need " + std::to_string(t.size() + 1) + " bytes");
+    memcpy(buf, t.c_str(), t.size() + 1);
+    return RDSEG_OK;
+}
+
+rdseg_status rdseg_tune_cache_import(const char* json) {
+    if (!json) return fail(RDSEG_ERR_ARG, "json is NULL");
+    std::vector<std::pair<TuneKey, TuneVal>> entries;
+    std::string why;
+    if (!parse_cache_text(json, entries, why)) return fail(RDSEG_ERR_ARG, "tuning cache text: " + why);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const auto& e : entries) g_tune[e.first] = e.second;
+    return RDSEG_OK;
+}
+
+rdseg_status rdseg_tune_cache_clear(void) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.clear();
     return RDSEG_OK;
 }
 

@@ -448,6 +448,35 @@ def set_components(on=True):
     check(_lib.load().rdseg_set_components(1 if on else 0))
 
 
+def tune_cache_export():
+    """The autotuner's cache as JSON text (see rdseg_tune_cache_export)."""
+    lib = _lib.load()
+    n = ctypes.c_size_t(0)
+    lib.rdseg_tune_cache_export(None, 0, ctypes.byref(n))   # asks for the size
+    buf = ctypes.create_string_buffer(n.value)
+    check(lib.rdseg_tune_cache_export(buf, n.value, ctypes.byref(n)))
+    return buf.value.decode()
+
+
+def tune_cache_import(text):
+    """Merge JSON text of rdseg_tune_cache_export's form into the cache."""
+    check(_lib.load().rdseg_tune_cache_import(text.encode()))
+
+
+def tune_cache_clear():
+    check(_lib.load().rdseg_tune_cache_clear())
+
+
+def tune_cache_save(path):
+    with open(path, "w") as fh:
+        fh.write(tune_cache_export())
+
+
+def tune_cache_load(path):
+    with open(path) as fh:
+        tune_cache_import(fh.read())
+
+
 def timing_reset():
     check(_lib.load().rdseg_timing_reset())
 

@@ -200,3 +200,71 @@ def test_primal_dual_validation(lib):
                               None) == 3
     assert lib.rdseg_solve_pd(P(1), sh, ctypes.byref(prm), None, None, P(1), P(3), P(8), n,
                               None) == 1   # u aliases f
+
+
+def test_tune_cache_text_round_trip():
+    """The autotuner's cache as JSON text: export, clear, import, export again
+    (host only: no GPU call)."""
+    import json
+
+    from paper_1807_11534_amd import rdseg
+    rdseg.tune_cache_clear()
+    assert json.loads(rdseg.tune_cache_export()) == {"version": 1, "entries": []}
+    entries = [
+        {"size_class": 4, "q_bucket": 4, "tile_w": 64, "tile_h": 64, "iters_per_launch": 8,
+         "components": 2},
+        {"size_class": 4, "q_bucket": 1, "tile_w": 16, "tile_h": 16, "iters_per_launch": 16,
+         "components": 1},
+        {"size_class": 6, "q_bucket": 0, "tile_w": 8, "tile_h": 8, "iters_per_launch": 32,
+         "components": 2},
+    ]
+    rdseg.tune_cache_import(json.dumps({"version": 1, "entries": entries}))
+    got = json.loads(rdseg.tune_cache_export())
+    key = lambda e: (e["size_class"], e["q_bucket"])
+    assert sorted(got["entries"], key=key) == sorted(entries, key=key)
+    # a later entry with the same key replaces the earlier one
+    repl = dict(entries[0], tile_w=32, tile_h=32)
+    rdseg.tune_cache_import(json.dumps({"entries": [repl], "version": 1}))
+    got = {key(e): e for e in json.loads(rdseg.tune_cache_export())["entries"]}
+    assert got[(4, 4)] == repl and len(got) == 3
+    rdseg.tune_cache_clear()
+    assert json.loads(rdseg.tune_cache_export())["entries"] == []
+
+
+@pytest.mark.parametrize("text", [
+    "",
+    "{}",
+    '{"version": 2, "entries": []}',
+    '{"version": 1}',
+    '{"version": 1, "entries": [{"size_class": 4, "q_bucket": 4, "tile_w": 64, "tile_h": 64, '
+    '"iters_per_launch": 8}]}',
+    '{"version": 1, "entries": [{"size_class": 4, "q_bucket": 5, "tile_w": 64, "tile_h": 64, '
+    '"iters_per_launch": 8, "components": 1}]}',
+    '{"version": 1, "entries": [{"size_class": 4, "q_bucket": 4, "tile_w": 48, "tile_h": 64, '
+    '"iters_per_launch": 8, "components": 1}]}',
+    '{"version": 1, "entries": [{"size_class": 4, "q_bucket": 4, "tile_w": 64, "tile_h": 64, '
+    '"iters_per_launch": 8, "components": 3}]}',
+    '{"version": 1, "entries": []} trailing',
+    '{"version": 1, "entries": [], "extra": 1}',
+])
+def test_tune_cache_rejects_bad_text(text):
+    from paper_1807_11534_amd import rdseg
+    from paper_1807_11534_amd._lib import RdsegError
+    rdseg.tune_cache_clear()
+    rdseg.tune_cache_import('{"version": 1, "entries": [{"size_class": 1, "q_bucket": 0, '
+                            '"tile_w": 8, "tile_h": 8, "iters_per_launch": 8, "components": 2}]}')
+    before = rdseg.tune_cache_export()
+    with pytest.raises(RdsegError):
+        rdseg.tune_cache_import(text)
+    assert rdseg.tune_cache_export() == before   # nothing merged
+    rdseg.tune_cache_clear()
+
+
+def test_tune_cache_export_needs_room(lib):
+    n = ctypes.c_size_t(0)
+    assert lib.rdseg_tune_cache_export(None, 0, ctypes.byref(n)) == 1
+    assert n.value > 10
+    buf = ctypes.create_string_buffer(n.value - 1)
+    assert lib.rdseg_tune_cache_export(buf, n.value - 1, ctypes.byref(n)) == 1
+    buf = ctypes.create_string_buffer(n.value)
+    assert lib.rdseg_tune_cache_export(buf, n.value, ctypes.byref(n)) == 0
