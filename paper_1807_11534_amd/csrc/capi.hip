@@ -365,6 +365,8 @@ struct SolvePlanArgs {
     bool resident = false;                   // try the resident form first (single image)
     const int32_t* mflags = nullptr;         // resident: queued flag per macro tile
     int32_t* epoch = nullptr;                // resident: max_items + 1 int32 of workspace
+    const CompWs* comp = nullptr;            // resident: small components for idle workgroups
+    const int64_t* comp_npix = nullptr;      // resident: full RD count (the labelling's)
 };
 
 // Stopping rule of a convergence-driven solve: change slots (one uint32
@@ -471,7 +473,7 @@ rdseg_status enqueue_iterations(SolvePlanArgs& a) {
         const int rc = launch_resident(a.ci, *a.d0, a.queue, a.n_queue, a.mflags, a.epoch,
                                        a.epoch + a.max_items, a.max_items, L % 2, a.iters, IT,
                                        a.inner, a.theta, a.inv_theta, a.tau, a.st,
-                                       timed ? rec.e0 : nullptr);
+                                       timed ? rec.e0 : nullptr, a.comp, a.comp_npix);
         if (rc > 0) return RDSEG_ERR_HIP;
         if (rc == 0) {
             a.launches = 1;
@@ -729,9 +731,9 @@ rdseg_status solve_impl(const float* f, rdseg_shape s, const rdseg_params* prm, 
                                  taped ? tape : nullptr, taped ? prm->ckpt_every : 0, cs);
     };
     if (comps) {
-        if (resident) {
-            if (small(st)) return RDSEG_ERR_HIP;
-        } else {
+        // resident: the idle workgroups of the resident kernel take the
+        // components, and the component kernel follows it (below)
+        if (!resident) {
             r = closed_beside(st, &join, small);
             if (r) return r;
         }
@@ -769,6 +771,10 @@ rdseg_status solve_impl(const float* f, rdseg_shape s, const rdseg_params* prm, 
     a.mflags = w.flags;
     a.epoch = w.epoch;
     if (comps) a.npix = w.comp.npix_tile;   // timing counts the tile path's pixels
+    if (comps && resident) {
+        a.comp = &w.comp;
+        a.comp_npix = w.npix;
+    }
     // A taped solve whose RD pixels all went to the component path leaves the
     // tile path nothing but launches on an empty queue and checkpoint copies
     // of no pixel: read the queue length once (synchronises; not under graph
@@ -786,6 +792,9 @@ rdseg_status solve_impl(const float* f, rdseg_shape s, const rdseg_params* prm, 
         }
     }
     if (!r && tiles_left) r = enqueue_iterations(a);
+    // after a resident launch: returns at once when its idle workgroups ran
+    // the components, else runs them (serially, after the tiles)
+    if (!r && comps && resident && small(st)) r = RDSEG_ERR_HIP;
     const rdseg_status rj = join_closed(st, join);
     if (r) return r;
     if (rj) return rj;

@@ -18,7 +18,7 @@
 // other), so tiles never read a neighbour's halo while it is being written.
 // Pixels off RD are never read from or written to the state buffers: their
 // values (v = H(-f), p = 0) come from c = -/+inf.
-#include "rdseg_internal.h"
+#include "components_device.h"
 
 namespace rdseg {
 
@@ -476,7 +476,8 @@ __global__ __launch_bounds__(NT) void k_resident(ImgDesc d, const int2* __restri
                                                  int32_t* __restrict__ epoch,
                                                  int32_t* __restrict__ status, int in_buf,
                                                  int iters, int per, int inner, float theta,
-                                                 float inv_theta, float tau) {
+                                                 float inv_theta, float tau, CompWs cw,
+                                                 const int64_t* __restrict__ cnpix, int citers) {
     constexpr int RX = BX + 2 * IT + 1;
     constexpr int RY = BY + 2 * IT + 1;
     constexpr int RC = RX * RY;
@@ -496,7 +497,24 @@ __global__ __launch_bounds__(NT) void k_resident(ImgDesc d, const int2* __restri
     const int rank = blockIdx.x >> 3;
     const int chunk = (nq + 7) >> 3;
     const int item = xcd * chunk + rank;
-    if (rank >= chunk || item >= nq) return;   // the whole workgroup leaves together
+    if (rank >= chunk || item >= nq) {   // no tile for this workgroup
+        // With citers > 0 the idle workgroups (the grid holds one per macro
+        // tile of the image, the queue only the tiles left to the tile path)
+        // run the small components' iterations beside the tiles, and flag
+        // that they did (ccount[7], cleared by the labelling).  Workgroup ids
+        // among the idle ones: XCD by XCD, ranks past that XCD's tiles.
+        if (citers > 0 && !cc_skip(cnpix, d)) {
+            const int per_x = (int)gridDim.x >> 3;
+            auto tiles_of = [&](int x) { return max(0, min(chunk, nq - x * chunk)); };
+            int gid = rank - tiles_of(xcd);
+            for (int x = 0; x < xcd; ++x) gid += per_x - tiles_of(x);
+            const int idle = (int)gridDim.x - nq;
+            if (gid == 0 && t == 0) cw.ccount[7] = 1;
+            component_waves(d, cw, citers, inner, theta, inv_theta, tau, nullptr, 0,
+                            gid * (NT / 64) + (t >> 6), idle * (NT / 64));
+        }
+        return;   // the whole workgroup leaves together
+    }
 
     for (int k = t; k < PAD; k += NT) {
         sPX[k] = 0.0f; sPY[k] = 0.0f; sW[k] = 0.0f;
@@ -710,7 +728,7 @@ constexpr int kNumCfgs = sizeof(kCfgs) / sizeof(kCfgs[0]);
 int g_grid_cache[kNumCfgs][3];
 
 using ResFn = void (*)(ImgDesc, const int2*, const int32_t*, const int32_t*, int32_t*, int32_t*,
-                       int, int, int, int, float, float, float);
+                       int, int, int, int, float, float, float, CompWs, const int64_t*, int);
 
 struct ResEntry {
     int bx, by, it, nt;
@@ -773,7 +791,8 @@ bool resident_fits(int ci, int64_t max_items) {
 int launch_resident(int ci, const ImgDesc& d, const int2* queue, const int32_t* n_queue,
                     const int32_t* mflags, int32_t* epoch, int32_t* status, int64_t max_items,
                     int in_buf, int iters, int per, int inner, float theta, float inv_theta,
-                    float tau, hipStream_t st, hipEvent_t before) {
+                    float tau, hipStream_t st, hipEvent_t before, const CompWs* comp,
+                    const int64_t* comp_npix) {
     const int r = resident_entry(ci);
     if (r < 0 || !resident_fits(ci, max_items)) return -1;
     // epoch[0 .. max_items) and *status start at 0
@@ -783,8 +802,12 @@ int launch_resident(int ci, const ImgDesc& d, const int2* queue, const int32_t* 
     if (before) (void)hipEventRecord(before, st);
     const unsigned grid = (unsigned)(((max_items + 7) / 8) * 8);
     ImgDesc dd = d;
-    void* args[] = {&dd,     &queue, &n_queue, &mflags, &epoch,     &status, &in_buf,
-                    &iters,  &per,   &inner,   &theta,  &inv_theta, &tau};
+    CompWs cw{};
+    if (comp) cw = *comp;
+    const int64_t* cnpix = comp ? comp_npix : nullptr;
+    int citers = comp ? iters : 0;
+    void* args[] = {&dd,    &queue, &n_queue,   &mflags, &epoch, &status, &in_buf, &iters,
+                    &per,   &inner, &theta,     &inv_theta, &tau, &cw,     &cnpix,  &citers};
     const hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kRes[r].fn),
                                                     dim3(grid), dim3(kRes[r].nt), args, 0, st);
     if (e != hipSuccess) {

@@ -203,11 +203,17 @@ int launch_components_restore(const ImgDesc& d, const CompWs& w, const int64_t* 
 // bounded wait expired, in which case u holds NaN).  Returns 0 when launched,
 // -1 when the resident form does not apply (nothing was enqueued), > 0 on error.
 // `before` (nullable) is recorded on st right before the resident kernel.
+// comp (nullable; labelled by launch_components_prepare with the full RD
+// count comp_npix): the workgroups left without a tile run the small
+// components' iterations and set comp->ccount[7]; a component kernel launched
+// afterwards on st then returns at once (and does the work itself if no
+// workgroup was left over).
 bool resident_fits(int ci, int64_t max_items);
 int launch_resident(int ci, const ImgDesc& d, const int2* queue, const int32_t* n_queue,
                     const int32_t* mflags, int32_t* epoch, int32_t* status, int64_t max_items,
                     int in_buf, int iters, int per, int inner, float theta, float inv_theta,
-                    float tau, hipStream_t st, hipEvent_t before);
+                    float tau, hipStream_t st, hipEvent_t before, const CompWs* comp = nullptr,
+                    const int64_t* comp_npix = nullptr);
 
 // Per-launch arguments of the convergence-driven solve: skip the launch when
 // *skip_slot <= tol (skip_slot nullable); reduce the last iteration's change

@@ -32,9 +32,9 @@ import re
 import sqlite3
 
 _CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
-# sources that define the iteration kernels: a change to either voids a
+# sources that define the iteration kernels: a change to any voids a
 # recorded traffic figure
-KERNEL_SOURCES = ("iterate.hip", "rdseg_device.h")
+KERNEL_SOURCES = ("iterate.hip", "rdseg_device.h", "components_device.h")
 
 
 def kernel_source_digest():

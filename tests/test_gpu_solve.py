@@ -225,14 +225,19 @@ def test_resident_matches_separate_launches(rd, shape, tile, ipl, frac, iters):
     dict(shape=(300, 257), lam=3.0, frac=0.4, iters=29, tile=(16, 16), ipl=8, inner=1),
     dict(shape=(300, 257), lam=3.0, frac=0.4, iters=21, tile=(32, 32), ipl=4, inner=2),
     dict(shape=(97, 131), lam=2.0, frac=0.3, iters=50, tile=(8, 8), ipl=8, inner=1),
+    # resident solves: the workgroups left without a tile run the components
+    dict(shape=(1024, 1024), lam=20.0, frac=0.5, iters=40, tile=(64, 32), ipl=4, inner=1),
+    dict(shape=(300, 257), lam=3.0, frac=0.4, iters=29, tile=(64, 64), ipl=8, inner=1),
+    dict(shape=(300, 257), lam=3.0, frac=0.4, iters=22, tile=(64, 32), ipl=4, inner=2),
 ])
 def test_small_components_match_tile_path(rd, case):
     """Pixels of RD components of at most 64 pixels run whole in the component
-    kernel; the results equal those of the tile path for every pixel bit for
-    bit, and match the oracle on the smaller grids."""
+    kernel (or, in a resident solve, in the resident kernel's workgroups that
+    hold no tile); the results equal those of the tile path for every pixel
+    bit for bit, and match the oracle on the smaller grids."""
     H, W = case["shape"]
     if H == 1024:
-        f = synth.config2(1 if case["lam"] == 5.0 else 0, size=1024, iters=500).f
+        f = synth.config2({1.0: 0, 5.0: 1, 20.0: 2}[case["lam"]], size=1024, iters=500).f
     else:
         f = synth.smooth_field(H, W, 41, noise=0.3)
     delta = synth.band_delta(f, case["frac"])
