@@ -11,10 +11,14 @@
 //
 // Steps (single image; skipped on the device when more than 55 % of the
 // pixels are RD, where one component spans the image):
-//   k_cc_init      labels: own index on RD, -1 elsewhere; counters cleared
-//   k_cc_union     lock-free union of right / down RD neighbours (the larger
-//                  root is linked below the smaller one with atomicMin)
-//   k_cc_flatten   every RD pixel points at its root; component sizes
+//   k_cc_init      labels: the first pixel of its horizontal RD run within
+//                  the wave's 64 pixels on RD, -1 elsewhere; counters cleared
+//   k_cc_union     lock-free union of runs, right across a wave boundary and
+//                  down (the larger root is linked below the smaller one with
+//                  atomicMin)
+//   k_cc_flatten   every RD pixel points at its root; component sizes (one
+//                  atomic per root and wave) and each pixel's rank in its
+//                  component
 //   k_cc_class     each small component (<= 64 pixels) takes a slot in the
 //                  class of its size rounded up to a power of two
 //   k_cc_assign    each of its pixels takes a lane: waves of one class hold
@@ -75,17 +79,30 @@ __device__ __forceinline__ void cc_unite(int32_t* lab, int a, int b) {
     }
 }
 
+// The grid-stride loops below run 256-thread workgroups over consecutive pixel
+// indices, so every wave holds 64 consecutive indices starting at a multiple
+// of 64 (a "segment"; lane = index mod 64).
+
 __global__ __launch_bounds__(256) void k_cc_init(ImgDesc d, CompWs w, const int64_t* npix) {
     if (blockIdx.x == 0 && threadIdx.x == 0) w.npix_tile[0] = npix[0];
     if (cc_skip(npix, d)) return;
     const int64_t plane = (int64_t)d.H * d.ld;
+    const int l = threadIdx.x & 63;
     for (int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x; g < plane;
          g += (int64_t)gridDim.x * 256) {
         const int y = (int)(g / d.ld), x = (int)(g - (int64_t)y * d.ld);
         const bool act = x < d.W && c_active(d.c[g]);
-        w.lab[g] = act ? (int32_t)g : -1;
+        // A horizontal run of RD pixels inside the segment (a run also starts
+        // at x = 0) is linked to its first pixel at once, so the union pass
+        // only joins runs.
+        const uint64_t gap = __ballot(!act);
+        const uint64_t row0 = __ballot(act && x == 0);
+        const uint64_t gb = gap & ((1ull << l) - 1);         // lanes below l
+        int start = gb ? 64 - __clzll(gb) : 0;                // past the last gap
+        const uint64_t rb = row0 & ((2ull << l) - 1);         // lanes up to l
+        if (rb) start = max(start, 63 - __clzll(rb));
+        w.lab[g] = act ? (int32_t)(g - (l - start)) : -1;
         w.csize[g] = 0;
-        w.crank[g] = 0;
         w.cslot[g] = 0;
         w.lane_of[g] = -1;
         w.wl_pix[2 * g] = -1;
@@ -95,6 +112,11 @@ __global__ __launch_bounds__(256) void k_cc_init(ImgDesc d, CompWs w, const int6
     }
 }
 
+// Joins of runs: across a segment boundary on the right, and down, where a
+// vertical pair of RD pixels has no vertical RD pair directly to its left
+// (that pair, or the first one of the stretch, already joins the two runs:
+// consecutive RD pixels of a row are linked by their run or by a boundary
+// join).
 __global__ __launch_bounds__(256) void k_cc_union(ImgDesc d, CompWs w, const int64_t* npix) {
     if (cc_skip(npix, d)) return;
     const int64_t plane = (int64_t)d.H * d.ld;
@@ -102,26 +124,56 @@ __global__ __launch_bounds__(256) void k_cc_union(ImgDesc d, CompWs w, const int
          g += (int64_t)gridDim.x * 256) {
         const int y = (int)(g / d.ld), x = (int)(g - (int64_t)y * d.ld);
         if (x >= d.W || !c_active(d.c[g])) continue;
-        if (x + 1 < d.W && c_active(d.c[g + 1])) cc_unite(w.lab, (int)g, (int)g + 1);
-        if (y + 1 < d.H && c_active(d.c[g + d.ld])) cc_unite(w.lab, (int)g, (int)g + d.ld);
+        if ((g & 63) == 63 && x + 1 < d.W && c_active(d.c[g + 1]))
+            cc_unite(w.lab, (int)g, (int)g + 1);
+        if (y + 1 < d.H && c_active(d.c[g + d.ld])) {
+            const bool left_pair = x > 0 && c_active(d.c[g - 1]) && c_active(d.c[g - 1 + d.ld]);
+            if (!left_pair) cc_unite(w.lab, (int)g, (int)g + d.ld);
+        }
     }
 }
 
 __global__ __launch_bounds__(256) void k_cc_flatten(ImgDesc d, CompWs w, const int64_t* npix) {
     if (cc_skip(npix, d)) return;
     const int64_t plane = (int64_t)d.H * d.ld;
+    const int l = threadIdx.x & 63;
     for (int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x; g < plane;
          g += (int64_t)gridDim.x * 256) {
-        if (w.lab[g] < 0) continue;
-        const int r = cc_root(w.lab, (int)g);
-        __hip_atomic_store(w.lab + g, r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const bool act = w.lab[g] >= 0;
+        int r = -1;
+        if (act) {
+            r = cc_root(w.lab, (int)g);
+            __hip_atomic_store(w.lab + g, r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
         // Sizes are exact up to kSmallMax + 1; beyond that only "large"
         // matters.  cslot[r] (cleared by the init pass, written for small
         // roots only by the class pass) flags a root that has passed
         // kSmallMax, so the pixels of large components stop adding to one
-        // contended counter.  A stale read only costs an extra add.
-        if (w.cslot[r]) continue;
-        if (atomicAdd(w.csize + r, 1) >= kSmallMax) w.cslot[r] = 1;
+        // contended counter (a stale read only costs an extra add).  The
+        // lanes of a wave that share a root add their count with one atomic,
+        // and each takes the count before it as its rank in the component
+        // (crank[g]: distinct, in [0, size) for every pixel of a small
+        // component, whose pixels are all counted).
+        bool want = act && !w.cslot[r];
+        while (true) {
+            const uint64_t m = __ballot(want);
+            if (!m) break;
+            const int leader = __ffsll((unsigned long long)m) - 1;
+            const int r0 = __shfl(r, leader);
+            const bool same = want && r == r0;
+            const uint64_t sm = __ballot(same);
+            int old = 0;
+            if (l == leader) {
+                const int cnt = __popcll(sm);
+                old = atomicAdd(w.csize + r0, cnt);
+                if (old + cnt > kSmallMax) w.cslot[r0] = 1;
+            }
+            old = __shfl(old, leader);
+            if (same) {
+                w.crank[g] = old + __popcll(sm & ((1ull << l) - 1));
+                want = false;
+            }
+        }
     }
 }
 
@@ -138,11 +190,23 @@ __global__ __launch_bounds__(256) void k_cc_class(ImgDesc d, CompWs w, const int
     const int64_t per_wg = (plane + gridDim.x - 1) / gridDim.x;
     const int64_t g0 = (int64_t)blockIdx.x * per_wg;
     const int64_t g1 = min(plane, g0 + per_wg);
+    const int l = t & 63;
     for (int64_t g = g0 + t; g < g1; g += 256) {
-        if (w.lab[g] != (int32_t)g) continue;   // roots only
-        const int s = w.csize[g];
-        if (s < 1 || s > kSmallMax) continue;
-        w.cslot[g] = atomicAdd(&sCount[size_class(s)], 1);   // local slot
+        int k = -1;   // size class of a small root
+        if (w.lab[g] == (int32_t)g) {
+            const int s = w.csize[g];
+            if (s >= 1 && s <= kSmallMax) k = size_class(s);
+        }
+        // local slots: one LDS atomic per class and wave, lanes in order
+        for (int c = 0; c < kClasses; ++c) {
+            const uint64_t m = __ballot(k == c);
+            if (!m) continue;   // uniform
+            const int leader = __ffsll((unsigned long long)m) - 1;
+            int base = 0;
+            if (l == leader) base = atomicAdd(&sCount[c], __popcll(m));
+            base = __shfl(base, leader);
+            if (k == c) w.cslot[g] = base + __popcll(m & ((1ull << l) - 1));
+        }
     }
     __syncthreads();
     if (t < kClasses) sBase[t] = sCount[t] ? atomicAdd(w.ccount + t, sCount[t]) : 0;
@@ -163,30 +227,45 @@ __global__ __launch_bounds__(256) void k_cc_assign(ImgDesc d, CompWs w, uint64_t
     __syncthreads();
     const int64_t plane = (int64_t)d.H * d.ld;
     int frozen = 0;
+    const int l = threadIdx.x & 63;
     for (int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x; g < plane;
          g += (int64_t)gridDim.x * 256) {
-        const int r = w.lab[g];
-        if (r < 0 || r >= plane) continue;
-        const int s = w.csize[r];
-        if (s < 1 || s > kSmallMax) continue;
-        const int k = size_class(s);
-        const int per = kSmallMax >> k;
-        const int slot = w.cslot[r];
-        const int rank = atomicAdd(w.crank + r, 1);
-        const int wave = class_base(w.ccount, k) + slot / per;
-        const int lane = (slot % per) * (1 << k) + rank;
-        const int L = wave * 64 + lane;
-        // never true for a well-formed labelling (see kWlExtra); a guard
-        // against writing outside the lane table
-        if (slot < 0 || rank >= s || L < 0 || L >= 2 * plane + kWlExtra) continue;
-        w.lane_of[g] = L;
-        w.wl_pix[L] = (int32_t)g;
-        // frozen for the tile path from here on
         const int y = (int)(g / d.ld), x = (int)(g - (int64_t)y * d.ld);
-        d.c[g] = __builtin_inff();
-        const int64_t T = (int64_t)(y >> 3) * d.tw + (x >> 3);
-        atomicAnd((unsigned long long*)(masks + T), ~(1ull << (8 * (y & 7) + (x & 7))));
-        ++frozen;
+        const int r = w.lab[g];
+        bool frz = false;
+        if (r >= 0 && r < plane) {
+            const int s = w.csize[r];
+            if (s >= 1 && s <= kSmallMax) {
+                const int k = size_class(s);
+                const int per = kSmallMax >> k;
+                const int slot = w.cslot[r];
+                const int rank = w.crank[g];
+                const int wave = class_base(w.ccount, k) + slot / per;
+                const int lane = (slot % per) * (1 << k) + rank;
+                const int L = wave * 64 + lane;
+                // never false for a well-formed labelling (see kWlExtra); a
+                // guard against writing outside the lane table
+                if (slot >= 0 && rank < s && L >= 0 && L < 2 * plane + kWlExtra) {
+                    w.lane_of[g] = L;
+                    w.wl_pix[L] = (int32_t)g;
+                    d.c[g] = __builtin_inff();   // frozen for the tile path from here on
+                    frz = true;
+                    ++frozen;
+                }
+            }
+        }
+        // Tile-mask bits of the frozen pixels: the lanes of one 8x8 tile row
+        // are consecutive in the wave (they start where x mod 8 = 0, or at
+        // lane 0), so the first of them clears all their bits with one atomic.
+        const uint64_t fm = __ballot(frz);
+        if (fm && ((x & 7) == 0 || l == 0) && x < d.W) {
+            const int glen = min(min(8 - (x & 7), 64 - l), d.W - x);
+            const uint64_t bits = (fm >> l) & ((1ull << glen) - 1);
+            if (bits) {
+                const int64_t T = (int64_t)(y >> 3) * d.tw + (x >> 3);
+                atomicAnd((unsigned long long*)(masks + T), ~(bits << (8 * (y & 7) + (x & 7))));
+            }
+        }
     }
     if (frozen) atomicAdd(&sFrozen, frozen);
     __syncthreads();
@@ -416,9 +495,12 @@ int launch_components_prepare(const ImgDesc& d, const CompWs& w, uint64_t* masks
     hipLaunchKernelGGL(k_cc_init, dim3(grid), dim3(256), 0, st, d, w, (const int64_t*)npix);
     hipLaunchKernelGGL(k_cc_union, dim3(grid), dim3(256), 0, st, d, w, (const int64_t*)npix);
     hipLaunchKernelGGL(k_cc_flatten, dim3(grid), dim3(256), 0, st, d, w, (const int64_t*)npix);
+    // the class and assignment passes end with per-workgroup atomics on a few
+    // shared counters (class counts, the tile path's RD count): fewer, larger
+    // workgroups keep that contention small
     hipLaunchKernelGGL(k_cc_class, dim3(std::min(grid, 1024u)), dim3(256), 0, st, d, w,
                        (const int64_t*)npix);
-    hipLaunchKernelGGL(k_cc_assign, dim3(grid), dim3(256), 0, st, d, w, masks,
+    hipLaunchKernelGGL(k_cc_assign, dim3(std::min(grid, 1024u)), dim3(256), 0, st, d, w, masks,
                        (const int64_t*)npix);
     RDSEG_HIP_CHECK(hipGetLastError());
     return 0;

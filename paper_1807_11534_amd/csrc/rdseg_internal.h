@@ -152,10 +152,11 @@ int prepare_iterate(int ci, bool batched, bool stop = false);
 
 // Work arrays of the small-component path (single image, indices g = y * ld
 // + x of the image's [H][ld] plane): lab (union-find parent, then root; -1
-// off RD), csize (pixels per root), crank (pixels placed so far per root),
+// off RD), csize (pixels per root), crank (each pixel's rank in its component),
 // cslot (slot of a root in its size class), lane_of (packed lane of a
 // small-component pixel, -1 otherwise), wl_pix (pixel of each packed lane, -1
-// for empty lanes; 2 * plane + 448 entries), ccount (components per class, 8),
+// for empty lanes; 2 * plane + 448 entries), ccount (components per class, 7;
+// [7]: set when the resident kernel ran them),
 // npix_tile (RD pixels left to the tile path).
 struct CompWs {
     int32_t* lab;
