@@ -181,6 +181,47 @@ def test_autotune_restrictions(rd):
         np.testing.assert_array_equal(x, y)
 
 
+def test_tune_cache_steers_library_choice(rd):
+    """A cache entry imported as text (for this size class and active-fraction
+    bucket) decides the configuration of a solve that leaves the choice to the
+    library: the timing records show launches of that configuration only, and
+    the result equals an explicit solve with it."""
+    import json
+    f = synth.smooth_field(300, 257, 31, noise=0.2)
+    ft = dev(f)
+    delta = 0.35
+    q = float((np.abs(f.astype(np.float64)) < delta).mean())
+    qb = 4 if q >= 0.5 else 3 if q >= 0.2 else 2 if q >= 0.05 else 1 if q >= 0.01 else 0
+    n, cls = 300 * 257, 0
+    while n > 4096 and cls < 12:
+        n >>= 2
+        cls += 1
+    say(f"tune cache steering (class {cls}, bucket {qb})")
+    try:
+        for tile, ipl in [((32, 16), 2), ((16, 16), 8)]:
+            rd.tune_cache_clear()
+            rd.tune_cache_import(json.dumps({"version": 1, "entries": [
+                {"size_class": cls, "q_bucket": qb, "tile_w": tile[0], "tile_h": tile[1],
+                 "iters_per_launch": ipl, "components": 2}]}))
+            rd.set_resident(False)
+            rd.timing_reset()
+            rd.timing_enable(True)
+            got = [host(x) for x in rd.solve(ft, 2.0, 0.1, 0.125, delta, 24)]
+            rd.timing_enable(False)
+            ci = rd.config_index(tile, ipl)
+            assert rd.timing_read(ci)[1] > 0
+            assert rd.timing_read(-1)[1] == rd.timing_read(ci)[1]
+            ref = [host(x) for x in rd.solve(ft, 2.0, 0.1, 0.125, delta, 24, tile=tile,
+                                             iters_per_launch=ipl)]
+            for a, b in zip(got, ref):
+                np.testing.assert_array_equal(a, b)
+    finally:
+        rd.timing_enable(False)
+        rd.timing_reset()
+        rd.set_resident(True)
+        rd.tune_cache_clear()
+
+
 @pytest.mark.parametrize("shape,tile,ipl,frac,iters", [
     ((1024, 1024), (64, 64), 8, math.inf, 61),
     ((1024, 1024), (64, 64), 8, 0.5, 40),
