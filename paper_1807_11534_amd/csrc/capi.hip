@@ -1657,11 +1657,16 @@ rdseg_status rdseg_backward(const float* f, rdseg_shape s, const rdseg_params* p
     // with the component path on, skip the tile path when no macro tile is
     // left to it (one read of the queue length, which synchronises)
     int32_t n_tiles_left = 1;
+    int32_t ccount[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int64_t comp_waves = -1;
     if (comps) {
         if (hipMemcpyAsync(&n_tiles_left, w.totals, sizeof(int32_t), hipMemcpyDeviceToHost, st) !=
                 hipSuccess ||
+            hipMemcpyAsync(ccount, w.comp.ccount, sizeof(ccount), hipMemcpyDeviceToHost, st) !=
+                hipSuccess ||
             hipStreamSynchronize(st) != hipSuccess)
             return fail(RDSEG_ERR_HIP, "reading the tile queue length failed");
+        comp_waves = component_waves_of(ccount);   // meaningless (unused) if labelling was skipped
     }
     AdjBufs ab;
     ab.pbx[0] = w.ab[0]; ab.pby[0] = w.ab[1]; ab.vb[0] = w.ab[2];
@@ -1673,7 +1678,8 @@ rdseg_status rdseg_backward(const float* f, rdseg_shape s, const rdseg_params* p
     if (comps) {
         rdseg_status rc = closed_beside(st, &join, [&](hipStream_t cs) {
             return launch_adj_components(d, w.comp, w.npix, tape, w.seg, K, ce, grad_u, grad_v,
-                                         ab.vb[K % 2], w.sacc, theta, inv_theta, tau, cs);
+                                         ab.vb[K % 2], w.sacc, theta, inv_theta, tau, cs,
+                                         comp_waves);
         });
         if (rc) return rc;
     }

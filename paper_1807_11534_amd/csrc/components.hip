@@ -289,17 +289,20 @@ __global__ __launch_bounds__(256) void k_components(ImgDesc d, CompWs w, const i
 // recomputes the segment's forward states (the arithmetic of one k_iterate
 // iteration) and then runs the segment's reverse steps with the arithmetic of
 // k_adj_step, neighbour values from other lanes and frozen neighbours as
-// constants (w right / below; p, ubar, gbar and wbar are 0 there).  The
-// recomputed states go to LDS when the segment fits (lds_slots = ce - 1 > 0:
-// one wave per workgroup, lane-major slots [ce - 1][3][64]), else to the
-// per-pixel slots of seg that the tile path uses.  The adjoint state (pbar,
-// vbar) and the clamp-adjoint sum stay in registers; the sum goes to sacc and
-// vbar^0 to vb_out at the end.  Results are bitwise those of the tile path.
+// constants (w right / below; p, ubar, gbar and wbar are 0 there).  Where
+// the segment fits a workgroup's LDS (one wave per workgroup, lane-major):
+// lds_mode 2 (ce x 1536 bytes) keeps each forward step's dual-update outputs
+// (p, g, m) and u, so the reverse steps recompute nothing; lds_mode 1
+// ((ce - 1) x 768 bytes) keeps the states and the reverse recomputes each
+// step's dual update from them; lds_mode 0 keeps the states in the per-pixel
+// slots of seg that the tile path uses.  The adjoint state (pbar, vbar) and
+// the clamp-adjoint sum stay in registers; the sum goes to sacc and vbar^0 to
+// vb_out at the end.  Results are bitwise those of the tile path.
 __global__ __launch_bounds__(256) void k_adj_components(
     ImgDesc d, CompWs w, const int64_t* npix, const float* __restrict__ tape,
     float* __restrict__ seg, int K, int ce, const float* __restrict__ grad_u,
     const float* __restrict__ grad_v, float* __restrict__ vb_out, float* __restrict__ sacc,
-    float theta, float inv_theta, float tau, int lds_slots) {
+    float theta, float inv_theta, float tau, int lds_mode) {
     extern __shared__ float s_states[];
     if (cc_skip(npix, d)) return;
     const int64_t plane = (int64_t)d.H * d.ld;
@@ -307,7 +310,10 @@ __global__ __launch_bounds__(256) void k_adj_components(
                                 (2 * plane + kWlExtra) / 64);
     const int lane = threadIdx.x & 63;
     const int wpb = (int)(blockDim.x >> 6);
-    float* __restrict__ my_states = s_states + (threadIdx.x >> 6) * lds_slots * 192 + lane;
+    // LDS per wave: lds_mode 1 holds states [ce - 1][3][64], lds_mode 2 the
+    // dual-update outputs and u [ce][6][64]; lds_mode 0 uses seg instead
+    const int per_wave = lds_mode == 2 ? ce * 384 : (lds_mode == 1 ? (ce - 1) * 192 : 0);
+    float* __restrict__ my_states = s_states + (threadIdx.x >> 6) * per_wave + lane;
     for (int wave = blockIdx.x * wpb + (threadIdx.x >> 6); wave < nwaves;
          wave += gridDim.x * wpb) {   // uniform per wave
         const int g = w.wl_pix[wave * 64 + lane];
@@ -359,6 +365,47 @@ __global__ __launch_bounds__(256) void k_adj_components(
         float pbx = 0.0f, pby = 0.0f;
         float vb = (mine && grad_v) ? grad_v[gg] : 0.0f;
         float S = 0.0f;
+        // one reverse step k from the dual update of step k (p^k, g, m of
+        // state k - 1) and u^k: the arithmetic of k_adj_step
+        auto reverse_step = [&](int k, float opx, float opy, float ogx, float ogy, float om,
+                                float u) {
+            const float sarg = u - c;
+            const float sb = (mine && sarg > 0.0f && sarg < 1.0f) ? vb : 0.0f;
+            float ub = sb;
+            if (k == K && grad_u && mine) ub += grad_u[gg];
+            ub = mine ? ub : 0.0f;
+            // pbt = pbar^k + theta grad(ubar); gbar
+            const float gux = lastc ? 0.0f : (right0(ub) - ub);
+            const float guy = lastr ? 0.0f : (down0(ub) - ub);
+            const float ptx = mine ? fmaf(theta, gux, pbx) : 0.0f;
+            const float pty = mine ? fmaf(theta, guy, pby) : 0.0f;
+            const float nn = __builtin_amdgcn_sqrtf(fmaf(ogx, ogx, ogy * ogy));
+            const float inv_n = nn > 0.0f ? __builtin_amdgcn_rcpf(nn) : 0.0f;
+            const float tm = tau * om;
+            const float dot = fmaf(opx, ptx, opy * pty);
+            const float k2 = tm * dot * inv_n;
+            float gbx = fmaf(tm, ptx, -k2 * ogx);
+            float gby = fmaf(tm, pty, -k2 * ogy);
+            gbx = (mine && !lastc) ? gbx : 0.0f;
+            gby = (mine && !lastr) ? gby : 0.0f;
+            // wbar = -div gbar; pbar^(k-1), vbar^(k-1)
+            const float dg = div_p(gbx, left(gbx), gby, up(gby));
+            const float wb = mine ? -dg : 0.0f;
+            const float gwx = lastc ? 0.0f : (right0(wb) - wb);
+            const float gwy = lastr ? 0.0f : (down0(wb) - wb);
+            pbx = lastc ? 0.0f : fmaf(om, ptx, -gwx);
+            pby = lastr ? 0.0f : fmaf(om, pty, -gwy);
+            vb = fmaf(-wb, inv_theta, ub);
+            S += sb;
+        };
+        // one forward step from state (v, px, py): the dual update and u
+        auto forward_step = [&](float v, float px, float py, DualOut& o, float& u) {
+            const float dd = div_p(px, left(px), py, up(py));
+            const float wv = w_of(dd, v, inv_theta, mine);
+            const float wr = from(aR, wv), wd = from(aD, wv);
+            o = dual_update(px, py, wv, nR >= 0 ? wr : wR, nD >= 0 ? wd : wD, fl, tau);
+            u = u_step(v, div_p(o.px, left(o.px), o.py, up(o.py)), theta);
+        };
         const int nseg = (K + ce - 1) / ce;
         for (int sg = nseg - 1; sg >= 0; --sg) {
             const int k0 = sg * ce;
@@ -370,20 +417,42 @@ __global__ __launch_bounds__(256) void k_adj_components(
                 cpx = s0[plane + gg];
                 cpy = s0[2 * plane + gg];
             }
+            if (lds_mode == 2) {
+                // forward over all len steps, keeping what the reverse reads:
+                // slot j = p^(k0+j+1), g, m and u^(k0+j+1) of the step from state k0 + j
+                float v = cv, px = cpx, py = cpy;
+                for (int j = 0; j < len; ++j) {
+                    DualOut o;
+                    float u;
+                    forward_step(v, px, py, o, u);
+                    float* __restrict__ sj = my_states + j * 384;
+                    sj[0] = o.px;
+                    sj[64] = o.py;
+                    sj[128] = o.gx;
+                    sj[192] = o.gy;
+                    sj[256] = o.m;
+                    sj[320] = u;
+                    px = o.px;
+                    py = o.py;
+                    v = v_step(u, c);
+                }
+                for (int k = k0 + len; k >= k0 + 1; --k) {
+                    const float* __restrict__ sj = my_states + (k - 1 - k0) * 384;
+                    reverse_step(k, sj[0], sj[64], sj[128], sj[192], sj[256], sj[320]);
+                }
+                continue;
+            }
             // forward: the states k0 + 1 .. k0 + len - 1 of this segment
             {
                 float v = cv, px = cpx, py = cpy;
                 for (int j = 1; j < len; ++j) {
-                    float dd = div_p(px, left(px), py, up(py));
-                    const float wv = w_of(dd, v, inv_theta, mine);
-                    const float wr = from(aR, wv), wd = from(aD, wv);
-                    const DualOut o = dual_update(px, py, wv, nR >= 0 ? wr : wR,
-                                                  nD >= 0 ? wd : wD, fl, tau);
+                    DualOut o;
+                    float u;
+                    forward_step(v, px, py, o, u);
                     px = o.px;
                     py = o.py;
-                    dd = div_p(px, left(px), py, up(py));
-                    v = v_step(u_step(v, dd, theta), c);
-                    if (lds_slots) {
+                    v = v_step(u, c);
+                    if (lds_mode == 1) {
                         float* __restrict__ sj = my_states + (j - 1) * 192;
                         sj[0] = v;
                         sj[64] = px;
@@ -404,7 +473,7 @@ __global__ __launch_bounds__(256) void k_adj_components(
                     sv = cv;
                     spx = cpx;
                     spy = cpy;
-                } else if (lds_slots) {
+                } else if (lds_mode == 1) {
                     const float* __restrict__ sj = my_states + (j - 1) * 192;
                     sv = mine ? sj[0] : 0.0f;
                     spx = mine ? sj[64] : 0.0f;
@@ -415,43 +484,11 @@ __global__ __launch_bounds__(256) void k_adj_components(
                     spx = sj[plane + gg];
                     spy = sj[2 * plane + gg];
                 }
-                // w from p^(k-1), v^(k-1); the dual update gives p^k, g and m
-                const float dd = div_p(spx, left(spx), spy, up(spy));
-                const float wv = w_of(dd, sv, inv_theta, mine);
-                const float wr = from(aR, wv), wd = from(aD, wv);
-                const DualOut o = dual_update(spx, spy, wv, nR >= 0 ? wr : wR, nD >= 0 ? wd : wD,
-                                              fl, tau);
-                // u^k, clamp argument, clamp adjoint, ubar
-                const float d1 = div_p(o.px, left(o.px), o.py, up(o.py));
-                const float u = u_step(sv, d1, theta);
-                const float sarg = u - c;
-                const float sb = (mine && sarg > 0.0f && sarg < 1.0f) ? vb : 0.0f;
-                float ub = sb;
-                if (k == K && grad_u && mine) ub += grad_u[gg];
-                ub = mine ? ub : 0.0f;
-                // pbt = pbar^k + theta grad(ubar); gbar
-                const float gux = lastc ? 0.0f : (right0(ub) - ub);
-                const float guy = lastr ? 0.0f : (down0(ub) - ub);
-                const float ptx = mine ? fmaf(theta, gux, pbx) : 0.0f;
-                const float pty = mine ? fmaf(theta, guy, pby) : 0.0f;
-                const float nn = __builtin_amdgcn_sqrtf(fmaf(o.gx, o.gx, o.gy * o.gy));
-                const float inv_n = nn > 0.0f ? __builtin_amdgcn_rcpf(nn) : 0.0f;
-                const float tm = tau * o.m;
-                const float dot = fmaf(o.px, ptx, o.py * pty);
-                const float k2 = tm * dot * inv_n;
-                float gbx = fmaf(tm, ptx, -k2 * o.gx);
-                float gby = fmaf(tm, pty, -k2 * o.gy);
-                gbx = (mine && !lastc) ? gbx : 0.0f;
-                gby = (mine && !lastr) ? gby : 0.0f;
-                // wbar = -div gbar; pbar^(k-1), vbar^(k-1)
-                const float dg = div_p(gbx, left(gbx), gby, up(gby));
-                const float wb = mine ? -dg : 0.0f;
-                const float gwx = lastc ? 0.0f : (right0(wb) - wb);
-                const float gwy = lastr ? 0.0f : (down0(wb) - wb);
-                pbx = lastc ? 0.0f : fmaf(o.m, ptx, -gwx);
-                pby = lastr ? 0.0f : fmaf(o.m, pty, -gwy);
-                vb = fmaf(-wb, inv_theta, ub);
-                S += sb;
+                // w from p^(k-1), v^(k-1); the dual update gives p^k, g and m; u^k
+                DualOut o;
+                float u;
+                forward_step(sv, spx, spy, o, u);
+                reverse_step(k, o.px, o.py, o.gx, o.gy, o.m, u);
             }
         }
         if (mine) {
@@ -481,8 +518,9 @@ unsigned grid_for(int64_t n) {
 
 int g_comp_grid = 0;
 int g_adj_comp_grid = 0;
-// LDS form of the component reverse sweep: (ce - 1) x 768 bytes per wave, at
-// most the default 64 KiB of a workgroup; the grid for the last size used
+// LDS forms of the component reverse sweep: ce x 1536 or (ce - 1) x 768 bytes
+// per wave, at most the default 64 KiB of a workgroup; the grid for the last
+// size used
 constexpr int kAdjLdsMax = 65536;
 size_t g_adj_lds_bytes = 0;
 int g_adj_lds_grid = 0;
@@ -527,12 +565,32 @@ int launch_components(const ImgDesc& d, const CompWs& w, const int64_t* npix, in
     return 0;
 }
 
+int64_t component_waves_of(const int32_t* ccount_host) {
+    int64_t b = 0;
+    for (int j = 0; j < kClasses; ++j) {
+        const int per = kSmallMax >> j;
+        b += ((int64_t)ccount_host[j] + per - 1) / per;
+    }
+    return b;
+}
+
 int launch_adj_components(const ImgDesc& d, const CompWs& w, const int64_t* npix,
                           const float* tape, float* seg, int K, int ce, const float* grad_u,
                           const float* grad_v, float* vb_out, float* sacc, float theta,
-                          float inv_theta, float tau, hipStream_t st) {
-    const size_t lds = (size_t)(ce - 1) * 192 * sizeof(float);
-    if (ce > 1 && lds <= (size_t)kAdjLdsMax) {
+                          float inv_theta, float tau, hipStream_t st, int64_t nwaves_hint) {
+    // The kept dual-update outputs (mode 2) shorten every reverse step but
+    // take twice the LDS of the states (mode 1), so fewer waves run at once:
+    // mode 2 when all the component waves fit on the chip together.
+    const size_t rich = (size_t)ce * 384 * sizeof(float);
+    const size_t lean = (size_t)(ce - 1) * 192 * sizeof(float);
+    const bool lean_ok = ce > 1 && lean <= (size_t)kAdjLdsMax;
+    int mode = lean_ok ? 1 : 0;
+    if (rich <= (size_t)kAdjLdsMax) {
+        const int cap = persistent_blocks(reinterpret_cast<const void*>(k_adj_components), 64, rich);
+        if (!lean_ok || (nwaves_hint >= 0 && cap > 0 && nwaves_hint <= cap)) mode = 2;
+    }
+    const size_t lds = mode == 2 ? rich : lean;
+    if (mode > 0) {
         if (g_adj_lds_bytes != lds || g_adj_lds_grid <= 0) {
             g_adj_lds_grid = persistent_blocks(reinterpret_cast<const void*>(k_adj_components), 64, lds);
             g_adj_lds_bytes = lds;
@@ -544,7 +602,7 @@ int launch_adj_components(const ImgDesc& d, const CompWs& w, const int64_t* npix
         }
         hipLaunchKernelGGL(k_adj_components, dim3((unsigned)g_adj_lds_grid), dim3(64), lds, st, d,
                            w, npix, tape, seg, K, ce, grad_u, grad_v, vb_out, sacc, theta,
-                           inv_theta, tau, ce - 1);
+                           inv_theta, tau, mode);
         RDSEG_HIP_CHECK(hipGetLastError());
         return 0;
     }

@@ -188,10 +188,13 @@ int launch_components(const ImgDesc& d, const CompWs& w, const int64_t* npix, in
 // (ce - 1) x 768 bytes fit a workgroup, else into seg, the (ce - 1) x
 // [3][H][ld] slots of the backward): writes sacc and vbar^0 (vb_out) of their
 // pixels.  Then c of those pixels back to theta lambda f.
+// nwaves_hint: the packed component waves (component_waves_of the class
+// counts read back), or -1 when unknown; it picks the LDS form.
 int launch_adj_components(const ImgDesc& d, const CompWs& w, const int64_t* npix,
                           const float* tape, float* seg, int K, int ce, const float* grad_u,
                           const float* grad_v, float* vb_out, float* sacc, float theta,
-                          float inv_theta, float tau, hipStream_t st);
+                          float inv_theta, float tau, hipStream_t st, int64_t nwaves_hint);
+int64_t component_waves_of(const int32_t* ccount_host);   // waves of classes 0..6
 int launch_components_restore(const ImgDesc& d, const CompWs& w, const int64_t* npix,
                               hipStream_t st);
 
