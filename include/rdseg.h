@@ -377,13 +377,16 @@ rdseg_status rdseg_autotune(const float* f, rdseg_shape s, const rdseg_params* p
  * form.  Process-wide. */
 rdseg_status rdseg_set_resident(int32_t on);
 
-/* In single-image solves without checkpoints or stopping rule, the RD pixels
- * whose 4-connected RD component has at most 64 pixels run every iteration in
- * one launch, one pixel per lane (an RD pixel interacts only with its own
- * component, Sec. 3); the tile path covers the larger components.  Skipped on
- * the device when more than 55 % of the pixels are RD.  Results are bitwise
- * equal either way.  on = 0 forces the tile path for every pixel, on != 0 (the
- * default) allows the component path.  Process-wide. */
+/* In single-image solves without the stopping rule, the RD pixels whose
+ * 4-connected RD component has at most 64 pixels run every iteration in one
+ * launch, one pixel per lane (an RD pixel interacts only with its own
+ * component, Sec. 3); the tile path covers the larger components.  In a
+ * resident solve the resident kernel's workgroups that hold no tile run them;
+ * with a tape they also write their checkpoints; rdseg_backward runs their
+ * whole reverse sweep in one launch.  Skipped on the device when more than
+ * 55 % of the pixels are RD.  Results are bitwise equal either way.  on = 0
+ * forces the tile path for every pixel, on != 0 (the default) allows the
+ * component path.  Process-wide. */
 rdseg_status rdseg_set_components(int32_t on);
 
 /* The autotuner's cache (the choices of rdseg_autotune, keyed by size class
