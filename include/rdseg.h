@@ -70,8 +70,9 @@ typedef struct {
  * (autotuned, see rdseg_autotune; choosing synchronises the stream once).
  * ckpt_every > 0 asks rdseg_solve to write a checkpoint of (v, p) every
  * ckpt_every iterations into `tape` for rdseg_backward (inner = 1 only).
- * components: whether a plain single-image solve runs the RD components of at
- * most 64 pixels whole in the component kernel (see rdseg_set_components):
+ * components: whether a single-image solve (not under the stopping rule) runs
+ * the RD components of at most 64 pixels whole in the component kernel (see
+ * rdseg_set_components; rdseg_backward follows it unless it is 2):
  * 1 = on, 2 = off, 0 = the autotuner's choice for this problem class when the
  * library chooses the tiles, else on.  Results are bitwise equal either way. */
 typedef struct {
