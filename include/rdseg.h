@@ -72,9 +72,10 @@ typedef struct {
  * ckpt_every iterations into `tape` for rdseg_backward (inner = 1 only).
  * components: whether a single-image solve (not under the stopping rule) runs
  * the RD components of at most 64 pixels whole in the component kernel (see
- * rdseg_set_components; rdseg_backward follows it unless it is 2):
- * 1 = on, 2 = off, 0 = the autotuner's choice for this problem class when the
- * library chooses the tiles, else on.  Results are bitwise equal either way. */
+ * rdseg_set_components): 1 = on, 2 = off, 0 = the autotuner's choice for
+ * this problem class when the library chooses the tiles, else on.
+ * rdseg_backward uses the component path unless components is 2.  Results
+ * are bitwise equal either way. */
 typedef struct {
     double lambda, theta, tau, delta;
     int32_t iters;
