@@ -95,10 +95,10 @@ def sweep_cases(torch, rdseg, synth, args, dev):
         c["ws"] = rdseg.workspace(rdseg.shape_of(f))
         if args.tune == "auto":
             tuned = rdseg.autotune(f, c["lam"], synth.THETA, synth.TAU, c["delta"], args.iters)
-            (tile, ipl), comps = tuned, tuned.components
+            (tile, ipl), comps, res = tuned, tuned.components, tuned.resident
         else:
-            tile, ipl, comps = (64, 64), 4, 0
-        c["tile"], c["ipl"], c["comps"] = tile, ipl, comps
+            tile, ipl, comps, res = (64, 64), 4, 0, 0
+        c["tile"], c["ipl"], c["comps"], c["res"] = tile, ipl, comps, res
     return probs, cases
 
 
@@ -273,13 +273,15 @@ def extras(torch, rdseg, synth, dev, which=EXTRAS):
         for key, fixed in (("ipl8", 8), ("free", 0)):
             tuned = rdseg.autotune(f, prob.lam, synth.THETA, synth.TAU, prob.delta, 200,
                                    iters_per_launch=fixed)
-            (tile, ipl), comps = tuned, tuned.components
+            (tile, ipl), comps, resv = tuned, tuned.components, tuned.resident
             run = lambda: rdseg.solve(f, prob.lam, synth.THETA, synth.TAU, prob.delta, 1000,
-                                      tile=tile, iters_per_launch=ipl, components=comps)
+                                      tile=tile, iters_per_launch=ipl, components=comps,
+                                      resident=resv)
             run()
             t = timed(torch, run, 2)
             res[key] = dict(ms=t, tile=list(tile), iters_per_launch=ipl,
                             small_components={1: "on", 2: "off"}[comps],
+                            barrier={1: "on-chip", 2: "launches"}[resv],
                             updates_per_s=q * prob.f.size * 1000 / (t * 1e-3))
         out["ds_4096"] = dict(size=4096, iters=1000, active_fraction=q, **res["ipl8"],
                               autotuned_free=res["free"])
@@ -321,7 +323,7 @@ def main():
         for c in cases:
             rdseg.solve(c["f"], c["lam"], synth.THETA, synth.TAU, c["delta"], args.iters,
                         tile=c["tile"], iters_per_launch=c["ipl"], out=c["out"], ws=c["ws"],
-                        components=c["comps"])
+                        components=c["comps"], resident=c["res"])
 
     for _ in range(args.warmup):
         step()
@@ -345,7 +347,7 @@ def main():
         e0.record()
         u, v, p = rdseg.solve(c["f"], c["lam"], synth.THETA, synth.TAU, c["delta"], args.iters,
                               tile=c["tile"], iters_per_launch=c["ipl"], out=c["out"], ws=c["ws"],
-                              components=c["comps"])
+                              components=c["comps"], resident=c["res"])
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
@@ -359,7 +361,8 @@ def main():
                            label_mismatch_vs_inf=float((lab != ref_lab).mean()),
                            speedup_vs_inf=round(ref_ms / ms, 3),
                            tile=list(c["tile"]), iters_per_launch=c["ipl"],
-                           small_components={1: "on", 2: "off"}.get(c["comps"], "default")))
+                           small_components={1: "on", 2: "off"}.get(c["comps"], "default"),
+                           barrier={1: "on-chip", 2: "launches"}.get(c["res"], "default")))
 
     # roofline pass: HIP events around every iteration-kernel launch; the last
     # GPU work before the extras, so that its launches are the last dispatches of

@@ -75,7 +75,14 @@ typedef struct {
  * rdseg_set_components): 1 = on, 2 = off, 0 = the autotuner's choice for
  * this problem class when the library chooses the tiles, else on.
  * rdseg_backward uses the component path unless components is 2.  Results
- * are bitwise equal either way. */
+ * are bitwise equal either way.
+ * resident: the barrier between blocks of iterations of a single-image solve
+ * without tape or stopping rule: 1 = on-chip exchange between the tiles of
+ * one cooperative launch where the queued tiles all fit on the chip (see
+ * rdseg_set_resident), else kernel boundaries; 2 = kernel boundaries
+ * (separate launches); 0 = the autotuner's choice for this problem class when
+ * the library chooses the tiles, else 1.  Results are bitwise equal either
+ * way. */
 typedef struct {
     double lambda, theta, tau, delta;
     int32_t iters;
@@ -84,6 +91,7 @@ typedef struct {
     int32_t ckpt_every;
     int32_t inner;
     int32_t components;
+    int32_t resident;
 } rdseg_params;
 
 /* Fitting term of Sec. 1: f = (z - c1)^2 - (z - c2)^2 + gamma P   (eq. CV when
@@ -355,20 +363,23 @@ rdseg_status rdseg_fit_backward(const rdseg_fit* fit, rdseg_shape s, const float
 /* ---------------------------------------------------------------------- */
 
 /* Times every compiled (tile_w, tile_h, iters_per_launch) configuration, with
- * the small-component path on and off, on this problem for `probe_iters`
- * iterations (synchronous) and returns the fastest (components: 1 on, 2 off).
- * A nonzero prm->tile_w, tile_h, iters_per_launch or components fixes that
- * parameter (only matching candidates are timed; RDSEG_ERR_ARG if no
- * configuration is compiled); with all four zero the result is also stored in
- * the process-wide cache under (shape class, active-fraction bucket) that
- * solves with tile_w = tile_h = iters_per_launch = components = 0 read.  u,
- * v, p, ws as for rdseg_solve (their contents are overwritten); any output
+ * the small-component path on and off and, where the configuration's queued
+ * tiles can all fit on the chip, with both barrier kinds (on-chip exchange and
+ * kernel boundaries), on this problem for `probe_iters` iterations
+ * (synchronous) and returns the fastest (components: 1 on, 2 off; resident:
+ * 1 on-chip exchange, 2 separate launches).  A nonzero prm->tile_w, tile_h,
+ * iters_per_launch, components or resident fixes that parameter (only
+ * matching candidates are timed; RDSEG_ERR_ARG if no configuration is
+ * compiled); with all five zero the result is also stored in the
+ * process-wide cache under (shape class, active-fraction bucket) that solves
+ * with tile_w = tile_h = iters_per_launch = components = resident = 0 read.
+ * u, v, p, ws as for rdseg_solve (their contents are overwritten); any output
  * pointer may be NULL. */
 rdseg_status rdseg_autotune(const float* f, rdseg_shape s, const rdseg_params* prm,
                             int32_t probe_iters, float* u, float* v, float* p,
                             void* ws, size_t ws_bytes, void* stream,
                             int32_t* tile_w, int32_t* tile_h, int32_t* iters_per_launch,
-                            int32_t* components);
+                            int32_t* components, int32_t* resident);
 
 /* Single-image solves without checkpoints or stopping rule whose queued
  * macro tiles all fit on the chip at once (one workgroup each; e.g. a 1024^2
@@ -395,11 +406,13 @@ rdseg_status rdseg_set_components(int32_t on);
  * and active-fraction bucket, read by solves that let the library choose) as
  * JSON text, so that a tuning run can be kept and reloaded in a later process:
  *   {"version": 1, "entries": [{"size_class": c, "q_bucket": b, "tile_w": w,
- *    "tile_h": h, "iters_per_launch": i, "components": m}, ...]}
+ *    "tile_h": h, "iters_per_launch": i, "components": m, "resident": r},
+ *    ...]}
  * size_class c: the number of times H * W can be divided by 4 while it stays
  * above 4096 (at most 12); q_bucket b: 0 for an active fraction q < 0.01,
  * 1 for q < 0.05, 2 for q < 0.2, 3 for q < 0.5, 4 above; components m: 1 on,
- * 2 off.  Host memory only; no GPU call.
+ * 2 off; resident r: 1 on-chip exchange, 2 separate launches.  Host memory
+ * only; no GPU call.
  * rdseg_tune_cache_export writes the text and its NUL into buf (host, cap
  * bytes; buf may be NULL when cap is 0) and the bytes needed, NUL included,
  * into *len; RDSEG_ERR_ARG (buf untouched) if cap is smaller than that.

@@ -31,7 +31,7 @@ class Params(ctypes.Structure):
                 ("iters", ctypes.c_int32), ("iters_per_launch", ctypes.c_int32),
                 ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
                 ("ckpt_every", ctypes.c_int32), ("inner", ctypes.c_int32),
-                ("components", ctypes.c_int32)]
+                ("components", ctypes.c_int32), ("resident", ctypes.c_int32)]
 
 
 class Shape3(ctypes.Structure):
@@ -95,7 +95,8 @@ SIGNATURES = {
                                           _vp]),
     "rdseg_autotune": (ctypes.c_int, [_vp, Shape, ctypes.POINTER(Params), _i32, _vp, _vp, _vp, _vp,
                                       _sz, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
-                                      ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
+                                      ctypes.POINTER(_i32), ctypes.POINTER(_i32),
+                                      ctypes.POINTER(_i32)]),
     "rdseg_config_count": (_i32, []),
     "rdseg_config_get": (ctypes.c_int, [_i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
                                         ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),

@@ -247,7 +247,7 @@ struct TuneKey {
 };
 // configuration index and small-component choice (1 on, 2 off)
 struct TuneVal {
-    int ci, comps;
+    int ci, comps, resident;   // resident: 1 on-chip exchange allowed, 2 separate launches
 };
 std::mutex g_tune_mu;
 std::map<TuneKey, TuneVal> g_tune;
@@ -610,7 +610,8 @@ int deeper_cfg(int ci, int inner) {
 
 // Choose the tile configuration for a single-image solve.
 rdseg_status choose_cfg(const rdseg_params& prm, const rdseg_shape& s, const int64_t* npix_dev,
-                        hipStream_t st, int* ci, int* comps = nullptr) {
+                        hipStream_t st, int* ci, int* comps = nullptr,
+                        int* resident = nullptr) {
     if (prm.tile_w > 0 && prm.tile_h > 0 && prm.iters_per_launch > 0) {
         *ci = config_index(prm.tile_w, prm.tile_h, prm.iters_per_launch);
         if (*ci < 0) return fail(RDSEG_ERR_ARG, "tile_w / tile_h / iters_per_launch is not a compiled configuration");
@@ -630,6 +631,7 @@ rdseg_status choose_cfg(const rdseg_params& prm, const rdseg_shape& s, const int
         if (it != g_tune.end()) {
             *ci = it->second.ci;
             if (comps) *comps = it->second.comps;
+            if (resident) *resident = it->second.resident;
             return RDSEG_OK;
         }
     }
@@ -654,6 +656,8 @@ rdseg_status solve_impl(const float* f, rdseg_shape s, const rdseg_params* prm, 
         return fail(RDSEG_ERR_ARG, "inner must lie in [0, 16]");
     if (prm->components < 0 || prm->components > 2)
         return fail(RDSEG_ERR_ARG, "components must be 0 (library's choice), 1 (on) or 2 (off)");
+    if (prm->resident < 0 || prm->resident > 2)
+        return fail(RDSEG_ERR_ARG, "resident must be 0 (library's choice), 1 (on-chip exchange) or 2 (separate launches)");
     const int inner = prm->inner > 1 ? prm->inner : 1;
     if (inner > 1 && prm->ckpt_every > 0)
         return fail(RDSEG_ERR_ARG, "checkpoints (for the adjoint) need inner = 1");
@@ -683,9 +687,9 @@ rdseg_status solve_impl(const float* f, rdseg_shape s, const rdseg_params* prm, 
     ImgDesc d = make_desc(f, s, prm->lambda, prm->theta, prm->delta, u, v, p, w.c, w.st, u0, p0, 8, 8);
     OffTables off{nullptr, nullptr, nullptr, nullptr};
     if (launch_tile_masks(&d, nullptr, off, 1, g.strips, w.masks, w.npix, st)) return RDSEG_ERR_HIP;
-    int tuned_comps = 0;
+    int tuned_comps = 0, tuned_res = 0;
     if (ci < 0) {
-        r = choose_cfg(*prm, s, w.npix, st, &ci, &tuned_comps);
+        r = choose_cfg(*prm, s, w.npix, st, &ci, &tuned_comps, &tuned_res);
         if (r) return r;
         if (config_at(ci).it < inner) ci = deeper_cfg(ci, inner);
     }
@@ -720,7 +724,9 @@ rdseg_status solve_impl(const float* f, rdseg_shape s, const rdseg_params* prm, 
     // solve; it needs all of them resident at once, so closed tiles then run
     // before it on the same stream instead of beside it.
     bool resident = false;
-    if (g_resident_on.load() && !stop && !taped && prm->iters > 0 && resident_fits(ci, nm)) {
+    const int want_res = prm->resident ? prm->resident : (tuned_res ? tuned_res : 1);
+    if (want_res == 1 && g_resident_on.load() && !stop && !taped && prm->iters > 0 &&
+        resident_fits(ci, nm)) {
         hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
         resident = hipStreamIsCapturing(st, &cap) == hipSuccess && cap == hipStreamCaptureStatusNone;
     }
@@ -1160,10 +1166,10 @@ bool parse_cache_text(const char* text, std::vector<std::pair<TuneKey, TuneVal>>
             if (ps.lit(']')) continue;
             do {
                 if (!ps.lit('{')) { why = "an entry must be an object"; return false; }
-                const char* names[6] = {"size_class", "q_bucket", "tile_w", "tile_h",
-                                        "iters_per_launch", "components"};
-                long val[6];
-                bool seen[6] = {false, false, false, false, false, false};
+                const char* names[7] = {"size_class", "q_bucket", "tile_w", "tile_h",
+                                        "iters_per_launch", "components", "resident"};
+                long val[7];
+                bool seen[7] = {false, false, false, false, false, false, false};
                 do {
                     long x = 0;
                     if (!ps.str(key) || !ps.lit(':') || !ps.integer(x)) {
@@ -1171,20 +1177,21 @@ bool parse_cache_text(const char* text, std::vector<std::pair<TuneKey, TuneVal>>
                         return false;
                     }
                     int k = -1;
-                    for (int j = 0; j < 6; ++j)
+                    for (int j = 0; j < 7; ++j)
                         if (key == names[j]) k = j;
                     if (k < 0 || seen[k]) { why = "unknown or repeated key \"" + key + "\""; return false; }
                     seen[k] = true;
                     val[k] = x;
                 } while (ps.lit(','));
                 if (!ps.lit('}')) { why = "expected '}' after an entry"; return false; }
-                for (int j = 0; j < 6; ++j)
+                for (int j = 0; j < 7; ++j)
                     if (!seen[j]) { why = std::string("entry without \"") + names[j] + "\""; return false; }
                 if (val[0] < 0 || val[0] > 12 || val[1] < 0 || val[1] > 4) {
                     why = "size_class must lie in [0, 12] and q_bucket in [0, 4]";
                     return false;
                 }
                 if (val[5] != 1 && val[5] != 2) { why = "components must be 1 or 2"; return false; }
+                if (val[6] != 1 && val[6] != 2) { why = "resident must be 1 or 2"; return false; }
                 if (val[2] < 1 || val[2] > 4096 || val[3] < 1 || val[3] > 4096 || val[4] < 1 ||
                     val[4] > 4096) {
                     why = "tile_w, tile_h and iters_per_launch out of range";
@@ -1192,7 +1199,7 @@ bool parse_cache_text(const char* text, std::vector<std::pair<TuneKey, TuneVal>>
                 }
                 const int ci = config_index((int)val[2], (int)val[3], (int)val[4]);
                 if (ci < 0) { why = "an entry names a configuration that is not compiled"; return false; }
-                out.push_back({TuneKey{(int)val[0], (int)val[1]}, TuneVal{ci, (int)val[5]}});
+                out.push_back({TuneKey{(int)val[0], (int)val[1]}, TuneVal{ci, (int)val[5], (int)val[6]}});
             } while (ps.lit(','));
             if (!ps.lit(']')) { why = "expected ']' after the entries"; return false; }
         } else {
@@ -1794,19 +1801,25 @@ rdseg_status rdseg_config_get(int32_t i, int32_t* tile_w, int32_t* tile_h,
 rdseg_status rdseg_autotune(const float* f, rdseg_shape s, const rdseg_params* prm,
                             int32_t probe_iters, float* u, float* v, float* p, void* ws,
                             size_t ws_bytes, void* stream, int32_t* tile_w, int32_t* tile_h,
-                            int32_t* iters_per_launch, int32_t* components) {
+                            int32_t* iters_per_launch, int32_t* components, int32_t* resident) {
     if (!prm) return fail(RDSEG_ERR_ARG, "prm is NULL");
     if (probe_iters < 1) return fail(RDSEG_ERR_ARG, "probe_iters must be >= 1");
     if (prm->components < 0 || prm->components > 2)
         return fail(RDSEG_ERR_ARG, "components must be 0 (library's choice), 1 (on) or 2 (off)");
+    if (prm->resident < 0 || prm->resident > 2)
+        return fail(RDSEG_ERR_ARG, "resident must be 0 (library's choice), 1 (on-chip exchange) or 2 (separate launches)");
+    {
+        const rdseg_status rs = check_shape(s);
+        if (rs) return rs;
+    }
     hipStream_t st = static_cast<hipStream_t>(stream);
     rdseg_params q = *prm;
     q.iters = probe_iters;
     q.ckpt_every = 0;
     hipEvent_t e0, e1;
     const int inner = prm->inner > 1 ? prm->inner : 1;
-    // a nonzero tile_w / tile_h / iters_per_launch / components in prm fixes
-    // that parameter: only candidates that match it take part
+    // a nonzero tile_w / tile_h / iters_per_launch / components / resident in
+    // prm fixes that parameter: only candidates that match it take part
     auto candidate = [&](int ci) {
         const TileCfg c = config_at(ci);
         return c.it >= inner && (prm->tile_w <= 0 || c.bx == prm->tile_w) &&
@@ -1814,7 +1827,7 @@ rdseg_status rdseg_autotune(const float* f, rdseg_shape s, const rdseg_params* p
                (prm->iters_per_launch <= 0 || c.it == prm->iters_per_launch);
     };
     const bool restricted = prm->tile_w > 0 || prm->tile_h > 0 || prm->iters_per_launch > 0 ||
-                            prm->components != 0;
+                            prm->components != 0 || prm->resident != 0;
     {
         bool any = false;
         for (int ci = 0; ci < config_count(); ++ci) any = any || candidate(ci);
@@ -1823,18 +1836,32 @@ rdseg_status rdseg_autotune(const float* f, rdseg_shape s, const rdseg_params* p
     }
     const int comp_lo = prm->components ? prm->components : 1;
     const int comp_hi = prm->components ? prm->components : 2;
+    // the barrier between blocks of iterations: on-chip exchange (resident
+    // form, only where the configuration's tiles can all fit on the chip) or
+    // kernel boundaries (what a configuration without that form runs, and is
+    // recorded as)
+    auto res_range = [&](int ci, int& lo, int& hi) {
+        const TileCfg c = config_at(ci);
+        const bool capable = resident_fits(ci, macro_count(s, c.bx, c.by));
+        lo = prm->resident ? prm->resident : (capable ? 1 : 2);
+        hi = prm->resident ? prm->resident : 2;
+    };
     q.tile_w = q.tile_h = q.iters_per_launch = 0;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return fail(RDSEG_ERR_HIP, "hipEventCreate failed");
     // two rounds over all candidates, each timed over three solves after a
     // warm-up; the minimum per candidate damps clock and cache noise
     const int n = config_count();
-    std::vector<float> ms_min(2 * n, -1.0f);
+    std::vector<float> ms_min(4 * n, -1.0f);   // [config][components - 1][resident - 1]
     for (int round = 0; round < 2; ++round) {
         for (int ci = 0; ci < n; ++ci) {
             if (!candidate(ci)) continue;
-            for (int cm = comp_lo; cm <= comp_hi; ++cm) {
+            int res_lo = 1, res_hi = 1;
+            res_range(ci, res_lo, res_hi);
+            for (int cm = comp_lo; cm <= comp_hi; ++cm)
+            for (int rk = res_lo; rk <= res_hi; ++rk) {
                 q.components = cm;
+                q.resident = rk;
                 rdseg_status r = solve_impl(f, s, &q, nullptr, nullptr, u, v, p, nullptr, ws, ws_bytes, st, ci);
                 if (r) { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); return r; }
                 (void)hipEventRecord(e0, st);
@@ -1849,18 +1876,18 @@ rdseg_status rdseg_autotune(const float* f, rdseg_shape s, const rdseg_params* p
                 }
                 float ms = 0.0f;
                 (void)hipEventElapsedTime(&ms, e0, e1);
-                float& m = ms_min[2 * ci + (cm - 1)];
+                float& m = ms_min[4 * ci + 2 * (cm - 1) + (rk - 1)];
                 if (m < 0.0f || ms < m) m = ms;
             }
         }
     }
     int best = -1;
     float best_ms = 0.0f;
-    for (int k = 0; k < 2 * n; ++k)
+    for (int k = 0; k < 4 * n; ++k)
         if (ms_min[k] >= 0.0f && (best < 0 || ms_min[k] < best_ms)) { best = k; best_ms = ms_min[k]; }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    const int best_ci = best / 2, best_comps = best % 2 + 1;
+    const int best_ci = best / 4, best_comps = (best / 2) % 2 + 1, best_res = best % 2 + 1;
     // record under the problem's class and active-fraction bucket (a search
     // over a restricted set does not speak for the class)
     if (!restricted) {
@@ -1870,13 +1897,14 @@ rdseg_status rdseg_autotune(const float* f, rdseg_shape s, const rdseg_params* p
             return fail(RDSEG_ERR_HIP, "reading the active-pixel count failed");
         double qf = (double)np / ((double)s.H * s.W);
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tune[TuneKey{size_class(s), q_bucket(qf)}] = TuneVal{best_ci, best_comps};
+        g_tune[TuneKey{size_class(s), q_bucket(qf)}] = TuneVal{best_ci, best_comps, best_res};
     }
     TileCfg c = config_at(best_ci);
     if (tile_w) *tile_w = c.bx;
     if (tile_h) *tile_h = c.by;
     if (iters_per_launch) *iters_per_launch = c.it;
     if (components) *components = best_comps;
+    if (resident) *resident = best_res;
     return RDSEG_OK;
 }
 
@@ -1891,9 +1919,9 @@ rdseg_status rdseg_tune_cache_export(char* buf, size_t cap, size_t* len) {
             char e[256];
             snprintf(e, sizeof(e),
                      "%s\n  {\"size_class\": %d, \"q_bucket\": %d, \"tile_w\": %d, \"tile_h\": %d, "
-                     "\"iters_per_launch\": %d, \"components\": %d}",
+                     "\"iters_per_launch\": %d, \"components\": %d, \"resident\": %d}",
                      first ? "" : ",", kv.first.cls, kv.first.qb, c.bx, c.by, c.it,
-                     kv.second.comps);
+                     kv.second.comps, kv.second.resident);
             t += e;
             first = false;
         }

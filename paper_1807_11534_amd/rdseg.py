@@ -40,10 +40,10 @@ def shape_of(f):
 
 
 def params(lam, theta=THETA, tau=TAU, delta=math.inf, iters=0, iters_per_launch=0, tile_w=0,
-           tile_h=0, ckpt_every=0, inner=1, components=0):
+           tile_h=0, ckpt_every=0, inner=1, components=0, resident=0):
     return Params(float(lam), float(theta), float(tau), float(delta), int(iters),
                   int(iters_per_launch), int(tile_w), int(tile_h), int(ckpt_every), int(inner),
-                  int(components))
+                  int(components), int(resident))
 
 
 def workspace(s, prm=None):
@@ -106,18 +106,20 @@ def delta_for_fraction(f, q):
 
 def solve(f, lam, theta=THETA, tau=TAU, delta=math.inf, iters=100, u0=None, p0=None,
           tile=None, iters_per_launch=0, ckpt_every=0, out=None, ws=None, inner=1,
-          components=0):
+          components=0, resident=0):
     """Restricted-domain dual iteration (Sec. 2.1 restricted as in Sec. 3).
 
     tile: (tile_w, tile_h) or None (autotuned); inner: dual steps per outer
     iteration; components: small-component path, 1 on, 2 off, 0 the library's
-    choice (see autotune).  Returns (u, v, p) with p of shape [2][H][W]; with
-    ckpt_every > 0 returns (u, v, p, tape)."""
+    choice (see autotune); resident: barrier between blocks of iterations, 1
+    on-chip exchange where the tiles fit, 2 separate launches, 0 the library's
+    choice.  Returns (u, v, p) with p of shape [2][H][W]; with ckpt_every > 0
+    returns (u, v, p, tape)."""
     lib = _lib.load()
     s = shape_of(f)
     tw, th = (0, 0) if tile is None else tile
     prm = params(lam, theta, tau, delta, iters, iters_per_launch, tw, th, ckpt_every, inner,
-                 components)
+                 components, resident)
     if out is None:
         u, v, p = _empty_like_grid(f), _empty_like_grid(f), _empty_like_grid(f, 2)
     else:
@@ -386,34 +388,37 @@ def configs():
 
 class Tuned(tuple):
     """((tile_w, tile_h), iters_per_launch) of an autotuned configuration; the
-    small-component choice (1 on, 2 off) rides along as `.components`."""
+    small-component choice (1 on, 2 off) rides along as `.components` and the
+    barrier kind (1 on-chip exchange, 2 separate launches) as `.resident`."""
 
-    def __new__(cls, tile, ipl, components):
+    def __new__(cls, tile, ipl, components, resident=1):
         t = super().__new__(cls, (tile, ipl))
         t.components = components
+        t.resident = resident
         return t
 
 
 def autotune(f, lam, theta=THETA, tau=TAU, delta=math.inf, probe_iters=16, iters_per_launch=0,
-             tile=None, components=0):
+             tile=None, components=0, resident=0):
     """Time every compiled configuration, with the small-component path on and
-    off, on this problem and return the best as Tuned ((tile_w, tile_h),
-    iters_per_launch) with `.components`.  A nonzero iters_per_launch, tile
-    or components fixes that parameter and only matching candidates are
-    timed; an unrestricted search is also cached for solves that leave the
-    choice to the library."""
+    off and both barrier kinds where the tiles fit on the chip, on this
+    problem and return the best as Tuned ((tile_w, tile_h), iters_per_launch)
+    with `.components` and `.resident`.  A nonzero iters_per_launch, tile,
+    components or resident fixes that parameter and only matching candidates
+    are timed; an unrestricted search is also cached for solves that leave
+    the choice to the library."""
     lib = _lib.load()
     s = shape_of(f)
     tw, th = (0, 0) if tile is None else tile
     prm = params(lam, theta, tau, delta, probe_iters, iters_per_launch=iters_per_launch, tile_w=tw,
-                 tile_h=th, components=components)
+                 tile_h=th, components=components, resident=resident)
     u, v, p = _empty_like_grid(f), _empty_like_grid(f), _empty_like_grid(f, 2)
     ws = workspace(s, prm)
-    a, b, c, k = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    a, b, c, k, r = (ctypes.c_int32() for _ in range(5))
     check(lib.rdseg_autotune(_vp(f), s, ctypes.byref(prm), int(probe_iters), _vp(u), _vp(v),
                              _vp(p), _vp(ws), ws.numel(), _stream(), ctypes.byref(a),
-                             ctypes.byref(b), ctypes.byref(c), ctypes.byref(k)))
-    return Tuned((a.value, b.value), c.value, k.value)
+                             ctypes.byref(b), ctypes.byref(c), ctypes.byref(k), ctypes.byref(r)))
+    return Tuned((a.value, b.value), c.value, k.value, r.value)
 
 
 def timing_enable(on=True):

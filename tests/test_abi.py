@@ -147,6 +147,11 @@ def test_components_choice_validation(lib):
     assert _solve(lib, (16, 16, 16), _prm(components=3)) == 1
 
 
+def test_barrier_choice_validation(lib):
+    assert _solve(lib, (16, 16, 16), _prm(resident=-1)) == 1
+    assert _solve(lib, (16, 16, 16), _prm(resident=3)) == 1
+
+
 def test_inner_steps_validation(lib):
     assert _solve(lib, (16, 16, 16), _prm(inner=-1)) == 1
     assert _solve(lib, (16, 16, 16), _prm(inner=17)) == 1
@@ -212,11 +217,11 @@ def test_tune_cache_text_round_trip():
     assert json.loads(rdseg.tune_cache_export()) == {"version": 1, "entries": []}
     entries = [
         {"size_class": 4, "q_bucket": 4, "tile_w": 64, "tile_h": 64, "iters_per_launch": 8,
-         "components": 2},
+         "components": 2, "resident": 1},
         {"size_class": 4, "q_bucket": 1, "tile_w": 16, "tile_h": 16, "iters_per_launch": 16,
-         "components": 1},
+         "components": 1, "resident": 2},
         {"size_class": 6, "q_bucket": 0, "tile_w": 8, "tile_h": 8, "iters_per_launch": 32,
-         "components": 2},
+         "components": 2, "resident": 1},
     ]
     rdseg.tune_cache_import(json.dumps({"version": 1, "entries": entries}))
     got = json.loads(rdseg.tune_cache_export())
@@ -237,13 +242,15 @@ def test_tune_cache_text_round_trip():
     '{"version": 2, "entries": []}',
     '{"version": 1}',
     '{"version": 1, "entries": [{"size_class": 4, "q_bucket": 4, "tile_w": 64, "tile_h": 64, '
-    '"iters_per_launch": 8}]}',
+    '"iters_per_launch": 8, "components": 1}]}',
     '{"version": 1, "entries": [{"size_class": 4, "q_bucket": 5, "tile_w": 64, "tile_h": 64, '
-    '"iters_per_launch": 8, "components": 1}]}',
+    '"iters_per_launch": 8, "components": 1, "resident": 1}]}',
     '{"version": 1, "entries": [{"size_class": 4, "q_bucket": 4, "tile_w": 48, "tile_h": 64, '
-    '"iters_per_launch": 8, "components": 1}]}',
+    '"iters_per_launch": 8, "components": 1, "resident": 1}]}',
     '{"version": 1, "entries": [{"size_class": 4, "q_bucket": 4, "tile_w": 64, "tile_h": 64, '
-    '"iters_per_launch": 8, "components": 3}]}',
+    '"iters_per_launch": 8, "components": 3, "resident": 1}]}',
+    '{"version": 1, "entries": [{"size_class": 4, "q_bucket": 4, "tile_w": 64, "tile_h": 64, '
+    '"iters_per_launch": 8, "components": 1, "resident": 0}]}',
     '{"version": 1, "entries": []} trailing',
     '{"version": 1, "entries": [], "extra": 1}',
 ])
@@ -252,7 +259,8 @@ def test_tune_cache_rejects_bad_text(text):
     from paper_1807_11534_amd._lib import RdsegError
     rdseg.tune_cache_clear()
     rdseg.tune_cache_import('{"version": 1, "entries": [{"size_class": 1, "q_bucket": 0, '
-                            '"tile_w": 8, "tile_h": 8, "iters_per_launch": 8, "components": 2}]}')
+                            '"tile_w": 8, "tile_h": 8, "iters_per_launch": 8, "components": 2, '
+                            '"resident": 2}]}')
     before = rdseg.tune_cache_export()
     with pytest.raises(RdsegError):
         rdseg.tune_cache_import(text)

@@ -164,8 +164,13 @@ def test_autotune_restrictions(rd):
     ft = dev(f)
     cfgs = {(tw, th, it) for (tw, th, it, _) in rd.configs()}
     say("autotune free")
-    tile, ipl = rd.autotune(ft, 2.0, 0.1, 0.125, 0.35, 8)
+    tuned = rd.autotune(ft, 2.0, 0.1, 0.125, 0.35, 8)
+    tile, ipl = tuned
     assert (tile[0], tile[1], ipl) in cfgs
+    assert tuned.components in (1, 2) and tuned.resident in (1, 2)
+    say("autotune resident=2")
+    t2 = rd.autotune(ft, 2.0, 0.1, 0.125, 0.35, 8, resident=2)
+    assert t2.resident == 2
     say("autotune iters_per_launch=8")
     tile8, ipl8 = rd.autotune(ft, 2.0, 0.1, 0.125, 0.35, 8, iters_per_launch=8)
     assert ipl8 == 8 and (tile8[0], tile8[1], 8) in cfgs
@@ -202,7 +207,7 @@ def test_tune_cache_steers_library_choice(rd):
             rd.tune_cache_clear()
             rd.tune_cache_import(json.dumps({"version": 1, "entries": [
                 {"size_class": cls, "q_bucket": qb, "tile_w": tile[0], "tile_h": tile[1],
-                 "iters_per_launch": ipl, "components": 2}]}))
+                 "iters_per_launch": ipl, "components": 2, "resident": 2}]}))
             rd.set_resident(False)
             rd.timing_reset()
             rd.timing_enable(True)
@@ -258,6 +263,20 @@ def test_resident_matches_separate_launches(rd, shape, tile, ipl, frac, iters):
     if H * W <= 300 * 257:
         uo, vo, po = oracle.solve(f, 3.0, 0.1, 0.125, delta, iters)
         assert np.abs(res[0] - uo).max() <= U_TOL
+    # the barrier kind as a parameter: resident = 2 runs separate launches only
+    try:
+        rd.timing_reset()
+        rd.timing_enable(True)
+        par = [host(x) for x in rd.solve(ft, 3.0, 0.1, 0.125, delta, iters, tile=tile,
+                                         iters_per_launch=ipl, resident=2)]
+        n_res = rd.timing_read_form(-1, 1)[1]
+        n_sep = rd.timing_read_form(-1, 0)[1]
+    finally:
+        rd.timing_enable(False)
+        rd.timing_reset()
+    assert n_res == 0 and n_sep > 0
+    for a, b in zip(par, sep):
+        np.testing.assert_array_equal(a, b)
 
 
 @pytest.mark.parametrize("case", [
