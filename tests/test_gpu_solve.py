@@ -392,3 +392,42 @@ def test_closed_tiles_match_blocked_path(rd, frac):
             np.testing.assert_array_equal(x, y)
     uo, vo, po = oracle.solve(prob.f, prob.lam, 0.1, 0.125, delta, 120)
     compare(dev(a[0]), dev(a[1]), dev(a[2]), uo, vo, po, prob.f, delta, "closed", 120)
+
+
+@pytest.mark.parametrize("comps", [1, 2])
+def test_single_solve_in_captured_graph(rd, comps):
+    """A single-image solve captured in a graph (the small-component kernels,
+    or the closed-tile kernel, on the captured stream; no resident form under
+    capture) replays to the eager result bit for bit, three times, with eager
+    work and synchronisation between the replays."""
+    f = synth.smooth_field(300, 257, 33, noise=0.3)
+    ft = dev(f)
+    delta = synth.band_delta(f, 0.3)
+    H, W = f.shape
+    kw = dict(tile=(16, 16), iters_per_launch=8, components=comps)
+    say(f"graph capture comps={comps}")
+    ref = [host(x) for x in rd.solve(ft, 3.0, 0.1, 0.125, delta, 40, **kw)]
+    out = (torch.empty((H, W), device="cuda"), torch.empty((H, W), device="cuda"),
+           torch.empty((2, H, W), device="cuda"))
+    ws = rd.workspace(rd.shape_of(ft))
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):   # warm-up on the capture stream (occupancy queries)
+        rd.solve(ft, 3.0, 0.1, 0.125, delta, 40, out=out, ws=ws, **kw)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        rd.solve(ft, 3.0, 0.1, 0.125, delta, 40, out=out, ws=ws, **kw)
+    for rep in range(3):
+        for t in out:
+            t.fill_(-7.0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        got = [host(x) for x in out]
+        for a, b in zip(got, ref):
+            np.testing.assert_array_equal(a, b)
+        junk = torch.randn(1 << 20, device="cuda").sum()   # eager work between replays
+        torch.cuda.synchronize()
+        del junk
