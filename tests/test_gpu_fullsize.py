@@ -89,6 +89,46 @@ def invariants(u, v, p, f, delta):
     assert v.min() >= 0 and v.max() <= 1
 
 
+# the execution forms the benchmark's autotuner picks among for the sweep
+SWEEP_FORMS = [
+    dict(tile=(64, 64), iters_per_launch=8, components=2, resident=1),   # resident, dense
+    dict(tile=(64, 64), iters_per_launch=8, components=1, resident=1),   # + components in idle workgroups
+    dict(tile=(64, 32), iters_per_launch=4, components=2, resident=1),
+    dict(tile=(32, 32), iters_per_launch=8, components=1, resident=2),   # launches + component kernel
+    dict(tile=(16, 16), iters_per_launch=8, components=2, resident=2),   # launches + closed tiles
+    dict(tile=(8, 8), iters_per_launch=32, components=2, resident=2),
+]
+
+
+@pytest.mark.parametrize("li", [0, 1, 2])
+def test_sweep_1024_full_forms(rd, li):
+    """The 1024^2 sweep at 500 iterations, every delta of the benchmark, in
+    each execution form it can pick (resident with and without the small
+    components in idle workgroups, separate launches with the component or
+    closed-tile kernel): all bitwise equal; sampled components against the
+    oracle (bands below 0.55 active) or invariants (denser ones, whose whole
+    grid is compared against the oracle at 1024^2 elsewhere)."""
+    prob = synth.config2(li, size=1024, iters=500)
+    fd = dev(prob.f)
+    for frac in synth.C2_FRACS:
+        delta = synth.band_delta(prob.f, frac)
+        outs = []
+        for form in SWEEP_FORMS:
+            print(f"C2 lam={prob.lam} frac={frac} {form}", flush=True)
+            outs.append([host(x) for x in rd.solve(fd, prob.lam, prob.theta, prob.tau, delta,
+                                                   prob.iters, **form)])
+        for o in outs[1:]:
+            for a, b in zip(o, outs[0]):
+                np.testing.assert_array_equal(a, b)
+        u, v, p = outs[0]
+        invariants(u, v, p, prob.f, delta)
+        q = float((np.abs(prob.f.astype(np.float64)) < delta).mean())
+        if q < 0.55:
+            lab, comps = sample_components(prob.f, delta, 4, li)
+            check_components(u, prob.f, prob.lam, prob.theta, prob.tau, delta, prob.iters,
+                             lab, comps)
+
+
 def test_distance_selective_4096_full(rd):
     """4096^2 eq. DS term, lambda 10, delta 0.1 max|f|, 1000 iterations with the
     persistent kernel at 8 iterations per launch (the autotuned tile and every
