@@ -21,6 +21,7 @@
 //                  component
 //   k_cc_class     each small component (<= 64 pixels) takes a slot in the
 //                  class of its size rounded up to a power of two
+//   k_cc_lanes     the lanes of the waves those classes need start empty
 //   k_cc_assign    each of its pixels takes a lane: waves of one class hold
 //                  64 / 2^k components of 2^k lanes; the pixel is then frozen
 //                  for the tile path (c = +inf, its tile-mask bit cleared; the
@@ -102,12 +103,11 @@ __global__ __launch_bounds__(256) void k_cc_init(ImgDesc d, CompWs w, const int6
         const uint64_t rb = row0 & ((2ull << l) - 1);         // lanes up to l
         if (rb) start = max(start, 63 - __clzll(rb));
         w.lab[g] = act ? (int32_t)(g - (l - start)) : -1;
-        w.csize[g] = 0;
-        w.cslot[g] = 0;
+        if (act) {   // read at roots only
+            w.csize[g] = 0;
+            w.cslot[g] = 0;
+        }
         w.lane_of[g] = -1;
-        w.wl_pix[2 * g] = -1;
-        w.wl_pix[2 * g + 1] = -1;
-        if (g < kWlExtra) w.wl_pix[2 * plane + g] = -1;
         if (g < 8) w.ccount[g] = 0;
     }
 }
@@ -217,6 +217,17 @@ __global__ __launch_bounds__(256) void k_cc_class(ImgDesc d, CompWs w, const int
         if (s < 1 || s > kSmallMax) continue;
         w.cslot[g] += sBase[size_class(s)];
     }
+}
+
+// The lanes of the packed waves start empty (-1); only the waves the class
+// counts call for are cleared (the assignment pass then fills its lanes).
+__global__ __launch_bounds__(256) void k_cc_lanes(ImgDesc d, CompWs w, const int64_t* npix) {
+    if (cc_skip(npix, d)) return;
+    const int64_t plane = (int64_t)d.H * d.ld;
+    const int64_t lanes = min((int64_t)class_base(w.ccount, kClasses) * 64, 2 * plane + kWlExtra);
+    for (int64_t L = (int64_t)blockIdx.x * 256 + threadIdx.x; L < lanes;
+         L += (int64_t)gridDim.x * 256)
+        w.wl_pix[L] = -1;
 }
 
 __global__ __launch_bounds__(256) void k_cc_assign(ImgDesc d, CompWs w, uint64_t* masks,
@@ -537,6 +548,8 @@ int launch_components_prepare(const ImgDesc& d, const CompWs& w, uint64_t* masks
     // shared counters (class counts, the tile path's RD count): fewer, larger
     // workgroups keep that contention small
     hipLaunchKernelGGL(k_cc_class, dim3(std::min(grid, 1024u)), dim3(256), 0, st, d, w,
+                       (const int64_t*)npix);
+    hipLaunchKernelGGL(k_cc_lanes, dim3(std::min(grid, 1024u)), dim3(256), 0, st, d, w,
                        (const int64_t*)npix);
     hipLaunchKernelGGL(k_cc_assign, dim3(std::min(grid, 1024u)), dim3(256), 0, st, d, w, masks,
                        (const int64_t*)npix);
