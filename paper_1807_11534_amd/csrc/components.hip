@@ -320,13 +320,19 @@ __global__ __launch_bounds__(256) void k_adj_components(
     const int nwaves = (int)min((int64_t)class_base(w.ccount, kClasses),
                                 (2 * plane + kWlExtra) / 64);
     const int lane = threadIdx.x & 63;
-    const int wpb = (int)(blockDim.x >> 6);
+    // lds_mode 4: two waves per workgroup on the same packed wave, one running
+    // the reverse of segment sg while the other runs the forward of segment
+    // sg - 1 into the other of two buffers [ce][6][64]
+    const bool duo = lds_mode == 4;
+    const bool fwd_wave = duo && (threadIdx.x >> 6) == 1;
+    const int wpb = duo ? 1 : (int)(blockDim.x >> 6);
+    const int wslot = duo ? 0 : (int)(threadIdx.x >> 6);
     // LDS per wave: lds_mode 1 holds states [ce - 1][3][64], lds_mode 2 the
     // dual-update outputs and u [ce][6][64]; lds_mode 0 uses seg instead
     const int per_wave = lds_mode == 2 ? ce * 384 : (lds_mode == 1 ? (ce - 1) * 192 : 0);
-    float* __restrict__ my_states = s_states + (threadIdx.x >> 6) * per_wave + lane;
-    for (int wave = blockIdx.x * wpb + (threadIdx.x >> 6); wave < nwaves;
-         wave += gridDim.x * wpb) {   // uniform per wave
+    float* __restrict__ my_states = s_states + wslot * per_wave + lane;
+    for (int wave = blockIdx.x * wpb + wslot; wave < nwaves;
+         wave += gridDim.x * wpb) {   // uniform per wave (per workgroup with lds_mode 4)
         const int g = w.wl_pix[wave * 64 + lane];
         const bool mine = g >= 0 && g < plane;
         const int gg = mine ? g : 0;
@@ -418,91 +424,138 @@ __global__ __launch_bounds__(256) void k_adj_components(
             u = u_step(v, div_p(o.px, left(o.px), o.py, up(o.py)), theta);
         };
         const int nseg = (K + ce - 1) / ce;
-        for (int sg = nseg - 1; sg >= 0; --sg) {
-            const int k0 = sg * ce;
-            const int len = min(ce, K - k0);
-            const float* __restrict__ s0 = tape + (int64_t)sg * 3 * plane;
-            float cv = 0.0f, cpx = 0.0f, cpy = 0.0f;   // the checkpoint, state k0
-            if (mine) {
-                cv = s0[gg];
-                cpx = s0[plane + gg];
-                cpy = s0[2 * plane + gg];
-            }
-            if (lds_mode == 2) {
-                // forward over all len steps, keeping what the reverse reads:
-                // slot j = p^(k0+j+1), g, m and u^(k0+j+1) of the step from state k0 + j
-                float v = cv, px = cpx, py = cpy;
-                for (int j = 0; j < len; ++j) {
-                    DualOut o;
-                    float u;
-                    forward_step(v, px, py, o, u);
-                    float* __restrict__ sj = my_states + j * 384;
-                    sj[0] = o.px;
-                    sj[64] = o.py;
-                    sj[128] = o.gx;
-                    sj[192] = o.gy;
-                    sj[256] = o.m;
-                    sj[320] = u;
-                    px = o.px;
-                    py = o.py;
-                    v = v_step(u, c);
-                }
-                for (int k = k0 + len; k >= k0 + 1; --k) {
-                    const float* __restrict__ sj = my_states + (k - 1 - k0) * 384;
-                    reverse_step(k, sj[0], sj[64], sj[128], sj[192], sj[256], sj[320]);
-                }
-                continue;
-            }
-            // forward: the states k0 + 1 .. k0 + len - 1 of this segment
-            {
-                float v = cv, px = cpx, py = cpy;
-                for (int j = 1; j < len; ++j) {
-                    DualOut o;
-                    float u;
-                    forward_step(v, px, py, o, u);
-                    px = o.px;
-                    py = o.py;
-                    v = v_step(u, c);
-                    if (lds_mode == 1) {
-                        float* __restrict__ sj = my_states + (j - 1) * 192;
-                        sj[0] = v;
-                        sj[64] = px;
-                        sj[128] = py;
-                    } else if (mine) {
-                        float* __restrict__ sj = seg + (int64_t)(j - 1) * 3 * plane;
-                        sj[gg] = v;
-                        sj[plane + gg] = px;
-                        sj[2 * plane + gg] = py;
-                    }
-                }
-            }
-            // reverse: steps k0 + len .. k0 + 1 from the states k - 1
-            for (int k = k0 + len; k >= k0 + 1; --k) {
-                const int j = k - 1 - k0;
-                float sv = 0.0f, spx = 0.0f, spy = 0.0f;
-                if (j == 0) {
-                    sv = cv;
-                    spx = cpx;
-                    spy = cpy;
-                } else if (lds_mode == 1) {
-                    const float* __restrict__ sj = my_states + (j - 1) * 192;
-                    sv = mine ? sj[0] : 0.0f;
-                    spx = mine ? sj[64] : 0.0f;
-                    spy = mine ? sj[128] : 0.0f;
-                } else if (mine) {
-                    const float* __restrict__ sj = seg + (int64_t)(j - 1) * 3 * plane;
-                    sv = sj[gg];
-                    spx = sj[plane + gg];
-                    spy = sj[2 * plane + gg];
-                }
-                // w from p^(k-1), v^(k-1); the dual update gives p^k, g and m; u^k
+        if (duo) {
+            auto fwd_store = [&](float* __restrict__ base, int j, float& v, float& px, float& py) {
                 DualOut o;
                 float u;
-                forward_step(sv, spx, spy, o, u);
-                reverse_step(k, o.px, o.py, o.gx, o.gy, o.m, u);
+                forward_step(v, px, py, o, u);
+                float* __restrict__ sj = base + j * 384;
+                sj[0] = o.px;
+                sj[64] = o.py;
+                sj[128] = o.gx;
+                sj[192] = o.gy;
+                sj[256] = o.m;
+                sj[320] = u;
+                px = o.px;
+                py = o.py;
+                v = v_step(u, c);
+            };
+            auto fwd_segment = [&](int sg, float* __restrict__ base) {
+                float v = 0.0f, px = 0.0f, py = 0.0f;
+                if (mine) {
+                    const float* __restrict__ s0 = tape + (int64_t)sg * 3 * plane;
+                    v = s0[gg];
+                    px = s0[plane + gg];
+                    py = s0[2 * plane + gg];
+                }
+                const int len = min(ce, K - sg * ce);
+                for (int j = 0; j < len; ++j) fwd_store(base, j, v, px, py);
+            };
+            float* const bufs[2] = {s_states + lane, s_states + ce * 384 + lane};
+            if (fwd_wave) fwd_segment(nseg - 1, bufs[(nseg - 1) & 1]);
+            __syncthreads();
+            for (int sg = nseg - 1; sg >= 0; --sg) {
+                if (fwd_wave) {
+                    if (sg > 0) fwd_segment(sg - 1, bufs[(sg - 1) & 1]);
+                } else {
+                    const int k0 = sg * ce;
+                    const int len = min(ce, K - k0);
+                    const float* __restrict__ cur = bufs[sg & 1];
+                    for (int i = 0; i < len; ++i) {
+                        const float* __restrict__ sj = cur + (len - 1 - i) * 384;
+                        reverse_step(k0 + len - i, sj[0], sj[64], sj[128], sj[192], sj[256],
+                                     sj[320]);
+                    }
+                }
+                __syncthreads();
+            }
+        } else {
+            for (int sg = nseg - 1; sg >= 0; --sg) {
+                const int k0 = sg * ce;
+                const int len = min(ce, K - k0);
+                const float* __restrict__ s0 = tape + (int64_t)sg * 3 * plane;
+                float cv = 0.0f, cpx = 0.0f, cpy = 0.0f;   // the checkpoint, state k0
+                if (mine) {
+                    cv = s0[gg];
+                    cpx = s0[plane + gg];
+                    cpy = s0[2 * plane + gg];
+                }
+                if (lds_mode == 2) {
+                    // forward over all len steps, keeping what the reverse reads:
+                    // slot j = p^(k0+j+1), g, m and u^(k0+j+1) of the step from state k0 + j
+                    float v = cv, px = cpx, py = cpy;
+                    for (int j = 0; j < len; ++j) {
+                        DualOut o;
+                        float u;
+                        forward_step(v, px, py, o, u);
+                        float* __restrict__ sj = my_states + j * 384;
+                        sj[0] = o.px;
+                        sj[64] = o.py;
+                        sj[128] = o.gx;
+                        sj[192] = o.gy;
+                        sj[256] = o.m;
+                        sj[320] = u;
+                        px = o.px;
+                        py = o.py;
+                        v = v_step(u, c);
+                    }
+                    for (int k = k0 + len; k >= k0 + 1; --k) {
+                        const float* __restrict__ sj = my_states + (k - 1 - k0) * 384;
+                        reverse_step(k, sj[0], sj[64], sj[128], sj[192], sj[256], sj[320]);
+                    }
+                    continue;
+                }
+                // forward: the states k0 + 1 .. k0 + len - 1 of this segment
+                {
+                    float v = cv, px = cpx, py = cpy;
+                    for (int j = 1; j < len; ++j) {
+                        DualOut o;
+                        float u;
+                        forward_step(v, px, py, o, u);
+                        px = o.px;
+                        py = o.py;
+                        v = v_step(u, c);
+                        if (lds_mode == 1) {
+                            float* __restrict__ sj = my_states + (j - 1) * 192;
+                            sj[0] = v;
+                            sj[64] = px;
+                            sj[128] = py;
+                        } else if (mine) {
+                            float* __restrict__ sj = seg + (int64_t)(j - 1) * 3 * plane;
+                            sj[gg] = v;
+                            sj[plane + gg] = px;
+                            sj[2 * plane + gg] = py;
+                        }
+                    }
+                }
+                // reverse: steps k0 + len .. k0 + 1 from the states k - 1
+                for (int k = k0 + len; k >= k0 + 1; --k) {
+                    const int j = k - 1 - k0;
+                    float sv = 0.0f, spx = 0.0f, spy = 0.0f;
+                    if (j == 0) {
+                        sv = cv;
+                        spx = cpx;
+                        spy = cpy;
+                    } else if (lds_mode == 1) {
+                        const float* __restrict__ sj = my_states + (j - 1) * 192;
+                        sv = mine ? sj[0] : 0.0f;
+                        spx = mine ? sj[64] : 0.0f;
+                        spy = mine ? sj[128] : 0.0f;
+                    } else if (mine) {
+                        const float* __restrict__ sj = seg + (int64_t)(j - 1) * 3 * plane;
+                        sv = sj[gg];
+                        spx = sj[plane + gg];
+                        spy = sj[2 * plane + gg];
+                    }
+                    // w from p^(k-1), v^(k-1); the dual update gives p^k, g and m; u^k
+                    DualOut o;
+                    float u;
+                    forward_step(sv, spx, spy, o, u);
+                    reverse_step(k, o.px, o.py, o.gx, o.gy, o.m, u);
+                }
             }
         }
-        if (mine) {
+        if (mine && !fwd_wave) {
             sacc[gg] = S;
             vb_out[gg] = vb;
         }
@@ -533,8 +586,7 @@ int g_adj_comp_grid = 0;
 // per wave, at most the default 64 KiB of a workgroup; the grid for the last
 // size used
 constexpr int kAdjLdsMax = 65536;
-size_t g_adj_lds_bytes = 0;
-int g_adj_lds_grid = 0;
+int g_adj_lds_limit = 0;   // the device's largest workgroup allocation
 
 }  // namespace
 
@@ -591,36 +643,60 @@ int launch_adj_components(const ImgDesc& d, const CompWs& w, const int64_t* npix
                           const float* tape, float* seg, int K, int ce, const float* grad_u,
                           const float* grad_v, float* vb_out, float* sacc, float theta,
                           float inv_theta, float tau, hipStream_t st, int64_t nwaves_hint) {
-    // The kept dual-update outputs (mode 2) shorten every reverse step but
+    // The kept dual-update outputs (modes 2, 4) shorten every reverse step but
     // take twice the LDS of the states (mode 1), so fewer waves run at once:
-    // mode 2 when all the component waves fit on the chip together.
+    // they are used when all the component waves fit on the chip together.
+    // Mode 4 adds a second wave per workgroup that runs the next segment's
+    // forward beside the current reverse (two buffers; a workgroup allocation
+    // above the default 64 KiB where the device offers one).
     const size_t rich = (size_t)ce * 384 * sizeof(float);
     const size_t lean = (size_t)(ce - 1) * 192 * sizeof(float);
     const bool lean_ok = ce > 1 && lean <= (size_t)kAdjLdsMax;
+    if (g_adj_lds_limit == 0) {
+        int dev = 0, v = 0;
+        g_adj_lds_limit = kAdjLdsMax;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) ==
+                hipSuccess &&
+            v > kAdjLdsMax)
+            g_adj_lds_limit = v;
+    }
+    const void* fn = reinterpret_cast<const void*>(k_adj_components);
+    auto cap_of = [&](int threads, size_t bytes) {
+        return bytes > (size_t)g_adj_lds_limit ? 0 : persistent_blocks(fn, threads, bytes);
+    };
+    const bool few = nwaves_hint >= 0;
     int mode = lean_ok ? 1 : 0;
     if (rich <= (size_t)kAdjLdsMax) {
-        const int cap = persistent_blocks(reinterpret_cast<const void*>(k_adj_components), 64, rich);
-        if (!lean_ok || (nwaves_hint >= 0 && cap > 0 && nwaves_hint <= cap)) mode = 2;
+        const int cap = cap_of(64, rich);
+        if (!lean_ok || (few && cap > 0 && nwaves_hint <= cap)) mode = 2;
     }
-    const size_t lds = mode == 2 ? rich : lean;
+    if (mode == 2 && few && K > ce) {
+        const int cap = cap_of(128, 2 * rich);
+        if (cap > 0 && nwaves_hint <= cap) mode = 4;
+    }
+    if (mode == 4 && 2 * rich > (size_t)kAdjLdsMax &&
+        hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(2 * rich)) !=
+            hipSuccess) {
+        (void)hipGetLastError();
+        mode = 2;   // the larger allocation is not available: one wave, one buffer
+    }
     if (mode > 0) {
-        if (g_adj_lds_bytes != lds || g_adj_lds_grid <= 0) {
-            g_adj_lds_grid = persistent_blocks(reinterpret_cast<const void*>(k_adj_components), 64, lds);
-            g_adj_lds_bytes = lds;
-            if (g_adj_lds_grid <= 0) {
-                g_adj_lds_grid = 0;
-                set_error("occupancy query failed for the component adjoint kernel");
-                return 4;
-            }
+        const int threads = mode == 4 ? 128 : 64;
+        const size_t lds = mode == 4 ? 2 * rich : (mode == 2 ? rich : lean);
+        const int grid = persistent_blocks(fn, threads, lds);
+        if (grid <= 0) {
+            set_error("occupancy query failed for the component adjoint kernel");
+            return 4;
         }
-        hipLaunchKernelGGL(k_adj_components, dim3((unsigned)g_adj_lds_grid), dim3(64), lds, st, d,
-                           w, npix, tape, seg, K, ce, grad_u, grad_v, vb_out, sacc, theta,
+        hipLaunchKernelGGL(k_adj_components, dim3((unsigned)grid), dim3(threads), lds, st, d, w,
+                           npix, tape, seg, K, ce, grad_u, grad_v, vb_out, sacc, theta,
                            inv_theta, tau, mode);
         RDSEG_HIP_CHECK(hipGetLastError());
         return 0;
     }
     if (g_adj_comp_grid == 0) {
-        g_adj_comp_grid = persistent_blocks(reinterpret_cast<const void*>(k_adj_components), 256, 0);
+        g_adj_comp_grid = persistent_blocks(fn, 256, 0);
         if (g_adj_comp_grid <= 0) {
             g_adj_comp_grid = 0;
             set_error("occupancy query failed for the component adjoint kernel");

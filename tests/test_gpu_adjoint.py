@@ -233,14 +233,17 @@ def test_backward_full_size_differentiation_workload(rd):
 
 @pytest.mark.parametrize("case", [("config5_512", 0.1, 300, 30), ("config5_512", 0.5, 120, 30),
                                   ("ragged", 0.4, 90, 30), ("ragged", 0.4, 90, 7),
-                                  ("ragged", 0.4, 130, 60), ("config5_512", 0.5, 120, 100)])
+                                  ("ragged", 0.4, 130, 60), ("ragged", 0.4, 25, 30),
+                                  ("config5_512", 0.5, 120, 100)])
 def test_component_reverse_matches_tile_path(rd, case):
     """RD components of at most 64 pixels in both directions: the component
     forward writes the same checkpoints (on RD, where the tape is defined) and
     the same u, v, p as the tile path, and their reverse sweep (all steps in
     one launch) gives the same bits as the tile path's per-step launches
-    (ckpt_every 7 and 30 keep each step's dual-update outputs in LDS, 60 the
-    states, 100 the per-pixel slots),
+    (with few waves, ckpt_every 7 and 30 keep each step's dual-update outputs
+    in LDS, with a second wave running the next segment's forward when there
+    are several segments; many waves or ckpt_every 60 keep the states; 100 the
+    per-pixel slots),
     with a fitting-term gradient and both adjoint inputs."""
     name, frac, K, ce = case
     if name == "ragged":
