@@ -203,9 +203,8 @@ def extras(torch, rdseg, synth, dev, which=EXTRAS):
                 rdseg.backward(f, prob.lam, synth.THETA, synth.TAU, delta, 300, 30, tape,
                                2 * (u - tgt))
 
-            def fwd_only():
-                rdseg.solve(f, prob.lam, synth.THETA, synth.TAU, delta, 300, tile=(32, 32),
-                            iters_per_launch=2)
+            def fwd_only():   # the untaped forward in the library's own configuration
+                rdseg.solve(f, prob.lam, synth.THETA, synth.TAU, delta, 300)
 
             fwd_bwd()
             t_fb = timed(torch, fwd_bwd, 3)

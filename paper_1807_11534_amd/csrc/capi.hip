@@ -267,12 +267,21 @@ int q_bucket(double q) {
     return 0;
 }
 
+// The configuration for a problem class the tuning cache does not hold, from
+// what the autotuner picked on measured workloads: deep launches on small
+// tiles for thin bands and bands of up to half the image (few launches; the
+// small tiles follow the band's shape), and for denser ones the 64x64 /
+// 8-iteration form, resident where all its tiles fit on the chip (else 4
+// iterations a launch, less halo recomputed).
 int heuristic_cfg(const rdseg_shape& s, double q) {
     int64_t n = (int64_t)s.H * s.W;
     if (n <= 128 * 128) return config_index(16, 16, 2);
-    if (q >= 0.2) return config_index(64, 64, 4);
-    if (q >= 0.03) return config_index(32, 32, 2);
-    return config_index(16, 16, 1);
+    if (q >= 0.5) {
+        const int deep = config_index(64, 64, 8);
+        return resident_fits(deep, macro_count(s, 64, 64)) ? deep : config_index(64, 64, 4);
+    }
+    if (q >= 0.01) return config_index(16, 16, 8);
+    return config_index(8, 8, 32);
 }
 
 // ------------------------------------------------------------------ side stream
