@@ -176,7 +176,7 @@ def extras(torch, rdseg, synth, dev, which=EXTRAS):
                                 iters_per_launch=ipl, out=seq_out[i], ws=wss[i])
 
             sequential()
-            t_seq = timed(torch, sequential, 1)
+            t_seq = timed(torch, sequential, 3)
             same = all(torch.equal(a[0], b[0]) for a, b in zip(outs, seq_out))
             upd = q * n_px * 300
             out[name] = dict(images=512, pixels=n_px, active_fraction=q, iters=300,
@@ -199,7 +199,7 @@ def extras(torch, rdseg, synth, dev, which=EXTRAS):
 
             def fwd_bwd():
                 u, v, p, tape = rdseg.solve(f, prob.lam, synth.THETA, synth.TAU, delta, 300,
-                                            tile=(32, 32), iters_per_launch=2, ckpt_every=30)
+                                            ckpt_every=30)
                 rdseg.backward(f, prob.lam, synth.THETA, synth.TAU, delta, 300, 30, tape,
                                2 * (u - tgt))
 
