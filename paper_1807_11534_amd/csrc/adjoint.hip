@@ -16,6 +16,7 @@
 // accumulated per pixel; dL/df = -theta lambda * that sum and dL/dlambda =
 // -theta sum f * that sum.  Six LDS phases separated by barriers; the halo is 3
 // pixels on every side (each phase reaches one cell further).
+#include <atomic>
 #include "rdseg_internal.h"
 
 namespace rdseg {
@@ -360,7 +361,8 @@ struct AdjEntry {
 const AdjEntry kAdj[] = {
     {32, 32, 256, k_adj_step<32, 32, 256>},
 };
-int g_adj_grid[sizeof(kAdj) / sizeof(kAdj[0])];
+// occupancy-derived grid sizes, filled on first use (any host thread)
+std::atomic<int> g_adj_grid[sizeof(kAdj) / sizeof(kAdj[0])];
 
 inline unsigned red_blocks(int H) { return (unsigned)(H < 1024 ? H : 1024); }
 
@@ -381,15 +383,16 @@ int launch_adj_step(const ImgDesc& d, const float* fx, const float* fy, const fl
         set_error("no adjoint kernel for this tile size");
         return 1;
     }
-    if (g_adj_grid[ai] == 0) {
-        g_adj_grid[ai] = persistent_blocks(reinterpret_cast<const void*>(kAdj[ai].fn), kAdj[ai].nt, 0);
-        if (g_adj_grid[ai] <= 0) {
-            g_adj_grid[ai] = 0;
+    int64_t g = g_adj_grid[ai].load(std::memory_order_relaxed);
+    if (g == 0) {
+        const int b = persistent_blocks(reinterpret_cast<const void*>(kAdj[ai].fn), kAdj[ai].nt, 0);
+        if (b <= 0) {
             set_error("occupancy query failed for the adjoint kernel");
             return 4;
         }
+        g_adj_grid[ai].store(b, std::memory_order_relaxed);
+        g = b;
     }
-    int64_t g = g_adj_grid[ai];
     if (max_items < g) g = max_items;
     if (g < 1) g = 1;
     const int out = 1 - in_buf;

@@ -4,6 +4,7 @@
 // it (the work lists flag such tiles in macro tiles that hold no open tile).
 // Its RD pixels then see nothing of the rest of the image but the constants of
 // frozen neighbours, so one wave can run all of its iterations alone.
+#include <atomic>
 #include "rdseg_internal.h"
 
 namespace rdseg {
@@ -104,19 +105,20 @@ __global__ __launch_bounds__(64) void k_closed(ImgDesc d0, const ImgDesc* __rest
 
 }  // namespace
 
-int g_closed_grid[2] = {0, 0};
+// occupancy-derived grid sizes, filled on first use (any host thread)
+std::atomic<int> g_closed_grid[2];
 
 int prepare_closed(bool batched) {
     const void* fn = batched ? reinterpret_cast<const void*>(k_closed<true>)
                              : reinterpret_cast<const void*>(k_closed<false>);
-    int& cached = g_closed_grid[batched ? 1 : 0];
-    if (cached == 0) {
-        cached = persistent_blocks(fn, 64, 0);
-        if (cached <= 0) {
-            cached = 0;
+    std::atomic<int>& cached = g_closed_grid[batched ? 1 : 0];
+    if (cached.load(std::memory_order_relaxed) == 0) {
+        const int b = persistent_blocks(fn, 64, 0);
+        if (b <= 0) {
             set_error("occupancy query failed for the closed-tile kernel");
             return 4;
         }
+        cached.store(b, std::memory_order_relaxed);
     }
     return 0;
 }
@@ -125,7 +127,7 @@ int launch_closed(const ImgDesc* d0, const ImgDesc* descs, bool batched, const i
                   const int32_t* n_closed, int64_t max_items, int iters, float theta,
                   float inv_theta, float tau, hipStream_t st, int inner) {
     if (prepare_closed(batched)) return 4;
-    int64_t g = g_closed_grid[batched ? 1 : 0];
+    int64_t g = g_closed_grid[batched ? 1 : 0].load(std::memory_order_relaxed);
     if (max_items < g) g = max_items;
     if (g < 1) g = 1;
     if (batched)

@@ -30,6 +30,7 @@
 // Lane order within a component depends on atomics, but no result does: each
 // pixel's arithmetic reads exact neighbour values, with the per-pixel
 // functions of the other kernels, so results are bitwise equal to theirs.
+#include <atomic>
 #include <algorithm>
 
 #include "components_device.h"
@@ -586,7 +587,7 @@ int g_adj_comp_grid = 0;
 // per wave, at most the default 64 KiB of a workgroup; the grid for the last
 // size used
 constexpr int kAdjLdsMax = 65536;
-int g_adj_lds_limit = 0;   // the device's largest workgroup allocation
+std::atomic<int> g_adj_lds_limit{0};   // the device's largest workgroup allocation
 
 }  // namespace
 
@@ -652,18 +653,20 @@ int launch_adj_components(const ImgDesc& d, const CompWs& w, const int64_t* npix
     const size_t rich = (size_t)ce * 384 * sizeof(float);
     const size_t lean = (size_t)(ce - 1) * 192 * sizeof(float);
     const bool lean_ok = ce > 1 && lean <= (size_t)kAdjLdsMax;
-    if (g_adj_lds_limit == 0) {
+    int lds_limit = g_adj_lds_limit.load(std::memory_order_relaxed);
+    if (lds_limit == 0) {
         int dev = 0, v = 0;
-        g_adj_lds_limit = kAdjLdsMax;
+        lds_limit = kAdjLdsMax;
         if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) ==
                 hipSuccess &&
             v > kAdjLdsMax)
-            g_adj_lds_limit = v;
+            lds_limit = v;
+        g_adj_lds_limit.store(lds_limit, std::memory_order_relaxed);
     }
     const void* fn = reinterpret_cast<const void*>(k_adj_components);
     auto cap_of = [&](int threads, size_t bytes) {
-        return bytes > (size_t)g_adj_lds_limit ? 0 : persistent_blocks(fn, threads, bytes);
+        return bytes > (size_t)lds_limit ? 0 : persistent_blocks(fn, threads, bytes);
     };
     const bool few = nwaves_hint >= 0;
     int mode = lean_ok ? 1 : 0;

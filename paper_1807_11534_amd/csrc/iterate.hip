@@ -18,6 +18,7 @@
 // other), so tiles never read a neighbour's halo while it is being written.
 // Pixels off RD are never read from or written to the state buffers: their
 // values (v = H(-f), p = 0) come from c = -/+inf.
+#include <atomic>
 #include "components_device.h"
 
 namespace rdseg {
@@ -725,7 +726,8 @@ const CfgEntry kCfgs[] = {
 };
 constexpr int kNumCfgs = sizeof(kCfgs) / sizeof(kCfgs[0]);
 
-int g_grid_cache[kNumCfgs][3];
+// occupancy-derived grid sizes, filled on first use (any host thread)
+std::atomic<int> g_grid_cache[kNumCfgs][3];
 
 using ResFn = void (*)(ImgDesc, const int2*, const int32_t*, const int32_t*, int32_t*, int32_t*,
                        int, int, int, int, float, float, float, CompWs, const int64_t*, int);
@@ -742,7 +744,7 @@ const ResEntry kRes[] = {
     RDSEG_RES(64, 64, 8, 1024),
 };
 constexpr int kNumRes = sizeof(kRes) / sizeof(kRes[0]);
-int g_res_cap[kNumRes];
+std::atomic<int> g_res_cap[kNumRes];   // co-resident workgroups; -1: none
 
 int resident_entry(int ci) {
     const TileCfg c = kCfgs[ci].cfg;
@@ -780,10 +782,11 @@ int persistent_blocks(const void* kernel, int threads, size_t dyn_lds) {
 bool resident_fits(int ci, int64_t max_items) {
     const int r = resident_entry(ci);
     if (r < 0 || max_items < 1) return false;
-    int& cap = g_res_cap[r];
+    int cap = g_res_cap[r].load(std::memory_order_relaxed);
     if (cap == 0) {
         cap = persistent_blocks(reinterpret_cast<const void*>(kRes[r].fn), kRes[r].nt, 0);
         if (cap <= 0) cap = -1;
+        g_res_cap[r].store(cap, std::memory_order_relaxed);
     }
     return cap > 0 && ((max_items + 7) / 8) * 8 <= cap;
 }
@@ -834,14 +837,14 @@ int prepare_iterate(int ci, bool batched, bool stop) {
     const CfgEntry& e = kCfgs[ci];
     const int kind = stop ? 2 : (batched ? 1 : 0);
     IterFn fn = e.fn[kind];
-    int& cached = g_grid_cache[ci][kind];
-    if (cached == 0) {
-        cached = persistent_blocks(reinterpret_cast<const void*>(fn), e.cfg.nt, 0);
-        if (cached <= 0) {
-            cached = 0;
+    std::atomic<int>& cached = g_grid_cache[ci][kind];
+    if (cached.load(std::memory_order_relaxed) == 0) {
+        const int b = persistent_blocks(reinterpret_cast<const void*>(fn), e.cfg.nt, 0);
+        if (b <= 0) {
             set_error("occupancy query failed for the iteration kernel");
             return 4;
         }
+        cached.store(b, std::memory_order_relaxed);
     }
     return 0;
 }
@@ -858,7 +861,7 @@ int launch_iterate(int ci, const ImgDesc* d0, const ImgDesc* descs, bool batched
     const int kind = stop ? 2 : (batched ? 1 : 0);
     IterFn fn = e.fn[kind];
     if (prepare_iterate(ci, batched, stop != nullptr)) return 4;
-    int64_t g = g_grid_cache[ci][kind];
+    int64_t g = g_grid_cache[ci][kind].load(std::memory_order_relaxed);
     if (max_items < g) g = max_items;
     g = ((g + 7) / 8) * 8;
     if (g < 8) g = 8;
