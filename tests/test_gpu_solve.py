@@ -227,6 +227,38 @@ def test_tune_cache_steers_library_choice(rd):
         rd.tune_cache_clear()
 
 
+@pytest.mark.parametrize("q_target,tile,ipl", [
+    (0.004, (8, 8), 32), (0.2, (16, 16), 8), (0.8, (64, 64), 8)])
+def test_untuned_choice_by_band_width(rd, q_target, tile, ipl):
+    """With an empty tuning cache the library picks the configuration from the
+    band's share of the image: deep launches on 8x8 tiles below 1 %, 16x16 with
+    8 iterations a launch up to half the image, the 64x64 / 8 resident form
+    above (all 25 of its tiles fit on the chip here).  The timing records show
+    that configuration only, and the result equals an explicit solve with it."""
+    f = synth.smooth_field(320, 300, 37, noise=0.2)
+    ft = dev(f)
+    delta = float(np.quantile(np.abs(f.astype(np.float64)), q_target))
+    say(f"untuned choice at q ~ {q_target}: expect {tile} x {ipl}")
+    try:
+        rd.tune_cache_clear()
+        rd.timing_reset()
+        rd.timing_enable(True)
+        got = [host(x) for x in rd.solve(ft, 2.0, 0.1, 0.125, delta, 40, components=2)]
+        rd.timing_enable(False)
+        ci = rd.config_index(tile, ipl)
+        assert rd.timing_read(ci)[1] > 0
+        assert rd.timing_read(-1)[1] == rd.timing_read(ci)[1]
+        if tile == (64, 64):
+            assert rd.timing_read_form(ci, 1)[1] == 1   # one resident launch
+        ref = [host(x) for x in rd.solve(ft, 2.0, 0.1, 0.125, delta, 40, tile=tile,
+                                         iters_per_launch=ipl, components=2)]
+        for a, b in zip(got, ref):
+            np.testing.assert_array_equal(a, b)
+    finally:
+        rd.timing_enable(False)
+        rd.timing_reset()
+
+
 @pytest.mark.parametrize("shape,tile,ipl,frac,iters", [
     ((1024, 1024), (64, 64), 8, math.inf, 61),
     ((1024, 1024), (64, 64), 8, 0.5, 40),
