@@ -49,7 +49,8 @@ typedef enum {
     RDSEG_ERR_SHAPE = 2,      /* H or W < 1, ld < W, or H*ld >= 2^31 */
     RDSEG_ERR_WORKSPACE = 3,  /* ws NULL or ws_bytes below the required size */
     RDSEG_ERR_HIP = 4,        /* a HIP runtime call or kernel launch failed */
-    RDSEG_ERR_TAPE = 5        /* tape missing or inconsistent with the parameters */
+    RDSEG_ERR_TAPE = 5,       /* tape missing or inconsistent with the parameters */
+    RDSEG_ERR_TIMEOUT = 6     /* a bounded on-chip wait expired (see rdseg_solve_status) */
 } rdseg_status;
 
 typedef struct {
@@ -187,6 +188,22 @@ rdseg_status rdseg_solve(const float* f, rdseg_shape s, const rdseg_params* prm,
                          const float* u0, const float* p0,
                          float* u, float* v, float* p, float* tape,
                          void* ws, size_t ws_bytes, void* stream);
+
+/* Status of the last rdseg_solve / rdseg_solve_until that used the workspace
+ * ws (device, the same shape s): synchronises `stream` (the stream that solve
+ * was enqueued on) and reads the solve's status word, which every solve
+ * clears when it starts.  RDSEG_ERR_TIMEOUT when the solve ran in the
+ * resident form (see rdseg_set_resident) and a tile's bounded wait for a
+ * neighbouring tile's frame expired: that tile, and every tile that would
+ * have read its later frames, stopped and wrote NaN into u, v and p (the other
+ * tiles hold their exact result); RDSEG_OK otherwise.  In normal operation the
+ * waits do not expire, because a cooperative launch keeps every tile
+ * resident; a preempted or time-sliced dispatch is the case this reports.
+ * Errors: RDSEG_ERR_ARG / _SHAPE / _WORKSPACE for a NULL or invalid shape or
+ * a workspace smaller than rdseg_workspace_size(s); RDSEG_ERR_HIP if the
+ * read fails. */
+rdseg_status rdseg_solve_status(const rdseg_shape* s, const void* ws, size_t ws_bytes,
+                                void* stream);
 
 /* Convergence-driven solve with the stopping rule of Sec. 4: stop at the
  * first iteration l, among the multiples of check_every, where
@@ -390,6 +407,13 @@ rdseg_status rdseg_autotune(const float* f, rdseg_shape s, const rdseg_params* p
  * form.  Process-wide. */
 rdseg_status rdseg_set_resident(int32_t on);
 
+/* Bound of each wait of the resident form in ticks of the GPU's 100 MHz
+ * wall clock: ticks > 0 sets it, 0 restores the default (10^8, one second),
+ * ticks < 0 makes every wait that is not already satisfied give up at once
+ * (the expiry path forced from the host, for tests of rdseg_solve_status).
+ * Process-wide; read when a resident solve is enqueued. */
+rdseg_status rdseg_set_resident_wait(int64_t ticks);
+
 /* In single-image solves without the stopping rule, the RD pixels whose
  * 4-connected RD component has at most 64 pixels run every iteration in one
  * launch, one pixel per lane (an RD pixel interacts only with its own
@@ -448,6 +472,15 @@ rdseg_status rdseg_timing_read_form(int32_t config, int32_t form, double* kernel
                                     int64_t* launches, double* alg_bytes,
                                     int64_t* pixel_updates);
 rdseg_status rdseg_timing_reset(void);
+
+/* Releases what the library keeps for the process on the host and in the
+ * HIP runtime: the per-device side streams (after their work completes), the
+ * timing events and the pinned host buffers of timing and polling.  Device
+ * memory of batched plans is not touched (rdseg_plan_destroy).  Call it
+ * before the HIP runtime shuts down (the Python binding does at interpreter
+ * exit); the library creates them again on later use.  Not concurrent with
+ * other calls of the library. */
+rdseg_status rdseg_release(void);
 
 const char* rdseg_status_string(rdseg_status st);
 const char* rdseg_last_error(void);

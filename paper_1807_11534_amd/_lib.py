@@ -4,6 +4,7 @@ Argument marshalling only: every step of the method runs in the HIP library.
 If the library has not been built this module raises instead of falling back
 to anything else.
 """
+import atexit
 import ctypes
 import os
 
@@ -12,7 +13,9 @@ LIB_PATH = os.path.join(HERE, "librdseg.so")
 
 RDSEG_OK = 0
 STATUS_NAMES = {0: "ok", 1: "invalid argument", 2: "invalid shape", 3: "workspace too small",
-                4: "HIP error", 5: "tape missing or inconsistent"}
+                4: "HIP error", 5: "tape missing or inconsistent",
+                6: "a bounded on-chip wait expired"}
+RDSEG_ERR_TIMEOUT = 6
 
 
 class RdsegError(RuntimeError):
@@ -113,6 +116,9 @@ SIGNATURES = {
                                                ctypes.POINTER(ctypes.c_size_t)]),
     "rdseg_tune_cache_import": (ctypes.c_int, [ctypes.c_char_p]),
     "rdseg_tune_cache_clear": (ctypes.c_int, []),
+    "rdseg_solve_status": (ctypes.c_int, [ctypes.POINTER(Shape), _vp, _sz, _vp]),
+    "rdseg_set_resident_wait": (ctypes.c_int, [ctypes.c_int64]),
+    "rdseg_release": (ctypes.c_int, []),
     "rdseg_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "rdseg_last_error": (ctypes.c_char_p, []),
 }
@@ -136,7 +142,15 @@ def load():
         fn.restype = res
         fn.argtypes = args
     _lib = lib
+    # release the library's streams, events and pinned buffers while the HIP
+    # runtime is still up (interpreter exit runs before the runtime's teardown)
+    atexit.register(_release)
     return lib
+
+
+def _release():
+    if _lib is not None:
+        _lib.rdseg_release()
 
 
 def check(status):

@@ -45,7 +45,7 @@ class FitTerm(torch.autograd.Function):
         saved = ctx.saved_tensors
         z = saved[0]
         P = saved[1] if ctx.has_P else None
-        a, b, g = rdseg.fit_backward(z, ctx.c[0], ctx.c[1], grad_f.contiguous(), P)
+        a, b, g = rdseg.fit_backward(z, ctx.c[0], ctx.c[1], rdseg.as_grid_of(grad_f, z), P)
         c1, c2, gamma = ctx.params
         return None, _grad_like(a, c1), _grad_like(b, c2), _grad_like(g, gamma), None
 
@@ -67,5 +67,5 @@ class RDSolve(torch.autograd.Function):
         f, tape = ctx.saved_tensors
         lamv, theta, tau, delta, iters, ckpt_every = ctx.args
         gf, gl = rdseg.backward(f, lamv, theta, tau, delta, iters, ckpt_every, tape,
-                                grad_u.contiguous())
+                                rdseg.as_grid_of(grad_u, f))
         return gf, _grad_like(gl, ctx.lam), None, None, None, None, None, None, None

@@ -132,7 +132,7 @@ SolveWs carve_solve(void* base, const rdseg_shape& s) {
     w.c = cv.take<float>(g.plane);
     for (int k = 0; k < 3; ++k) w.st[k] = cv.take<float>(g.plane);
     w.masks = cv.take<uint64_t>(g.nt);
-    w.npix = cv.take<int64_t>(1);
+    w.npix = cv.take<int64_t>(2);   // [0] RD count, [1] status word (int32) of the last solve
     int64_t nflag = std::max<int64_t>(g.nt, g.chunks);
     w.flags = cv.take<int32_t>(nflag);
     w.offs = cv.take<int32_t>(nflag);
@@ -373,7 +373,8 @@ struct SolvePlanArgs {
     int launches_per_check = 0;              // out (with stop)
     bool resident = false;                   // try the resident form first (single image)
     const int32_t* mflags = nullptr;         // resident: queued flag per macro tile
-    int32_t* epoch = nullptr;                // resident: max_items + 1 int32 of workspace
+    int32_t* epoch = nullptr;                // resident: max_items int32 of workspace
+    int32_t* status = nullptr;               // resident: the solve's status word
     const CompWs* comp = nullptr;            // resident: small components for idle workgroups
     const int64_t* comp_npix = nullptr;      // resident: full RD count (the labelling's)
 };
@@ -480,7 +481,7 @@ rdseg_status enqueue_iterations(SolvePlanArgs& a) {
             rec.e1 = timing_event();
         }
         const int rc = launch_resident(a.ci, *a.d0, a.queue, a.n_queue, a.mflags, a.epoch,
-                                       a.epoch + a.max_items, a.max_items, L % 2, a.iters, IT,
+                                       a.status, a.max_items, L % 2, a.iters, IT,
                                        a.inner, a.theta, a.inv_theta, a.tau, a.st,
                                        timed ? rec.e0 : nullptr, a.comp, a.comp_npix);
         if (rc > 0) return RDSEG_ERR_HIP;
@@ -695,7 +696,9 @@ rdseg_status solve_impl(const float* f, rdseg_shape s, const rdseg_params* prm, 
     // tile-configuration independent part of the descriptor first
     ImgDesc d = make_desc(f, s, prm->lambda, prm->theta, prm->delta, u, v, p, w.c, w.st, u0, p0, 8, 8);
     OffTables off{nullptr, nullptr, nullptr, nullptr};
-    if (launch_tile_masks(&d, nullptr, off, 1, g.strips, w.masks, w.npix, st)) return RDSEG_ERR_HIP;
+    // the RD count and the solve's status word start at 0
+    if (launch_tile_masks(&d, nullptr, off, 1, g.strips, w.masks, w.npix, st, 2))
+        return RDSEG_ERR_HIP;
     int tuned_comps = 0, tuned_res = 0;
     if (ci < 0) {
         r = choose_cfg(*prm, s, w.npix, st, &ci, &tuned_comps, &tuned_res);
@@ -785,6 +788,7 @@ rdseg_status solve_impl(const float* f, rdseg_shape s, const rdseg_params* prm, 
     a.resident = resident;
     a.mflags = w.flags;
     a.epoch = w.epoch;
+    a.status = reinterpret_cast<int32_t*>(w.npix + 1);
     if (comps) a.npix = w.comp.npix_tile;   // timing counts the tile path's pixels
     if (comps && resident) {
         a.comp = &w.comp;
@@ -1236,6 +1240,7 @@ const char* rdseg_status_string(rdseg_status st) {
         case RDSEG_ERR_WORKSPACE: return "workspace too small";
         case RDSEG_ERR_HIP: return "HIP error";
         case RDSEG_ERR_TAPE: return "tape missing or inconsistent";
+        case RDSEG_ERR_TIMEOUT: return "a bounded on-chip wait expired";
     }
     return "unknown status";
 }
@@ -1316,6 +1321,32 @@ rdseg_status rdseg_solve(const float* f, rdseg_shape s, const rdseg_params* prm,
                          size_t ws_bytes, void* stream) {
     return solve_impl(f, s, prm, u0, p0, u, v, p, tape, ws, ws_bytes,
                       static_cast<hipStream_t>(stream), -1);
+}
+
+rdseg_status rdseg_solve_status(const rdseg_shape* s, const void* ws, size_t ws_bytes,
+                                void* stream) {
+    if (!s) return fail(RDSEG_ERR_ARG, "s is NULL");
+    rdseg_status r = check_shape(*s);
+    if (r) return r;
+    const SolveWs need = carve_solve(nullptr, *s);
+    if (!ws || ws_bytes < need.bytes)
+        return fail(RDSEG_ERR_WORKSPACE, "workspace too small: need " + std::to_string(need.bytes) + " bytes");
+    const SolveWs w = carve_solve(const_cast<void*>(ws), *s);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    int32_t word = 0;
+    if (hipMemcpyAsync(&word, w.npix + 1, sizeof(word), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return fail(RDSEG_ERR_HIP, "reading the solve's status word failed");
+    if (word != 0)
+        return fail(RDSEG_ERR_TIMEOUT,
+                    "a wait of the resident solve for a neighbouring tile expired; u, v and p "
+                    "hold NaN on the tiles that stopped");
+    return RDSEG_OK;
+}
+
+rdseg_status rdseg_set_resident_wait(int64_t ticks) {
+    set_resident_wait_ticks(ticks);
+    return RDSEG_OK;
 }
 
 rdseg_status rdseg_solve_until(const float* f, rdseg_shape s, const rdseg_params* prm,
@@ -2004,6 +2035,50 @@ rdseg_status rdseg_timing_read_form(int32_t config, int32_t form, double* kernel
     if (alg_bytes) *alg_bytes = bytes;
     if (pixel_updates) *pixel_updates = upd;
     return RDSEG_OK;
+}
+
+rdseg_status rdseg_release(void) {
+    rdseg_status r = RDSEG_OK;
+    {
+        std::lock_guard<std::mutex> lk(g_side_mu);
+        for (auto& kv : g_side) {
+            int cur = 0;
+            if (hipGetDevice(&cur) != hipSuccess || hipSetDevice(kv.first) != hipSuccess ||
+                hipStreamSynchronize(kv.second) != hipSuccess ||
+                hipStreamDestroy(kv.second) != hipSuccess)
+                r = fail(RDSEG_ERR_HIP, "releasing a side stream failed");
+            (void)hipSetDevice(cur);
+        }
+        g_side.clear();
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_timing.mu);
+        for (auto& rec : g_timing.recs) {
+            (void)hipEventSynchronize(rec.e1);
+            g_timing.pool.push_back(rec.e0);
+            g_timing.pool.push_back(rec.e1);
+        }
+        g_timing.recs.clear();
+        if (g_timing.has_open) {
+            g_timing.pool.push_back(g_timing.open.e0);
+            g_timing.pool.push_back(g_timing.open.e1);
+            g_timing.has_open = false;
+        }
+        for (hipEvent_t e : g_timing.pool)
+            if (e && hipEventDestroy(e) != hipSuccess) r = fail(RDSEG_ERR_HIP, "releasing an event failed");
+        g_timing.pool.clear();
+        if (g_timing.pinned && hipHostFree(g_timing.pinned) != hipSuccess)
+            r = fail(RDSEG_ERR_HIP, "releasing the pinned timing buffer failed");
+        g_timing.pinned = nullptr;
+        g_timing.pinned_cap = g_timing.pinned_used = 0;
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_poll_mu);
+        if (g_poll_host && hipHostFree(g_poll_host) != hipSuccess)
+            r = fail(RDSEG_ERR_HIP, "releasing the pinned polling buffer failed");
+        g_poll_host = nullptr;
+    }
+    return r;
 }
 
 rdseg_status rdseg_timing_reset(void) {

@@ -397,9 +397,10 @@ int launch_scan_ints(const int32_t* counts, int64_t n, int32_t* out, int32_t* pa
 }
 
 int launch_tile_masks(const ImgDesc* d0, const ImgDesc* descs, OffTables off, int n_img,
-                      int64_t n_strips, uint64_t* masks, int64_t* npix, hipStream_t st) {
-    hipLaunchKernelGGL(k_fill_i64, dim3(nblk(n_img, 256)), dim3(256), 0, st, npix,
-                       (int64_t)n_img, (int64_t)0);
+                      int64_t n_strips, uint64_t* masks, int64_t* npix, hipStream_t st,
+                      int64_t n_clear) {
+    const int64_t nz = n_clear > n_img ? n_clear : (int64_t)n_img;
+    hipLaunchKernelGGL(k_fill_i64, dim3(nblk(nz, 256)), dim3(256), 0, st, npix, nz, (int64_t)0);
     if (descs)
         hipLaunchKernelGGL(k_tile_masks<true>, dim3(nblk(n_strips, 4)), dim3(256), 0, st, *d0,
                            descs, off, n_img, n_strips, masks, npix);

@@ -466,9 +466,21 @@ __global__ __launch_bounds__(NT) void k_iterate(ImgDesc d0, const ImgDesc* __res
 // neighbours' counts and the workgroup has passed a barrier.  (Release and
 // acquire fences at device scope would write back and invalidate the whole
 // L2 of the XCD at every block, which costs more than a separate launch.)
-// Every wait is bounded in time: on expiry the workgroup records the failure
-// in *status, stops waiting and writes NaN for u, so a solve can never hang.
-constexpr uint64_t kResidentWaitTicks = 100000000ull;   // 1 s of the 100 MHz clock
+// This ordering rests on gfx950's memory system (device-scope atomics bypass
+// the non-coherent L2 lines; s_waitcnt 0 covers the completion of stores), not
+// on the HIP memory model alone, so the kernel is built for gfx950 only.
+//
+// Every wait is bounded in time (wait_ticks of the 100 MHz wall clock; < 0:
+// each wait gives up at once, a failure the host can force to test this
+// path).  On expiry the workgroup sets *status, publishes the epoch value -1
+// and stops: it writes NaN for u, v and p of its tile and publishes nothing
+// more.  A neighbour waiting for it sees -1 and stops the same way, so every
+// tile that would have read a frame computed from a stale ring holds NaN,
+// every other tile holds its exact result, and a solve can never hang.
+#if !defined(__gfx950__) && defined(__HIP_DEVICE_COMPILE__)
+#error "k_resident's cross-workgroup ordering is written for gfx950"
+#endif
+constexpr int32_t kEpochFailed = -1;
 
 template <int BX, int BY, int IT, int NT>
 __global__ __launch_bounds__(NT) void k_resident(ImgDesc d, const int2* __restrict__ queue,
@@ -478,7 +490,8 @@ __global__ __launch_bounds__(NT) void k_resident(ImgDesc d, const int2* __restri
                                                  int32_t* __restrict__ status, int in_buf,
                                                  int iters, int per, int inner, float theta,
                                                  float inv_theta, float tau, CompWs cw,
-                                                 const int64_t* __restrict__ cnpix, int citers) {
+                                                 const int64_t* __restrict__ cnpix, int citers,
+                                                 int64_t wait_ticks) {
     constexpr int RX = BX + 2 * IT + 1;
     constexpr int RY = BY + 2 * IT + 1;
     constexpr int RC = RX * RY;
@@ -631,15 +644,18 @@ __global__ __launch_bounds__(NT) void k_resident(ImgDesc d, const int2* __restri
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         if (t == 0) __hip_atomic_store(epoch + m, b + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (t < 9 && t != 4 && !sFail) {
+        if (t < 9 && t != 4) {
             const int nx = mx + (t % 3) - 1, ny = my + (t / 3) - 1;
             if (nx >= 0 && nx < d.mw && ny >= 0 && ny < d.mh && mflags[ny * d.mw + nx]) {
                 const int32_t* e = epoch + ny * d.mw + nx;
                 const uint64_t t0 = wall_clock64();
-                while (__hip_atomic_load(e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < b + 1) {
-                    if (wall_clock64() - t0 > kResidentWaitTicks) {
+                while (true) {
+                    const int32_t seen = __hip_atomic_load(e, __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT);
+                    if (seen >= b + 1) break;
+                    if (seen == kEpochFailed || wait_ticks < 0 ||
+                        wall_clock64() - t0 > (uint64_t)wait_ticks) {
                         sFail = 1;
-                        __hip_atomic_store(status, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         break;
                     }
                     __builtin_amdgcn_s_sleep(1);
@@ -647,6 +663,14 @@ __global__ __launch_bounds__(NT) void k_resident(ImgDesc d, const int2* __restri
             }
         }
         __syncthreads();
+        if (sFail) {   // uniform: set before the barrier, read after it
+            if (t == 0) {
+                __hip_atomic_store(status, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(epoch + m, kEpochFailed, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            }
+            break;
+        }
         // the halo ring from the neighbours' frames, as device-coherent loads
         // issued after the counts were seen
 #pragma unroll
@@ -667,9 +691,18 @@ __global__ __launch_bounds__(NT) void k_resident(ImgDesc d, const int2* __restri
         __syncthreads();
     }
     if (sFail) {
+        // the buffer the last block writes (the caller's v, p)
+        const int xf = (in_buf + nb) & 1;
+        const float nan = __builtin_nanf("");
 #pragma unroll
-        for (int j = 0; j < CPT; ++j)
-            if (fl[j] & CF_OUT) d.u[gi[j]] = __builtin_nanf("");
+        for (int j = 0; j < CPT; ++j) {
+            if (fl[j] & CF_OUT) {
+                d.u[gi[j]] = nan;
+                d.st[xf][0][gi[j]] = nan;
+                d.st[xf][1][gi[j]] = nan;
+                d.st[xf][2][gi[j]] = nan;
+            }
+        }
     }
 }
 
@@ -730,7 +763,8 @@ constexpr int kNumCfgs = sizeof(kCfgs) / sizeof(kCfgs[0]);
 std::atomic<int> g_grid_cache[kNumCfgs][3];
 
 using ResFn = void (*)(ImgDesc, const int2*, const int32_t*, const int32_t*, int32_t*, int32_t*,
-                       int, int, int, int, float, float, float, CompWs, const int64_t*, int);
+                       int, int, int, int, float, float, float, CompWs, const int64_t*, int,
+                       int64_t);
 
 struct ResEntry {
     int bx, by, it, nt;
@@ -779,6 +813,18 @@ int persistent_blocks(const void* kernel, int threads, size_t dyn_lds) {
     return per * ncu;
 }
 
+namespace {
+// 1 s of the 100 MHz wall clock per wait, unless the host set another bound
+constexpr int64_t kResidentWaitTicks = 100000000;
+std::atomic<int64_t> g_wait_ticks{kResidentWaitTicks};
+}  // namespace
+
+void set_resident_wait_ticks(int64_t ticks) {
+    g_wait_ticks.store(ticks == 0 ? kResidentWaitTicks : ticks, std::memory_order_relaxed);
+}
+
+int64_t resident_wait_ticks() { return g_wait_ticks.load(std::memory_order_relaxed); }
+
 bool resident_fits(int ci, int64_t max_items) {
     const int r = resident_entry(ci);
     if (r < 0 || max_items < 1) return false;
@@ -798,9 +844,8 @@ int launch_resident(int ci, const ImgDesc& d, const int2* queue, const int32_t* 
                     const int64_t* comp_npix) {
     const int r = resident_entry(ci);
     if (r < 0 || !resident_fits(ci, max_items)) return -1;
-    // epoch[0 .. max_items) and *status start at 0
-    if (launch_fill(reinterpret_cast<float*>(epoch), 1, (int)max_items, (int)max_items, 0.0f, st) ||
-        launch_fill(reinterpret_cast<float*>(status), 1, 1, 1, 0.0f, st))
+    // epoch[0 .. max_items) starts at 0 (*status was cleared with the RD count)
+    if (launch_fill(reinterpret_cast<float*>(epoch), 1, (int)max_items, (int)max_items, 0.0f, st))
         return 1;
     if (before) (void)hipEventRecord(before, st);
     const unsigned grid = (unsigned)(((max_items + 7) / 8) * 8);
@@ -809,8 +854,10 @@ int launch_resident(int ci, const ImgDesc& d, const int2* queue, const int32_t* 
     if (comp) cw = *comp;
     const int64_t* cnpix = comp ? comp_npix : nullptr;
     int citers = comp ? iters : 0;
+    int64_t wait = resident_wait_ticks();
     void* args[] = {&dd,    &queue, &n_queue,   &mflags, &epoch, &status, &in_buf, &iters,
-                    &per,   &inner, &theta,     &inv_theta, &tau, &cw,     &cnpix,  &citers};
+                    &per,   &inner, &theta,     &inv_theta, &tau, &cw,     &cnpix,  &citers,
+                    &wait};
     const hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kRes[r].fn),
                                                     dim3(grid), dim3(kRes[r].nt), args, 0, st);
     if (e != hipSuccess) {

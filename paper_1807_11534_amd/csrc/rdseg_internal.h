@@ -42,9 +42,11 @@ int launch_scan_ints(const int32_t* counts, int64_t n, int32_t* out, int32_t* pa
                      int32_t* total, hipStream_t st);
 
 // Dense 8x8 tile masks of every image (masks[toff[i] + ty * tw + tx]) and the
-// number of RD pixels per image (npix[i], zeroed by this launcher).
+// number of RD pixels per image (npix[i], zeroed by this launcher together
+// with the int64 slots after them up to npix[n_clear - 1]).
 int launch_tile_masks(const ImgDesc* d0, const ImgDesc* descs, OffTables off, int n_img,
-                      int64_t n_strips, uint64_t* masks, int64_t* npix, hipStream_t st);
+                      int64_t n_strips, uint64_t* masks, int64_t* npix, hipStream_t st,
+                      int64_t n_clear = 0);
 
 // Fixed-order sum of n int64 device values into *out.
 int launch_sum_i64(const int64_t* a, int n, int64_t* out, hipStream_t st);
@@ -203,8 +205,9 @@ int launch_components_restore(const ImgDesc& d, const CompWs& w, const int64_t* 
 // max_items), all fit on the chip at once; and the launch, which runs `iters`
 // outer iterations in blocks of `per` (per * inner <= cfg.it), reading buffer
 // in_buf and leaving the final state where the equivalent separate launches
-// would.  epoch: max_items int32 of workspace, status: one int32 (set to 1 if a
-// bounded wait expired, in which case u holds NaN).  Returns 0 when launched,
+// would.  epoch: max_items int32 of workspace, status: one int32, zero before
+// the launch (set to 1 if a bounded wait expired; u, v and p then hold NaN on
+// every tile that stopped).  Returns 0 when launched,
 // -1 when the resident form does not apply (nothing was enqueued), > 0 on error.
 // `before` (nullable) is recorded on st right before the resident kernel.
 // comp (nullable; labelled by launch_components_prepare with the full RD
@@ -213,6 +216,10 @@ int launch_components_restore(const ImgDesc& d, const CompWs& w, const int64_t* 
 // afterwards on st then returns at once (and does the work itself if no
 // workgroup was left over).
 bool resident_fits(int ci, int64_t max_items);
+// Bound of each wait of the resident kernel in ticks of the 100 MHz wall
+// clock: 0 restores the default (1 s), < 0 makes every wait give up at once.
+void set_resident_wait_ticks(int64_t ticks);
+int64_t resident_wait_ticks();
 int launch_resident(int ci, const ImgDesc& d, const int2* queue, const int32_t* n_queue,
                     const int32_t* mflags, int32_t* epoch, int32_t* status, int64_t max_items,
                     int in_buf, int iters, int per, int inner, float theta, float inv_theta,

@@ -139,6 +139,24 @@ def solve(f, lam, theta=THETA, tau=TAU, delta=math.inf, iters=100, u0=None, p0=N
     return u, v, p
 
 
+def solve_status(f, ws):
+    """Status of the last solve of f's shape that used workspace ws
+    (synchronises the current stream): 0, or 6 (RDSEG_ERR_TIMEOUT) when a
+    resident solve's bounded wait expired and its affected tiles hold NaN."""
+    lib = _lib.load()
+    s = shape_of(f)
+    st = lib.rdseg_solve_status(ctypes.byref(s), _vp(ws), ws.numel(), _stream())
+    if st not in (_lib.RDSEG_OK, _lib.RDSEG_ERR_TIMEOUT):
+        check(st)
+    return st
+
+
+def set_resident_wait(ticks):
+    """Bound of each resident-form wait in 100 MHz wall-clock ticks (0: the
+    default of one second; < 0: every wait gives up at once, for tests)."""
+    check(_lib.load().rdseg_set_resident_wait(int(ticks)))
+
+
 def solve_until(f, lam, theta=THETA, tau=TAU, delta=math.inf, max_iters=1000, tol=1e-2,
                 check_every=1, u0=None, p0=None, tile=None, iters_per_launch=0, out=None,
                 ws=None, poll=True, inner=1):
@@ -315,15 +333,40 @@ class BatchedSolver:
             pass
 
 
+def as_grid_of(t, like):
+    """t in the layout of the plane `like` (same shape, row pitch and unit
+    stride along x): t itself when it already is, else a copy (any strides,
+    expanded ones included)."""
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32:
+        raise TypeError("a gradient must be a float32 tensor on the GPU")
+    if tuple(t.shape) != tuple(like.shape):
+        raise ValueError(f"gradient has shape {tuple(t.shape)}, expected {tuple(like.shape)}")
+    if t.stride(1) == 1 and t.stride(0) == like.stride(0):
+        return t
+    out = _empty_like_grid(like)
+    out.copy_(t)
+    return out
+
+
 def backward(f, lam, theta, tau, delta, iters, ckpt_every, tape, grad_u, grad_v=None,
              fit=None):
     """Reverse mode of the solve that wrote `tape` (default start).
 
     fit: None or (z, P or None, c1, c2, gamma) -- the f of the solve came from
-    fit_forward with these values.  Returns (grad_f, grad_lambda) and, with fit,
-    (grad_c1, grad_c2, grad_gamma) as float64 device scalars."""
+    fit_forward with these values.  grad_u / grad_v are read with f's row
+    pitch (copied into that layout when theirs differs).  Returns (grad_f,
+    grad_lambda) and, with fit, (grad_c1, grad_c2, grad_gamma) as float64
+    device scalars."""
     lib = _lib.load()
     s = shape_of(f)
+    grad_u = as_grid_of(grad_u, f)
+    if grad_v is not None:
+        grad_v = as_grid_of(grad_v, f)
+    if fit is not None:
+        _check_plane(fit[0], "z", f.shape)
+        if fit[0].stride(0) != f.stride(0) or (fit[1] is not None and
+                                               fit[1].stride(0) != f.stride(0)):
+            raise ValueError("z and P must have the row pitch of f")
     prm = params(lam, theta, tau, delta, iters, 0, 0, 0, ckpt_every)
     nbytes = lib.rdseg_backward_workspace_size(ctypes.byref(s), ctypes.byref(prm))
     if nbytes == 0:
@@ -359,9 +402,14 @@ def fit_forward(z, c1, c2, gamma=0.0, P=None):
 
 
 def fit_backward(z, c1, c2, grad_f, P=None):
-    """(dL/dc1, dL/dc2, dL/dgamma) from dL/df, as float64 device scalars."""
+    """(dL/dc1, dL/dc2, dL/dgamma) from dL/df, as float64 device scalars.
+    grad_f is read with z's row pitch (copied into that layout when its own
+    differs)."""
     lib = _lib.load()
     s = shape_of(z)
+    grad_f = as_grid_of(grad_f, z)
+    if P is not None and P.stride(0) != z.stride(0):
+        raise ValueError("P must have the row pitch of z")
     nbytes = lib.rdseg_reduce_workspace_size(ctypes.byref(s))
     ws = torch.empty(nbytes, dtype=torch.uint8, device=z.device)
     out = torch.zeros(3, dtype=torch.float64, device=z.device)

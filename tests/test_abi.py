@@ -36,8 +36,9 @@ def test_binding_covers_header():
 
 
 def test_status_strings(lib):
-    for st in range(6):
+    for st in range(7):
         assert lib.rdseg_status_string(st)
+    assert lib.rdseg_status_string(6) == b"a bounded on-chip wait expired"
 
 
 def _solve(lib, shape, prm, f=1, u=2, v=3, p=4, ws=8, ws_bytes=1 << 40, tape=None):

@@ -209,6 +209,41 @@ def test_autograd_end_to_end(rd):
     assert abs(float(lam.grad) - lbo) <= REL * max(abs(lbo), 1e-9), (float(lam.grad), lbo)
 
 
+def test_autograd_pitched_inputs(rd):
+    """FitTerm -> RDSolve on planes with a row pitch above their width (views
+    big[:, :W]) gives the gradients of the same chain on contiguous planes:
+    incoming gradients are read with the pitch of f and z."""
+    from paper_1807_11534_amd.autograd import FitTerm, RDSolve
+    prob = synth.config5(size=512)
+    sl = boundary_crop(prob)
+    z = np.ascontiguousarray(prob.z[sl])
+    H, W = z.shape
+    target = dev(prob.mask[sl].astype(np.float32))
+    grads = []
+    for pitched in (False, True):
+        if pitched:
+            big = torch.zeros((H, W + 40), dtype=torch.float32, device="cuda")
+            big[:, :W] = dev(z)
+            zt = big[:, :W]
+            assert zt.stride(0) == W + 40
+        else:
+            zt = dev(z)
+        c1 = torch.tensor(prob.c1, dtype=torch.float64, requires_grad=True)
+        c2 = torch.tensor(prob.c2, dtype=torch.float64, requires_grad=True)
+        lam = torch.tensor(5.0, dtype=torch.float64, requires_grad=True)
+        f = FitTerm.apply(zt, c1, c2, 0.0, None)
+        delta = synth.band_delta(host(f), 0.5)
+        u = RDSolve.apply(f, lam, 0.1, 0.125, delta, 90, 30)
+        # an expanded weight makes the incoming gradient non-contiguous
+        w = torch.ones((1, W), dtype=torch.float32, device="cuda").expand(H, W)
+        loss = (w * (u - target) ** 2).sum()
+        loss.backward()
+        grads.append((float(c1.grad), float(c2.grad), float(lam.grad), host(u)))
+    for a, b in zip(grads[0][:3], grads[1][:3]):
+        assert a == b, (a, b)
+    np.testing.assert_array_equal(grads[0][3], grads[1][3])
+
+
 def test_backward_full_size_differentiation_workload(rd):
     """2048^2, 300 iterations, checkpoints every 30, delta 0.1 and 0.5 max|f|:
     deterministic, zero off the domain, finite."""

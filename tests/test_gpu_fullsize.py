@@ -106,8 +106,8 @@ def test_sweep_1024_full_forms(rd, li):
     each execution form it can pick (resident with and without the small
     components in idle workgroups, separate launches with the component or
     closed-tile kernel): all bitwise equal; sampled components against the
-    oracle (bands below 0.55 active) or invariants (denser ones, whose whole
-    grid is compared against the oracle at 1024^2 elsewhere)."""
+    oracle (bands below 0.55 active) or invariants (the denser ones: their
+    whole grid is compared with the oracle in test_dense_sweep_1024_whole_grid)."""
     prob = synth.config2(li, size=1024, iters=500)
     fd = dev(prob.f)
     for frac in synth.C2_FRACS:
@@ -127,6 +127,45 @@ def test_sweep_1024_full_forms(rd, li):
             lab, comps = sample_components(prob.f, delta, 4, li)
             check_components(u, prob.f, prob.lam, prob.theta, prob.tau, delta, prob.iters,
                              lab, comps)
+
+
+# the dense sweep cases: delta = inf at every lambda, and the one band above
+# 0.55 active (lambda 1, delta 0.5 max|f|: q = 0.80, one component spans the
+# image), each with the fraction of max|f| that sets its delta
+DENSE_CASES = [(0, math.inf), (1, math.inf), (2, math.inf), (0, 0.5)]
+# the resident form the benchmark's autotuner picks for them, and separate
+# launches of the same tile
+DENSE_FORMS = [dict(tile=(64, 64), iters_per_launch=8, components=2, resident=1),
+               dict(tile=(64, 64), iters_per_launch=4, components=2, resident=2)]
+
+
+@pytest.mark.parametrize("li,frac", DENSE_CASES)
+def test_dense_sweep_1024_whole_grid(rd, li, frac):
+    """The dense cases of the 1024^2 sweep at the full 500 iterations, in the
+    resident form and in separate launches, against the FP64 oracle on the
+    whole grid (Sec. 2.1 iteration, Sec. 3 restriction; delta = inf is the
+    unrestricted method): u, v, p within 1e-4, labels u > 0.5 differing on at
+    most 0.01 % of the pixels; the two forms bitwise equal."""
+    prob = synth.config2(li, size=1024, iters=500)
+    delta = synth.band_delta(prob.f, frac)
+    fd = dev(prob.f)
+    ws = rd.workspace(rd.shape_of(fd))
+    outs = []
+    for form in DENSE_FORMS:
+        print(f"C2 dense lam={prob.lam} frac={frac} {form}", flush=True)
+        outs.append([host(x) for x in rd.solve(fd, prob.lam, prob.theta, prob.tau, delta,
+                                               prob.iters, ws=ws, **form)])
+        assert rd.solve_status(fd, ws) == 0
+    for a, b in zip(outs[1], outs[0]):
+        np.testing.assert_array_equal(a, b)
+    u, v, p = outs[0]
+    uo, vo, po = oracle.solve(prob.f, prob.lam, prob.theta, prob.tau, delta, prob.iters)
+    assert np.abs(u - uo).max() <= U_TOL
+    assert np.abs(v - vo).max() <= U_TOL
+    assert np.abs(p - po).max() <= U_TOL
+    mism = int(((u > 0.5) != (uo > 0.5)).sum())
+    assert mism <= 1e-4 * u.size, mism
+    invariants(u, v, p, prob.f, delta)
 
 
 def test_distance_selective_4096_full(rd):

@@ -282,8 +282,10 @@ def test_resident_matches_separate_launches(rd, shape, tile, ipl, frac, iters):
         rd.set_resident(True)
         rd.timing_reset()
         rd.timing_enable(True)
+        ws = rd.workspace(rd.shape_of(ft))
         res = [host(x) for x in rd.solve(ft, 3.0, 0.1, 0.125, delta, iters, tile=tile,
-                                         iters_per_launch=ipl)]
+                                         iters_per_launch=ipl, ws=ws)]
+        assert rd.solve_status(ft, ws) == 0
         ms, n, _, _ = rd.timing_read_form(-1, 1)
     finally:
         rd.timing_enable(False)
@@ -308,6 +310,37 @@ def test_resident_matches_separate_launches(rd, shape, tile, ipl, frac, iters):
         rd.timing_reset()
     assert n_res == 0 and n_sep > 0
     for a, b in zip(par, sep):
+        np.testing.assert_array_equal(a, b)
+
+
+def test_resident_expired_wait_is_reported(rd):
+    """A resident solve whose waits for neighbouring tiles expire (forced from
+    the host: every wait gives up at once) ends normally, reports
+    RDSEG_ERR_TIMEOUT through rdseg_solve_status and leaves NaN in u, v and p
+    of the tiles that stopped (here every tile: each has a queued
+    neighbour); the next solve on the same workspace starts with a clear
+    status and gives the exact result again."""
+    from paper_1807_11534_amd import _lib
+    f = synth.smooth_field(1024, 1024, 31, noise=0.2)
+    ft = dev(f)
+    ws = rd.workspace(rd.shape_of(ft))
+    say("resident forced expiry 1024^2 64x64/8")
+    ref = [host(x) for x in rd.solve(ft, 3.0, 0.1, 0.125, math.inf, 24, tile=(64, 64),
+                                     iters_per_launch=8, resident=2, ws=ws)]
+    assert rd.solve_status(ft, ws) == 0
+    try:
+        rd.set_resident_wait(-1)
+        bad = [host(x) for x in rd.solve(ft, 3.0, 0.1, 0.125, math.inf, 24, tile=(64, 64),
+                                         iters_per_launch=8, resident=1, ws=ws)]
+        st = rd.solve_status(ft, ws)
+    finally:
+        rd.set_resident_wait(0)
+    assert st == _lib.RDSEG_ERR_TIMEOUT
+    assert np.isnan(bad[0]).all() and np.isnan(bad[1]).all() and np.isnan(bad[2]).all()
+    good = [host(x) for x in rd.solve(ft, 3.0, 0.1, 0.125, math.inf, 24, tile=(64, 64),
+                                      iters_per_launch=8, resident=1, ws=ws)]
+    assert rd.solve_status(ft, ws) == 0
+    for a, b in zip(good, ref):
         np.testing.assert_array_equal(a, b)
 
 
