@@ -652,7 +652,10 @@ __global__ __launch_bounds__(NT) void k_resident(ImgDesc d, const int2* __restri
                 while (true) {
                     const int32_t seen = __hip_atomic_load(e, __ATOMIC_RELAXED,
                                                            __HIP_MEMORY_SCOPE_AGENT);
-                    if (seen >= b + 1) break;
+                    // a host-forced failure (wait_ticks < 0) gives up before
+                    // looking at the count, so every tile with a queued
+                    // neighbour stops at its first exchange
+                    if (wait_ticks >= 0 && seen >= b + 1) break;
                     if (seen == kEpochFailed || wait_ticks < 0 ||
                         wall_clock64() - t0 > (uint64_t)wait_ticks) {
                         sFail = 1;
