@@ -205,6 +205,33 @@ rdseg_status rdseg_solve(const float* f, rdseg_shape s, const rdseg_params* prm,
 rdseg_status rdseg_solve_status(const rdseg_shape* s, const void* ws, size_t ws_bytes,
                                 void* stream);
 
+/* Allocation-free rdseg_solve, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, outputs and results (bitwise) as
+ * rdseg_solve without tape and workspace: prm->ckpt_every must be 0.  The
+ * workspace is a file-scope device array of RDSEG_NOALLOC_SCRATCH_BYTES
+ * (64 MiB) that each GPU holds from the library's load until the process
+ * ends; its device address is looked up once per device, on the first call
+ * with that device current.  The call allocates nothing (no hipMalloc /
+ * hipFree, no stream or event creation, no pinned host memory, no timing
+ * records) and runs every kernel on `stream`: the closed-tile and component
+ * kernels run before the tiles instead of beside them on a side stream, and
+ * the tiles use separate launches (not the resident form, so there is no
+ * status word to read afterwards).  Letting the library choose the tile
+ * configuration (tile_w = tile_h = iters_per_launch = 0) synchronises the
+ * stream once, as in rdseg_solve.  Every call on one GPU shares that GPU's
+ * array, which keeps the last call's contents (each call initialises what it
+ * reads): calls that overlap on one GPU, on any streams, race.
+ * Errors: as rdseg_solve; RDSEG_ERR_WORKSPACE when the image needs more than
+ * RDSEG_NOALLOC_SCRATCH_BYTES of workspace (rdseg_workspace_size(s, NULL);
+ * about 44 bytes a pixel: a 1024 x 1024 image needs 46.7 MB); RDSEG_ERR_ARG
+ * when ckpt_every != 0; RDSEG_ERR_HIP when the array's address cannot be
+ * obtained. */
+#define RDSEG_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+rdseg_status rdseg_solve_noalloc(const float* f, rdseg_shape s, const rdseg_params* prm,
+                                 const float* u0, const float* p0, float* u, float* v, float* p,
+                                 void* stream);
+
 /* Convergence-driven solve with the stopping rule of Sec. 4: stop at the
  * first iteration l, among the multiples of check_every, where
  *     max( max|u^l - u^(l-1)|, max|v^l - v^(l-1)| ) <= tol

@@ -117,6 +117,8 @@ SIGNATURES = {
     "rdseg_tune_cache_import": (ctypes.c_int, [ctypes.c_char_p]),
     "rdseg_tune_cache_clear": (ctypes.c_int, []),
     "rdseg_solve_status": (ctypes.c_int, [ctypes.POINTER(Shape), _vp, _sz, _vp]),
+    "rdseg_solve_noalloc": (ctypes.c_int, [_vp, Shape, ctypes.POINTER(Params), _vp, _vp, _vp, _vp,
+                                           _vp, _vp]),
     "rdseg_set_resident_wait": (ctypes.c_int, [ctypes.c_int64]),
     "rdseg_release": (ctypes.c_int, []),
     "rdseg_status_string": (ctypes.c_char_p, [ctypes.c_int]),

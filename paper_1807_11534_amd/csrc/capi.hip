@@ -377,6 +377,7 @@ struct SolvePlanArgs {
     int32_t* status = nullptr;               // resident: the solve's status word
     const CompWs* comp = nullptr;            // resident: small components for idle workgroups
     const int64_t* comp_npix = nullptr;      // resident: full RD count (the labelling's)
+    bool no_alloc = false;                   // take no timing records (they create events)
 };
 
 // Stopping rule of a convergence-driven solve: change slots (one uint32
@@ -473,9 +474,10 @@ rdseg_status enqueue_iterations(SolvePlanArgs& a) {
     const int L = (int)nits.size();
     a.launches = L;
     a.launches_per_check = (ce + IT - 1) / IT;
+    const bool timing_on = g_timing.on && !a.no_alloc;
     if (a.resident && !a.descs && !a.tape && !stop) {
         TimingRec rec{};
-        const bool timed = g_timing.on;
+        const bool timed = timing_on;
         if (timed) {
             rec.e0 = timing_event();
             rec.e1 = timing_event();
@@ -543,7 +545,7 @@ rdseg_status enqueue_iterations(SolvePlanArgs& a) {
         const bool run_start = (j == 0) || (a.tape && seg_start.size() > seg - 1 && seg >= 1 &&
                                             seg_start[seg - 1] == j);
         const bool run_end = (j == L - 1) || (a.tape && seg < seg_start.size() && seg_start[seg] == j + 1);
-        if (g_timing.on && run_start) {
+        if (timing_on && run_start) {
             std::lock_guard<std::mutex> lk(g_timing.mu);
             TimingRec rec{};
             rec.e0 = timing_event();
@@ -576,7 +578,7 @@ rdseg_status enqueue_iterations(SolvePlanArgs& a) {
             if (!poller->ok) return fail(RDSEG_ERR_HIP, "reading back the changes failed");
             stop_now = poller->stopped;
         }
-        if (g_timing.on) {
+        if (timing_on) {
             std::lock_guard<std::mutex> lk(g_timing.mu);
             if (g_timing.has_open) {
                 g_timing.open.nit += nits[j];
@@ -652,7 +654,7 @@ rdseg_status choose_cfg(const rdseg_params& prm, const rdseg_shape& s, const int
 rdseg_status solve_impl(const float* f, rdseg_shape s, const rdseg_params* prm, const float* u0,
                         const float* p0, float* u, float* v, float* p, float* tape, void* ws,
                         size_t ws_bytes, hipStream_t st, int forced_ci,
-                        const StopSpec* stop = nullptr) {
+                        const StopSpec* stop = nullptr, bool no_alloc = false) {
     if (!prm) return fail(RDSEG_ERR_ARG, "prm is NULL");
     rdseg_status r = check_shape(s);
     if (r) return r;
@@ -737,7 +739,9 @@ rdseg_status solve_impl(const float* f, rdseg_shape s, const rdseg_params* prm, 
     // before it on the same stream instead of beside it.
     bool resident = false;
     const int want_res = prm->resident ? prm->resident : (tuned_res ? tuned_res : 1);
-    if (want_res == 1 && g_resident_on.load() && !stop && !taped && prm->iters > 0 &&
+    // (the allocation-free form has no status word for the caller to read, so
+    // it keeps to separate launches, whose waits cannot expire)
+    if (want_res == 1 && g_resident_on.load() && !stop && !taped && !no_alloc && prm->iters > 0 &&
         resident_fits(ci, nm)) {
         hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
         resident = hipStreamIsCapturing(st, &cap) == hipSuccess && cap == hipStreamCaptureStatusNone;
@@ -750,10 +754,15 @@ rdseg_status solve_impl(const float* f, rdseg_shape s, const rdseg_params* prm, 
     };
     if (comps) {
         // resident: the idle workgroups of the resident kernel take the
-        // components, and the component kernel follows it (below)
+        // components, and the component kernel follows it (below); without
+        // allocation (no side stream, no events) it runs before the tiles
         if (!resident) {
-            r = closed_beside(st, &join, small);
-            if (r) return r;
+            if (no_alloc) {
+                if (small(st)) return RDSEG_ERR_HIP;
+            } else {
+                r = closed_beside(st, &join, small);
+                if (r) return r;
+            }
         }
     } else if (use_closed) {
         auto closed = [&](hipStream_t cs) {
@@ -761,7 +770,7 @@ rdseg_status solve_impl(const float* f, rdseg_shape s, const rdseg_params* prm, 
                                  (float)prm->theta, (float)(1.0 / prm->theta), (float)prm->tau,
                                  cs, inner);
         };
-        if (resident) {
+        if (resident || no_alloc) {
             if (closed(st)) return RDSEG_ERR_HIP;
         } else {
             r = closed_beside(st, &join, closed);
@@ -789,6 +798,7 @@ rdseg_status solve_impl(const float* f, rdseg_shape s, const rdseg_params* prm, 
     a.mflags = w.flags;
     a.epoch = w.epoch;
     a.status = reinterpret_cast<int32_t*>(w.npix + 1);
+    a.no_alloc = no_alloc;
     if (comps) a.npix = w.comp.npix_tile;   // timing counts the tile path's pixels
     if (comps && resident) {
         a.comp = &w.comp;
@@ -1321,6 +1331,57 @@ rdseg_status rdseg_solve(const float* f, rdseg_shape s, const rdseg_params* prm,
                          size_t ws_bytes, void* stream) {
     return solve_impl(f, s, prm, u0, p0, u, v, p, tape, ws, ws_bytes,
                       static_cast<hipStream_t>(stream), -1);
+}
+
+// ------------------------------------------------------------------ allocation-free solve
+// The workspace of rdseg_solve_noalloc: one array per GPU, held from the
+// library's load until the process ends.  Its name is a host-side stand-in in
+// host code; the device address comes from hipGetSymbolAddress, taken once per
+// device with that device current, and only that address is handed to kernels.
+static __device__ __align__(256) unsigned char scratch[RDSEG_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+rdseg_status scratch_of_current_device(void** out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(RDSEG_ERR_HIP, "hipGetDevice failed");
+    if (dev < 0 || dev >= kMaxDevices) return fail(RDSEG_ERR_HIP, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(RDSEG_ERR_HIP, std::string("hipGetSymbolAddress of the scratch array failed: ") +
+                                           hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return RDSEG_OK;
+}
+}  // namespace
+
+rdseg_status rdseg_solve_noalloc(const float* f, rdseg_shape s, const rdseg_params* prm,
+                                 const float* u0, const float* p0, float* u, float* v, float* p,
+                                 void* stream) {
+    if (!prm) return fail(RDSEG_ERR_ARG, "prm is NULL");
+    rdseg_status r = check_shape(s);
+    if (r) return r;
+    if (prm->ckpt_every != 0)
+        return fail(RDSEG_ERR_ARG, "rdseg_solve_noalloc writes no tape: ckpt_every must be 0");
+    const size_t need = carve_solve(nullptr, s).bytes;
+    if (need > RDSEG_NOALLOC_SCRATCH_BYTES)
+        return fail(RDSEG_ERR_WORKSPACE,
+                    "the image needs " + std::to_string(need) + " bytes of workspace, more than the " +
+                        std::to_string((size_t)RDSEG_NOALLOC_SCRATCH_BYTES) +
+                        " bytes of the allocation-free solve's scratch array (use rdseg_solve)");
+    void* ws = nullptr;
+    r = scratch_of_current_device(&ws);
+    if (r) return r;
+    return solve_impl(f, s, prm, u0, p0, u, v, p, nullptr, ws, RDSEG_NOALLOC_SCRATCH_BYTES,
+                      static_cast<hipStream_t>(stream), -1, nullptr, true);
 }
 
 rdseg_status rdseg_solve_status(const rdseg_shape* s, const void* ws, size_t ws_bytes,

@@ -277,3 +277,24 @@ def test_tune_cache_export_needs_room(lib):
     assert lib.rdseg_tune_cache_export(buf, n.value - 1, ctypes.byref(n)) == 1
     buf = ctypes.create_string_buffer(n.value)
     assert lib.rdseg_tune_cache_export(buf, n.value, ctypes.byref(n)) == 0
+
+
+def test_noalloc_validation_before_any_gpu_call(lib):
+    """rdseg_solve_noalloc rejects, on the host and before touching the GPU,
+    an image whose workspace exceeds its scratch array (RDSEG_ERR_WORKSPACE)
+    and a request for a tape (RDSEG_ERR_ARG)."""
+    from paper_1807_11534_amd._lib import Shape
+
+    def call(shape, prm):
+        return lib.rdseg_solve_noalloc(ctypes.c_void_p(8), Shape(*shape), ctypes.byref(prm),
+                                       None, None, ctypes.c_void_p(1 << 32),
+                                       ctypes.c_void_p(2 << 32), ctypes.c_void_p(3 << 32), None)
+
+    big = (2048, 2048, 2048)
+    assert lib.rdseg_workspace_size(ctypes.byref(Shape(*big)), None) > (64 << 20)
+    assert call(big, _prm()) == 3
+    assert b"scratch array" in lib.rdseg_last_error()
+    assert call((64, 64, 64), _prm(ckpt_every=5)) == 1
+    assert call((0, 64, 64), _prm()) == 2
+    # the largest benchmark image fits
+    assert lib.rdseg_workspace_size(ctypes.byref(Shape(1024, 1024, 1024)), None) <= (64 << 20)
