@@ -40,6 +40,19 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_UPDATE = 28
+# FP32 operations of one active pixel-update (FMA counted as 2; sqrt,
+# reciprocal, min and max as 1 each): divergence 3, u-step 2, v-step 3, w 2,
+# gradient 2, |g| 4, 1 / (1 + tau |g|) 3, the two p components 6
+FLOPS_PER_UPDATE = 25
+# FP32 vector peak without packed instructions (the library is built without
+# them): 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz
+FP32_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+FP32_PEAK_PACKED_TFLOPS = 157.3
+# VALU issue of the chip: each SIMD takes 4 cycles for a full-rate wave64
+# instruction and 16 for a quarter-rate one (square root, reciprocal)
+N_SIMDS = 256 * 4
+CLOCK_HZ = 2.4e9
+DEFAULT_TUNE_CACHE = os.path.join(ROOT, "paper_1807_11534_amd", "tuning", "mi355x.json")
 
 
 def parse():
@@ -53,8 +66,13 @@ def parse():
                     help="iterations per case for the oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--tune", default="auto", choices=["auto", "fixed"],
-                    help="auto: autotune each case; fixed: 64x64 tiles, 4 iterations/launch")
+    ap.add_argument("--tune", default="cache", choices=["cache", "auto", "fixed"],
+                    help="cache: the library's choice from the tuning cache file (--tune-cache); "
+                         "auto: autotune each case; fixed: 64x64 tiles, 4 iterations/launch")
+    ap.add_argument("--tune-cache", default=DEFAULT_TUNE_CACHE,
+                    help="tuning cache (rdseg.tune_cache_save text) read with --tune cache")
+    ap.add_argument("--save-tune-cache", metavar="PATH",
+                    help="write the tuning cache after the sweep's autotuning (--tune auto)")
     ap.add_argument("--extras", default="all",
                     help="comma-separated subset of the extra workloads: " + ", ".join(EXTRAS))
     ap.add_argument("--extras-only", action="store_true",
@@ -62,6 +80,17 @@ def parse():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy a MIB-sized buffer with torch (counter calibration)")
     return ap.parse_args()
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def log(msg):
@@ -96,9 +125,16 @@ def sweep_cases(torch, rdseg, synth, args, dev):
         if args.tune == "auto":
             tuned = rdseg.autotune(f, c["lam"], synth.THETA, synth.TAU, c["delta"], args.iters)
             (tile, ipl), comps, res = tuned, tuned.components, tuned.resident
+        elif args.tune == "cache":
+            # what a solve that leaves the choice to the library runs, given
+            # the cache: every run with the same file times the same launches
+            tuned = rdseg.tune_lookup(f.shape, c["q"])
+            (tile, ipl), comps, res = tuned, tuned.components, tuned.resident
         else:
             tile, ipl, comps, res = (64, 64), 4, 0, 0
         c["tile"], c["ipl"], c["comps"], c["res"] = tile, ipl, comps, res
+    if args.tune == "auto" and args.save_tune_cache:
+        rdseg.tune_cache_save(args.save_tune_cache)
     return probs, cases
 
 
@@ -315,6 +351,13 @@ def main():
     if args.extras_only:
         print(json.dumps(dict(extras=extras(torch, rdseg, synth, dev, which))), flush=True)
         return
+    if args.tune == "cache":
+        if not os.path.exists(args.tune_cache):
+            print(f"tuning cache {args.tune_cache} not found (make one with --tune auto "
+                  f"--save-tune-cache PATH)", file=sys.stderr)
+            sys.exit(2)
+        rdseg.tune_cache_clear()
+        rdseg.tune_cache_load(args.tune_cache)
     log("sweep: generating and tuning")
     probs, cases = sweep_cases(torch, rdseg, synth, args, dev)
 
@@ -383,7 +426,9 @@ def main():
     dom = max(per_cfg, key=lambda r: r["ms"])
     avg_ms = dom["ms"] / dom["launches"]
     bytes_per_launch = dom["alg_bytes"] / dom["launches"]
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    updates_per_launch = dom["updates"] / dom["launches"]
+    alg_gbs = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    achieved = FLOPS_PER_UPDATE * updates_per_launch / (avg_ms * 1e-3) / 1e12
     all_ms, all_n, all_b, _ = rdseg.timing_read(-1)
     rdseg.timing_reset()
 
@@ -403,15 +448,33 @@ def main():
         dt = time.perf_counter() - t0
         cpu = dict(value=upd / dt, unit="active pixel-updates/s", cores=1, kind="oracle",
                    sample=f"all 12 sweep cases at {args.size}^2, {args.cpu_iters} iterations each "
-                          f"(FP64, single thread), {dt:.1f} s")
+                          f"(FP64, single thread), {dt:.1f} s; the oracle sweeps the whole grid "
+                          f"every iteration (frozen pixels included), so the sparse bands are "
+                          f"charged full-grid work",
+                   cpu_model=cpu_model(), host_cpus=os.cpu_count())
 
-    # HBM bytes per launch of the dominant kernel from the counter passes
-    # (FETCH_SIZE + WRITE_SIZE, copy-calibrated) recorded under profiles/,
-    # only when they were taken from the current kernel sources
-    from paper_1807_11534_amd.profiling import recorded_traffic
-    rec = recorded_traffic(dom["kernel"], os.path.join(os.path.dirname(os.path.abspath(__file__)),
-                                                       "profiles"))
+    # HBM bytes and instruction counts per launch of the dominant kernel from
+    # the counter passes recorded under profiles/ (FETCH_SIZE + WRITE_SIZE,
+    # copy-calibrated; SQ instruction counters), only when they were taken
+    # from the current kernel sources
+    from paper_1807_11534_amd.profiling import recorded_counters, recorded_traffic
+    prof_dir = os.path.join(ROOT, "profiles")
+    rec = recorded_traffic(dom["kernel"], prof_dir)
     traffic = rec[0] if rec else None
+    sq = recorded_counters(dom["kernel"], prof_dir)
+    valu = None
+    if sq:
+        cnt, src = sq
+        insts = cnt.get("SQ_INSTS_VALU")
+        trans = cnt.get("SQ_INSTS_VALU_TRANS_F32", 0.0)
+        if insts:
+            # SIMD cycles of VALU issue: 4 per full-rate wave64 instruction,
+            # 16 per quarter-rate one, over all SIMDs for the launch's duration
+            cycles = 4.0 * (insts - trans) + 16.0 * trans
+            valu = dict(insts_per_launch=insts, trans_insts_per_launch=trans,
+                        issue_frac=cycles / (N_SIMDS * CLOCK_HZ * avg_ms * 1e-3),
+                        insts_per_update=insts * 64.0 / updates_per_launch,
+                        counters=cnt, source=src)
 
     line = dict(
         metric="active pixel-updates/s (restricted-domain sweep)",
@@ -429,12 +492,19 @@ def main():
                              f"{args.iters} iterations",
                     images=len(probs), solves_per_step=len(cases),
                     pixel_updates_per_step=updates_per_step),
-        roofline=dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
-                      frac=achieved / HBM_PEAK_GBS, traffic=traffic,
+        roofline=dict(bound="alu", achieved=achieved, peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
+                      frac=achieved / FP32_PEAK_TFLOPS, traffic=traffic,
                       traffic_source=rec[1] if rec else None,
                       kernel=dom["kernel"], launches=dom["launches"], avg_launch_ms=avg_ms,
-                      alg_bytes_per_launch=bytes_per_launch,
-                      alg_bytes_per_update=BYTES_PER_UPDATE,
+                      flops_per_update=FLOPS_PER_UPDATE, updates_per_launch=updates_per_launch,
+                      frac_of_packed_peak=achieved / FP32_PEAK_PACKED_TFLOPS,
+                      valu=valu,
+                      hbm=dict(alg_bytes_per_update=BYTES_PER_UPDATE,
+                               alg_bytes_per_launch=bytes_per_launch, alg_gbs=alg_gbs,
+                               alg_frac=alg_gbs / HBM_PEAK_GBS,
+                               traffic_gbs=(traffic / (avg_ms * 1e-3) / 1e9) if traffic else None,
+                               traffic_frac=(traffic / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
+                               if traffic else None, peak=HBM_PEAK_GBS),
                       all_iterate_launches=dict(launches=all_n, ms=all_ms,
                                                 gbs=all_b / (all_ms * 1e-3) / 1e9 if all_ms else 0.0),
                       per_config=per_cfg),

@@ -473,6 +473,17 @@ rdseg_status rdseg_set_components(int32_t on);
  * compiled is RDSEG_ERR_ARG and nothing is merged.
  * rdseg_tune_cache_clear empties the cache. */
 rdseg_status rdseg_tune_cache_export(char* buf, size_t cap, size_t* len);
+/* The configuration that a solve leaving the choice to the library uses for
+ * an image of shape s whose RD holds the fraction q in [0, 1] of its pixels:
+ * the cache entry of (size class, q bucket) when there is one (*cached = 1),
+ * else the fixed choice by band width (*cached = 0; components and resident
+ * then 0, i.e. the library's defaults).  Host only: reads the cache and, for
+ * the fixed choice, whether the resident form's tiles fit on the current
+ * device.  Any output pointer may be NULL.  RDSEG_ERR_ARG for q outside
+ * [0, 1] or NaN. */
+rdseg_status rdseg_tune_lookup(const rdseg_shape* s, double q, int32_t* tile_w, int32_t* tile_h,
+                               int32_t* iters_per_launch, int32_t* components,
+                               int32_t* resident, int32_t* cached);
 rdseg_status rdseg_tune_cache_import(const char* json);
 rdseg_status rdseg_tune_cache_clear(void);
 

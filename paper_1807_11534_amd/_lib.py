@@ -9,7 +9,8 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "librdseg.so")
+# RDSEG_LIBRARY selects another build of the same ABI (the sanitizer build)
+LIB_PATH = os.environ.get("RDSEG_LIBRARY") or os.path.join(HERE, "librdseg.so")
 
 RDSEG_OK = 0
 STATUS_NAMES = {0: "ok", 1: "invalid argument", 2: "invalid shape", 3: "workspace too small",
@@ -115,6 +116,10 @@ SIGNATURES = {
     "rdseg_tune_cache_export": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_size_t,
                                                ctypes.POINTER(ctypes.c_size_t)]),
     "rdseg_tune_cache_import": (ctypes.c_int, [ctypes.c_char_p]),
+    "rdseg_tune_lookup": (ctypes.c_int, [ctypes.POINTER(Shape), _d, ctypes.POINTER(_i32),
+                                         ctypes.POINTER(_i32), ctypes.POINTER(_i32),
+                                         ctypes.POINTER(_i32), ctypes.POINTER(_i32),
+                                         ctypes.POINTER(_i32)]),
     "rdseg_tune_cache_clear": (ctypes.c_int, []),
     "rdseg_solve_status": (ctypes.c_int, [ctypes.POINTER(Shape), _vp, _sz, _vp]),
     "rdseg_solve_noalloc": (ctypes.c_int, [_vp, Shape, ctypes.POINTER(Params), _vp, _vp, _vp, _vp,

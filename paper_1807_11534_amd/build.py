@@ -3,6 +3,12 @@
 hipcc compiles every csrc/*.hip translation unit for gfx950 only (no other
 architecture, no host fallback) and links them into one shared library with a
 C ABI (include/rdseg.h).  Packed FP32 instructions are disabled.
+
+`build(sanitize=True)` (or RDSEG_SANITIZE=1 with `python -m
+paper_1807_11534_amd.build`) builds librdseg_san.so instead: the host code
+instrumented with AddressSanitizer and UndefinedBehaviorSanitizer (device code
+unchanged), linked against clang's shared sanitizer runtime.  Load it with
+RDSEG_LIBRARY=<path> and that runtime preloaded (see `sanitizer_runtime()`).
 """
 import glob
 import os
@@ -16,6 +22,7 @@ CSRC = os.path.join(HERE, "csrc")
 INC = os.path.join(ROOT, "include")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librdseg.so")
+LIB_SAN = os.path.join(HERE, "librdseg_san.so")
 ARCH = os.environ.get("RDSEG_ARCH", "gfx950")
 
 CFLAGS = [
@@ -30,14 +37,34 @@ def _hipcc():
     return os.path.join(rocm, "bin", "hipcc")
 
 
-def build(verbose: bool = False, jobs: int = 8) -> str:
-    os.makedirs(OBJ, exist_ok=True)
+# host-only instrumentation: every -fsanitize= sits right after -Xarch_host
+SAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host",
+             "-fno-sanitize-recover=undefined"]
+
+
+def sanitizer_runtime() -> str:
+    """clang's shared AddressSanitizer runtime, to preload into a process that
+    loads librdseg_san.so."""
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    hits = sorted(glob.glob(os.path.join(rocm, "llvm", "lib", "clang", "*", "lib", "linux",
+                                         "libclang_rt.asan-x86_64.so")))
+    if not hits:
+        raise RuntimeError("clang's libclang_rt.asan-x86_64.so not found under " + rocm)
+    return hits[-1]
+
+
+def build(verbose: bool = False, jobs: int = 8, sanitize: bool = False) -> str:
+    obj_dir = OBJ + ("_san" if sanitize else "")
+    out = LIB_SAN if sanitize else LIB
+    os.makedirs(obj_dir, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
     objs = []
+    extra = SAN_FLAGS if sanitize else []
 
     def compile_one(src):
-        obj = os.path.join(OBJ, os.path.basename(src) + ".o")
-        cmd = [_hipcc()] + CFLAGS + ["-c", src, "-o", obj]
+        obj = os.path.join(obj_dir, os.path.basename(src) + ".o")
+        cmd = [_hipcc()] + CFLAGS + extra + ["-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         res = subprocess.run(cmd, capture_output=True, text=True)
@@ -49,13 +76,16 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
 
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(compile_one, srcs))
-    cmd = [_hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", LIB + ".tmp"] + objs
+    link = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-shared-libsan"] if sanitize else []
+    cmd = [_hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC"] + link + \
+        ["-o", out + ".tmp"] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(out + ".tmp", out)
+    return out
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    print(build(verbose=True, sanitize=os.environ.get("RDSEG_SANITIZE") == "1"))

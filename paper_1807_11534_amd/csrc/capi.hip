@@ -2035,6 +2035,35 @@ rdseg_status rdseg_tune_cache_export(char* buf, size_t cap, size_t* len) {
     return RDSEG_OK;
 }
 
+rdseg_status rdseg_tune_lookup(const rdseg_shape* s, double q, int32_t* tile_w, int32_t* tile_h,
+                               int32_t* iters_per_launch, int32_t* components,
+                               int32_t* resident, int32_t* cached) {
+    if (!s) return fail(RDSEG_ERR_ARG, "s is NULL");
+    rdseg_status r = check_shape(*s);
+    if (r) return r;
+    if (!(q >= 0.0 && q <= 1.0)) return fail(RDSEG_ERR_ARG, "q must lie in [0, 1]");
+    int ci = -1, cm = 0, rk = 0, hit = 0;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(TuneKey{size_class(*s), q_bucket(q)});
+        if (it != g_tune.end()) {
+            ci = it->second.ci;
+            cm = it->second.comps;
+            rk = it->second.resident;
+            hit = 1;
+        }
+    }
+    if (ci < 0) ci = heuristic_cfg(*s, q);
+    const TileCfg c = config_at(ci);
+    if (tile_w) *tile_w = c.bx;
+    if (tile_h) *tile_h = c.by;
+    if (iters_per_launch) *iters_per_launch = c.it;
+    if (components) *components = cm;
+    if (resident) *resident = rk;
+    if (cached) *cached = hit;
+    return RDSEG_OK;
+}
+
 rdseg_status rdseg_tune_cache_import(const char* json) {
     if (!json) return fail(RDSEG_ERR_ARG, "json is NULL");
     std::vector<std::pair<TuneKey, TuneVal>> entries;

@@ -4,6 +4,7 @@
         [--kernel SUBSTRING] [--copy-mib N] [--bench-json B.json] [--traced-json T.out]
         [--fetch-json F.out] [--write-json W.out]
     python -m paper_1807_11534_amd.profiling --combine PART.md [PART.md ...]
+    python -m paper_1807_11534_amd.profiling --sq S.db --sq-json S.out
 
 --trace    database of `rocprofv3 --kernel-trace --stats`
 --fetch    database of `rocprofv3 --pmc FETCH_SIZE`   (KiB per dispatch)
@@ -16,6 +17,9 @@
            the kernel are the launches its HIP events timed
 --fetch-json, --write-json  the same for the two counter runs (their roofline
            pass gives the dispatches averaged)
+--sq, --sq-json  database and benchmark output of a run of instruction
+           counters (SQ_INSTS_VALU, ...): their per-launch averages over the
+           roofline pass, as the record bench.py reads for roofline.valu
 Prints a short markdown report: per-kernel duration table, and for the kernel
 matching --kernel its average duration, calibrated HBM bytes per launch and,
 with --bench-json, the benchmark's live figures beside them.  Each counter
@@ -56,6 +60,24 @@ def recorded_traffic(kernel, profiles_dir):
         d = re.search(r"^traffic_source_digest: ([0-9a-f]+)$", text, re.M)
         if k and b and d and k.group(1).strip() == kernel and d.group(1) == want:
             return float(b.group(1)), os.path.basename(path)
+    return None
+
+
+def recorded_counters(kernel, profiles_dir):
+    """Instruction-counter averages per launch of `kernel` ({counter: value})
+    recorded in a summary under profiles_dir, or None when none was taken
+    from the current kernel sources."""
+    want = kernel_source_digest()
+    for path in sorted(glob.glob(os.path.join(profiles_dir, "*.md"))):
+        text = open(path).read()
+        k = re.search(r"^counters_kernel: (.+)$", text, re.M)
+        d = re.search(r"^counters_source_digest: ([0-9a-f]+)$", text, re.M)
+        if not (k and d and k.group(1).strip() == kernel and d.group(1) == want):
+            continue
+        vals = {c: float(v) for c, v in
+                re.findall(r"^counter_per_launch: (\S+) ([0-9.eE+-]+)$", text, re.M)}
+        if vals:
+            return vals, os.path.basename(path)
     return None
 
 
@@ -113,11 +135,20 @@ def last_counter_values(db, counter, substring, n):
     if key is None:
         con.close()
         return None
-    rows = con.execute(f'select value from counters_collection where counter_name = ? and '
-                       f'kernel_name like ? order by "{key}"',
+    # one value per dispatch (rows split by hardware dimension are summed)
+    group = f'group by "{key}" ' if key in ("dispatch_id", "correlation_id") else ""
+    rows = con.execute(f'select sum(value) from counters_collection where counter_name = ? and '
+                       f'kernel_name like ? {group}order by "{key}"',
                        (counter, "%" + substring + "%")).fetchall()
     con.close()
     return [r[0] for r in rows[-n:]]
+
+
+def counters_in(db):
+    con = sqlite3.connect(db)
+    rows = con.execute("select distinct counter_name from counters_collection").fetchall()
+    con.close()
+    return sorted(r[0] for r in rows)
 
 
 def copy_reading(db, counter):
@@ -147,11 +178,17 @@ def main():
     ap.add_argument("--traced-json", help="benchmark output of the traced run itself")
     ap.add_argument("--fetch-json", help="benchmark output of the FETCH_SIZE run")
     ap.add_argument("--write-json", help="benchmark output of the WRITE_SIZE run")
+    ap.add_argument("--sq", help="database of a `rocprofv3 --pmc` run of instruction "
+                    "counters (SQ_*, GRBM_*): per-launch averages over the roofline pass")
+    ap.add_argument("--sq-json", help="benchmark output of the --sq run")
     ap.add_argument("--top", type=int, default=12)
     a = ap.parse_args()
 
     if a.combine:
         combine(a.combine)
+        return
+    if a.sq:
+        sq_report(a)
         return
     if not a.kernel:
         src = a.traced_json or a.bench_json or a.fetch_json or a.write_json
@@ -234,6 +271,35 @@ def main():
         print(f"traffic_bytes_per_launch: {total:.0f}")
         print(f"traffic_source_digest: {kernel_source_digest()}")
         print("```")
+
+
+def sq_report(a):
+    """Per-launch averages of every counter in an instruction-counter run, over
+    the benchmark's roofline pass (the last `launches` dispatches of its
+    dominant kernel), as a machine-readable record."""
+    lines = [l for l in open(a.sq_json).read().splitlines() if l.strip().startswith("{")]
+    r = json.loads(lines[-1])["roofline"]
+    kname = r["kernel"]
+    sub = a.kernel or kname.replace(",", ", ").rstrip(">")
+    print(f"benchmark roofline pass: {r['launches']} launches of {kname}, HIP-event average "
+          f"{r['avg_launch_ms'] * 1e3:.3f} us, {r['updates_per_launch']:.6g} active pixel-updates "
+          f"per launch\n")
+    print("| counter | per launch (average over the roofline pass) |")
+    print("|---|---:|")
+    out = {}
+    for c in counters_in(a.sq):
+        vals = last_counter_values(a.sq, c, sub, r["launches"])
+        if not vals:
+            continue
+        out[c] = sum(vals) / len(vals)
+        print(f"| {c} | {out[c]:.6g} |")
+    print("\nmachine-readable record (read by bench.py for roofline.valu):\n")
+    print("```")
+    print(f"counters_kernel: {kname}")
+    for c, v in out.items():
+        print(f"counter_per_launch: {c} {v:.6g}")
+    print(f"counters_source_digest: {kernel_source_digest()}")
+    print("```")
 
 
 def record_name(bench, name):

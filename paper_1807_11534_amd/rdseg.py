@@ -516,6 +516,21 @@ def tune_cache_import(text):
     check(_lib.load().rdseg_tune_cache_import(text.encode()))
 
 
+def tune_lookup(shape, q):
+    """The configuration a library-chosen solve uses for an image of `shape`
+    ((H, W) or a Shape) whose RD holds the fraction q of its pixels: Tuned
+    ((tile_w, tile_h), iters_per_launch) with `.components` / `.resident`
+    (0 = the library's default) and `.cached` (whether it came from the
+    tuning cache)."""
+    lib = _lib.load()
+    s = shape if isinstance(shape, Shape) else Shape(int(shape[0]), int(shape[1]), int(shape[1]))
+    v = [ctypes.c_int32(0) for _ in range(6)]
+    check(lib.rdseg_tune_lookup(ctypes.byref(s), float(q), *[ctypes.byref(x) for x in v]))
+    t = Tuned((v[0].value, v[1].value), v[2].value, v[3].value, v[4].value)
+    t.cached = bool(v[5].value)
+    return t
+
+
 def tune_cache_clear():
     check(_lib.load().rdseg_tune_cache_clear())
 

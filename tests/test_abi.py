@@ -298,3 +298,31 @@ def test_noalloc_validation_before_any_gpu_call(lib):
     assert call((0, 64, 64), _prm()) == 2
     # the largest benchmark image fits
     assert lib.rdseg_workspace_size(ctypes.byref(Shape(1024, 1024, 1024)), None) <= (64 << 20)
+
+
+def test_tune_lookup_reads_the_cache():
+    """rdseg_tune_lookup returns the cache entry of (size class, q bucket) for
+    a shape and active fraction, and reports when it has none (host only)."""
+    import json
+
+    from paper_1807_11534_amd import rdseg
+    rdseg.tune_cache_clear()
+    entries = [
+        {"size_class": 4, "q_bucket": 3, "tile_w": 32, "tile_h": 32, "iters_per_launch": 8,
+         "components": 1, "resident": 2},
+        {"size_class": 4, "q_bucket": 0, "tile_w": 8, "tile_h": 8, "iters_per_launch": 32,
+         "components": 2, "resident": 1},
+    ]
+    rdseg.tune_cache_import(json.dumps({"version": 1, "entries": entries}))
+    # 1024^2 is size class 4; q = 0.42 lies in bucket 3 ([0.2, 0.5)), 0.004 in bucket 0
+    t = rdseg.tune_lookup((1024, 1024), 0.42)
+    assert (t, t.components, t.resident, t.cached) == (((32, 32), 8), 1, 2, True)
+    t = rdseg.tune_lookup((1024, 1024), 0.004)
+    assert (t, t.components, t.resident, t.cached) == (((8, 8), 32), 2, 1, True)
+    t = rdseg.tune_lookup((1024, 1024), 0.03)   # bucket 1: no entry, the fixed choice
+    assert not t.cached and (t.components, t.resident) == (0, 0)
+    assert t == ((16, 16), 8)
+    from paper_1807_11534_amd._lib import RdsegError
+    with pytest.raises(RdsegError):
+        rdseg.tune_lookup((1024, 1024), 1.5)
+    rdseg.tune_cache_clear()

@@ -37,3 +37,20 @@ def test_combine_sums_fetch_and_write(tmp_path):
                          check=True).stdout
     (tmp_path / "rec.md").write_text(out)
     assert profiling.recorded_traffic(KERNEL, str(tmp_path)) == (1000.0, "rec.md")
+
+
+def test_counter_record_needs_matching_kernel_and_sources(tmp_path):
+    cur = profiling.kernel_source_digest()
+
+    def rec(kernel, digest, vals):
+        body = "".join(f"counter_per_launch: {c} {v}\n" for c, v in vals.items())
+        return f"```\ncounters_kernel: {kernel}\n{body}counters_source_digest: {digest}\n```\n"
+
+    (tmp_path / "a_stale.md").write_text(rec(KERNEL, "0" * 16, {"SQ_INSTS_VALU": 5}))
+    assert profiling.recorded_counters(KERNEL, str(tmp_path)) is None
+    (tmp_path / "b_other.md").write_text(rec("k_iterate<8,8,32,512>", cur, {"SQ_INSTS_VALU": 6}))
+    assert profiling.recorded_counters(KERNEL, str(tmp_path)) is None
+    (tmp_path / "c_cur.md").write_text(rec(KERNEL, cur, {"SQ_INSTS_VALU": 7.5e8,
+                                                         "SQ_INSTS_LDS": 2e8}))
+    assert profiling.recorded_counters(KERNEL, str(tmp_path)) == (
+        {"SQ_INSTS_VALU": 7.5e8, "SQ_INSTS_LDS": 2e8}, "c_cur.md")
