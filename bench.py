@@ -79,6 +79,10 @@ def parse():
                     help="run only the selected extra workloads and print their JSON")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy a MIB-sized buffer with torch (counter calibration)")
+    ap.add_argument("--maps-at-exit", metavar="PATH",
+                    help="write /proc/self/maps to PATH at interpreter exit (attributes the "
+                         "addresses of a crash in the process's exit handlers to the mapped "
+                         "files)")
     return ap.parse_args()
 
 
@@ -329,6 +333,13 @@ def main():
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(pass --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if args.maps_at_exit:
+        import atexit
+
+        def dump_maps(path=args.maps_at_exit):
+            with open("/proc/self/maps") as src, open(path, "w") as dst:
+                dst.write(src.read())
+        atexit.register(dump_maps)   # registered first: runs after the binding's release
     import torch
 
     import synth

@@ -223,14 +223,18 @@ def main():
         print(f"\nthe benchmark's roofline pass = the last {len(durs)} of {total} dispatches: "
               f"rocprof average {mean:.3f} us; the same run's HIP-event average "
               f"{r['avg_launch_ms'] * 1e3:.3f} us (ratio {r['avg_launch_ms'] * 1e3 / mean:.4f})")
-        print(f"algorithmic bytes per launch {r['alg_bytes_per_launch']:.4g} -> "
-              f"{r['alg_bytes_per_launch'] / (mean * 1e-6) / 1e9:.1f} GB/s at the rocprof average")
+        flops = r["flops_per_update"] * r["updates_per_launch"]
+        print(f"algorithmic FP32 operations per launch {flops:.4g} "
+              f"({r['flops_per_update']} per active pixel-update x {r['updates_per_launch']:.6g}) -> "
+              f"{flops / (mean * 1e-6) / 1e12:.2f} TFLOP/s at the rocprof average "
+              f"({flops / (mean * 1e-6) / 1e12 / r['peak']:.4f} of the {r['peak']:.1f} TFLOP/s peak); "
+              f"unblocked-equivalent bytes per launch {r['hbm']['alg_bytes_per_launch']:.4g}")
     if a.bench_json:
         bench = bench_line(a.bench_json)
         r = bench["roofline"]
         print(f"unprofiled benchmark (HIP events): average {r['avg_launch_ms'] * 1e3:.3f} us over "
-              f"{r['launches']} launches, algorithmic bytes per launch {r['alg_bytes_per_launch']:.4g}, "
-              f"achieved {r['achieved']:.1f} GB/s ({r['frac']:.3f} of peak)")
+              f"{r['launches']} launches, achieved {r['achieved']:.2f} {r['unit']} "
+              f"({r['frac']:.4f} of peak)")
     total = 0.0
     n_counters = 0
     if a.fetch or a.write:
