@@ -79,6 +79,10 @@ def parse():
                     help="run only the selected extra workloads and print their JSON")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy a MIB-sized buffer with torch (counter calibration)")
+    ap.add_argument("--roofline-kernel", metavar="NAME",
+                    help="report the roofline of this iteration-kernel instantiation (as named "
+                         "in roofline.kernel) instead of the one with the most time in the step "
+                         "(counter runs, where the profiler's per-dispatch cost reorders them)")
     ap.add_argument("--maps-at-exit", metavar="PATH",
                     help="write /proc/self/maps to PATH at interpreter exit (attributes the "
                          "addresses of a crash in the process's exit handlers to the mapped "
@@ -434,7 +438,15 @@ def main():
             if nl:
                 per_cfg.append(dict(config=ci, kernel=f"{name}<{tw},{th},{it},{nt}>", ms=ms,
                                     launches=nl, alg_bytes=by, updates=upd))
-    dom = max(per_cfg, key=lambda r: r["ms"])
+    if args.roofline_kernel:
+        named = [r for r in per_cfg if r["kernel"] == args.roofline_kernel]
+        if not named:
+            print(f"--roofline-kernel {args.roofline_kernel}: not launched in the step "
+                  f"(launched: {[r['kernel'] for r in per_cfg]})", file=sys.stderr)
+            sys.exit(2)
+        dom = named[0]
+    else:
+        dom = max(per_cfg, key=lambda r: r["ms"])
     avg_ms = dom["ms"] / dom["launches"]
     bytes_per_launch = dom["alg_bytes"] / dom["launches"]
     updates_per_launch = dom["updates"] / dom["launches"]
