@@ -51,6 +51,7 @@ FP32_PEAK_PACKED_TFLOPS = 157.3
 # VALU issue of the chip: each SIMD takes 4 cycles for a full-rate wave64
 # instruction and 16 for a quarter-rate one (square root, reciprocal)
 N_SIMDS = 256 * 4
+N_XCDS = 8
 CLOCK_HZ = 2.4e9
 DEFAULT_TUNE_CACHE = os.path.join(ROOT, "paper_1807_11534_amd", "tuning", "mi355x.json")
 
@@ -492,12 +493,19 @@ def main():
         trans = cnt.get("SQ_INSTS_VALU_TRANS_F32", 0.0)
         if insts:
             # SIMD cycles of VALU issue: 4 per full-rate wave64 instruction,
-            # 16 per quarter-rate one, over all SIMDs for the launch's duration
+            # 16 per quarter-rate one, over all SIMDs for this run's launch
+            # duration at the nominal clock
             cycles = 4.0 * (insts - trans) + 16.0 * trans
             valu = dict(insts_per_launch=insts, trans_insts_per_launch=trans,
                         issue_frac=cycles / (N_SIMDS * CLOCK_HZ * avg_ms * 1e-3),
-                        insts_per_update=insts * 64.0 / updates_per_launch,
+                        lane_insts_per_update=insts * 64.0 / updates_per_launch,
                         counters=cnt, source=src)
+            act, gui = cnt.get("SQ_ACTIVE_INST_VALU"), cnt.get("GRBM_GUI_ACTIVE")
+            if act and gui:
+                # within the counter run: VALU-busy SIMD cycles (the counter is
+                # in quad-cycles) over all SIMDs for the dispatch's GPU cycles
+                # (GRBM_GUI_ACTIVE sums the 8 XCDs)
+                valu["busy_frac"] = 4.0 * act / (N_SIMDS * gui / N_XCDS)
 
     line = dict(
         metric="active pixel-updates/s (restricted-domain sweep)",
