@@ -698,8 +698,9 @@ rdseg_status solve_impl(const float* f, rdseg_shape s, const rdseg_params* prm, 
     // tile-configuration independent part of the descriptor first
     ImgDesc d = make_desc(f, s, prm->lambda, prm->theta, prm->delta, u, v, p, w.c, w.st, u0, p0, 8, 8);
     OffTables off{nullptr, nullptr, nullptr, nullptr};
-    // the RD count and the solve's status word start at 0
-    if (launch_tile_masks(&d, nullptr, off, 1, g.strips, w.masks, w.npix, st, 2))
+    // initial state and tile masks in one pass; the RD count and the solve's
+    // status word start at 0
+    if (launch_prepare(&d, nullptr, off, 1, g.strips, w.masks, w.npix, st, 2))
         return RDSEG_ERR_HIP;
     int tuned_comps = 0, tuned_res = 0;
     if (ci < 0) {
@@ -709,7 +710,6 @@ rdseg_status solve_impl(const float* f, rdseg_shape s, const rdseg_params* prm, 
     }
     TileCfg cfg = config_at(ci);
     d = make_desc(f, s, prm->lambda, prm->theta, prm->delta, u, v, p, w.c, w.st, u0, p0, cfg.bx, cfg.by);
-    if (launch_init(&d, nullptr, off, 1, s.H, st)) return RDSEG_ERR_HIP;
     int64_t nm = macro_count(s, cfg.bx, cfg.by);
     // Closed tiles run every iteration in one launch; a solve that writes a
     // checkpoint tape sends every tile through the blocked kernel instead.
@@ -947,8 +947,7 @@ rdseg_status enqueue_batch(const BatchLayout& L, int n, int ci, int iters, doubl
     TileCfg cfg = config_at(ci);
     OffTables off = tables_of(L, n);
     const ImgDesc* d0 = &L.descs[0];   // unused by the batched kernels
-    if (launch_init(d0, L.d_descs, off, n, L.rows, st)) return RDSEG_ERR_HIP;
-    if (launch_tile_masks(d0, L.d_descs, off, n, L.strips, L.masks, L.npix, st)) return RDSEG_ERR_HIP;
+    if (launch_prepare(d0, L.d_descs, off, n, L.strips, L.masks, L.npix, st)) return RDSEG_ERR_HIP;
     if (launch_sum_i64(L.npix, n, L.npix_total, st)) return RDSEG_ERR_HIP;
     QueueScratch qs{L.cflags, L.tstate, L.flags, L.offs, L.part};
     const bool use_closed = iters > 0;

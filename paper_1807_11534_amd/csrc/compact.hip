@@ -184,6 +184,107 @@ __global__ __launch_bounds__(256) void k_tile_masks(ImgDesc d0, const ImgDesc* _
     }
 }
 
+// ---------------------------------------------------------------- prepare
+// The initial state (u0 = H(-f) or the caller's start on RD, v0 = clamp(u0 -
+// theta lambda f), p0 = 0 or the caller's; frozen pixels u = v = H(-f), p = 0)
+// and the 8x8 tile masks of RD in one pass over f.  One wave per 8-row x
+// 64-column strip as in k_tile_masks; each wave takes a contiguous run of
+// `per_wave` strips, so a batch looks up the image of its first strip once
+// and then walks forward (a lookup per strip is a chain of dependent loads
+// that left the batched passes latency bound).  Writes c, u and the caller's
+// state buffer (v, p_x, p_y) on every pixel, the workspace's state buffer
+// only on RD pixels: no kernel reads a frozen pixel's state from it.  With
+// d.u == NULL only c and the masks are written.
+template <bool BATCHED>
+__global__ __launch_bounds__(256) void k_prepare(ImgDesc d0, const ImgDesc* __restrict__ descs,
+                                                 OffTables off, int n_img, int64_t n_strips,
+                                                 int64_t per_wave, uint64_t* __restrict__ masks,
+                                                 int64_t* __restrict__ npix) {
+    __shared__ unsigned long long sCnt[4];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int64_t s0 = ((int64_t)blockIdx.x * 4 + wv) * per_wave;
+    const int64_t s1 = s0 + per_wave < n_strips ? s0 + per_wave : n_strips;
+    unsigned long long cnt = 0;   // RD pixels of the current image (this wave)
+    int img = 0;
+    int64_t img_lo = 0, img_hi = n_strips;
+    if (BATCHED && s0 < s1) {
+        img = find_image(off.soff, n_img, s0);
+        img_lo = off.soff[img];
+        img_hi = off.soff[img + 1];
+    }
+    for (int64_t s = s0; s < s1; ++s) {
+        if (BATCHED) {
+            while (s >= img_hi) {
+                if (lane == 0 && cnt) atomicAdd((unsigned long long*)&npix[img], cnt);
+                cnt = 0;
+                ++img;
+                img_lo = img_hi;
+                img_hi = off.soff[img + 1];
+            }
+        }
+        const ImgDesc& d = BATCHED ? descs[img] : d0;
+        const int64_t ls = s - img_lo;
+        const int sw = (d.tw + 7) >> 3;
+        const int ty = (int)(ls / sw);
+        const int sx = (int)(ls - (int64_t)ty * sw);
+        const int x = sx * 64 + lane;
+        const int W = d.W, H = d.H;
+        uint64_t b[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int y = ty * 8 + r;
+            bool a = false;
+            if (x < W && y < H) {
+                const int64_t g = (int64_t)y * d.ld + x;
+                const float fv = d.f[g];
+                a = fabs((double)fv) < d.delta;
+                const float c = c_of(fv, d.delta, d.tl);
+                const bool act = c_active(c);
+                const float h = (fv < 0.0f) ? 1.0f : 0.0f;
+                d.c[g] = c;
+                if (d.u) {
+                    const float u0 = act ? (d.u0 ? d.u0[g] : h) : h;
+                    const float v0 = v_step(u0, c);
+                    const float px = (act && x < W - 1 && d.p0x) ? d.p0x[g] : 0.0f;
+                    const float py = (act && y < H - 1 && d.p0y) ? d.p0y[g] : 0.0f;
+                    d.u[g] = u0;
+                    d.st[0][0][g] = v0;
+                    d.st[0][1][g] = px;
+                    d.st[0][2][g] = py;
+                    if (act) {
+                        d.st[1][0][g] = v0;
+                        d.st[1][1][g] = px;
+                        d.st[1][2][g] = py;
+                    }
+                }
+            }
+            b[r] = __ballot(a);
+            cnt += (unsigned long long)__popcll(b[r]);
+        }
+        if (lane < 8) {
+            const int tx = sx * 8 + lane;
+            if (tx < d.tw) {
+                uint64_t m = 0;
+#pragma unroll
+                for (int r = 0; r < 8; ++r) m |= ((b[r] >> (8 * lane)) & 0xFFull) << (8 * r);
+                masks[d.toff + (int64_t)ty * d.tw + tx] = m;
+            }
+        }
+    }
+    if (BATCHED) {
+        if (lane == 0 && cnt) atomicAdd((unsigned long long*)&npix[img], cnt);
+    } else {
+        // one atomic per workgroup on the single counter
+        if (lane == 0) sCnt[wv] = cnt;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const unsigned long long tot = sCnt[0] + sCnt[1] + sCnt[2] + sCnt[3];
+            if (tot) atomicAdd((unsigned long long*)npix, tot);
+        }
+    }
+}
+
 __global__ void k_mask_flags(const uint64_t* __restrict__ masks, int64_t n,
                              int32_t* __restrict__ flags) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -299,6 +400,59 @@ __global__ __launch_bounds__(256) void k_lists(ImgDesc d0, const ImgDesc* __rest
     if (use_closed && mine) cflags[T] = (!any_open && mk && !open) ? 1 : 0;
 }
 
+// Batched form of k_lists: each wave takes a contiguous run of macro tiles and
+// covers 64 / (bx8 * by8) of them per step, one lane per 8x8 tile; a lane
+// finds its image by walking forward from the image of the step's first
+// macro tile (the wave looks the first one up once), instead of a lookup per
+// macro tile.
+__global__ __launch_bounds__(256) void k_lists_batched(const ImgDesc* __restrict__ descs,
+                                                       OffTables off, int n_img, int64_t n_macro,
+                                                       int64_t per_wave, int bx8, int by8,
+                                                       const uint64_t* __restrict__ masks,
+                                                       int use_closed,
+                                                       int32_t* __restrict__ mflags,
+                                                       int32_t* __restrict__ cflags) {
+    const int lane = threadIdx.x & 63;
+    const int tpm = bx8 * by8;   // 8x8 tiles per macro tile (<= 64)
+    const int mpi = 64 / tpm;    // macro tiles per step
+    const int64_t m0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * per_wave;
+    const int64_t m1 = m0 + per_wave < n_macro ? m0 + per_wave : n_macro;
+    if (m0 >= m1) return;   // uniform per wave
+    int img = find_image(off.moff, n_img, m0);
+    const int k = lane / tpm;   // macro tile of this lane within the step
+    const int j = lane - k * tpm;
+    for (int64_t base = m0; base < m1; base += mpi) {
+        const int64_t m = base + k;
+        const bool valid = k < mpi && m < m1;
+        int im = img;
+        if (valid)
+            while (m >= off.moff[im + 1]) ++im;
+        bool mine = false, open = false;
+        uint64_t mk = 0;
+        int64_t T = 0;
+        if (valid) {
+            const ImgDesc& d = descs[im];
+            const int64_t lm = m - off.moff[im];
+            const int my = (int)(lm / d.mw), mx = (int)(lm - (int64_t)my * d.mw);
+            const int tx = mx * bx8 + j % bx8, ty = my * by8 + j / bx8;
+            mine = tx < d.tw && ty < d.th;
+            T = d.toff + (int64_t)ty * d.tw + tx;
+            if (mine) {
+                mk = masks[T];
+                if (mk) open = !use_closed || tile_touches_neighbour(masks, T, tx, ty, d.tw, d.th, mk);
+            }
+        }
+        const uint64_t bal = __ballot(open);
+        const uint64_t grp = (tpm == 64) ? ~0ull : (((1ull << tpm) - 1ull) << (k * tpm));
+        const bool any_open = (bal & grp) != 0ull;
+        if (valid && j == 0) mflags[m] = any_open ? 1 : 0;
+        if (use_closed && mine) cflags[T] = (!any_open && mk && !open) ? 1 : 0;
+        // the image of the step's last macro tile starts the next step
+        const int64_t mlast = (base + mpi < m1 ? base + mpi : m1) - 1;
+        while (mlast >= off.moff[img + 1]) ++img;
+    }
+}
+
 // Exclusive scans of up to two int32 arrays of at most SMALL_N elements, one
 // 1024-thread block per array (the arrays are 16-byte aligned workspace).
 constexpr int SMALL_T = 1024;
@@ -411,6 +565,25 @@ int launch_tile_masks(const ImgDesc* d0, const ImgDesc* descs, OffTables off, in
     return 0;
 }
 
+int launch_prepare(const ImgDesc* d0, const ImgDesc* descs, OffTables off, int n_img,
+                   int64_t n_strips, uint64_t* masks, int64_t* npix, hipStream_t st,
+                   int64_t n_clear) {
+    const int64_t nz = n_clear > n_img ? n_clear : (int64_t)n_img;
+    hipLaunchKernelGGL(k_fill_i64, dim3(nblk(nz, 256)), dim3(256), 0, st, npix, nz, (int64_t)0);
+    // 2048 workgroups of 4 waves (8 per SIMD), or fewer for small images
+    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(2048, nblk(n_strips, 4)));
+    const int64_t waves = grid * 4;
+    const int64_t per_wave = (n_strips + waves - 1) / waves;
+    if (descs)
+        hipLaunchKernelGGL(k_prepare<true>, dim3((unsigned)grid), dim3(256), 0, st, *d0, descs,
+                           off, n_img, n_strips, per_wave, masks, npix);
+    else
+        hipLaunchKernelGGL(k_prepare<false>, dim3((unsigned)grid), dim3(256), 0, st, *d0, descs,
+                           off, n_img, n_strips, per_wave, masks, npix);
+    RDSEG_HIP_CHECK(hipGetLastError());
+    return 0;
+}
+
 int launch_sum_i64(const int64_t* a, int n, int64_t* out, hipStream_t st) {
     hipLaunchKernelGGL(k_sum_i64, dim3(1), dim3(256), 0, st, a, n, out);
     RDSEG_HIP_CHECK(hipGetLastError());
@@ -450,11 +623,13 @@ int launch_macro_queue(const ImgDesc* d0, const ImgDesc* descs, OffTables off, i
                        const QueueScratch& q, int2* queue, int32_t* n_queue, int64_t n_tiles,
                        int2* cqueue, int32_t* n_closed, hipStream_t st) {
     const bool use_closed = cqueue != nullptr;
-    if (descs)
-        hipLaunchKernelGGL(k_lists<true>, dim3(nblk(n_macro, 4)), dim3(256), 0, st, *d0, descs,
-                           off, n_img, n_macro, bx / 8, by / 8, masks, use_closed ? 1 : 0,
+    if (descs) {
+        const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(2048, nblk(n_macro, 4)));
+        const int64_t per_wave = (n_macro + grid * 4 - 1) / (grid * 4);
+        hipLaunchKernelGGL(k_lists_batched, dim3((unsigned)grid), dim3(256), 0, st, descs, off,
+                           n_img, n_macro, per_wave, bx / 8, by / 8, masks, use_closed ? 1 : 0,
                            q.mflags, q.cflags);
-    else
+    } else
         hipLaunchKernelGGL(k_lists<false>, dim3(nblk(n_macro, 4)), dim3(256), 0, st, *d0, descs,
                            off, n_img, n_macro, bx / 8, by / 8, masks, use_closed ? 1 : 0,
                            q.mflags, q.cflags);

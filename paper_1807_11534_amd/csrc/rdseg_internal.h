@@ -48,6 +48,13 @@ int launch_tile_masks(const ImgDesc* d0, const ImgDesc* descs, OffTables off, in
                       int64_t n_strips, uint64_t* masks, int64_t* npix, hipStream_t st,
                       int64_t n_clear = 0);
 
+// Initial state and 8x8 tile masks in one pass (k_init + k_tile_masks fused;
+// the workspace state buffer st[1] is written on RD pixels only).  Clears
+// npix[0 .. max(n_img, n_clear)) first.
+int launch_prepare(const ImgDesc* d0, const ImgDesc* descs, OffTables off, int n_img,
+                   int64_t n_strips, uint64_t* masks, int64_t* npix, hipStream_t st,
+                   int64_t n_clear = 0);
+
 // Fixed-order sum of n int64 device values into *out.
 int launch_sum_i64(const int64_t* a, int n, int64_t* out, hipStream_t st);
 
