@@ -355,9 +355,17 @@ rdseg_status rdseg_metrics(const float* u, const float* u_ref, rdseg_shape s, do
  * pointers and scalars must then be unchanged; only the contents of f may
  * change).  The plan allocates its device memory once, at creation, and
  * frees it in rdseg_plan_destroy.  With graph_plan NULL, the call runs eagerly
- * using `ws` (size rdseg_batched_workspace_size).  tile_w / tile_h /
- * iters_per_launch 0 = defaults.  Results are bitwise identical to rdseg_solve
- * on each image with the same tile configuration. */
+ * using `ws` (size rdseg_batched_workspace_size; with tile_w = tile_h = 0 it is
+ * the size for any configuration).  tile_w / tile_h / iters_per_launch all 0:
+ * the library chooses the configuration and the form of the iterations (see
+ * rdseg_set_batched_form) from the tuning cache's entry for the batch's class
+ * (the size class of its total pixel count and the bucket of its active
+ * fraction; entries written by rdseg_autotune_batched), else 16x16 tiles and
+ * 8 iterations per launch below half active, 64x64 and 8 above, in the
+ * process-wide form; choosing reads the batch's active-pixel count back
+ * (synchronises the stream; a plan chooses once, when it is built).  Results
+ * are bitwise identical to rdseg_solve on each image with the same tile
+ * configuration, in either form. */
 size_t rdseg_batched_workspace_size(const rdseg_image* imgs, int32_t n, int32_t tile_w,
                                     int32_t tile_h);
 rdseg_status rdseg_solve_batched(const rdseg_image* imgs, int32_t n, double theta, double tau,
@@ -365,6 +373,32 @@ rdseg_status rdseg_solve_batched(const rdseg_image* imgs, int32_t n, double thet
                                  int32_t tile_h, void** graph_plan, void* ws, size_t ws_bytes,
                                  void* stream);
 rdseg_status rdseg_plan_destroy(void* plan);
+
+/* Times the batched solve of these images (`probe_iters` iterations, captured
+ * in a graph as a plan runs it; two rounds of three timed replays after a
+ * warm-up per candidate) for every
+ * compiled (tile_w, tile_h, iters_per_launch) configuration and both forms of
+ * the iterations (1: one persistent launch, 2: one launch per block) and
+ * returns the fastest.  A nonzero fix_tile_w, fix_tile_h,
+ * fix_iters_per_launch or fix_form restricts the search to matching
+ * candidates (RDSEG_ERR_ARG if no configuration matches); an unrestricted
+ * search also stores the result in the tuning cache under the batch's class,
+ * which rdseg_solve_batched reads when it chooses.  ws: at least
+ * rdseg_batched_workspace_size(imgs, n, 0, 0) bytes; the images' u, v, p are
+ * overwritten.  Synchronous. */
+rdseg_status rdseg_autotune_batched(const rdseg_image* imgs, int32_t n, double theta, double tau,
+                                    int32_t probe_iters, int32_t fix_tile_w, int32_t fix_tile_h,
+                                    int32_t fix_iters_per_launch, int32_t fix_form, void* ws,
+                                    size_t ws_bytes, void* stream, int32_t* tile_w,
+                                    int32_t* tile_h, int32_t* iters_per_launch, int32_t* form);
+
+/* The configuration and form rdseg_solve_batched chooses (all of tile_w,
+ * tile_h, iters_per_launch 0) for these images when their active fraction is
+ * q in [0, 1]: the tuning cache's entry (*cached = 1) or the fixed choice
+ * (*cached = 0).  Host only.  Any output pointer may be NULL. */
+rdseg_status rdseg_batched_lookup(const rdseg_image* imgs, int32_t n, double q, int32_t* tile_w,
+                                  int32_t* tile_h, int32_t* iters_per_launch, int32_t* form,
+                                  int32_t* cached);
 
 /* ---------------------------------------------------------------------- */
 /* Adjoint of the unrolled solve                                            */
@@ -440,6 +474,16 @@ rdseg_status rdseg_set_resident(int32_t on);
  * (the expiry path forced from the host, for tests of rdseg_solve_status).
  * Process-wide; read when a resident solve is enqueued. */
 rdseg_status rdseg_set_resident_wait(int64_t ticks);
+
+/* The form of the iterations of rdseg_solve_batched when the caller fixes the
+ * configuration (or the tuning cache holds none for the batch): form 1 runs
+ * every block of iterations_per_launch iterations over the global (image,
+ * macro tile) queue in one persistent cooperative launch, with a grid-wide
+ * barrier between blocks (an empty queue ends it at once); form 2 (the
+ * default) enqueues one launch per block.  Results are bitwise equal either
+ * way.  A plan keeps the form it was built with.  Process-wide.
+ * RDSEG_ERR_ARG for any other value. */
+rdseg_status rdseg_set_batched_form(int32_t form);
 
 /* In single-image solves without the stopping rule, the RD pixels whose
  * 4-connected RD component has at most 64 pixels run every iteration in one

@@ -91,6 +91,14 @@ SIGNATURES = {
     "rdseg_solve_batched": (ctypes.c_int, [ctypes.POINTER(Image), _i32, _d, _d, _i32, _i32, _i32,
                                            _i32, ctypes.POINTER(_vp), _vp, _sz, _vp]),
     "rdseg_plan_destroy": (ctypes.c_int, [_vp]),
+    "rdseg_autotune_batched": (ctypes.c_int, [ctypes.POINTER(Image), _i32, _d, _d, _i32, _i32,
+                                              _i32, _i32, _i32, _vp, _sz, _vp,
+                                              ctypes.POINTER(_i32), ctypes.POINTER(_i32),
+                                              ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
+    "rdseg_batched_lookup": (ctypes.c_int, [ctypes.POINTER(Image), _i32, _d,
+                                            ctypes.POINTER(_i32), ctypes.POINTER(_i32),
+                                            ctypes.POINTER(_i32), ctypes.POINTER(_i32),
+                                            ctypes.POINTER(_i32)]),
     "rdseg_backward": (ctypes.c_int, [_vp, Shape, ctypes.POINTER(Params), _vp, _vp, _vp, _vp, _vp,
                                       ctypes.POINTER(Fit), _vp, _vp, _vp, _vp, _sz, _vp]),
     "rdseg_fit_forward": (ctypes.c_int, [ctypes.POINTER(Fit), Shape, _vp, _vp]),
@@ -113,6 +121,7 @@ SIGNATURES = {
     "rdseg_timing_reset": (ctypes.c_int, []),
     "rdseg_set_resident": (ctypes.c_int, [_i32]),
     "rdseg_set_components": (ctypes.c_int, [_i32]),
+    "rdseg_set_batched_form": (ctypes.c_int, [_i32]),
     "rdseg_tune_cache_export": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_size_t,
                                                ctypes.POINTER(ctypes.c_size_t)]),
     "rdseg_tune_cache_import": (ctypes.c_int, [ctypes.c_char_p]),

@@ -204,6 +204,9 @@ struct TimingRec {
 
 std::atomic<bool> g_resident_on{true};
 std::atomic<bool> g_components_on{true};
+// batched solves: 1 = every block in one persistent cooperative launch,
+// 2 = one launch per block of iterations
+std::atomic<int> g_batch_form{2};
 
 struct Timing {
     std::mutex mu;
@@ -243,7 +246,11 @@ int64_t* timing_slot() {
 // ------------------------------------------------------------------ tuning cache
 struct TuneKey {
     int cls, qb;
-    bool operator<(const TuneKey& o) const { return cls != o.cls ? cls < o.cls : qb < o.qb; }
+    int batched = 0;   // 1: a batched solve (cls from the batch's total pixel count)
+    bool operator<(const TuneKey& o) const {
+        if (batched != o.batched) return batched < o.batched;
+        return cls != o.cls ? cls < o.cls : qb < o.qb;
+    }
 };
 // configuration index and small-component choice (1 on, 2 off)
 struct TuneVal {
@@ -251,6 +258,12 @@ struct TuneVal {
 };
 std::mutex g_tune_mu;
 std::map<TuneKey, TuneVal> g_tune;
+
+int size_class_of(int64_t n) {
+    int c = 0;
+    while (n > 4096 && c < 12) { n >>= 2; ++c; }
+    return c;
+}
 
 int size_class(const rdseg_shape& s) {
     int64_t n = (int64_t)s.H * s.W;
@@ -317,10 +330,8 @@ hipStream_t side_stream() {
 template <class Launch>
 rdseg_status closed_beside(hipStream_t st, hipEvent_t* join, Launch launch) {
     *join = nullptr;
-    // under graph capture (batched plans) the kernel stays on the captured stream
-    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-    if (hipStreamIsCapturing(st, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone)
-        return launch(st) ? RDSEG_ERR_HIP : RDSEG_OK;
+    // under graph capture the fork and join make the kernel a parallel branch
+    // of the captured graph
     hipStream_t side = side_stream();
     hipEvent_t fork = nullptr;
     if (!side || hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess)
@@ -876,9 +887,10 @@ rdseg_status validate_batch(const rdseg_image* imgs, int32_t n, double theta, do
     return RDSEG_OK;
 }
 
-int resolve_batch_cfg(int32_t tile_w, int32_t tile_h, int32_t ipl) {
-    if (tile_w == 0 && tile_h == 0 && ipl == 0) return config_index(32, 32, 4);
-    return config_index(tile_w, tile_h, ipl);
+int64_t batch_pixels(const rdseg_image* imgs, int32_t n) {
+    int64_t px = 0;
+    for (int i = 0; i < n; ++i) px += (int64_t)imgs[i].s.H * imgs[i].s.W;
+    return px;
 }
 
 // Host-side layout of a batch; with base != NULL also fills device pointers.
@@ -927,7 +939,7 @@ BatchLayout layout_batch(const rdseg_image* imgs, int32_t n, int bx, int by, dou
     L.cflags = cv.take<int32_t>(L.tiles);
     L.cqueue = cv.take<int2>(L.tiles);
     L.queue = cv.take<int2>(L.macros);
-    L.totals = cv.take<int32_t>(4);
+    L.totals = cv.take<int32_t>(8);   // [0] n_queue, [2] n_closed, [3] status, [4] barrier
     L.bytes = cv.off;
     return L;
 }
@@ -941,9 +953,11 @@ OffTables tables_of(const BatchLayout& L, int n) {
     return t;
 }
 
-// Enqueue the whole batched solve (descriptors already resident).
+// Enqueue the whole batched solve (descriptors already resident).  persist:
+// every block of iterations in one cooperative launch of the persistent
+// kernel (grid-wide barriers), else one launch per block.
 rdseg_status enqueue_batch(const BatchLayout& L, int n, int ci, int iters, double theta,
-                           double tau, hipStream_t st) {
+                           double tau, hipStream_t st, bool persist) {
     TileCfg cfg = config_at(ci);
     OffTables off = tables_of(L, n);
     const ImgDesc* d0 = &L.descs[0];   // unused by the batched kernels
@@ -977,9 +991,82 @@ rdseg_status enqueue_batch(const BatchLayout& L, int n, int ci, int iters, doubl
     a.tape = nullptr;
     a.npix = L.npix_total;
     a.st = st;
-    const rdseg_status r = enqueue_iterations(a);
+    rdseg_status r = RDSEG_OK;
+    int rc = -1;
+    if (persist && iters > 0) {
+        // the solve's status word starts at 0
+        if (launch_fill(reinterpret_cast<float*>(L.totals + 3), 1, 1, 1, 0.0f, st)) return RDSEG_ERR_HIP;
+        const int IT = config_at(ci).it;
+        rc = launch_iterate_persist(ci, d0, L.d_descs, L.queue, L.totals, iters, IT, a.theta,
+                                    a.inv_theta, a.tau, L.totals + 4, L.totals + 3, st);
+        if (rc > 0) r = RDSEG_ERR_HIP;
+    }
+    if (!r && rc < 0) r = enqueue_iterations(a);   // separate launches
     const rdseg_status rj = join_closed(st, join);
     return r ? r : rj;
+}
+
+// Upload a batch layout's descriptors and offset tables (synchronous).
+rdseg_status upload_layout(const BatchLayout& L, int32_t n, hipStream_t st) {
+    if (hipMemcpyAsync(L.d_descs, L.descs.data(), n * sizeof(ImgDesc), hipMemcpyHostToDevice,
+                       st) != hipSuccess ||
+        hipMemcpyAsync(L.d_tabs, L.tabs.data(), L.tabs.size() * sizeof(int64_t),
+                       hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return fail(RDSEG_ERR_HIP, "uploading batch descriptors failed");
+    return RDSEG_OK;
+}
+
+// The batch's active fraction (RD pixels over all pixels): one pass of the
+// initial-state kernel in `mem` (at least the 8x8 layout's bytes), read back.
+rdseg_status batch_active_fraction(const rdseg_image* imgs, int32_t n, double theta, void* mem,
+                                   hipStream_t st, double* q) {
+    BatchLayout L = layout_batch(imgs, n, 8, 8, theta, mem);
+    rdseg_status r = upload_layout(L, n, st);
+    if (r) return r;
+    const ImgDesc* d0 = &L.descs[0];
+    if (launch_prepare(d0, L.d_descs, tables_of(L, n), n, L.strips, L.masks, L.npix, st) ||
+        launch_sum_i64(L.npix, n, L.npix_total, st))
+        return RDSEG_ERR_HIP;
+    int64_t np = 0;
+    if (hipMemcpyAsync(&np, L.npix_total, sizeof(np), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return fail(RDSEG_ERR_HIP, "reading the batch's active-pixel count failed");
+    *q = (double)np / (double)batch_pixels(imgs, n);
+    return RDSEG_OK;
+}
+
+// Configuration and form of a batched solve.  Explicit tile / launch depth:
+// that configuration, in the process-wide form (rdseg_set_batched_form).
+// All 0: the tuning cache's entry for the batch's class (size class of its
+// total pixel count, bucket of its active fraction), else 16x16 / 8 below
+// half active and 64x64 / 8 above, in the process-wide form.
+rdseg_status choose_batch(const rdseg_image* imgs, int32_t n, double theta, int32_t tile_w,
+                          int32_t tile_h, int32_t ipl, void* mem, size_t mem_bytes,
+                          hipStream_t st, int* ci, bool* persist) {
+    *persist = g_batch_form.load() == 1;
+    if (tile_w || tile_h || ipl) {
+        *ci = config_index(tile_w, tile_h, ipl);
+        if (*ci < 0)
+            return fail(RDSEG_ERR_ARG, "tile_w / tile_h / iters_per_launch is not a compiled configuration");
+        return RDSEG_OK;
+    }
+    if (!mem || mem_bytes < layout_batch(imgs, n, 8, 8, theta, nullptr).bytes)
+        return fail(RDSEG_ERR_WORKSPACE, "workspace too small for the library's choice of configuration");
+    double q = 0.0;
+    rdseg_status r = batch_active_fraction(imgs, n, theta, mem, st, &q);
+    if (r) return r;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(TuneKey{size_class_of(batch_pixels(imgs, n)), q_bucket(q), 1});
+        if (it != g_tune.end()) {
+            *ci = it->second.ci;
+            *persist = it->second.resident == 1;
+            return RDSEG_OK;
+        }
+    }
+    *ci = q >= 0.5 ? config_index(64, 64, 8) : config_index(16, 16, 8);
+    return RDSEG_OK;
 }
 
 // ------------------------------------------------------------------ backward
@@ -1045,6 +1132,8 @@ struct BatchPlan {
     std::vector<rdseg_image> imgs;
     double theta, tau;
     int32_t iters, ci;
+    bool persist = false;
+    bool library_choice = false;   // built with tile / launch depth left to the library
     void* mem = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -1188,10 +1277,10 @@ bool parse_cache_text(const char* text, std::vector<std::pair<TuneKey, TuneVal>>
             if (ps.lit(']')) continue;
             do {
                 if (!ps.lit('{')) { why = "an entry must be an object"; return false; }
-                const char* names[7] = {"size_class", "q_bucket", "tile_w", "tile_h",
-                                        "iters_per_launch", "components", "resident"};
-                long val[7];
-                bool seen[7] = {false, false, false, false, false, false, false};
+                const char* names[8] = {"size_class", "q_bucket", "tile_w", "tile_h",
+                                        "iters_per_launch", "components", "resident", "batched"};
+                long val[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+                bool seen[8] = {false, false, false, false, false, false, false, false};
                 do {
                     long x = 0;
                     if (!ps.str(key) || !ps.lit(':') || !ps.integer(x)) {
@@ -1199,7 +1288,7 @@ bool parse_cache_text(const char* text, std::vector<std::pair<TuneKey, TuneVal>>
                         return false;
                     }
                     int k = -1;
-                    for (int j = 0; j < 7; ++j)
+                    for (int j = 0; j < 8; ++j)
                         if (key == names[j]) k = j;
                     if (k < 0 || seen[k]) { why = "unknown or repeated key \"" + key + "\""; return false; }
                     seen[k] = true;
@@ -1214,6 +1303,7 @@ bool parse_cache_text(const char* text, std::vector<std::pair<TuneKey, TuneVal>>
                 }
                 if (val[5] != 1 && val[5] != 2) { why = "components must be 1 or 2"; return false; }
                 if (val[6] != 1 && val[6] != 2) { why = "resident must be 1 or 2"; return false; }
+                if (val[7] != 0 && val[7] != 1) { why = "batched must be 0 or 1"; return false; }
                 if (val[2] < 1 || val[2] > 4096 || val[3] < 1 || val[3] > 4096 || val[4] < 1 ||
                     val[4] > 4096) {
                     why = "tile_w, tile_h and iters_per_launch out of range";
@@ -1221,7 +1311,8 @@ bool parse_cache_text(const char* text, std::vector<std::pair<TuneKey, TuneVal>>
                 }
                 const int ci = config_index((int)val[2], (int)val[3], (int)val[4]);
                 if (ci < 0) { why = "an entry names a configuration that is not compiled"; return false; }
-                out.push_back({TuneKey{(int)val[0], (int)val[1]}, TuneVal{ci, (int)val[5], (int)val[6]}});
+                out.push_back({TuneKey{(int)val[0], (int)val[1], (int)val[7]},
+                               TuneVal{ci, (int)val[5], (int)val[6]}});
             } while (ps.lit(','));
             if (!ps.lit(']')) { why = "expected ']' after the entries"; return false; }
         } else {
@@ -1612,7 +1703,8 @@ size_t rdseg_batched_workspace_size(const rdseg_image* imgs, int32_t n, int32_t 
     if (!imgs || n < 1) return 0;
     for (int i = 0; i < n; ++i)
         if (!shape_ok(imgs[i].s)) return 0;
-    int bx = tile_w > 0 ? tile_w : 32, by = tile_h > 0 ? tile_h : 32;
+    // the library's choice may pick any tile: the 8x8 layout is the largest
+    int bx = tile_w > 0 ? tile_w : 8, by = tile_h > 0 ? tile_h : 8;
     if (bx % 8 || by % 8) return 0;
     return layout_batch(imgs, n, bx, by, 1.0, nullptr).bytes;
 }
@@ -1623,51 +1715,70 @@ rdseg_status rdseg_solve_batched(const rdseg_image* imgs, int32_t n, double thet
                                  void* stream) {
     rdseg_status r = validate_batch(imgs, n, theta, tau, iters);
     if (r) return r;
-    int ci = resolve_batch_cfg(tile_w, tile_h, iters_per_launch);
-    if (ci < 0) return fail(RDSEG_ERR_ARG, "tile_w / tile_h / iters_per_launch is not a compiled configuration");
-    TileCfg cfg = config_at(ci);
+    const bool library_choice = tile_w == 0 && tile_h == 0 && iters_per_launch == 0;
+    if (!library_choice && config_index(tile_w, tile_h, iters_per_launch) < 0)
+        return fail(RDSEG_ERR_ARG, "tile_w / tile_h / iters_per_launch is not a compiled configuration");
     hipStream_t st = static_cast<hipStream_t>(stream);
+    int ci = -1;
+    bool persist = false;
 
     if (!graph_plan) {
         // eager: caller workspace, descriptors uploaded synchronously
+        r = choose_batch(imgs, n, theta, tile_w, tile_h, iters_per_launch, ws, ws_bytes, st, &ci,
+                         &persist);
+        if (r) return r;
+        const TileCfg cfg = config_at(ci);
         BatchLayout need = layout_batch(imgs, n, cfg.bx, cfg.by, theta, nullptr);
         if (!ws || ws_bytes < need.bytes)
             return fail(RDSEG_ERR_WORKSPACE, "workspace too small: need " + std::to_string(need.bytes) + " bytes");
         BatchLayout L = layout_batch(imgs, n, cfg.bx, cfg.by, theta, ws);
-        if (hipMemcpyAsync(L.d_descs, L.descs.data(), n * sizeof(ImgDesc), hipMemcpyHostToDevice, st) != hipSuccess ||
-            hipMemcpyAsync(L.d_tabs, L.tabs.data(), L.tabs.size() * sizeof(int64_t), hipMemcpyHostToDevice, st) != hipSuccess ||
-            hipStreamSynchronize(st) != hipSuccess)
-            return fail(RDSEG_ERR_HIP, "uploading batch descriptors failed");
-        return enqueue_batch(L, n, ci, iters, theta, tau, st);
+        r = upload_layout(L, n, st);
+        if (r) return r;
+        return enqueue_batch(L, n, ci, iters, theta, tau, st, persist);
     }
 
     BatchPlan* P = static_cast<BatchPlan*>(*graph_plan);
     if (P) {
-        if (!same_batch(*P, imgs, n, theta, tau, iters, ci))
+        const int want = library_choice ? P->ci : config_index(tile_w, tile_h, iters_per_launch);
+        if (library_choice != P->library_choice || !same_batch(*P, imgs, n, theta, tau, iters, want))
             return fail(RDSEG_ERR_ARG, "plan was built for a different batch");
         if (hipGraphLaunch(P->exec, st) != hipSuccess) return fail(RDSEG_ERR_HIP, "hipGraphLaunch failed");
         return RDSEG_OK;
     }
-    // build a plan: own workspace, resident descriptors, captured graph
+    // build a plan: own workspace (the largest layout when the library
+    // chooses the configuration), resident descriptors, captured graph
     P = new BatchPlan();
     P->imgs.assign(imgs, imgs + n);
     P->theta = theta;
     P->tau = tau;
     P->iters = iters;
+    P->library_choice = library_choice;
+    {
+        const int bx = library_choice ? 8 : tile_w, by = library_choice ? 8 : tile_h;
+        const size_t bytes = layout_batch(imgs, n, bx, by, theta, nullptr).bytes;
+        if (hipMalloc(&P->mem, bytes) != hipSuccess) {
+            plan_free(P);
+            return fail(RDSEG_ERR_HIP, "hipMalloc of the plan workspace failed");
+        }
+        r = choose_batch(imgs, n, theta, tile_w, tile_h, iters_per_launch, P->mem, bytes, st, &ci,
+                         &persist);
+        if (r) {
+            plan_free(P);
+            return r;
+        }
+    }
     P->ci = ci;
-    BatchLayout need = layout_batch(imgs, n, cfg.bx, cfg.by, theta, nullptr);
-    if (hipMalloc(&P->mem, need.bytes) != hipSuccess) {
-        plan_free(P);
-        return fail(RDSEG_ERR_HIP, "hipMalloc of the plan workspace failed");
-    }
+    P->persist = persist;
+    const TileCfg cfg = config_at(ci);
     BatchLayout L = layout_batch(imgs, n, cfg.bx, cfg.by, theta, P->mem);
-    if (hipMemcpy(L.d_descs, L.descs.data(), n * sizeof(ImgDesc), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(L.d_tabs, L.tabs.data(), L.tabs.size() * sizeof(int64_t), hipMemcpyHostToDevice) != hipSuccess) {
+    r = upload_layout(L, n, st);
+    if (r) {
         plan_free(P);
-        return fail(RDSEG_ERR_HIP, "uploading batch descriptors failed");
+        return r;
     }
-    // occupancy query outside the capture
-    if (prepare_iterate(ci, true) || prepare_closed(true)) {
+    // occupancy queries outside the capture
+    if (prepare_iterate(ci, true) || prepare_closed(true) ||
+        (P->persist && prepare_iterate_persist(ci))) {
         plan_free(P);
         return RDSEG_ERR_HIP;
     }
@@ -1682,7 +1793,7 @@ rdseg_status rdseg_solve_batched(const rdseg_image* imgs, int32_t n, double thet
     if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
         r = fail(RDSEG_ERR_HIP, "hipStreamBeginCapture failed");
     } else {
-        r = enqueue_batch(L, n, ci, iters, theta, tau, cap);
+        r = enqueue_batch(L, n, ci, iters, theta, tau, cap, P->persist);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(cap, &g);
         if (r == RDSEG_OK && e != hipSuccess) r = fail(RDSEG_ERR_HIP, "hipStreamEndCapture failed");
@@ -1698,6 +1809,148 @@ rdseg_status rdseg_solve_batched(const rdseg_image* imgs, int32_t n, double thet
     }
     *graph_plan = P;
     if (hipGraphLaunch(P->exec, st) != hipSuccess) return fail(RDSEG_ERR_HIP, "hipGraphLaunch failed");
+    return RDSEG_OK;
+}
+
+rdseg_status rdseg_autotune_batched(const rdseg_image* imgs, int32_t n, double theta, double tau,
+                                    int32_t probe_iters, int32_t fix_tile_w, int32_t fix_tile_h,
+                                    int32_t fix_iters_per_launch, int32_t fix_form, void* ws,
+                                    size_t ws_bytes, void* stream, int32_t* tile_w,
+                                    int32_t* tile_h, int32_t* iters_per_launch, int32_t* form) {
+    rdseg_status r = validate_batch(imgs, n, theta, tau, probe_iters);
+    if (r) return r;
+    if (probe_iters < 1) return fail(RDSEG_ERR_ARG, "probe_iters must be >= 1");
+    if (fix_form < 0 || fix_form > 2)
+        return fail(RDSEG_ERR_ARG, "form must be 0 (both are timed), 1 or 2");
+    if (fix_tile_w < 0 || fix_tile_h < 0 || fix_iters_per_launch < 0)
+        return fail(RDSEG_ERR_ARG, "fixed tile / launch depth must be >= 0");
+    if (!ws || ws_bytes < layout_batch(imgs, n, 8, 8, theta, nullptr).bytes)
+        return fail(RDSEG_ERR_WORKSPACE, "workspace too small: need rdseg_batched_workspace_size(imgs, n, 0, 0) bytes");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    auto candidate = [&](int ci) {
+        const TileCfg c = config_at(ci);
+        return (fix_tile_w <= 0 || c.bx == fix_tile_w) && (fix_tile_h <= 0 || c.by == fix_tile_h) &&
+               (fix_iters_per_launch <= 0 || c.it == fix_iters_per_launch);
+    };
+    {
+        bool any = false;
+        for (int ci = 0; ci < config_count(); ++ci) any = any || candidate(ci);
+        if (!any)
+            return fail(RDSEG_ERR_ARG, "no compiled configuration matches the fixed tile_w / tile_h / iters_per_launch");
+    }
+    const bool restricted = fix_tile_w > 0 || fix_tile_h > 0 || fix_iters_per_launch > 0 || fix_form != 0;
+    const int f_lo = fix_form ? fix_form : 1, f_hi = fix_form ? fix_form : 2;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(RDSEG_ERR_HIP, "hipEventCreate failed");
+    hipStream_t cap = nullptr;
+    if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return fail(RDSEG_ERR_HIP, "hipStreamCreate failed");
+    }
+    const bool timing_was = g_timing.on;
+    g_timing.on = false;
+    // two rounds over all candidates, each timed over three graph replays
+    // after a warm-up; the minimum per candidate damps clock and cache noise
+    const int nc = config_count();
+    std::vector<float> ms_min(2 * nc, -1.0f);   // [config][form - 1]
+    for (int round = 0; round < 2 && !r; ++round) {
+        for (int ci = 0; ci < nc && !r; ++ci) {
+            if (!candidate(ci)) continue;
+            const TileCfg cfg = config_at(ci);
+            BatchLayout L = layout_batch(imgs, n, cfg.bx, cfg.by, theta, ws);
+            r = upload_layout(L, n, st);
+            if (r) break;
+            if (prepare_iterate(ci, true) || prepare_closed(true) || prepare_iterate_persist(ci)) {
+                r = RDSEG_ERR_HIP;
+                break;
+            }
+            for (int fm = f_lo; fm <= f_hi && !r; ++fm) {
+                // timed as it runs in a plan: the whole sequence captured in
+                // a graph, replayed
+                hipGraph_t g = nullptr;
+                hipGraphExec_t ge = nullptr;
+                if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+                    r = fail(RDSEG_ERR_HIP, "hipStreamBeginCapture failed");
+                    break;
+                }
+                r = enqueue_batch(L, n, ci, probe_iters, theta, tau, cap, fm == 1);
+                const hipError_t ce = hipStreamEndCapture(cap, &g);
+                if (!r && (ce != hipSuccess || hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) != hipSuccess))
+                    r = fail(RDSEG_ERR_HIP, "capturing a candidate of the batched autotune failed");
+                if (!r && hipGraphLaunch(ge, st) != hipSuccess)
+                    r = fail(RDSEG_ERR_HIP, "hipGraphLaunch failed");
+                if (!r) {
+                    (void)hipEventRecord(e0, st);
+                    for (int rep = 0; rep < 3 && !r; ++rep)
+                        if (hipGraphLaunch(ge, st) != hipSuccess)
+                            r = fail(RDSEG_ERR_HIP, "hipGraphLaunch failed");
+                    (void)hipEventRecord(e1, st);
+                }
+                if (!r && hipEventSynchronize(e1) != hipSuccess)
+                    r = fail(RDSEG_ERR_HIP, "batched autotune timing failed");
+                if (ge) (void)hipGraphExecDestroy(ge);
+                if (g) (void)hipGraphDestroy(g);
+                if (r) break;
+                float ms = 0.0f;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                float& m = ms_min[2 * ci + (fm - 1)];
+                if (m < 0.0f || ms < m) m = ms;
+            }
+        }
+    }
+    g_timing.on = timing_was;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipStreamDestroy(cap);
+    if (r) return r;
+    int best = -1;
+    for (int k = 0; k < 2 * nc; ++k)
+        if (ms_min[k] >= 0.0f && (best < 0 || ms_min[k] < ms_min[best])) best = k;
+    const int best_ci = best / 2, best_form = best % 2 + 1;
+    if (!restricted) {
+        double q = 0.0;
+        r = batch_active_fraction(imgs, n, theta, ws, st, &q);
+        if (r) return r;
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[TuneKey{size_class_of(batch_pixels(imgs, n)), q_bucket(q), 1}] =
+            TuneVal{best_ci, 2, best_form};
+    }
+    const TileCfg c = config_at(best_ci);
+    if (tile_w) *tile_w = c.bx;
+    if (tile_h) *tile_h = c.by;
+    if (iters_per_launch) *iters_per_launch = c.it;
+    if (form) *form = best_form;
+    return RDSEG_OK;
+}
+
+rdseg_status rdseg_batched_lookup(const rdseg_image* imgs, int32_t n, double q, int32_t* tile_w,
+                                  int32_t* tile_h, int32_t* iters_per_launch, int32_t* form,
+                                  int32_t* cached) {
+    if (!imgs || n < 1) return fail(RDSEG_ERR_ARG, "imgs must hold n >= 1 images");
+    for (int i = 0; i < n; ++i) {
+        const rdseg_status r = check_shape(imgs[i].s);
+        if (r) return r;
+    }
+    if (!(q >= 0.0 && q <= 1.0)) return fail(RDSEG_ERR_ARG, "q must lie in [0, 1]");
+    int ci = -1, fm = g_batch_form.load(), hit = 0;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(TuneKey{size_class_of(batch_pixels(imgs, n)), q_bucket(q), 1});
+        if (it != g_tune.end()) {
+            ci = it->second.ci;
+            fm = it->second.resident;
+            hit = 1;
+        }
+    }
+    if (ci < 0) ci = q >= 0.5 ? config_index(64, 64, 8) : config_index(16, 16, 8);
+    const TileCfg c = config_at(ci);
+    if (tile_w) *tile_w = c.bx;
+    if (tile_h) *tile_h = c.by;
+    if (iters_per_launch) *iters_per_launch = c.it;
+    if (form) *form = fm;
+    if (cached) *cached = hit;
     return RDSEG_OK;
 }
 
@@ -2019,9 +2272,10 @@ rdseg_status rdseg_tune_cache_export(char* buf, size_t cap, size_t* len) {
             char e[256];
             snprintf(e, sizeof(e),
                      "%s\n  {\"size_class\": %d, \"q_bucket\": %d, \"tile_w\": %d, \"tile_h\": %d, "
-                     "\"iters_per_launch\": %d, \"components\": %d, \"resident\": %d}",
+                     "\"iters_per_launch\": %d, \"components\": %d, \"resident\": %d%s}",
                      first ? "" : ",", kv.first.cls, kv.first.qb, c.bx, c.by, c.it,
-                     kv.second.comps, kv.second.resident);
+                     kv.second.comps, kv.second.resident,
+                     kv.first.batched ? ", \"batched\": 1" : "");
             t += e;
             first = false;
         }
@@ -2081,6 +2335,13 @@ rdseg_status rdseg_tune_cache_clear(void) {
 
 rdseg_status rdseg_set_resident(int32_t on) {
     g_resident_on.store(on != 0);
+    return RDSEG_OK;
+}
+
+rdseg_status rdseg_set_batched_form(int32_t form) {
+    if (form != 1 && form != 2)
+        return fail(RDSEG_ERR_ARG, "form must be 1 (one persistent launch) or 2 (separate launches)");
+    g_batch_form.store(form);
     return RDSEG_OK;
 }
 

@@ -184,14 +184,24 @@ __global__ __launch_bounds__(256) void k_tile_masks(ImgDesc d0, const ImgDesc* _
     }
 }
 
+// Global-address-space views of the descriptor's generic pointers: global
+// loads and stores are counted in order, so a load's use waits only for that
+// load, where a generic (flat) access makes the compiler wait for every
+// outstanding access, stores included.
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* as_global(T* p) {
+    return (__attribute__((address_space(1))) T*)p;
+}
+
 // ---------------------------------------------------------------- prepare
 // The initial state (u0 = H(-f) or the caller's start on RD, v0 = clamp(u0 -
 // theta lambda f), p0 = 0 or the caller's; frozen pixels u = v = H(-f), p = 0)
 // and the 8x8 tile masks of RD in one pass over f.  One wave per 8-row x
-// 64-column strip as in k_tile_masks; each wave takes a contiguous run of
-// `per_wave` strips, so a batch looks up the image of its first strip once
-// and then walks forward (a lookup per strip is a chain of dependent loads
-// that left the batched passes latency bound).  Writes c, u and the caller's
+// 64-column strip as in k_tile_masks; each workgroup takes a contiguous run
+// of 4 * `per_wave` strips, its waves every fourth one, so a batch looks up
+// the image of a wave's first strip once and then walks forward (a lookup per
+// strip is a chain of dependent loads that left the batched passes latency
+// bound).  Writes c, u and the caller's
 // state buffer (v, p_x, p_y) on every pixel, the workspace's state buffer
 // only on RD pixels: no kernel reads a frozen pixel's state from it.  With
 // d.u == NULL only c and the masks are written.
@@ -202,65 +212,118 @@ __global__ __launch_bounds__(256) void k_prepare(ImgDesc d0, const ImgDesc* __re
                                                  int64_t* __restrict__ npix) {
     __shared__ unsigned long long sCnt[4];
     const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
-    const int64_t s0 = ((int64_t)blockIdx.x * 4 + wv) * per_wave;
-    const int64_t s1 = s0 + per_wave < n_strips ? s0 + per_wave : n_strips;
+    // wave-uniform (readfirstlane tells the compiler so): the strip loop, the
+    // image index and its descriptor then live in scalar registers
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    // the workgroup's run of 4 * per_wave strips, its waves interleaved: the
+    // four waves write adjacent strips (1 KB of each row of each plane)
+    const int64_t g0 = (int64_t)blockIdx.x * 4 * per_wave;
+    const int64_t s0 = g0 + wv;
+    const int64_t s1 = g0 + 4 * per_wave < n_strips ? g0 + 4 * per_wave : n_strips;
     unsigned long long cnt = 0;   // RD pixels of the current image (this wave)
+    // the image index is wave-uniform (readfirstlane tells the compiler so):
+    // its descriptor is read with scalar loads, once per image
     int img = 0;
     int64_t img_lo = 0, img_hi = n_strips;
+    ImgDesc d = d0;
     if (BATCHED && s0 < s1) {
-        img = find_image(off.soff, n_img, s0);
+        img = __builtin_amdgcn_readfirstlane(find_image(off.soff, n_img, s0));
         img_lo = off.soff[img];
         img_hi = off.soff[img + 1];
+        d = descs[img];
     }
-    for (int64_t s = s0; s < s1; ++s) {
-        if (BATCHED) {
-            while (s >= img_hi) {
+    for (int64_t s = s0; s < s1; s += 4) {
+        if (BATCHED && s >= img_hi) {
+            do {
                 if (lane == 0 && cnt) atomicAdd((unsigned long long*)&npix[img], cnt);
                 cnt = 0;
                 ++img;
                 img_lo = img_hi;
                 img_hi = off.soff[img + 1];
-            }
+            } while (s >= img_hi);
+            img = __builtin_amdgcn_readfirstlane(img);
+            d = descs[img];
         }
-        const ImgDesc& d = BATCHED ? descs[img] : d0;
         const int64_t ls = s - img_lo;
         const int sw = (d.tw + 7) >> 3;
         const int ty = (int)(ls / sw);
         const int sx = (int)(ls - (int64_t)ty * sw);
         const int x = sx * 64 + lane;
         const int W = d.W, H = d.H;
-        uint64_t b[8];
+        // every load of the strip is issued before its first store: a load
+        // after a store waits for that store too (one counter), and a round
+        // trip per row left the pass latency bound
+        const auto F = as_global(d.f), U0 = as_global(d.u0);
+        const auto P0X = as_global(d.p0x), P0Y = as_global(d.p0y);
+        const auto C = as_global(d.c), U = as_global(d.u);
+        const auto V0 = as_global(d.st[0][0]), X0 = as_global(d.st[0][1]);
+        const auto Y0 = as_global(d.st[0][2]), V1 = as_global(d.st[1][0]);
+        const auto X1 = as_global(d.st[1][1]), Y1 = as_global(d.st[1][2]);
+        // unconditional loads (clamped into the image; the values of lanes
+        // outside it are not used), so that the compiler can count them
+        float fr[8], ur[8], pxr[8], pyr[8];
+        const int xc = x < W ? x : W - 1;
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
             const int y = ty * 8 + r;
-            bool a = false;
+            const int yc = y < H ? y : H - 1;
+            fr[r] = F[(int64_t)yc * d.ld + xc];
+            ur[r] = 0.0f;
+            pxr[r] = 0.0f;
+            pyr[r] = 0.0f;
+        }
+        if (d.u0 || d.p0x) {   // a caller's start (single image only)
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                const int y = ty * 8 + r;
+                const int64_t g = (int64_t)y * d.ld + x;
+                const bool in = x < W && y < H;
+                ur[r] = (in && d.u0) ? U0[g] : 0.0f;
+                pxr[r] = (in && d.p0x) ? P0X[g] : 0.0f;
+                pyr[r] = (in && d.p0y) ? P0Y[g] : 0.0f;
+            }
+        }
+        // the whole strip's values first, then its stores (no load of this
+        // strip waits behind a store of it)
+        uint64_t b[8];
+        float cr[8], u0r[8], v0r[8];
+        uint32_t actm = 0u;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int y = ty * 8 + r;
+            const bool in = x < W && y < H;
+            const float fv = fr[r];
+            const bool a = in && fabs((double)fv) < d.delta;
+            const float c = c_of(fv, d.delta, d.tl);
+            const bool act = c_active(c);
+            const float h = (fv < 0.0f) ? 1.0f : 0.0f;
+            cr[r] = c;
+            u0r[r] = act ? (d.u0 ? ur[r] : h) : h;
+            v0r[r] = v_step(u0r[r], c);
+            pxr[r] = (act && x < W - 1) ? pxr[r] : 0.0f;
+            pyr[r] = (act && y < H - 1) ? pyr[r] : 0.0f;
+            actm |= act ? (1u << r) : 0u;
+            b[r] = __ballot(a);
+            cnt += (unsigned long long)__popcll(b[r]);
+        }
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int y = ty * 8 + r;
             if (x < W && y < H) {
                 const int64_t g = (int64_t)y * d.ld + x;
-                const float fv = d.f[g];
-                a = fabs((double)fv) < d.delta;
-                const float c = c_of(fv, d.delta, d.tl);
-                const bool act = c_active(c);
-                const float h = (fv < 0.0f) ? 1.0f : 0.0f;
-                d.c[g] = c;
+                C[g] = cr[r];
                 if (d.u) {
-                    const float u0 = act ? (d.u0 ? d.u0[g] : h) : h;
-                    const float v0 = v_step(u0, c);
-                    const float px = (act && x < W - 1 && d.p0x) ? d.p0x[g] : 0.0f;
-                    const float py = (act && y < H - 1 && d.p0y) ? d.p0y[g] : 0.0f;
-                    d.u[g] = u0;
-                    d.st[0][0][g] = v0;
-                    d.st[0][1][g] = px;
-                    d.st[0][2][g] = py;
-                    if (act) {
-                        d.st[1][0][g] = v0;
-                        d.st[1][1][g] = px;
-                        d.st[1][2][g] = py;
+                    U[g] = u0r[r];
+                    V0[g] = v0r[r];
+                    X0[g] = pxr[r];
+                    Y0[g] = pyr[r];
+                    if ((actm >> r) & 1u) {
+                        V1[g] = v0r[r];
+                        X1[g] = pxr[r];
+                        Y1[g] = pyr[r];
                     }
                 }
             }
-            b[r] = __ballot(a);
-            cnt += (unsigned long long)__popcll(b[r]);
         }
         if (lane < 8) {
             const int tx = sx * 8 + lane;
@@ -415,7 +478,8 @@ __global__ __launch_bounds__(256) void k_lists_batched(const ImgDesc* __restrict
     const int lane = threadIdx.x & 63;
     const int tpm = bx8 * by8;   // 8x8 tiles per macro tile (<= 64)
     const int mpi = 64 / tpm;    // macro tiles per step
-    const int64_t m0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * per_wave;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t m0 = ((int64_t)blockIdx.x * 4 + wv) * per_wave;
     const int64_t m1 = m0 + per_wave < n_macro ? m0 + per_wave : n_macro;
     if (m0 >= m1) return;   // uniform per wave
     int img = find_image(off.moff, n_img, m0);

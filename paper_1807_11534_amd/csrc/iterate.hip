@@ -217,16 +217,16 @@ __device__ __forceinline__ uint32_t cell_flags(bool act, int rx, int ry, int gx,
 // previous iteration is loaded with the state, and with diff_slot non-NULL the
 // last iteration's max(|u - u_prev|, |v - v_prev|) over RD is reduced into
 // *diff_slot (one atomicMax per wave).
-template <int BX, int BY, int IT, int NT, bool BATCHED, bool STOP, bool FAST_OK = (BX >= 64),
-          bool COMPACT_OK = (BX < 64)>
-__global__ __launch_bounds__(NT) void k_iterate(ImgDesc d0, const ImgDesc* __restrict__ descs,
-                                                const int2* __restrict__ queue,
-                                                const int32_t* __restrict__ n_queue, int in_buf,
-                                                int nit, int write_u, float theta,
-                                                float inv_theta, float tau,
-                                                const uint32_t* __restrict__ skip_slot,
-                                                uint32_t* __restrict__ diff_slot, double tol,
-                                                int inner) {
+// One launch's work (the kernel below; the persistent form runs it once per
+// block of iterations).
+template <int BX, int BY, int IT, int NT, bool BATCHED, bool STOP, bool FAST_OK, bool COMPACT_OK>
+__device__ __forceinline__ void iterate_pass(ImgDesc d0, const ImgDesc* __restrict__ descs,
+                                             const int2* __restrict__ queue,
+                                             const int32_t* __restrict__ n_queue, int in_buf,
+                                             int nit, int write_u, float theta, float inv_theta,
+                                             float tau, const uint32_t* __restrict__ skip_slot,
+                                             uint32_t* __restrict__ diff_slot, double tol,
+                                             int inner) {
     if (STOP && skip_slot && (double)__uint_as_float(*skip_slot) <= tol) return;
     constexpr int RX = BX + 2 * IT + 1;
     constexpr int RY = BY + 2 * IT + 1;
@@ -439,6 +439,81 @@ __global__ __launch_bounds__(NT) void k_iterate(ImgDesc d0, const ImgDesc* __res
     if (check) {
         for (int o = 32; o > 0; o >>= 1) dmax = max(dmax, (uint32_t)__shfl_xor((int)dmax, o));
         if ((threadIdx.x & 63) == 0 && dmax) atomicMax(diff_slot, dmax);
+    }
+}
+
+template <int BX, int BY, int IT, int NT, bool BATCHED, bool STOP, bool FAST_OK = (BX >= 64),
+          bool COMPACT_OK = (BX < 64)>
+__global__ __launch_bounds__(NT) void k_iterate(ImgDesc d0, const ImgDesc* __restrict__ descs,
+                                                const int2* __restrict__ queue,
+                                                const int32_t* __restrict__ n_queue, int in_buf,
+                                                int nit, int write_u, float theta,
+                                                float inv_theta, float tau,
+                                                const uint32_t* __restrict__ skip_slot,
+                                                uint32_t* __restrict__ diff_slot, double tol,
+                                                int inner) {
+    iterate_pass<BX, BY, IT, NT, BATCHED, STOP, FAST_OK, COMPACT_OK>(
+        d0, descs, queue, n_queue, in_buf, nit, write_u, theta, inv_theta, tau, skip_slot,
+        diff_slot, tol, inner);
+}
+
+// Grid-wide barrier of a cooperative launch: every workgroup adds one to
+// *bar (a counter that starts at 0 and only grows), then waits until it reads
+// gen * gridDim.x.  The release fence before the arrival and the acquire fence
+// after the wait order the state buffers written before the barrier against
+// the loads after it, as a kernel boundary does.  The wait is bounded
+// (wait_ticks of the 100 MHz wall clock; < 0 gives up at once): on expiry the
+// workgroup sets *status and returns false.
+__device__ __forceinline__ bool grid_barrier(int32_t* bar, int gen, int64_t wait_ticks,
+                                             int32_t* status) {
+    __shared__ int sOk;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_fetch_add(bar, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int32_t target = gen * (int32_t)gridDim.x;
+        const uint64_t t0 = wall_clock64();
+        int ok = 1;
+        while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (wait_ticks < 0 || wall_clock64() - t0 > (uint64_t)wait_ticks) {
+                ok = 0;
+                __hip_atomic_store(status, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        sOk = ok;
+    }
+    __syncthreads();
+    return sOk != 0;
+}
+
+// Persistent form of the batched iteration: one cooperative launch runs every
+// block of `per` outer iterations over the global (image, macro tile) queue,
+// exactly the work and buffer parities of the L = ceil(iters / per) separate
+// launches, with a grid-wide barrier in place of each kernel boundary (so the
+// results are bitwise those of the separate launches).  An empty queue ends
+// the launch at once.  A barrier whose wait expires stops the workgroup (the
+// solve's status word is set; the results are then incomplete).
+template <int BX, int BY, int IT, int NT>
+__global__ __launch_bounds__(NT) void k_iterate_persist(ImgDesc d0,
+                                                        const ImgDesc* __restrict__ descs,
+                                                        const int2* __restrict__ queue,
+                                                        const int32_t* __restrict__ n_queue,
+                                                        int iters, int per, float theta,
+                                                        float inv_theta, float tau,
+                                                        int32_t* __restrict__ bar,
+                                                        int32_t* __restrict__ status,
+                                                        int64_t wait_ticks) {
+    if (*n_queue == 0) return;   // the same value for every workgroup
+    const int L = (iters + per - 1) / per;
+    for (int j = 0; j < L; ++j) {
+        const int nit = min(per, iters - j * per);
+        iterate_pass<BX, BY, IT, NT, true, false, (BX >= 64), (BX < 64)>(
+            d0, descs, queue, n_queue, (L - j) & 1, nit, j == L - 1 ? 1 : 0, theta, inv_theta,
+            tau, nullptr, nullptr, 0.0, 1);
+        if (j < L - 1 && !grid_barrier(bar, j + 1, wait_ticks, status)) return;
     }
 }
 
@@ -729,15 +804,20 @@ __global__ __launch_bounds__(256) void k_state_copy(ImgDesc d, int buf, float* _
 using IterFn = void (*)(ImgDesc, const ImgDesc*, const int2*, const int32_t*, int, int, int,
                         float, float, float, const uint32_t*, uint32_t*, double, int);
 
+using PersistFn = void (*)(ImgDesc, const ImgDesc*, const int2*, const int32_t*, int, int,
+                           float, float, float, int32_t*, int32_t*, int64_t);
+
 struct CfgEntry {
     TileCfg cfg;
     IterFn fn[3];   // single image, batched, single image with the stopping rule
+    PersistFn pfn;  // batched, every block in one cooperative launch
 };
 
 #define RDSEG_CFG(bx, by, it, nt)                                                         \
     CfgEntry{TileCfg{bx, by, it, nt},                                                     \
              {k_iterate<bx, by, it, nt, false, false>, k_iterate<bx, by, it, nt, true, false>, \
-              k_iterate<bx, by, it, nt, false, true>}}
+              k_iterate<bx, by, it, nt, false, true>},                                    \
+             k_iterate_persist<bx, by, it, nt>}
 
 const CfgEntry kCfgs[] = {
     RDSEG_CFG(8, 8, 1, 64),
@@ -764,6 +844,7 @@ constexpr int kNumCfgs = sizeof(kCfgs) / sizeof(kCfgs[0]);
 
 // occupancy-derived grid sizes, filled on first use (any host thread)
 std::atomic<int> g_grid_cache[kNumCfgs][3];
+std::atomic<int> g_persist_cap[kNumCfgs];
 
 using ResFn = void (*)(ImgDesc, const int2*, const int32_t*, const int32_t*, int32_t*, int32_t*,
                        int, int, int, int, float, float, float, CompWs, const int64_t*, int,
@@ -920,6 +1001,41 @@ int launch_iterate(int ci, const ImgDesc* d0, const ImgDesc* descs, bool batched
                        stop ? stop->skip_slot : nullptr, stop ? stop->diff_slot : nullptr,
                        stop ? stop->tol : 0.0, inner);
     RDSEG_HIP_CHECK(hipGetLastError());
+    return 0;
+}
+
+int prepare_iterate_persist(int ci) {
+    const CfgEntry& e = kCfgs[ci];
+    int cap = g_persist_cap[ci].load(std::memory_order_relaxed);
+    if (cap == 0) {
+        cap = persistent_blocks(reinterpret_cast<const void*>(e.pfn), e.cfg.nt, 0);
+        if (cap <= 0) cap = -1;
+        g_persist_cap[ci].store(cap, std::memory_order_relaxed);
+    }
+    return 0;
+}
+
+int launch_iterate_persist(int ci, const ImgDesc* d0, const ImgDesc* descs, const int2* queue,
+                           const int32_t* n_queue, int iters, int per, float theta,
+                           float inv_theta, float tau, int32_t* bar, int32_t* status,
+                           hipStream_t st) {
+    const CfgEntry& e = kCfgs[ci];
+    prepare_iterate_persist(ci);
+    const int cap = g_persist_cap[ci].load(std::memory_order_relaxed);
+    const int grid = cap > 0 ? cap / 8 * 8 : 0;
+    if (grid < 8) return -1;
+    // the barrier counter starts at 0 (a fill kernel: no memset node in a graph)
+    if (launch_fill(reinterpret_cast<float*>(bar), 1, 1, 1, 0.0f, st)) return 1;
+    ImgDesc dd = *d0;
+    int64_t wait = resident_wait_ticks();
+    void* args[] = {&dd,    &descs, &queue, &n_queue, &iters, &per, &theta,
+                    &inv_theta, &tau, &bar, &status, &wait};
+    const hipError_t err = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(e.pfn),
+                                                      dim3(grid), dim3(e.cfg.nt), args, 0, st);
+    if (err != hipSuccess) {
+        (void)hipGetLastError();
+        return -1;
+    }
     return 0;
 }
 

@@ -251,6 +251,17 @@ int launch_iterate(int cfg_index, const ImgDesc* d0, const ImgDesc* descs, bool 
                    int nit, bool write_u, float theta, float inv_theta, float tau,
                    hipStream_t st, const StopLaunch* stop = nullptr, int inner = 1);
 
+// Every block of a batched solve in one cooperative launch of the persistent
+// iteration kernel (grid-wide barriers between blocks of `per` iterations;
+// bitwise the separate launches).  *bar is cleared first; *status is set if
+// a barrier's wait expires.  Returns -1 when the form cannot be launched
+// (the caller then enqueues separate launches), > 0 on a HIP error.
+int prepare_iterate_persist(int cfg_index);   // occupancy query (outside graph capture)
+int launch_iterate_persist(int cfg_index, const ImgDesc* d0, const ImgDesc* descs,
+                           const int2* queue, const int32_t* n_queue, int iters, int per,
+                           float theta, float inv_theta, float tau, int32_t* bar,
+                           int32_t* status, hipStream_t st);
+
 // After a convergence-driven solve: *iters_done = (c + 1) * check_every for
 // the first check c with slots[c] <= tol (else iters), then the state of
 // that check is moved into buffer 0 when it lies in buffer 1.  The check c

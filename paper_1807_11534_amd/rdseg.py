@@ -287,6 +287,9 @@ class BatchedSolver:
 
     def __init__(self, fs, lams, deltas, theta=THETA, tau=TAU, iters=100, tile=(32, 32),
                  iters_per_launch=4, graph=True):
+        """tile=None with iters_per_launch=0 leaves the configuration (and the
+        form of the iterations) to the library: the tuning cache's entry for
+        the batch (see autotune), else a fixed choice by active fraction."""
         self.lib = _lib.load()
         n = len(fs)
         if not (len(lams) == len(deltas) == n and n > 0):
@@ -303,12 +306,12 @@ class BatchedSolver:
         self.imgs = arr
         self.n = n
         self.theta, self.tau, self.iters = float(theta), float(tau), int(iters)
-        self.tile, self.ipl = tile, int(iters_per_launch)
+        self.tile, self.ipl = (tile if tile is not None else (0, 0)), int(iters_per_launch)
         self.graph = graph
         self.plan = ctypes.c_void_p(None)
         self.ws = None
         if not graph:
-            nbytes = self.lib.rdseg_batched_workspace_size(arr, n, tile[0], tile[1])
+            nbytes = self.lib.rdseg_batched_workspace_size(arr, n, self.tile[0], self.tile[1])
             if nbytes == 0:
                 raise ValueError("invalid batch")
             self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.fs[0].device)
@@ -320,6 +323,34 @@ class BatchedSolver:
                                            self.ipl, self.tile[0], self.tile[1], plan, _vp(ws),
                                            0 if ws is None else ws.numel(), _stream()))
         return self.out
+
+    def autotune(self, probe_iters=None, tile=None, iters_per_launch=0, form=0):
+        """Time every configuration and both forms of the iterations on this
+        batch (rdseg_autotune_batched; the outputs are overwritten) and return
+        Tuned ((tile_w, tile_h), iters_per_launch) with `.form`; an
+        unrestricted search is stored in the tuning cache, which a solve that
+        leaves the choice to the library reads."""
+        nbytes = self.lib.rdseg_batched_workspace_size(self.imgs, self.n, 0, 0)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=self.fs[0].device)
+        tw, th = (0, 0) if tile is None else tile
+        v = [ctypes.c_int32(0) for _ in range(4)]
+        check(self.lib.rdseg_autotune_batched(
+            self.imgs, self.n, self.theta, self.tau, int(probe_iters or self.iters), int(tw),
+            int(th), int(iters_per_launch), int(form), _vp(ws), ws.numel(), _stream(),
+            *[ctypes.byref(x) for x in v]))
+        t = Tuned((v[0].value, v[1].value), v[2].value, 2, v[3].value)
+        t.form = v[3].value
+        return t
+
+    def lookup(self, q):
+        """The configuration and form a library-chosen solve of this batch
+        uses when its active fraction is q (host only)."""
+        v = [ctypes.c_int32(0) for _ in range(5)]
+        check(self.lib.rdseg_batched_lookup(self.imgs, self.n, float(q),
+                                            *[ctypes.byref(x) for x in v]))
+        t = Tuned((v[0].value, v[1].value), v[2].value, 2, v[3].value)
+        t.form, t.cached = v[3].value, bool(v[4].value)
+        return t
 
     def close(self):
         if self.plan.value:
@@ -494,6 +525,13 @@ def timing_read_form(config=-1, form=-1):
 def set_resident(on=True):
     """Allow (default) or forbid the resident form of single-image solves."""
     check(_lib.load().rdseg_set_resident(1 if on else 0))
+
+
+def set_batched_form(form):
+    """Batched solves with a fixed configuration: 1 = every block of
+    iterations in one persistent cooperative launch, 2 = one launch per block
+    (default)."""
+    check(_lib.load().rdseg_set_batched_form(int(form)))
 
 
 def set_components(on=True):

@@ -326,3 +326,57 @@ def test_tune_lookup_reads_the_cache():
     with pytest.raises(RdsegError):
         rdseg.tune_lookup((1024, 1024), 1.5)
     rdseg.tune_cache_clear()
+
+
+def _fake_batch(shapes):
+    from paper_1807_11534_amd._lib import Image, Shape
+    arr = (Image * len(shapes))()
+    for i, (H, W) in enumerate(shapes):
+        base = (i + 1) << 36
+        arr[i] = Image(base, base + (1 << 32), base + (2 << 32), base + (3 << 32),
+                       Shape(H, W, W), 5.0, 1.0)
+    return arr
+
+
+def test_batched_cache_entries_and_lookup(lib):
+    """Batched entries of the tuning cache ("batched": 1) round-trip through the
+    text and are what rdseg_batched_lookup returns for a batch of that class
+    (size class of its total pixel count, bucket of its active fraction); a
+    single-image entry of the same class and bucket is a different key (host
+    only)."""
+    import json
+
+    from paper_1807_11534_amd import rdseg
+    rdseg.tune_cache_clear()
+    shapes = [(512, 512)] * 4 + [(256, 1024)] * 4   # 2^21 pixels: size class 5
+    arr = _fake_batch(shapes)
+    entries = [
+        {"size_class": 5, "q_bucket": 0, "tile_w": 16, "tile_h": 16, "iters_per_launch": 16,
+         "components": 2, "resident": 1, "batched": 1},
+        {"size_class": 5, "q_bucket": 0, "tile_w": 8, "tile_h": 8, "iters_per_launch": 32,
+         "components": 2, "resident": 2},
+    ]
+    rdseg.tune_cache_import(json.dumps({"version": 1, "entries": entries}))
+    got = json.loads(rdseg.tune_cache_export())["entries"]
+    assert sorted(got, key=lambda e: e.get("batched", 0)) == [entries[1], entries[0]]
+    v = [ctypes.c_int32(0) for _ in range(5)]
+    assert lib.rdseg_batched_lookup(arr, len(shapes), 0.001, *[ctypes.byref(x) for x in v]) == 0
+    assert [x.value for x in v] == [16, 16, 16, 1, 1]
+    # no entry for bucket 4: the fixed choice for dense batches
+    assert lib.rdseg_batched_lookup(arr, len(shapes), 0.9, *[ctypes.byref(x) for x in v]) == 0
+    assert [x.value for x in v[:3]] == [64, 64, 8] and v[4].value == 0
+    assert lib.rdseg_batched_lookup(arr, len(shapes), -0.1, *[ctypes.byref(x) for x in v]) == 1
+    with pytest.raises(Exception):
+        rdseg.tune_cache_import(json.dumps({"version": 1, "entries": [dict(entries[0], batched=2)]}))
+    rdseg.tune_cache_clear()
+
+
+def test_batched_autotune_validation(lib):
+    arr = _fake_batch([(64, 64)])
+    v = [ctypes.c_int32(0) for _ in range(4)]
+    args = lambda probe, form, ws_bytes: (arr, 1, 0.1, 0.125, probe, 0, 0, 0, form,
+                                          ctypes.c_void_p(8), ws_bytes, None,
+                                          *[ctypes.byref(x) for x in v])
+    assert lib.rdseg_autotune_batched(*args(0, 0, 1 << 40)) == 1    # probe_iters < 1
+    assert lib.rdseg_autotune_batched(*args(10, 3, 1 << 40)) == 1   # form out of range
+    assert lib.rdseg_autotune_batched(*args(10, 0, 16)) == 3        # workspace too small

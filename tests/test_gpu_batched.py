@@ -41,16 +41,26 @@ def make_batch(n, seed, lo=17, hi=300):
     return fs, lams, deltas
 
 
+@pytest.mark.parametrize("form", [1, 2])
 @pytest.mark.parametrize("graph", [False, True])
 @pytest.mark.parametrize("cfg", [((32, 32), 4), ((16, 16), 2), ((64, 64), 4)])
-def test_batched_equals_single(rd, graph, cfg):
+def test_batched_equals_single(rd, graph, cfg, form):
+    """Both forms of the iterations (one persistent cooperative launch with
+    grid-wide barriers, one launch per block), eager and captured in a graph,
+    bitwise equal to per-image solves."""
     (tile, ipl) = cfg
     fs, lams, deltas = make_batch(11, 3)
-    print(f"batched graph={graph} tile={tile} ipl={ipl}", flush=True)
+    print(f"batched graph={graph} tile={tile} ipl={ipl} form={form}", flush=True)
     fd = [dev(f) for f in fs]
-    bs = rd.BatchedSolver(fd, lams, deltas, 0.1, 0.125, 45, tile=tile, iters_per_launch=ipl,
-                          graph=graph)
-    outs = bs.run()
+    rd.set_batched_form(form)
+    try:
+        bs = rd.BatchedSolver(fd, lams, deltas, 0.1, 0.125, 45, tile=tile, iters_per_launch=ipl,
+                              graph=graph)
+        outs = bs.run()
+        if graph:
+            outs = bs.run()   # a replay
+    finally:
+        rd.set_batched_form(2)
     for i, f in enumerate(fd):
         u, v, p = rd.solve(f, lams[i], 0.1, 0.125, deltas[i], 45, tile=tile, iters_per_launch=ipl)
         for a, b in zip(outs[i], (u, v, p)):
@@ -111,3 +121,55 @@ def test_batched_disc_rect_workload_subset(rd):
         np.testing.assert_array_equal(host(outs[i][0]), host(u))
         np.testing.assert_array_equal(host(outs[i][2]), host(pp))
     bs.close()
+
+
+def test_batched_form_validation(rd):
+    from paper_1807_11534_amd._lib import RdsegError
+    with pytest.raises(RdsegError):
+        rd.set_batched_form(0)
+    with pytest.raises(RdsegError):
+        rd.set_batched_form(3)
+    rd.set_batched_form(2)
+
+
+def test_batched_autotune_and_library_choice(rd):
+    """rdseg_autotune_batched times every configuration and both forms on the
+    batch and caches its pick under the batch's class; a solve that leaves the
+    choice to the library (eager and as a plan) then runs that configuration
+    and form: bitwise equal to the same batch with the configuration fixed,
+    and to per-image solves."""
+    fs, lams, deltas = make_batch(9, 7)
+    fd = [dev(f) for f in fs]
+    rd.tune_cache_clear()
+    try:
+        tuner = rd.BatchedSolver(fd, lams, deltas, 0.1, 0.125, 24, tile=None,
+                                 iters_per_launch=0, graph=False)
+        t = tuner.autotune(probe_iters=8)
+        (tile, ipl), form = t, t.form
+        print(f"batched autotune: tile={tile} ipl={ipl} form={form}", flush=True)
+        assert form in (1, 2)
+        n_px = sum(f.size for f in fs)
+        q = sum(float((np.abs(f.astype(np.float64)) < d).sum()) for f, d in zip(fs, deltas)) / n_px
+        lk = tuner.lookup(q)
+        assert lk.cached and tuple(lk[0]) == tuple(tile) and lk[1] == ipl and lk.form == form
+        lib_out = [tuple(host(x) for x in o) for o in tuner.run()]
+        plan = rd.BatchedSolver(fd, lams, deltas, 0.1, 0.125, 24, tile=None, iters_per_launch=0,
+                                graph=True)
+        plan.run()
+        plan_out = [tuple(host(x) for x in o) for o in plan.run()]
+        plan.close()
+        rd.set_batched_form(form)
+        fixed = rd.BatchedSolver(fd, lams, deltas, 0.1, 0.125, 24, tile=tuple(tile),
+                                 iters_per_launch=ipl, graph=False)
+        fixed_out = [tuple(host(x) for x in o) for o in fixed.run()]
+        for a, b, c in zip(lib_out, plan_out, fixed_out):
+            for x, y, z in zip(a, b, c):
+                np.testing.assert_array_equal(x, z)
+                np.testing.assert_array_equal(y, z)
+        for i in (0, 4):
+            u, v, p = rd.solve(fd[i], lams[i], 0.1, 0.125, deltas[i], 24, tile=tuple(tile),
+                               iters_per_launch=ipl)
+            np.testing.assert_array_equal(lib_out[i][0], host(u))
+    finally:
+        rd.set_batched_form(2)
+        rd.tune_cache_clear()
