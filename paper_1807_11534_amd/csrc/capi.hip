@@ -1992,8 +1992,6 @@ rdseg_status rdseg_backward(const float* f, rdseg_shape s, const rdseg_params* p
     BackWs w = carve_back(ws, s, ce);
     hipStream_t st = static_cast<hipStream_t>(stream);
     Geo g = geo_of(s);
-    const int fci = config_index(kAdjTile, kAdjTile, 2);
-    if (fci < 0) return fail(RDSEG_ERR_ARG, "recompute configuration missing");
     float* nost[3] = {nullptr, nullptr, nullptr};
     ImgDesc d = make_desc(f, s, prm->lambda, prm->theta, prm->delta, nullptr, nullptr, nullptr,
                           w.c, nost, nullptr, nullptr, kAdjTile, kAdjTile);
@@ -2051,13 +2049,16 @@ rdseg_status rdseg_backward(const float* f, rdseg_shape s, const rdseg_params* p
             return j == 0 ? const_cast<float*>(tape) + (int64_t)sg * 3 * plane
                           : w.seg + (int64_t)(j - 1) * 3 * plane;
         };
-        // recompute the forward states k0+1 .. k0+len-1 of this segment
-        for (int j = 0; j + 1 < len; ++j) {
+        // recompute the forward states k0+1 .. k0+len-1 of this segment: up
+        // to 8 steps a launch, each step's state written to its slot
+        for (int j = 0; j + 1 < len; j += 8) {
+            const int nit = std::min(8, len - 1 - j);
             ImgDesc dr = d;
             dr.st[1][0] = slot(j); dr.st[1][1] = slot(j) + plane; dr.st[1][2] = slot(j) + 2 * plane;
-            dr.st[0][0] = slot(j + 1); dr.st[0][1] = slot(j + 1) + plane; dr.st[0][2] = slot(j + 1) + 2 * plane;
-            if (launch_iterate(fci, &dr, nullptr, false, w.queue, w.totals, nm, 1, 1, false, theta,
-                               inv_theta, tau, st))
+            float* last = slot(j + nit);
+            dr.st[0][0] = last; dr.st[0][1] = last + plane; dr.st[0][2] = last + 2 * plane;
+            if (launch_recompute(dr, w.queue, w.totals, nm, 1, nit, theta, inv_theta, tau,
+                                 slot(j + 1), 3 * plane, plane, st))
                 return RDSEG_ERR_HIP;
         }
         // reverse sweep

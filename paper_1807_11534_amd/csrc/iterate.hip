@@ -79,14 +79,19 @@ __global__ __launch_bounds__(256) void k_init(ImgDesc d0, const ImgDesc* __restr
 // dmax (bit patterns of non-negative floats order like their values).
 enum { MODE_DENSE = 0, MODE_FAST = 1, MODE_COMPACT = 2, MODE_DENSE_IN = 3 };
 
-template <int BX, int BY, int IT, int NT, int MODE, bool STOP>
+// TAPE: after outer iteration s of the call, the state (v, p_x, p_y) of the
+// tile's RD cells is also written to tape + s * tape_step (planes tape_plane
+// apart): the adjoint's recompute of a checkpoint segment.
+template <int BX, int BY, int IT, int NT, int MODE, bool STOP, bool TAPE = false>
 __device__ __forceinline__ void run_iterations(float* __restrict__ sPX, float* __restrict__ sPY,
                                                float* __restrict__ sW, const int* idx, float* rv,
                                                float* rpx, float* rpy, const float* rc,
                                                const uint32_t* fl, const int* gi,
                                                float* __restrict__ U, int nit, int write_u,
                                                float theta, float inv_theta, float tau, float* ru,
-                                               bool check, uint32_t& dmax, int inner) {
+                                               bool check, uint32_t& dmax, int inner,
+                                               float* __restrict__ tape = nullptr,
+                                               int64_t tape_step = 0, int64_t tape_plane = 0) {
     constexpr int RX = BX + 2 * IT + 1;
     constexpr int RY = BY + 2 * IT + 1;
     constexpr int RC = RX * RY;
@@ -171,6 +176,12 @@ __device__ __forceinline__ void run_iterations(float* __restrict__ sPX, float* _
                         ru[j] = u;
                     }
                     rv[j] = vn;
+                    if (TAPE && (fl[j] & CF_OUT)) {
+                        float* __restrict__ ts = tape + (int64_t)(it / inner) * tape_step + gi[j];
+                        ts[0] = vn;
+                        ts[tape_plane] = rpx[j];
+                        ts[2 * tape_plane] = rpy[j];
+                    }
                     if (last) {
                         if (write_u && (fl[j] & CF_OUT)) U[gi[j]] = u;
                     } else {
@@ -219,14 +230,16 @@ __device__ __forceinline__ uint32_t cell_flags(bool act, int rx, int ry, int gx,
 // *diff_slot (one atomicMax per wave).
 // One launch's work (the kernel below; the persistent form runs it once per
 // block of iterations).
-template <int BX, int BY, int IT, int NT, bool BATCHED, bool STOP, bool FAST_OK, bool COMPACT_OK>
+template <int BX, int BY, int IT, int NT, bool BATCHED, bool STOP, bool FAST_OK, bool COMPACT_OK,
+          bool TAPE = false>
 __device__ __forceinline__ void iterate_pass(ImgDesc d0, const ImgDesc* __restrict__ descs,
                                              const int2* __restrict__ queue,
                                              const int32_t* __restrict__ n_queue, int in_buf,
                                              int nit, int write_u, float theta, float inv_theta,
                                              float tau, const uint32_t* __restrict__ skip_slot,
                                              uint32_t* __restrict__ diff_slot, double tol,
-                                             int inner) {
+                                             int inner, float* __restrict__ tape = nullptr,
+                                             int64_t tape_step = 0, int64_t tape_plane = 0) {
     if (STOP && skip_slot && (double)__uint_as_float(*skip_slot) <= tol) return;
     constexpr int RX = BX + 2 * IT + 1;
     constexpr int RY = BY + 2 * IT + 1;
@@ -339,20 +352,20 @@ __device__ __forceinline__ void iterate_pass(ImgDesc d0, const ImgDesc* __restri
         // does the region reach the grid's last column or row?
         const bool edge = ox + RX >= W || oy + RY >= H;
         if (fast) {
-            run_iterations<BX, BY, IT, NT, MODE_FAST, STOP>(sPX, sPY, sW, idx, rv, rpx, rpy, rc,
+            run_iterations<BX, BY, IT, NT, MODE_FAST, STOP, TAPE>(sPX, sPY, sW, idx, rv, rpx, rpy, rc,
                                                             fl, gi, d.u, nit, write_u, theta,
-                                                            inv_theta, tau, ru, check, dmax, inner);
+                                                            inv_theta, tau, ru, check, dmax, inner, tape, tape_step, tape_plane);
         } else if (!COMPACT_OK) {
             if (edge)
-                run_iterations<BX, BY, IT, NT, MODE_DENSE, STOP>(sPX, sPY, sW, idx, rv, rpx, rpy,
+                run_iterations<BX, BY, IT, NT, MODE_DENSE, STOP, TAPE>(sPX, sPY, sW, idx, rv, rpx, rpy,
                                                                  rc, fl, gi, d.u, nit, write_u,
                                                                  theta, inv_theta, tau, ru,
-                                                                 check, dmax, inner);
+                                                                 check, dmax, inner, tape, tape_step, tape_plane);
             else
-                run_iterations<BX, BY, IT, NT, MODE_DENSE_IN, STOP>(sPX, sPY, sW, idx, rv, rpx,
+                run_iterations<BX, BY, IT, NT, MODE_DENSE_IN, STOP, TAPE>(sPX, sPY, sW, idx, rv, rpx,
                                                                     rpy, rc, fl, gi, d.u, nit,
                                                                     write_u, theta, inv_theta,
-                                                                    tau, ru, check, dmax, inner);
+                                                                    tau, ru, check, dmax, inner, tape, tape_step, tape_plane);
         } else {
             // count the RD cells of the region (ascending list offsets)
             if (lane == 0) {
@@ -378,14 +391,14 @@ __device__ __forceinline__ void iterate_pass(ImgDesc d0, const ImgDesc* __restri
             const int n_act = sCnt[NCNT];
             if (5 * n_act >= 2 * RC) {   // dense enough: every region cell
                 if (edge)
-                    run_iterations<BX, BY, IT, NT, MODE_DENSE, STOP>(sPX, sPY, sW, idx, rv, rpx,
+                    run_iterations<BX, BY, IT, NT, MODE_DENSE, STOP, TAPE>(sPX, sPY, sW, idx, rv, rpx,
                                                                      rpy, rc, fl, gi, d.u, nit,
                                                                      write_u, theta, inv_theta,
-                                                                     tau, ru, check, dmax, inner);
+                                                                     tau, ru, check, dmax, inner, tape, tape_step, tape_plane);
                 else
-                    run_iterations<BX, BY, IT, NT, MODE_DENSE_IN, STOP>(
+                    run_iterations<BX, BY, IT, NT, MODE_DENSE_IN, STOP, TAPE>(
                         sPX, sPY, sW, idx, rv, rpx, rpy, rc, fl, gi, d.u, nit, write_u, theta,
-                        inv_theta, tau, ru, check, dmax, inner);
+                        inv_theta, tau, ru, check, dmax, inner, tape, tape_step, tape_plane);
             } else {
                 const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
@@ -418,10 +431,10 @@ __device__ __forceinline__ void iterate_pass(ImgDesc d0, const ImgDesc* __restri
                     }
                 }
                 __syncthreads();   // parked v read before the prologue overwrites it
-                run_iterations<BX, BY, IT, NT, MODE_COMPACT, STOP>(sPX, sPY, sW, idx, rv, rpx, rpy,
+                run_iterations<BX, BY, IT, NT, MODE_COMPACT, STOP, TAPE>(sPX, sPY, sW, idx, rv, rpx, rpy,
                                                                    rc, fl, gi, d.u, nit, write_u,
                                                                    theta, inv_theta, tau, ru,
-                                                                   check, dmax, inner);
+                                                                   check, dmax, inner, tape, tape_step, tape_plane);
             }
         }
         float* __restrict__ Vo = d.st[out_buf][0];
@@ -455,6 +468,23 @@ __global__ __launch_bounds__(NT) void k_iterate(ImgDesc d0, const ImgDesc* __res
     iterate_pass<BX, BY, IT, NT, BATCHED, STOP, FAST_OK, COMPACT_OK>(
         d0, descs, queue, n_queue, in_buf, nit, write_u, theta, inv_theta, tau, skip_slot,
         diff_slot, tol, inner);
+}
+
+// The adjoint's recompute of a checkpoint segment: `nit` outer iterations of
+// the single-image blocked kernel from state buffer in_buf, with the state
+// after each iteration s written to tape + s * tape_step (the segment's slots)
+// for the queued tiles' RD pixels; the arithmetic and buffer parities of
+// k_iterate, so the states are bitwise those of single-step launches.
+template <int BX, int BY, int IT, int NT>
+__global__ __launch_bounds__(NT) void k_recompute(ImgDesc d0, const int2* __restrict__ queue,
+                                                  const int32_t* __restrict__ n_queue,
+                                                  int in_buf, int nit, float theta,
+                                                  float inv_theta, float tau,
+                                                  float* __restrict__ tape, int64_t tape_step,
+                                                  int64_t tape_plane) {
+    iterate_pass<BX, BY, IT, NT, false, false, (BX >= 64), (BX < 64), true>(
+        d0, nullptr, queue, n_queue, in_buf, nit, 0, theta, inv_theta, tau, nullptr, nullptr,
+        0.0, 1, tape, tape_step, tape_plane);
 }
 
 // Grid-wide barrier of a cooperative launch: every workgroup adds one to
@@ -1000,6 +1030,36 @@ int launch_iterate(int ci, const ImgDesc* d0, const ImgDesc* descs, bool batched
                        in_buf, nit, write_u ? 1 : 0, theta, inv_theta, tau,
                        stop ? stop->skip_slot : nullptr, stop ? stop->diff_slot : nullptr,
                        stop ? stop->tol : 0.0, inner);
+    RDSEG_HIP_CHECK(hipGetLastError());
+    return 0;
+}
+
+int launch_recompute(const ImgDesc& d, const int2* queue, const int32_t* n_queue,
+                     int64_t max_items, int in_buf, int nit, float theta, float inv_theta,
+                     float tau, float* tape, int64_t tape_step, int64_t tape_plane,
+                     hipStream_t st) {
+    constexpr int BX = 32, BY = 32, IT = 8, NT = 512;
+    if (nit < 1 || nit > IT) {
+        set_error("recompute: 1 <= nit <= 8");
+        return 1;
+    }
+    static std::atomic<int> cap{0};
+    int g = cap.load(std::memory_order_relaxed);
+    if (g == 0) {
+        g = persistent_blocks(reinterpret_cast<const void*>(k_recompute<BX, BY, IT, NT>), NT, 0);
+        if (g <= 0) {
+            set_error("occupancy query failed for the recompute kernel");
+            return 4;
+        }
+        cap.store(g, std::memory_order_relaxed);
+    }
+    int64_t grid = g;
+    if (max_items < grid) grid = max_items;
+    grid = ((grid + 7) / 8) * 8;
+    if (grid < 8) grid = 8;
+    hipLaunchKernelGGL((k_recompute<BX, BY, IT, NT>), dim3((unsigned)grid), dim3(NT), 0, st, d,
+                       queue, n_queue, in_buf, nit, theta, inv_theta, tau, tape, tape_step,
+                       tape_plane);
     RDSEG_HIP_CHECK(hipGetLastError());
     return 0;
 }
