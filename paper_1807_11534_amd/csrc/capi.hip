@@ -1070,7 +1070,8 @@ rdseg_status choose_batch(const rdseg_image* imgs, int32_t n, double theta, int3
 }
 
 // ------------------------------------------------------------------ backward
-constexpr int kAdjTile = 32;   // macro tile of the reverse sweep and its recompute
+constexpr int kAdjTile = 32;        // macro tile of the reverse sweep
+constexpr int kRecomputeTile = 16;  // macro tile of the segment recompute (8 steps a launch)
 
 struct BackWs {
     float* c;
@@ -1085,6 +1086,8 @@ struct BackWs {
     int2* queue;
     int32_t* tstate;
     int32_t* totals;
+    int2* rqueue;      // the recompute's queue (its own macro tile)
+    int32_t* rtotals;
     double* red;       // reduction partials
     double* out4;
     CompWs comp;       // small-component path
@@ -1107,6 +1110,8 @@ BackWs carve_back(void* base, const rdseg_shape& s, int ce) {
     w.queue = cv.take<int2>(g.nt);
     w.tstate = cv.take<int32_t>(g.nt);
     w.totals = cv.take<int32_t>(4);
+    w.rqueue = cv.take<int2>(g.nt);
+    w.rtotals = cv.take<int32_t>(4);
     w.red = cv.take<double>(reduce_partials(s.H));
     w.out4 = cv.take<double>(4);
     w.comp.lab = cv.take<int32_t>(g.plane);
@@ -2009,6 +2014,13 @@ rdseg_status rdseg_backward(const float* f, rdseg_shape s, const rdseg_params* p
     if (launch_macro_queue(&d, nullptr, off, 1, nm, kAdjTile, kAdjTile, w.masks, qs, w.queue,
                            w.totals, g.nt, nullptr, nullptr, st))
         return RDSEG_ERR_HIP;
+    // the recompute's own queue, of its own macro tile
+    ImgDesc dre = make_desc(f, s, prm->lambda, prm->theta, prm->delta, nullptr, nullptr, nullptr,
+                            w.c, nost, nullptr, nullptr, kRecomputeTile, kRecomputeTile);
+    const int64_t nmr = macro_count(s, kRecomputeTile, kRecomputeTile);
+    if (launch_macro_queue(&dre, nullptr, off, 1, nmr, kRecomputeTile, kRecomputeTile, w.masks,
+                           qs, w.rqueue, w.rtotals, g.nt, nullptr, nullptr, st))
+        return RDSEG_ERR_HIP;
     if (launch_fill(w.sacc, s.H, s.W, (int)s.ld, 0.0f, st)) return RDSEG_ERR_HIP;
     const float theta = (float)prm->theta, inv_theta = (float)(1.0 / prm->theta);
     const float tau = (float)prm->tau;
@@ -2053,11 +2065,11 @@ rdseg_status rdseg_backward(const float* f, rdseg_shape s, const rdseg_params* p
         // to 8 steps a launch, each step's state written to its slot
         for (int j = 0; j + 1 < len; j += 8) {
             const int nit = std::min(8, len - 1 - j);
-            ImgDesc dr = d;
+            ImgDesc dr = dre;
             dr.st[1][0] = slot(j); dr.st[1][1] = slot(j) + plane; dr.st[1][2] = slot(j) + 2 * plane;
             float* last = slot(j + nit);
             dr.st[0][0] = last; dr.st[0][1] = last + plane; dr.st[0][2] = last + 2 * plane;
-            if (launch_recompute(dr, w.queue, w.totals, nm, 1, nit, theta, inv_theta, tau,
+            if (launch_recompute(dr, w.rqueue, w.rtotals, nmr, 1, nit, theta, inv_theta, tau,
                                  slot(j + 1), 3 * plane, plane, st))
                 return RDSEG_ERR_HIP;
         }

@@ -1038,7 +1038,7 @@ int launch_recompute(const ImgDesc& d, const int2* queue, const int32_t* n_queue
                      int64_t max_items, int in_buf, int nit, float theta, float inv_theta,
                      float tau, float* tape, int64_t tape_step, int64_t tape_plane,
                      hipStream_t st) {
-    constexpr int BX = 32, BY = 32, IT = 8, NT = 512;
+    constexpr int BX = 16, BY = 16, IT = 8, NT = 512;
     if (nit < 1 || nit > IT) {
         set_error("recompute: 1 <= nit <= 8");
         return 1;

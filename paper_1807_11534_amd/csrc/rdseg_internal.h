@@ -256,8 +256,8 @@ int launch_iterate(int cfg_index, const ImgDesc* d0, const ImgDesc* descs, bool 
 // bitwise the separate launches).  *bar is cleared first; *status is set if
 // a barrier's wait expires.  Returns -1 when the form cannot be launched
 // (the caller then enqueues separate launches), > 0 on a HIP error.
-// The adjoint's recompute: nit (<= 8) outer iterations of the 32x32 / 8
-// blocked kernel over the queued 32x32 macro tiles from state buffer in_buf
+// The adjoint's recompute: nit (<= 8) outer iterations of the 16x16 / 8
+// blocked kernel over the queued 16x16 macro tiles from state buffer in_buf
 // (writing 1 - in_buf), with the state after iteration s also written to
 // tape + s * tape_step (v, p_x, p_y planes tape_plane apart) on RD pixels.
 int launch_recompute(const ImgDesc& d, const int2* queue, const int32_t* n_queue,
