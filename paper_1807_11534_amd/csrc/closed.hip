@@ -46,7 +46,9 @@ __global__ __launch_bounds__(64) void k_closed(ImgDesc d0, const ImgDesc* __rest
         const int gx = tx * 8 + x, gy = ty * 8 + y;
         const bool inb = gx < d.W && gy < d.H;
         const int g = gy * d.ld + gx;
-        const float c = inb ? d.c[g] : __builtin_inff();
+        // a batch keeps no c plane: c from f (the function that fills it)
+        auto c_at = [&](int gg) { return BATCHED ? c_of(d.f[gg], d.delta, d.tl) : d.c[gg]; };
+        const float c = inb ? c_at(g) : __builtin_inff();
         const bool act = c_active(c);
         float v = heav_from_c(c), px = 0.0f, py = 0.0f;
         if (act) {
@@ -60,12 +62,12 @@ __global__ __launch_bounds__(64) void k_closed(ImgDesc d0, const ImgDesc* __rest
         // w of the ring cells right of x = 7 and below y = 7 (frozen)
         float wR = 0.0f, wD = 0.0f;
         if (x == 7) {
-            float cr = (gx + 1 < d.W && gy < d.H) ? d.c[g + 1] : __builtin_inff();
+            float cr = (gx + 1 < d.W && gy < d.H) ? c_at(g + 1) : __builtin_inff();
             if (c_active(cr)) cr = __builtin_inff();
             wR = w_of(0.0f, heav_from_c(cr), inv_theta, false);
         }
         if (y == 7) {
-            float cd = (gx < d.W && gy + 1 < d.H) ? d.c[g + d.ld] : __builtin_inff();
+            float cd = (gx < d.W && gy + 1 < d.H) ? c_at(g + d.ld) : __builtin_inff();
             if (c_active(cd)) cd = __builtin_inff();
             wD = w_of(0.0f, heav_from_c(cd), inv_theta, false);
         }

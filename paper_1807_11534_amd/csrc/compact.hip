@@ -201,10 +201,11 @@ __device__ __forceinline__ __attribute__((address_space(1))) T* as_global(T* p) 
 // of 4 * `per_wave` strips, its waves every fourth one, so a batch looks up
 // the image of a wave's first strip once and then walks forward (a lookup per
 // strip is a chain of dependent loads that left the batched passes latency
-// bound).  Writes c, u and the caller's
-// state buffer (v, p_x, p_y) on every pixel, the workspace's state buffer
-// only on RD pixels: no kernel reads a frozen pixel's state from it.  With
-// d.u == NULL only c and the masks are written.
+// bound).  Writes u and the caller's state buffer (v, p_x, p_y) on every
+// pixel, the workspace's state buffer only on RD pixels (no kernel reads a
+// frozen pixel's state from it) and, for a single image, c (a batch's kernels
+// derive c from f: one plane less to write).  With d.u == NULL only c and the
+// masks are written.
 template <bool BATCHED>
 __global__ __launch_bounds__(256) void k_prepare(ImgDesc d0, const ImgDesc* __restrict__ descs,
                                                  OffTables off, int n_img, int64_t n_strips,
@@ -311,7 +312,7 @@ __global__ __launch_bounds__(256) void k_prepare(ImgDesc d0, const ImgDesc* __re
             const int y = ty * 8 + r;
             if (x < W && y < H) {
                 const int64_t g = (int64_t)y * d.ld + x;
-                C[g] = cr[r];
+                if (!BATCHED) C[g] = cr[r];   // a batch derives c from f where it needs it
                 if (d.u) {
                     U[g] = u0r[r];
                     V0[g] = v0r[r];

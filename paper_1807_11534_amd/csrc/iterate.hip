@@ -320,7 +320,9 @@ __device__ __forceinline__ void iterate_pass(ImgDesc d0, const ImgDesc* __restri
                 // trip); state read off RD is discarded by the selects below
                 float c = __builtin_inff(), v = 0.0f, px = 0.0f, py = 0.0f, uo = 0.0f;
                 if (inb) {
-                    c = C[g];
+                    // a batch keeps no c plane: c from f (the same function
+                    // that fills the plane of a single image)
+                    c = BATCHED ? c_of(d.f[g], d.delta, d.tl) : C[g];
                     v = Vi[g];
                     px = PXi[g];
                     py = PYi[g];
