@@ -310,7 +310,20 @@ __global__ __launch_bounds__(256) void k_components(ImgDesc d, CompWs w, const i
 // slots of seg that the tile path uses.  The adjoint state (pbar, vbar) and
 // the clamp-adjoint sum stay in registers; the sum goes to sacc and vbar^0 to
 // vb_out at the end.  Results are bitwise those of the tile path.
-__global__ __launch_bounds__(256) void k_adj_components(
+//
+// REG (a separate instantiation, so that its registers do not weigh on the
+// LDS forms): no LDS at all, for many waves.  A first forward pass over the
+// segment keeps a checkpoint every kSubLen states in registers; then per
+// sub-segment (last first) a second forward pass from its checkpoint keeps
+// the dual-update outputs and u of its at most kSubLen steps in registers and
+// the reverse steps read them.  The occupancy follows the registers instead
+// of 22 KB of LDS per wave.  The same forward and reverse arithmetic, so
+// bitwise the other forms.
+constexpr int kSubLen = 8;   // steps per sub-segment
+constexpr int kSubMax = 5;   // sub-segments per segment: ckpt_every <= 40
+
+template <bool REG>
+__global__ __launch_bounds__(256) void k_adj_components_t(
     ImgDesc d, CompWs w, const int64_t* npix, const float* __restrict__ tape,
     float* __restrict__ seg, int K, int ce, const float* __restrict__ grad_u,
     const float* __restrict__ grad_v, float* __restrict__ vb_out, float* __restrict__ sacc,
@@ -425,7 +438,73 @@ __global__ __launch_bounds__(256) void k_adj_components(
             u = u_step(v, div_p(o.px, left(o.px), o.py, up(o.py)), theta);
         };
         const int nseg = (K + ce - 1) / ce;
-        if (duo) {
+        if (REG) {
+            for (int sg = nseg - 1; sg >= 0; --sg) {
+                const int k0 = sg * ce;
+                const int len = min(ce, K - k0);
+                const int nb = (len + kSubLen - 1) / kSubLen;
+                float cpv[kSubMax], cpx[kSubMax], cpy[kSubMax];
+                {
+                    float v = 0.0f, px = 0.0f, py = 0.0f;   // the checkpoint, state k0
+                    if (mine) {
+                        const float* __restrict__ s0 = tape + (int64_t)sg * 3 * plane;
+                        v = s0[gg];
+                        px = s0[plane + gg];
+                        py = s0[2 * plane + gg];
+                    }
+#pragma unroll
+                    for (int b = 0; b < kSubMax; ++b) {
+                        cpv[b] = v;
+                        cpx[b] = px;
+                        cpy[b] = py;
+                        if (b + 1 < nb) {   // uniform
+                            for (int j = 0; j < kSubLen; ++j) {
+                                DualOut o;
+                                float u;
+                                forward_step(v, px, py, o, u);
+                                px = o.px;
+                                py = o.py;
+                                v = v_step(u, c);
+                            }
+                        }
+                    }
+                }
+                for (int b = nb - 1; b >= 0; --b) {
+                    const int j0 = b * kSubLen;
+                    const int sl = min(kSubLen, len - j0);
+                    float v = cpv[0], px = cpx[0], py = cpy[0];
+#pragma unroll
+                    for (int q = 1; q < kSubMax; ++q) {
+                        if (q == b) {
+                            v = cpv[q];
+                            px = cpx[q];
+                            py = cpy[q];
+                        }
+                    }
+                    float opx[kSubLen], opy[kSubLen], ogx[kSubLen], ogy[kSubLen], om[kSubLen],
+                        ou[kSubLen];
+#pragma unroll
+                    for (int i = 0; i < kSubLen; ++i) {
+                        opx[i] = 0.0f; opy[i] = 0.0f; ogx[i] = 0.0f; ogy[i] = 0.0f;
+                        om[i] = 0.0f; ou[i] = 0.0f;
+                        if (i < sl) {   // uniform
+                            DualOut o;
+                            float u;
+                            forward_step(v, px, py, o, u);
+                            opx[i] = o.px; opy[i] = o.py; ogx[i] = o.gx; ogy[i] = o.gy;
+                            om[i] = o.m; ou[i] = u;
+                            px = o.px;
+                            py = o.py;
+                            v = v_step(u, c);
+                        }
+                    }
+#pragma unroll
+                    for (int i = kSubLen - 1; i >= 0; --i)
+                        if (i < sl) reverse_step(k0 + j0 + i + 1, opx[i], opy[i], ogx[i], ogy[i],
+                                                 om[i], ou[i]);
+                }
+            }
+        } else if (duo) {
             auto fwd_store = [&](float* __restrict__ base, int j, float& v, float& px, float& py) {
                 DualOut o;
                 float u;
@@ -664,7 +743,7 @@ int launch_adj_components(const ImgDesc& d, const CompWs& w, const int64_t* npix
             lds_limit = v;
         g_adj_lds_limit.store(lds_limit, std::memory_order_relaxed);
     }
-    const void* fn = reinterpret_cast<const void*>(k_adj_components);
+    const void* fn = reinterpret_cast<const void*>(k_adj_components_t<false>);
     auto cap_of = [&](int threads, size_t bytes) {
         return bytes > (size_t)lds_limit ? 0 : persistent_blocks(fn, threads, bytes);
     };
@@ -684,6 +763,26 @@ int launch_adj_components(const ImgDesc& d, const CompWs& w, const int64_t* npix
         (void)hipGetLastError();
         mode = 2;   // the larger allocation is not available: one wave, one buffer
     }
+    // many waves: the register form (no LDS, occupancy by registers) in place
+    // of the states in LDS (22 KB a wave at ckpt_every = 30: seven waves a CU)
+    if (mode == 1 && ce <= kSubLen * kSubMax) {
+        static std::atomic<int> reg_grid{0};
+        const void* rfn = reinterpret_cast<const void*>(k_adj_components_t<true>);
+        int grid = reg_grid.load(std::memory_order_relaxed);
+        if (grid == 0) {
+            grid = persistent_blocks(rfn, 256, 0);
+            if (grid <= 0) {
+                set_error("occupancy query failed for the component adjoint kernel");
+                return 4;
+            }
+            reg_grid.store(grid, std::memory_order_relaxed);
+        }
+        hipLaunchKernelGGL(k_adj_components_t<true>, dim3((unsigned)grid), dim3(256), 0, st, d,
+                           w, npix, tape, seg, K, ce, grad_u, grad_v, vb_out, sacc, theta,
+                           inv_theta, tau, 0);
+        RDSEG_HIP_CHECK(hipGetLastError());
+        return 0;
+    }
     if (mode > 0) {
         const int threads = mode == 4 ? 128 : 64;
         const size_t lds = mode == 4 ? 2 * rich : (mode == 2 ? rich : lean);
@@ -692,7 +791,7 @@ int launch_adj_components(const ImgDesc& d, const CompWs& w, const int64_t* npix
             set_error("occupancy query failed for the component adjoint kernel");
             return 4;
         }
-        hipLaunchKernelGGL(k_adj_components, dim3((unsigned)grid), dim3(threads), lds, st, d, w,
+        hipLaunchKernelGGL(k_adj_components_t<false>, dim3((unsigned)grid), dim3(threads), lds, st, d, w,
                            npix, tape, seg, K, ce, grad_u, grad_v, vb_out, sacc, theta,
                            inv_theta, tau, mode);
         RDSEG_HIP_CHECK(hipGetLastError());
@@ -706,7 +805,7 @@ int launch_adj_components(const ImgDesc& d, const CompWs& w, const int64_t* npix
             return 4;
         }
     }
-    hipLaunchKernelGGL(k_adj_components, dim3((unsigned)g_adj_comp_grid), dim3(256), 0, st, d, w,
+    hipLaunchKernelGGL(k_adj_components_t<false>, dim3((unsigned)g_adj_comp_grid), dim3(256), 0, st, d, w,
                        npix, tape, seg, K, ce, grad_u, grad_v, vb_out, sacc, theta, inv_theta,
                        tau, 0);
     RDSEG_HIP_CHECK(hipGetLastError());

@@ -269,7 +269,8 @@ def test_backward_full_size_differentiation_workload(rd):
 @pytest.mark.parametrize("case", [("config5_512", 0.1, 300, 30), ("config5_512", 0.5, 120, 30),
                                   ("ragged", 0.4, 90, 30), ("ragged", 0.4, 90, 7),
                                   ("ragged", 0.4, 130, 60), ("ragged", 0.4, 25, 30),
-                                  ("config5_512", 0.5, 120, 100)])
+                                  ("config5_512", 0.5, 120, 100),
+                                  ("config5_2048", 0.5, 60, 30), ("config5_2048", 0.5, 44, 30)])
 def test_component_reverse_matches_tile_path(rd, case):
     """RD components of at most 64 pixels in both directions: the component
     forward writes the same checkpoints (on RD, where the tape is defined) and
@@ -278,10 +279,15 @@ def test_component_reverse_matches_tile_path(rd, case):
     (with few waves, ckpt_every 7 and 30 keep each step's dual-update outputs
     in LDS, with a second wave running the next segment's forward when there
     are several segments; many waves or ckpt_every 60 keep the states; 100 the
-    per-pixel slots),
+    per-pixel slots; at 2048^2, ~35K waves, the register form: checkpoints
+    every 8 states and each 8-step sub-segment's dual-update outputs in
+    registers, ragged sub-segments included),
     with a fitting-term gradient and both adjoint inputs."""
     name, frac, K, ce = case
-    if name == "ragged":
+    if name == "config5_2048":
+        prob = synth.config5(size=2048)
+        f, z, target = prob.f, prob.z, prob.mask.astype(np.float32)
+    elif name == "ragged":
         f = synth.smooth_field(173, 211, 45, noise=0.35)
         z = synth.smooth_field(173, 211, 46, noise=0.1)
         target = (f < 0).astype(np.float32)
