@@ -497,6 +497,15 @@ rdseg_status rdseg_set_batched_form(int32_t form);
  * component path.  Process-wide. */
 rdseg_status rdseg_set_components(int32_t on);
 
+/* The reverse sweep of rdseg_backward's tile path (the RD pixels outside
+ * the component path) runs `steps` reverse iterations per launch on tile x
+ * tile macro tiles with a halo of 3 * steps pixels (the adjoint state stays
+ * on chip between the steps; each step reads its stored forward state).
+ * Forms: (32, 1), (16, 2), (16, 4), (32, 2), (32, 4); 0 selects the default
+ * (32 and 2).  Results are bitwise equal across forms.  RDSEG_ERR_ARG for a
+ * form that has no kernel.  Process-wide. */
+rdseg_status rdseg_set_adjoint_form(int32_t tile, int32_t steps);
+
 /* The autotuner's cache (the choices of rdseg_autotune, keyed by size class
  * and active-fraction bucket, read by solves that let the library choose) as
  * JSON text, so that a tuning run can be kept and reloaded in a later process:

@@ -122,6 +122,7 @@ SIGNATURES = {
     "rdseg_set_resident": (ctypes.c_int, [_i32]),
     "rdseg_set_components": (ctypes.c_int, [_i32]),
     "rdseg_set_batched_form": (ctypes.c_int, [_i32]),
+    "rdseg_set_adjoint_form": (ctypes.c_int, [_i32, _i32]),
     "rdseg_tune_cache_export": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_size_t,
                                                ctypes.POINTER(ctypes.c_size_t)]),
     "rdseg_tune_cache_import": (ctypes.c_int, [ctypes.c_char_p]),

@@ -204,6 +204,9 @@ struct TimingRec {
 
 std::atomic<bool> g_resident_on{true};
 std::atomic<bool> g_components_on{true};
+// form of the adjoint's reverse sweep: macro tile and steps per launch
+std::atomic<int> g_adj_tile{32};
+std::atomic<int> g_adj_steps{2};
 // batched solves: 1 = every block in one persistent cooperative launch,
 // 2 = one launch per block of iterations
 std::atomic<int> g_batch_form{2};
@@ -547,7 +550,7 @@ rdseg_status enqueue_iterations(SolvePlanArgs& a) {
     for (int j = 0; j < L; ++j) {
         int in_buf = (L - j) % 2;
         if (a.tape && seg < seg_start.size() && seg_start[seg] == j) {
-            int rc = launch_state_copy(*a.d0, in_buf, a.tape + (int64_t)seg * 3 * plane, true, a.st);
+            int rc = launch_state_copy(*a.d0, in_buf, a.tape + (int64_t)seg * 3 * plane, a.st);
             if (rc) return RDSEG_ERR_HIP;
             ++seg;
         }
@@ -2044,11 +2047,25 @@ rdseg_status rdseg_backward(const float* f, rdseg_shape s, const rdseg_params* p
     ab.sacc = w.sacc;
     const int nseg = (K + ce - 1) / ce;
     const int64_t plane = g.plane;
+    // the reverse kernel: its macro tile (16: the recompute's queue) and
+    // steps per launch
+    const int adj_tile = g_adj_tile.load();
+    const int adj_ns = g_adj_steps.load();
+    const int adj_ai = adj_config_find(adj_tile, adj_ns);
+    if (adj_ai < 0) return fail(RDSEG_ERR_ARG, "no reverse kernel for the selected form");
+    const bool adj_small = adj_tile == kRecomputeTile;
+    // vbar^0 ends in buffer (number of reverse launches) % 2; the component
+    // reverse writes its pixels' vbar^0 there too
+    int final_buf = 0;
+    for (int sg = 0; sg < nseg; ++sg) {
+        const int len = std::min(ce, K - sg * ce);
+        final_buf ^= ((len + adj_ns - 1) / adj_ns) & 1;
+    }
     hipEvent_t join = nullptr;
     if (comps) {
         rdseg_status rc = closed_beside(st, &join, [&](hipStream_t cs) {
             return launch_adj_components(d, w.comp, w.npix, tape, w.seg, K, ce, grad_u, grad_v,
-                                         ab.vb[K % 2], w.sacc, theta, inv_theta, tau, cs,
+                                         ab.vb[final_buf], w.sacc, theta, inv_theta, tau, cs,
                                          comp_waves);
         });
         if (rc) return rc;
@@ -2073,18 +2090,23 @@ rdseg_status rdseg_backward(const float* f, rdseg_shape s, const rdseg_params* p
                                  slot(j + 1), 3 * plane, plane, st))
                 return RDSEG_ERR_HIP;
         }
-        // reverse sweep
-        for (int k = k0 + len; k >= k0 + 1; --k) {
-            float* sl = slot(k - 1 - k0);
+        // reverse sweep, up to adj_ns steps a launch
+        for (int k = k0 + len; k >= k0 + 1;) {
+            const int ns = std::min(adj_ns, k - k0);
+            AdjSlots sl;
+            sl.plane = plane;
+            for (int i = 0; i < kAdjMaxSteps; ++i) sl.s[i] = i < ns ? slot(k - 1 - i - k0) : nullptr;
             const bool first = (k == K);
-            if (launch_adj_step(d, sl + plane, sl + 2 * plane, sl, ab, in_buf, first, grad_v,
-                                first ? grad_u : nullptr, w.queue, w.totals, nm, kAdjTile,
-                                kAdjTile, theta, tau, st))
+            if (launch_adj_block(adj_ai, adj_small ? dre : d, sl, ns, ab, in_buf, first, grad_v,
+                                 first ? grad_u : nullptr, adj_small ? w.rqueue : w.queue,
+                                 adj_small ? w.rtotals : w.totals, adj_small ? nmr : nm, theta,
+                                 tau, st))
                 return RDSEG_ERR_HIP;
             in_buf = 1 - in_buf;
+            k -= ns;
         }
     }
-    if (n_tiles_left == 0) in_buf = K % 2;   // where the skipped steps would have left vbar
+    if (n_tiles_left == 0) in_buf = final_buf;   // where the skipped launches would have left vbar
     {
         const rdseg_status rj = join_closed(st, join);
         if (rj) return rj;
@@ -2355,6 +2377,17 @@ rdseg_status rdseg_set_batched_form(int32_t form) {
     if (form != 1 && form != 2)
         return fail(RDSEG_ERR_ARG, "form must be 1 (one persistent launch) or 2 (separate launches)");
     g_batch_form.store(form);
+    return RDSEG_OK;
+}
+
+rdseg_status rdseg_set_adjoint_form(int32_t tile, int32_t steps) {
+    if (tile == 0) tile = 32;
+    if (steps == 0) steps = 2;
+    if (adj_config_find(tile, steps) < 0)
+        return fail(RDSEG_ERR_ARG, "no reverse kernel for tile " + std::to_string(tile) +
+                                       " and " + std::to_string(steps) + " steps a launch");
+    g_adj_tile.store(tile);
+    g_adj_steps.store(steps);
     return RDSEG_OK;
 }
 

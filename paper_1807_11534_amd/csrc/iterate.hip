@@ -816,18 +816,49 @@ __global__ __launch_bounds__(NT) void k_resident(ImgDesc d, const int2* __restri
     }
 }
 
-__global__ __launch_bounds__(256) void k_state_copy(ImgDesc d, int buf, float* __restrict__ slot,
-                                                    int to_slot) {
+// (v, p_x, p_y) of the RD pixels from state buffer `buf` into a full-grid
+// slot [3][H][ld].  VEC: ld is a multiple of 4 and every plane 16-byte
+// aligned; each lane takes 4 pixels of a row (a row's last group may reach
+// into the row padding, which is read but never written).
+template <bool VEC>
+__global__ __launch_bounds__(256) void k_state_copy(ImgDesc d, int buf, float* __restrict__ slot) {
     const int64_t plane = (int64_t)d.H * d.ld;
-    for (int y = blockIdx.x; y < d.H; y += gridDim.x) {
-        for (int x = threadIdx.x; x < d.W; x += blockDim.x) {
-            int g = y * d.ld + x;
-            if (!c_active(d.c[g])) continue;
+    const int W = d.W, ld = d.ld;
+    const int gpr = VEC ? (W + 3) >> 2 : W;   // groups per row
+    const int64_t ng = (int64_t)gpr * d.H;
+    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < ng;
+         q += (int64_t)gridDim.x * 256) {
+        const int y = (int)(q / gpr);
+        const int x = (int)(q - (int64_t)y * gpr) * (VEC ? 4 : 1);
+        const int64_t g = (int64_t)y * ld + x;
+        if (VEC) {
+            const float4 c = *reinterpret_cast<const float4*>(d.c + g);
+            const float cc[4] = {c.x, c.y, c.z, c.w};
+            bool act[4];
+            bool all = x + 3 < W;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                act[e] = x + e < W && c_active(cc[e]);
+                all = all && act[e];
+            }
+            if (!(act[0] || act[1] || act[2] || act[3])) continue;
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
-                if (to_slot) slot[k * plane + g] = d.st[buf][k][g];
-                else d.st[buf][k][g] = slot[k * plane + g];
+                const float4 v = *reinterpret_cast<const float4*>(d.st[buf][k] + g);
+                float* o = slot + k * plane + g;
+                if (all) {
+                    *reinterpret_cast<float4*>(o) = v;
+                } else {
+                    if (act[0]) o[0] = v.x;
+                    if (act[1]) o[1] = v.y;
+                    if (act[2]) o[2] = v.z;
+                    if (act[3]) o[3] = v.w;
+                }
             }
+        } else {
+            if (!c_active(d.c[g])) continue;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) slot[k * plane + g] = d.st[buf][k][g];
         }
     }
 }
@@ -1157,10 +1188,18 @@ int launch_stop_finalize(const ImgDesc& d, const uint32_t* slots, int n_checks, 
     return 0;
 }
 
-int launch_state_copy(const ImgDesc& d, int buf, float* slot, bool to_slot, hipStream_t st) {
-    unsigned grid = (unsigned)(d.H < 65536 ? d.H : 65536);
-    hipLaunchKernelGGL(k_state_copy, dim3(grid), dim3(256), 0, st, d, buf, slot,
-                       to_slot ? 1 : 0);
+int launch_state_copy(const ImgDesc& d, int buf, float* slot, hipStream_t st) {
+    auto al16 = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; };
+    const bool vec = (d.ld & 3) == 0 && al16(d.c) && al16(slot) && al16(d.st[buf][0]) &&
+                     al16(d.st[buf][1]) && al16(d.st[buf][2]);
+    const int64_t groups = (int64_t)d.H * (vec ? (d.W + 3) / 4 : d.W);
+    int64_t grid = (groups + 255) / 256;
+    if (grid > 8192) grid = 8192;
+    if (grid < 1) grid = 1;
+    if (vec)
+        hipLaunchKernelGGL(k_state_copy<true>, dim3((unsigned)grid), dim3(256), 0, st, d, buf, slot);
+    else
+        hipLaunchKernelGGL(k_state_copy<false>, dim3((unsigned)grid), dim3(256), 0, st, d, buf, slot);
     RDSEG_HIP_CHECK(hipGetLastError());
     return 0;
 }

@@ -280,9 +280,9 @@ int launch_stop_finalize(const ImgDesc& d, const uint32_t* slots, int n_checks, 
                          int check_every, int launches_per_check, int n_launches, int iters,
                          int32_t* iters_done, hipStream_t st);
 
-// Copy (v, px, py) of RD pixels between a state buffer and a full-grid slot
-// [3][H][ld] (to_slot: buffer -> slot, else slot -> buffer).
-int launch_state_copy(const ImgDesc& d, int buf, float* slot, bool to_slot, hipStream_t st);
+// Copy (v, px, py) of RD pixels from a state buffer into a full-grid slot
+// [3][H][ld].
+int launch_state_copy(const ImgDesc& d, int buf, float* slot, hipStream_t st);
 
 // ---------------------------------------------------------------- adjoint
 struct AdjBufs {
@@ -291,11 +291,27 @@ struct AdjBufs {
     float* vb[2];
     float* sacc;          // sum over steps of the clamp adjoint
 };
+// The stored state of each reverse step of one launch: s[i] holds v^{k-1-i},
+// p_x at +plane and p_y at +2 plane (full-grid planes).
+constexpr int kAdjMaxSteps = 8;
+struct AdjSlots {
+    const float* s[kAdjMaxSteps];
+    int64_t plane;
+};
 int adj_config_count();
-int launch_adj_step(const ImgDesc& d, const float* fx, const float* fy, const float* fv,
-                    const AdjBufs& ab, int in_buf, bool first, const float* grad_v,
-                    const float* grad_u, const int2* queue, const int32_t* n_queue,
-                    int64_t max_items, int bx, int by, float theta, float tau, hipStream_t st);
+// index of the reverse kernel for tile x tile macro tiles and up to ns steps
+// a launch, -1 if there is none
+int adj_config_find(int tile, int ns);
+int adj_config_steps(int ai);
+int adj_config_tile(int ai);
+// Reverse steps k, ..., k - ns + 1 (ns <= the kernel's step count) on the
+// queued macro tiles of d's tile size: (pbar, vbar) from buffer in_buf to
+// 1 - in_buf, the clamp-adjoint sum accumulated; first: k is the last
+// iteration (pbar^k = 0, vbar^k = grad_v, dL/du = grad_u enters).
+int launch_adj_block(int ai, const ImgDesc& d, const AdjSlots& sl, int ns, const AdjBufs& ab,
+                     int in_buf, bool first, const float* grad_v, const float* grad_u,
+                     const int2* queue, const int32_t* n_queue, int64_t max_items, float theta,
+                     float tau, hipStream_t st);
 int launch_adj_final(const ImgDesc& d, const float* sacc, const float* vb0, float* grad_f,
                      double lambda, double theta, const float* z, const float* P, double c1,
                      double c2, double* partials, int64_t n_part, double* out4,

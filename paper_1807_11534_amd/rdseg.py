@@ -534,6 +534,12 @@ def set_batched_form(form):
     check(_lib.load().rdseg_set_batched_form(int(form)))
 
 
+def set_adjoint_form(tile=0, steps=0):
+    """Form of the backward's reverse sweep: `steps` reverse iterations per
+    launch on tile x tile macro tiles (0, 0 = the default, 32 and 2)."""
+    check(_lib.load().rdseg_set_adjoint_form(int(tile), int(steps)))
+
+
 def set_components(on=True):
     """Allow (default) or forbid the small-component path of single-image solves."""
     check(_lib.load().rdseg_set_components(1 if on else 0))

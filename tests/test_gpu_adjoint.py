@@ -316,3 +316,44 @@ def test_component_reverse_matches_tile_path(rd, case):
         rd.set_components(True)
     for a, b in zip(out[True], out[False]):
         np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("case", [("config5_512", 0.5, 120, 30), ("config5_512", math.inf, 62, 30),
+                                  ("ragged", 0.4, 90, 7), ("ragged", 0.4, 25, 30),
+                                  ("ragged", math.inf, 33, 11)])
+@pytest.mark.parametrize("components", [False, True])
+def test_reverse_forms_bitwise(rd, case, components):
+    """The reverse sweep's forms (steps per launch 1, 2 and 4 on 16x16 and
+    32x32 macro tiles, ragged last launches of a segment included) give the
+    same bits as one step per launch: every gradient output."""
+    name, frac, K, ce = case
+    if name == "ragged":
+        f = synth.smooth_field(173, 211, 45, noise=0.35)
+        z = synth.smooth_field(173, 211, 46, noise=0.1)
+        target = (f < 0).astype(np.float32)
+    else:
+        prob = synth.config5(size=512)
+        f, z, target = prob.f, prob.z, prob.mask.astype(np.float32)
+    delta = synth.band_delta(f, frac) if math.isfinite(frac) else math.inf
+    fd = dev(f)
+    print(f"reverse forms {case} components={components}", flush=True)
+    out = {}
+    try:
+        rd.set_components(components)
+        u, v, p, tape = rd.solve(fd, 4.0, 0.1, 0.125, delta, K, tile=(32, 32),
+                                 iters_per_launch=2, ckpt_every=ce)
+        gu = 2 * (u - dev(target))
+        gv = 0.5 * (v - dev(target))
+        fit = (dev(z), None, 0.8, 0.2, 0.0)
+        for form in ((32, 1), (16, 2), (16, 4), (32, 2), (32, 4)):
+            rd.set_adjoint_form(*form)
+            out[form] = [host(x) for x in rd.backward(fd, 4.0, 0.1, 0.125, delta, K, ce, tape,
+                                                      gu, gv, fit=fit)]
+    finally:
+        rd.set_components(True)
+        rd.set_adjoint_form(0, 0)
+    ref = out[(32, 1)]
+    assert np.abs(ref[0]).max() > 0
+    for form, res in out.items():
+        for a, b in zip(res, ref):
+            np.testing.assert_array_equal(a, b, err_msg=str(form))
