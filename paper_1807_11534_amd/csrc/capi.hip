@@ -391,6 +391,7 @@ struct SolvePlanArgs {
     int32_t* status = nullptr;               // resident: the solve's status word
     const CompWs* comp = nullptr;            // resident: small components for idle workgroups
     const int64_t* comp_npix = nullptr;      // resident: full RD count (the labelling's)
+    int64_t res_grid = 0;                    // resident: workgroups (0: max_items)
     bool no_alloc = false;                   // take no timing records (they create events)
 };
 
@@ -499,7 +500,8 @@ rdseg_status enqueue_iterations(SolvePlanArgs& a) {
         const int rc = launch_resident(a.ci, *a.d0, a.queue, a.n_queue, a.mflags, a.epoch,
                                        a.status, a.max_items, L % 2, a.iters, IT,
                                        a.inner, a.theta, a.inv_theta, a.tau, a.st,
-                                       timed ? rec.e0 : nullptr, a.comp, a.comp_npix);
+                                       timed ? rec.e0 : nullptr, a.comp, a.comp_npix,
+                                       a.res_grid);
         if (rc > 0) return RDSEG_ERR_HIP;
         if (rc == 0) {
             a.launches = 1;
@@ -752,13 +754,39 @@ rdseg_status solve_impl(const float* f, rdseg_shape s, const rdseg_params* prm, 
     // solve; it needs all of them resident at once, so closed tiles then run
     // before it on the same stream instead of beside it.
     bool resident = false;
+    int64_t res_grid = 0;          // 0: one workgroup per macro tile of the image
+    bool res_idle_comps = true;    // idle workgroups of the resident grid run the components
     const int want_res = prm->resident ? prm->resident : (tuned_res ? tuned_res : 1);
     // (the allocation-free form has no status word for the caller to read, so
     // it keeps to separate launches, whose waits cannot expire)
     if (want_res == 1 && g_resident_on.load() && !stop && !taped && !no_alloc && prm->iters > 0 &&
-        resident_fits(ci, nm)) {
+        resident_available(ci)) {
         hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-        resident = hipStreamIsCapturing(st, &cap) == hipSuccess && cap == hipStreamCaptureStatusNone;
+        const bool eager =
+            hipStreamIsCapturing(st, &cap) == hipSuccess && cap == hipStreamCaptureStatusNone;
+        if (eager && resident_fits(ci, nm)) {
+            resident = true;
+        } else if (eager) {
+            // Finer tiles than fit on the chip all at once: the queue (the
+            // band's tiles) may.  Read its length (synchronises).  The grid
+            // is the co-resident capacity (the queued tiles, then idle
+            // workgroups for the small components) when that leaves at least
+            // half as many idle workgroups as tiles; otherwise just the
+            // tiles, and the component kernel follows on the whole chip (a few
+            // idle workgroups would hold every component chain).
+            int32_t nq = 0;
+            if (hipMemcpyAsync(&nq, w.totals, sizeof(int32_t), hipMemcpyDeviceToHost, st) !=
+                    hipSuccess ||
+                hipStreamSynchronize(st) != hipSuccess)
+                return fail(RDSEG_ERR_HIP, "reading the tile queue length failed");
+            const int64_t tiles = ((int64_t)nq + 7) / 8 * 8;
+            const int64_t cap = resident_capacity(ci) / 8 * 8;
+            if (nq > 0 && tiles <= cap) {
+                resident = true;
+                res_idle_comps = 2 * (cap - tiles) >= tiles;
+                res_grid = res_idle_comps ? cap : tiles;
+            }
+        }
     }
     hipEvent_t join = nullptr;
     auto small = [&](hipStream_t cs) {
@@ -809,12 +837,13 @@ rdseg_status solve_impl(const float* f, rdseg_shape s, const rdseg_params* prm, 
     a.stop = stop;
     a.inner = inner;
     a.resident = resident;
+    a.res_grid = res_grid;
     a.mflags = w.flags;
     a.epoch = w.epoch;
     a.status = reinterpret_cast<int32_t*>(w.npix + 1);
     a.no_alloc = no_alloc;
     if (comps) a.npix = w.comp.npix_tile;   // timing counts the tile path's pixels
-    if (comps && resident) {
+    if (comps && resident && res_idle_comps) {
         a.comp = &w.comp;
         a.comp_npix = w.npix;
     }
@@ -2225,12 +2254,11 @@ rdseg_status rdseg_autotune(const float* f, rdseg_shape s, const rdseg_params* p
     const int comp_lo = prm->components ? prm->components : 1;
     const int comp_hi = prm->components ? prm->components : 2;
     // the barrier between blocks of iterations: on-chip exchange (resident
-    // form, only where the configuration's tiles can all fit on the chip) or
-    // kernel boundaries (what a configuration without that form runs, and is
-    // recorded as)
+    // form, where the configuration has one: a solve uses it when the image's
+    // tiles, or else the queued ones, fit on the chip) or kernel boundaries
+    // (what a configuration without that form runs, and is recorded as)
     auto res_range = [&](int ci, int& lo, int& hi) {
-        const TileCfg c = config_at(ci);
-        const bool capable = resident_fits(ci, macro_count(s, c.bx, c.by));
+        const bool capable = resident_available(ci);
         lo = prm->resident ? prm->resident : (capable ? 1 : 2);
         hi = prm->resident ? prm->resident : 2;
     };

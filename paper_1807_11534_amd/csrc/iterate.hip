@@ -921,6 +921,8 @@ struct ResEntry {
 #define RDSEG_RES(bx, by, it, nt) ResEntry{bx, by, it, nt, k_resident<bx, by, it, nt>}
 
 const ResEntry kRes[] = {
+    RDSEG_RES(16, 16, 8, 512),
+    RDSEG_RES(32, 32, 8, 512),
     RDSEG_RES(64, 32, 4, 512),
     RDSEG_RES(64, 64, 8, 1024),
 };
@@ -972,15 +974,23 @@ void set_resident_wait_ticks(int64_t ticks) {
 
 int64_t resident_wait_ticks() { return g_wait_ticks.load(std::memory_order_relaxed); }
 
-bool resident_fits(int ci, int64_t max_items) {
+int resident_capacity(int ci) {
     const int r = resident_entry(ci);
-    if (r < 0 || max_items < 1) return false;
+    if (r < 0) return 0;
     int cap = g_res_cap[r].load(std::memory_order_relaxed);
     if (cap == 0) {
         cap = persistent_blocks(reinterpret_cast<const void*>(kRes[r].fn), kRes[r].nt, 0);
         if (cap <= 0) cap = -1;
         g_res_cap[r].store(cap, std::memory_order_relaxed);
     }
+    return cap > 0 ? cap : 0;
+}
+
+bool resident_available(int ci) { return resident_entry(ci) >= 0; }
+
+bool resident_fits(int ci, int64_t max_items) {
+    if (max_items < 1) return false;
+    const int cap = resident_capacity(ci);
     return cap > 0 && ((max_items + 7) / 8) * 8 <= cap;
 }
 
@@ -988,14 +998,15 @@ int launch_resident(int ci, const ImgDesc& d, const int2* queue, const int32_t* 
                     const int32_t* mflags, int32_t* epoch, int32_t* status, int64_t max_items,
                     int in_buf, int iters, int per, int inner, float theta, float inv_theta,
                     float tau, hipStream_t st, hipEvent_t before, const CompWs* comp,
-                    const int64_t* comp_npix) {
+                    const int64_t* comp_npix, int64_t n_grid) {
     const int r = resident_entry(ci);
-    if (r < 0 || !resident_fits(ci, max_items)) return -1;
+    if (n_grid <= 0) n_grid = max_items;
+    if (r < 0 || !resident_fits(ci, n_grid)) return -1;
     // epoch[0 .. max_items) starts at 0 (*status was cleared with the RD count)
     if (launch_fill(reinterpret_cast<float*>(epoch), 1, (int)max_items, (int)max_items, 0.0f, st))
         return 1;
     if (before) (void)hipEventRecord(before, st);
-    const unsigned grid = (unsigned)(((max_items + 7) / 8) * 8);
+    const unsigned grid = (unsigned)(((n_grid + 7) / 8) * 8);
     ImgDesc dd = d;
     CompWs cw{};
     if (comp) cw = *comp;

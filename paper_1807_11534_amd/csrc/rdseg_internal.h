@@ -223,15 +223,22 @@ int launch_components_restore(const ImgDesc& d, const CompWs& w, const int64_t* 
 // afterwards on st then returns at once (and does the work itself if no
 // workgroup was left over).
 bool resident_fits(int ci, int64_t max_items);
+// whether configuration ci has a resident form at all
+bool resident_available(int ci);
+// co-resident workgroups of ci's resident form (0: none)
+int resident_capacity(int ci);
 // Bound of each wait of the resident kernel in ticks of the 100 MHz wall
 // clock: 0 restores the default (1 s), < 0 makes every wait give up at once.
 void set_resident_wait_ticks(int64_t ticks);
 int64_t resident_wait_ticks();
+// grid (0: one workgroup per macro tile of the image, max_items of them) is
+// the number of workgroups otherwise: at least the queue length rounded up to
+// a multiple of 8, and within the co-resident capacity.
 int launch_resident(int ci, const ImgDesc& d, const int2* queue, const int32_t* n_queue,
                     const int32_t* mflags, int32_t* epoch, int32_t* status, int64_t max_items,
                     int in_buf, int iters, int per, int inner, float theta, float inv_theta,
                     float tau, hipStream_t st, hipEvent_t before, const CompWs* comp = nullptr,
-                    const int64_t* comp_npix = nullptr);
+                    const int64_t* comp_npix = nullptr, int64_t grid = 0);
 
 // Per-launch arguments of the convergence-driven solve: skip the launch when
 // *skip_slot <= tol (skip_slot nullable); reduce the last iteration's change

@@ -265,11 +265,18 @@ def test_untuned_choice_by_band_width(rd, q_target, tile, ipl):
     ((700, 515), (64, 64), 8, 0.3, 33),
     ((300, 257), (64, 32), 4, 0.5, 29),
     ((64, 64), (64, 64), 8, math.inf, 5),
+    ((700, 515), (32, 32), 8, 0.1, 33),
+    ((1024, 1024), (32, 32), 8, 0.1, 40),
+    ((512, 512), (16, 16), 8, 0.1, 27),
 ])
 def test_resident_matches_separate_launches(rd, shape, tile, ipl, frac, iters):
     """Single-image solves whose tiles fit on the chip run as one resident
     launch; the results equal those of separate launches bit for bit, and the
-    resident form is the one that ran (timing records of form 1)."""
+    resident form is the one that ran (timing records of form 1).  The 32x32
+    and 16x16 cases at 1024^2 and 512^2 have more macro tiles than fit on the
+    chip at once, but their queues (the tiles of components above 64 pixels)
+    do: the grid is then sized by the queue, the small components running in
+    the idle workgroups (512^2) or after the tiles (1024^2)."""
     H, W = shape
     f = synth.smooth_field(H, W, 31, noise=0.2)
     delta = synth.band_delta(f, frac) if math.isfinite(frac) else math.inf
