@@ -75,7 +75,8 @@ def parse():
     ap.add_argument("--save-tune-cache", metavar="PATH",
                     help="write the tuning cache after the sweep's autotuning (--tune auto)")
     ap.add_argument("--extras", default="all",
-                    help="comma-separated subset of the extra workloads: " + ", ".join(EXTRAS))
+                    help="comma-separated subset of the extra workloads: " + ", ".join(EXTRAS) +
+                    " (batched_512: the batched workload at the specified delta only)")
     ap.add_argument("--extras-only", action="store_true",
                     help="run only the selected extra workloads and print their JSON")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -194,11 +195,13 @@ EXTRAS = ("batched", "adjoint", "protocol", "primal_dual", "volume", "ds_4096")
 
 def extras(torch, rdseg, synth, dev, which=EXTRAS):
     out = {}
-    if "batched" in which:
+    if "batched" in which or "batched_512" in which:
         # ---- batched workload: 512 images, sides 64..1024, 300 iterations
+        # ("batched_512": the specified delta only)
         log("extras: generating the batched workload")
         probs = synth.config4(512, frac=0.1)
-        for frac, name in [(0.1, "batched_512"), (math.inf, "batched_512_delta_inf")]:
+        runs = [(0.1, "batched_512"), (math.inf, "batched_512_delta_inf")]
+        for frac, name in (runs if "batched" in which else runs[:1]):
             log(f"extras: {name}")
             fs = [torch.from_numpy(p.f).to(dev) for p in probs]
             lams = [p.lam for p in probs]
@@ -383,7 +386,7 @@ def main():
         torch.cuda.synchronize()
         del a, b
     which = EXTRAS if args.extras == "all" else tuple(x.strip() for x in args.extras.split(","))
-    unknown = [x for x in which if x not in EXTRAS]
+    unknown = [x for x in which if x not in EXTRAS + ("batched_512",)]
     if unknown:
         print(f"unknown extra workloads: {unknown}; choose from {EXTRAS}", file=sys.stderr)
         sys.exit(2)

@@ -300,8 +300,9 @@ __global__ __launch_bounds__(256) void k_components(ImgDesc d, CompWs w, const i
 // segment (last first) each lane loads its pixel's checkpoint from the tape,
 // recomputes the segment's forward states (the arithmetic of one k_iterate
 // iteration) and then runs the segment's reverse steps with the arithmetic of
-// k_adj_step, neighbour values from other lanes and frozen neighbours as
-// constants (w right / below; p, ubar, gbar and wbar are 0 there).  Where
+// the tile path's reverse kernel (k_adj_block), neighbour values from other
+// lanes and frozen neighbours as constants (w right / below; p, ubar, gbar
+// and wbar are 0 there).  Where
 // the segment fits a workgroup's LDS (one wave per workgroup, lane-major):
 // lds_mode 2 (ce x 1536 bytes) keeps each forward step's dual-update outputs
 // (p, g, m) and u, so the reverse steps recompute nothing; lds_mode 1
@@ -397,7 +398,7 @@ __global__ __launch_bounds__(256) void k_adj_components_t(
         float vb = (mine && grad_v) ? grad_v[gg] : 0.0f;
         float S = 0.0f;
         // one reverse step k from the dual update of step k (p^k, g, m of
-        // state k - 1) and u^k: the arithmetic of k_adj_step
+        // state k - 1) and u^k: the arithmetic of k_adj_block
         auto reverse_step = [&](int k, float opx, float opy, float ogx, float ogy, float om,
                                 float u) {
             const float sarg = u - c;
