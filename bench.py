@@ -40,6 +40,10 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_UPDATE = 28
+# forward + adjoint with checkpoints: forward 28, segment recompute 28, segment
+# tape 12, reverse step 40 (stored state, adjoint state, accumulator, c) per
+# active pixel-iteration
+ADJ_BYTES_PER_UPDATE = 108
 # FP32 operations of one active pixel-update (FMA counted as 2; sqrt,
 # reciprocal, min and max as 1 each): divergence 3, u-step 2, v-step 3, w 2,
 # gradient 2, |g| 4, 1 / (1 + tau |g|) 3, the two p components 6
@@ -281,8 +285,12 @@ def extras(torch, rdseg, synth, dev, which=EXTRAS):
             t_fb = timed(torch, fwd_bwd, 3)
             fwd_only()
             t_f = timed(torch, fwd_only, 3)
+            alg = ADJ_BYTES_PER_UPDATE * q * 2048 * 2048 * 300
             out[name] = dict(size=2048, iters=300, ckpt_every=30, active_fraction=q,
-                             fwd_adjoint_ms=t_fb, forward_ms=t_f)
+                             fwd_adjoint_ms=t_fb, forward_ms=t_f,
+                             alg_bytes_per_update=ADJ_BYTES_PER_UPDATE,
+                             alg_gbs=alg / (t_fb * 1e-3) / 1e9,
+                             alg_frac=alg / (t_fb * 1e-3) / (HBM_PEAK_GBS * 1e9))
         del f, tgt
     if "protocol" in which:
         out["paper_protocol_128"] = protocol(torch, rdseg, synth, dev)
