@@ -298,8 +298,9 @@ def extras(torch, rdseg, synth, dev, which=EXTRAS):
             out[name] = dict(size=2048, iters=300, ckpt_every=30, active_fraction=q,
                              checked=checked, fwd_adjoint_ms=t_fb, forward_ms=t_f,
                              alg_bytes_per_update=ADJ_BYTES_PER_UPDATE,
-                             alg_gbs=alg / (t_fb * 1e-3) / 1e9,
-                             alg_frac=alg / (t_fb * 1e-3) / (HBM_PEAK_GBS * 1e9))
+                             # unblocked-equivalent: the component path keeps its
+                             # chains on chip, so this can exceed the HBM peak
+                             alg_gbs=alg / (t_fb * 1e-3) / 1e9)
         del f, tgt
     if "protocol" in which:
         out["paper_protocol_128"] = protocol(torch, rdseg, synth, dev)

@@ -148,8 +148,8 @@ SolveWs carve_solve(void* base, const rdseg_shape& s) {
     w.comp.crank = cv.take<int32_t>(g.plane);
     w.comp.cslot = cv.take<int32_t>(g.plane);
     w.comp.lane_of = cv.take<int32_t>(g.plane);
-    w.comp.wl_pix = cv.take<int32_t>(2 * g.plane + 7 * 64);
-    w.comp.ccount = cv.take<int32_t>(8);
+    w.comp.wl_pix = cv.take<int32_t>(2 * g.plane + kCompLaneExtra);
+    w.comp.ccount = cv.take<int32_t>(kCompCount);
     w.comp.npix_tile = cv.take<int64_t>(1);
     w.bytes = cv.off;
     return w;
@@ -1151,8 +1151,8 @@ BackWs carve_back(void* base, const rdseg_shape& s, int ce) {
     w.comp.crank = cv.take<int32_t>(g.plane);
     w.comp.cslot = cv.take<int32_t>(g.plane);
     w.comp.lane_of = cv.take<int32_t>(g.plane);
-    w.comp.wl_pix = cv.take<int32_t>(2 * g.plane + 7 * 64);
-    w.comp.ccount = cv.take<int32_t>(8);
+    w.comp.wl_pix = cv.take<int32_t>(2 * g.plane + kCompLaneExtra);
+    w.comp.ccount = cv.take<int32_t>(kCompCount);
     w.comp.npix_tile = cv.take<int64_t>(1);
     w.bytes = cv.off;
     return w;
@@ -2059,8 +2059,8 @@ rdseg_status rdseg_backward(const float* f, rdseg_shape s, const rdseg_params* p
     // with the component path on, skip the tile path when no macro tile is
     // left to it (one read of the queue length, which synchronises)
     int32_t n_tiles_left = 1;
-    int32_t ccount[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    int64_t comp_waves = -1;
+    int32_t ccount[kCompCount] = {};
+    int64_t comp_waves = -1, comp_jobs = -1;
     if (comps) {
         if (hipMemcpyAsync(&n_tiles_left, w.totals, sizeof(int32_t), hipMemcpyDeviceToHost, st) !=
                 hipSuccess ||
@@ -2068,7 +2068,9 @@ rdseg_status rdseg_backward(const float* f, rdseg_shape s, const rdseg_params* p
                 hipSuccess ||
             hipStreamSynchronize(st) != hipSuccess)
             return fail(RDSEG_ERR_HIP, "reading the tile queue length failed");
-        comp_waves = component_waves_of(ccount);   // meaningless (unused) if labelling was skipped
+        // (meaningless, and unused on the device, if the labelling was skipped)
+        comp_waves = component_waves_of(ccount);
+        comp_jobs = component_group_jobs_of(ccount);
     }
     AdjBufs ab;
     ab.pbx[0] = w.ab[0]; ab.pby[0] = w.ab[1]; ab.vb[0] = w.ab[2];
@@ -2095,7 +2097,7 @@ rdseg_status rdseg_backward(const float* f, rdseg_shape s, const rdseg_params* p
         rdseg_status rc = closed_beside(st, &join, [&](hipStream_t cs) {
             return launch_adj_components(d, w.comp, w.npix, tape, w.seg, K, ce, grad_u, grad_v,
                                          ab.vb[final_buf], w.sacc, theta, inv_theta, tau, cs,
-                                         comp_waves);
+                                         comp_waves, comp_jobs);
         });
         if (rc) return rc;
     }

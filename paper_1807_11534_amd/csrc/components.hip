@@ -109,7 +109,7 @@ __global__ __launch_bounds__(256) void k_cc_init(ImgDesc d, CompWs w, const int6
             w.cslot[g] = 0;
         }
         w.lane_of[g] = -1;
-        if (g < 8) w.ccount[g] = 0;
+        if (g < kCompCount) w.ccount[g] = 0;
     }
 }
 
@@ -146,10 +146,10 @@ __global__ __launch_bounds__(256) void k_cc_flatten(ImgDesc d, CompWs w, const i
             r = cc_root(w.lab, (int)g);
             __hip_atomic_store(w.lab + g, r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        // Sizes are exact up to kSmallMax + 1; beyond that only "large"
+        // Sizes are exact up to kCompMax + 1; beyond that only "large"
         // matters.  cslot[r] (cleared by the init pass, written for small
         // roots only by the class pass) flags a root that has passed
-        // kSmallMax, so the pixels of large components stop adding to one
+        // kCompMax, so the pixels of large components stop adding to one
         // contended counter (a stale read only costs an extra add).  The
         // lanes of a wave that share a root add their count with one atomic,
         // and each takes the count before it as its rank in the component
@@ -167,7 +167,7 @@ __global__ __launch_bounds__(256) void k_cc_flatten(ImgDesc d, CompWs w, const i
             if (l == leader) {
                 const int cnt = __popcll(sm);
                 old = atomicAdd(w.csize + r0, cnt);
-                if (old + cnt > kSmallMax) w.cslot[r0] = 1;
+                if (old + cnt > kCompMax) w.cslot[r0] = 1;
             }
             old = __shfl(old, leader);
             if (same) {
@@ -182,10 +182,10 @@ __global__ __launch_bounds__(256) void k_cc_flatten(ImgDesc d, CompWs w, const i
 // class in LDS, takes one block of slots per class with a single global
 // atomic, and hands them out in the order of its local counting.
 __global__ __launch_bounds__(256) void k_cc_class(ImgDesc d, CompWs w, const int64_t* npix) {
-    __shared__ int sCount[kClasses], sBase[kClasses];
+    __shared__ int sCount[kCompClasses], sBase[kCompClasses];
     if (cc_skip(npix, d)) return;   // uniform: npix is not changed by this pass
     const int t = threadIdx.x;
-    if (t < kClasses) sCount[t] = 0;
+    if (t < kCompClasses) sCount[t] = 0;
     __syncthreads();
     const int64_t plane = (int64_t)d.H * d.ld;
     const int64_t per_wg = (plane + gridDim.x - 1) / gridDim.x;
@@ -196,10 +196,10 @@ __global__ __launch_bounds__(256) void k_cc_class(ImgDesc d, CompWs w, const int
         int k = -1;   // size class of a small root
         if (w.lab[g] == (int32_t)g) {
             const int s = w.csize[g];
-            if (s >= 1 && s <= kSmallMax) k = size_class(s);
+            if (s >= 1 && s <= kCompMax) k = size_class(s);
         }
         // local slots: one LDS atomic per class and wave, lanes in order
-        for (int c = 0; c < kClasses; ++c) {
+        for (int c = 0; c < kCompClasses; ++c) {
             const uint64_t m = __ballot(k == c);
             if (!m) continue;   // uniform
             const int leader = __ffsll((unsigned long long)m) - 1;
@@ -210,12 +210,12 @@ __global__ __launch_bounds__(256) void k_cc_class(ImgDesc d, CompWs w, const int
         }
     }
     __syncthreads();
-    if (t < kClasses) sBase[t] = sCount[t] ? atomicAdd(w.ccount + t, sCount[t]) : 0;
+    if (t < kCompClasses) sBase[t] = sCount[t] ? atomicAdd(w.ccount + t, sCount[t]) : 0;
     __syncthreads();
     for (int64_t g = g0 + t; g < g1; g += 256) {
         if (w.lab[g] != (int32_t)g) continue;
         const int s = w.csize[g];
-        if (s < 1 || s > kSmallMax) continue;
+        if (s < 1 || s > kCompMax) continue;
         w.cslot[g] += sBase[size_class(s)];
     }
 }
@@ -225,7 +225,8 @@ __global__ __launch_bounds__(256) void k_cc_class(ImgDesc d, CompWs w, const int
 __global__ __launch_bounds__(256) void k_cc_lanes(ImgDesc d, CompWs w, const int64_t* npix) {
     if (cc_skip(npix, d)) return;
     const int64_t plane = (int64_t)d.H * d.ld;
-    const int64_t lanes = min((int64_t)class_base(w.ccount, kClasses) * 64, 2 * plane + kWlExtra);
+    const int64_t lanes =
+        min((int64_t)class_base(w.ccount, kCompClasses) * 64, 2 * plane + kCompLaneExtra);
     for (int64_t L = (int64_t)blockIdx.x * 256 + threadIdx.x; L < lanes;
          L += (int64_t)gridDim.x * 256)
         w.wl_pix[L] = -1;
@@ -247,17 +248,21 @@ __global__ __launch_bounds__(256) void k_cc_assign(ImgDesc d, CompWs w, uint64_t
         bool frz = false;
         if (r >= 0 && r < plane) {
             const int s = w.csize[r];
-            if (s >= 1 && s <= kSmallMax) {
+            if (s >= 1 && s <= kCompMax) {
                 const int k = size_class(s);
-                const int per = kSmallMax >> k;
                 const int slot = w.cslot[r];
                 const int rank = w.crank[g];
-                const int wave = class_base(w.ccount, k) + slot / per;
-                const int lane = (slot % per) * (1 << k) + rank;
-                const int L = wave * 64 + lane;
-                // never false for a well-formed labelling (see kWlExtra); a
-                // guard against writing outside the lane table
-                if (slot >= 0 && rank < s && L >= 0 && L < 2 * plane + kWlExtra) {
+                int L;
+                if (k < kWaveClasses) {   // 64 / 2^k components packed into a wave
+                    const int per = kSmallMax >> k;
+                    const int wave = class_base(w.ccount, k) + slot / per;
+                    L = wave * 64 + (slot % per) * (1 << k) + rank;
+                } else {                  // one component a group of 2^k lanes
+                    L = class_base(w.ccount, k) * 64 + slot * (1 << k) + rank;
+                }
+                // never false for a well-formed labelling (see kCompLaneExtra);
+                // a guard against writing outside the lane table
+                if (slot >= 0 && rank < s && L >= 0 && L < 2 * plane + kCompLaneExtra) {
                     w.lane_of[g] = L;
                     w.wl_pix[L] = (int32_t)g;
                     d.c[g] = __builtin_inff();   // frozen for the tile path from here on
@@ -285,13 +290,18 @@ __global__ __launch_bounds__(256) void k_cc_assign(ImgDesc d, CompWs w, uint64_t
         atomicAdd((unsigned long long*)w.npix_tile, (unsigned long long)(-(long long)sFrozen));
 }
 
-// Every iteration of the packed small components (unless the resident kernel's
-// idle workgroups already ran them: ccount[7] set).
+// Every iteration of the component path: first the group classes (jobs of a
+// whole workgroup), then the packed one-wave classes unless the resident
+// kernel's idle workgroups already ran them (ccount[kCompFlag] set).
 __global__ __launch_bounds__(256) void k_components(ImgDesc d, CompWs w, const int64_t* npix,
                                                     int iters, int inner, float theta,
                                                     float inv_theta, float tau,
                                                     float* __restrict__ tape, int ce) {
-    if (cc_skip(npix, d) || w.ccount[7]) return;
+    __shared__ float xbuf[1024];
+    if (cc_skip(npix, d)) return;
+    component_groups(d, w, iters, inner, theta, inv_theta, tau, tape, ce, blockIdx.x,
+                     gridDim.x, xbuf);
+    if (w.ccount[kCompFlag]) return;
     component_waves(d, w, iters, inner, theta, inv_theta, tau, tape, ce,
                     blockIdx.x * 4 + (threadIdx.x >> 6), gridDim.x * 4);
 }
@@ -323,32 +333,54 @@ __global__ __launch_bounds__(256) void k_components(ImgDesc d, CompWs w, const i
 constexpr int kSubLen = 8;   // steps per sub-segment
 constexpr int kSubMax = 5;   // sub-segments per segment: ckpt_every <= 40
 
-template <bool REG>
+template <bool G> struct XOf { using type = WaveX; };
+template <> struct XOf<true> { using type = GroupX; };
+
+template <bool REG, bool GRP>
 __global__ __launch_bounds__(256) void k_adj_components_t(
     ImgDesc d, CompWs w, const int64_t* npix, const float* __restrict__ tape,
     float* __restrict__ seg, int K, int ce, const float* __restrict__ grad_u,
     const float* __restrict__ grad_v, float* __restrict__ vb_out, float* __restrict__ sacc,
     float theta, float inv_theta, float tau, int lds_mode) {
     extern __shared__ float s_states[];
+    __shared__ float xbuf[GRP ? 1024 : 1];
     if (cc_skip(npix, d)) return;
     const int64_t plane = (int64_t)d.H * d.ld;
-    const int nwaves = (int)min((int64_t)class_base(w.ccount, kClasses),
-                                (2 * plane + kWlExtra) / 64);
-    const int lane = threadIdx.x & 63;
+    // GRP: the group classes, one job (two components of class 7 or one of
+    // class 8) per 256-thread workgroup, the register form or the per-pixel
+    // slots; else the packed one-wave classes
+    if (GRP && lds_mode != 0) lds_mode = 0;
+    const int nwork = GRP ? group_jobs(w.ccount)
+                          : (int)min((int64_t)class_base(w.ccount, kWaveClasses),
+                                     (2 * plane + kCompLaneExtra) / 64);
+    const int lane = GRP ? (int)threadIdx.x : (int)(threadIdx.x & 63);
     // lds_mode 4: two waves per workgroup on the same packed wave, one running
     // the reverse of segment sg while the other runs the forward of segment
     // sg - 1 into the other of two buffers [ce][6][64]
-    const bool duo = lds_mode == 4;
+    const bool duo = !GRP && lds_mode == 4;
     const bool fwd_wave = duo && (threadIdx.x >> 6) == 1;
-    const int wpb = duo ? 1 : (int)(blockDim.x >> 6);
-    const int wslot = duo ? 0 : (int)(threadIdx.x >> 6);
+    const int wpb = (duo || GRP) ? 1 : (int)(blockDim.x >> 6);
+    const int wslot = (duo || GRP) ? 0 : (int)(threadIdx.x >> 6);
     // LDS per wave: lds_mode 1 holds states [ce - 1][3][64], lds_mode 2 the
     // dual-update outputs and u [ce][6][64]; lds_mode 0 uses seg instead
     const int per_wave = lds_mode == 2 ? ce * 384 : (lds_mode == 1 ? (ce - 1) * 192 : 0);
     float* __restrict__ my_states = s_states + wslot * per_wave + lane;
-    for (int wave = blockIdx.x * wpb + wslot; wave < nwaves;
-         wave += gridDim.x * wpb) {   // uniform per wave (per workgroup with lds_mode 4)
-        const int g = w.wl_pix[wave * 64 + lane];
+    typename XOf<GRP>::type xc;
+    if constexpr (GRP) {
+        xc.buf = xbuf;
+        xc.par = 0;
+    }
+    for (int item = blockIdx.x * wpb + wslot; item < nwork;
+         item += gridDim.x * wpb) {   // uniform per wave (per workgroup with lds_mode 4 or GRP)
+        int g, base;
+        if constexpr (GRP) {
+            int ln;
+            group_lane(w.ccount, item, lane, ln, base);
+            g = (ln >= 0 && ln < 2 * plane + kCompLaneExtra) ? w.wl_pix[ln] : -1;
+        } else {
+            g = w.wl_pix[item * 64 + lane];
+            base = item * 64;
+        }
         const bool mine = g >= 0 && g < plane;
         const int gg = mine ? g : 0;
         const int y = gg / d.ld, x = gg - y * d.ld;
@@ -362,37 +394,45 @@ __global__ __launch_bounds__(256) void k_adj_components_t(
         if (mine) {
             if (x + 1 < d.W) {
                 const int L = w.lane_of[gg + 1];
-                if (L >= 0) nR = L & 63;
+                if (L >= 0) nR = L - base;
                 else wR = w_of(0.0f, heav_from_c(c_of(d.f[gg + 1], d.delta, d.tl)), inv_theta, false);
             } else {
                 wR = w_of(0.0f, 0.0f, inv_theta, false);
             }
             if (y + 1 < d.H) {
                 const int L = w.lane_of[gg + d.ld];
-                if (L >= 0) nD = L & 63;
+                if (L >= 0) nD = L - base;
                 else wD = w_of(0.0f, heav_from_c(c_of(d.f[gg + d.ld], d.delta, d.tl)), inv_theta, false);
             } else {
                 wD = w_of(0.0f, 0.0f, inv_theta, false);
             }
             if (x > 0) {
                 const int L = w.lane_of[gg - 1];
-                if (L >= 0) nL = L & 63;
+                if (L >= 0) nL = L - base;
             }
             if (y > 0) {
                 const int L = w.lane_of[gg - d.ld];
-                if (L >= 0) nU = L & 63;
+                if (L >= 0) nU = L - base;
             }
         }
-        const int aR = 4 * (nR >= 0 ? nR : lane), aD = 4 * (nD >= 0 ? nD : lane);
-        const int aL = 4 * (nL >= 0 ? nL : lane), aU = 4 * (nU >= 0 ? nU : lane);
-        auto from = [](int addr, float a) {
-            return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(a)));
+        // exchange indices (a lane reads itself when the neighbour is frozen)
+        const int iR = nR >= 0 ? nR : lane, iD = nD >= 0 ? nD : lane;
+        const int iL = nL >= 0 ? nL : lane, iU = nU >= 0 ? nU : lane;
+        // x - 1 and y - 1 neighbours of (a, b), x + 1 and y + 1 neighbours of
+        // a, of quantities that are 0 at frozen cells; every lane calls them
+        // together
+        auto left_up = [&](float a, float b, float& l, float& u) {
+            float tl, tu;
+            xc.two(a, iL, b, iU, tl, tu);
+            l = nL >= 0 ? tl : 0.0f;
+            u = nU >= 0 ? tu : 0.0f;
         };
-        // x - 1 / y - 1 neighbours of a quantity that is 0 at frozen cells
-        auto left = [&](float a) { const float t = from(aL, a); return nL >= 0 ? t : 0.0f; };
-        auto up = [&](float a) { const float t = from(aU, a); return nU >= 0 ? t : 0.0f; };
-        auto right0 = [&](float a) { const float t = from(aR, a); return nR >= 0 ? t : 0.0f; };
-        auto down0 = [&](float a) { const float t = from(aD, a); return nD >= 0 ? t : 0.0f; };
+        auto right_down0 = [&](float a, float& r, float& dn) {
+            float tr, td;
+            xc.same2(a, iR, iD, tr, td);
+            r = nR >= 0 ? tr : 0.0f;
+            dn = nD >= 0 ? td : 0.0f;
+        };
 
         float pbx = 0.0f, pby = 0.0f;
         float vb = (mine && grad_v) ? grad_v[gg] : 0.0f;
@@ -407,8 +447,10 @@ __global__ __launch_bounds__(256) void k_adj_components_t(
             if (k == K && grad_u && mine) ub += grad_u[gg];
             ub = mine ? ub : 0.0f;
             // pbt = pbar^k + theta grad(ubar); gbar
-            const float gux = lastc ? 0.0f : (right0(ub) - ub);
-            const float guy = lastr ? 0.0f : (down0(ub) - ub);
+            float ubr, ubd;
+            right_down0(ub, ubr, ubd);
+            const float gux = lastc ? 0.0f : (ubr - ub);
+            const float guy = lastr ? 0.0f : (ubd - ub);
             const float ptx = mine ? fmaf(theta, gux, pbx) : 0.0f;
             const float pty = mine ? fmaf(theta, guy, pby) : 0.0f;
             const float nn = __builtin_amdgcn_sqrtf(fmaf(ogx, ogx, ogy * ogy));
@@ -421,10 +463,14 @@ __global__ __launch_bounds__(256) void k_adj_components_t(
             gbx = (mine && !lastc) ? gbx : 0.0f;
             gby = (mine && !lastr) ? gby : 0.0f;
             // wbar = -div gbar; pbar^(k-1), vbar^(k-1)
-            const float dg = div_p(gbx, left(gbx), gby, up(gby));
+            float gbl, gbu;
+            left_up(gbx, gby, gbl, gbu);
+            const float dg = div_p(gbx, gbl, gby, gbu);
             const float wb = mine ? -dg : 0.0f;
-            const float gwx = lastc ? 0.0f : (right0(wb) - wb);
-            const float gwy = lastr ? 0.0f : (down0(wb) - wb);
+            float wbr, wbd;
+            right_down0(wb, wbr, wbd);
+            const float gwx = lastc ? 0.0f : (wbr - wb);
+            const float gwy = lastr ? 0.0f : (wbd - wb);
             pbx = lastc ? 0.0f : fmaf(om, ptx, -gwx);
             pby = lastr ? 0.0f : fmaf(om, pty, -gwy);
             vb = fmaf(-wb, inv_theta, ub);
@@ -432,14 +478,19 @@ __global__ __launch_bounds__(256) void k_adj_components_t(
         };
         // one forward step from state (v, px, py): the dual update and u
         auto forward_step = [&](float v, float px, float py, DualOut& o, float& u) {
-            const float dd = div_p(px, left(px), py, up(py));
+            float pl, pu;
+            left_up(px, py, pl, pu);
+            const float dd = div_p(px, pl, py, pu);
             const float wv = w_of(dd, v, inv_theta, mine);
-            const float wr = from(aR, wv), wd = from(aD, wv);
+            float wr, wd;
+            xc.same2(wv, iR, iD, wr, wd);
             o = dual_update(px, py, wv, nR >= 0 ? wr : wR, nD >= 0 ? wd : wD, fl, tau);
-            u = u_step(v, div_p(o.px, left(o.px), o.py, up(o.py)), theta);
+            float ol, ou;
+            left_up(o.px, o.py, ol, ou);
+            u = u_step(v, div_p(o.px, ol, o.py, ou), theta);
         };
         const int nseg = (K + ce - 1) / ce;
-        if (REG) {
+        if constexpr (REG) {
             for (int sg = nseg - 1; sg >= 0; --sg) {
                 const int k0 = sg * ce;
                 const int len = min(ce, K - k0);
@@ -640,6 +691,7 @@ __global__ __launch_bounds__(256) void k_adj_components_t(
             sacc[gg] = S;
             vb_out[gg] = vb;
         }
+        if constexpr (GRP) __syncthreads();   // the exchange buffers are reused by the next job
     }
 }
 
@@ -648,7 +700,8 @@ __global__ __launch_bounds__(256) void k_adj_components_t(
 __global__ __launch_bounds__(256) void k_cc_restore(ImgDesc d, CompWs w, const int64_t* npix) {
     if (cc_skip(npix, d)) return;
     const int64_t plane = (int64_t)d.H * d.ld;
-    const int64_t lanes = min((int64_t)class_base(w.ccount, kClasses) * 64, 2 * plane + kWlExtra);
+    const int64_t lanes =
+        min((int64_t)class_base(w.ccount, kCompClasses) * 64, 2 * plane + kCompLaneExtra);
     for (int64_t L = (int64_t)blockIdx.x * 256 + threadIdx.x; L < lanes;
          L += (int64_t)gridDim.x * 256) {
         const int g = w.wl_pix[L];
@@ -713,17 +766,51 @@ int launch_components(const ImgDesc& d, const CompWs& w, const int64_t* npix, in
 
 int64_t component_waves_of(const int32_t* ccount_host) {
     int64_t b = 0;
-    for (int j = 0; j < kClasses; ++j) {
+    for (int j = 0; j < kWaveClasses; ++j) {
         const int per = kSmallMax >> j;
         b += ((int64_t)ccount_host[j] + per - 1) / per;
     }
     return b;
 }
 
+int64_t component_group_jobs_of(const int32_t* ccount_host) {
+    return ((int64_t)ccount_host[7] + 1) / 2 + ccount_host[8];
+}
+
 int launch_adj_components(const ImgDesc& d, const CompWs& w, const int64_t* npix,
                           const float* tape, float* seg, int K, int ce, const float* grad_u,
                           const float* grad_v, float* vb_out, float* sacc, float theta,
-                          float inv_theta, float tau, hipStream_t st, int64_t nwaves_hint) {
+                          float inv_theta, float tau, hipStream_t st, int64_t nwaves_hint,
+                          int64_t group_jobs) {
+    // The group classes (components of 65-256 pixels): one job a 256-thread
+    // workgroup, the register form where ckpt_every allows, else the
+    // per-pixel slots of seg.
+    if (group_jobs != 0) {
+        const bool reg = ce <= kSubLen * kSubMax;
+        static std::atomic<int> cap_reg{0}, cap_slots{0};
+        std::atomic<int>& cap = reg ? cap_reg : cap_slots;
+        const void* gfn = reg ? reinterpret_cast<const void*>(k_adj_components_t<true, true>)
+                              : reinterpret_cast<const void*>(k_adj_components_t<false, true>);
+        int grid = cap.load(std::memory_order_relaxed);
+        if (grid == 0) {
+            grid = persistent_blocks(gfn, 256, 0);
+            if (grid <= 0) {
+                set_error("occupancy query failed for the component adjoint kernel");
+                return 4;
+            }
+            cap.store(grid, std::memory_order_relaxed);
+        }
+        if (group_jobs > 0 && group_jobs < grid) grid = (int)group_jobs;
+        if (reg)
+            hipLaunchKernelGGL((k_adj_components_t<true, true>), dim3((unsigned)grid), dim3(256), 0,
+                               st, d, w, npix, tape, seg, K, ce, grad_u, grad_v, vb_out, sacc,
+                               theta, inv_theta, tau, 0);
+        else
+            hipLaunchKernelGGL((k_adj_components_t<false, true>), dim3((unsigned)grid), dim3(256),
+                               0, st, d, w, npix, tape, seg, K, ce, grad_u, grad_v, vb_out, sacc,
+                               theta, inv_theta, tau, 0);
+        RDSEG_HIP_CHECK(hipGetLastError());
+    }
     // The kept dual-update outputs (modes 2, 4) shorten every reverse step but
     // take twice the LDS of the states (mode 1), so fewer waves run at once:
     // they are used when all the component waves fit on the chip together.
@@ -744,7 +831,7 @@ int launch_adj_components(const ImgDesc& d, const CompWs& w, const int64_t* npix
             lds_limit = v;
         g_adj_lds_limit.store(lds_limit, std::memory_order_relaxed);
     }
-    const void* fn = reinterpret_cast<const void*>(k_adj_components_t<false>);
+    const void* fn = reinterpret_cast<const void*>(k_adj_components_t<false, false>);
     auto cap_of = [&](int threads, size_t bytes) {
         return bytes > (size_t)lds_limit ? 0 : persistent_blocks(fn, threads, bytes);
     };
@@ -768,7 +855,7 @@ int launch_adj_components(const ImgDesc& d, const CompWs& w, const int64_t* npix
     // of the states in LDS (22 KB a wave at ckpt_every = 30: seven waves a CU)
     if (mode == 1 && ce <= kSubLen * kSubMax) {
         static std::atomic<int> reg_grid{0};
-        const void* rfn = reinterpret_cast<const void*>(k_adj_components_t<true>);
+        const void* rfn = reinterpret_cast<const void*>(k_adj_components_t<true, false>);
         int grid = reg_grid.load(std::memory_order_relaxed);
         if (grid == 0) {
             grid = persistent_blocks(rfn, 256, 0);
@@ -778,7 +865,7 @@ int launch_adj_components(const ImgDesc& d, const CompWs& w, const int64_t* npix
             }
             reg_grid.store(grid, std::memory_order_relaxed);
         }
-        hipLaunchKernelGGL(k_adj_components_t<true>, dim3((unsigned)grid), dim3(256), 0, st, d,
+        hipLaunchKernelGGL((k_adj_components_t<true, false>), dim3((unsigned)grid), dim3(256), 0, st, d,
                            w, npix, tape, seg, K, ce, grad_u, grad_v, vb_out, sacc, theta,
                            inv_theta, tau, 0);
         RDSEG_HIP_CHECK(hipGetLastError());
@@ -792,7 +879,7 @@ int launch_adj_components(const ImgDesc& d, const CompWs& w, const int64_t* npix
             set_error("occupancy query failed for the component adjoint kernel");
             return 4;
         }
-        hipLaunchKernelGGL(k_adj_components_t<false>, dim3((unsigned)grid), dim3(threads), lds, st, d, w,
+        hipLaunchKernelGGL((k_adj_components_t<false, false>), dim3((unsigned)grid), dim3(threads), lds, st, d, w,
                            npix, tape, seg, K, ce, grad_u, grad_v, vb_out, sacc, theta,
                            inv_theta, tau, mode);
         RDSEG_HIP_CHECK(hipGetLastError());
@@ -806,7 +893,7 @@ int launch_adj_components(const ImgDesc& d, const CompWs& w, const int64_t* npix
             return 4;
         }
     }
-    hipLaunchKernelGGL(k_adj_components_t<false>, dim3((unsigned)g_adj_comp_grid), dim3(256), 0, st, d, w,
+    hipLaunchKernelGGL((k_adj_components_t<false, false>), dim3((unsigned)g_adj_comp_grid), dim3(256), 0, st, d, w,
                        npix, tape, seg, K, ce, grad_u, grad_v, vb_out, sacc, theta, inv_theta,
                        tau, 0);
     RDSEG_HIP_CHECK(hipGetLastError());

@@ -622,7 +622,9 @@ __global__ __launch_bounds__(NT) void k_resident(ImgDesc d, const int2* __restri
         // With citers > 0 the idle workgroups (the grid holds one per macro
         // tile of the image, the queue only the tiles left to the tile path)
         // run the small components' iterations beside the tiles, and flag
-        // that they did (ccount[7], cleared by the labelling).  Workgroup ids
+        // that they did (ccount[kCompFlag], cleared by the labelling; the
+        // component kernel that follows still runs the group classes, which
+        // need whole workgroups of 256 threads).  Workgroup ids
         // among the idle ones: XCD by XCD, ranks past that XCD's tiles.
         if (citers > 0 && !cc_skip(cnpix, d)) {
             const int per_x = (int)gridDim.x >> 3;
@@ -630,7 +632,7 @@ __global__ __launch_bounds__(NT) void k_resident(ImgDesc d, const int2* __restri
             int gid = rank - tiles_of(xcd);
             for (int x = 0; x < xcd; ++x) gid += per_x - tiles_of(x);
             const int idle = (int)gridDim.x - nq;
-            if (gid == 0 && t == 0) cw.ccount[7] = 1;
+            if (gid == 0 && t == 0) cw.ccount[kCompFlag] = 1;
             component_waves(d, cw, citers, inner, theta, inv_theta, tau, nullptr, 0,
                             gid * (NT / 64) + (t >> 6), idle * (NT / 64));
         }

@@ -164,9 +164,13 @@ int prepare_iterate(int ci, bool batched, bool stop = false);
 // off RD), csize (pixels per root), crank (each pixel's rank in its component),
 // cslot (slot of a root in its size class), lane_of (packed lane of a
 // small-component pixel, -1 otherwise), wl_pix (pixel of each packed lane, -1
-// for empty lanes; 2 * plane + 448 entries), ccount (components per class, 7;
-// [7]: set when the resident kernel ran them),
-// npix_tile (RD pixels left to the tile path).
+// for empty lanes; 2 * plane + kCompLaneExtra entries), ccount (kCompCount:
+// components per size class, then [kCompFlag] set when the resident kernel
+// ran the one-wave classes), npix_tile (RD pixels left to the tile path).
+constexpr int kCompClasses = 9;                    // padded sizes 1, 2, 4, ..., 256
+constexpr int kCompLaneExtra = kCompClasses * 64;  // a partly filled last wave per class
+constexpr int kCompCount = 16;
+constexpr int kCompFlag = 15;
 struct CompWs {
     int32_t* lab;
     int32_t* csize;
@@ -198,12 +202,16 @@ int launch_components(const ImgDesc& d, const CompWs& w, const int64_t* npix, in
 // [3][H][ld] slots of the backward): writes sacc and vbar^0 (vb_out) of their
 // pixels.  Then c of those pixels back to theta lambda f.
 // nwaves_hint: the packed component waves (component_waves_of the class
-// counts read back), or -1 when unknown; it picks the LDS form.
+// counts read back), or -1 when unknown; it picks the LDS form.  group_jobs:
+// the jobs of the group classes (component_group_jobs_of), -1 when unknown;
+// their reverse runs first, in a launch of its own (skipped at 0).
 int launch_adj_components(const ImgDesc& d, const CompWs& w, const int64_t* npix,
                           const float* tape, float* seg, int K, int ce, const float* grad_u,
                           const float* grad_v, float* vb_out, float* sacc, float theta,
-                          float inv_theta, float tau, hipStream_t st, int64_t nwaves_hint);
-int64_t component_waves_of(const int32_t* ccount_host);   // waves of classes 0..6
+                          float inv_theta, float tau, hipStream_t st, int64_t nwaves_hint,
+                          int64_t group_jobs = -1);
+int64_t component_waves_of(const int32_t* ccount_host);       // waves of classes 0..6
+int64_t component_group_jobs_of(const int32_t* ccount_host);  // jobs of classes 7, 8
 int launch_components_restore(const ImgDesc& d, const CompWs& w, const int64_t* npix,
                               hipStream_t st);
 

@@ -272,7 +272,10 @@ def test_backward_full_size_differentiation_workload(rd):
                                   ("config5_512", 0.5, 120, 100),
                                   ("config5_2048", 0.5, 60, 30), ("config5_2048", 0.5, 44, 30)])
 def test_component_reverse_matches_tile_path(rd, case):
-    """RD components of at most 64 pixels in both directions: the component
+    """RD components of at most 256 pixels in both directions (those of 65-256
+    pixels, the only ones above 64 at 2048^2 and delta = 0.5 max|f|, as groups
+    of 128 / 256 lanes: the register form, or the per-pixel slots at
+    ckpt_every 60 and 100): the component
     forward writes the same checkpoints (on RD, where the tape is defined) and
     the same u, v, p as the tile path, and their reverse sweep (all steps in
     one launch) gives the same bits as the tile path's per-step launches

@@ -363,10 +363,12 @@ def test_resident_expired_wait_is_reported(rd):
     dict(shape=(300, 257), lam=3.0, frac=0.4, iters=22, tile=(64, 32), ipl=4, inner=2),
 ])
 def test_small_components_match_tile_path(rd, case):
-    """Pixels of RD components of at most 64 pixels run whole in the component
-    kernel (or, in a resident solve, in the resident kernel's workgroups that
-    hold no tile); the results equal those of the tile path for every pixel
-    bit for bit, and match the oracle on the smaller grids."""
+    """Pixels of RD components of at most 256 pixels run whole in the component
+    kernel (those of at most 64 packed into waves, the larger ones in groups of
+    128 or 256 lanes with LDS exchange; in a resident solve the one-wave classes
+    run in the resident kernel's workgroups that hold no tile and the groups in
+    the component kernel after it); the results equal those of the tile path
+    for every pixel bit for bit, and match the oracle on the smaller grids."""
     H, W = case["shape"]
     if H == 1024:
         f = synth.config2({1.0: 0, 5.0: 1, 20.0: 2}[case["lam"]], size=1024, iters=500).f
