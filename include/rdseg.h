@@ -72,7 +72,7 @@ typedef struct {
  * ckpt_every > 0 asks rdseg_solve to write a checkpoint of (v, p) every
  * ckpt_every iterations into `tape` for rdseg_backward (inner = 1 only).
  * components: whether a single-image solve (not under the stopping rule) runs
- * the RD components of at most 64 pixels whole in the component kernel (see
+ * the RD components of at most 256 pixels whole in the component kernel (see
  * rdseg_set_components): 1 = on, 2 = off, 0 = the autotuner's choice for
  * this problem class when the library chooses the tiles, else on.
  * rdseg_backward uses the component path unless components is 2.  Results
@@ -414,7 +414,7 @@ rdseg_status rdseg_batched_lookup(const rdseg_image* imgs, int32_t n, double q, 
  * same fit), also grad_c1, grad_c2 and grad_gamma (device doubles) through
  * eq. CV / eq. DS.  Scalar reductions are FP64 in a fixed order
  * (deterministic).  With the component path on (prm->components != 2 and
- * rdseg_set_components), the RD components of at most 64 pixels run their
+ * rdseg_set_components), the RD components of at most 256 pixels run their
  * whole reverse sweep in one launch and the call synchronises the stream once
  * (to learn whether any tile is left to the per-step path); the results are
  * bitwise those of the per-step path.  RDSEG_ERR_TAPE if tape is NULL or
@@ -486,10 +486,12 @@ rdseg_status rdseg_set_resident_wait(int64_t ticks);
 rdseg_status rdseg_set_batched_form(int32_t form);
 
 /* In single-image solves without the stopping rule, the RD pixels whose
- * 4-connected RD component has at most 64 pixels run every iteration in one
+ * 4-connected RD component has at most 256 pixels run every iteration in one
  * launch, one pixel per lane (an RD pixel interacts only with its own
- * component, Sec. 3); the tile path covers the larger components.  In a
- * resident solve the resident kernel's workgroups that hold no tile run them;
+ * component, Sec. 3; up to 64 pixels in one wave, larger ones in a
+ * workgroup); the tile path covers the larger components.  In a resident
+ * solve the resident kernel's workgroups that hold no tile run the one-wave
+ * ones;
  * with a tape they also write their checkpoints; rdseg_backward runs their
  * whole reverse sweep in one launch.  Skipped on the device when more than
  * 55 % of the pixels are RD.  Results are bitwise equal either way.  on = 0

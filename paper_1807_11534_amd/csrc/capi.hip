@@ -731,7 +731,7 @@ rdseg_status solve_impl(const float* f, rdseg_shape s, const rdseg_params* prm, 
     // checkpoint tape sends every tile through the blocked kernel instead.
     // The stopping rule needs every RD pixel's change at each check, so it
     // also keeps closed tiles in the blocked kernel.
-    // Small RD components (<= 64 pixels) run whole in the component kernel
+    // Small RD components (<= 256 pixels) run whole in the component kernel
     // (which covers every closed tile as well: a closed tile's components are
     // inside it); not under the stopping rule, and index arithmetic in int32.
     // With a tape the component kernel writes its pixels' checkpoints (the
@@ -2036,7 +2036,7 @@ rdseg_status rdseg_backward(const float* f, rdseg_shape s, const rdseg_params* p
     if (launch_init(&d, nullptr, off, 1, s.H, st)) return RDSEG_ERR_HIP;   // c only
     if (launch_tile_masks(&d, nullptr, off, 1, g.strips, w.masks, w.npix, st)) return RDSEG_ERR_HIP;
     const int K = prm->iters;
-    // RD components of at most 64 pixels take the component reverse sweep
+    // RD components of at most 256 pixels take the component reverse sweep
     // (every step in one launch); the tile path below covers the rest
     const bool comps = g_components_on.load() && prm->components != 2 && K > 0 &&
                        g.plane <= ((int64_t)1 << 29);

@@ -5,9 +5,11 @@
 // and at frozen neighbours both are constants (w = -H(-f)/theta, p = 0).  A
 // component of at most 64 pixels can therefore run every iteration inside one
 // wave, one pixel per lane, its neighbours' values fetched from other lanes
-// (ds_bpermute) and its frozen neighbours entering as constants.  Below the
-// percolation threshold of the band most RD pixels sit in such components;
-// the tile path then only has to cover the large ones.
+// (ds_bpermute) and its frozen neighbours entering as constants; one of 65-256
+// pixels in a group of 128 or 256 threads of a workgroup (values exchanged
+// through LDS).  Below the percolation threshold of the band most RD pixels
+// sit in such components; the tile path then only has to cover the large
+// ones.
 //
 // Steps (single image; skipped on the device when more than 55 % of the
 // pixels are RD, where one component spans the image):
@@ -19,14 +21,15 @@
 //   k_cc_flatten   every RD pixel points at its root; component sizes (one
 //                  atomic per root and wave) and each pixel's rank in its
 //                  component
-//   k_cc_class     each small component (<= 64 pixels) takes a slot in the
+//   k_cc_class     each small component (<= 256 pixels) takes a slot in the
 //                  class of its size rounded up to a power of two
 //   k_cc_lanes     the lanes of the waves those classes need start empty
-//   k_cc_assign    each of its pixels takes a lane: waves of one class hold
-//                  64 / 2^k components of 2^k lanes; the pixel is then frozen
+//   k_cc_assign    each of its pixels takes a lane: waves of a class k <= 6
+//                  hold 64 / 2^k components of 2^k lanes, classes 7 and 8 a
+//                  group of 2^k lanes a component; the pixel is then frozen
 //                  for the tile path (c = +inf, its tile-mask bit cleared; the
 //                  tile path's RD count is the full count less these pixels)
-//   k_components   every iteration of the packed waves
+//   k_components   every iteration of the groups, then of the packed waves
 // Lane order within a component depends on atomics, but no result does: each
 // pixel's arithmetic reads exact neighbour values, with the per-pixel
 // functions of the other kernels, so results are bitwise equal to theirs.

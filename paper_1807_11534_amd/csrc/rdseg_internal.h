@@ -183,8 +183,8 @@ struct CompWs {
 };
 
 // Small-component path of a single-image solve (components.hip): label the
-// RD components of d (c already written), pack those of at most 64 pixels
-// into waves and freeze their pixels for the tile path (c = +inf, tile-mask
+// RD components of d (c already written), pack those of at most 256 pixels
+// into waves or groups and freeze their pixels for the tile path (c = +inf, tile-mask
 // bits cleared, w.npix_tile = the RD pixels left to it); then run every
 // iteration of them.  Both do nothing on the device when more than 55 % of
 // the pixels are RD (npix_tile is still written).  With a tape (inner = 1,
