@@ -380,3 +380,15 @@ def test_batched_autotune_validation(lib):
     assert lib.rdseg_autotune_batched(*args(0, 0, 1 << 40)) == 1    # probe_iters < 1
     assert lib.rdseg_autotune_batched(*args(10, 3, 1 << 40)) == 1   # form out of range
     assert lib.rdseg_autotune_batched(*args(10, 0, 16)) == 3        # workspace too small
+
+
+def test_adjoint_form_validation(lib):
+    """The reverse sweep's forms: the compiled (tile, steps) pairs are accepted
+    (0, 0 restores the default), others are rejected with RDSEG_ERR_ARG."""
+    try:
+        for tile, steps in ((32, 1), (16, 2), (16, 4), (32, 2), (32, 4), (0, 0), (16, 0)):
+            assert lib.rdseg_set_adjoint_form(tile, steps) == 0, (tile, steps)
+        for tile, steps in ((64, 2), (32, 3), (16, 1), (8, 2), (-1, 2), (32, 9)):
+            assert lib.rdseg_set_adjoint_form(tile, steps) == 1, (tile, steps)
+    finally:
+        assert lib.rdseg_set_adjoint_form(0, 0) == 0
