@@ -293,18 +293,17 @@ __global__ __launch_bounds__(256) void k_cc_assign(ImgDesc d, CompWs w, uint64_t
         atomicAdd((unsigned long long*)w.npix_tile, (unsigned long long)(-(long long)sFrozen));
 }
 
-// Every iteration of the component path: first the group classes (jobs of a
-// whole workgroup), then the packed one-wave classes unless the resident
-// kernel's idle workgroups already ran them (ccount[kCompFlag] set).
+// Every iteration of the component path (unless the resident kernel's idle
+// workgroups already ran them: ccount[kCompFlag] set): first the group
+// classes (jobs of a whole workgroup), then the packed one-wave classes.
 __global__ __launch_bounds__(256) void k_components(ImgDesc d, CompWs w, const int64_t* npix,
                                                     int iters, int inner, float theta,
                                                     float inv_theta, float tau,
                                                     float* __restrict__ tape, int ce) {
     __shared__ float xbuf[1024];
-    if (cc_skip(npix, d)) return;
+    if (cc_skip(npix, d) || w.ccount[kCompFlag]) return;
     component_groups(d, w, iters, inner, theta, inv_theta, tau, tape, ce, blockIdx.x,
                      gridDim.x, xbuf);
-    if (w.ccount[kCompFlag]) return;
     component_waves(d, w, iters, inner, theta, inv_theta, tau, tape, ce,
                     blockIdx.x * 4 + (threadIdx.x >> 6), gridDim.x * 4);
 }
@@ -372,6 +371,7 @@ __global__ __launch_bounds__(256) void k_adj_components_t(
     if constexpr (GRP) {
         xc.buf = xbuf;
         xc.par = 0;
+        xc.t = (int)threadIdx.x;
     }
     for (int item = blockIdx.x * wpb + wslot; item < nwork;
          item += gridDim.x * wpb) {   // uniform per wave (per workgroup with lds_mode 4 or GRP)

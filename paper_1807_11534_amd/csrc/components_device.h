@@ -67,11 +67,12 @@ struct WaveX {
 };
 
 struct GroupX {
-    float* buf;   // LDS: 2 buffers x 2 values x 256 threads
+    float* buf;   // LDS of this 256-thread slice: 2 buffers x 2 values x 256
     int par;
+    int t;        // the thread's index in its slice
     __device__ __forceinline__ void same2(float a, int i1, int i2, float& r1, float& r2) {
         float* b = buf + par * 512;
-        b[threadIdx.x] = a;
+        b[t] = a;
         __syncthreads();
         r1 = b[i1];
         r2 = b[i2];
@@ -79,8 +80,8 @@ struct GroupX {
     }
     __device__ __forceinline__ void two(float a, int i1, float bb, int i2, float& r1, float& r2) {
         float* b = buf + par * 512;
-        b[threadIdx.x] = a;
-        b[256 + threadIdx.x] = bb;
+        b[t] = a;
+        b[256 + t] = bb;
         __syncthreads();
         r1 = b[i1];
         r2 = b[256 + i2];
@@ -234,20 +235,28 @@ __device__ __forceinline__ void group_lane(const int32_t* ccount, int job, int t
     }
 }
 
-// Jobs of the group classes taken by one 256-thread workgroup: job0, job0 +
-// stride, ... (uniform per workgroup).
+// Jobs of the group classes taken by the 256-thread slices of one workgroup
+// (blockDim.x a multiple of 256, xbuf 1024 floats a slice): workgroup wg of
+// n_wg takes jobs (wg + r n_wg) slices + slice, r = 0, 1, ..., the same
+// number of rounds in every slice (a slice past the last job runs an empty
+// chain), so the slices pass the same workgroup barriers.
 __device__ __forceinline__ void component_groups(const ImgDesc& d, const CompWs& w, int iters,
                                                  int inner, float theta, float inv_theta,
                                                  float tau, float* __restrict__ tape, int ce,
-                                                 int job0, int stride, float* xbuf) {
+                                                 int wg, int n_wg, float* xbuf) {
     const int64_t plane = (int64_t)d.H * d.ld;
     const int njobs = group_jobs(w.ccount);
     const int64_t lanes = 2 * plane + kCompLaneExtra;
-    const int t = threadIdx.x;
-    GroupX xc{xbuf, 0};
-    for (int job = job0; job < njobs; job += stride) {   // uniform per workgroup
-        int lane, base;
-        group_lane(w.ccount, job, t, lane, base);
+    const int slices = (int)(blockDim.x >> 8);
+    const int slice = (int)(threadIdx.x >> 8);
+    const int t = (int)(threadIdx.x & 255);
+    const int per_round = n_wg * slices;
+    const int rounds = (njobs + per_round - 1) / per_round;
+    GroupX xc{xbuf + slice * 1024, 0, t};
+    for (int r = 0; r < rounds; ++r) {   // uniform per workgroup
+        const int job = (wg + r * n_wg) * slices + slice;
+        int lane = -1, base = 0;
+        if (job < njobs) group_lane(w.ccount, job, t, lane, base);
         const int g = (lane >= 0 && lane < lanes) ? w.wl_pix[lane] : -1;
         component_chain(d, w, xc, g, t, base, iters, inner, theta, inv_theta, tau, tape, ce);
         __syncthreads();   // the exchange buffers are reused by the next job

@@ -610,6 +610,8 @@ __global__ __launch_bounds__(NT) void k_resident(ImgDesc d, const int2* __restri
     __shared__ float sPY[LS];
     __shared__ float sW[LS];
     __shared__ int sFail;
+    __shared__ float sGrp[NT / 256 * 1024];   // idle workgroups: the group classes' exchange
+    static_assert(NT % 256 == 0, "idle workgroups run the group classes in 256-thread slices");
 
     const int t = threadIdx.x;
     // the same XCD-contiguous assignment of queue items as the launched kernel
@@ -620,12 +622,12 @@ __global__ __launch_bounds__(NT) void k_resident(ImgDesc d, const int2* __restri
     const int item = xcd * chunk + rank;
     if (rank >= chunk || item >= nq) {   // no tile for this workgroup
         // With citers > 0 the idle workgroups (the grid holds one per macro
-        // tile of the image, the queue only the tiles left to the tile path)
-        // run the small components' iterations beside the tiles, and flag
-        // that they did (ccount[kCompFlag], cleared by the labelling; the
-        // component kernel that follows still runs the group classes, which
-        // need whole workgroups of 256 threads).  Workgroup ids
-        // among the idle ones: XCD by XCD, ranks past that XCD's tiles.
+        // tile of the image, or the queued tiles and some more, the queue only
+        // the tiles left to the tile path) run the component path's
+        // iterations beside the tiles, the group classes in 256-thread slices
+        // and then the packed waves, and flag that they did (ccount[kCompFlag],
+        // cleared by the labelling).  Workgroup ids among the idle ones: XCD
+        // by XCD, ranks past that XCD's tiles.
         if (citers > 0 && !cc_skip(cnpix, d)) {
             const int per_x = (int)gridDim.x >> 3;
             auto tiles_of = [&](int x) { return max(0, min(chunk, nq - x * chunk)); };
@@ -633,6 +635,8 @@ __global__ __launch_bounds__(NT) void k_resident(ImgDesc d, const int2* __restri
             for (int x = 0; x < xcd; ++x) gid += per_x - tiles_of(x);
             const int idle = (int)gridDim.x - nq;
             if (gid == 0 && t == 0) cw.ccount[kCompFlag] = 1;
+            component_groups(d, cw, citers, inner, theta, inv_theta, tau, nullptr, 0, gid, idle,
+                             sGrp);
             component_waves(d, cw, citers, inner, theta, inv_theta, tau, nullptr, 0,
                             gid * (NT / 64) + (t >> 6), idle * (NT / 64));
         }
