@@ -414,6 +414,42 @@ constexpr int kPollMax = 1024;
 std::mutex g_poll_mu;
 float* g_poll_host = nullptr;   // 2 * kPollMax floats, pinned, kept for the process
 
+// Small read-backs that a solve waits for (queue lengths, class counts):
+// through a pinned buffer, which the copy writes directly, so the wait ends
+// as soon as the copy has landed.
+std::mutex g_rb_mu;
+int32_t* g_rb_host = nullptr;   // kReadBack int32, pinned, kept for the process
+constexpr int kReadBack = 64;
+
+// Copy n[i] int32 from each src[i] to dst[i] (k pieces, sum n <= kReadBack),
+// synchronising st once.
+rdseg_status read_back(int k, const int32_t* const* src, const int* n, int32_t* const* dst,
+                       hipStream_t st) {
+    std::lock_guard<std::mutex> lk(g_rb_mu);
+    if (!g_rb_host &&
+        hipHostMalloc(reinterpret_cast<void**>(&g_rb_host), kReadBack * sizeof(int32_t), 0) !=
+            hipSuccess) {
+        g_rb_host = nullptr;
+        return fail(RDSEG_ERR_HIP, "pinned host buffer for read-backs could not be allocated");
+    }
+    int off = 0;
+    for (int i = 0; i < k; ++i) {
+        if (off + n[i] > kReadBack) return fail(RDSEG_ERR_ARG, "read-back too large");
+        if (hipMemcpyAsync(g_rb_host + off, src[i], n[i] * sizeof(int32_t), hipMemcpyDeviceToHost,
+                           st) != hipSuccess)
+            return fail(RDSEG_ERR_HIP, "reading back from the device failed");
+        off += n[i];
+    }
+    if (hipStreamSynchronize(st) != hipSuccess)
+        return fail(RDSEG_ERR_HIP, "reading back from the device failed");
+    off = 0;
+    for (int i = 0; i < k; ++i) {
+        memcpy(dst[i], g_rb_host + off, n[i] * sizeof(int32_t));
+        off += n[i];
+    }
+    return RDSEG_OK;
+}
+
 struct Poller {
     const StopSpec& sp;
     hipStream_t st;
@@ -775,10 +811,13 @@ rdseg_status solve_impl(const float* f, rdseg_shape s, const rdseg_params* prm, 
             // tiles, and the component kernel follows on the whole chip (a few
             // idle workgroups would hold every component chain).
             int32_t nq = 0;
-            if (hipMemcpyAsync(&nq, w.totals, sizeof(int32_t), hipMemcpyDeviceToHost, st) !=
-                    hipSuccess ||
-                hipStreamSynchronize(st) != hipSuccess)
-                return fail(RDSEG_ERR_HIP, "reading the tile queue length failed");
+            {
+                const int32_t* src[1] = {w.totals};
+                const int cnt[1] = {1};
+                int32_t* dst[1] = {&nq};
+                r = read_back(1, src, cnt, dst, st);
+                if (r) return r;
+            }
             const int64_t tiles = ((int64_t)nq + 7) / 8 * 8;
             const int64_t cap = resident_capacity(ci) / 8 * 8;
             if (nq > 0 && tiles <= cap) {
@@ -856,10 +895,10 @@ rdseg_status solve_impl(const float* f, rdseg_shape s, const rdseg_params* prm, 
         hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
         if (hipStreamIsCapturing(st, &cap) == hipSuccess && cap == hipStreamCaptureStatusNone) {
             int32_t nq = 1;
-            if (hipMemcpyAsync(&nq, w.totals, sizeof(int32_t), hipMemcpyDeviceToHost, st) !=
-                    hipSuccess ||
-                hipStreamSynchronize(st) != hipSuccess)
-                r = fail(RDSEG_ERR_HIP, "reading the tile queue length failed");
+            const int32_t* src[1] = {w.totals};
+            const int cnt[1] = {1};
+            int32_t* dst[1] = {&nq};
+            r = read_back(1, src, cnt, dst, st);
             tiles_left = nq > 0;
         }
     }
@@ -2062,12 +2101,11 @@ rdseg_status rdseg_backward(const float* f, rdseg_shape s, const rdseg_params* p
     int32_t ccount[kCompCount] = {};
     int64_t comp_waves = -1, comp_jobs = -1;
     if (comps) {
-        if (hipMemcpyAsync(&n_tiles_left, w.totals, sizeof(int32_t), hipMemcpyDeviceToHost, st) !=
-                hipSuccess ||
-            hipMemcpyAsync(ccount, w.comp.ccount, sizeof(ccount), hipMemcpyDeviceToHost, st) !=
-                hipSuccess ||
-            hipStreamSynchronize(st) != hipSuccess)
-            return fail(RDSEG_ERR_HIP, "reading the tile queue length failed");
+        const int32_t* src[2] = {w.totals, w.comp.ccount};
+        const int cnt[2] = {1, kCompCount};
+        int32_t* dst[2] = {&n_tiles_left, ccount};
+        const rdseg_status rb = read_back(2, src, cnt, dst, st);
+        if (rb) return rb;
         // (meaningless, and unused on the device, if the labelling was skipped)
         comp_waves = component_waves_of(ccount);
         comp_jobs = component_group_jobs_of(ccount);
@@ -2503,6 +2541,12 @@ rdseg_status rdseg_release(void) {
         if (g_poll_host && hipHostFree(g_poll_host) != hipSuccess)
             r = fail(RDSEG_ERR_HIP, "releasing the pinned polling buffer failed");
         g_poll_host = nullptr;
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_rb_mu);
+        if (g_rb_host && hipHostFree(g_rb_host) != hipSuccess)
+            r = fail(RDSEG_ERR_HIP, "releasing the pinned read-back buffer failed");
+        g_rb_host = nullptr;
     }
     return r;
 }
