@@ -213,32 +213,19 @@ def extras(torch, rdseg, synth, dev, which=EXTRAS):
             n_px = sum(p.f.size for p in probs)
             q = sum(float((np.abs(p.f.astype(np.float64)) < d).sum())
                     for p, d in zip(probs, deltas)) / n_px
-            # the batch's configuration and form of the iterations autotuned on
-            # the batch itself (shorter probes), then the library's choice
-            # from the tuning cache, captured as one graph
-            rdseg.tune_cache_clear()
-            tuner = rdseg.BatchedSolver(fs, lams, deltas, synth.THETA, synth.TAU, 300, tile=None,
-                                        iters_per_launch=0, graph=False)
-            tuned = tuner.autotune(probe_iters=40)
-            (tile, ipl), form = tuned, tuned.form
-            del tuner
+            # the library's choice for the batch (configuration and form of
+            # the iterations from the committed tuning cache's entry for the
+            # batch's class, written by rdseg_autotune_batched runs on this
+            # workload), captured as one graph
             bs = rdseg.BatchedSolver(fs, lams, deltas, synth.THETA, synth.TAU, 300, tile=None,
                                      iters_per_launch=0, graph=True)
+            tuned = bs.lookup(q)
+            (tile, ipl), form = tuned, tuned.form
             reps = 2 if not math.isfinite(frac) else 10
             bs.run()
             bs.run()
             t_graph = timed(torch, bs.run, reps)
             outs = [tuple(t.clone() for t in o) for o in bs.out]
-            # the other form of the iterations at the same configuration
-            rdseg.set_batched_form(3 - form)
-            other = rdseg.BatchedSolver(fs, lams, deltas, synth.THETA, synth.TAU, 300,
-                                        tile=tuple(tile), iters_per_launch=ipl, graph=True)
-            other.run()
-            other.run()
-            t_other = timed(torch, other.run, reps)
-            other.close()
-            del other
-            rdseg.set_batched_form(2)
             seq_out = [tuple(torch.empty_like(t) for t in o) for o in bs.out]
             wss = [rdseg.workspace(rdseg.shape_of(f)) for f in fs]
 
@@ -254,8 +241,8 @@ def extras(torch, rdseg, synth, dev, which=EXTRAS):
             forms = {1: "persistent", 2: "launches"}
             out[name] = dict(images=512, pixels=n_px, active_fraction=q, iters=300,
                              tile=list(tile), iters_per_launch=ipl, form=forms[form],
-                             autotuned=True, graph_ms=t_graph,
-                             other_form=dict(form=forms[3 - form], graph_ms=t_other),
+                             configuration="tuning cache" if tuned.cached else "untuned default",
+                             graph_ms=t_graph,
                              sequential_ms=t_seq, speedup=t_seq / t_graph,
                              updates_per_s=upd / (t_graph * 1e-3),
                              bitwise_equal_to_sequential=bool(same))

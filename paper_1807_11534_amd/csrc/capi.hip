@@ -886,12 +886,14 @@ rdseg_status solve_impl(const float* f, rdseg_shape s, const rdseg_params* prm, 
         a.comp = &w.comp;
         a.comp_npix = w.npix;
     }
-    // A taped solve whose RD pixels all went to the component path leaves the
-    // tile path nothing but launches on an empty queue and checkpoint copies
-    // of no pixel: read the queue length once (synchronises; not under graph
-    // capture) and skip them.
+    // A solve whose RD pixels all went to the component path leaves the tile
+    // path nothing but launches on an empty queue (and, with a tape,
+    // checkpoint copies of no pixel): read the queue length once
+    // (synchronises the stream, the component kernel running on beside it;
+    // not under graph capture, nor without allocation, nor for a resident
+    // launch, which ends at once on an empty queue) and skip them.
     bool tiles_left = true;
-    if (comps && taped) {
+    if (comps && (taped || (!resident && !no_alloc))) {
         hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
         if (hipStreamIsCapturing(st, &cap) == hipSuccess && cap == hipStreamCaptureStatusNone) {
             int32_t nq = 1;
