@@ -178,10 +178,12 @@ rdseg_status rdseg_band_threshold(const float* f, rdseg_shape s, double q, doubl
  * hold u = v = H(-f), p = 0).  u0 == u and p0 == p are allowed (warm start in
  * place); u, v, p must not overlap f or each other.  iters == 0 returns the
  * initial state.  tape (device, nullable) receives the checkpoints when
- * prm->ckpt_every > 0 (size rdseg_tape_size; defined on RD pixels only); such
- * a solve with the component path on reads the tile-queue length once
+ * prm->ckpt_every > 0 (size rdseg_tape_size; defined on RD pixels only).  A
+ * solve with the component path on reads the tile-queue length once
  * (synchronises the stream, except under graph capture) to skip the tile path
- * when the components hold every RD pixel.  Results are bitwise identical
+ * when the components hold every RD pixel: always with a tape, and without
+ * one unless the iterations run in the resident form (which ends at once on
+ * an empty queue).  Results are bitwise identical
  * for every tile configuration and iters_per_launch, and a solve of K1
  * iterations resumed for K2 more (u0 = u, p0 = p) equals one of K1 + K2. */
 rdseg_status rdseg_solve(const float* f, rdseg_shape s, const rdseg_params* prm,

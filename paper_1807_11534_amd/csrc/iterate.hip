@@ -491,14 +491,19 @@ __global__ __launch_bounds__(NT) void k_recompute(ImgDesc d0, const int2* __rest
 
 // Grid-wide barrier of a cooperative launch: every workgroup adds one to
 // *bar (a counter that starts at 0 and only grows), then waits until it reads
-// gen * gridDim.x.  The release fence before the arrival and the acquire fence
-// after the wait order the state buffers written before the barrier against
-// the loads after it, as a kernel boundary does.  The wait is bounded
+// gen * gridDim.x.  Every thread first waits until its own stores have
+// completed (s_waitcnt 0: the workgroup barrier alone does not wait for
+// them, and a store that reaches the XCD's L2 after thread 0's write-back
+// would stay there, unseen by the other XCDs); then thread 0's release fence
+// writes the L2 back before the arrival, and its acquire fence after the wait
+// invalidates it, so the state buffers written before the barrier are ordered
+// against the loads after it, as at a kernel boundary.  The wait is bounded
 // (wait_ticks of the 100 MHz wall clock; < 0 gives up at once): on expiry the
 // workgroup sets *status and returns false.
 __device__ __forceinline__ bool grid_barrier(int32_t* bar, int gen, int64_t wait_ticks,
                                              int32_t* status) {
     __shared__ int sOk;
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x == 0) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -968,6 +973,27 @@ int persistent_blocks(const void* kernel, int threads, size_t dyn_lds) {
     return per * ncu;
 }
 
+// Workgroups of a cooperative launch (every workgroup must be resident at
+// once): the occupancy query's count, but at most 24 waves (6 a SIMD) and 16
+// workgroups per CU.  The query allows up to 8 waves a SIMD; measured on
+// gfx950, persistent grids sized to 7 or 8 waves a SIMD did not all become
+// resident (their grid barriers' bounded waits expired), while grids of up
+// to 6 waves a SIMD always did.
+int cooperative_blocks(const void* kernel, int threads, size_t dyn_lds) {
+    constexpr int kWavesPerCu = 24, kGroupsPerCu = 16;
+    const int total = persistent_blocks(kernel, threads, dyn_lds);
+    int dev = 0, ncu = 0;
+    if (total <= 0 || hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        ncu <= 0)
+        return 0;
+    const int waves = (threads + 63) / 64;
+    int per = total / ncu;
+    per = std::min(per, std::max(1, kWavesPerCu / waves));
+    per = std::min(per, kGroupsPerCu);
+    return per * ncu;
+}
+
 namespace {
 // 1 s of the 100 MHz wall clock per wait, unless the host set another bound
 constexpr int64_t kResidentWaitTicks = 100000000;
@@ -985,7 +1011,7 @@ int resident_capacity(int ci) {
     if (r < 0) return 0;
     int cap = g_res_cap[r].load(std::memory_order_relaxed);
     if (cap == 0) {
-        cap = persistent_blocks(reinterpret_cast<const void*>(kRes[r].fn), kRes[r].nt, 0);
+        cap = cooperative_blocks(reinterpret_cast<const void*>(kRes[r].fn), kRes[r].nt, 0);
         if (cap <= 0) cap = -1;
         g_res_cap[r].store(cap, std::memory_order_relaxed);
     }
@@ -1118,7 +1144,7 @@ int prepare_iterate_persist(int ci) {
     const CfgEntry& e = kCfgs[ci];
     int cap = g_persist_cap[ci].load(std::memory_order_relaxed);
     if (cap == 0) {
-        cap = persistent_blocks(reinterpret_cast<const void*>(e.pfn), e.cfg.nt, 0);
+        cap = cooperative_blocks(reinterpret_cast<const void*>(e.pfn), e.cfg.nt, 0);
         if (cap <= 0) cap = -1;
         g_persist_cap[ci].store(cap, std::memory_order_relaxed);
     }

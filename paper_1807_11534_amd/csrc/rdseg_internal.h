@@ -342,5 +342,6 @@ int launch_scatter_scalars(const double* src, double* a, double* b, double* c, d
                            hipStream_t st);
 
 int persistent_blocks(const void* kernel, int threads, size_t dyn_lds);
+int cooperative_blocks(const void* kernel, int threads, size_t dyn_lds);
 
 }  // namespace rdseg

@@ -123,6 +123,35 @@ def test_batched_disc_rect_workload_subset(rd):
     bs.close()
 
 
+def test_persistent_form_every_config(rd):
+    """The persistent form (every block of iterations in one cooperative
+    launch, grid-wide barriers) in every compiled configuration, bitwise equal
+    to one launch per block.  Its grid is sized to the workgroups that are
+    resident at once; a grid larger than that would leave the barriers' bounded
+    waits to expire with the iterations incomplete."""
+    import ctypes
+    lib = rd._lib.load()
+    fs, lams, deltas = make_batch(9, 7)
+    fd = [dev(f) for f in fs]
+    for ci in range(lib.rdseg_config_count()):
+        v = [ctypes.c_int32(0) for _ in range(4)]
+        lib.rdseg_config_get(ci, *[ctypes.byref(x) for x in v])
+        tile, ipl = (v[0].value, v[1].value), v[2].value
+        print(f"persistent form tile={tile} ipl={ipl} threads={v[3].value}", flush=True)
+        outs = {}
+        try:
+            for form in (2, 1):
+                rd.set_batched_form(form)
+                bs = rd.BatchedSolver(fd, lams, deltas, 0.1, 0.125, 24, tile=tile,
+                                      iters_per_launch=ipl, graph=False)
+                outs[form] = [tuple(host(x) for x in o) for o in bs.run()]
+        finally:
+            rd.set_batched_form(2)
+        for a, b in zip(outs[1], outs[2]):
+            for x, y in zip(a, b):
+                np.testing.assert_array_equal(x, y)
+
+
 def test_batched_form_validation(rd):
     from paper_1807_11534_amd._lib import RdsegError
     with pytest.raises(RdsegError):
