@@ -570,7 +570,8 @@ rdseg_status rdseg_timing_reset(void);
 
 /* Releases what the library keeps for the process on the host and in the
  * HIP runtime: the per-device side streams (after their work completes), the
- * timing events and the pinned host buffers of timing and polling.  Device
+ * timing events and the pinned host buffers of timing, polling and the small
+ * read-backs a solve waits for (queue lengths, class counts).  Device
  * memory of batched plans is not touched (rdseg_plan_destroy).  Call it
  * before the HIP runtime shuts down (the Python binding does at interpreter
  * exit); the library creates them again on later use.  Not concurrent with

@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <map>
 #include <atomic>
 #include <mutex>
@@ -414,35 +415,80 @@ constexpr int kPollMax = 1024;
 std::mutex g_poll_mu;
 float* g_poll_host = nullptr;   // 2 * kPollMax floats, pinned, kept for the process
 
-// Small read-backs that a solve waits for (queue lengths, class counts):
-// through a pinned buffer, which the copy writes directly, so the wait ends
-// as soon as the copy has landed.
+// Small read-backs that a solve waits for (queue lengths, class counts): a
+// one-wave kernel copies the values into pinned, host-coherent memory and then
+// stores a sequence number there (system scope, after a system-scope fence),
+// which the host spins on.  The wait therefore ends as soon as the values have
+// landed, without a copy command or a wake-up of a blocked thread; after 2 ms
+// of spinning it blocks on the stream instead (long work ahead on it, or an
+// error, which the stream synchronisation then reports).
 std::mutex g_rb_mu;
 int32_t* g_rb_host = nullptr;   // kReadBack int32, pinned, kept for the process
-constexpr int kReadBack = 64;
+int32_t g_rb_seq = 0;
+constexpr int kReadBack = 64;   // the last word holds the sequence number
+constexpr int kReadBackPieces = 4;
 
-// Copy n[i] int32 from each src[i] to dst[i] (k pieces, sum n <= kReadBack),
-// synchronising st once.
+struct ReadBackArgs {
+    const int32_t* src[kReadBackPieces];
+    int n[kReadBackPieces];
+    int k;
+};
+
+__global__ __launch_bounds__(64) void k_read_back(ReadBackArgs a, int32_t* host, int32_t seq) {
+    int off = 0;
+    for (int i = 0; i < a.k; ++i) {
+        for (int j = threadIdx.x; j < a.n[i]; j += 64) host[off + j] = a.src[i][j];
+        off += a.n[i];
+    }
+    __threadfence_system();
+    __syncthreads();
+    if (threadIdx.x == 0)
+        __hip_atomic_store(host + kReadBack - 1, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// Copy n[i] int32 from each src[i] to dst[i] (k <= kReadBackPieces pieces,
+// sum n < kReadBack) once the work enqueued on st before has written them.
 rdseg_status read_back(int k, const int32_t* const* src, const int* n, int32_t* const* dst,
                        hipStream_t st) {
     std::lock_guard<std::mutex> lk(g_rb_mu);
     if (!g_rb_host &&
-        hipHostMalloc(reinterpret_cast<void**>(&g_rb_host), kReadBack * sizeof(int32_t), 0) !=
+        hipHostMalloc(reinterpret_cast<void**>(&g_rb_host), kReadBack * sizeof(int32_t),
+                      hipHostMallocMapped | hipHostMallocCoherent | hipHostMallocPortable) !=
             hipSuccess) {
         g_rb_host = nullptr;
         return fail(RDSEG_ERR_HIP, "pinned host buffer for read-backs could not be allocated");
     }
-    int off = 0;
+    if (g_rb_seq == 0)   // a new buffer: no sequence number written yet
+        __atomic_store_n(g_rb_host + kReadBack - 1, 0, __ATOMIC_RELEASE);
+    if (k < 1 || k > kReadBackPieces) return fail(RDSEG_ERR_ARG, "read-back: 1 to 4 pieces");
+    ReadBackArgs a{};
+    a.k = k;
+    int total = 0;
     for (int i = 0; i < k; ++i) {
-        if (off + n[i] > kReadBack) return fail(RDSEG_ERR_ARG, "read-back too large");
-        if (hipMemcpyAsync(g_rb_host + off, src[i], n[i] * sizeof(int32_t), hipMemcpyDeviceToHost,
-                           st) != hipSuccess)
-            return fail(RDSEG_ERR_HIP, "reading back from the device failed");
-        off += n[i];
+        a.src[i] = src[i];
+        a.n[i] = n[i];
+        total += n[i];
     }
-    if (hipStreamSynchronize(st) != hipSuccess)
-        return fail(RDSEG_ERR_HIP, "reading back from the device failed");
-    off = 0;
+    if (total >= kReadBack) return fail(RDSEG_ERR_ARG, "read-back too large");
+    int32_t* dev = nullptr;
+    if (hipHostGetDevicePointer(reinterpret_cast<void**>(&dev), g_rb_host, 0) != hipSuccess)
+        return fail(RDSEG_ERR_HIP, "mapping the read-back buffer failed");
+    const int32_t seq = g_rb_seq = g_rb_seq == INT32_MAX ? 1 : g_rb_seq + 1;
+    hipLaunchKernelGGL(k_read_back, dim3(1), dim3(64), 0, st, a, dev, seq);
+    if (hipGetLastError() != hipSuccess) return fail(RDSEG_ERR_HIP, "reading back from the device failed");
+    const auto t0 = std::chrono::steady_clock::now();
+    int spins = 0;
+    while (__atomic_load_n(g_rb_host + kReadBack - 1, __ATOMIC_ACQUIRE) != seq) {
+        if ((++spins & 255) == 0 &&
+            std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(2)) {
+            if (hipStreamSynchronize(st) != hipSuccess)
+                return fail(RDSEG_ERR_HIP, "reading back from the device failed");
+            if (__atomic_load_n(g_rb_host + kReadBack - 1, __ATOMIC_ACQUIRE) != seq)
+                return fail(RDSEG_ERR_HIP, "the read-back did not arrive");
+            break;
+        }
+    }
+    int off = 0;
     for (int i = 0; i < k; ++i) {
         memcpy(dst[i], g_rb_host + off, n[i] * sizeof(int32_t));
         off += n[i];
@@ -2549,6 +2595,7 @@ rdseg_status rdseg_release(void) {
         if (g_rb_host && hipHostFree(g_rb_host) != hipSuccess)
             r = fail(RDSEG_ERR_HIP, "releasing the pinned read-back buffer failed");
         g_rb_host = nullptr;
+        g_rb_seq = 0;
     }
     return r;
 }

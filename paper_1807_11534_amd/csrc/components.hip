@@ -195,31 +195,56 @@ __global__ __launch_bounds__(256) void k_cc_class(ImgDesc d, CompWs w, const int
     const int64_t g0 = (int64_t)blockIdx.x * per_wg;
     const int64_t g1 = min(plane, g0 + per_wg);
     const int l = t & 63;
-    for (int64_t g = g0 + t; g < g1; g += 256) {
-        int k = -1;   // size class of a small root
-        if (w.lab[g] == (int32_t)g) {
-            const int s = w.csize[g];
-            if (s >= 1 && s <= kCompMax) k = size_class(s);
+    // four pixels a thread per round, their loads issued together
+    for (int64_t gb = g0; gb < g1; gb += 1024) {
+        int lv[4], sz[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t g = gb + t + i * 256;
+            lv[i] = g < g1 ? w.lab[g] : -1;
         }
-        // local slots: one LDS atomic per class and wave, lanes in order
-        for (int c = 0; c < kCompClasses; ++c) {
-            const uint64_t m = __ballot(k == c);
-            if (!m) continue;   // uniform
-            const int leader = __ffsll((unsigned long long)m) - 1;
-            int base = 0;
-            if (l == leader) base = atomicAdd(&sCount[c], __popcll(m));
-            base = __shfl(base, leader);
-            if (k == c) w.cslot[g] = base + __popcll(m & ((1ull << l) - 1));
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t g = gb + t + i * 256;
+            sz[i] = (g < g1 && lv[i] == (int32_t)g) ? w.csize[g] : 0;
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t g = gb + t + i * 256;
+            // size class of a small root
+            const int k = (sz[i] >= 1 && sz[i] <= kCompMax) ? size_class(sz[i]) : -1;
+            // local slots: one LDS atomic per class and wave, lanes in order
+            for (int c = 0; c < kCompClasses; ++c) {
+                const uint64_t m = __ballot(k == c);
+                if (!m) continue;   // uniform
+                const int leader = __ffsll((unsigned long long)m) - 1;
+                int base = 0;
+                if (l == leader) base = atomicAdd(&sCount[c], __popcll(m));
+                base = __shfl(base, leader);
+                if (k == c) w.cslot[g] = base + __popcll(m & ((1ull << l) - 1));
+            }
         }
     }
     __syncthreads();
     if (t < kCompClasses) sBase[t] = sCount[t] ? atomicAdd(w.ccount + t, sCount[t]) : 0;
     __syncthreads();
-    for (int64_t g = g0 + t; g < g1; g += 256) {
-        if (w.lab[g] != (int32_t)g) continue;
-        const int s = w.csize[g];
-        if (s < 1 || s > kCompMax) continue;
-        w.cslot[g] += sBase[size_class(s)];
+    for (int64_t gb = g0; gb < g1; gb += 1024) {
+        int lv[4], sz[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t g = gb + t + i * 256;
+            lv[i] = g < g1 ? w.lab[g] : -1;
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t g = gb + t + i * 256;
+            sz[i] = (g < g1 && lv[i] == (int32_t)g) ? w.csize[g] : 0;
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t g = gb + t + i * 256;
+            if (sz[i] >= 1 && sz[i] <= kCompMax) w.cslot[g] += sBase[size_class(sz[i])];
+        }
     }
 }
 
@@ -238,30 +263,50 @@ __global__ __launch_bounds__(256) void k_cc_lanes(ImgDesc d, CompWs w, const int
 __global__ __launch_bounds__(256) void k_cc_assign(ImgDesc d, CompWs w, uint64_t* masks,
                                                    const int64_t* npix) {
     __shared__ int sFrozen;
+    __shared__ int sCB[kCompClasses];   // class_base of each class
     if (cc_skip(npix, d)) return;   // uniform: npix is not changed by this pass
     if (threadIdx.x == 0) sFrozen = 0;
+    if (threadIdx.x < kCompClasses) sCB[threadIdx.x] = class_base(w.ccount, threadIdx.x);
     __syncthreads();
     const int64_t plane = (int64_t)d.H * d.ld;
     int frozen = 0;
     const int l = threadIdx.x & 63;
-    for (int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x; g < plane;
-         g += (int64_t)gridDim.x * 256) {
-        const int y = (int)(g / d.ld), x = (int)(g - (int64_t)y * d.ld);
-        const int r = w.lab[g];
-        bool frz = false;
-        if (r >= 0 && r < plane) {
-            const int s = w.csize[r];
-            if (s >= 1 && s <= kCompMax) {
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    // four pixels a thread per round (each wave still 64 consecutive pixels
+    // for each of them), their loads issued together
+    for (int64_t gb = (int64_t)blockIdx.x * 256 + threadIdx.x; gb < plane; gb += 4 * stride) {
+        int rr[4], sz[4], sl[4], rk[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t g = gb + i * stride;
+            rr[i] = g < plane ? w.lab[g] : -1;
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t g = gb + i * stride;
+            const bool ok = rr[i] >= 0 && rr[i] < plane;
+            sz[i] = ok ? w.csize[rr[i]] : 0;
+            sl[i] = ok ? w.cslot[rr[i]] : -1;
+            rk[i] = ok ? w.crank[g] : 0;
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t g = gb + i * stride;
+            if (g - threadIdx.x + (threadIdx.x & ~63) >= plane) break;   // uniform per wave
+            const int y = (int)(g / d.ld), x = (int)(g - (int64_t)y * d.ld);
+            const int s = sz[i];
+            bool frz = false;
+            if (g < plane && s >= 1 && s <= kCompMax) {
                 const int k = size_class(s);
-                const int slot = w.cslot[r];
-                const int rank = w.crank[g];
+                const int slot = sl[i];
+                const int rank = rk[i];
                 int L;
                 if (k < kWaveClasses) {   // 64 / 2^k components packed into a wave
                     const int per = kSmallMax >> k;
-                    const int wave = class_base(w.ccount, k) + slot / per;
+                    const int wave = sCB[k] + slot / per;
                     L = wave * 64 + (slot % per) * (1 << k) + rank;
                 } else {                  // one component a group of 2^k lanes
-                    L = class_base(w.ccount, k) * 64 + slot * (1 << k) + rank;
+                    L = sCB[k] * 64 + slot * (1 << k) + rank;
                 }
                 // never false for a well-formed labelling (see kCompLaneExtra);
                 // a guard against writing outside the lane table
@@ -273,17 +318,18 @@ __global__ __launch_bounds__(256) void k_cc_assign(ImgDesc d, CompWs w, uint64_t
                     ++frozen;
                 }
             }
-        }
-        // Tile-mask bits of the frozen pixels: the lanes of one 8x8 tile row
-        // are consecutive in the wave (they start where x mod 8 = 0, or at
-        // lane 0), so the first of them clears all their bits with one atomic.
-        const uint64_t fm = __ballot(frz);
-        if (fm && ((x & 7) == 0 || l == 0) && x < d.W) {
-            const int glen = min(min(8 - (x & 7), 64 - l), d.W - x);
-            const uint64_t bits = (fm >> l) & ((1ull << glen) - 1);
-            if (bits) {
-                const int64_t T = (int64_t)(y >> 3) * d.tw + (x >> 3);
-                atomicAnd((unsigned long long*)(masks + T), ~(bits << (8 * (y & 7) + (x & 7))));
+            // Tile-mask bits of the frozen pixels: the lanes of one 8x8 tile
+            // row are consecutive in the wave (they start where x mod 8 = 0,
+            // or at lane 0), so the first of them clears all their bits with
+            // one atomic.
+            const uint64_t fm = __ballot(frz);
+            if (fm && g < plane && ((x & 7) == 0 || l == 0) && x < d.W) {
+                const int glen = min(min(8 - (x & 7), 64 - l), d.W - x);
+                const uint64_t bits = (fm >> l) & ((1ull << glen) - 1);
+                if (bits) {
+                    const int64_t T = (int64_t)(y >> 3) * d.tw + (x >> 3);
+                    atomicAnd((unsigned long long*)(masks + T), ~(bits << (8 * (y & 7) + (x & 7))));
+                }
             }
         }
     }
