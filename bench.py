@@ -395,9 +395,6 @@ def main():
     if unknown:
         print(f"unknown extra workloads: {unknown}; choose from {EXTRAS}", file=sys.stderr)
         sys.exit(2)
-    if args.extras_only:
-        print(json.dumps(dict(extras=extras(torch, rdseg, synth, dev, which))), flush=True)
-        return
     if args.tune == "cache":
         if not os.path.exists(args.tune_cache):
             print(f"tuning cache {args.tune_cache} not found (make one with --tune auto "
@@ -405,6 +402,9 @@ def main():
             sys.exit(2)
         rdseg.tune_cache_clear()
         rdseg.tune_cache_load(args.tune_cache)
+    if args.extras_only:
+        print(json.dumps(dict(extras=extras(torch, rdseg, synth, dev, which))), flush=True)
+        return
     log("sweep: generating and tuning")
     probs, cases = sweep_cases(torch, rdseg, synth, args, dev)
 
