@@ -526,13 +526,48 @@ __device__ __forceinline__ bool grid_barrier(int32_t* bar, int gen, int64_t wait
     return sOk != 0;
 }
 
+// The macro tiles a workgroup takes in iterate_pass (the same XCD-chunked
+// split of the queue) marked as failed: NaN in u, v and p of every pixel of
+// the tile.
+template <int BX, int BY, int NT>
+__device__ void mark_failed_tiles(const ImgDesc* __restrict__ descs,
+                                  const int2* __restrict__ queue,
+                                  const int32_t* __restrict__ n_queue) {
+    const int nq = *n_queue;
+    const int per = gridDim.x >> 3;
+    const int xcd = blockIdx.x & 7;
+    const int rank = blockIdx.x >> 3;
+    const int chunk = (nq + 7) >> 3;
+    const int q0 = xcd * chunk;
+    const int q1 = min(nq, q0 + chunk);
+    const float nan = __builtin_nanf("");
+    for (int item = q0 + rank; item < q1; item += per) {
+        const int2 q = queue[item];
+        const ImgDesc& d = descs[q.x];
+        const int my = q.y / d.mw;
+        const int mx = q.y - my * d.mw;
+        for (int k = threadIdx.x; k < BX * BY; k += NT) {
+            const int x = mx * BX + k % BX, y = my * BY + k / BX;
+            if (x >= d.W || y >= d.H) continue;
+            const int64_t g = (int64_t)y * d.ld + x;
+            d.u[g] = nan;
+            d.st[0][0][g] = nan;
+            d.st[0][1][g] = nan;
+            d.st[0][2][g] = nan;
+        }
+    }
+}
+
 // Persistent form of the batched iteration: one cooperative launch runs every
 // block of `per` outer iterations over the global (image, macro tile) queue,
 // exactly the work and buffer parities of the L = ceil(iters / per) separate
 // launches, with a grid-wide barrier in place of each kernel boundary (so the
 // results are bitwise those of the separate launches).  An empty queue ends
-// the launch at once.  A barrier whose wait expires stops the workgroup (the
-// solve's status word is set; the results are then incomplete).
+// the launch at once.  A barrier whose wait expires stops the workgroup: the
+// solve's status word is set and the workgroup writes NaN into u, v and p of
+// its macro tiles, so that the incomplete result cannot pass for a solution
+// (the other workgroups' waits then expire too, or they read those NaN in
+// their halos).
 template <int BX, int BY, int IT, int NT>
 __global__ __launch_bounds__(NT) void k_iterate_persist(ImgDesc d0,
                                                         const ImgDesc* __restrict__ descs,
@@ -550,7 +585,10 @@ __global__ __launch_bounds__(NT) void k_iterate_persist(ImgDesc d0,
         iterate_pass<BX, BY, IT, NT, true, false, (BX >= 64), (BX < 64)>(
             d0, descs, queue, n_queue, (L - j) & 1, nit, j == L - 1 ? 1 : 0, theta, inv_theta,
             tau, nullptr, nullptr, 0.0, 1);
-        if (j < L - 1 && !grid_barrier(bar, j + 1, wait_ticks, status)) return;
+        if (j < L - 1 && !grid_barrier(bar, j + 1, wait_ticks, status)) {
+            mark_failed_tiles<BX, BY, NT>(descs, queue, n_queue);
+            return;
+        }
     }
 }
 

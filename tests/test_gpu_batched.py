@@ -152,6 +152,38 @@ def test_persistent_form_every_config(rd):
                 np.testing.assert_array_equal(x, y)
 
 
+def test_persistent_expired_wait_marks_tiles(rd):
+    """A persistent batched solve whose grid-barrier waits expire (forced from
+    the host: every wait gives up at once) leaves NaN in u, v and p of its
+    queued macro tiles instead of an incomplete result that could pass for a
+    solution: every pixel of the images whose whole grid is RD.  The same
+    batch with the default bound afterwards is bitwise the launches form."""
+    fs, lams, deltas = make_batch(9, 7)
+    fd = [dev(f) for f in fs]
+    tile, ipl = (16, 16), 2
+    print("persistent form, forced expiry", flush=True)
+    try:
+        rd.set_batched_form(1)
+        rd.set_resident_wait(-1)
+        bs = rd.BatchedSolver(fd, lams, deltas, 0.1, 0.125, 24, tile=tile, iters_per_launch=ipl,
+                              graph=False)
+        failed = [tuple(host(x).copy() for x in o) for o in bs.run()]
+        rd.set_resident_wait(0)
+        again = [tuple(host(x).copy() for x in o) for o in bs.run()]
+        rd.set_batched_form(2)
+        ref = [tuple(host(x).copy() for x in o) for o in bs.run()]
+    finally:
+        rd.set_resident_wait(0)
+        rd.set_batched_form(2)
+    for i, d in enumerate(deltas):
+        if math.isinf(d):
+            for a in failed[i]:
+                assert np.isnan(a).all(), f"image {i}: a pixel of a queued tile kept a value"
+    for a, b in zip(again, ref):
+        for x, y in zip(a, b):
+            np.testing.assert_array_equal(x, y)
+
+
 def test_batched_form_validation(rd):
     from paper_1807_11534_amd._lib import RdsegError
     with pytest.raises(RdsegError):
