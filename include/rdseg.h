@@ -473,8 +473,9 @@ rdseg_status rdseg_set_resident(int32_t on);
 /* Bound of each wait of the resident form in ticks of the GPU's 100 MHz
  * wall clock: ticks > 0 sets it, 0 restores the default (10^8, one second),
  * ticks < 0 makes every wait that is not already satisfied give up at once
- * (the expiry path forced from the host, for tests of rdseg_solve_status).
- * Process-wide; read when a resident solve is enqueued. */
+ * (the expiry path forced from the host, for tests of rdseg_solve_status and
+ * of the persistent batched form).  Process-wide; read when a resident solve
+ * or a persistent batched launch is enqueued. */
 rdseg_status rdseg_set_resident_wait(int64_t ticks);
 
 /* The form of the iterations of rdseg_solve_batched when the caller fixes the
@@ -483,7 +484,10 @@ rdseg_status rdseg_set_resident_wait(int64_t ticks);
  * macro tile) queue in one persistent cooperative launch, with a grid-wide
  * barrier between blocks (an empty queue ends it at once); form 2 (the
  * default) enqueues one launch per block.  Results are bitwise equal either
- * way.  A plan keeps the form it was built with.  Process-wide.
+ * way.  Form 1's barrier waits are bounded like the resident form's
+ * (rdseg_set_resident_wait); a workgroup whose wait expires writes NaN into
+ * u, v and p of its macro tiles, so an incomplete batch never reads as a
+ * solution.  A plan keeps the form it was built with.  Process-wide.
  * RDSEG_ERR_ARG for any other value. */
 rdseg_status rdseg_set_batched_form(int32_t form);
 
