@@ -368,7 +368,7 @@ rdseg_status join_closed(hipStream_t st, hipEvent_t join) {
     return e == hipSuccess ? RDSEG_OK : fail(RDSEG_ERR_HIP, "joining the closed-tile stream failed");
 }
 
-// ------------------------------------------------------------------ solve core// ------------------------------------------------------------------ solve core
+// ------------------------------------------------------------------ solve core
 struct SolvePlanArgs {
     const ImgDesc* d0;
     const ImgDesc* descs;   // batched when non-NULL
