@@ -505,3 +505,34 @@ def test_single_solve_in_captured_graph(rd, comps):
         junk = torch.randn(1 << 20, device="cuda").sum()   # eager work between replays
         torch.cuda.synchronize()
         del junk
+
+
+def test_release_and_reuse(rd):
+    """rdseg_release frees what the library keeps for the process (side
+    streams, events, the pinned buffers of timing, polling and the small
+    read-backs); later calls create them again.  A component-path solve in
+    separate launches (which reads its queue length back), a taped solve and
+    its backward (which reads the class counts back) give the same bits
+    before and after a release, and a second release in a row is harmless."""
+    from paper_1807_11534_amd import _lib
+    f = synth.smooth_field(300, 257, 5, noise=0.2)
+    ft = dev(f)
+    delta = synth.band_delta(f, 0.3)
+    kw = dict(tile=(16, 16), iters_per_launch=8, components=1, resident=2)
+    say("release and reuse")
+
+    def run():
+        u, v, p = rd.solve(ft, 3.0, 0.1, 0.125, delta, 40, **kw)
+        out = [host(x).copy() for x in (u, v, p)]
+        u2, v2, p2, tape = rd.solve(ft, 3.0, 0.1, 0.125, delta, 30, ckpt_every=10, **kw)
+        gu = torch.ones_like(u2)
+        gf = rd.backward(ft, 3.0, 0.1, 0.125, delta, 30, 10, tape, gu)
+        out.append(host(gf[0] if isinstance(gf, tuple) else gf).copy())
+        return out
+
+    before = run()
+    _lib.check(_lib.load().rdseg_release())
+    _lib.check(_lib.load().rdseg_release())
+    after = run()
+    for a, b in zip(before, after):
+        np.testing.assert_array_equal(a, b)
