@@ -390,6 +390,7 @@ struct SolvePlanArgs {
     const int32_t* mflags = nullptr;         // resident: queued flag per macro tile
     int32_t* epoch = nullptr;                // resident: max_items int32 of workspace
     int32_t* status = nullptr;               // resident: the solve's status word
+    bool epoch_cleared = false;              // resident: epoch words already zeroed
     const CompWs* comp = nullptr;            // resident: small components for idle workgroups
     const int64_t* comp_npix = nullptr;      // resident: full RD count (the labelling's)
     int64_t res_grid = 0;                    // resident: workgroups (0: max_items)
@@ -583,7 +584,7 @@ rdseg_status enqueue_iterations(SolvePlanArgs& a) {
                                        a.status, a.max_items, L % 2, a.iters, IT,
                                        a.inner, a.theta, a.inv_theta, a.tau, a.st,
                                        timed ? rec.e0 : nullptr, a.comp, a.comp_npix,
-                                       a.res_grid);
+                                       a.res_grid, a.epoch_cleared);
         if (rc > 0) return RDSEG_ERR_HIP;
         if (rc == 0) {
             a.launches = 1;
@@ -838,6 +839,7 @@ rdseg_status solve_impl(const float* f, rdseg_shape s, const rdseg_params* prm, 
     bool resident = false;
     int64_t res_grid = 0;          // 0: one workgroup per macro tile of the image
     bool res_idle_comps = true;    // idle workgroups of the resident grid run the components
+    bool epoch_cleared = false;    // the resident form's epoch words zeroed ahead
     const int want_res = prm->resident ? prm->resident : (tuned_res ? tuned_res : 1);
     // (the allocation-free form has no status word for the caller to read, so
     // it keeps to separate launches, whose waits cannot expire)
@@ -856,6 +858,11 @@ rdseg_status solve_impl(const float* f, rdseg_shape s, const rdseg_params* prm, 
             // half as many idle workgroups as tiles; otherwise just the
             // tiles, and the component kernel follows on the whole chip (a few
             // idle workgroups would hold every component chain).
+            // the epoch words' clearing goes ahead of the wait, off the path
+            // from the read to the launch
+            if (launch_fill(reinterpret_cast<float*>(w.epoch), 1, (int)nm, (int)nm, 0.0f, st))
+                return RDSEG_ERR_HIP;
+            epoch_cleared = true;
             int32_t nq = 0;
             {
                 const int32_t* src[1] = {w.totals};
@@ -923,6 +930,7 @@ rdseg_status solve_impl(const float* f, rdseg_shape s, const rdseg_params* prm, 
     a.inner = inner;
     a.resident = resident;
     a.res_grid = res_grid;
+    a.epoch_cleared = epoch_cleared;
     a.mflags = w.flags;
     a.epoch = w.epoch;
     a.status = reinterpret_cast<int32_t*>(w.npix + 1);

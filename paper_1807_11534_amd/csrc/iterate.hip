@@ -1068,12 +1068,14 @@ int launch_resident(int ci, const ImgDesc& d, const int2* queue, const int32_t* 
                     const int32_t* mflags, int32_t* epoch, int32_t* status, int64_t max_items,
                     int in_buf, int iters, int per, int inner, float theta, float inv_theta,
                     float tau, hipStream_t st, hipEvent_t before, const CompWs* comp,
-                    const int64_t* comp_npix, int64_t n_grid) {
+                    const int64_t* comp_npix, int64_t n_grid, bool epoch_cleared) {
     const int r = resident_entry(ci);
     if (n_grid <= 0) n_grid = max_items;
     if (r < 0 || !resident_fits(ci, n_grid)) return -1;
-    // epoch[0 .. max_items) starts at 0 (*status was cleared with the RD count)
-    if (launch_fill(reinterpret_cast<float*>(epoch), 1, (int)max_items, (int)max_items, 0.0f, st))
+    // epoch[0 .. max_items) starts at 0 (*status was cleared with the RD count;
+    // epoch_cleared: the caller enqueued that fill already)
+    if (!epoch_cleared &&
+        launch_fill(reinterpret_cast<float*>(epoch), 1, (int)max_items, (int)max_items, 0.0f, st))
         return 1;
     if (before) (void)hipEventRecord(before, st);
     const unsigned grid = (unsigned)(((n_grid + 7) / 8) * 8);

@@ -246,7 +246,8 @@ int launch_resident(int ci, const ImgDesc& d, const int2* queue, const int32_t* 
                     const int32_t* mflags, int32_t* epoch, int32_t* status, int64_t max_items,
                     int in_buf, int iters, int per, int inner, float theta, float inv_theta,
                     float tau, hipStream_t st, hipEvent_t before, const CompWs* comp = nullptr,
-                    const int64_t* comp_npix = nullptr, int64_t grid = 0);
+                    const int64_t* comp_npix = nullptr, int64_t grid = 0,
+                    bool epoch_cleared = false);
 
 // Per-launch arguments of the convergence-driven solve: skip the launch when
 // *skip_slot <= tol (skip_slot nullable); reduce the last iteration's change
