@@ -23,12 +23,13 @@
 //                  component
 //   k_cc_class     each small component (<= 256 pixels) takes a slot in the
 //                  class of its size rounded up to a power of two
-//   k_cc_lanes     the lanes of the waves those classes need start empty
 //   k_cc_assign    each of its pixels takes a lane: waves of a class k <= 6
 //                  hold 64 / 2^k components of 2^k lanes, classes 7 and 8 a
-//                  group of 2^k lanes a component; the pixel is then frozen
-//                  for the tile path (c = +inf, its tile-mask bit cleared; the
-//                  tile path's RD count is the full count less these pixels)
+//                  group of 2^k lanes a component (the lanes no pixel takes
+//                  are marked -1 by the components' first pixels); the pixel
+//                  is then frozen for the tile path (c = +inf, its tile-mask
+//                  bit cleared; the tile path's RD count is the full count
+//                  less these pixels)
 //   k_components   every iteration of the groups, then of the packed waves
 // Lane order within a component depends on atomics, but no result does: each
 // pixel's arithmetic reads exact neighbour values, with the per-pixel
@@ -248,18 +249,6 @@ __global__ __launch_bounds__(256) void k_cc_class(ImgDesc d, CompWs w, const int
     }
 }
 
-// The lanes of the packed waves start empty (-1); only the waves the class
-// counts call for are cleared (the assignment pass then fills its lanes).
-__global__ __launch_bounds__(256) void k_cc_lanes(ImgDesc d, CompWs w, const int64_t* npix) {
-    if (cc_skip(npix, d)) return;
-    const int64_t plane = (int64_t)d.H * d.ld;
-    const int64_t lanes =
-        min((int64_t)class_base(w.ccount, kCompClasses) * 64, 2 * plane + kCompLaneExtra);
-    for (int64_t L = (int64_t)blockIdx.x * 256 + threadIdx.x; L < lanes;
-         L += (int64_t)gridDim.x * 256)
-        w.wl_pix[L] = -1;
-}
-
 __global__ __launch_bounds__(256) void k_cc_assign(ImgDesc d, CompWs w, uint64_t* masks,
                                                    const int64_t* npix) {
     __shared__ int sFrozen;
@@ -316,6 +305,22 @@ __global__ __launch_bounds__(256) void k_cc_assign(ImgDesc d, CompWs w, uint64_t
                     d.c[g] = __builtin_inff();   // frozen for the tile path from here on
                     frz = true;
                     ++frozen;
+                    // The component's first pixel marks the lanes no pixel
+                    // takes: the rest of its 2^k lanes and, for the last
+                    // component of a wave class, the free slots after it in
+                    // its wave (every lane the component passes read lies in
+                    // some class's slot, so all of them are written)
+                    if (rank == 0) {
+                        const int64_t top = 2 * plane + kCompLaneExtra;
+                        for (int j = s; j < (1 << k); ++j)
+                            if (L + j < top) w.wl_pix[L + j] = -1;
+                        if (k < kWaveClasses && slot == w.ccount[k] - 1) {
+                            const int per = kSmallMax >> k;
+                            const int64_t w0 = (int64_t)(sCB[k] + slot / per) * 64;
+                            for (int j = (slot % per + 1) << k; j < 64; ++j)
+                                if (w0 + j < top) w.wl_pix[w0 + j] = -1;
+                        }
+                    }
                 }
             }
             // Tile-mask bits of the frozen pixels: the lanes of one 8x8 tile
@@ -783,8 +788,6 @@ int launch_components_prepare(const ImgDesc& d, const CompWs& w, uint64_t* masks
     // shared counters (class counts, the tile path's RD count): fewer, larger
     // workgroups keep that contention small
     hipLaunchKernelGGL(k_cc_class, dim3(std::min(grid, 1024u)), dim3(256), 0, st, d, w,
-                       (const int64_t*)npix);
-    hipLaunchKernelGGL(k_cc_lanes, dim3(std::min(grid, 1024u)), dim3(256), 0, st, d, w,
                        (const int64_t*)npix);
     hipLaunchKernelGGL(k_cc_assign, dim3(std::min(grid, 1024u)), dim3(256), 0, st, d, w, masks,
                        (const int64_t*)npix);
