@@ -829,28 +829,32 @@ rdseg_status solve_impl(const float* f, rdseg_shape s, const rdseg_params* prm, 
                     0.0f, st))
         return RDSEG_ERR_HIP;
     if (comps && launch_components_prepare(d, w.comp, w.masks, w.npix, st)) return RDSEG_ERR_HIP;
-    QueueScratch qs{w.cflags, w.tstate, w.flags, w.offs, w.part};
-    if (launch_macro_queue(&d, nullptr, off, 1, nm, cfg.bx, cfg.by, w.masks, qs, w.queue, w.totals,
-                           g.nt, use_closed ? w.cqueue : nullptr, w.totals + 2, st))
-        return RDSEG_ERR_HIP;
     // The resident form keeps every queued macro tile on chip for the whole
     // solve; it needs all of them resident at once, so closed tiles then run
-    // before it on the same stream instead of beside it.
+    // before it on the same stream instead of beside it.  When it may run,
+    // the queue pass also zeroes its epoch words.
     bool resident = false;
     int64_t res_grid = 0;          // 0: one workgroup per macro tile of the image
     bool res_idle_comps = true;    // idle workgroups of the resident grid run the components
-    bool epoch_cleared = false;    // the resident form's epoch words zeroed ahead
     const int want_res = prm->resident ? prm->resident : (tuned_res ? tuned_res : 1);
     // (the allocation-free form has no status word for the caller to read, so
     // it keeps to separate launches, whose waits cannot expire)
+    bool eager = false;
     if (want_res == 1 && g_resident_on.load() && !stop && !taped && !no_alloc && prm->iters > 0 &&
         resident_available(ci)) {
         hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-        const bool eager =
-            hipStreamIsCapturing(st, &cap) == hipSuccess && cap == hipStreamCaptureStatusNone;
-        if (eager && resident_fits(ci, nm)) {
+        eager = hipStreamIsCapturing(st, &cap) == hipSuccess && cap == hipStreamCaptureStatusNone;
+    }
+    const bool epoch_cleared = eager;   // the resident form's epoch words zeroed ahead
+    QueueScratch qs{w.cflags, w.tstate, w.flags, w.offs, w.part};
+    if (epoch_cleared) qs.epoch = w.epoch;
+    if (launch_macro_queue(&d, nullptr, off, 1, nm, cfg.bx, cfg.by, w.masks, qs, w.queue, w.totals,
+                           g.nt, use_closed ? w.cqueue : nullptr, w.totals + 2, st))
+        return RDSEG_ERR_HIP;
+    if (eager) {
+        if (resident_fits(ci, nm)) {
             resident = true;
-        } else if (eager) {
+        } else {
             // Finer tiles than fit on the chip all at once: the queue (the
             // band's tiles) may.  Read its length (synchronises).  The grid
             // is the co-resident capacity (the queued tiles, then idle
@@ -858,11 +862,6 @@ rdseg_status solve_impl(const float* f, rdseg_shape s, const rdseg_params* prm, 
             // half as many idle workgroups as tiles; otherwise just the
             // tiles, and the component kernel follows on the whole chip (a few
             // idle workgroups would hold every component chain).
-            // the epoch words' clearing goes ahead of the wait, off the path
-            // from the read to the launch
-            if (launch_fill(reinterpret_cast<float*>(w.epoch), 1, (int)nm, (int)nm, 0.0f, st))
-                return RDSEG_ERR_HIP;
-            epoch_cleared = true;
             int32_t nq = 0;
             {
                 const int32_t* src[1] = {w.totals};

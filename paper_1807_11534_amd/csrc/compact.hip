@@ -442,10 +442,12 @@ __global__ __launch_bounds__(256) void k_lists(ImgDesc d0, const ImgDesc* __rest
                                                OffTables off, int n_img, int64_t n_macro, int bx8,
                                                int by8, const uint64_t* __restrict__ masks,
                                                int use_closed, int32_t* __restrict__ mflags,
-                                               int32_t* __restrict__ cflags) {
+                                               int32_t* __restrict__ cflags,
+                                               int32_t* __restrict__ epoch) {
     const int64_t m = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (m >= n_macro) return;   // uniform per wave
     const int lane = threadIdx.x & 63;
+    if (epoch && lane == 0) epoch[m] = 0;   // the resident form's words start at 0
     const int img = BATCHED ? find_image(off.moff, n_img, m) : 0;
     const ImgDesc& d = BATCHED ? descs[img] : d0;
     const int64_t lm = m - (BATCHED ? off.moff[img] : 0);
@@ -697,7 +699,7 @@ int launch_macro_queue(const ImgDesc* d0, const ImgDesc* descs, OffTables off, i
     } else
         hipLaunchKernelGGL(k_lists<false>, dim3(nblk(n_macro, 4)), dim3(256), 0, st, *d0, descs,
                            off, n_img, n_macro, bx / 8, by / 8, masks, use_closed ? 1 : 0,
-                           q.mflags, q.cflags);
+                           q.mflags, q.cflags, q.epoch);
     if (n_macro <= SMALL_N && (!use_closed || n_tiles <= SMALL_N)) {
         hipLaunchKernelGGL(k_scan_small2, dim3(use_closed ? 2 : 1), dim3(SMALL_T), 0, st,
                            q.mflags, n_macro, q.offs, n_queue,

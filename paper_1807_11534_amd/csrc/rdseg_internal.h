@@ -74,6 +74,7 @@ struct QueueScratch {
     int32_t* mflags;
     int32_t* offs;
     int32_t* part;
+    int32_t* epoch = nullptr;   // single image: one word per macro tile, zeroed on the way
 };
 
 // Work lists from dense tile masks.  Macro-tile queue (bx x by pixels,
