@@ -366,7 +366,7 @@ def extras(torch, rdseg, synth, dev, which=EXTRAS):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(pass --gpus 1)", file=sys.stderr)
         sys.exit(2)
     if args.maps_at_exit:
